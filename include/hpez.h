@@ -1,0 +1,198 @@
+/*
+ * hpez.h -- C ABI of the MI355X HPEZ compression library.
+ *
+ * The library implements the data-parallel hot path of HPEZ (Liu et al.,
+ * "High-performance Effective Scientific Error-bounded Lossy Compression with
+ * Auto-tuned Multi-component Interpolation", SIGMOD 2024) as HIP kernels for
+ * gfx950:
+ *   - compression C_theta(X) -> Z and decompression D_theta(Z) -> X' under
+ *     the point-wise bound |x - x'| <= e of Sec. 3.1, Eq. (1);
+ *   - the level-wise interpolation predictor of Sec. 5 with linear-scale
+ *     quantization (Sec. 4, step 3) and Huffman coding (Sec. 4, step 4);
+ *   - the auto-tuner of Sec. 6.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers ("d_") are memory on the context's GPU (for instance
+ *     torch tensors' data_ptr()); host pointers ("h_" or unprefixed structs) are
+ *     ordinary process memory.  The caller owns every buffer it passes; the
+ *     library keeps no pointer past the call.
+ *   - `stream` is a hipStream_t (NULL = the default stream) on which all
+ *     device work of the call is ordered.  Calls that need a result on the host
+ *     (compress: the stream size; tune: the decisions) synchronise that stream
+ *     before returning; all other calls return after enqueueing.
+ *   - Return value: HPEZ_OK (0) or a negative error code; hpez_strerror()
+ *     describes it.  No exception crosses the ABI.  After HPEZ_EDEVICE the
+ *     context should be destroyed.
+ *   - A context is used by one host thread at a time.
+ *
+ * Arrays are row-major with the last dimension varying fastest.
+ */
+#ifndef HPEZ_H
+#define HPEZ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HPEZ_OK = 0,
+  HPEZ_EINVAL = -1,      /* invalid argument, shape, bound, configuration, or non-finite input */
+  HPEZ_ENOMEM = -2,      /* device or host allocation failed */
+  HPEZ_EDEVICE = -3,     /* a HIP call failed */
+  HPEZ_ECORRUPT = -4,    /* the compressed stream is malformed */
+  HPEZ_ENOSPC = -5,      /* output capacity too small */
+  HPEZ_EUNSUPPORTED = -6 /* valid request this build does not handle */
+};
+
+enum { HPEZ_F32 = 0, HPEZ_F64 = 1 };
+enum { HPEZ_ABS = 0, HPEZ_REL = 1 };
+enum { HPEZ_INTERP = 0, HPEZ_LORENZO = 1 };
+enum { HPEZ_LINEAR = 0, HPEZ_CUBIC_NAK = 1, HPEZ_CUBIC_NATURAL = 2 };
+
+/* One interpolation configuration (the choices tuned per level in Sec. 6.2):
+ *   kind        0 linear spline Eq. (2), 1 not-a-knot cubic Eq. (6),
+ *               2 natural cubic Eq. (8);
+ *   md          0: one dimension at a time (1D style); 1: multi-dimensional
+ *               interpolation, Eq. (9), Sec. 5.3;
+ *   same_level  cubic, 1D style: split every pass in two, the second half
+ *               using the same-level stencils Eq. (13)/(14), Sec. 5.4.2;
+ *   order       1D style: the dimension of each pass, first pass first; the
+ *               first ndims entries must be a permutation of 0..ndims-1. */
+typedef struct {
+  uint8_t kind;
+  uint8_t md;
+  uint8_t same_level;
+  uint8_t order[4];
+  uint8_t pad;
+} hpez_interp;
+
+/* The field: dtype HPEZ_F32/HPEZ_F64, 1..4 dims (row-major), and the error
+ * bound: absolute (eb = e) or value-range relative (e = eb * (max - min),
+ * Sec. 7.1.3).  eb > 0 and finite.  The product of dims must be below 2^32. */
+typedef struct {
+  uint8_t dtype;
+  uint8_t ndims;
+  uint8_t eb_mode;
+  uint8_t pad[5];
+  uint64_t dims[4];
+  double eb;
+} hpez_field_desc;
+
+/* Predictor configuration (theta of Eq. 1).
+ *   predictor    HPEZ_INTERP, or HPEZ_LORENZO (first-order Lorenzo, Sec. 6.5);
+ *   anchor_log2  anchor stride A = 2^anchor_log2 (Sec. 5.1), 0..16;
+ *   block_log2   0, or block side B = 2^block_log2 for block-wise configurations
+ *                (Sec. 6.6): levels with stride < B use, per block,
+ *                cand[block_cfg[b]];
+ *   frozen_dim   -1, or a dimension that is never interpolated along (Sec. 6.3);
+ *   radius       quantization radius R (1..32768): codes are q + R, 0 marks a
+ *                value stored verbatim;
+ *   chunk        Huffman chunk length in symbols (power of two, 64..1024);
+ *   alpha, beta  level error bounds e_l = e / min(alpha^(l-1), beta), Eq. (15),
+ *                both >= 1;
+ *   md_w         per stencil kind and dimension, the weight 1/sigma^2 of Eq. (12)
+ *                used by multi-dimensional interpolation (> 0);
+ *   level        level[l-1] is the configuration of level l (stride 2^(l-1));
+ *   cand, n_cand block-wise candidates;
+ *   block_cfg    host array of one candidate index per block (blocks in
+ *                row-major order, ceil(dims[d] / B) per dim), or NULL when
+ *                block_log2 == 0.  Borrowed for the call. */
+typedef struct {
+  uint8_t predictor;
+  uint8_t anchor_log2;
+  uint8_t block_log2;
+  int8_t frozen_dim;
+  uint32_t radius;
+  uint32_t chunk;
+  uint32_t n_cand;
+  double alpha;
+  double beta;
+  double md_w[3][4];
+  hpez_interp level[16];
+  hpez_interp cand[16];
+  const uint8_t* block_cfg;
+} hpez_config;
+
+/* Options of the auto-tuner (Sec. 6).
+ *   global_rate  fraction of B^D blocks whose (B+1)^D boxes feed global tuning;
+ *   sub_rate     volume fraction of the centred sub-block of block-wise tuning
+ *                (the paper's default is 0.04);
+ *   lorenzo_coef multiplies the Lorenzo bit-rate estimate (Sec. 6.5);
+ *   block_log2   tuning block side (the paper uses 32, i.e. 5);
+ *   allow_freeze, allow_lorenzo, block_wise  enable Sec. 6.3 / 6.5 / 6.6;
+ *   anchor_log2  0 for the default (64 for 3+ dims, 128 for 2, 256 for 1). */
+typedef struct {
+  double global_rate;
+  double sub_rate;
+  double lorenzo_coef;
+  uint8_t block_log2;
+  uint8_t allow_freeze;
+  uint8_t allow_lorenzo;
+  uint8_t block_wise;
+  uint8_t anchor_log2;
+  uint8_t pad[3];
+} hpez_tune_opts;
+
+typedef struct hpez_ctx hpez_ctx;
+
+/* Human-readable text for an error code.  Static storage. */
+const char* hpez_strerror(int code);
+
+/* Create a context bound to GPU `device`; it owns a growable device workspace
+ * and the per-device scratch state.  Destroy releases everything. */
+int hpez_ctx_create(hpez_ctx** out, int device);
+void hpez_ctx_destroy(hpez_ctx* ctx);
+
+/* Default configuration for a field: interpolation, linear 1D style in natural
+ * order on every level, anchor stride by dimension count, R = 32768,
+ * chunk = 1024, alpha = beta = 1, unit MD weights, no block-wise, no freeze. */
+int hpez_config_default(const hpez_field_desc* desc, hpez_config* cfg);
+
+/* Upper bound of the compressed size of any field matching desc/cfg.  Pure. */
+int hpez_compress_bound(const hpez_field_desc* desc, const hpez_config* cfg, uint64_t* out_bytes);
+
+/* Compress the device field d_in (desc) into the device buffer d_out of
+ * out_cap bytes.  On success *out_size (host) is the stream length; the stream
+ * is complete when the call returns.  Stream layout: a 512-byte header then
+ * sections (block configs, anchors, verbatim values, Lorenzo outliers and
+ * patches, code lengths, chunk bit counts, payload), little-endian, each on an
+ * 8-byte boundary.  HPEZ_ENOSPC if out_cap is below the stream length. */
+int hpez_compress(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
+                  const hpez_config* cfg, void* d_out, uint64_t out_cap, uint64_t* out_size,
+                  hipStream_t stream);
+
+/* Read the field description and size facts of a stream whose first bytes
+ * (at least 512) are at h_hdr (host).  n_points / total_bytes may be NULL. */
+int hpez_inspect(const void* h_hdr, uint64_t n, hpez_field_desc* desc, uint64_t* n_points,
+                 uint64_t* total_bytes);
+
+/* Decompress the device stream d_in (in_size bytes) into d_out (device,
+ * out_cap bytes >= points * sizeof(dtype)).  HPEZ_ECORRUPT for a malformed
+ * stream, HPEZ_ENOSPC if out_cap is too small.  Synchronises the stream to
+ * read the header, then enqueues the rest. */
+int hpez_decompress(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_out,
+                    uint64_t out_cap, hipStream_t stream);
+
+/* Auto-tune a configuration for the device field d_in (Sec. 6).  *out_cfg is
+ * in/out: on entry its radius, chunk, alpha and beta are used (the rest is
+ * ignored); on return it holds a complete configuration.  When block-wise
+ * tuning is on,
+ * h_block_cfg (host, one byte per block, caller-owned, capacity
+ * block_cfg_cap) receives the per-block choices and out_cfg->block_cfg points
+ * to it.  Synchronous. */
+int hpez_tune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
+              const hpez_tune_opts* opts, hpez_config* out_cfg, uint8_t* h_block_cfg,
+              uint64_t block_cfg_cap, hipStream_t stream);
+
+/* Device bytes the context needs for op (0 compress, 1 decompress, 2 tune) of
+ * such a field, beyond the caller's input and output buffers.  Pure. */
+int hpez_footprint(const hpez_field_desc* desc, const hpez_config* cfg, int op, uint64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPEZ_H */

@@ -1,0 +1,287 @@
+"""ctypes binding of libhpez.so: argument marshalling only.
+
+Every step of compression, decompression and tuning runs in the library's HIP
+kernels; this module converts Python configuration dicts into the C structs of
+``include/hpez.h``, passes torch device pointers and the current HIP stream,
+and turns error codes into exceptions.  There is no fallback: if the library
+is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhpez.so")
+
+HPEZ_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECORRUPT", -5: "ENOSPC",
+          -6: "EUNSUPPORTED"}
+
+
+class HpezError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str = ""):
+        super().__init__(f"{what}: {ERRORS.get(code, code)} ({msg})")
+        self.code = code
+
+
+class Interp(C.Structure):
+    _fields_ = [("kind", C.c_uint8), ("md", C.c_uint8), ("same_level", C.c_uint8),
+                ("order", C.c_uint8 * 4), ("pad", C.c_uint8)]
+
+
+class FieldDesc(C.Structure):
+    _fields_ = [("dtype", C.c_uint8), ("ndims", C.c_uint8), ("eb_mode", C.c_uint8),
+                ("pad", C.c_uint8 * 5), ("dims", C.c_uint64 * 4), ("eb", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("predictor", C.c_uint8), ("anchor_log2", C.c_uint8), ("block_log2", C.c_uint8),
+                ("frozen_dim", C.c_int8), ("radius", C.c_uint32), ("chunk", C.c_uint32),
+                ("n_cand", C.c_uint32), ("alpha", C.c_double), ("beta", C.c_double),
+                ("md_w", (C.c_double * 4) * 3), ("level", Interp * 16), ("cand", Interp * 16),
+                ("block_cfg", C.c_void_p)]
+
+
+class TuneOpts(C.Structure):
+    _fields_ = [("global_rate", C.c_double), ("sub_rate", C.c_double),
+                ("lorenzo_coef", C.c_double), ("block_log2", C.c_uint8),
+                ("allow_freeze", C.c_uint8), ("allow_lorenzo", C.c_uint8),
+                ("block_wise", C.c_uint8), ("anchor_log2", C.c_uint8), ("pad", C.c_uint8 * 3)]
+
+
+EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_default",
+           "hpez_compress_bound", "hpez_compress", "hpez_inspect", "hpez_decompress",
+           "hpez_tune", "hpez_footprint"]
+
+_lib = None
+_lock = threading.Lock()
+_ctx = {}
+
+
+def lib():
+    """Load libhpez.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+            L = C.CDLL(LIB_PATH)
+            vp, u64, P = C.c_void_p, C.c_uint64, C.POINTER
+            L.hpez_strerror.argtypes = [C.c_int]
+            L.hpez_strerror.restype = C.c_char_p
+            L.hpez_ctx_create.argtypes = [P(vp), C.c_int]
+            L.hpez_ctx_destroy.argtypes = [vp]
+            L.hpez_ctx_destroy.restype = None
+            L.hpez_config_default.argtypes = [P(FieldDesc), P(Config)]
+            L.hpez_compress_bound.argtypes = [P(FieldDesc), P(Config), P(u64)]
+            L.hpez_compress.argtypes = [vp, P(FieldDesc), vp, P(Config), vp, u64, P(u64), vp]
+            L.hpez_inspect.argtypes = [vp, u64, P(FieldDesc), P(u64), P(u64)]
+            L.hpez_decompress.argtypes = [vp, vp, u64, vp, u64, vp]
+            L.hpez_tune.argtypes = [vp, P(FieldDesc), vp, P(TuneOpts), P(Config), vp, u64, vp]
+            L.hpez_footprint.argtypes = [P(FieldDesc), P(Config), C.c_int, P(u64)]
+            _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != HPEZ_OK:
+        raise HpezError(rc, what, lib().hpez_strerror(rc).decode())
+
+
+def ctx(device: int):
+    with _lock:
+        c = _ctx.get(device)
+    if c is None:
+        p = C.c_void_p()
+        _check(lib().hpez_ctx_create(C.byref(p), device), "hpez_ctx_create")
+        with _lock:
+            _ctx[device] = p
+        c = p
+    return c
+
+
+# ---------------------------------------------------------------------------
+# config dict <-> structs
+
+def desc_from(dims, dtype: str, eb: float, eb_mode: str) -> FieldDesc:
+    d = FieldDesc()
+    d.dtype = {"f32": 0, "f64": 1}[dtype]
+    d.ndims = len(dims)
+    for i in range(4):
+        d.dims[i] = int(dims[i]) if i < len(dims) else 1
+    d.eb_mode = {"abs": 0, "rel": 1}[eb_mode]
+    d.eb = float(eb)
+    return d
+
+
+def _fill_interp(dst: Interp, src):
+    if src is None:
+        dst.kind = dst.md = dst.same_level = 0
+        for j in range(4):
+            dst.order[j] = j
+        dst.pad = 0
+        return
+    dst.kind = int(src["kind"])
+    dst.md = int(src.get("md", 0))
+    dst.same_level = int(src.get("same_level", 0))
+    order = list(src.get("order", (0, 1, 2, 3)))
+    order = order + [j for j in range(4) if j not in order]
+    for j in range(4):
+        dst.order[j] = order[j]
+    dst.pad = 0
+
+
+def config_from(cfg: dict, keep: list) -> Config:
+    c = Config()
+    c.predictor = {"interp": 0, "lorenzo": 1}[cfg.get("predictor", "interp")]
+    c.anchor_log2 = int(cfg["anchor_log2"])
+    c.block_log2 = int(cfg.get("block_log2", 0))
+    c.frozen_dim = int(cfg.get("frozen_dim", -1))
+    c.radius = int(cfg.get("radius", 32768))
+    c.chunk = int(cfg.get("chunk", 1024))
+    c.alpha = float(cfg.get("alpha", 1.0))
+    c.beta = float(cfg.get("beta", 1.0))
+    mw = cfg.get("md_w", [[1.0] * 4] * 3)
+    for k in range(3):
+        for d in range(4):
+            c.md_w[k][d] = float(mw[k][d])
+    levels = cfg["levels"]
+    for i in range(16):
+        _fill_interp(c.level[i], levels[i] if i < len(levels) else levels[-1])
+    cand = cfg.get("cand", [])
+    c.n_cand = len(cand)
+    for i in range(16):
+        _fill_interp(c.cand[i], cand[i] if i < len(cand) else None)
+    bc = cfg.get("block_cfg")
+    if bc is not None:
+        arr = np.ascontiguousarray(np.asarray(bc, dtype=np.uint8))
+        keep.append(arr)
+        c.block_cfg = arr.ctypes.data
+    return c
+
+
+def interp_dict(s: Interp) -> dict:
+    return dict(kind=int(s.kind), md=int(s.md), same_level=int(s.same_level),
+                order=tuple(int(v) for v in s.order))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dtype_of(t) -> str:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return "f32"
+    if t.dtype == torch.float64:
+        return "f64"
+    raise TypeError("hpez compresses float32 or float64 tensors")
+
+
+# ---------------------------------------------------------------------------
+# public calls
+
+def compress_bound(dims, dtype: str, cfg: dict) -> int:
+    keep = []
+    d = desc_from(dims, dtype, cfg.get("eb", 1e-3), cfg.get("eb_mode", "rel"))
+    c = config_from(cfg, keep)
+    n = C.c_uint64()
+    _check(lib().hpez_compress_bound(C.byref(d), C.byref(c), C.byref(n)), "hpez_compress_bound")
+    return n.value
+
+
+def compress(x, cfg: dict, stream=None, out=None):
+    """Compress a CUDA tensor (float32/float64, contiguous).  Returns a uint8 CUDA
+    tensor holding the stream (a view of `out` when given)."""
+    torch = _torch()
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous device tensor")
+    dtype = _dtype_of(x)
+    keep = []
+    d = desc_from(tuple(x.shape) if x.dim() else (1,), dtype, cfg["eb"], cfg["eb_mode"])
+    c = config_from(cfg, keep)
+    cap = C.c_uint64()
+    _check(lib().hpez_compress_bound(C.byref(d), C.byref(c), C.byref(cap)), "hpez_compress_bound")
+    if out is None:
+        out = torch.empty(cap.value, dtype=torch.uint8, device=x.device)
+    n = C.c_uint64()
+    rc = lib().hpez_compress(ctx(x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
+                             C.byref(c), C.c_void_p(out.data_ptr()), out.numel(), C.byref(n),
+                             _stream_ptr(stream))
+    _check(rc, "hpez_compress")
+    return out[: n.value]
+
+
+def inspect(header_bytes: bytes):
+    d = FieldDesc()
+    npts, tot = C.c_uint64(), C.c_uint64()
+    buf = np.frombuffer(header_bytes, dtype=np.uint8)
+    _check(lib().hpez_inspect(buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(d), C.byref(npts),
+                              C.byref(tot)), "hpez_inspect")
+    return dict(dims=tuple(int(d.dims[i]) for i in range(d.ndims)),
+                dtype="f64" if d.dtype else "f32", points=npts.value, total=tot.value)
+
+
+def decompress(stream_t, stream=None, out=None):
+    """Decompress a uint8 CUDA tensor holding a stream; returns the field."""
+    torch = _torch()
+    hdr = stream_t[:512].cpu().numpy().tobytes()
+    info = inspect(hdr + b"\0" * max(0, 512 - len(hdr)))
+    dt = torch.float64 if info["dtype"] == "f64" else torch.float32
+    if out is None:
+        out = torch.empty(info["dims"], dtype=dt, device=stream_t.device)
+    rc = lib().hpez_decompress(ctx(stream_t.device.index or 0), C.c_void_p(stream_t.data_ptr()),
+                               stream_t.numel(), C.c_void_p(out.data_ptr()),
+                               out.numel() * out.element_size(), _stream_ptr(stream))
+    _check(rc, "hpez_decompress")
+    return out
+
+
+def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
+    """Run the auto-tuner on a CUDA tensor; returns a complete config dict."""
+    opts = opts or {}
+    dtype = _dtype_of(x)
+    keep = []
+    d = desc_from(tuple(x.shape), dtype, cfg["eb"], cfg["eb_mode"])
+    c = config_from(cfg, keep)
+    o = TuneOpts()
+    o.global_rate = opts.get("global_rate", 0.01)
+    o.sub_rate = opts.get("sub_rate", 0.04)
+    o.lorenzo_coef = opts.get("lorenzo_coef", 1.0)
+    o.block_log2 = opts.get("block_log2", 5)
+    o.allow_freeze = opts.get("allow_freeze", 1)
+    o.allow_lorenzo = opts.get("allow_lorenzo", 1)
+    o.block_wise = opts.get("block_wise", 1)
+    o.anchor_log2 = opts.get("anchor_log2", 0)
+    B = 1 << o.block_log2
+    nb = 1
+    for n in x.shape:
+        nb *= (n + B - 1) // B
+    bc = np.zeros(max(nb, 1), dtype=np.uint8)
+    out = Config()
+    rc = lib().hpez_tune(ctx(x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
+                         C.byref(o), C.byref(c), bc.ctypes.data_as(C.c_void_p), bc.size,
+                         _stream_ptr(stream))
+    _check(rc, "hpez_tune")
+    res = dict(cfg)
+    res["predictor"] = "lorenzo" if c.predictor == 1 else "interp"
+    res["anchor_log2"] = int(c.anchor_log2)
+    res["frozen_dim"] = int(c.frozen_dim)
+    res["block_log2"] = int(c.block_log2)
+    res["md_w"] = [[float(c.md_w[k][dd]) for dd in range(4)] for k in range(3)]
+    res["levels"] = [interp_dict(c.level[i]) for i in range(16)]
+    res["cand"] = [interp_dict(c.cand[i]) for i in range(c.n_cand)]
+    res["block_cfg"] = bc[:nb].copy() if c.block_log2 else None
+    return res

@@ -1,0 +1,40 @@
+// hpez_host.h -- host-side helpers of the runtime (stream layout, validation,
+// Huffman codebook, geometry).  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include "hpez_internal.h"
+
+namespace hpez {
+
+// Section sizes and offsets of one stream.
+struct Layout {
+  uint8_t predictor;  // 0 interpolation, 1 Lorenzo, 2 constant field
+  double e;           // absolute error bound
+  uint64_t n_blocks, n_anchor, n_unpred, n_outlier, n_patch, n_chunks, payload_bits;
+  uint32_t sym_min, sym_max;
+  uint64_t off_blocks, off_anchor, off_unpred, off_outl, off_pidx, off_pval, off_len, off_chunks,
+      off_payload, total;
+};
+
+const char* err_text(int c);
+uint64_t points_of(const hpez_field_desc* d);
+int check_desc(const hpez_field_desc* d);
+int check_cfg(const hpez_field_desc* d, const hpez_config* c, bool need_blocks);
+uint64_t n_blocks(const hpez_field_desc* d, const hpez_config* c);
+Geom make_geom(const hpez_field_desc* d, int frozen);
+int n_active(const Geom& g);
+Lattice make_lattice(const Geom& g, const int64_t* r, const int64_t* m);
+double level_eb(double e, double alpha, double beta, int l);
+uint64_t anchors_of(const Geom& g, int anchor_log2);
+void layout(Layout* L, uint64_t s);
+void write_header(uint8_t* h, const hpez_field_desc* d, const hpez_config* c, const Layout& L);
+int read_header(const uint8_t* h, uint64_t n, hpez_field_desc* d, hpez_config* c, Layout* L);
+int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
+void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw);
+void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint32_t* first,
+                   uint32_t* count, uint32_t* offset, uint16_t* sorted);
+void md_table(const hpez_config* c, double* wq);
+
+}  // namespace hpez

@@ -1,0 +1,105 @@
+// hpez_internal.h -- shared declarations of the HIP kernels and the host
+// runtime of the MI355X HPEZ library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hpez.h"
+
+namespace hpez {
+
+constexpr int kMaxLevels = 16;
+constexpr int kHdrBytes = 512;
+constexpr uint32_t kMagic = 0x5A455048u;  // "HPEZ"
+constexpr int kLmax = 32;                 // longest Huffman codeword
+constexpr int kLutBits = 12;              // first-level decode table width
+
+// Grid geometry, always padded to four dims (size-1 dims are inactive).
+struct Geom {
+  int64_t n[4];
+  int64_t st[4];
+  int32_t act[4];
+};
+
+// A lattice {first_d + k * step_d, k < cnt_d} in every dim.
+struct Lattice {
+  int64_t first[4];
+  int64_t step[4];
+  uint32_t cnt[4];
+  uint64_t total;
+};
+
+// One step (pass, half pass or multi-dimensional sub-step) of one level.
+struct StepArgs {
+  Geom g;
+  Lattice lat;
+  int64_t s;          // stride of the level
+  int64_t B;          // block side (face filter), 0 = none
+  int32_t filter;     // 0 all lattice points, 1 only points on block faces
+  int32_t kind;       // 0 linear, 1 not-a-knot, 2 natural
+  int32_t md;         // multi-dimensional
+  int32_t sl;         // same-level second half
+  int32_t pdim;       // pass dimension (1D style)
+  uint32_t odd;       // odd set (multi-dimensional)
+  double wq[4];       // normalised MD weights for this odd set (double, cast to T on use)
+  double el, inv2e, twoe;
+  uint32_t R;
+};
+
+// Interior points of every block at one level, one step index of each block's
+// own configuration.
+struct BlockStepArgs {
+  Geom g;
+  Lattice lat;        // the level's coarse lattice (multiples of s on active dims)
+  int64_t s, B;
+  int64_t nb[4];
+  int32_t t;          // step index processed by this launch
+  double el, inv2e, twoe;
+  uint32_t R;
+  hpez_interp cand[16];
+};
+
+// Launchers (defined in the .hip files).  All return hipError_t.
+template <typename T>
+hipError_t launch_step(const StepArgs& a, const T* X, T* W, uint16_t* code, int mode,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_block_step(const BlockStepArgs& a, const T* X, T* W, uint16_t* code,
+                             const uint8_t* d_block_cfg, const double* d_wq, int mode,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_anchors(const Geom& g, const Lattice& lat, const T* X, T* W, uint16_t* code,
+                          T* out_anchor, uint32_t R, int mode, hipStream_t st);
+template <typename T>
+hipError_t launch_minmax(const T* X, uint64_t n, double* d_part, int* d_bad, int nblocks,
+                         hipStream_t st);
+hipError_t launch_minmax_final(double* d_part, int nblocks, double* d_out, hipStream_t st);
+
+// Huffman
+hipError_t launch_histogram(const uint16_t* code, uint64_t n, uint32_t* hist, uint32_t nsym,
+                            uint32_t R, hipStream_t st);
+hipError_t launch_chunk_lengths(const uint16_t* code, uint64_t n, uint32_t chunk,
+                                const uint8_t* d_len, uint32_t* chunk_bits, uint32_t* chunk_zero,
+                                hipStream_t st);
+hipError_t launch_scan_u32_to_u64(const uint32_t* in, uint64_t n, uint64_t* out_excl,
+                                  uint64_t* d_total, uint64_t* tmp, hipStream_t st);
+hipError_t launch_zero_words(uint32_t* words, const uint64_t* d_total_bits, hipStream_t st);
+template <typename T>
+hipError_t launch_encode(const uint16_t* code, uint64_t n, uint32_t chunk, const uint8_t* d_len,
+                         const uint32_t* d_cw, const uint64_t* bit_off, const uint64_t* zero_off,
+                         const uint32_t* chunk_bits, const uint32_t* chunk_zero, uint32_t* payload,
+                         uint16_t* out_chunk_bits, const T* X, T* out_unpred, hipStream_t st);
+hipError_t launch_u16_to_u32(const uint16_t* in, uint64_t n, uint32_t* out, hipStream_t st);
+template <typename T>
+hipError_t launch_decode(const uint32_t* payload, uint64_t nbits, const uint64_t* bit_off,
+                         uint64_t n, uint32_t chunk, const uint32_t* d_lut, const uint32_t* d_first,
+                         const uint32_t* d_count, const uint32_t* d_offset, const uint16_t* d_sorted,
+                         uint16_t* code, uint32_t* chunk_zero, int* d_status, hipStream_t st);
+template <typename T>
+hipError_t launch_scatter_unpred(const uint16_t* code, uint64_t n, uint32_t chunk,
+                                 const uint32_t* chunk_zero, const uint64_t* zero_off,
+                                 const T* unpred, uint64_t n_unpred, T* W, int* d_status,
+                                 hipStream_t st);
+
+}  // namespace hpez

@@ -1,0 +1,396 @@
+// k_interp.hip -- interpolation predictor kernels (gfx950).
+//
+// Level-wise anchor-based interpolation (Sec. 5.1) with linear-scale
+// quantization (Sec. 4, step 3): for each level, each step (one 1D pass, one
+// half of a same-level split pass, or one multi-dimensional sub-step) is one
+// launch over exactly the points that step predicts.  Each thread predicts one
+// point from already reconstructed neighbours in W, quantizes the error
+// (compress) or applies the decoded code (decompress), and writes the
+// reconstruction back to W.  Points of one step never read each other, so the
+// traversal order inside a launch does not matter (Sec. 5.4.1); lanes map to
+// the fastest-varying dimension so that reads and writes coalesce.
+//
+// Floating point: the stencils are evaluated in T in the order written, the
+// quantizer in double; the library is built with -ffp-contract=off so no
+// operation is fused.
+
+#include "hpez_internal.h"
+
+namespace hpez {
+
+template <typename T>
+struct SplineK;
+template <>
+struct SplineK<float> {
+  static __device__ float k6() { return 0x1.555556p-3f; }
+  static __device__ float k40() { return 0x1.99999ap-6f; }
+  static __device__ float k62() { return 0x1.084210p-6f; }
+};
+template <>
+struct SplineK<double> {
+  static __device__ double k6() { return 0x1.5555555555555p-3; }
+  static __device__ double k40() { return 0x1.999999999999ap-6; }
+  static __device__ double k62() { return 0x1.0842108421084p-6; }
+};
+
+// One-dimensional spline prediction along a dimension with index step sd = s *
+// stride, for a point at coordinate x whose usable neighbours lie in [lo, hi].
+// Interior stencils: Eq. (2) linear, Eq. (6) not-a-knot, Eq. (8) natural,
+// Eq. (13)/(14) same-level.  At the grid (or block) end the Lagrange polynomial
+// through the neighbours that exist is used.
+template <typename T>
+__device__ __forceinline__ T spline(const T* __restrict__ W, int64_t idx, int64_t sd, int64_t x,
+                                    int64_t s, int64_t lo, int64_t hi, int kind, int sl)
+{
+  const bool ha = x - 3 * s >= lo;
+  const bool hc = x + s <= hi;
+  const bool hd = x + 3 * s <= hi;
+  const T b = W[idx - sd];
+  if (kind == 0) {
+    if (hc) return (b + W[idx + sd]) * (T)0.5;
+    if (ha) return (b * (T)3 - W[idx - 3 * sd]) * (T)0.5;
+    return b;
+  }
+  if (sl) {
+    const bool ha2 = x - 2 * s >= lo;
+    const bool hd2 = x + 2 * s <= hi;
+    if (kind == 1 && ha2 && hc && hd2)
+      return ((b + W[idx + sd]) * (T)4 - (W[idx - 2 * sd] + W[idx + 2 * sd])) * SplineK<T>::k6();
+    if (kind == 2 && ha && ha2 && hc && hd2 && hd)
+      return ((b + W[idx + sd]) * (T)46 - (W[idx - 2 * sd] + W[idx + 2 * sd]) * (T)18 +
+              (W[idx - 3 * sd] + W[idx + 3 * sd]) * (T)3) *
+             SplineK<T>::k62();
+  }
+  if (ha && hc && hd) {
+    const T a = W[idx - 3 * sd], c = W[idx + sd], d = W[idx + 3 * sd];
+    if (kind == 1) return ((b + c) * (T)9 - (a + d)) * (T)0.0625;
+    return ((b + c) * (T)23 - (a + d) * (T)3) * SplineK<T>::k40();
+  }
+  if (hc && hd) return (b * (T)3 + W[idx + sd] * (T)6 - W[idx + 3 * sd]) * (T)0.125;
+  if (ha && hc) return (b * (T)6 + W[idx + sd] * (T)3 - W[idx - 3 * sd]) * (T)0.125;
+  if (hc) return (b + W[idx + sd]) * (T)0.5;
+  if (ha) return (b * (T)3 - W[idx - 3 * sd]) * (T)0.5;
+  return b;
+}
+
+// Linear-scale quantization (Sec. 4, step 3): bins of width 2 e_l, rounding
+// half away from zero, radius R, double arithmetic; the value the decompressor
+// will rebuild must meet the bound or the point is stored verbatim (code 0).
+template <typename T>
+__device__ __forceinline__ uint32_t quantize(T x, T p, double inv2e, double twoe, double el,
+                                             uint32_t R, T& xr)
+{
+  const double t = ((double)x - (double)p) * inv2e;
+  const double qf = floor(fabs(t) + 0.5);
+  if (!(qf < (double)R)) return 0;
+  const double q = t < 0 ? -qf : qf;
+  const T r = (T)((double)p + q * twoe);
+  if (!(fabs((double)r - (double)x) <= el)) return 0;
+  xr = r;
+  return (uint32_t)((int64_t)q + (int64_t)R);
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void finish(T p, int64_t idx, const T* __restrict__ X, T* __restrict__ W,
+                                       uint16_t* __restrict__ code, double el, double inv2e,
+                                       double twoe, uint32_t R)
+{
+  if (MODE == 0) {
+    const T x = X[idx];
+    T xr = x;
+    const uint32_t q = quantize<T>(x, p, inv2e, twoe, el, R, xr);
+    code[idx] = (uint16_t)q;
+    W[idx] = q ? xr : x;
+  } else {
+    const uint32_t q = code[idx];
+    if (q != 0) W[idx] = (T)((double)p + (double)((int64_t)q - (int64_t)R) * twoe);
+  }
+}
+
+__device__ __forceinline__ void lattice_point(const Lattice& L, uint64_t k, int64_t* x)
+{
+  uint64_t r = k;
+  for (int d = 3; d >= 0; d--) {
+    const uint64_t c = L.cnt[d];
+    const uint64_t q = r / c;
+    x[d] = L.first[d] + (int64_t)(r - q * c) * L.step[d];
+    r = q;
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restrict__ X,
+                                                   T* __restrict__ W, uint16_t* __restrict__ code)
+{
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.lat.total;
+       k += stride) {
+    int64_t x[4];
+    lattice_point(a.lat, k, x);
+    if (a.filter) {
+      bool face = false;
+      for (int d = 0; d < 4; d++)
+        if (a.g.act[d] && x[d] % a.B == 0) face = true;
+      if (!face) continue;
+    }
+    const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
+    T p;
+    if (!a.md) {
+      const int d = a.pdim;
+      p = spline<T>(W, idx, a.s * a.g.st[d], x[d], a.s, 0, a.g.n[d] - 1, a.kind, a.sl);
+    } else {
+      bool first = true;
+      T acc = (T)0;
+      for (int d = 0; d < 4; d++) {
+        if (!(a.odd >> d & 1u)) continue;
+        const T pd = spline<T>(W, idx, a.s * a.g.st[d], x[d], a.s, 0, a.g.n[d] - 1, a.kind, 0);
+        const T term = (T)a.wq[d] * pd;
+        acc = first ? term : acc + term;
+        first = false;
+      }
+      p = acc;
+    }
+    finish<T, MODE>(p, idx, X, W, code, a.el, a.inv2e, a.twoe, a.R);
+  }
+}
+
+// Step index of a level point under a configuration: 1D style, 2 * pass + half
+// (the pass is the last dimension in pass order whose coordinate is an odd
+// multiple of s; the half is 1 for coordinates at 3s mod 4s with same-level
+// cubic); multi-dimensional, the number of odd coordinates minus one.
+__device__ __forceinline__ int step_of(const hpez_interp& c, const int32_t* act, const int64_t* x,
+                                       int64_t s, unsigned* odd_out, int* pdim_out, int* half_out)
+{
+  unsigned odd = 0;
+  for (int d = 0; d < 4; d++)
+    if (act[d] && (x[d] / s) & 1) odd |= 1u << d;
+  *odd_out = odd;
+  if (c.md) {
+    *pdim_out = -1;
+    *half_out = 0;
+    return __popc(odd) - 1;
+  }
+  int pass = -1, pd = -1, k = 0;
+  bool seen[4] = {false, false, false, false};
+  for (int i = 0; i < 4; i++) {
+    const int d = c.order[i];
+    if (d < 4 && act[d] && !seen[d]) {
+      seen[d] = true;
+      if (odd >> d & 1u) {
+        pass = k;
+        pd = d;
+      }
+      k++;
+    }
+  }
+  *pdim_out = pd;
+  const int half = (c.kind != 0 && c.same_level && ((x[pd] / s) & 3) == 3) ? 1 : 0;
+  *half_out = half;
+  return 2 * pass + half;
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const T* __restrict__ X,
+                                                         T* __restrict__ W,
+                                                         uint16_t* __restrict__ code,
+                                                         const uint8_t* __restrict__ bcfg,
+                                                         const double* __restrict__ wq)
+{
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.lat.total;
+       k += stride) {
+    int64_t x[4];
+    lattice_point(a.lat, k, x);
+    bool face = false, level = false;
+    for (int d = 0; d < 4; d++) {
+      if (!a.g.act[d]) continue;
+      if (x[d] % a.B == 0) face = true;
+      if ((x[d] / a.s) & 1) level = true;
+    }
+    if (face || !level) continue;
+    int64_t b[4], lo[4], hi[4];
+    for (int d = 0; d < 4; d++) {
+      b[d] = x[d] / a.B;
+      lo[d] = b[d] * a.B;
+      hi[d] = lo[d] + a.B < a.g.n[d] - 1 ? lo[d] + a.B : a.g.n[d] - 1;
+    }
+    const int64_t bi = ((b[0] * a.nb[1] + b[1]) * a.nb[2] + b[2]) * a.nb[3] + b[3];
+    const hpez_interp c = a.cand[bcfg[bi]];
+    unsigned odd;
+    int pd, half;
+    if (step_of(c, a.g.act, x, a.s, &odd, &pd, &half) != a.t) continue;
+    const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
+    T p;
+    if (!c.md) {
+      p = spline<T>(W, idx, a.s * a.g.st[pd], x[pd], a.s, lo[pd], hi[pd], c.kind, half);
+    } else {
+      bool first = true;
+      T acc = (T)0;
+      for (int d = 0; d < 4; d++) {
+        if (!(odd >> d & 1u)) continue;
+        const T pdv = spline<T>(W, idx, a.s * a.g.st[d], x[d], a.s, lo[d], hi[d], c.kind, 0);
+        const T term = (T)wq[(c.kind * 16 + odd) * 4 + d] * pdv;
+        acc = first ? term : acc + term;
+        first = false;
+      }
+      p = acc;
+    }
+    finish<T, MODE>(p, idx, X, W, code, a.el, a.inv2e, a.twoe, a.R);
+  }
+}
+
+// Anchors (Sec. 5.1): kept verbatim, in row-major order.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) anchor_kernel(Geom g, Lattice lat, const T* __restrict__ X,
+                                                     T* __restrict__ W, uint16_t* __restrict__ code,
+                                                     T* __restrict__ out_anchor, uint32_t R)
+{
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < lat.total; k += stride) {
+    int64_t x[4];
+    lattice_point(lat, k, x);
+    const int64_t idx = x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3];
+    if (MODE == 0) {
+      const T v = X[idx];
+      W[idx] = v;
+      code[idx] = (uint16_t)R;
+      out_anchor[k] = v;
+    } else {
+      W[idx] = out_anchor[k];
+    }
+  }
+}
+
+static unsigned grid_for(uint64_t total)
+{
+  uint64_t b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <typename T>
+hipError_t launch_step(const StepArgs& a, const T* X, T* W, uint16_t* code, int mode,
+                       hipStream_t st)
+{
+  if (a.lat.total == 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL((step_kernel<T, 0>), dim3(grid_for(a.lat.total)), dim3(256), 0, st, a, X,
+                       W, code);
+  else
+    hipLaunchKernelGGL((step_kernel<T, 1>), dim3(grid_for(a.lat.total)), dim3(256), 0, st, a, X,
+                       W, code);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_block_step(const BlockStepArgs& a, const T* X, T* W, uint16_t* code,
+                             const uint8_t* d_block_cfg, const double* d_wq, int mode,
+                             hipStream_t st)
+{
+  if (a.lat.total == 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL((block_step_kernel<T, 0>), dim3(grid_for(a.lat.total)), dim3(256), 0, st,
+                       a, X, W, code, d_block_cfg, d_wq);
+  else
+    hipLaunchKernelGGL((block_step_kernel<T, 1>), dim3(grid_for(a.lat.total)), dim3(256), 0, st,
+                       a, X, W, code, d_block_cfg, d_wq);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_anchors(const Geom& g, const Lattice& lat, const T* X, T* W, uint16_t* code,
+                          T* out_anchor, uint32_t R, int mode, hipStream_t st)
+{
+  if (lat.total == 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL((anchor_kernel<T, 0>), dim3(grid_for(lat.total)), dim3(256), 0, st, g, lat,
+                       X, W, code, out_anchor, R);
+  else
+    hipLaunchKernelGGL((anchor_kernel<T, 1>), dim3(grid_for(lat.total)), dim3(256), 0, st, g, lat,
+                       X, W, code, out_anchor, R);
+  return hipGetLastError();
+}
+
+// min / max with a non-finite flag (value-range bound, Sec. 7.1.3)
+template <typename T>
+__global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ X, uint64_t n,
+                                                     double* __restrict__ part, int* __restrict__ bad)
+{
+  __shared__ double smn[256], smx[256];
+  double mn = INFINITY, mx = -INFINITY;
+  bool nf = false;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = (double)X[i];
+    if (!isfinite(v)) nf = true;
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  if (nf) atomicOr(bad, 1);
+  smn[threadIdx.x] = mn;
+  smx[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + w]);
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smn[0];
+    part[2 * blockIdx.x + 1] = smx[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) minmax_final_kernel(const double* __restrict__ part, int nb,
+                                                           double* __restrict__ out)
+{
+  __shared__ double smn[256], smx[256];
+  double mn = INFINITY, mx = -INFINITY;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    mn = fmin(mn, part[2 * i]);
+    mx = fmax(mx, part[2 * i + 1]);
+  }
+  smn[threadIdx.x] = mn;
+  smx[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + w]);
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smn[0];
+    out[1] = smx[0];
+  }
+}
+
+template <typename T>
+hipError_t launch_minmax(const T* X, uint64_t n, double* d_part, int* d_bad, int nblocks,
+                         hipStream_t st)
+{
+  hipLaunchKernelGGL((minmax_kernel<T>), dim3(nblocks), dim3(256), 0, st, X, n, d_part, d_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax_final(double* d_part, int nblocks, double* d_out, hipStream_t st)
+{
+  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(256), 0, st, d_part, nblocks, d_out);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                 \
+  template hipError_t launch_step<T>(const StepArgs&, const T*, T*, uint16_t*, int, hipStream_t); \
+  template hipError_t launch_block_step<T>(const BlockStepArgs&, const T*, T*, uint16_t*,         \
+                                           const uint8_t*, const double*, int, hipStream_t);     \
+  template hipError_t launch_anchors<T>(const Geom&, const Lattice&, const T*, T*, uint16_t*, T*, \
+                                        uint32_t, int, hipStream_t);                              \
+  template hipError_t launch_minmax<T>(const T*, uint64_t, double*, int*, int, hipStream_t);
+INST(float)
+INST(double)
+
+}  // namespace hpez

@@ -1,0 +1,149 @@
+"""GPU parity: the HIP library through the C ABI against the CPU oracle on the
+same seeded inputs.  Integer outputs (codes, Huffman bitstream, the whole
+stream) must be byte-identical; decompressed values bit-identical (the method
+is deterministic: FP contraction is off on both sides and every stencil and
+quantizer operation is written in the same order).  Every case also checks
+|x - x'| <= e on every point."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from cfgs import candidates, make_cfg
+from oracle import oracle as O
+from paper_2311_12133_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_12133_amd import binding
+    binding.lib()
+    return torch
+
+
+def roundtrip(torch, x, cfg, label):
+    from paper_2311_12133_amd import binding
+    print(f"[case] {label} shape={x.shape} dtype={cfg['dtype']}", flush=True)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    s = binding.compress(xt, cfg)
+    torch.cuda.synchronize()
+    got = s.cpu().numpy().tobytes()
+    ref = O.compress(x, cfg)
+    if got != ref:
+        a = np.frombuffer(got, np.uint8)
+        b = np.frombuffer(ref, np.uint8)
+        n = min(a.size, b.size)
+        first = int(np.nonzero(a[:n] != b[:n])[0][0]) if (a[:n] != b[:n]).any() else n
+        raise AssertionError(f"{label}: stream differs (gpu {a.size} B, oracle {b.size} B, "
+                             f"first diff at byte {first})")
+    y = binding.decompress(s).cpu().numpy()
+    yo = O.decompress(ref)
+    assert np.array_equal(y.view(np.uint8), yo.view(np.uint8)), f"{label}: decompressed differs"
+    if cfg["eb_mode"] == "rel":
+        e, const = O.error_bound(x, cfg)
+    else:
+        e, const = cfg["eb"], False
+    if not const:
+        assert np.abs(x.astype(np.float64) - y.astype(np.float64)).max() <= e
+    return got
+
+
+KW = [
+    dict(kind="lin"), dict(kind="nak"), dict(kind="nat"),
+    dict(kind="lin", md=1), dict(kind="nak", md=1), dict(kind="nat", md=1),
+    dict(kind="nak", same_level=1), dict(kind="nat", same_level=1),
+    dict(kind="nak", order=(2, 0, 1)), dict(kind="nat", order=(1, 2, 0), same_level=1),
+]
+
+
+@pytest.mark.parametrize("kw", KW, ids=[str(i) for i in range(len(KW))])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_configs_3d(torch_cuda, kw, dtype):
+    x = fields.random_field((37, 70, 129), 3, np.float32 if dtype == "f32" else np.float64,
+                            "smooth")
+    roundtrip(torch_cuda, x, make_cfg(x.shape, dtype=dtype, eb=1e-3, **kw), f"3d {kw}")
+
+
+@pytest.mark.parametrize("shape", [(1,), (2,), (7,), (1000,), (5000,), (3, 1),
+                                   (1, 300), (257, 129), (1800, 36), (2, 3, 4),
+                                   (64, 1, 65), (9, 17, 33, 5)])
+def test_shapes(torch_cuda, shape):
+    x = fields.random_field(shape, len(shape) + shape[0], np.float32, "mixed")
+    for kw in (dict(kind="nak"), dict(kind="nat", md=1)):
+        roundtrip(torch_cuda, x, make_cfg(shape, eb=1e-3, **kw), f"shape {shape} {kw}")
+
+
+def test_plain_64cube(torch_cuda):
+    """The plain-method workload: 64^3 k^-3 field, linear, natural order."""
+    x = fields.plain_field((64, 64, 64))
+    roundtrip(torch_cuda, x, make_cfg(x.shape, eb=1e-3), "plain 64^3")
+
+
+def test_unpredictable_and_radius(torch_cuda):
+    """Spikes with a tiny radius force out-of-range codes (verbatim values)."""
+    x = fields.random_field((40, 50, 60), 5, np.float32, "mixed")
+    cfg = make_cfg(x.shape, eb=1e-4, kind="nak", radius=64)
+    s = roundtrip(torch_cuda, x, cfg, "radius 64")
+    n_unpred = int(np.frombuffer(s[456:464], np.uint64)[0])
+    assert n_unpred > 100
+
+
+def test_abs_bound_alpha_beta_frozen(torch_cuda):
+    x = fields.random_field((30, 64, 70), 8, np.float64, "rough")
+    for kw in (dict(kind="nak", alpha=1.5, beta=4.0), dict(kind="lin", frozen_dim=1),
+               dict(kind="nat", md=1, frozen_dim=2, alpha=2.0, beta=2.0)):
+        roundtrip(torch_cuda, x, make_cfg(x.shape, dtype="f64", eb=0.01, eb_mode="abs", **kw),
+                  f"abs {kw}")
+
+
+def test_constant_field(torch_cuda):
+    x = np.full((33, 17, 5), -2.5, dtype=np.float32)
+    roundtrip(torch_cuda, x, make_cfg(x.shape, eb=1e-3), "constant")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_block_wise(torch_cuda, dtype):
+    x = fields.random_field((70, 66, 97), 9, np.float32 if dtype == "f32" else np.float64,
+                            "mixed")
+    cand = candidates(3)
+    for B, al in ((8, 4), (32, 6)):
+        nb = int(np.prod([(s + B - 1) // B for s in x.shape]))
+        bc = (np.arange(nb) * 5 % 11).astype(np.uint8)
+        cfg = make_cfg(x.shape, dtype=dtype, eb=1e-3, kind="nat", anchor_log2=al,
+                       block_log2=int(np.log2(B)), cand=cand, block_cfg=bc)
+        roundtrip(torch_cuda, x, cfg, f"block-wise B={B}")
+
+
+def test_chunk_sizes(torch_cuda):
+    x = fields.random_field((50, 61, 33), 2, np.float32, "smooth")
+    for chunk in (64, 256, 1024):
+        roundtrip(torch_cuda, x, make_cfg(x.shape, eb=1e-4, kind="nak", chunk=chunk),
+                  f"chunk {chunk}")
+
+
+def test_corrupt_stream_rejected(torch_cuda):
+    from paper_2311_12133_amd import binding
+    x = fields.random_field((20, 20, 20), 2, np.float32, "smooth")
+    cfg = make_cfg(x.shape)
+    s = binding.compress(torch_cuda.from_numpy(x).cuda(), cfg)
+    bad = s.clone()
+    bad[0] ^= 0xFF
+    with pytest.raises(binding.HpezError):
+        binding.decompress(bad)
+    with pytest.raises(binding.HpezError):
+        binding.decompress(s[: s.numel() - 8])
+
+
+def test_nonfinite_rejected(torch_cuda):
+    from paper_2311_12133_amd import binding
+    x = fields.random_field((10, 10, 10), 2, np.float32, "smooth")
+    x[3, 4, 5] = np.nan
+    with pytest.raises(binding.HpezError):
+        binding.compress(torch_cuda.from_numpy(x).cuda(), make_cfg(x.shape))
