@@ -1,0 +1,232 @@
+"""Benchmark: compress/decompress throughput of the HPEZ hot path on one MI355X.
+
+Workload: one 512^3 float32 field, exp(1.5 g) of a unit-variance Gaussian
+field g with E(k) ~ k^-5/3 (heavy-tailed, density-like; stands in for the
+paper's 512^3 turbulence volume), value-range-relative bound 1e-3.  A step is
+one pass of the whole hot path over the field: auto-tuning (Sec. 6) when the
+library provides it, compression (prediction, quantization, histogram,
+Huffman) and decompression.  Inputs are resident in HBM before the timed
+region; every step runs on one stream and is bracketed by synchronisation.
+
+Prints one JSON line.  `value` is input bytes / step time (GB/s).  Per-phase
+rates, the roofline of the dominant kernel group (timed live with HIP events
+inside the library over the timed steps) and the CPU oracle's rate on a
+bounded sample of the same field are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--shape 512,512,512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def default_levels(kind: int, ndims: int):
+    return [dict(kind=kind, md=0, same_level=0, order=tuple(range(ndims)) +
+                 tuple(range(ndims, 4)))] * 16
+
+
+def base_config(shape, eb):
+    nd = len(shape)
+    big = sum(1 for s in shape if s > 1)
+    return dict(dtype="f32", dims=tuple(shape), eb=eb, eb_mode="rel", predictor="interp",
+                anchor_log2=6 if big >= 3 else 7 if big == 2 else 8, frozen_dim=-1,
+                block_log2=0, radius=32768, chunk=1024, alpha=1.0, beta=1.0,
+                md_w=[[1.0] * 4 for _ in range(3)], levels=default_levels(1, nd), cand=[],
+                block_cfg=None)
+
+
+TUNE_OPTS = dict(global_rate=0.01, sub_rate=0.04, lorenzo_coef=1.0, block_log2=5,
+                 allow_freeze=1, allow_lorenzo=1, block_wise=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--shape", default="512,512,512")
+    ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build measures "
+              "the single-GPU path only.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2311_12133_amd import binding, fields
+
+    shape = tuple(int(v) for v in args.shape.split(","))
+    log("generating field", shape)
+    t0 = time.time()
+    x = fields.lognormal_field(shape)
+    log(f"field ready in {time.time() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    xt = torch.from_numpy(x).to(dev)
+    torch.cuda.synchronize()
+    nbytes = x.nbytes
+    cfg0 = base_config(shape, args.eb)
+    cap = binding.compress_bound(shape, "f32", cfg0)
+    out = torch.empty(cap, dtype=torch.uint8, device=dev)
+    rec = torch.empty_like(xt)
+
+    have_tune = True
+    try:
+        binding.tune(xt, cfg0, TUNE_OPTS)
+    except binding.HpezError as e:
+        if e.code != -6:
+            raise
+        have_tune = False
+        log("library tuner unavailable: fixed not-a-knot configuration")
+
+    def step():
+        ta = time.perf_counter()
+        cfg = binding.tune(xt, cfg0, TUNE_OPTS) if have_tune else cfg0
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        s = binding.compress(xt, cfg, out=out)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        binding.decompress(s, out=rec)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        return (tb - ta, tc - tb, td - tc, int(s.numel()), cfg)
+
+    for i in range(args.warmup):
+        r = step()
+        log(f"warmup {i}: tune {r[0]*1e3:.2f} ms compress {r[1]*1e3:.2f} ms "
+            f"decompress {r[2]*1e3:.2f} ms ratio {nbytes / r[3]:.2f}")
+
+    binding.profile_enable(0, True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    times = []
+    for i in range(args.steps):
+        times.append(step())
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    stats = binding.profile_read(0)
+    binding.profile_enable(0, False)
+    log(f"timed {args.steps} steps in {t_total:.3f} s")
+
+    # correctness of the last round trip at full size: the bound on every point
+    e = args.eb * (float(x.max()) - float(x.min()))
+    err = (rec.double() - xt.double()).abs().max().item()
+    if not err <= e:
+        raise SystemExit(f"error bound violated: {err} > {e}")
+
+    tune_s = sum(t[0] for t in times) / len(times)
+    comp_s = sum(t[1] for t in times) / len(times)
+    dec_s = sum(t[2] for t in times) / len(times)
+    ms_step = t_total / args.steps * 1e3
+    size = times[-1][3]
+    cfg_used = times[-1][4]
+
+    # roofline of the dominant kernel group
+    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    name, st = dom
+    per_launch_bytes = st["bytes"] / st["launches"]
+    per_launch_ms = st["ms"] / st["launches"]
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBPS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                    avg_ms=round(per_launch_ms, 4), bytes_per_launch=int(per_launch_bytes))
+    groups = {k: dict(ms_per_step=round(v["ms"] / args.steps, 4),
+                      GBps=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
+              for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(x, cfg_used, nbytes)
+
+    res = {
+        "metric": "compress/decompress GB/s (fp32, rel eb 1e-3) and batched-vs-plain speedup",
+        "value": round(nbytes / (ms_step * 1e-3) / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"lognormal exp(1.5 g), g ~ k^-5/3, {'x'.join(map(str, shape))} "
+                               f"float32, rel eb {args.eb:g}, "
+                               f"{'tune + ' if have_tune else 'fixed not-a-knot config, '}"
+                               "compress + decompress",
+                   "shape": list(shape), "eb_rel": args.eb, "tuned": have_tune},
+        "compress_GBps": round(nbytes / comp_s / 1e9, 3),
+        "decompress_GBps": round(nbytes / dec_s / 1e9, 3),
+        "tune_ms": round(tune_s * 1e3, 3),
+        "compress_ms": round(comp_s * 1e3, 3),
+        "decompress_ms": round(dec_s * 1e3, 3),
+        "compression_ratio": round(nbytes / size, 3),
+        "bits_per_value": round(size * 8 / x.size, 4),
+        "max_err_over_eb": round(err / e, 6),
+        "roofline": roofline,
+        "kernel_groups": groups,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+def cpu_baseline(x, cfg, nbytes):
+    """The oracle (single-threaded C, as it stands) on a bounded slab of the same
+    field: compress + decompress, reported as input GB/s like `value`."""
+    from oracle import oracle as O
+    import numpy as np
+    planes = x.shape[0]
+    probe = max(1, min(planes, 16))
+    c = dict(cfg)
+    c["dims"] = (probe,) + tuple(x.shape[1:])
+    c["block_cfg"] = None if not cfg.get("block_log2") else _slab_blocks(cfg, x.shape, probe)
+    t = time.perf_counter()
+    s = O.compress(np.ascontiguousarray(x[:probe]), c)
+    O.decompress(s)
+    dt = time.perf_counter() - t
+    per_plane = dt / probe
+    take = int(min(planes, max(probe, 15.0 / max(per_plane, 1e-9))))
+    if take > probe:
+        c["dims"] = (take,) + tuple(x.shape[1:])
+        c["block_cfg"] = None if not cfg.get("block_log2") else _slab_blocks(cfg, x.shape, take)
+        sl = np.ascontiguousarray(x[:take])
+        t = time.perf_counter()
+        s = O.compress(sl, c)
+        O.decompress(s)
+        dt = time.perf_counter() - t
+    else:
+        take = probe
+    b = x[:take].nbytes
+    log(f"oracle: {take} planes, {dt:.2f} s")
+    return dict(value=round(b / dt / 1e9, 5), unit="GB/s", cores=1, kind="oracle",
+                sample=f"first {take} of {x.shape[0]} planes ({b / 1e6:.0f} MB), same config, "
+                       "compress + decompress, single thread", seconds=round(dt, 2))
+
+
+def _slab_blocks(cfg, shape, planes):
+    import numpy as np
+    B = 1 << cfg["block_log2"]
+    nb = [(n + B - 1) // B for n in shape]
+    full = np.asarray(cfg["block_cfg"], dtype=np.uint8).reshape(nb)
+    return np.ascontiguousarray(full[: (planes + B - 1) // B]).reshape(-1)
+
+
+if __name__ == "__main__":
+    main()

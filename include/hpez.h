@@ -191,6 +191,23 @@ int hpez_tune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
  * such a field, beyond the caller's input and output buffers.  Pure. */
 int hpez_footprint(const hpez_field_desc* desc, const hpez_config* cfg, int op, uint64_t* bytes);
 
+/* Per-kernel timing (tracing aid).  While enabled, every kernel group the
+ * context launches is bracketed by HIP events on its stream; each entry point
+ * folds the elapsed times into per-name totals before returning.  `bytes` is
+ * the algorithmic HBM traffic of the group (what the method must move: inputs
+ * read once, outputs written once), so bytes / time is the achieved rate
+ * against the HBM roofline.  Enabling clears the totals. */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  uint64_t bytes;
+  double total_ms;
+} hpez_kernel_stat;
+
+int hpez_profile_enable(hpez_ctx* ctx, int on);
+/* Copy up to cap entries into out; *n receives the number of entries. */
+int hpez_profile_read(hpez_ctx* ctx, hpez_kernel_stat* out, int cap, int* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,9 +53,14 @@ class TuneOpts(C.Structure):
                 ("block_wise", C.c_uint8), ("anchor_log2", C.c_uint8), ("pad", C.c_uint8 * 3)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("bytes", C.c_uint64),
+                ("total_ms", C.c_double)]
+
+
 EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_default",
            "hpez_compress_bound", "hpez_compress", "hpez_inspect", "hpez_decompress",
-           "hpez_tune", "hpez_footprint"]
+           "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read"]
 
 _lib = None
 _lock = threading.Lock()
@@ -83,6 +88,8 @@ def lib():
             L.hpez_decompress.argtypes = [vp, vp, u64, vp, u64, vp]
             L.hpez_tune.argtypes = [vp, P(FieldDesc), vp, P(TuneOpts), P(Config), vp, u64, vp]
             L.hpez_footprint.argtypes = [P(FieldDesc), P(Config), C.c_int, P(u64)]
+            L.hpez_profile_enable.argtypes = [vp, C.c_int]
+            L.hpez_profile_read.argtypes = [vp, P(KernelStat), C.c_int, P(C.c_int)]
             _lib = L
     return _lib
 
@@ -285,3 +292,18 @@ def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
     res["cand"] = [interp_dict(c.cand[i]) for i in range(c.n_cand)]
     res["block_cfg"] = bc[:nb].copy() if c.block_log2 else None
     return res
+
+
+def profile_enable(device: int = 0, on: bool = True):
+    """Start (clearing totals) or stop per-kernel event timing in the library."""
+    _check(lib().hpez_profile_enable(ctx(device), int(on)), "hpez_profile_enable")
+
+
+def profile_read(device: int = 0):
+    """Per-kernel-group totals: {name: dict(launches, bytes, ms)}."""
+    n = C.c_int()
+    _check(lib().hpez_profile_read(ctx(device), None, 0, C.byref(n)), "hpez_profile_read")
+    arr = (KernelStat * max(n.value, 1))()
+    _check(lib().hpez_profile_read(ctx(device), arr, n.value, C.byref(n)), "hpez_profile_read")
+    return {arr[i].name.decode(): dict(launches=int(arr[i].launches), bytes=int(arr[i].bytes),
+                                       ms=float(arr[i].total_ms)) for i in range(n.value)}

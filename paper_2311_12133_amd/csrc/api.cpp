@@ -19,13 +19,86 @@
 
 using namespace hpez;
 
+struct ProfRec {
+  hipEvent_t a, b;
+  const char* name;
+  uint64_t bytes;
+};
+
 struct hpez_ctx {
   int device = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   uint8_t* pinned = nullptr;
   size_t pinned_bytes = 0;
+  // kernel timing (hpez_profile_enable)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<ProfRec> pend;
+  std::vector<hpez_kernel_stat> stats;
+
+  hipEvent_t take_event()
+  {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
 };
+
+namespace {
+
+// Brackets a group of kernel launches with events while profiling is on.
+struct Span {
+  hpez_ctx* c;
+  hipStream_t st;
+  const char* name;
+  uint64_t bytes;
+  hipEvent_t a = nullptr;
+  Span(hpez_ctx* c_, const char* name_, uint64_t bytes_, hipStream_t st_)
+      : c(c_), st(st_), name(name_), bytes(bytes_)
+  {
+    if (c && c->prof) {
+      a = c->take_event();
+      if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+    }
+  }
+  ~Span()
+  {
+    if (!a) return;
+    hipEvent_t b = c->take_event();
+    if (b && hipEventRecord(b, st) == hipSuccess) c->pend.push_back({a, b, name, bytes});
+  }
+};
+
+// Fold finished spans into the per-name totals (call after a stream sync).
+void prof_collect(hpez_ctx* c)
+{
+  for (const ProfRec& r : c->pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    hpez_kernel_stat* s = nullptr;
+    for (auto& x : c->stats)
+      if (std::strncmp(x.name, r.name, sizeof x.name) == 0) s = &x;
+    if (!s) {
+      hpez_kernel_stat z;
+      std::memset(&z, 0, sizeof z);
+      std::strncpy(z.name, r.name, sizeof z.name - 1);
+      c->stats.push_back(z);
+      s = &c->stats.back();
+    }
+    s->launches++;
+    s->bytes += r.bytes;
+    s->total_ms += ms;
+  }
+  c->pend.clear();
+  c->ev_used = 0;
+}
+
+}  // namespace
 
 namespace hpez {
 
@@ -537,16 +610,30 @@ size_t ws_need(uint64_t N, uint64_t s, uint32_t R, uint32_t chunk, uint64_t nb, 
   return b;
 }
 
+// points of the grid of stride s (multiples of s on active dims)
+uint64_t grid_points(const Geom& g, int64_t s)
+{
+  uint64_t p = 1;
+  for (int d = 0; d < 4; d++) p *= g.act[d] ? (uint64_t)((g.n[d] - 1) / s + 1) : (uint64_t)g.n[d];
+  return p;
+}
+
 template <typename T>
-int run_levels(const hpez_field_desc* d, const hpez_config* c, const Geom& g, double e,
-               const T* X, T* W, uint16_t* code, const uint8_t* d_bcfg, const double* d_wq,
-               const double* h_wq, int mode, hipStream_t st)
+int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, const Geom& g,
+               double e, const T* X, T* W, uint16_t* code, const uint8_t* d_bcfg,
+               const double* d_wq, const double* h_wq, int mode, hipStream_t st)
 {
   const int L = c->anchor_log2;
   const int64_t B = c->block_log2 ? (int64_t)1 << c->block_log2 : 0;
   const int nact = n_active(g);
   for (int l = L; l >= 1; l--) {
     const int64_t s = (int64_t)1 << (l - 1);
+    // algorithmic traffic of the level: each of its points reads its value
+    // (original or code) once and writes its code or reconstruction once
+    const uint64_t pts = grid_points(g, s) - grid_points(g, 2 * s);
+    Span span(ctx, mode == 0 ? (l == 1 ? "predict_l1" : "predict_coarse")
+                             : (l == 1 ? "reconstruct_l1" : "reconstruct_coarse"),
+              pts * (sizeof(T) + 2), st);
     const double el = level_eb(e, c->alpha, c->beta, l);
     const double inv2e = 1.0 / (2.0 * el), twoe = 2.0 * el;
     const hpez_interp& ip = c->level[l - 1];
@@ -700,8 +787,11 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   // --- error bound (Sec. 7.1.3) and the non-finite check
   const int mblocks = 1024;
   HIPCK(hipMemsetAsync(bad, 0, sizeof(int), st));
-  HIPCK(launch_minmax<T>(X, N, part, bad, mblocks, st));
-  HIPCK(launch_minmax_final(part, mblocks, mm, st));
+  {
+    Span sp(ctx, "minmax", N * s, st);
+    HIPCK(launch_minmax<T>(X, N, part, bad, mblocks, st));
+    HIPCK(launch_minmax_final(part, mblocks, mm, st));
+  }
   HIPCK(hipMemcpyAsync(h_mm, mm, 16, hipMemcpyDeviceToHost, st));
   HIPCK(hipMemcpyAsync(h_bad, bad, 4, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
@@ -747,12 +837,15 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   const Lattice al = anchor_lattice(g, c->anchor_log2);
   Lo.n_anchor = al.total;
   HIPCK(launch_anchors<T>(g, al, X, W, code, anc, c->radius, 0, st));
-  rc = run_levels<T>(d, c, g, e, X, W, code, dbcfg, dwq, h_wq, 0, st);
+  rc = run_levels<T>(ctx, d, c, g, e, X, W, code, dbcfg, dwq, h_wq, 0, st);
   if (rc) return rc;
 
   // --- histogram and codebook (Sec. 4 step 4)
   HIPCK(hipMemsetAsync(hist, 0, (size_t)nsym * 4, st));
-  HIPCK(launch_histogram(code, N, hist, nsym, c->radius, st));
+  {
+    Span sp(ctx, "histogram", N * 2, st);
+    HIPCK(launch_histogram(code, N, hist, nsym, c->radius, st));
+  }
   HIPCK(hipMemcpyAsync(h_hist, hist, (size_t)nsym * 4, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   rc = huffman_lengths(h_hist, nsym, h_len);
@@ -782,13 +875,20 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   if (Lo.sym_max >= Lo.sym_min)
     HIPCK(hipMemcpyAsync(out + Lo.off_len, h_len + Lo.sym_min, Lo.sym_max - Lo.sym_min + 1,
                          hipMemcpyHostToDevice, st));
-  HIPCK(launch_chunk_lengths(code, N, c->chunk, dlen, cbits, czero, st));
-  HIPCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, tmp1, st));
-  HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
-  HIPCK(launch_encode<T>(code, N, c->chunk, dlen, dcw, boff, zoff, cbits, czero,
-                         (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), X,
-                         (T*)(out + Lo.off_unpred), st));
+  {
+    Span sp(ctx, "encode_lengths", N * 2, st);
+    HIPCK(launch_chunk_lengths(code, N, c->chunk, dlen, cbits, czero, st));
+    HIPCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, tmp1, st));
+    HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
+  }
+  {
+    Span sp(ctx, "encode", N * 2 + (bits + 7) / 8, st);
+    HIPCK(launch_encode<T>(code, N, c->chunk, dlen, dcw, boff, zoff, cbits, czero,
+                           (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), X,
+                           (T*)(out + Lo.off_unpred), st));
+  }
   HIPCK(hipStreamSynchronize(st));
+  prof_collect(ctx);
   *out_size = Lo.total;
   return HPEZ_OK;
 }
@@ -873,10 +973,17 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   HIPCK(hipMemcpyAsync(dwq, h_wq, sizeof h_wq, hipMemcpyHostToDevice, st));
   HIPCK(hipMemsetAsync(status, 0, sizeof(int), st));
   // chunk offsets, decode
-  HIPCK(launch_u16_to_u32((const uint16_t*)(in + Lo.off_chunks), nch, cbits, st));
-  HIPCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, tmp1, st));
-  HIPCK(launch_decode<T>((const uint32_t*)(in + Lo.off_payload), Lo.payload_bits, boff, N, c->chunk,
-                         dlut, dfirst, dcount, doffset, dsorted, code, czero, status, st));
+  {
+    Span sp(ctx, "decode_offsets", nch * 2, st);
+    HIPCK(launch_u16_to_u32((const uint16_t*)(in + Lo.off_chunks), nch, cbits, st));
+    HIPCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, tmp1, st));
+  }
+  {
+    Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
+    HIPCK(launch_decode<T>((const uint32_t*)(in + Lo.off_payload), Lo.payload_bits, boff, N,
+                           c->chunk, dlut, dfirst, dcount, doffset, dsorted, code, czero, status,
+                           st));
+  }
   HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
   if (Lo.n_unpred)
     HIPCK(launch_scatter_unpred<T>(code, N, c->chunk, czero, zoff, (const T*)(in + Lo.off_unpred),
@@ -884,12 +991,13 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   const Lattice al = anchor_lattice(g, c->anchor_log2);
   if (al.total != Lo.n_anchor) return HPEZ_ECORRUPT;
   HIPCK(launch_anchors<T>(g, al, nullptr, out, code, (T*)(in + Lo.off_anchor), c->radius, 1, st));
-  rc = run_levels<T>(d, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq, 1, st);
+  rc = run_levels<T>(ctx, d, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq, 1, st);
   if (rc) return rc;
   uint64_t h_tot[2];
   HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCK(hipMemcpyAsync(&h_tot[0], zoff + nch, 8, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
+  prof_collect(ctx);
   if (*h_status) return HPEZ_ECORRUPT;
   if (h_tot[0] != Lo.n_unpred) return HPEZ_ECORRUPT;
   return HPEZ_OK;
@@ -922,6 +1030,7 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   DevScope ds(ctx->device);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -1023,6 +1132,24 @@ int hpez_decompress(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_o
   if (d.dtype == HPEZ_F32)
     return decompress_t<float>(ctx, &d, &c, L, (const uint8_t*)d_in, (float*)d_out, stream);
   return decompress_t<double>(ctx, &d, &c, L, (const uint8_t*)d_in, (double*)d_out, stream);
+}
+
+int hpez_profile_enable(hpez_ctx* ctx, int on)
+{
+  if (!ctx) return HPEZ_EINVAL;
+  ctx->prof = on != 0;
+  ctx->stats.clear();
+  ctx->pend.clear();
+  ctx->ev_used = 0;
+  return HPEZ_OK;
+}
+
+int hpez_profile_read(hpez_ctx* ctx, hpez_kernel_stat* out, int cap, int* n)
+{
+  if (!ctx || !n || (cap > 0 && !out)) return HPEZ_EINVAL;
+  *n = (int)ctx->stats.size();
+  for (int i = 0; i < cap && i < *n; i++) out[i] = ctx->stats[i];
+  return HPEZ_OK;
 }
 
 int hpez_tune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,

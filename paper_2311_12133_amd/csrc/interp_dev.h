@@ -1,0 +1,97 @@
+// interp_dev.h -- device-side spline stencils and quantizer shared by the
+// predictor kernels and the tuner's trial kernels (gfx950).
+//
+// Floating point: the stencils are evaluated in T in the order written, the
+// quantizer in double; the library is built with -ffp-contract=off so no
+// operation is fused.
+#pragma once
+
+#include "hpez_internal.h"
+
+namespace hpez {
+
+template <typename T>
+struct SplineK;
+template <>
+struct SplineK<float> {
+  static __device__ __forceinline__ float k6() { return 0x1.555556p-3f; }
+  static __device__ __forceinline__ float k40() { return 0x1.99999ap-6f; }
+  static __device__ __forceinline__ float k62() { return 0x1.084210p-6f; }
+};
+template <>
+struct SplineK<double> {
+  static __device__ __forceinline__ double k6() { return 0x1.5555555555555p-3; }
+  static __device__ __forceinline__ double k40() { return 0x1.999999999999ap-6; }
+  static __device__ __forceinline__ double k62() { return 0x1.0842108421084p-6; }
+};
+
+// One-dimensional spline prediction along a dimension with index step sd = s *
+// stride, for a point at coordinate x whose usable neighbours lie in [lo, hi].
+// Interior stencils: Eq. (2) linear, Eq. (6) not-a-knot, Eq. (8) natural,
+// Eq. (13)/(14) same-level.  At the grid (or block) end the Lagrange polynomial
+// through the neighbours that exist is used.
+template <typename T, typename P>
+__device__ __forceinline__ T spline(const P* __restrict__ W, int64_t idx, int64_t sd, int64_t x,
+                                    int64_t s, int64_t lo, int64_t hi, int kind, int sl)
+{
+  const bool ha = x - 3 * s >= lo;
+  const bool hc = x + s <= hi;
+  const bool hd = x + 3 * s <= hi;
+  const T b = W[idx - sd];
+  if (kind == 0) {
+    if (hc) return (b + (T)W[idx + sd]) * (T)0.5;
+    if (ha) return (b * (T)3 - (T)W[idx - 3 * sd]) * (T)0.5;
+    return b;
+  }
+  if (sl) {
+    const bool ha2 = x - 2 * s >= lo;
+    const bool hd2 = x + 2 * s <= hi;
+    if (kind == 1 && ha2 && hc && hd2)
+      return ((b + (T)W[idx + sd]) * (T)4 - ((T)W[idx - 2 * sd] + (T)W[idx + 2 * sd])) *
+             SplineK<T>::k6();
+    if (kind == 2 && ha && ha2 && hc && hd2 && hd)
+      return ((b + (T)W[idx + sd]) * (T)46 - ((T)W[idx - 2 * sd] + (T)W[idx + 2 * sd]) * (T)18 +
+              ((T)W[idx - 3 * sd] + (T)W[idx + 3 * sd]) * (T)3) *
+             SplineK<T>::k62();
+  }
+  if (ha && hc && hd) {
+    const T a = W[idx - 3 * sd], c = W[idx + sd], d = W[idx + 3 * sd];
+    if (kind == 1) return ((b + c) * (T)9 - (a + d)) * (T)0.0625;
+    return ((b + c) * (T)23 - (a + d) * (T)3) * SplineK<T>::k40();
+  }
+  if (hc && hd) return (b * (T)3 + (T)W[idx + sd] * (T)6 - (T)W[idx + 3 * sd]) * (T)0.125;
+  if (ha && hc) return (b * (T)6 + (T)W[idx + sd] * (T)3 - (T)W[idx - 3 * sd]) * (T)0.125;
+  if (hc) return (b + (T)W[idx + sd]) * (T)0.5;
+  if (ha) return (b * (T)3 - (T)W[idx - 3 * sd]) * (T)0.5;
+  return b;
+}
+
+// Linear-scale quantization (Sec. 4, step 3): bins of width 2 e_l, rounding
+// half away from zero, radius R, double arithmetic; the value the decompressor
+// will rebuild must meet the bound or the point is stored verbatim (code 0).
+template <typename T>
+__device__ __forceinline__ uint32_t quantize(T x, T p, double inv2e, double twoe, double el,
+                                             uint32_t R, T& xr)
+{
+  const double t = ((double)x - (double)p) * inv2e;
+  const double qf = floor(fabs(t) + 0.5);
+  if (!(qf < (double)R)) return 0;
+  const double q = t < 0 ? -qf : qf;
+  const T r = (T)((double)p + q * twoe);
+  if (!(fabs((double)r - (double)x) <= el)) return 0;
+  xr = r;
+  return (uint32_t)((int64_t)q + (int64_t)R);
+}
+
+__device__ __forceinline__ void lattice_point(const Lattice& L, uint64_t k, int64_t* x)
+{
+  uint64_t r = k;
+  for (int d = 3; d >= 0; d--) {
+    const uint64_t c = L.cnt[d];
+    const uint64_t q = r / c;
+    x[d] = L.first[d] + (int64_t)(r - q * c) * L.step[d];
+    r = q;
+  }
+}
+
+}  // namespace hpez

@@ -1,0 +1,333 @@
+// k_tune.hip -- auto-tuner kernels (Sec. 6), gfx950.
+//
+//  * stats_kernel: the sampling statistics of Sec. 6.1 -- open-loop 1D linear,
+//    not-a-knot and natural prediction errors along every dimension on a
+//    sparse lattice, accumulated as integer sums of squared fixed-point errors.
+//  * trial_kernel: closed-loop trial compressions of Sec. 6.2/6.3/6.6.  One
+//    work-group per (region, candidate) runs the whole level schedule of the
+//    region treated as a small field (its own anchors), predicting,
+//    quantizing and writing reconstructions exactly as compression does, and
+//    sums the integer error score per level (or per region); optionally it
+//    histograms the codes for the size estimate.  Steps are separated by
+//    work-group barriers; the region's working grid lives in LDS when it fits.
+//  * lorenzo_trial_kernel: codes of the first-order Lorenzo predictor on the
+//    same regions (Sec. 6.5), histogrammed.
+// All scores are integers, so decisions are independent of summation order.
+
+#include "interp_dev.h"
+#include "tune_dev.h"
+
+namespace hpez {
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) stats_kernel(const T* __restrict__ X, Geom g, Lattice lat,
+                                                    double mul, unsigned long long* __restrict__ sums)
+{
+  unsigned long long acc[3][4];
+  for (int k = 0; k < 3; k++)
+    for (int d = 0; d < 4; d++) acc[k][d] = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < lat.total; k += stride) {
+    int64_t x[4];
+    lattice_point(lat, k, x);
+    const int64_t idx = x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3];
+    const T xv = X[idx];
+    for (int d = 0; d < 4; d++) {
+      if (!g.act[d]) continue;
+      const int64_t sd = g.st[d];
+      const T a = X[idx - 3 * sd], b = X[idx - sd], c = X[idx + sd], dd = X[idx + 3 * sd];
+      T p[3];
+      p[0] = (b + c) * (T)0.5;
+      p[1] = ((b + c) * (T)9 - (a + dd)) * (T)0.0625;
+      p[2] = ((b + c) * (T)23 - (a + dd) * (T)3) * SplineK<T>::k40();
+      for (int kk = 0; kk < 3; kk++) {
+        const double t = fabs((double)xv - (double)p[kk]) * mul;
+        const unsigned long long q = (t < 1048576.0) ? (unsigned long long)floor(t) : 1048576ull;
+        acc[kk][d] += q * q;
+      }
+    }
+  }
+  __shared__ unsigned long long red[256];
+  for (int k = 0; k < 3; k++)
+    for (int d = 0; d < 4; d++) {
+      if (!g.act[d]) continue;
+      const unsigned long long v = block_sum_u64(acc[k][d], red);
+      if (threadIdx.x == 0 && v) atomicAdd(&sums[k * 4 + d], v);
+    }
+}
+
+template <typename T>
+hipError_t launch_stats(const T* X, const Geom& g, const Lattice& lat, double mul,
+                        unsigned long long* d_sums, hipStream_t st)
+{
+  if (lat.total == 0) return hipSuccess;
+  uint64_t b = (lat.total + 255) / 256;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL((stats_kernel<T>), dim3((unsigned)b), dim3(256), 0, st, X, g, lat, mul, d_sums);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// one step of a trial over a region-local lattice
+template <typename T, typename P>
+__device__ void trial_step(const TrialArgs& a, const TrialBox& bx, const int64_t* bst,
+                           const T* __restrict__ X, P* W, const int64_t* r, const int64_t* m,
+                           int kind, int md, int sl, int pd, unsigned odd, int64_t s, int level,
+                           const double* __restrict__ wq, unsigned long long& score,
+                           uint32_t* __restrict__ hist)
+{
+  uint32_t cnt[4];
+  uint64_t total = 1;
+  for (int d = 0; d < 4; d++) {
+    cnt[d] = r[d] <= bx.m[d] - 1 ? (uint32_t)((bx.m[d] - 1 - r[d]) / m[d] + 1) : 0;
+    total *= cnt[d];
+  }
+  const double el = a.el[level], inv2e = a.inv2e[level], twoe = a.twoe[level];
+  for (uint64_t k = threadIdx.x; k < total; k += blockDim.x) {
+    int64_t x[4];
+    uint64_t rr = k;
+    for (int d = 3; d >= 0; d--) {
+      const uint64_t q = rr / cnt[d];
+      x[d] = r[d] + (int64_t)(rr - q * cnt[d]) * m[d];
+      rr = q;
+    }
+    const int64_t idx = x[0] * bst[0] + x[1] * bst[1] + x[2] * bst[2] + x[3];
+    const int64_t fidx = (bx.o[0] + x[0]) * a.fg.st[0] + (bx.o[1] + x[1]) * a.fg.st[1] +
+                         (bx.o[2] + x[2]) * a.fg.st[2] + (bx.o[3] + x[3]);
+    T p;
+    if (!md) {
+      p = spline<T, P>(W, idx, s * bst[pd], x[pd], s, 0, bx.m[pd] - 1, kind, sl);
+    } else {
+      bool first = true;
+      T acc = (T)0;
+      for (int d = 0; d < 4; d++) {
+        if (!(odd >> d & 1u)) continue;
+        const T pv = spline<T, P>(W, idx, s * bst[d], x[d], s, 0, bx.m[d] - 1, kind, 0);
+        const T term = (T)wq[(kind * 16 + odd) * 4 + d] * pv;
+        acc = first ? term : acc + term;
+        first = false;
+      }
+      p = acc;
+    }
+    const T xv = X[fidx];
+    const double t = fabs((double)xv - (double)p) * a.score_mul;
+    score += (t < 4294967296.0) ? (unsigned long long)floor(t) : 4294967296ull;
+    T xr = xv;
+    const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, a.R, xr);
+    W[idx] = q ? xr : xv;
+    if (hist) atomicAdd(&hist[q], 1u);
+  }
+}
+
+template <typename T, typename P>
+__device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __restrict__ X, P* W,
+                           int cand, const double* __restrict__ wq,
+                           unsigned long long* __restrict__ score, uint32_t* __restrict__ hist)
+{
+  __shared__ unsigned long long red[256];
+  int32_t act[4];
+  int64_t bst[4];
+  bst[3] = 1;
+  for (int d = 2; d >= 0; d--) bst[d] = bst[d + 1] * bx.m[d + 1];
+  int nact = 0;
+  for (int d = 0; d < 4; d++) {
+    act[d] = (bx.m[d] > 1 && d != a.frozen) ? 1 : 0;
+    nact += act[d];
+  }
+  const int64_t npts = bst[0] * bx.m[0];
+  const int64_t A = (int64_t)1 << a.L;
+  // anchors
+  for (int64_t i = threadIdx.x; i < npts; i += blockDim.x) {
+    int64_t x[4];
+    int64_t rr = i;
+    bool anc = true;
+    for (int d = 3; d >= 0; d--) {
+      x[d] = rr % bx.m[d];
+      rr /= bx.m[d];
+      if (act[d] && x[d] % A != 0) anc = false;
+    }
+    if (anc) {
+      const int64_t fidx = (bx.o[0] + x[0]) * a.fg.st[0] + (bx.o[1] + x[1]) * a.fg.st[1] +
+                           (bx.o[2] + x[2]) * a.fg.st[2] + (bx.o[3] + x[3]);
+      W[i] = X[fidx];
+    }
+  }
+  __syncthreads();
+  unsigned long long total_score = 0;
+  for (int l = a.L; l >= 1; l--) {
+    const int64_t s = (int64_t)1 << (l - 1);
+    const hpez_interp ip = a.tuned ? a.level[l - 1] : a.cand[cand];
+    unsigned long long sc = 0;
+    int64_t r[4], m[4];
+    if (ip.md) {
+      for (int cnt = 1; cnt <= nact; cnt++) {
+        for (unsigned odd = 1; odd < 16; odd++) {
+          bool ok = __popc(odd) == cnt;
+          for (int d = 0; d < 4; d++)
+            if ((odd >> d & 1u) && !act[d]) ok = false;
+          if (!ok) continue;
+          for (int d = 0; d < 4; d++) {
+            if (!act[d]) { r[d] = 0; m[d] = 1; }
+            else if (odd >> d & 1u) { r[d] = s; m[d] = 2 * s; }
+            else { r[d] = 0; m[d] = 2 * s; }
+          }
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 1, 0, -1, odd, s, l, wq, sc, hist);
+        }
+        __syncthreads();
+      }
+    } else {
+      int pos[4] = {-1, -1, -1, -1}, np = 0;
+      for (int i = 0; i < 4; i++) {
+        const int d = ip.order[i];
+        if (d < 4 && act[d] && pos[d] < 0) pos[d] = np++;
+      }
+      for (int k = 0; k < np; k++) {
+        int pd = 0;
+        for (int d = 0; d < 4; d++)
+          if (pos[d] == k) pd = d;
+        for (int d = 0; d < 4; d++) {
+          if (!act[d]) { r[d] = 0; m[d] = 1; }
+          else if (d == pd) { r[d] = s; m[d] = 2 * s; }
+          else if (pos[d] < k) { r[d] = 0; m[d] = s; }
+          else { r[d] = 0; m[d] = 2 * s; }
+        }
+        if (ip.kind != 0 && ip.same_level) {
+          m[pd] = 4 * s;
+          r[pd] = s;
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist);
+          __syncthreads();
+          r[pd] = 3 * s;
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 1, pd, 0, s, l, wq, sc, hist);
+        } else {
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist);
+        }
+        __syncthreads();
+      }
+    }
+    const unsigned long long v = block_sum_u64(sc, red);
+    if (a.score_mode == 0) {
+      if (threadIdx.x == 0 && v) atomicAdd(&score[cand * 16 + (l - 1)], v);
+    } else {
+      total_score += v;
+    }
+  }
+  if (a.score_mode == 1 && threadIdx.x == 0) score[(uint64_t)blockIdx.x * gridDim.y + cand] = total_score;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) trial_kernel_global(TrialArgs a,
+                                                           const TrialBox* __restrict__ boxes,
+                                                           const T* __restrict__ X,
+                                                           T* __restrict__ scratch,
+                                                           const double* __restrict__ wq,
+                                                           unsigned long long* __restrict__ score,
+                                                           uint32_t* __restrict__ hist)
+{
+  const TrialBox bx = boxes[blockIdx.x];
+  T* W = scratch + ((uint64_t)blockIdx.x * gridDim.y + blockIdx.y) * a.box_cap;
+  trial_body<T, T>(a, bx, X, W, (int)blockIdx.y, wq, score, hist);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) trial_kernel_lds(TrialArgs a,
+                                                        const TrialBox* __restrict__ boxes,
+                                                        const T* __restrict__ X,
+                                                        const double* __restrict__ wq,
+                                                        unsigned long long* __restrict__ score,
+                                                        uint32_t* __restrict__ hist)
+{
+  extern __shared__ unsigned char lds_raw[];
+  T* W = reinterpret_cast<T*>(lds_raw);
+  const TrialBox bx = boxes[blockIdx.x];
+  trial_body<T, T>(a, bx, X, W, (int)blockIdx.y, wq, score, hist);
+}
+
+template <typename T>
+hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n_boxes,
+                         uint32_t n_cand, const T* X, T* scratch, const double* d_wq,
+                         unsigned long long* d_score, uint32_t* d_hist, hipStream_t st)
+{
+  if (!n_boxes || !n_cand) return hipSuccess;
+  const size_t lds = (size_t)a.box_cap * sizeof(T);
+  if (lds <= kTrialLdsBytes)
+    hipLaunchKernelGGL((trial_kernel_lds<T>), dim3(n_boxes, n_cand), dim3(256), lds, st, a, d_boxes,
+                       X, d_wq, d_score, d_hist);
+  else
+    hipLaunchKernelGGL((trial_kernel_global<T>), dim3(n_boxes, n_cand), dim3(256), 0, st, a,
+                       d_boxes, X, scratch, d_wq, d_score, d_hist);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lorenzo trial: dual-quantized first-order residuals of every region point
+template <typename T>
+__global__ void __launch_bounds__(256) lorenzo_trial_kernel(Geom fg, const TrialBox* __restrict__ boxes,
+                                                            const T* __restrict__ X, double inv2e,
+                                                            uint32_t R, uint32_t* __restrict__ hist,
+                                                            int* __restrict__ unsupported)
+{
+  const TrialBox bx = boxes[blockIdx.y];
+  const int64_t npts = (int64_t)bx.m[0] * bx.m[1] * bx.m[2] * bx.m[3];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t x[4], rr = i;
+    for (int d = 3; d >= 0; d--) {
+      x[d] = rr % bx.m[d];
+      rr /= bx.m[d];
+    }
+    long long delta = 0;
+    bool bad = false;
+    for (unsigned S = 0; S < 16; S++) {
+      bool in = true;
+      int64_t y[4];
+      for (int d = 0; d < 4; d++) {
+        y[d] = x[d] - ((S >> d) & 1u);
+        if (y[d] < 0) in = false;
+      }
+      if (!in) continue;
+      const int64_t fidx = (bx.o[0] + y[0]) * fg.st[0] + (bx.o[1] + y[1]) * fg.st[1] +
+                           (bx.o[2] + y[2]) * fg.st[2] + (bx.o[3] + y[3]);
+      const double t = (double)X[fidx] * inv2e;
+      const double qf = floor(fabs(t) + 0.5);
+      if (!(qf < 4503599627370496.0)) {
+        bad = true;
+        continue;
+      }
+      const long long v = (long long)(t < 0 ? -qf : qf);
+      delta += (__popc(S) & 1) ? -v : v;
+    }
+    if (bad) {
+      atomicOr(unsupported, 1);
+      continue;
+    }
+    const uint32_t code = (delta > -(long long)R && delta < (long long)R) ? (uint32_t)(delta + R) : 0u;
+    atomicAdd(&hist[code], 1u);
+  }
+}
+
+template <typename T>
+hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_t n_boxes,
+                                uint32_t max_pts, const T* X, double inv2e, uint32_t R,
+                                uint32_t* d_hist, int* d_unsupported, hipStream_t st)
+{
+  if (!n_boxes) return hipSuccess;
+  const unsigned gx = (max_pts + 255) / 256;
+  hipLaunchKernelGGL((lorenzo_trial_kernel<T>), dim3(gx ? gx : 1, n_boxes), dim3(256), 0, st, fg,
+                     d_boxes, X, inv2e, R, d_hist, d_unsupported);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                 \
+  template hipError_t launch_stats<T>(const T*, const Geom&, const Lattice&, double,            \
+                                      unsigned long long*, hipStream_t);                        \
+  template hipError_t launch_trials<T>(const TrialArgs&, const TrialBox*, uint32_t, uint32_t,   \
+                                       const T*, T*, const double*, unsigned long long*,        \
+                                       uint32_t*, hipStream_t);                                 \
+  template hipError_t launch_lorenzo_trial<T>(const Geom&, const TrialBox*, uint32_t, uint32_t, \
+                                              const T*, double, uint32_t, uint32_t*, int*,      \
+                                              hipStream_t);
+INST(float)
+INST(double)
+
+}  // namespace hpez

@@ -1,0 +1,59 @@
+// tune_dev.h -- shared declarations of the auto-tuner kernels (Sec. 6).
+#pragma once
+
+#include "hpez_internal.h"
+
+namespace hpez {
+
+constexpr size_t kTrialLdsBytes = 48 * 1024;  // regions up to this size run from LDS
+
+// A trial region: origin and extents inside the field.
+struct TrialBox {
+  int64_t o[4];
+  int64_t m[4];
+};
+
+struct TrialArgs {
+  Geom fg;             // field geometry (for addressing X)
+  int32_t frozen;      // frozen dim of the trial, -1 none
+  int32_t L;           // anchor_log2 of the region
+  uint32_t R;
+  int32_t tuned;       // 1: level[] per level; 0: candidate blockIdx.y on every level
+  int32_t score_mode;  // 0: score[cand][level] summed over regions; 1: score[region][cand]
+  uint32_t pad;
+  uint64_t box_cap;    // points of the largest region (scratch stride)
+  double score_mul;    // 4096 / e
+  double el[17], inv2e[17], twoe[17];
+  hpez_interp cand[16];
+  hpez_interp level[16];
+};
+
+#ifdef __HIPCC__
+// Sum over the work-group; every thread receives the total.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
+                                                            unsigned long long* red)
+{
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  const int nw = (blockDim.x + 63) / 64;
+  for (int w = 0; w < nw; w++) t += red[w];
+  return t;
+}
+#endif
+
+template <typename T>
+hipError_t launch_stats(const T* X, const Geom& g, const Lattice& lat, double mul,
+                        unsigned long long* d_sums, hipStream_t st);
+template <typename T>
+hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n_boxes,
+                         uint32_t n_cand, const T* X, T* scratch, const double* d_wq,
+                         unsigned long long* d_score, uint32_t* d_hist, hipStream_t st);
+template <typename T>
+hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_t n_boxes,
+                                uint32_t max_pts, const T* X, double inv2e, uint32_t R,
+                                uint32_t* d_hist, int* d_unsupported, hipStream_t st);
+
+}  // namespace hpez
