@@ -16,6 +16,7 @@
 
 #include "hpez_internal.h"
 #include "hpez_host.h"
+#include "lorenzo_dev.h"
 
 using namespace hpez;
 
@@ -827,7 +828,8 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   if (!(e > 0)) return HPEZ_EINVAL;
   Lo.e = e;
   Lo.predictor = c->predictor;
-  if (c->predictor != HPEZ_INTERP) return HPEZ_EUNSUPPORTED;
+  if (c->predictor == HPEZ_LORENZO)
+    return lorenzo_compress<T>(ctx, d, X, c, e, out, cap, out_size, st);
 
   // --- interpolation predictor + quantization (Sec. 5, Sec. 4 step 3)
   double h_wq[3 * 16 * 4];
@@ -902,7 +904,8 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   const uint32_t nsym = 2 * c->radius;
   const uint64_t nb = Lo.n_blocks;
   const Geom g = make_geom(d, c->frozen_dim);
-  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 1));
+  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 1) +
+                              (Lo.predictor == 1 ? N * 8 + 256 : 0));
   if (rc) return rc;
   rc = ensure_pinned(ctx, (size_t)nsym + 4096 + nb + 64);
   if (rc) return rc;
@@ -940,7 +943,6 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
     HIPCK(hipStreamSynchronize(st));
     return HPEZ_OK;
   }
-  if (Lo.predictor != 0) return HPEZ_EUNSUPPORTED;
   // code lengths and block configurations to the host
   std::memset(h_len, 0, nsym);
   if (Lo.sym_max >= Lo.sym_min)
@@ -985,6 +987,26 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
                            st));
   }
   HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
+  uint64_t h_tot[2];
+  if (Lo.predictor == 1) {
+    // Lorenzo alternative: residuals, running sums, patches
+    long long* v = bw.take<long long>(N);
+    const Geom gl = make_geom(d, -1);
+    {
+      Span sp(ctx, "lorenzo_rebuild", N * (2 + s), st);
+      HIPCK(launch_lorenzo_rebuild<T>(code, gl, N, c->radius, c->chunk, czero, zoff,
+                                      (const long long*)(in + Lo.off_outl), Lo.n_outlier,
+                                      (const uint64_t*)(in + Lo.off_pidx),
+                                      (const T*)(in + Lo.off_pval), Lo.n_patch, 2.0 * Lo.e, v, out,
+                                      status, st));
+    }
+    HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(&h_tot[0], zoff + nch, 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    prof_collect(ctx);
+    if (*h_status || h_tot[0] != Lo.n_outlier) return HPEZ_ECORRUPT;
+    return HPEZ_OK;
+  }
   if (Lo.n_unpred)
     HIPCK(launch_scatter_unpred<T>(code, N, c->chunk, czero, zoff, (const T*)(in + Lo.off_unpred),
                                    Lo.n_unpred, out, status, st));
@@ -993,7 +1015,6 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   HIPCK(launch_anchors<T>(g, al, nullptr, out, code, (T*)(in + Lo.off_anchor), c->radius, 1, st));
   rc = run_levels<T>(ctx, d, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq, 1, st);
   if (rc) return rc;
-  uint64_t h_tot[2];
   HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCK(hipMemcpyAsync(&h_tot[0], zoff + nch, 8, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
@@ -1152,13 +1173,40 @@ int hpez_profile_read(hpez_ctx* ctx, hpez_kernel_stat* out, int cap, int* n)
   return HPEZ_OK;
 }
 
-int hpez_tune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
-              const hpez_tune_opts* opts, hpez_config* out_cfg, uint8_t* h_block_cfg,
-              uint64_t block_cfg_cap, hipStream_t stream)
+}  // extern "C"
+
+// helpers for the other translation units of the runtime
+namespace hpez {
+
+void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc)
 {
-  (void)ctx; (void)desc; (void)d_in; (void)opts; (void)out_cfg; (void)h_block_cfg;
-  (void)block_cfg_cap; (void)stream;
-  return HPEZ_EUNSUPPORTED;
+  *rc = ensure_ws(c, bytes);
+  return *rc ? nullptr : c->ws;
 }
 
-}  // extern "C"
+uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc)
+{
+  *rc = ensure_pinned(c, bytes);
+  return *rc ? nullptr : c->pinned;
+}
+
+int ctx_device(hpez_ctx* c) { return c->device; }
+
+hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st)
+{
+  if (!c->prof) return nullptr;
+  hipEvent_t a = c->take_event();
+  if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+  return a;
+}
+
+void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st)
+{
+  if (!a) return;
+  hipEvent_t b = c->take_event();
+  if (b && hipEventRecord(b, st) == hipSuccess) c->pend.push_back({a, b, name, bytes});
+}
+
+void ctx_prof_collect(hpez_ctx* c) { prof_collect(c); }
+
+}  // namespace hpez

@@ -37,4 +37,33 @@ void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint32_t* f
                    uint32_t* count, uint32_t* offset, uint16_t* sorted);
 void md_table(const hpez_config* c, double* wq);
 
+// Lorenzo alternative (lorenzo.cpp): compress after the error bound is known
+template <typename T>
+int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_config* c,
+                     double e, uint8_t* out, uint64_t cap, uint64_t* out_size, hipStream_t st);
+
+// context services (api.cpp)
+void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc);
+uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc);
+int ctx_device(hpez_ctx* c);
+hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
+void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);
+void ctx_prof_collect(hpez_ctx* c);
+
+// Scope guard that makes the context's device current.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev)
+  {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard()
+  {
+    int cur = prev;
+    if (hipGetDevice(&cur) != hipSuccess) return;
+    if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 }  // namespace hpez

@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) encode_kernel(
     const uint32_t L = len[c];
     put_code(words, pos, cw[c], L);
     pos += L;
-    if (c == 0) unpred[zp++] = X[i];
+    if (c == 0 && unpred) unpred[zp++] = X[i];
   }
   if (lane == 0) out_cb[k] = (uint16_t)cbits[k];
   (void)czero;

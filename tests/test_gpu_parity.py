@@ -147,3 +147,24 @@ def test_nonfinite_rejected(torch_cuda):
     x[3, 4, 5] = np.nan
     with pytest.raises(binding.HpezError):
         binding.compress(torch_cuda.from_numpy(x).cuda(), make_cfg(x.shape))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_lorenzo(torch_cuda, dtype):
+    """Lorenzo alternative (Sec. 6.5): residual codes, outliers and patches."""
+    T = np.float32 if dtype == "f32" else np.float64
+    for shape in ((3000,), (70, 90), (33, 40, 29), (6, 7, 8, 9)):
+        x = fields.random_field(shape, 4, T, "mixed")
+        roundtrip(torch_cuda, x, make_cfg(shape, dtype=dtype, eb=1e-3, predictor="lorenzo"),
+                  f"lorenzo {shape}")
+    # small radius forces outliers
+    x = fields.random_field((40, 50, 60), 6, T, "rough")
+    s = roundtrip(torch_cuda, x, make_cfg(x.shape, dtype=dtype, eb=1e-4, predictor="lorenzo",
+                                          radius=16), "lorenzo outliers")
+    assert int(np.frombuffer(s[464:472], np.uint64)[0]) > 100
+    if dtype == "f32":
+        # values far above the bound: (float)(v * 2e) often misses -> patches
+        x = (fields.random_field((30, 40, 50), 7, np.float64, "smooth") * 1e3 + 3e6).astype(T)
+        s = roundtrip(torch_cuda, x, make_cfg(x.shape, dtype=dtype, eb=0.13, eb_mode="abs",
+                                              predictor="lorenzo"), "lorenzo patches")
+        assert int(np.frombuffer(s[472:480], np.uint64)[0]) > 10

@@ -1,0 +1,69 @@
+"""GPU parity of the auto-tuner (Sec. 6): the library's tuned configuration
+(per-level interpolators, MD weights, freeze and Lorenzo decisions, per-block
+choices) must equal the oracle's on the same inputs -- every decision is made
+from integer scores and histograms -- and compressing with it must give the
+oracle's stream byte for byte."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from cfgs import make_cfg
+from oracle import oracle as O
+from paper_2311_12133_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_12133_amd import binding
+    binding.lib()
+    return torch
+
+
+def anisotropic(n=64, seed=1):
+    rng = np.random.default_rng(seed)
+    base = fields.gaussian_field((n, n), -3.0, rng)
+    return (base[None, :, :] + 0.5 * rng.standard_normal((n, 1, 1))).astype(np.float32)
+
+
+CASES = [
+    ("fronts", lambda: fields.fronts_field((64, 96, 80)), 1e-3,
+     dict(global_rate=0.2, sub_rate=0.04)),
+    ("fronts-1pct", lambda: fields.fronts_field((96, 64, 70)), 1e-4,
+     dict(global_rate=0.5, sub_rate=0.01)),
+    ("aniso-freeze", anisotropic, 1e-3, dict(global_rate=0.25, allow_lorenzo=0)),
+    ("noise-lorenzo", lambda: fields.random_field((48, 40, 56), 9, np.float32, "rough"), 1e-4,
+     dict(global_rate=0.3, lorenzo_coef=0.5)),
+    ("plain-noblock", lambda: fields.plain_field((64, 64, 64)), 1e-4,
+     dict(global_rate=0.1, block_wise=0)),
+    ("f64", lambda: fields.fronts_field((40, 70, 66)).astype(np.float64), 1e-3,
+     dict(global_rate=0.3)),
+    ("2d", lambda: fields.turbulence_field((300, 257), 3), 1e-3, dict(global_rate=0.2)),
+    ("constant", lambda: np.full((20, 30, 40), 1.5, np.float32), 1e-3, dict()),
+]
+
+
+@pytest.mark.parametrize("name,make,eb,opts", CASES, ids=[c[0] for c in CASES])
+def test_tune_matches_oracle(torch_cuda, name, make, eb, opts):
+    from paper_2311_12133_amd import binding
+    x = make()
+    dt = "f64" if x.dtype == np.float64 else "f32"
+    print(f"[case] tune {name} shape={x.shape} dtype={dt}", flush=True)
+    cfg = make_cfg(x.shape, dtype=dt, eb=eb)
+    ref, rep = O.tune(x, cfg, opts)
+    xt = torch_cuda.from_numpy(x).cuda()
+    got = binding.tune(xt, cfg, opts)
+    for k in ("predictor", "anchor_log2", "frozen_dim", "block_log2", "md_w", "levels", "cand"):
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    if ref["block_cfg"] is None:
+        assert got["block_cfg"] is None
+    else:
+        assert np.array_equal(got["block_cfg"], ref["block_cfg"])
+    s = binding.compress(xt, got)
+    torch_cuda.cuda.synchronize()
+    assert s.cpu().numpy().tobytes() == O.compress(x, ref)
