@@ -97,6 +97,7 @@ def lib():
         L.orc_stats.argtypes = [vp, P(Params), C.c_double, vp, P(i64)]
         L.orc_tune.argtypes = [vp, P(Params), P(TuneOpts), P(Params), vp, P(TuneReport)]
         L.orc_candidates.argtypes = [C.c_int, vp]
+        L.orc_stream_order.argtypes = [P(u64), C.c_int, vp]
         _lib = L
     return _lib
 
@@ -367,3 +368,12 @@ def tune(x: np.ndarray, cfg: dict, opts: dict):
                   H=(rep.H[0], rep.H[1]), H_lorenzo=rep.H_lorenzo, frozen=rep.frozen,
                   lorenzo=rep.lorenzo)
     return out, report
+
+
+def stream_order(dims) -> np.ndarray:
+    """Row-major index of each code in stream order (brick order)."""
+    dims = list(dims)
+    d = (C.c_uint64 * 4)(*(dims + [1] * (4 - len(dims))))
+    out = np.zeros(int(np.prod(dims)), dtype=np.int64)
+    lib().orc_stream_order(d, len(dims), _ptr(out))
+    return out

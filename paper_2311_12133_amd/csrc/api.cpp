@@ -287,6 +287,7 @@ void write_header(uint8_t* h, const hpez_field_desc* d, const hpez_config* c, co
   h[43] = (uint8_t)c->frozen_dim;
   h[44] = c->block_log2;
   h[45] = (uint8_t)c->n_cand;
+  h[46] = (uint8_t)kBrickLog2;
   std::memcpy(h + 48, &c->radius, 4);
   std::memcpy(h + 52, &c->chunk, 4);
   std::memcpy(h + 56, &d->eb, 8);
@@ -334,6 +335,7 @@ int read_header(const uint8_t* h, uint64_t n, hpez_field_desc* d, hpez_config* c
   c->frozen_dim = (int8_t)h[43];
   c->block_log2 = h[44];
   c->n_cand = h[45];
+  if (h[46] != kBrickLog2 || h[47] != 0) return HPEZ_ECORRUPT;
   std::memcpy(&c->radius, h + 48, 4);
   std::memcpy(&c->chunk, h + 52, 4);
   std::memcpy(&d->eb, h + 56, 8);
@@ -887,7 +889,7 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
     Span sp(ctx, "encode", N * 2 + (bits + 7) / 8, st);
     HIPCK(launch_encode<T>(code, N, c->chunk, dlen, dcw, boff, zoff, cbits, czero,
                            (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), X,
-                           (T*)(out + Lo.off_unpred), st));
+                           (T*)(out + Lo.off_unpred), g, st));
   }
   HIPCK(hipStreamSynchronize(st));
   prof_collect(ctx);
@@ -1009,7 +1011,7 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   }
   if (Lo.n_unpred)
     HIPCK(launch_scatter_unpred<T>(code, N, c->chunk, czero, zoff, (const T*)(in + Lo.off_unpred),
-                                   Lo.n_unpred, out, status, st));
+                                   Lo.n_unpred, out, status, g, st));
   const Lattice al = anchor_lattice(g, c->anchor_log2);
   if (al.total != Lo.n_anchor) return HPEZ_ECORRUPT;
   HIPCK(launch_anchors<T>(g, al, nullptr, out, code, (T*)(in + Lo.off_anchor), c->radius, 1, st));

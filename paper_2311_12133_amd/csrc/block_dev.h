@@ -1,0 +1,61 @@
+// block_dev.h -- declarations of the block-wise kernels (k_block.hip).
+#pragma once
+
+#include "hpez_internal.h"
+
+namespace hpez {
+
+constexpr int kBlockHistWin = 8192;  // LDS histogram window of the block kernel
+
+// Compact face arrays: family e holds the planes x_e = 0, B, 2B, ... with layout
+// [plane][other dims row-major]; index = (x_e / B) * plane[e] + sum_k x_k fs[e][k].
+struct FaceGeo {
+  void* val[4];        // T values per family (nullptr for inactive dims)
+  uint16_t* code[4];   // codes per family
+  int64_t plane[4];    // points per plane
+  int64_t fs[4][4];    // strides of the other dims inside a plane (fs[e][e] = 0)
+  int64_t B;
+  int32_t blog2;
+  int32_t pad;
+};
+
+// one step of the face phase for one family d
+struct FaceStep {
+  Geom g;
+  int64_t first[4], step[4];
+  uint32_t cnt[4];     // lattice of the other dims (entry d unused)
+  uint64_t total;      // planes * product of the other counts
+  int32_t fam;
+  int32_t kind, md, sl, pdim;
+  uint32_t odd;
+  double wq[4];
+  int64_t s;
+  double el, inv2e, twoe;
+  uint32_t R;
+};
+
+struct BlockArgs {
+  Geom g;
+  int64_t nb[4];       // blocks per dim (block side 32)
+  int32_t L;           // levels handled: stride 2^(L-1) .. 1
+  uint32_t R;
+  uint32_t hist_lo;    // first symbol of the LDS histogram window
+  uint32_t pad;
+  double el_l[17], inv2e_l[17], twoe_l[17];
+  hpez_interp cand[16];
+};
+
+template <typename T>
+hipError_t launch_face_init(const FaceGeo& f, const Geom& g, const Lattice& lat, const T* W,
+                            const uint16_t* code, int mode, hipStream_t st);
+template <typename T>
+hipError_t launch_face_step(const FaceStep& a, const FaceGeo& f, const T* X, uint16_t* code,
+                            const T* out, int mode, hipStream_t st);
+template <typename T>
+size_t block_lds_bytes(const Geom& g);
+template <typename T>
+hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint16_t* code,
+                         const uint8_t* d_bcfg, const double* d_wq, uint32_t* hist, T* out,
+                         int mode, hipStream_t st);
+
+}  // namespace hpez

@@ -67,3 +67,16 @@ struct DeviceGuard {
 };
 
 }  // namespace hpez
+
+namespace hpez {
+// block-wise fast path (block.cpp)
+template <typename T>
+bool block_fast_ok(const hpez_config* c, const Geom& g);
+template <typename T>
+size_t block_fast_bytes(const Geom& g);
+template <typename T>
+int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e, const T* X,
+                   const T* Wg, uint16_t* code, const uint8_t* d_bcfg, const double* d_wq,
+                   const double* h_wq, uint32_t* hist, uint32_t hist_lo, void* area, T* out,
+                   int mode, hipStream_t st);
+}  // namespace hpez

@@ -14,6 +14,7 @@ constexpr int kHdrBytes = 512;
 constexpr uint32_t kMagic = 0x5A455048u;  // "HPEZ"
 constexpr int kLmax = 32;                 // longest Huffman codeword
 constexpr int kLutBits = 12;              // first-level decode table width
+constexpr int kBrickLog2 = 5;             // code order: bricks of 32 points per dim
 
 // Grid geometry, always padded to four dims (size-1 dims are inactive).
 struct Geom {
@@ -89,7 +90,8 @@ template <typename T>
 hipError_t launch_encode(const uint16_t* code, uint64_t n, uint32_t chunk, const uint8_t* d_len,
                          const uint32_t* d_cw, const uint64_t* bit_off, const uint64_t* zero_off,
                          const uint32_t* chunk_bits, const uint32_t* chunk_zero, uint32_t* payload,
-                         uint16_t* out_chunk_bits, const T* X, T* out_unpred, hipStream_t st);
+                         uint16_t* out_chunk_bits, const T* X, T* out_unpred, const Geom& g,
+                         hipStream_t st);
 hipError_t launch_u16_to_u32(const uint16_t* in, uint64_t n, uint32_t* out, hipStream_t st);
 template <typename T>
 hipError_t launch_decode(const uint32_t* payload, uint64_t nbits, const uint64_t* bit_off,
@@ -100,6 +102,6 @@ template <typename T>
 hipError_t launch_scatter_unpred(const uint16_t* code, uint64_t n, uint32_t chunk,
                                  const uint32_t* chunk_zero, const uint64_t* zero_off,
                                  const T* unpred, uint64_t n_unpred, T* W, int* d_status,
-                                 hipStream_t st);
+                                 const Geom& g, hipStream_t st);
 
 }  // namespace hpez

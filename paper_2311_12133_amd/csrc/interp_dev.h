@@ -83,6 +83,51 @@ __device__ __forceinline__ uint32_t quantize(T x, T p, double inv2e, double twoe
   return (uint32_t)((int64_t)q + (int64_t)R);
 }
 
+// Stream (code) order: bricks of kBrick points per dimension, clipped at the
+// grid end, in row-major order; points of a brick in row-major order.
+constexpr int64_t kBrick = 1 << kBrickLog2;
+
+__host__ __device__ __forceinline__ int64_t brick_ext(int64_t n, int64_t b)
+{
+  const int64_t r = n - b * kBrick;
+  return r < kBrick ? r : kBrick;
+}
+
+// stream position of the point with coordinates x in a grid of dims n
+__host__ __device__ __forceinline__ int64_t brick_pos(const int64_t* n, const int64_t* x)
+{
+  int64_t b[4], c[4], E[4];
+  for (int d = 0; d < 4; d++) {
+    b[d] = x[d] >> kBrickLog2;
+    c[d] = x[d] & (kBrick - 1);
+    E[d] = brick_ext(n[d], b[d]);
+  }
+  return kBrick * b[0] * (n[1] * n[2] * n[3]) + E[0] * kBrick * b[1] * (n[2] * n[3]) +
+         E[0] * E[1] * kBrick * b[2] * n[3] + E[0] * E[1] * E[2] * kBrick * b[3] +
+         ((c[0] * E[1] + c[1]) * E[2] + c[2]) * E[3] + c[3];
+}
+
+// inverse of brick_pos: coordinates of the point at stream position pos
+__host__ __device__ __forceinline__ void brick_coords(const int64_t* n, int64_t pos, int64_t* x)
+{
+  int64_t b[4], E[4], r = pos;
+  int64_t above = 1;  // product of extents of the brick slabs already fixed
+  for (int d = 0; d < 4; d++) {
+    int64_t tail = 1;
+    for (int e = d + 1; e < 4; e++) tail *= n[e];
+    const int64_t slab = above * kBrick * tail;
+    b[d] = r / slab;
+    r -= b[d] * slab;
+    E[d] = brick_ext(n[d], b[d]);
+    above *= E[d];
+  }
+  // r is the row-major index inside the brick of extents E
+  for (int d = 3; d >= 0; d--) {
+    x[d] = b[d] * kBrick + r % E[d];
+    r /= E[d];
+  }
+}
+
 __device__ __forceinline__ void lattice_point(const Lattice& L, uint64_t k, int64_t* x)
 {
   uint64_t r = k;

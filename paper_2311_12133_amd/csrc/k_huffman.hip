@@ -7,7 +7,7 @@
 // symbols; the stream stores each chunk's bit count so chunks decode in
 // parallel.
 
-#include "hpez_internal.h"
+#include "interp_dev.h"
 
 namespace hpez {
 
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(256) encode_kernel(
     const uint32_t* __restrict__ cw, const uint64_t* __restrict__ bit_off,
     const uint64_t* __restrict__ zero_off, const uint32_t* __restrict__ cbits,
     const uint32_t* __restrict__ czero, uint32_t* __restrict__ words, uint16_t* __restrict__ out_cb,
-    const T* __restrict__ X, T* __restrict__ unpred, uint64_t nch)
+    const T* __restrict__ X, T* __restrict__ unpred, uint64_t nch, Geom g)
 {
   const uint64_t k = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= nch) return;
@@ -269,7 +269,11 @@ __global__ void __launch_bounds__(256) encode_kernel(
     const uint32_t L = len[c];
     put_code(words, pos, cw[c], L);
     pos += L;
-    if (c == 0 && unpred) unpred[zp++] = X[i];
+    if (c == 0 && unpred) {
+      int64_t x[4];
+      brick_coords(g.n, (int64_t)i, x);
+      unpred[zp++] = X[x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]];
+    }
   }
   if (lane == 0) out_cb[k] = (uint16_t)cbits[k];
   (void)czero;
@@ -279,13 +283,14 @@ template <typename T>
 hipError_t launch_encode(const uint16_t* code, uint64_t n, uint32_t chunk, const uint8_t* d_len,
                          const uint32_t* d_cw, const uint64_t* bit_off, const uint64_t* zero_off,
                          const uint32_t* chunk_bits, const uint32_t* chunk_zero, uint32_t* payload,
-                         uint16_t* out_chunk_bits, const T* X, T* out_unpred, hipStream_t st)
+                         uint16_t* out_chunk_bits, const T* X, T* out_unpred, const Geom& g,
+                         hipStream_t st)
 {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return hipSuccess;
   hipLaunchKernelGGL((encode_kernel<T>), dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, code, n,
                      chunk, d_len, d_cw, bit_off, zero_off, chunk_bits, chunk_zero, payload,
-                     out_chunk_bits, X, out_unpred, nch);
+                     out_chunk_bits, X, out_unpred, nch, g);
   return hipGetLastError();
 }
 
@@ -387,7 +392,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) scatter_unpred_kernel(
     const uint16_t* __restrict__ code, uint64_t n, uint32_t chunk, const uint32_t* __restrict__ czero,
     const uint64_t* __restrict__ zero_off, const T* __restrict__ unpred, uint64_t n_unpred,
-    T* __restrict__ W, int* __restrict__ status, uint64_t nch)
+    T* __restrict__ W, int* __restrict__ status, uint64_t nch, Geom g)
 {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch || czero[k] == 0) return;
@@ -400,7 +405,9 @@ __global__ void __launch_bounds__(256) scatter_unpred_kernel(
       atomicOr(status, 1);
       return;
     }
-    W[i] = unpred[z++];
+    int64_t x[4];
+    brick_coords(g.n, (int64_t)i, x);
+    W[x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]] = unpred[z++];
   }
 }
 
@@ -408,12 +415,12 @@ template <typename T>
 hipError_t launch_scatter_unpred(const uint16_t* code, uint64_t n, uint32_t chunk,
                                  const uint32_t* chunk_zero, const uint64_t* zero_off,
                                  const T* unpred, uint64_t n_unpred, T* W, int* d_status,
-                                 hipStream_t st)
+                                 const Geom& g, hipStream_t st)
 {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return hipSuccess;
   hipLaunchKernelGGL((scatter_unpred_kernel<T>), dim3((unsigned)((nch + 255) / 256)), dim3(256), 0,
-                     st, code, n, chunk, chunk_zero, zero_off, unpred, n_unpred, W, d_status, nch);
+                     st, code, n, chunk, chunk_zero, zero_off, unpred, n_unpred, W, d_status, nch, g);
   return hipGetLastError();
 }
 
@@ -421,14 +428,14 @@ hipError_t launch_scatter_unpred(const uint16_t* code, uint64_t n, uint32_t chun
   template hipError_t launch_encode<T>(const uint16_t*, uint64_t, uint32_t, const uint8_t*,        \
                                        const uint32_t*, const uint64_t*, const uint64_t*,          \
                                        const uint32_t*, const uint32_t*, uint32_t*, uint16_t*,     \
-                                       const T*, T*, hipStream_t);                                 \
+                                       const T*, T*, const Geom&, hipStream_t);                    \
   template hipError_t launch_decode<T>(const uint32_t*, uint64_t, const uint64_t*, uint64_t,       \
                                        uint32_t, const uint32_t*, const uint32_t*,                 \
                                        const uint32_t*, const uint32_t*, const uint16_t*,          \
                                        uint16_t*, uint32_t*, int*, hipStream_t);                   \
   template hipError_t launch_scatter_unpred<T>(const uint16_t*, uint64_t, uint32_t,                \
                                                const uint32_t*, const uint64_t*, const T*,         \
-                                               uint64_t, T*, int*, hipStream_t);
+                                               uint64_t, T*, int*, const Geom&, hipStream_t);
 INST(float)
 INST(double)
 

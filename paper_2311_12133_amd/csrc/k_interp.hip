@@ -19,18 +19,18 @@
 namespace hpez {
 
 template <typename T, int MODE>
-__device__ __forceinline__ void finish(T p, int64_t idx, const T* __restrict__ X, T* __restrict__ W,
-                                       uint16_t* __restrict__ code, double el, double inv2e,
-                                       double twoe, uint32_t R)
+__device__ __forceinline__ void finish(T p, int64_t idx, int64_t cpos, const T* __restrict__ X,
+                                       T* __restrict__ W, uint16_t* __restrict__ code, double el,
+                                       double inv2e, double twoe, uint32_t R)
 {
   if (MODE == 0) {
     const T x = X[idx];
     T xr = x;
     const uint32_t q = quantize<T>(x, p, inv2e, twoe, el, R, xr);
-    code[idx] = (uint16_t)q;
+    code[cpos] = (uint16_t)q;
     W[idx] = q ? xr : x;
   } else {
-    const uint32_t q = code[idx];
+    const uint32_t q = code[cpos];
     if (q != 0) W[idx] = (T)((double)p + (double)((int64_t)q - (int64_t)R) * twoe);
   }
 }
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
       }
       p = acc;
     }
-    finish<T, MODE>(p, idx, X, W, code, a.el, a.inv2e, a.twoe, a.R);
+    finish<T, MODE>(p, idx, brick_pos(a.g.n, x), X, W, code, a.el, a.inv2e, a.twoe, a.R);
   }
 }
 
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const 
       }
       p = acc;
     }
-    finish<T, MODE>(p, idx, X, W, code, a.el, a.inv2e, a.twoe, a.R);
+    finish<T, MODE>(p, idx, brick_pos(a.g.n, x), X, W, code, a.el, a.inv2e, a.twoe, a.R);
   }
 }
 
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) anchor_kernel(Geom g, Lattice lat, const 
     if (MODE == 0) {
       const T v = X[idx];
       W[idx] = v;
-      code[idx] = (uint16_t)R;
+      code[brick_pos(g.n, x)] = (uint16_t)R;
       out_anchor[k] = v;
     } else {
       W[idx] = out_anchor[k];

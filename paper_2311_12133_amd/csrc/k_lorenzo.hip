@@ -10,7 +10,7 @@
 // along every dimension and outputs (T)(v * 2e); the rare points where that
 // misses the bound are patched verbatim.
 
-#include "hpez_internal.h"
+#include "interp_dev.h"
 #include "lorenzo_dev.h"
 
 namespace hpez {
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) lorenzo_code_kernel(const T* __restrict__
     const long long v = preq<T>(X[i], a.inv2e, bad);
     if (bad) atomicOr(bad_flag, 1);
     const long long R = a.R;
-    code[i] = (delta > -R && delta < R) ? (uint16_t)(delta + R) : (uint16_t)0;
+    code[brick_pos(g.n, x)] = (delta > -R && delta < R) ? (uint16_t)(delta + R) : (uint16_t)0;
     if (!bad && misses<T>(X[i], v, a.twoe, a.e)) atomicAdd(&pcount[i / a.chunk], 1u);
   }
 }
@@ -97,15 +97,23 @@ __global__ void __launch_bounds__(256) lorenzo_gather_kernel(
   if (k >= nch || (czero[k] == 0 && pcount[k] == 0)) return;
   const uint64_t beg = k * a.chunk;
   const uint64_t end = beg + a.chunk < n ? beg + a.chunk : n;
-  uint64_t z = zoff[k], p = poff[k];
-  for (uint64_t i = beg; i < end; i++) {
-    int64_t x[4];
-    bool bad = false;
-    if (code[i] == 0 && czero[k]) {
-      coords(g, (int64_t)i, x);
-      outl[z++] = residual<T>(X, g, (int64_t)i, x, a.inv2e, bad);
+  // outliers: chunk k of the stream order
+  if (czero[k]) {
+    uint64_t z = zoff[k];
+    for (uint64_t i = beg; i < end; i++) {
+      if (code[i] != 0) continue;
+      int64_t x[4];
+      bool bad = false;
+      brick_coords(g.n, (int64_t)i, x);
+      const int64_t r = x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3];
+      outl[z++] = residual<T>(X, g, r, x, a.inv2e, bad);
     }
-    if (pcount[k]) {
+  }
+  // patches: chunk k of the row-major order
+  if (pcount[k]) {
+    uint64_t p = poff[k];
+    for (uint64_t i = beg; i < end; i++) {
+      bool bad = false;
       const long long v = preq<T>(X[i], a.inv2e, bad);
       if (misses<T>(X[i], v, a.twoe, a.e)) {
         pidx[p] = i;
@@ -118,11 +126,14 @@ __global__ void __launch_bounds__(256) lorenzo_gather_kernel(
 
 // decompression: residuals from codes and outliers
 __global__ void __launch_bounds__(256) lorenzo_delta_kernel(const uint16_t* __restrict__ code, uint64_t n,
-                                                            uint32_t R, long long* __restrict__ v)
+                                                            uint32_t R, long long* __restrict__ v,
+                                                            Geom g)
 {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t c = code[i];
+    int64_t x[4];
+    coords(g, (int64_t)i, x);
+    const uint32_t c = code[brick_pos(g.n, x)];
     v[i] = c ? (long long)c - (long long)R : 0;
   }
 }
@@ -130,7 +141,7 @@ __global__ void __launch_bounds__(256) lorenzo_delta_kernel(const uint16_t* __re
 __global__ void __launch_bounds__(256) lorenzo_outlier_kernel(
     const uint16_t* __restrict__ code, uint64_t n, uint32_t chunk, const uint32_t* __restrict__ czero,
     const uint64_t* __restrict__ zoff, const long long* __restrict__ outl, uint64_t n_outl,
-    long long* __restrict__ v, int* __restrict__ status, uint64_t nch)
+    long long* __restrict__ v, int* __restrict__ status, uint64_t nch, Geom g)
 {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch || czero[k] == 0) return;
@@ -143,7 +154,9 @@ __global__ void __launch_bounds__(256) lorenzo_outlier_kernel(
       atomicOr(status, 1);
       return;
     }
-    v[i] = outl[z++];
+    int64_t x[4];
+    brick_coords(g.n, (int64_t)i, x);
+    v[x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]] = outl[z++];
   }
 }
 
@@ -250,9 +263,9 @@ hipError_t launch_lorenzo_rebuild(const uint16_t* code, const Geom& g, uint64_t 
 {
   if (!n) return hipSuccess;
   const uint64_t nch = (n + chunk - 1) / chunk;
-  hipLaunchKernelGGL(lorenzo_delta_kernel, dim3(gridn(n)), dim3(256), 0, st, code, n, R, v);
+  hipLaunchKernelGGL(lorenzo_delta_kernel, dim3(gridn(n)), dim3(256), 0, st, code, n, R, v, g);
   hipLaunchKernelGGL(lorenzo_outlier_kernel, dim3((unsigned)((nch + 255) / 256)), dim3(256), 0, st,
-                     code, n, chunk, czero, zoff, outl, n_outl, v, status, nch);
+                     code, n, chunk, czero, zoff, outl, n_outl, v, status, nch, g);
   for (int d = 0; d < 4; d++) {
     if (g.n[d] <= 1) continue;
     if (g.st[d] == 1) {

@@ -120,7 +120,7 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
   LCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, t3, st));
   LCK(launch_encode<T>(code, N, c->chunk, dlen, dcw, boff, zoff, cbits, czero,
                        (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), X,
-                       (T*)nullptr, st));
+                       (T*)nullptr, g, st));
   LCK(launch_lorenzo_gather<T>(X, g, N, a, code, czero, zoff, pcount, poff,
                                (long long*)(out + Lo.off_outl), (uint64_t*)(out + Lo.off_pidx),
                                (T*)(out + Lo.off_pval), st));

@@ -12,6 +12,25 @@ from oracle import oracle as O
 from paper_2311_12133_amd import fields
 
 
+def brick_order(shape, S=32):
+    """Stream order: bricks of S points per dim in row-major order, points of a
+    brick in row-major order (re-derived with numpy index arithmetic)."""
+    idx = np.arange(int(np.prod(shape))).reshape(shape)
+    nb = [(n + S - 1) // S for n in shape]
+    out = []
+    for b in np.ndindex(*nb):
+        sl = tuple(slice(bi * S, min((bi + 1) * S, n)) for bi, n in zip(b, shape))
+        out.append(idx[sl].reshape(-1))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("shape", [(70,), (33, 65), (40, 31, 70), (5, 33, 2, 40)])
+def test_stream_order(shape):
+    o = O.stream_order(shape)
+    assert np.array_equal(o, brick_order(shape))
+    assert np.array_equal(np.sort(o), np.arange(o.size))
+
+
 def mixed_difference(v):
     """First-order Lorenzo residual: backward difference along every axis with
     zero outside the grid."""
@@ -37,7 +56,9 @@ def test_lorenzo_residuals_and_bound(shape, dtype):
     inr = np.abs(delta) < R
     assert np.array_equal(r["code"][inr].astype(np.int64), delta[inr] + R)
     assert (r["code"][~inr] == 0).all()
-    assert np.array_equal(r["outliers"], delta[~inr])
+    # outliers are listed in stream (brick) order
+    flat = delta.reshape(-1)[brick_order(shape)]
+    assert np.array_equal(r["outliers"], flat[np.abs(flat) >= R])
     s = O.compress(x, cfg)
     y = O.decompress(s)
     assert np.abs(x.astype(np.float64) - y).max() <= e
