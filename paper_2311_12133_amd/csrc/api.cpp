@@ -17,6 +17,7 @@
 #include "hpez_internal.h"
 #include "hpez_host.h"
 #include "lorenzo_dev.h"
+#include "block_dev.h"
 
 using namespace hpez;
 
@@ -624,12 +625,12 @@ uint64_t grid_points(const Geom& g, int64_t s)
 template <typename T>
 int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, const Geom& g,
                double e, const T* X, T* W, uint16_t* code, const uint8_t* d_bcfg,
-               const double* d_wq, const double* h_wq, int mode, hipStream_t st)
+               const double* d_wq, const double* h_wq, int mode, hipStream_t st, int l_stop = 0)
 {
   const int L = c->anchor_log2;
   const int64_t B = c->block_log2 ? (int64_t)1 << c->block_log2 : 0;
   const int nact = n_active(g);
-  for (int l = L; l >= 1; l--) {
+  for (int l = L; l > l_stop; l--) {
     const int64_t s = (int64_t)1 << (l - 1);
     // algorithmic traffic of the level: each of its points reads its value
     // (original or code) once and writes its code or reconstruction once
@@ -753,7 +754,7 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   const uint32_t nsym = 2 * c->radius;
   const uint64_t nb = n_blocks(d, c);
   const Geom g = make_geom(d, c->frozen_dim);
-  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 0));
+  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 0) + block_fast_bytes<T>(g) + 256);
   if (rc) return rc;
   const size_t pin_need = (size_t)nsym * 4 + nsym + kHdrBytes + nb + 4096 + (size_t)nsym * 4;
   rc = ensure_pinned(ctx, pin_need);
@@ -841,12 +842,23 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   const Lattice al = anchor_lattice(g, c->anchor_log2);
   Lo.n_anchor = al.total;
   HIPCK(launch_anchors<T>(g, al, X, W, code, anc, c->radius, 0, st));
-  rc = run_levels<T>(ctx, d, c, g, e, X, W, code, dbcfg, dwq, h_wq, 0, st);
+  const bool fast = block_fast_ok<T>(c, g);
+  rc = run_levels<T>(ctx, d, c, g, e, X, W, code, dbcfg, dwq, h_wq, 0, st,
+                     fast ? c->block_log2 : 0);
   if (rc) return rc;
+  HIPCK(hipMemsetAsync(hist, 0, (size_t)nsym * 4, st));
+  if (fast) {
+    // faces, then block interiors with the brick histogram fused in
+    uint32_t lo = c->radius > kBlockHistWin / 2 ? c->radius - kBlockHistWin / 2 : 0;
+    if (lo + kBlockHistWin > nsym) lo = nsym > (uint32_t)kBlockHistWin ? nsym - kBlockHistWin : 0;
+    void* area = bw.take<uint8_t>(block_fast_bytes<T>(g));
+    rc = run_block_fast<T>(ctx, c, g, e, X, W, code, dbcfg, dwq, h_wq, hist, lo, area, nullptr, 0,
+                           st);
+    if (rc) return rc;
+  }
 
   // --- histogram and codebook (Sec. 4 step 4)
-  HIPCK(hipMemsetAsync(hist, 0, (size_t)nsym * 4, st));
-  {
+  if (!fast) {
     Span sp(ctx, "histogram", N * 2, st);
     HIPCK(launch_histogram(code, N, hist, nsym, c->radius, st));
   }
@@ -907,7 +919,7 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   const uint64_t nb = Lo.n_blocks;
   const Geom g = make_geom(d, c->frozen_dim);
   int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 1) +
-                              (Lo.predictor == 1 ? N * 8 + 256 : 0));
+                              (Lo.predictor == 1 ? N * 8 + 256 : 0) + block_fast_bytes<T>(g) + 256);
   if (rc) return rc;
   rc = ensure_pinned(ctx, (size_t)nsym + 4096 + nb + 64);
   if (rc) return rc;
@@ -1015,8 +1027,16 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   const Lattice al = anchor_lattice(g, c->anchor_log2);
   if (al.total != Lo.n_anchor) return HPEZ_ECORRUPT;
   HIPCK(launch_anchors<T>(g, al, nullptr, out, code, (T*)(in + Lo.off_anchor), c->radius, 1, st));
-  rc = run_levels<T>(ctx, d, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq, 1, st);
+  const bool fast = block_fast_ok<T>(c, g);
+  rc = run_levels<T>(ctx, d, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq, 1, st,
+                     fast ? c->block_log2 : 0);
   if (rc) return rc;
+  if (fast) {
+    void* area = bw.take<uint8_t>(block_fast_bytes<T>(g));
+    rc = run_block_fast<T>(ctx, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq,
+                           nullptr, 0, area, out, 1, st);
+    if (rc) return rc;
+  }
   HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCK(hipMemcpyAsync(&h_tot[0], zoff + nch, 8, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));

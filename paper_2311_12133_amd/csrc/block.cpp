@@ -8,6 +8,7 @@
 
 #include "block_dev.h"
 #include "hpez_host.h"
+#include "interp_dev.h"
 
 namespace hpez {
 

@@ -1,6 +1,6 @@
 // k_block.hip -- block-wise interpolation on MI355X (Sec. 6.6 configurations,
 // Sec. 5 predictor), for block side B = 32 (the paper's default, equal to the
-// stream's brick side).
+// stream's brick side) and grids of up to three dimensions.
 //
 // With block-wise configurations, levels with stride s < B are computed in two
 // phases (the reading the whole library uses for how blocks meet):
@@ -118,91 +118,125 @@ __global__ void __launch_bounds__(256) face_step_kernel(FaceStep a, FaceGeo f,
 }
 
 // ---------------------------------------------------------------------------
-// interiors: one work-group per block, the whole schedule below B in LDS
+// interiors: one work-group per block, the whole schedule below B in LDS.
+// The grid has at most three dims here (dims 0..2; dim 3 has size 1), so all
+// per-dimension quantities are scalars (no per-lane arrays, no scratch).
 
-struct BoxGeo {
-  int64_t o[4];    // block origin
-  int32_t E[4];    // box extents (closed box along active dims)
-  int32_t bs[4];   // LDS strides
-  int32_t hi[4];   // last interior coordinate (box-local)
-  int32_t Eb[4];   // brick extents (half-open)
+// exact n / d for n, d < 2^16 (so n * d < 2^32) with m = ceil(2^32 / d); for
+// d = 1 the multiplier 2^32 does not fit and is stored as 0
+__device__ __forceinline__ uint32_t fmagic(uint32_t d) { return (uint32_t)((0xFFFFFFFFull / d) + 1); }
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
+
+struct Box3 {
+  int64_t o0, o1, o2;   // block origin
+  int32_t E0, E1, E2;   // box extents (closed box along active dims)
+  int32_t h0, h1, h2;   // last interior coordinate
+  int32_t l0, l1, l2;   // first interior coordinate (1 along active dims, else 0)
+  int32_t b0, b1;       // LDS strides of dims 0 and 1 (dim 2 stride 1)
+  int32_t Eb0, Eb1, Eb2;  // brick extents
 };
 
-__device__ __forceinline__ void box_setup(const Geom& g, int64_t bi, const int64_t* nb, BoxGeo& bx)
+__device__ __forceinline__ void box3(const Geom& g, int64_t bi, const int64_t* nb, Box3& x)
 {
-  int64_t r = bi;
-  int64_t b[4];
-  for (int d = 3; d >= 0; d--) {
-    b[d] = r % nb[d];
-    r /= nb[d];
-  }
-  for (int d = 0; d < 4; d++) {
-    bx.o[d] = b[d] * kBrick;
-    const int64_t rem = g.n[d] - bx.o[d];
-    bx.Eb[d] = (int32_t)(rem < kBrick ? rem : kBrick);
-    if (g.act[d]) {
-      bx.E[d] = (int32_t)(rem < kBrick + 1 ? rem : kBrick + 1);
-      bx.hi[d] = (int32_t)(rem - 1 < kBrick - 1 ? rem - 1 : kBrick - 1);
-    } else {
-      bx.E[d] = bx.Eb[d];
-      bx.hi[d] = bx.Eb[d] - 1;
-    }
-  }
-  bx.bs[3] = 1;
-  for (int d = 2; d >= 0; d--) bx.bs[d] = bx.bs[d + 1] * bx.E[d + 1];
+  const int64_t q2 = bi / nb[2];
+  const int64_t i2 = bi - q2 * nb[2];
+  const int64_t i0 = q2 / nb[1];
+  const int64_t i1 = q2 - i0 * nb[1];
+  x.o0 = i0 * kBrick;
+  x.o1 = i1 * kBrick;
+  x.o2 = i2 * kBrick;
+  const int64_t r0 = g.n[0] - x.o0, r1 = g.n[1] - x.o1, r2 = g.n[2] - x.o2;
+  x.Eb0 = (int32_t)(r0 < kBrick ? r0 : kBrick);
+  x.Eb1 = (int32_t)(r1 < kBrick ? r1 : kBrick);
+  x.Eb2 = (int32_t)(r2 < kBrick ? r2 : kBrick);
+  x.E0 = g.act[0] ? (int32_t)(r0 < kBrick + 1 ? r0 : kBrick + 1) : x.Eb0;
+  x.E1 = g.act[1] ? (int32_t)(r1 < kBrick + 1 ? r1 : kBrick + 1) : x.Eb1;
+  x.E2 = g.act[2] ? (int32_t)(r2 < kBrick + 1 ? r2 : kBrick + 1) : x.Eb2;
+  x.h0 = x.Eb0 - 1;
+  x.h1 = x.Eb1 - 1;
+  x.h2 = x.Eb2 - 1;
+  x.l0 = g.act[0] ? 1 : 0;
+  x.l1 = g.act[1] ? 1 : 0;
+  x.l2 = g.act[2] ? 1 : 0;
+  x.b1 = x.E2;
+  x.b0 = x.E1 * x.E2;
 }
 
-// smallest c in [lo, ...] with (o + c) == r (mod m)
-__device__ __forceinline__ int32_t first_in(int64_t o, int32_t lo, int64_t r, int64_t m)
+// smallest c >= lo with (o + c) == r (mod m), m a power of two
+__device__ __forceinline__ int32_t first_in(int64_t o, int32_t lo, int32_t r, int32_t m)
 {
-  const int64_t x0 = o + lo;
-  int64_t v = x0 - ((x0 - r) % m + m) % m;
-  if (v < x0) v += m;
-  return (int32_t)(v - o);
+  const int32_t x0 = (int32_t)(o & (int64_t)(m - 1)) + lo;  // o + lo modulo m, offset kept
+  const int32_t d = (r - x0) & (m - 1);
+  return lo + d;
 }
 
+// one step: every interior point with coordinates c_d == r_d (mod m_d) along the
+// three dims; pd is the pass dim (1D style) or -1 with the odd set (MD)
 template <typename T, int MODE>
-__device__ void interior_step(const BlockArgs& a, const BoxGeo& bx, T* L, const int64_t* r,
-                              const int64_t* m, const hpez_interp& c, int sl, int pd, unsigned odd,
-                              int64_t s, double el, double inv2e, double twoe,
-                              const double* __restrict__ wq, uint16_t* __restrict__ code,
-                              uint64_t brick_base, const T* __restrict__ out)
+__device__ __forceinline__ void interior_step(const BlockArgs& a, const Box3& bx, T* L, int32_t r0,
+                                              int32_t r1, int32_t r2, int32_t m0, int32_t m1,
+                                              int32_t m2, int kind, int sl, int pd, unsigned odd,
+                                              int32_t s, double el, double inv2e, double twoe,
+                                              const double* __restrict__ wq,
+                                              uint16_t* __restrict__ code, uint64_t brick_base,
+                                              const T* __restrict__ out)
 {
-  int32_t f[4], cnt[4], mm[4];
-  uint32_t total = 1;
-  for (int d = 0; d < 4; d++) {
-    const int32_t lo = a.g.act[d] ? 1 : 0;
-    mm[d] = (int32_t)m[d];
-    f[d] = first_in(bx.o[d], lo, r[d], m[d]);
-    cnt[d] = f[d] <= bx.hi[d] ? (bx.hi[d] - f[d]) / mm[d] + 1 : 0;
-    total *= (uint32_t)cnt[d];
+  const int32_t f0 = first_in(bx.o0, bx.l0, r0, m0), f1 = first_in(bx.o1, bx.l1, r1, m1),
+                f2 = first_in(bx.o2, bx.l2, r2, m2);
+  const int32_t c0 = f0 <= bx.h0 ? (bx.h0 - f0) / m0 + 1 : 0;
+  const int32_t c1 = f1 <= bx.h1 ? (bx.h1 - f1) / m1 + 1 : 0;
+  const int32_t c2 = f2 <= bx.h2 ? (bx.h2 - f2) / m2 + 1 : 0;
+  const uint32_t c12 = (uint32_t)(c1 * c2);
+  const uint32_t total = (uint32_t)c0 * c12;
+  if (!total) return;
+  const uint32_t mg12 = fmagic(c12), mg2 = fmagic((uint32_t)c2);
+  // stride and extent of the pass dim (uniform)
+  const int32_t B0 = bx.b0, B1 = bx.b1, E0 = bx.E0, E1 = bx.E1, E2 = bx.E2;
+  int32_t bsd = 1, Ed = E2;
+  if (pd == 0) {
+    bsd = B0;
+    Ed = E0;
+  } else if (pd == 1) {
+    bsd = B1;
+    Ed = E1;
+  }
+  T w0 = 0, w1 = 0, w2 = 0;
+  if (pd < 0) {
+    w0 = (T)wq[(kind * 16 + odd) * 4 + 0];
+    w1 = (T)wq[(kind * 16 + odd) * 4 + 1];
+    w2 = (T)wq[(kind * 16 + odd) * 4 + 2];
   }
   for (uint32_t k = threadIdx.x; k < total; k += blockDim.x) {
-    int32_t cc[4];
-    uint32_t rr = k;
-    for (int d = 3; d >= 0; d--) {
-      const uint32_t q = rr / (uint32_t)cnt[d];
-      cc[d] = f[d] + (int32_t)(rr - q * (uint32_t)cnt[d]) * mm[d];
-      rr = q;
-    }
-    const int32_t li = cc[0] * bx.bs[0] + cc[1] * bx.bs[1] + cc[2] * bx.bs[2] + cc[3];
+    const uint32_t i0 = fdiv(k, mg12);
+    const uint32_t rem = k - i0 * c12;
+    const uint32_t i1 = fdiv(rem, mg2);
+    const uint32_t i2 = rem - i1 * (uint32_t)c2;
+    const int32_t x0 = f0 + (int32_t)i0 * m0, x1 = f1 + (int32_t)i1 * m1, x2 = f2 + (int32_t)i2 * m2;
+    const int32_t li = x0 * bx.b0 + x1 * bx.b1 + x2;
     T p;
-    if (!c.md) {
-      p = spline<T, T>(L, li, s * bx.bs[pd], cc[pd], s, 0, bx.E[pd] - 1, c.kind, sl);
+    if (pd >= 0) {
+      const int32_t xd = pd == 0 ? x0 : pd == 1 ? x1 : x2;
+      p = spline<T, T>(L, li, (int64_t)s * bsd, xd, s, 0, Ed - 1, kind, sl);
     } else {
       bool first = true;
       T acc = (T)0;
-      for (int d = 0; d < 4; d++) {
-        if (!(odd >> d & 1u)) continue;
-        const T pv = spline<T, T>(L, li, s * bx.bs[d], cc[d], s, 0, bx.E[d] - 1, c.kind, 0);
-        const T term = (T)wq[(c.kind * 16 + odd) * 4 + d] * pv;
-        acc = first ? term : acc + term;
+      if (odd & 1u) {
+        const T t = w0 * spline<T, T>(L, li, (int64_t)s * bx.b0, x0, s, 0, bx.E0 - 1, kind, 0);
+        acc = t;
         first = false;
+      }
+      if (odd & 2u) {
+        const T t = w1 * spline<T, T>(L, li, (int64_t)s * bx.b1, x1, s, 0, bx.E1 - 1, kind, 0);
+        acc = first ? t : acc + t;
+        first = false;
+      }
+      if (odd & 4u) {
+        const T t = w2 * spline<T, T>(L, li, (int64_t)s, x2, s, 0, bx.E2 - 1, kind, 0);
+        acc = first ? t : acc + t;
       }
       p = acc;
     }
-    const uint64_t cpos =
-        brick_base + (uint64_t)(((cc[0] * bx.Eb[1] + cc[1]) * bx.Eb[2] + cc[2]) * bx.Eb[3] + cc[3]);
+    const uint64_t cpos = brick_base + (uint64_t)((x0 * bx.Eb1 + x1) * bx.Eb2 + x2);
     if (MODE == 0) {
       const T xv = L[li];
       T xr = xv;
@@ -214,9 +248,7 @@ __device__ void interior_step(const BlockArgs& a, const BoxGeo& bx, T* L, const 
       if (q) {
         L[li] = (T)((double)p + (double)((int64_t)q - (int64_t)a.R) * twoe);
       } else {
-        const int64_t idx = (bx.o[0] + cc[0]) * a.g.st[0] + (bx.o[1] + cc[1]) * a.g.st[1] +
-                            (bx.o[2] + cc[2]) * a.g.st[2] + (bx.o[3] + cc[3]);
-        L[li] = out[idx];
+        L[li] = out[(bx.o0 + x0) * a.g.st[0] + (bx.o1 + x1) * a.g.st[1] + (bx.o2 + x2)];
       }
     }
   }
@@ -232,130 +264,143 @@ __global__ void __launch_bounds__(1024) block_kernel(BlockArgs a, FaceGeo f, con
   extern __shared__ unsigned char lds_raw[];
   T* L = reinterpret_cast<T*>(lds_raw);
   const int64_t bi = blockIdx.x;
-  BoxGeo bx;
-  box_setup(a.g, bi, a.nb, bx);
-  const int32_t nbox = bx.bs[0] * bx.E[0];
-  // brick base: stream position of the brick's first point
-  int64_t b0[4];
-  for (int d = 0; d < 4; d++) b0[d] = bx.o[d];
-  const uint64_t brick_base = (uint64_t)brick_pos(a.g.n, b0);
-  const uint32_t nbrick = (uint32_t)bx.Eb[0] * bx.Eb[1] * bx.Eb[2] * bx.Eb[3];
+  Box3 bx;
+  box3(a.g, bi, a.nb, bx);
+  const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
+  // stream position of the brick's first point (all earlier bricks are full
+  // along the dims before the last partial one)
+  const uint64_t brick_base = (uint64_t)(bx.o0 * a.g.n[1] * a.g.n[2] + bx.Eb0 * bx.o1 * a.g.n[2] +
+                                         bx.Eb0 * bx.Eb1 * bx.o2);
+  const uint32_t nbrick = (uint32_t)bx.Eb0 * bx.Eb1 * bx.Eb2;
+  const uint32_t nbox = (uint32_t)bx.E0 * bx.b0;
+  const uint32_t mgb0 = fmagic((uint32_t)bx.b0), mgE2 = fmagic((uint32_t)bx.E2);
+  const int a0 = a.g.act[0], a1 = a.g.act[1], a2 = a.g.act[2];
 
   // load: faces from the face arrays, interiors from X (compress)
-  for (int32_t i = threadIdx.x; i < nbox; i += blockDim.x) {
-    int32_t cc[4], rr = i;
-    for (int d = 3; d >= 0; d--) {
-      cc[d] = rr % bx.E[d];
-      rr /= bx.E[d];
-    }
-    int fam = -1;
-    for (int d = 0; d < 4; d++)
-      if (a.g.act[d] && (cc[d] == 0 || cc[d] == kBrick)) {
-        fam = d;
-        break;
+  const T* __restrict__ F0 = reinterpret_cast<const T*>(f.val[0]);
+  const T* __restrict__ F1 = reinterpret_cast<const T*>(f.val[1]);
+  const T* __restrict__ F2 = reinterpret_cast<const T*>(f.val[2]);
+  // eight loads in flight per lane before their LDS stores
+  constexpr int kU = 8;
+  for (uint32_t i0 = threadIdx.x; i0 < nbox; i0 += kU * blockDim.x) {
+    T v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint32_t i = i0 + u * blockDim.x;
+      v[u] = (T)0;
+      if (i >= nbox) continue;
+      const int32_t c0 = (int32_t)fdiv(i, mgb0);
+      const uint32_t rem = i - (uint32_t)c0 * bx.b0;
+      const int32_t c1 = (int32_t)fdiv(rem, mgE2);
+      const int32_t c2 = (int32_t)(rem - (uint32_t)c1 * bx.E2);
+      const int64_t x0 = bx.o0 + c0, x1 = bx.o1 + c1, x2 = bx.o2 + c2;
+      if (a0 && (c0 == 0 || c0 == kBrick)) {
+        v[u] = F0[(x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2 * f.fs[0][2]];
+      } else if (a1 && (c1 == 0 || c1 == kBrick)) {
+        v[u] = F1[(x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2 * f.fs[1][2]];
+      } else if (a2 && (c2 == 0 || c2 == kBrick)) {
+        v[u] = F2[(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] + x1 * f.fs[2][1]];
+      } else if (MODE == 0) {
+        v[u] = X[x0 * st0 + x1 * st1 + x2];
       }
-    int64_t x[4];
-    for (int d = 0; d < 4; d++) x[d] = bx.o[d] + cc[d];
-    if (fam >= 0) {
-      L[i] = reinterpret_cast<const T*>(f.val[fam])[face_index(f, fam, x)];
-    } else if (MODE == 0) {
-      L[i] = X[x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3]];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint32_t i = i0 + u * blockDim.x;
+      if (i < nbox) L[i] = v[u];
     }
   }
   __syncthreads();
 
   const hpez_interp c = a.cand[bcfg[bi]];
-  int nact = 0;
-  for (int d = 0; d < 4; d++) nact += a.g.act[d];
+  const int nact = a0 + a1 + a2;
   for (int l = a.L; l >= 1; l--) {
-    const int64_t s = (int64_t)1 << (l - 1);
+    const int32_t s = 1 << (l - 1);
     const double el = a.el_l[l], inv2e = a.inv2e_l[l], twoe = a.twoe_l[l];
-    int64_t r[4], m[4];
     if (c.md) {
       for (int cnt = 1; cnt <= nact; cnt++) {
-        for (unsigned odd = 1; odd < 16; odd++) {
-          bool ok = __popc(odd) == cnt;
-          for (int d = 0; d < 4; d++)
-            if ((odd >> d & 1u) && !a.g.act[d]) ok = false;
-          if (!ok) continue;
-          for (int d = 0; d < 4; d++) {
-            if (!a.g.act[d]) { r[d] = 0; m[d] = 1; }
-            else if (odd >> d & 1u) { r[d] = s; m[d] = 2 * s; }
-            else { r[d] = 0; m[d] = 2 * s; }
-          }
-          interior_step<T, MODE>(a, bx, L, r, m, c, 0, -1, odd, s, el, inv2e, twoe, wq, code,
-                                 brick_base, out);
+        for (unsigned odd = 1; odd < 8; odd++) {
+          if ((int)__popc(odd) != cnt) continue;
+          if (((odd & 1u) && !a0) || ((odd & 2u) && !a1) || ((odd & 4u) && !a2)) continue;
+          const int32_t r0 = (odd & 1u) ? s : 0, r1 = (odd & 2u) ? s : 0, r2 = (odd & 4u) ? s : 0;
+          const int32_t m0 = a0 ? 2 * s : 1, m1 = a1 ? 2 * s : 1, m2 = a2 ? 2 * s : 1;
+          interior_step<T, MODE>(a, bx, L, r0, r1, r2, m0, m1, m2, c.kind, 0, -1, odd, s, el, inv2e,
+                                 twoe, wq, code, brick_base, out);
         }
         __syncthreads();
       }
     } else {
-      int pos[4] = {-1, -1, -1, -1}, np = 0;
+      // pass order over the active dims, two bits per pass
+      const unsigned actm = (unsigned)a0 | (unsigned)a1 << 1 | (unsigned)a2 << 2;
+      unsigned seen = 0, pds = 0;
+      int np = 0;
+#pragma unroll
       for (int i = 0; i < 4; i++) {
-        const int d = c.order[i];
-        if (d < 4 && a.g.act[d] && pos[d] < 0) pos[d] = np++;
+        const unsigned d = (unsigned)c.order[i];
+        if (d < 3 && (actm >> d & 1u) && !(seen >> d & 1u)) {
+          seen |= 1u << d;
+          pds |= d << (2 * np);
+          np++;
+        }
       }
+      unsigned earlier = 0;  // dims of earlier passes: multiples of s; later: of 2s
       for (int k = 0; k < np; k++) {
-        int pd = 0;
-        for (int d = 0; d < 4; d++)
-          if (pos[d] == k) pd = d;
-        for (int d = 0; d < 4; d++) {
-          if (!a.g.act[d]) { r[d] = 0; m[d] = 1; }
-          else if (d == pd) { r[d] = s; m[d] = 2 * s; }
-          else if (pos[d] < k) { r[d] = 0; m[d] = s; }
-          else { r[d] = 0; m[d] = 2 * s; }
-        }
+        const int pd = (int)(pds >> (2 * k) & 3u);
+        int32_t r0 = 0, r1 = 0, r2 = 0;
+        int32_t m0 = !a0 ? 1 : ((earlier & 1u) ? s : 2 * s);
+        int32_t m1 = !a1 ? 1 : ((earlier & 2u) ? s : 2 * s);
+        int32_t m2 = !a2 ? 1 : ((earlier & 4u) ? s : 2 * s);
         if (c.kind != 0 && c.same_level) {
-          m[pd] = 4 * s;
-          r[pd] = s;
-          interior_step<T, MODE>(a, bx, L, r, m, c, 0, pd, 0, s, el, inv2e, twoe, wq, code,
-                                 brick_base, out);
-          __syncthreads();
-          r[pd] = 3 * s;
-          interior_step<T, MODE>(a, bx, L, r, m, c, 1, pd, 0, s, el, inv2e, twoe, wq, code,
-                                 brick_base, out);
+          for (int half = 0; half < 2; half++) {
+            const int32_t rh = half ? 3 * s : s;
+            if (pd == 0) { r0 = rh; m0 = 4 * s; }
+            if (pd == 1) { r1 = rh; m1 = 4 * s; }
+            if (pd == 2) { r2 = rh; m2 = 4 * s; }
+            interior_step<T, MODE>(a, bx, L, r0, r1, r2, m0, m1, m2, c.kind, half, pd, 0, s, el,
+                                   inv2e, twoe, wq, code, brick_base, out);
+            __syncthreads();
+          }
         } else {
-          interior_step<T, MODE>(a, bx, L, r, m, c, 0, pd, 0, s, el, inv2e, twoe, wq, code,
-                                 brick_base, out);
+          if (pd == 0) { r0 = s; m0 = 2 * s; }
+          if (pd == 1) { r1 = s; m1 = 2 * s; }
+          if (pd == 2) { r2 = s; m2 = 2 * s; }
+          interior_step<T, MODE>(a, bx, L, r0, r1, r2, m0, m1, m2, c.kind, 0, pd, 0, s, el, inv2e,
+                                 twoe, wq, code, brick_base, out);
+          __syncthreads();
         }
-        __syncthreads();
+        earlier |= 1u << pd;
       }
     }
   }
 
+  const uint32_t mgEb12 = fmagic((uint32_t)(bx.Eb1 * bx.Eb2)), mgEb2 = fmagic((uint32_t)bx.Eb2);
+  const uint32_t Eb12 = (uint32_t)(bx.Eb1 * bx.Eb2);
   if (MODE == 1) {
     // the whole brick (interiors from the schedule, near faces as loaded)
     for (uint32_t i = threadIdx.x; i < nbrick; i += blockDim.x) {
-      int32_t cc[4];
-      uint32_t rr = i;
-      for (int d = 3; d >= 0; d--) {
-        cc[d] = (int32_t)(rr % (uint32_t)bx.Eb[d]);
-        rr /= (uint32_t)bx.Eb[d];
-      }
-      const int32_t li = cc[0] * bx.bs[0] + cc[1] * bx.bs[1] + cc[2] * bx.bs[2] + cc[3];
-      out[(bx.o[0] + cc[0]) * a.g.st[0] + (bx.o[1] + cc[1]) * a.g.st[1] +
-          (bx.o[2] + cc[2]) * a.g.st[2] + (bx.o[3] + cc[3])] = L[li];
+      const uint32_t c0 = fdiv(i, mgEb12);
+      const uint32_t rem = i - c0 * Eb12;
+      const uint32_t c1 = fdiv(rem, mgEb2);
+      const uint32_t c2 = rem - c1 * (uint32_t)bx.Eb2;
+      out[(bx.o0 + c0) * st0 + (bx.o1 + c1) * st1 + (bx.o2 + c2)] =
+          L[c0 * bx.b0 + c1 * bx.b1 + c2];
     }
     return;
   }
 
   // near-face codes of the brick, from the face arrays
   for (uint32_t i = threadIdx.x; i < nbrick; i += blockDim.x) {
-    int32_t cc[4];
-    uint32_t rr = i;
-    for (int d = 3; d >= 0; d--) {
-      cc[d] = (int32_t)(rr % (uint32_t)bx.Eb[d]);
-      rr /= (uint32_t)bx.Eb[d];
-    }
-    int fam = -1;
-    for (int d = 0; d < 4; d++)
-      if (a.g.act[d] && cc[d] == 0) {
-        fam = d;
-        break;
-      }
-    if (fam < 0) continue;
-    int64_t x[4];
-    for (int d = 0; d < 4; d++) x[d] = bx.o[d] + cc[d];
-    code[brick_base + i] = f.code[fam][face_index(f, fam, x)];
+    const uint32_t c0 = fdiv(i, mgEb12);
+    const uint32_t rem = i - c0 * Eb12;
+    const uint32_t c1 = fdiv(rem, mgEb2);
+    const uint32_t c2 = rem - c1 * (uint32_t)bx.Eb2;
+    const int64_t x0 = bx.o0 + c0, x1 = bx.o1 + c1, x2 = bx.o2 + c2;
+    if (a0 && c0 == 0)
+      code[brick_base + i] = f.code[0][(x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2 * f.fs[0][2]];
+    else if (a1 && c1 == 0)
+      code[brick_base + i] = f.code[1][(x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2 * f.fs[1][2]];
+    else if (a2 && c2 == 0)
+      code[brick_base + i] = f.code[2][(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] + x1 * f.fs[2][1]];
   }
   __syncthreads();
 

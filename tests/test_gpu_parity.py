@@ -168,3 +168,33 @@ def test_lorenzo(torch_cuda, dtype):
         s = roundtrip(torch_cuda, x, make_cfg(x.shape, dtype=dtype, eb=0.13, eb_mode="abs",
                                               predictor="lorenzo"), "lorenzo patches")
         assert int(np.frombuffer(s[472:480], np.uint64)[0]) > 10
+
+
+FAST_SHAPES = [(64, 64, 64), (65, 33, 97), (96, 31, 130), (33, 64, 1), (200, 161), (1, 77, 64),
+               (40, 40, 40)]
+
+
+@pytest.mark.parametrize("shape", FAST_SHAPES, ids=["x".join(map(str, s)) for s in FAST_SHAPES])
+def test_block_fast_path(torch_cuda, shape):
+    """Block-wise configurations with B = 32 (faces + per-block LDS kernel)."""
+    x = fields.random_field(shape, sum(shape), np.float32, "mixed")
+    nd = len(shape)
+    cand = candidates(nd)
+    nb = int(np.prod([(s + 31) // 32 for s in shape]))
+    rng = np.random.default_rng(nb)
+    for trial, kw in enumerate((dict(kind="nak"), dict(kind="nat", md=1),
+                                dict(kind="lin", same_level=1, alpha=1.5, beta=3.0),
+                                dict(kind="nak", same_level=1, frozen_dim=0, radius=512))):
+        bc = rng.integers(0, len(cand), nb).astype(np.uint8)
+        cfg = make_cfg(shape, eb=1e-3 if trial != 3 else 2e-5, anchor_log2=6 if nd >= 3 else 7,
+                       block_log2=5, cand=cand, block_cfg=bc, **kw)
+        roundtrip(torch_cuda, x, cfg, f"fast {shape} {kw}")
+
+
+def test_block_fast_2d_f64(torch_cuda):
+    x = fields.random_field((150, 230), 3, np.float64, "mixed")
+    cand = candidates(2)
+    nb = 5 * 8
+    bc = (np.arange(nb) * 3 % 11).astype(np.uint8)
+    roundtrip(torch_cuda, x, make_cfg(x.shape, dtype="f64", eb=1e-4, anchor_log2=7, block_log2=5,
+                                      cand=cand, block_cfg=bc, kind="nat", md=1), "fast 2d f64")
