@@ -18,6 +18,7 @@
 #include "hpez_host.h"
 #include "lorenzo_dev.h"
 #include "block_dev.h"
+#include "codec_dev.h"
 
 using namespace hpez;
 
@@ -477,32 +478,71 @@ void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw)
   for (uint32_t s = 0; s < nsym; s++) cw[s] = len[s] ? (uint32_t)next[len[s]]++ : 0;
 }
 
+int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
+                   const uint8_t* h_len, const uint32_t* h_cw, uint32_t sym_min, uint32_t sym_max,
+                   const uint8_t* dlen, const uint32_t* dcw, uint32_t* d_tab, uint64_t* d_flags,
+                   uint32_t* d_ticket, uint32_t* h_tab, uint32_t* payload, uint16_t* chunks,
+                   hipStream_t st)
+{
+  const uint64_t nch = (N + chunk - 1) / chunk;
+  if (!nch) return HPEZ_OK;
+  if (sym_max < sym_min) return HPEZ_EINVAL;
+  EncodeArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.n = N;
+  a.nch = nch;
+  a.chunk = chunk;
+  a.smin = sym_min;
+  a.ntab = sym_max - sym_min + 1;
+  a.lds_tab = a.ntab <= kEncTab;
+  // packed entries (codeword << 6 | length) need codewords of at most 26 bits
+  uint32_t maxlen = 0;
+  for (uint32_t k = sym_min; k <= sym_max; k++) maxlen = std::max<uint32_t>(maxlen, h_len[k]);
+  a.packed_ok = maxlen <= 26;
+  if (a.packed_ok) {
+    for (uint32_t k = 0; k < a.ntab; k++)
+      h_tab[k] = h_len[sym_min + k] ? (h_cw[sym_min + k] << 6 | h_len[sym_min + k]) : 0u;
+    if (hipMemcpyAsync(d_tab, h_tab, (size_t)a.ntab * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+      return HPEZ_EDEVICE;
+  }
+  if (hipMemsetAsync(d_flags, 0, nch * 8, st) != hipSuccess) return HPEZ_EDEVICE;
+  if (hipMemsetAsync(d_ticket, 0, 4, st) != hipSuccess) return HPEZ_EDEVICE;
+  hipEvent_t ev = ctx_span_begin(ctx, st);
+  if (launch_encode1(a, code, payload, chunks, d_flags, d_ticket, d_tab, dlen, dcw, st) !=
+      hipSuccess)
+    return HPEZ_EDEVICE;
+  ctx_span_end(ctx, ev, "encode", N * 2, st);
+  return HPEZ_OK;
+}
+
 // Decode tables: 12-bit lookup (sym << 8 | len) plus per-length first code,
 // count and offset into the (length, symbol)-sorted symbol list.
-void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint32_t* first,
-                   uint32_t* count, uint32_t* offset, uint16_t* sorted)
+void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint16_t* sorted,
+                   uint64_t* lim, uint32_t* base)
 {
-  std::vector<uint32_t> cw(nsym);
-  canonical_codes(len, nsym, cw.data());
-  std::memset(lut, 0, sizeof(uint32_t) << kLutBits);
-  for (int l = 0; l <= kLmax + 1; l++) first[l] = count[l] = offset[l] = 0;
+  uint64_t count[kLmax + 2] = {0}, next[kLmax + 2] = {0}, offset[kLmax + 2] = {0};
   for (uint32_t s = 0; s < nsym; s++)
     if (len[s]) count[len[s]]++;
-  uint32_t k = 0;
+  // canonical first code per length, lengths without codes included
+  for (int l = 2; l <= kLmax; l++) next[l] = (next[l - 1] + count[l - 1]) << 1;
+  for (int l = 2; l <= kLmax; l++) offset[l] = offset[l - 1] + count[l - 1];
+  lim[0] = 0;
+  base[0] = 0;
   for (int l = 1; l <= kLmax; l++) {
-    offset[l] = k;
-    bool firstset = false;
-    for (uint32_t s = 0; s < nsym; s++) {
-      if (len[s] != l) continue;
-      if (!firstset) {
-        first[l] = cw[s];
-        firstset = true;
-      }
-      sorted[k++] = (uint16_t)s;
-      if (l <= kLutBits) {
-        const uint32_t base = cw[s] << (kLutBits - l);
-        for (uint32_t j = 0; j < (1u << (kLutBits - l)); j++) lut[base + j] = (s << 8) | (uint32_t)l;
-      }
+    lim[l] = (next[l] + count[l]) << (32 - l);
+    base[l] = (uint32_t)(offset[l] - next[l]);
+  }
+  std::memset(lut, 0, sizeof(uint32_t) << kLutBits);
+  uint64_t fill[kLmax + 2];
+  for (int l = 0; l <= kLmax + 1; l++) fill[l] = 0;
+  for (uint32_t s = 0; s < nsym; s++) {
+    const int l = len[s];
+    if (!l) continue;
+    const uint64_t rank = fill[l]++;
+    sorted[offset[l] + rank] = (uint16_t)s;
+    if (l <= kLutBits) {
+      const uint64_t first = (next[l] + rank) << (kLutBits - l);
+      for (uint64_t j = 0; j < (1ull << (kLutBits - l)); j++) lut[first + j] = (s << 8) | (uint32_t)l;
     }
   }
 }
@@ -611,6 +651,7 @@ size_t ws_need(uint64_t N, uint64_t s, uint32_t R, uint32_t chunk, uint64_t nb, 
   add(3 * 16 * 4 * 8);                     // MD weights
   add((1u << kLutBits) * 4 + 4 * 34 * 4 + nsym * 2);  // decode tables
   add(64);                                 // status
+  add(64);                                 // encoder ticket
   return b;
 }
 
@@ -778,6 +819,7 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   T* anc = bw.take<T>(N);
   uint8_t* dbcfg = bw.take<uint8_t>(nb + 16);
   double* dwq = bw.take<double>(3 * 16 * 4);
+  uint32_t* ticket = bw.take<uint32_t>(16);
 
   uint8_t* pin = ctx->pinned;
   uint32_t* h_hist = (uint32_t*)pin;
@@ -785,8 +827,7 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   uint8_t* h_hdr = h_len + nsym;
   double* h_mm = (double*)(h_hdr + kHdrBytes);
   int* h_bad = (int*)(h_mm + 2);
-  uint32_t* h_cw = (uint32_t*)(pin + (size_t)nsym * 4 + nsym + kHdrBytes + 64);
-  (void)h_cw;
+  uint32_t* h_tab = (uint32_t*)(pin + (((size_t)nsym * 5 + kHdrBytes + 64 + 63) & ~(size_t)63));
 
   // --- error bound (Sec. 7.1.3) and the non-finite check
   const int mblocks = 1024;
@@ -891,18 +932,16 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   if (Lo.sym_max >= Lo.sym_min)
     HIPCK(hipMemcpyAsync(out + Lo.off_len, h_len + Lo.sym_min, Lo.sym_max - Lo.sym_min + 1,
                          hipMemcpyHostToDevice, st));
-  {
-    Span sp(ctx, "encode_lengths", N * 2, st);
-    HIPCK(launch_chunk_lengths(code, N, c->chunk, dlen, cbits, czero, st));
-    HIPCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, tmp1, st));
-    HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
+  if (Lo.n_unpred) {
+    // verbatim values in stream order (Sec. 4: unpredictable points)
+    Span sp(ctx, "gather_unpred", N * 2 + Lo.n_unpred * s * 2, st);
+    HIPCK(launch_gather_unpred<T>(code, N, c->chunk, czero, zoff, tmp2, X,
+                                  (T*)(out + Lo.off_unpred), g, st));
   }
-  {
-    Span sp(ctx, "encode", N * 2 + (bits + 7) / 8, st);
-    HIPCK(launch_encode<T>(code, N, c->chunk, dlen, dcw, boff, zoff, cbits, czero,
-                           (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), X,
-                           (T*)(out + Lo.off_unpred), g, st));
-  }
+  rc = encode_payload(ctx, code, N, c->chunk, h_len, cw.data(), Lo.sym_min, Lo.sym_max, dlen, dcw,
+                      hist, boff, ticket, h_tab, (uint32_t*)(out + Lo.off_payload),
+                      (uint16_t*)(out + Lo.off_chunks), st);
+  if (rc) return rc;
   HIPCK(hipStreamSynchronize(st));
   prof_collect(ctx);
   *out_size = Lo.total;
@@ -934,9 +973,6 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   uint64_t* tmp2 = bw.take<uint64_t>((nch + 1023) / 1024 + 1);
   double* dwq = bw.take<double>(3 * 16 * 4);
   uint32_t* dlut = bw.take<uint32_t>(1u << kLutBits);
-  uint32_t* dfirst = bw.take<uint32_t>(kLmax + 2);
-  uint32_t* dcount = bw.take<uint32_t>(kLmax + 2);
-  uint32_t* doffset = bw.take<uint32_t>(kLmax + 2);
   uint16_t* dsorted = bw.take<uint16_t>(nsym);
   int* status = bw.take<int>(4);
   uint8_t* pin = ctx->pinned;
@@ -976,13 +1012,16 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   }
   if (N > 0 && !(kraft == (1ull << kLmax) || (used == 1 && kraft == (1ull << (kLmax - 1)))))
     return HPEZ_ECORRUPT;
-  std::vector<uint32_t> lut(1u << kLutBits), first(kLmax + 2), count(kLmax + 2), offset(kLmax + 2);
+  std::vector<uint32_t> lut(1u << kLutBits);
   std::vector<uint16_t> sorted(nsym);
-  decode_tables(h_len, nsym, lut.data(), first.data(), count.data(), offset.data(), sorted.data());
+  DecodeArgs da;
+  std::memset(&da, 0, sizeof da);
+  da.n = N;
+  da.nch = nch;
+  da.nbits = Lo.payload_bits;
+  da.chunk = c->chunk;
+  decode_tables(h_len, nsym, lut.data(), sorted.data(), da.lim, da.base);
   HIPCK(hipMemcpyAsync(dlut, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(dfirst, first.data(), first.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(dcount, count.data(), count.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(doffset, offset.data(), offset.size() * 4, hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(dsorted, sorted.data(), sorted.size() * 2, hipMemcpyHostToDevice, st));
   double h_wq[3 * 16 * 4];
   md_table(c, h_wq);
@@ -996,9 +1035,8 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   }
   {
     Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
-    HIPCK(launch_decode<T>((const uint32_t*)(in + Lo.off_payload), Lo.payload_bits, boff, N,
-                           c->chunk, dlut, dfirst, dcount, doffset, dsorted, code, czero, status,
-                           st));
+    HIPCK(launch_decode2(da, (const uint32_t*)(in + Lo.off_payload), boff, dlut, dsorted, code,
+                         czero, status, st));
   }
   HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
   uint64_t h_tot[2];

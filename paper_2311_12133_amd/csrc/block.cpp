@@ -108,24 +108,26 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
     a.inv2e = 1.0 / (2.0 * el);
     a.twoe = 2.0 * el;
     a.R = c->radius;
-    // launch one step over every family whose planes the step touches
+    // one launch per step over every family whose planes the step touches
     auto step = [&](const int64_t* rr, const int64_t* mm) -> int {
+      for (int k = 0; k < 4; k++) {
+        a.first[k] = rr[k];
+        a.step[k] = mm[k];
+        a.cnt[k] = rr[k] <= g.n[k] - 1 ? (uint32_t)((g.n[k] - 1 - rr[k]) / mm[k] + 1) : 0;
+      }
+      a.off[0] = 0;
       for (int d = 0; d < 4; d++) {
         // a step that predicts odd multiples of s along d has no points on d's planes
-        if (!g.act[d] || rr[d] != 0) continue;
-        a.fam = d;
-        uint64_t tot = (uint64_t)((g.n[d] - 1) / B + 1);
-        for (int k = 0; k < 4; k++) {
-          if (k == d) continue;
-          a.first[k] = rr[k];
-          a.step[k] = mm[k];
-          a.cnt[k] = rr[k] <= g.n[k] - 1 ? (uint32_t)((g.n[k] - 1 - rr[k]) / mm[k] + 1) : 0;
-          tot *= a.cnt[k];
+        uint64_t tot = 0;
+        if (g.act[d] && rr[d] == 0) {
+          tot = (uint64_t)((g.n[d] - 1) / B + 1);
+          for (int k = 0; k < 4; k++)
+            if (k != d) tot *= a.cnt[k];
         }
-        a.total = tot;
-        face_pts += tot;
-        if (launch_face_step<T>(a, f, X, code, out, mode, st) != hipSuccess) return HPEZ_EDEVICE;
+        a.off[d + 1] = a.off[d] + tot;
       }
+      face_pts += a.off[4];
+      if (launch_face_step<T>(a, f, X, code, out, mode, st) != hipSuccess) return HPEZ_EDEVICE;
       return HPEZ_OK;
     };
     if (ip.md) {

@@ -19,19 +19,21 @@ struct FaceGeo {
   int32_t pad;
 };
 
-// one step of the face phase for one family d
+// One step of the face phase over every family it touches.  The step's
+// lattice (first/step/cnt per dim) is shared; family d enumerates its planes
+// x_d = 0, B, 2B, ... (slowest) times the lattice of the other dims, and owns
+// the launch indices [off[d], off[d + 1]).
 struct FaceStep {
   Geom g;
   int64_t first[4], step[4];
-  uint32_t cnt[4];     // lattice of the other dims (entry d unused)
-  uint64_t total;      // planes * product of the other counts
-  int32_t fam;
+  uint32_t cnt[4];
+  uint64_t off[5];
   int32_t kind, md, sl, pdim;
   uint32_t odd;
+  uint32_t R;
   double wq[4];
   int64_t s;
   double el, inv2e, twoe;
-  uint32_t R;
 };
 
 struct BlockArgs {

@@ -19,25 +19,33 @@ struct EncodeArgs {
   int32_t pad;
 };
 
+// Canonical-code decoding state.  A 32-bit window w (next bits, first bit in
+// the most significant position) starts a codeword of length l iff
+// lim[l-1] <= w < lim[l]; that codeword's symbol is sorted[base[l] + (w >> (32 - l))].
 struct DecodeArgs {
-  uint64_t n;
-  uint64_t nch;
-  uint64_t nbits;
+  uint64_t n;        // symbols
+  uint64_t nch;      // chunks
+  uint64_t nbits;    // payload bits
   uint32_t chunk;
   uint32_t pad;
+  uint64_t lim[kLmax + 1];   // lim[l] = (first code of length l + count) << (32 - l)
+  uint32_t base[kLmax + 1];  // offset of length l in sorted[] minus its first code (mod 2^32)
 };
 
 hipError_t launch_encode1(const EncodeArgs& a, const uint16_t* code, uint32_t* words,
                           uint16_t* out_cb, uint64_t* flags, uint32_t* ticket,
                           const uint32_t* packed, const uint8_t* len, const uint32_t* cw,
                           hipStream_t st);
+// per-chunk counts of code 0 and their exclusive scan (zoff[nch] = total)
+hipError_t launch_count_zeros(const uint16_t* code, uint64_t n, uint32_t chunk, uint32_t* czero,
+                              uint64_t* zoff, uint64_t* tmp, hipStream_t st);
+// verbatim values (code 0) gathered in stream order; counts zeros first
 template <typename T>
 hipError_t launch_gather_unpred(const uint16_t* code, uint64_t n, uint32_t chunk, uint32_t* czero,
                                 uint64_t* zoff, uint64_t* tmp, const T* X, T* unpred, const Geom& g,
                                 hipStream_t st);
 hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
-                          const uint32_t* lut, const uint32_t* first, const uint32_t* count,
-                          const uint32_t* offset, const uint16_t* sorted, uint16_t* code,
+                          const uint32_t* lut, const uint16_t* sorted, uint16_t* code,
                           uint32_t* czero, int* status, hipStream_t st);
 
 }  // namespace hpez

@@ -33,9 +33,23 @@ void write_header(uint8_t* h, const hpez_field_desc* d, const hpez_config* c, co
 int read_header(const uint8_t* h, uint64_t n, hpez_field_desc* d, hpez_config* c, Layout* L);
 int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw);
-void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint32_t* first,
-                   uint32_t* count, uint32_t* offset, uint16_t* sorted);
+// Canonical decoding tables: lut[2^kLutBits] (symbol << 8 | length, 0 for
+// longer codes), symbols sorted by (length, symbol), and per length the window
+// limit lim[l] and base[l] (kLmax + 1 entries each, index 0 unused).
+void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint16_t* sorted,
+                   uint64_t* lim, uint32_t* base);
 void md_table(const hpez_config* c, double* wq);
+
+// Huffman payload (Sec. 4 step 4, api.cpp): encode codes[0, N) with the
+// canonical codebook (h_len, h_cw: host, 2R entries; dlen, dcw: the same on the
+// device) into the zeroed payload words and the per-chunk bit counts.  d_tab
+// (2R words), d_flags (one word per chunk) and d_ticket are device scratch,
+// h_tab (2R words) pinned host scratch.
+int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
+                   const uint8_t* h_len, const uint32_t* h_cw, uint32_t sym_min, uint32_t sym_max,
+                   const uint8_t* dlen, const uint32_t* dcw, uint32_t* d_tab, uint64_t* d_flags,
+                   uint32_t* d_ticket, uint32_t* h_tab, uint32_t* payload, uint16_t* chunks,
+                   hipStream_t st);
 
 // Lorenzo alternative (lorenzo.cpp): compress after the error bound is known
 template <typename T>

@@ -128,6 +128,27 @@ __host__ __device__ __forceinline__ void brick_coords(const int64_t* n, int64_t 
   }
 }
 
+// Histogram update for every lane with `valid`: lanes holding equal codes are
+// counted together (one atomic per distinct code in the wavefront), into the
+// LDS window [lo, lo + win) or the global table outside it.
+__device__ __forceinline__ void hist_add_wave(uint32_t* lh, uint32_t* gh, uint32_t lo, uint32_t win,
+                                              uint32_t q, bool valid)
+{
+  uint64_t pending = __ballot(valid);
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const uint32_t v = __builtin_amdgcn_readlane(q, leader);
+    const uint64_t same = __ballot(valid && q == v) & pending;
+    if ((int)(threadIdx.x & 63) == leader) {
+      const uint32_t c = (uint32_t)__popcll(same);
+      const uint32_t w = v - lo;
+      if (w < win) atomicAdd(&lh[w], c);
+      else atomicAdd(&gh[v], c);
+    }
+    pending &= ~same;
+  }
+}
+
 __device__ __forceinline__ void lattice_point(const Lattice& L, uint64_t k, int64_t* x)
 {
   uint64_t r = k;

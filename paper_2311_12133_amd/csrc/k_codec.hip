@@ -1,18 +1,20 @@
 // k_codec.hip -- single-pass Huffman encode and table-driven decode (gfx950).
 //
 // Encode: one wavefront per chunk of `chunk` symbols, chunks taken in order
-// from a ticket counter.  Each lane sums the code lengths of its run of
-// symbols; a wave prefix sum gives the chunk's bit count, and the chunk's bit
-// offset comes from a decoupled look-back over the chunks before it (each
-// chunk publishes its count, then its inclusive prefix; a chunk only waits on
-// chunks with smaller tickets, which are already running, so every wait ends).
+// from a ticket counter by persistent waves.  Each lane sums the code lengths
+// of its run of symbols; a wave prefix sum gives the chunk's bit count, and the
+// chunk's bit offset comes from a decoupled look-back over the chunks before it
+// (each chunk publishes its count, then its inclusive prefix; a chunk only
+// waits on chunks with smaller tickets, whose waves took them earlier and are
+// running, and a wave publishes its count before it waits, so every wait ends).
 // The codewords are assembled in LDS and written out as whole 32-bit words;
 // only the two words a chunk shares with its neighbours are OR-ed atomically
 // into the zeroed payload.
 //
 // Decode: one lane per chunk; a 2^12-entry first-level table in LDS resolves
-// codewords up to 12 bits in one lookup; codes are packed eight at a time into
-// 16-byte stores.
+// codewords up to 12 bits in one lookup, longer ones are found by comparing the
+// window with the per-length limits of the canonical code (uniform values, no
+// table walk); codes are packed eight at a time into 16-byte stores.
 
 #include "codec_dev.h"
 #include "interp_dev.h"
@@ -24,38 +26,54 @@ constexpr uint64_t kFlagIncl = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr int kEncWaves = 4;  // chunks per work-group
 
-__device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p)
+// A flag word carries its own payload (status bits + bit count), and no other
+// data is published through it, so relaxed device-scope atomics suffice: they
+// are coherent across the chip's L2 slices without cache maintenance, which
+// acquire/release ordering would add to every poll.
+__device__ __forceinline__ uint64_t flag_load(const uint64_t* p)
 {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v)
+__device__ __forceinline__ void flag_store(uint64_t* p, uint64_t v)
 {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16_t* __restrict__ code,
-                                                      uint32_t* __restrict__ words,
-                                                      uint16_t* __restrict__ out_cb,
-                                                      uint64_t* __restrict__ flags,
-                                                      uint32_t* __restrict__ ticket,
-                                                      const uint32_t* __restrict__ gtab)
+// Exclusive bit offset of chunk k by decoupled look-back, run by the whole
+// wave: each round reads the flags of the 64 chunks before the current window
+// end, waits until all of them are published, and stops at the nearest one that
+// carries an inclusive prefix.  Called after chunk k published its aggregate.
+__device__ __forceinline__ uint64_t look_back(uint64_t* flags, uint64_t k, int lane)
 {
-  // codebook window in LDS: entry = codeword << 6 | length (lengths <= 32, codewords < 2^26
-  // when the table is used; longer codes fall back to the global table)
-  __shared__ uint32_t tab[kEncTab];
-  __shared__ uint32_t buf[kEncWaves][kEncWords];
-  __shared__ uint32_t tk[kEncWaves];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (a.lds_tab)
-    for (uint32_t i = threadIdx.x; i < a.ntab; i += blockDim.x) tab[i] = gtab[i];
-  if (lane == 0) tk[w] = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint64_t k = tk[w];
-  if (k >= a.nch) return;
+  uint64_t excl = 0;
+  int64_t top = (int64_t)k - 1;
+  for (;;) {
+    const int64_t j = top - lane;
+    uint64_t f = j >= 0 ? flag_load(&flags[j]) : kFlagIncl;
+    while (__ballot(f == 0)) {
+      __builtin_amdgcn_s_sleep(1);
+      if (f == 0) f = flag_load(&flags[j]);
+    }
+    const uint64_t incl = __ballot((f & ~kValMask) == kFlagIncl);
+    // lanes up to (and including) the nearest inclusive flag contribute
+    const int stop = incl ? __builtin_ctzll(incl) : 64;
+    uint64_t v = lane <= stop ? (f & kValMask) : 0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    excl += v;
+    if (incl) return excl;
+    top -= 64;
+  }
+}
+
+// bit count of one chunk (lane sums of `per` symbols, wave total); ent[]
+// receives the packed entries of the lane's symbols
+__device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uint16_t* __restrict__ code,
+                                                  const uint32_t* tab, const uint32_t* __restrict__ gtab,
+                                                  uint64_t k, int lane, uint32_t* ent, uint32_t& lane_bits)
+{
   const uint32_t per = a.chunk / 64;
   const uint64_t beg = k * a.chunk + (uint64_t)lane * per;
   const uint64_t cend = k * a.chunk + a.chunk < a.n ? k * a.chunk + a.chunk : a.n;
-  uint32_t ent[16];
   uint32_t bits = 0;
   for (uint32_t j = 0; j < per; j++) {
     const uint64_t i = beg + j;
@@ -67,68 +85,126 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     ent[j] = e;
     bits += e & 63u;
   }
-  // wave prefix sum of the lanes' bit counts
-  uint32_t incl = bits;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t total = __shfl(incl, 63, 64);
-  const uint32_t lane_off = incl - bits;
-  // look-back for the chunk's bit offset
-  uint64_t excl = 0;
-  if (lane == 0) {
-    if (k == 0) {
-      st_release(&flags[0], kFlagIncl | total);
-    } else {
-      st_release(&flags[k], kFlagAgg | total);
-      int64_t j = (int64_t)k - 1;
-      for (;;) {
-        uint64_t f;
-        do {
-          f = ld_acquire(&flags[j]);
-        } while (f == 0);
-        excl += f & kValMask;
-        if ((f & ~kValMask) == kFlagIncl) break;
-        j--;
-      }
-      st_release(&flags[k], kFlagIncl | (excl + total));
-    }
-    out_cb[k] = (uint16_t)total;
-  }
-  excl = __shfl(excl, 0, 64);
-  // assemble in LDS: local bit 0 is global bit (excl & ~31)
-  const uint32_t sh = (uint32_t)(excl & 31);
-  const uint32_t nw = (sh + total + 31) / 32;
+  lane_bits = bits;
+  uint32_t t = bits;
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
+// Persistent work-groups take partitions of kPart chunks in ticket order.  A
+// partition's chunk bit counts are summed in LDS, one decoupled look-back per
+// partition gives its bit offset, then each wave packs its chunks: codewords
+// are assembled in LDS and written as whole 32-bit words (the two words a
+// chunk shares with its neighbours are OR-ed atomically into the zeroed
+// payload).  The codebook window lives in LDS once per work-group.
+constexpr int kPart = 64;  // chunks per partition
+
+__global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16_t* __restrict__ code,
+                                                      uint32_t* __restrict__ words,
+                                                      uint16_t* __restrict__ out_cb,
+                                                      uint64_t* __restrict__ flags,
+                                                      uint32_t* __restrict__ ticket,
+                                                      const uint32_t* __restrict__ gtab)
+{
+  // codebook window in LDS: entry = codeword << 6 | length (codewords < 2^26)
+  __shared__ uint32_t tab[kEncTab];
+  __shared__ uint32_t buf[kEncWaves][kEncWords];
+  __shared__ uint32_t cbits[kPart];
+  __shared__ uint64_t s_excl;
+  __shared__ uint32_t s_part;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (a.lds_tab)
+    for (uint32_t i = threadIdx.x; i < a.ntab; i += blockDim.x) tab[i] = gtab[i];
+  const uint64_t nparts = (a.nch + kPart - 1) / kPart;
   uint32_t* B = buf[w];
-  for (uint32_t i = lane; i < nw + 1; i += 64) B[i] = 0;
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  uint32_t pos = sh + lane_off;
-  for (uint32_t j = 0; j < per; j++) {
-    const uint32_t e = ent[j];
-    const uint32_t L = e & 63u;
-    if (L) {
-      const uint32_t cw = e >> 6;
-      const uint32_t wi = pos >> 5, off = pos & 31;
-      const uint64_t v = (uint64_t)cw << (64 - L - off);
-      const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
-      if (hi) atomicOr(&B[wi], hi);
-      if (lo) atomicOr(&B[wi + 1], lo);
-      pos += L;
+  for (;;) {
+    if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint64_t part = s_part;
+    if (part >= nparts) return;
+    const uint64_t k0 = part * kPart;
+    const uint32_t np = (uint32_t)(a.nch - k0 < (uint64_t)kPart ? a.nch - k0 : (uint64_t)kPart);
+    uint32_t ent[16];
+    // 1. chunk bit counts
+    for (uint32_t j = w; j < np; j += kEncWaves) {
+      uint32_t lb;
+      const uint32_t t = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+      if (lane == 0) {
+        cbits[j] = t;
+        out_cb[k0 + j] = (uint16_t)t;
+      }
     }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const uint64_t w0 = excl >> 5;
-  for (uint32_t i = lane; i < nw; i += 64) {
-    const uint32_t v = B[i];
-    if (i == 0 || i == nw - 1) {
-      if (v) atomicOr(&words[w0 + i], v);
-    } else {
-      words[w0 + i] = v;
+    __syncthreads();
+    // 2. partition prefix and look-back (wave 0)
+    if (w == 0) {
+      const uint32_t v = (uint32_t)lane < np ? cbits[lane] : 0u;
+      uint32_t incl = v;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      const uint64_t total = __shfl(incl, 63, 64);
+      if ((uint32_t)lane < np) cbits[lane] = incl - v;  // exclusive prefix inside the partition
+      uint64_t excl = 0;
+      if (part == 0) {
+        if (lane == 0) flag_store(&flags[0], kFlagIncl | total);
+      } else {
+        if (lane == 0) flag_store(&flags[part], kFlagAgg | total);
+        excl = look_back(flags, part, lane);
+        if (lane == 0) flag_store(&flags[part], kFlagIncl | (excl + total));
+      }
+      if (lane == 0) s_excl = excl;
     }
+    __syncthreads();
+    // 3. pack each chunk
+    const uint64_t pexcl = s_excl;
+    for (uint32_t j = w; j < np; j += kEncWaves) {
+      uint32_t lb;
+      const uint32_t total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+      uint32_t incl = lb;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      const uint32_t lane_off = incl - lb;
+      const uint64_t excl = pexcl + cbits[j];
+      // assemble in LDS: local bit 0 is global bit (excl & ~31)
+      const uint32_t sh = (uint32_t)(excl & 31);
+      const uint32_t nw = (sh + total + 31) / 32;
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t i = lane; i < nw + 1; i += 64) B[i] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint32_t pos = sh + lane_off;
+      const uint32_t per = a.chunk / 64;
+      for (uint32_t jj = 0; jj < per; jj++) {
+        const uint32_t e = ent[jj];
+        const uint32_t L = e & 63u;
+        if (L) {
+          const uint32_t cw = e >> 6;
+          const uint32_t wi = pos >> 5, off = pos & 31;
+          const uint64_t v = (uint64_t)cw << (64 - L - off);
+          const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+          if (hi) atomicOr(&B[wi], hi);
+          if (lo) atomicOr(&B[wi + 1], lo);
+          pos += L;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint64_t w0 = excl >> 5;
+      for (uint32_t i = lane; i < nw; i += 64) {
+        const uint32_t v = B[i];
+        if (i == 0 || i == nw - 1) {
+          if (v) atomicOr(&words[w0 + i], v);
+        } else {
+          words[w0 + i] = v;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -141,57 +217,46 @@ __global__ void __launch_bounds__(256) encode1_wide_kernel(EncodeArgs a, const u
                                                            const uint8_t* __restrict__ len,
                                                            const uint32_t* __restrict__ cw)
 {
-  __shared__ uint32_t tk[kEncWaves];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) tk[w] = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint64_t k = tk[w];
-  if (k >= a.nch) return;
+  const int lane = threadIdx.x & 63;
   const uint32_t per = a.chunk / 64;
-  const uint64_t beg = k * a.chunk + (uint64_t)lane * per;
-  const uint64_t cend = k * a.chunk + a.chunk < a.n ? k * a.chunk + a.chunk : a.n;
-  uint32_t bits = 0;
-  for (uint32_t j = 0; j < per; j++)
-    if (beg + j < cend) bits += len[code[beg + j]];
-  uint32_t incl = bits;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t total = __shfl(incl, 63, 64);
-  uint64_t excl = 0;
-  if (lane == 0) {
-    if (k == 0) {
-      st_release(&flags[0], kFlagIncl | total);
-    } else {
-      st_release(&flags[k], kFlagAgg | total);
-      int64_t j = (int64_t)k - 1;
-      for (;;) {
-        uint64_t f;
-        do {
-          f = ld_acquire(&flags[j]);
-        } while (f == 0);
-        excl += f & kValMask;
-        if ((f & ~kValMask) == kFlagIncl) break;
-        j--;
-      }
-      st_release(&flags[k], kFlagIncl | (excl + total));
+  for (;;) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(ticket, 1u);
+    const uint64_t k = (uint64_t)__shfl(t, 0, 64);
+    if (k >= a.nch) return;
+    const uint64_t beg = k * a.chunk + (uint64_t)lane * per;
+    const uint64_t cend = k * a.chunk + a.chunk < a.n ? k * a.chunk + a.chunk : a.n;
+    uint32_t bits = 0;
+    for (uint32_t j = 0; j < per; j++)
+      if (beg + j < cend) bits += len[code[beg + j]];
+    uint32_t incl = bits;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
     }
-    out_cb[k] = (uint16_t)total;
-  }
-  excl = __shfl(excl, 0, 64);
-  uint64_t pos = excl + (incl - bits);
-  for (uint32_t j = 0; j < per; j++) {
-    if (beg + j >= cend) break;
-    const uint32_t c = code[beg + j];
-    const uint32_t L = len[c];
-    const uint64_t wi = pos >> 5;
-    const uint32_t off = (uint32_t)(pos & 31);
-    const uint64_t v = (uint64_t)cw[c] << (64 - L - off);
-    const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
-    if (hi) atomicOr(&words[wi], hi);
-    if (lo) atomicOr(&words[wi + 1], lo);
-    pos += L;
+    const uint32_t total = __shfl(incl, 63, 64);
+    uint64_t excl = 0;
+    if (k == 0) {
+      if (lane == 0) flag_store(&flags[0], kFlagIncl | total);
+    } else {
+      if (lane == 0) flag_store(&flags[k], kFlagAgg | total);
+      excl = look_back(flags, k, lane);
+      if (lane == 0) flag_store(&flags[k], kFlagIncl | (excl + total));
+    }
+    if (lane == 0) out_cb[k] = (uint16_t)total;
+    uint64_t pos = excl + (incl - bits);
+    for (uint32_t j = 0; j < per; j++) {
+      if (beg + j >= cend) break;
+      const uint32_t c = code[beg + j];
+      const uint32_t L = len[c];
+      const uint64_t wi = pos >> 5;
+      const uint32_t off = (uint32_t)(pos & 31);
+      const uint64_t v = (uint64_t)cw[c] << (64 - L - off);
+      const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+      if (hi) atomicOr(&words[wi], hi);
+      if (lo) atomicOr(&words[wi + 1], lo);
+      pos += L;
+    }
   }
 }
 
@@ -201,13 +266,18 @@ hipError_t launch_encode1(const EncodeArgs& a, const uint16_t* code, uint32_t* w
                           hipStream_t st)
 {
   if (!a.nch) return hipSuccess;
-  const unsigned grid = (unsigned)((a.nch + kEncWaves - 1) / kEncWaves);
-  if (a.packed_ok)
+  if (a.packed_ok) {
+    // persistent grid: a few work-groups per CU, each taking partitions in order
+    const uint64_t want = (a.nch + kPart - 1) / kPart;
+    const unsigned grid = (unsigned)(want < 1024 ? want : 1024);
     hipLaunchKernelGGL(encode1_kernel, dim3(grid), dim3(64 * kEncWaves), 0, st, a, code, words,
                        out_cb, flags, ticket, packed);
-  else
+  } else {
+    const uint64_t want = (a.nch + kEncWaves - 1) / kEncWaves;
+    const unsigned grid = (unsigned)(want < 2048 ? want : 2048);
     hipLaunchKernelGGL(encode1_wide_kernel, dim3(grid), dim3(64 * kEncWaves), 0, st, a, code, words,
                        out_cb, flags, ticket, len, cw);
+  }
   return hipGetLastError();
 }
 
@@ -248,6 +318,16 @@ __global__ void __launch_bounds__(256) count_zero_kernel(const uint16_t* __restr
   if (lane == 0) czero[k] = z;
 }
 
+hipError_t launch_count_zeros(const uint16_t* code, uint64_t n, uint32_t chunk, uint32_t* czero,
+                              uint64_t* zoff, uint64_t* tmp, hipStream_t st)
+{
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  if (!nch) return hipSuccess;
+  hipLaunchKernelGGL(count_zero_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, code, n, chunk,
+                     czero, nch);
+  return launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp, st);
+}
+
 template <typename T>
 hipError_t launch_gather_unpred(const uint16_t* code, uint64_t n, uint32_t chunk, uint32_t* czero,
                                 uint64_t* zoff, uint64_t* tmp, const T* X, T* unpred, const Geom& g,
@@ -255,9 +335,7 @@ hipError_t launch_gather_unpred(const uint16_t* code, uint64_t n, uint32_t chunk
 {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (!nch) return hipSuccess;
-  hipLaunchKernelGGL(count_zero_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, code, n, chunk,
-                     czero, nch);
-  hipError_t e = launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp, st);
+  hipError_t e = launch_count_zeros(code, n, chunk, czero, zoff, tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((gather_unpred_kernel<T>), dim3((unsigned)((nch + 255) / 256)), dim3(256), 0, st,
                      code, n, chunk, czero, zoff, X, unpred, g, nch);
@@ -266,25 +344,37 @@ hipError_t launch_gather_unpred(const uint16_t* code, uint64_t n, uint32_t chunk
 
 // ---------------------------------------------------------------------------
 // decode
+
+// symbol of the codeword at the top of the window; L = its length (0: invalid)
+__device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32_t* lut,
+                                               const uint16_t* __restrict__ sorted, uint32_t w,
+                                               uint32_t& L)
+{
+  const uint32_t e = lut[w >> (32 - kLutBits)];
+  L = e & 0xFFu;
+  if (L) return e >> 8;
+  // longer than the table: count the limits at or below w (they are sorted)
+  uint32_t c = kLutBits + 1;
+#pragma unroll
+  for (int l = kLutBits + 1; l <= kLmax; l++) c += (uint64_t)w >= a.lim[l] ? 1u : 0u;
+  if (c > (uint32_t)kLmax) {
+    L = 0;
+    return 0;
+  }
+  L = c;
+  return sorted[a.base[c] + (w >> (32 - c))];
+}
+
 __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32_t* __restrict__ words,
                                                       const uint64_t* __restrict__ bit_off,
                                                       const uint32_t* __restrict__ glut,
-                                                      const uint32_t* __restrict__ first,
-                                                      const uint32_t* __restrict__ count,
-                                                      const uint32_t* __restrict__ offset,
                                                       const uint16_t* __restrict__ sorted,
                                                       uint16_t* __restrict__ code,
                                                       uint32_t* __restrict__ czero,
                                                       int* __restrict__ status)
 {
   __shared__ uint32_t lut[1 << kLutBits];
-  __shared__ uint32_t s_first[kLmax + 2], s_count[kLmax + 2], s_offset[kLmax + 2];
   for (int i = threadIdx.x; i < (1 << kLutBits); i += blockDim.x) lut[i] = glut[i];
-  for (int i = threadIdx.x; i < kLmax + 2; i += blockDim.x) {
-    s_first[i] = first[i];
-    s_count[i] = count[i];
-    s_offset[i] = offset[i];
-  }
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0 && bit_off[a.nch] != a.nbits) atomicOr(status, 1);
@@ -292,12 +382,13 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   const uint64_t beg = k * a.chunk;
   const uint64_t end = beg + a.chunk < a.n ? beg + a.chunk : a.n;
   uint64_t pos = bit_off[k];
-  const uint64_t stop = k + 1 < a.nch ? bit_off[k + 1] : bit_off[a.nch];
-  if (stop > a.nbits) {
+  const uint64_t stop = bit_off[k + 1];
+  if (stop > a.nbits || pos > stop) {
     atomicOr(status, 1);
     return;
   }
   const uint64_t nwords = (a.nbits + 31) / 32;
+  // 64-bit bit buffer, next bit at the top; `have` valid bits
   uint64_t wi = pos >> 5;
   uint64_t buf;
   int have;
@@ -310,52 +401,42 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   }
   uint32_t zeros = 0;
   bool bad = false;
-  uint32_t pack[4] = {0, 0, 0, 0};
-  const bool aligned = (beg & 7) == 0;
-  for (uint64_t i = beg; i < end; i++) {
-    if (have < 32) {
-      const uint64_t w = wi < nwords ? words[wi] : 0;
-      buf |= (w << 32) >> have;
-      have += 32;
-      wi++;
-    }
-    const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-    uint32_t sym, L = e & 0xFFu;
-    if (L) {
-      sym = e >> 8;
-    } else {
-      sym = 0;
-      for (uint32_t l = kLutBits + 1; l <= (uint32_t)kLmax; l++) {
-        const uint32_t v = (uint32_t)(buf >> (64 - l));
-        if (s_count[l] && v - s_first[l] < s_count[l]) {
-          L = l;
-          sym = sorted[s_offset[l] + (v - s_first[l])];
-          break;
-        }
+  // chunks start at multiples of 64 symbols: eight codes per 16-byte store
+  for (uint64_t i = beg; i < end && !bad; i += 8) {
+    const uint32_t cnt = end - i < 8 ? (uint32_t)(end - i) : 8u;
+    uint32_t pk0 = 0, pk1 = 0, pk2 = 0, pk3 = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < 8; t++) {
+      if (t >= cnt || bad) break;
+      if (have < 32) {
+        const uint64_t w = wi < nwords ? words[wi] : 0;
+        buf |= (w << 32) >> have;
+        have += 32;
+        wi++;
       }
+      uint32_t L;
+      const uint32_t sym = decode_one(a, lut, sorted, (uint32_t)(buf >> 32), L);
       if (!L) {
         bad = true;
         break;
       }
+      zeros += sym == 0;
+      buf <<= L;
+      have -= (int)L;
+      pos += L;
+      const uint32_t v = sym << ((t & 1) * 16);
+      if (t < 2) pk0 |= v;
+      else if (t < 4) pk1 |= v;
+      else if (t < 6) pk2 |= v;
+      else pk3 |= v;
     }
-    zeros += sym == 0;
-    buf <<= L;
-    have -= (int)L;
-    pos += L;
-    const uint32_t slot = (uint32_t)(i - beg) & 7u;
-    if (aligned) {
-      pack[slot >> 1] |= sym << ((slot & 1) * 16);
-      if (slot == 7 || i + 1 == end) {
-        const uint64_t base = i & ~7ull;
-        if (slot == 7) {
-          *reinterpret_cast<uint4*>(code + base) = make_uint4(pack[0], pack[1], pack[2], pack[3]);
-        } else {
-          for (uint32_t t = 0; t <= slot; t++) code[base + t] = (uint16_t)(pack[t >> 1] >> ((t & 1) * 16));
-        }
-        pack[0] = pack[1] = pack[2] = pack[3] = 0;
-      }
+    if (cnt == 8) {
+      *reinterpret_cast<uint4*>(code + i) = make_uint4(pk0, pk1, pk2, pk3);
     } else {
-      code[i] = (uint16_t)sym;
+      for (uint32_t t = 0; t < cnt; t++) {
+        const uint32_t wv = t < 2 ? pk0 : t < 4 ? pk1 : t < 6 ? pk2 : pk3;
+        code[i + t] = (uint16_t)(wv >> ((t & 1) * 16));
+      }
     }
   }
   if (bad || pos != stop) atomicOr(status, 1);
@@ -363,13 +444,12 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
 }
 
 hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
-                          const uint32_t* lut, const uint32_t* first, const uint32_t* count,
-                          const uint32_t* offset, const uint16_t* sorted, uint16_t* code,
+                          const uint32_t* lut, const uint16_t* sorted, uint16_t* code,
                           uint32_t* czero, int* status, hipStream_t st)
 {
   if (!a.nch) return hipSuccess;
   hipLaunchKernelGGL(decode2_kernel, dim3((unsigned)((a.nch + 255) / 256)), dim3(256), 0, st, a, words,
-                     bit_off, lut, first, count, offset, sorted, code, czero, status);
+                     bit_off, lut, sorted, code, czero, status);
   return hipGetLastError();
 }
 

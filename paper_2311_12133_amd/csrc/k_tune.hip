@@ -14,6 +14,7 @@
 //    same regions (Sec. 6.5), histogrammed.
 // All scores are integers, so decisions are independent of summation order.
 
+#include "box_dev.h"
 #include "interp_dev.h"
 #include "tune_dev.h"
 
@@ -75,7 +76,7 @@ __device__ void trial_step(const TrialArgs& a, const TrialBox& bx, const int64_t
                            const T* __restrict__ X, P* W, const int64_t* r, const int64_t* m,
                            int kind, int md, int sl, int pd, unsigned odd, int64_t s, int level,
                            const double* __restrict__ wq, unsigned long long& score,
-                           uint32_t* __restrict__ hist)
+                           uint32_t* __restrict__ hist, uint32_t* lh)
 {
   uint32_t cnt[4];
   uint64_t total = 1;
@@ -116,16 +117,19 @@ __device__ void trial_step(const TrialArgs& a, const TrialBox& bx, const int64_t
     T xr = xv;
     const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, a.R, xr);
     W[idx] = q ? xr : xv;
-    if (hist) atomicAdd(&hist[q], 1u);
+    if (hist) hist_add_wave(lh, hist, a.hist_lo, kTrialHistWin, q, true);
   }
 }
 
 template <typename T, typename P>
 __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __restrict__ X, P* W,
                            int cand, const double* __restrict__ wq,
-                           unsigned long long* __restrict__ score, uint32_t* __restrict__ hist)
+                           unsigned long long* __restrict__ score, uint32_t* __restrict__ hist,
+                           uint32_t* lh)
 {
   __shared__ unsigned long long red[256];
+  if (hist)
+    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x) lh[i] = 0;
   int32_t act[4];
   int64_t bst[4];
   bst[3] = 1;
@@ -172,7 +176,7 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
             else if (odd >> d & 1u) { r[d] = s; m[d] = 2 * s; }
             else { r[d] = 0; m[d] = 2 * s; }
           }
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 1, 0, -1, odd, s, l, wq, sc, hist);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 1, 0, -1, odd, s, l, wq, sc, hist, lh);
         }
         __syncthreads();
       }
@@ -195,12 +199,12 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
         if (ip.kind != 0 && ip.same_level) {
           m[pd] = 4 * s;
           r[pd] = s;
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh);
           __syncthreads();
           r[pd] = 3 * s;
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 1, pd, 0, s, l, wq, sc, hist);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 1, pd, 0, s, l, wq, sc, hist, lh);
         } else {
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh);
         }
         __syncthreads();
       }
@@ -213,6 +217,11 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
     }
   }
   if (a.score_mode == 1 && threadIdx.x == 0) score[(uint64_t)blockIdx.x * gridDim.y + cand] = total_score;
+  if (hist) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x)
+      if (lh[i]) atomicAdd(&hist[a.hist_lo + i], lh[i]);
+  }
 }
 
 template <typename T>
@@ -224,9 +233,11 @@ __global__ void __launch_bounds__(256) trial_kernel_global(TrialArgs a,
                                                            unsigned long long* __restrict__ score,
                                                            uint32_t* __restrict__ hist)
 {
+  extern __shared__ unsigned char lds_raw[];
   const TrialBox bx = boxes[blockIdx.x];
   T* W = scratch + ((uint64_t)blockIdx.x * gridDim.y + blockIdx.y) * a.box_cap;
-  trial_body<T, T>(a, bx, X, W, (int)blockIdx.y, wq, score, hist);
+  trial_body<T, T>(a, bx, X, W, (int)blockIdx.y, wq, score, hist,
+                   reinterpret_cast<uint32_t*>(lds_raw));
 }
 
 template <typename T>
@@ -240,7 +251,86 @@ __global__ void __launch_bounds__(256) trial_kernel_lds(TrialArgs a,
   extern __shared__ unsigned char lds_raw[];
   T* W = reinterpret_cast<T*>(lds_raw);
   const TrialBox bx = boxes[blockIdx.x];
-  trial_body<T, T>(a, bx, X, W, (int)blockIdx.y, wq, score, hist);
+  trial_body<T, T>(a, bx, X, W, (int)blockIdx.y, wq, score, hist,
+                   reinterpret_cast<uint32_t*>(lds_raw + ((a.box_cap * sizeof(T) + 15) & ~15ull)));
+}
+
+// Trial of a region of at most three dims held entirely in LDS (original
+// values, then reconstructions in place), on the shared box schedule.
+template <typename T, bool HIST>
+__global__ void __launch_bounds__(1024) trial_box_kernel(TrialArgs a,
+                                                         const TrialBox* __restrict__ boxes,
+                                                         const T* __restrict__ X,
+                                                         const double* __restrict__ wq,
+                                                         unsigned long long* __restrict__ score,
+                                                         uint32_t* __restrict__ hist)
+{
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ unsigned long long red[16];
+  T* L = reinterpret_cast<T*>(lds_raw);
+  uint32_t* lh = reinterpret_cast<uint32_t*>(lds_raw + ((a.box_cap * sizeof(T) + 15) & ~15ull));
+  const TrialBox tb = boxes[blockIdx.x];
+  const int cand = (int)blockIdx.y;
+  Box bx;
+  bx.E0 = (int32_t)tb.m[0];
+  bx.E1 = (int32_t)tb.m[1];
+  bx.E2 = (int32_t)tb.m[2];
+  bx.b1 = bx.E2;
+  bx.b0 = bx.E1 * bx.E2;
+  bx.a0 = bx.E0 > 1 && a.frozen != 0;
+  bx.a1 = bx.E1 > 1 && a.frozen != 1;
+  bx.a2 = bx.E2 > 1 && a.frozen != 2;
+  bx.lo0 = bx.lo1 = bx.lo2 = 0;
+  bx.hi0 = bx.E0 - 1;
+  bx.hi1 = bx.E1 - 1;
+  bx.hi2 = bx.E2 - 1;
+  // the region, row-major
+  const uint32_t npts = (uint32_t)bx.E0 * bx.b0;
+  const uint32_t mgb0 = fmagic((uint32_t)bx.b0), mgE2 = fmagic((uint32_t)bx.E2);
+  const int64_t st0 = a.fg.st[0], st1 = a.fg.st[1];
+  const T* __restrict__ Xo = X + tb.o[0] * st0 + tb.o[1] * st1 + tb.o[2];
+  for (uint32_t i = threadIdx.x; i < npts; i += blockDim.x) {
+    const uint32_t c0 = fdiv(i, mgb0);
+    const uint32_t rem = i - c0 * (uint32_t)bx.b0;
+    const uint32_t c1 = fdiv(rem, mgE2);
+    const uint32_t c2 = rem - c1 * (uint32_t)bx.E2;
+    L[i] = Xo[c0 * st0 + c1 * st1 + c2];
+  }
+  if (HIST)
+    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
+  const uint32_t R = a.R;
+  const double mul = a.score_mul;
+  unsigned long long total_score = 0;
+  for (int l = a.L; l >= 1; l--) {
+    const int32_t s = 1 << (l - 1);
+    const hpez_interp ip = a.tuned ? a.level[l - 1] : a.cand[cand];
+    const double el = a.el[l], inv2e = a.inv2e[l], twoe = a.twoe[l];
+    unsigned long long sc = 0;
+    auto op = [&](int32_t li, int32_t, int32_t, int32_t, T p) {
+      const T xv = L[li];
+      const double t = fabs((double)xv - (double)p) * mul;
+      sc += (t < 4294967296.0) ? (unsigned long long)floor(t) : 4294967296ull;
+      T xr = xv;
+      const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
+      L[li] = q ? xr : xv;
+      if (HIST) hist_add_wave(lh, hist, a.hist_lo, kTrialHistWin, q, true);
+    };
+    box_level<T>(ip, bx, L, 0, 0, 0, s, wq, op);
+    const unsigned long long v = block_sum_u64(sc, red);
+    if (a.score_mode == 0) {
+      if (threadIdx.x == 0 && v) atomicAdd(&score[cand * 16 + (l - 1)], v);
+    } else {
+      total_score += v;
+    }
+  }
+  if (a.score_mode == 1 && threadIdx.x == 0)
+    score[(uint64_t)blockIdx.x * gridDim.y + cand] = total_score;
+  if (HIST) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x)
+      if (lh[i]) atomicAdd(&hist[a.hist_lo + i], lh[i]);
+  }
 }
 
 template <typename T>
@@ -249,12 +339,33 @@ hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n
                          unsigned long long* d_score, uint32_t* d_hist, hipStream_t st)
 {
   if (!n_boxes || !n_cand) return hipSuccess;
-  const size_t lds = (size_t)a.box_cap * sizeof(T);
-  if (lds <= kTrialLdsBytes)
-    hipLaunchKernelGGL((trial_kernel_lds<T>), dim3(n_boxes, n_cand), dim3(256), lds, st, a, d_boxes,
-                       X, d_wq, d_score, d_hist);
-  else
-    hipLaunchKernelGGL((trial_kernel_global<T>), dim3(n_boxes, n_cand), dim3(256), 0, st, a,
+  const size_t box = (size_t)a.box_cap * sizeof(T);
+  const size_t hb = d_hist ? (size_t)kTrialHistWin * 4 : 0;
+  const size_t lds_all = ((box + 15) & ~(size_t)15) + hb;
+  if (a.fg.n[3] == 1 && lds_all <= kTrialBoxLdsBytes) {
+    // regions of at most three dims in LDS: 1024 lanes for large regions
+    const unsigned threads = a.box_cap > 4096 ? 1024u : 256u;
+    if (d_hist) {
+      (void)hipFuncSetAttribute((const void*)trial_box_kernel<T, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
+      hipLaunchKernelGGL((trial_box_kernel<T, true>), dim3(n_boxes, n_cand), dim3(threads), lds_all,
+                         st, a, d_boxes, X, d_wq, d_score, d_hist);
+    } else {
+      (void)hipFuncSetAttribute((const void*)trial_box_kernel<T, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
+      hipLaunchKernelGGL((trial_box_kernel<T, false>), dim3(n_boxes, n_cand), dim3(threads),
+                         lds_all, st, a, d_boxes, X, d_wq, d_score, d_hist);
+    }
+    return hipGetLastError();
+  }
+  if (box <= kTrialLdsBytes) {
+    const size_t lds = ((box + 15) & ~(size_t)15) + hb;
+    (void)hipFuncSetAttribute((const void*)trial_kernel_lds<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((trial_kernel_lds<T>), dim3(n_boxes, n_cand), dim3(256), lds, st, a,
+                       d_boxes, X, d_wq, d_score, d_hist);
+  } else
+    hipLaunchKernelGGL((trial_kernel_global<T>), dim3(n_boxes, n_cand), dim3(256), hb, st, a,
                        d_boxes, X, scratch, d_wq, d_score, d_hist);
   return hipGetLastError();
 }
@@ -264,9 +375,13 @@ hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n
 template <typename T>
 __global__ void __launch_bounds__(256) lorenzo_trial_kernel(Geom fg, const TrialBox* __restrict__ boxes,
                                                             const T* __restrict__ X, double inv2e,
-                                                            uint32_t R, uint32_t* __restrict__ hist,
+                                                            uint32_t R, uint32_t hist_lo,
+                                                            uint32_t* __restrict__ hist,
                                                             int* __restrict__ unsupported)
 {
+  __shared__ uint32_t lh[kTrialHistWin];
+  for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
   const TrialBox bx = boxes[blockIdx.y];
   const int64_t npts = (int64_t)bx.m[0] * bx.m[1] * bx.m[2] * bx.m[3];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts;
@@ -302,19 +417,26 @@ __global__ void __launch_bounds__(256) lorenzo_trial_kernel(Geom fg, const Trial
       continue;
     }
     const uint32_t code = (delta > -(long long)R && delta < (long long)R) ? (uint32_t)(delta + R) : 0u;
-    atomicAdd(&hist[code], 1u);
+    hist_add_wave(lh, hist, hist_lo, kTrialHistWin, code, true);
   }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x)
+    if (lh[i]) atomicAdd(&hist[hist_lo + i], lh[i]);
 }
 
 template <typename T>
 hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_t n_boxes,
                                 uint32_t max_pts, const T* X, double inv2e, uint32_t R,
-                                uint32_t* d_hist, int* d_unsupported, hipStream_t st)
+                                uint32_t hist_lo, uint32_t* d_hist, int* d_unsupported,
+                                hipStream_t st)
 {
   if (!n_boxes) return hipSuccess;
-  const unsigned gx = (max_pts + 255) / 256;
+  // a few work-groups per region, each walking many points, so the LDS
+  // histogram is flushed rarely
+  unsigned gx = (max_pts + 255) / 256;
+  if (gx > 8) gx = 8;
   hipLaunchKernelGGL((lorenzo_trial_kernel<T>), dim3(gx ? gx : 1, n_boxes), dim3(256), 0, st, fg,
-                     d_boxes, X, inv2e, R, d_hist, d_unsupported);
+                     d_boxes, X, inv2e, R, hist_lo, d_hist, d_unsupported);
   return hipGetLastError();
 }
 
@@ -325,8 +447,8 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
                                        const T*, T*, const double*, unsigned long long*,        \
                                        uint32_t*, hipStream_t);                                 \
   template hipError_t launch_lorenzo_trial<T>(const Geom&, const TrialBox*, uint32_t, uint32_t, \
-                                              const T*, double, uint32_t, uint32_t*, int*,      \
-                                              hipStream_t);
+                                              const T*, double, uint32_t, uint32_t, uint32_t*,  \
+                                              int*, hipStream_t);
 INST(float)
 INST(double)
 

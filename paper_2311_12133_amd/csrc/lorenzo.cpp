@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "hpez_host.h"
+#include "codec_dev.h"
 #include "lorenzo_dev.h"
 
 namespace hpez {
@@ -36,7 +37,7 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
   int rc;
   uint8_t* base = (uint8_t*)ctx_ws(ctx, need, &rc);
   if (rc) return rc;
-  uint8_t* pin = ctx_pin(ctx, nsym * 4 + nsym + kHdrBytes + 64, &rc);
+  uint8_t* pin = ctx_pin(ctx, nsym * 4 + nsym + kHdrBytes + 128 + nsym * 4, &rc);
   if (rc) return rc;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -63,6 +64,7 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
   uint8_t* h_hdr = h_len + nsym;
   uint64_t* h_np = (uint64_t*)(h_hdr + kHdrBytes);
   int* h_bad = (int*)(h_np + 1);
+  uint32_t* h_tab = (uint32_t*)(pin + (((size_t)nsym * 5 + kHdrBytes + 64 + 63) & ~(size_t)63));
 
   LorenzoArgs a;
   a.inv2e = 1.0 / (2.0 * e);
@@ -115,12 +117,11 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
   if (Lo.sym_max >= Lo.sym_min)
     LCK(hipMemcpyAsync(out + Lo.off_len, h_len + Lo.sym_min, Lo.sym_max - Lo.sym_min + 1,
                        hipMemcpyHostToDevice, st));
-  LCK(launch_chunk_lengths(code, N, c->chunk, dlen, cbits, czero, st));
-  LCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, t2, st));
-  LCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, t3, st));
-  LCK(launch_encode<T>(code, N, c->chunk, dlen, dcw, boff, zoff, cbits, czero,
-                       (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), X,
-                       (T*)nullptr, g, st));
+  LCK(launch_count_zeros(code, N, c->chunk, czero, zoff, t3, st));
+  rc = encode_payload(ctx, code, N, c->chunk, h_len, cw.data(), Lo.sym_min, Lo.sym_max, dlen, dcw,
+                      hist, boff, (uint32_t*)bad, h_tab, (uint32_t*)(out + Lo.off_payload),
+                      (uint16_t*)(out + Lo.off_chunks), st);
+  if (rc) return rc;
   LCK(launch_lorenzo_gather<T>(X, g, N, a, code, czero, zoff, pcount, poff,
                                (long long*)(out + Lo.off_outl), (uint64_t*)(out + Lo.off_pidx),
                                (T*)(out + Lo.off_pval), st));

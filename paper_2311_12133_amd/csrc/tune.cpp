@@ -177,6 +177,7 @@ int global_tune(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_
       if (w.h_score[ci * 16 + l - 1] < w.h_score[best[l] * 16 + l - 1]) best[l] = ci;
   }
   a.tuned = 1;
+  a.hist_lo = trial_hist_lo(Q->radius);
   for (int l = 1; l <= Lb; l++) a.level[l - 1] = cand[best[l]];
   TCK(hipMemsetAsync(w.hist, 0, sizeof(uint32_t) * nsym, st));
   TCK(hipMemsetAsync(w.dummy, 0, sizeof(unsigned long long) * 16, st));
@@ -207,7 +208,7 @@ int lorenzo_tune(const hpez_field_desc* d, const T* X, const hpez_config* Q, dou
   TCK(hipMemsetAsync(w.hist, 0, sizeof(uint32_t) * nsym, st));
   TCK(hipMemsetAsync(w.flag, 0, sizeof(int), st));
   TCK(launch_lorenzo_trial<T>(g, w.boxes, (uint32_t)bx.size(), (uint32_t)cap, X, 1.0 / (2.0 * e),
-                              Q->radius, w.hist, w.flag, st));
+                              Q->radius, trial_hist_lo(Q->radius), w.hist, w.flag, st));
   int h_flag = 0;
   TCK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(uint32_t) * nsym, hipMemcpyDeviceToHost, st));
   TCK(hipMemcpyAsync(&h_flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -6,6 +6,8 @@
 namespace hpez {
 
 constexpr size_t kTrialLdsBytes = 48 * 1024;  // regions up to this size run from LDS
+constexpr uint32_t kTrialHistWin = 4096;      // histogram bins kept in LDS (codes hist_lo ...)
+constexpr size_t kTrialBoxLdsBytes = 160 * 1024 - 256;  // in-LDS regions of up to three dims
 
 // A trial region: origin and extents inside the field.
 struct TrialBox {
@@ -20,7 +22,7 @@ struct TrialArgs {
   uint32_t R;
   int32_t tuned;       // 1: level[] per level; 0: candidate blockIdx.y on every level
   int32_t score_mode;  // 0: score[cand][level] summed over regions; 1: score[region][cand]
-  uint32_t pad;
+  uint32_t hist_lo;    // first code of the LDS histogram window
   uint64_t box_cap;    // points of the largest region (scratch stride)
   double score_mul;    // 4096 / e
   double el[17], inv2e[17], twoe[17];
@@ -54,6 +56,15 @@ hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n
 template <typename T>
 hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_t n_boxes,
                                 uint32_t max_pts, const T* X, double inv2e, uint32_t R,
-                                uint32_t* d_hist, int* d_unsupported, hipStream_t st);
+                                uint32_t hist_lo, uint32_t* d_hist, int* d_unsupported,
+                                hipStream_t st);
+// first code of a kTrialHistWin-wide window centred on R inside [0, 2R)
+inline uint32_t trial_hist_lo(uint32_t R)
+{
+  const uint32_t nsym = 2 * R;
+  uint32_t lo = R > kTrialHistWin / 2 ? R - kTrialHistWin / 2 : 0;
+  if (lo + kTrialHistWin > nsym) lo = nsym > kTrialHistWin ? nsym - kTrialHistWin : 0;
+  return lo;
+}
 
 }  // namespace hpez
