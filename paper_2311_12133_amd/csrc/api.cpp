@@ -1021,6 +1021,15 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   da.nbits = Lo.payload_bits;
   da.chunk = c->chunk;
   decode_tables(h_len, nsym, lut.data(), sorted.data(), da.lim, da.base);
+  {
+    uint32_t nshort = 0, nused = 0;
+    for (uint32_t k = 0; k < nsym; k++) {
+      nused += h_len[k] != 0;
+      nshort += h_len[k] != 0 && h_len[k] <= kLutBits;
+    }
+    da.long_first = nshort;
+    da.n_long = nused - nshort;
+  }
   HIPCK(hipMemcpyAsync(dlut, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(dsorted, sorted.data(), sorted.size() * 2, hipMemcpyHostToDevice, st));
   double h_wq[3 * 16 * 4];
@@ -1060,8 +1069,8 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
     return HPEZ_OK;
   }
   if (Lo.n_unpred)
-    HIPCK(launch_scatter_unpred<T>(code, N, c->chunk, czero, zoff, (const T*)(in + Lo.off_unpred),
-                                   Lo.n_unpred, out, status, g, st));
+    HIPCK(launch_scatter_unpred2<T>(code, N, c->chunk, czero, zoff, (const T*)(in + Lo.off_unpred),
+                                    Lo.n_unpred, out, status, g, st));
   const Lattice al = anchor_lattice(g, c->anchor_log2);
   if (al.total != Lo.n_anchor) return HPEZ_ECORRUPT;
   HIPCK(launch_anchors<T>(g, al, nullptr, out, code, (T*)(in + Lo.off_anchor), c->radius, 1, st));

@@ -60,7 +60,7 @@ size_t block_fast_bytes(const Geom& g)
   size_t b = 0;
   for (int e = 0; e < 4; e++)
     b += ((elems[e] * sizeof(T) + 255) & ~(size_t)255) + ((elems[e] * 2 + 255) & ~(size_t)255);
-  return b + 1024;
+  return b + 1024;  // + the work counter of the block kernel
 }
 
 template <typename T>
@@ -81,6 +81,7 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
     f.code[k] = (uint16_t*)p;
     p += (elems[k] * 2 + 255) & ~(size_t)255;
   }
+  uint32_t* ticket = (uint32_t*)p;
   // anchors and levels >= B: copy the coarse grid into the face arrays
   int64_t r[4], m[4];
   for (int k = 0; k < 4; k++) {
@@ -198,6 +199,7 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
   ba.L = Lb;
   ba.R = c->radius;
   ba.hist_lo = hist_lo;
+  ba.vec = (g.n[2] % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)out % 16 == 0);
   for (int l = 1; l <= 16; l++) {
     const double el = level_eb(e, c->alpha, c->beta, l);
     ba.el_l[l] = el;
@@ -205,8 +207,17 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
     ba.twoe_l[l] = 2.0 * el;
   }
   for (uint32_t i = 0; i < c->n_cand && i < 16; i++) ba.cand[i] = c->cand[i];
+  for (int k = 0; k < 3; k++)
+    for (int odd = 0; odd < 8; odd++)
+      for (int d = 0; d < 4; d++) ba.wmd[(k * 8 + odd) * 4 + d] = h_wq[(k * 16 + odd) * 4 + d];
   ev = ctx_span_begin(ctx, st);
-  BCK(launch_blocks<T>(ba, f, X, code, d_bcfg, d_wq, hist, out, mode, st));
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx_device(ctx)) !=
+          hipSuccess ||
+      n_cu <= 0)
+    return HPEZ_EDEVICE;
+  BCK(hipMemsetAsync(ticket, 0, sizeof(uint32_t), st));
+  BCK(launch_blocks<T>(ba, f, X, code, d_bcfg, hist, out, ticket, n_cu, mode, st));
   ctx_span_end(ctx, ev, mode == 0 ? "blocks_predict" : "blocks_reconstruct",
                npts * (sizeof(T) + 2), st);
   return HPEZ_OK;

@@ -5,13 +5,14 @@
 
 namespace hpez {
 
-constexpr int kBlockHistWin = 8192;  // LDS histogram window of the block kernel
+constexpr int kBlockHistWin = 4096;  // LDS histogram window of the block kernel
+constexpr int kBlockThreads = 1024;  // work-group size of the block kernel
 
 // Compact face arrays: family e holds the planes x_e = 0, B, 2B, ... with layout
 // [plane][other dims row-major]; index = (x_e / B) * plane[e] + sum_k x_k fs[e][k].
 struct FaceGeo {
   void* val[4];        // T values per family (nullptr for inactive dims)
-  uint16_t* code[4];   // codes per family
+  uint16_t* code[4];   // compress: codes of the points whose lowest face family is d
   int64_t plane[4];    // points per plane
   int64_t fs[4][4];    // strides of the other dims inside a plane (fs[e][e] = 0)
   int64_t B;
@@ -42,8 +43,9 @@ struct BlockArgs {
   int32_t L;           // levels handled: stride 2^(L-1) .. 1
   uint32_t R;
   uint32_t hist_lo;    // first symbol of the LDS histogram window
-  uint32_t pad;
+  int32_t vec;         // rows along dim 2 are 16-byte aligned in X / out / face arrays
   double el_l[17], inv2e_l[17], twoe_l[17];
+  double wmd[3 * 8 * 4];  // MD weights [kind][odd set][dim] (Eq. 12), first three dims
   hpez_interp cand[16];
 };
 
@@ -55,9 +57,10 @@ hipError_t launch_face_step(const FaceStep& a, const FaceGeo& f, const T* X, uin
                             const T* out, int mode, hipStream_t st);
 template <typename T>
 size_t block_lds_bytes(const Geom& g);
+// ticket: one zeroed device word (work distribution); n_cu: compute units
 template <typename T>
 hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint16_t* code,
-                         const uint8_t* d_bcfg, const double* d_wq, uint32_t* hist, T* out,
+                         const uint8_t* d_bcfg, uint32_t* hist, T* out, uint32_t* ticket, int n_cu,
                          int mode, hipStream_t st);
 
 }  // namespace hpez

@@ -24,11 +24,6 @@ struct Box {
   int32_t a0, a1, a2;     // active dims
 };
 
-// exact n / d for n, d < 2^16 (so n * d < 2^32) with m = ceil(2^32 / d); for
-// d = 1 the multiplier 2^32 does not fit and is stored as 0
-__device__ __forceinline__ uint32_t fmagic(uint32_t d) { return (uint32_t)((0xFFFFFFFFull / d) + 1); }
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
-
 // smallest c >= lo with (o + c) == r (mod m), m a power of two
 __device__ __forceinline__ int32_t first_in(int64_t o, int32_t lo, int32_t r, int32_t m)
 {
@@ -79,9 +74,13 @@ __device__ __forceinline__ T stencil_box(const T* L, int32_t li, int32_t sd, int
 
 // One step: every cell with c_d == r_d (mod m_d), c_d in [lo_d, hi_d], for the
 // three dims.  pd >= 0: 1D prediction along pd; pd < 0: multi-dimensional over
-// the odd set `odd` with weights w0..w2 (sum left to right, Eq. 12).  op(li,
-// x0, x1, x2, p) consumes each prediction.
-template <typename T, int KIND, int SL, bool MD, class Op>
+// the odd set `odd` with weights w0..w2 (sum left to right, Eq. 12).  NT is the
+// work-group size.  The points of a step are independent, so each lane takes
+// kU of them at once: op.fetch(x0, x1, x2) for all of them first (global loads
+// in flight together), then the predictions and op.apply(li, x0, x1, x2, p, f).
+constexpr int kU = 4;
+
+template <typename T, int KIND, int SL, bool MD, int NT, class Op>
 __device__ __forceinline__ void box_step(const Box& bx, const T* L, int32_t r0, int32_t r1,
                                          int32_t r2, int32_t m0, int32_t m1, int32_t m2,
                                          int64_t o0, int64_t o1, int64_t o2, int pd, unsigned odd,
@@ -89,65 +88,83 @@ __device__ __forceinline__ void box_step(const Box& bx, const T* L, int32_t r0, 
 {
   const int32_t f0 = first_in(o0, bx.lo0, r0, m0), f1 = first_in(o1, bx.lo1, r1, m1),
                 f2 = first_in(o2, bx.lo2, r2, m2);
-  const int32_t c0 = f0 <= bx.hi0 ? (bx.hi0 - f0) / m0 + 1 : 0;
-  const int32_t c1 = f1 <= bx.hi1 ? (bx.hi1 - f1) / m1 + 1 : 0;
-  const int32_t c2 = f2 <= bx.hi2 ? (bx.hi2 - f2) / m2 + 1 : 0;
+  const int32_t c0 = f0 <= bx.hi0 ? ((bx.hi0 - f0) >> (31 - __clz(m0))) + 1 : 0;
+  const int32_t c1 = f1 <= bx.hi1 ? ((bx.hi1 - f1) >> (31 - __clz(m1))) + 1 : 0;
+  const int32_t c2 = f2 <= bx.hi2 ? ((bx.hi2 - f2) >> (31 - __clz(m2))) + 1 : 0;
   const uint32_t c12 = (uint32_t)(c1 * c2);
   const uint32_t total = (uint32_t)c0 * c12;
-  if (!total) return;
-  const uint32_t mg12 = fmagic(c12), mg2 = fmagic((uint32_t)c2);
+  // waves with no point in this step skip it before any further setup
+  if ((threadIdx.x & ~63u) >= total) return;
+  const Divisor mg12 = fmagic(c12);
+  const Divisor mg2 = fmagic((uint32_t)c2);
   // plain values first: a select between two fields of bx would keep bx in memory
   const int32_t B0 = bx.b0, B1 = bx.b1, L0 = bx.E0 - 1, L1 = bx.E1 - 1, L2 = bx.E2 - 1;
   const int32_t bsd = pd == 0 ? B0 : (pd == 1 ? B1 : 1);
   const int32_t last = pd == 0 ? L0 : (pd == 1 ? L1 : L2);
   const int32_t sd = s * bsd;
-  for (uint32_t k = threadIdx.x; k < total; k += blockDim.x) {
-    const uint32_t i0 = fdiv(k, mg12);
-    const uint32_t rem = k - i0 * c12;
-    const uint32_t i1 = fdiv(rem, mg2);
-    const uint32_t i2 = rem - i1 * (uint32_t)c2;
-    const int32_t x0 = f0 + (int32_t)i0 * m0, x1 = f1 + (int32_t)i1 * m1, x2 = f2 + (int32_t)i2 * m2;
-    const int32_t li = x0 * B0 + x1 * B1 + x2;
-    T p;
-    if (!MD) {
-      const int32_t xd = pd == 0 ? x0 : (pd == 1 ? x1 : x2);
-      p = stencil_box<T, KIND, SL>(L, li, sd, xd, s, last);
-    } else {
-      bool first = true;
-      T acc = (T)0;
-      if (odd & 1u) {
-        acc = w0 * stencil_box<T, KIND, 0>(L, li, s * B0, x0, s, L0);
-        first = false;
-      }
-      if (odd & 2u) {
-        const T t = w1 * stencil_box<T, KIND, 0>(L, li, s * B1, x1, s, L1);
-        acc = first ? t : acc + t;
-        first = false;
-      }
-      if (odd & 4u) {
-        const T t = w2 * stencil_box<T, KIND, 0>(L, li, s, x2, s, L2);
-        acc = first ? t : acc + t;
-      }
-      p = acc;
+  for (uint32_t kb = 0; kb < total; kb += kU * NT) {
+    int32_t x0[kU], x1[kU], x2[kU];
+    typename Op::Fetched fv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint32_t k = kb + u * NT + threadIdx.x;
+      const uint32_t kk = k < total ? k : 0u;
+      const uint32_t i0 = fdiv(kk, mg12);
+      const uint32_t rem = kk - i0 * c12;
+      const uint32_t i1 = fdiv(rem, mg2);
+      const uint32_t i2 = rem - i1 * (uint32_t)c2;
+      x0[u] = f0 + (int32_t)i0 * m0;
+      x1[u] = f1 + (int32_t)i1 * m1;
+      x2[u] = f2 + (int32_t)i2 * m2;
+      fv[u] = op.fetch(x0[u], x1[u], x2[u], k < total);
     }
-    op(li, x0, x1, x2, p);
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      if (kb + u * NT + threadIdx.x >= total) continue;
+      const int32_t li = x0[u] * B0 + x1[u] * B1 + x2[u];
+      T p;
+      if (!MD) {
+        const int32_t xd = pd == 0 ? x0[u] : (pd == 1 ? x1[u] : x2[u]);
+        p = stencil_box<T, KIND, SL>(L, li, sd, xd, s, last);
+      } else {
+        bool first = true;
+        T acc = (T)0;
+        if (odd & 1u) {
+          acc = w0 * stencil_box<T, KIND, 0>(L, li, s * B0, x0[u], s, L0);
+          first = false;
+        }
+        if (odd & 2u) {
+          const T t = w1 * stencil_box<T, KIND, 0>(L, li, s * B1, x1[u], s, L1);
+          acc = first ? t : acc + t;
+          first = false;
+        }
+        if (odd & 4u) {
+          const T t = w2 * stencil_box<T, KIND, 0>(L, li, s, x2[u], s, L2);
+          acc = first ? t : acc + t;
+        }
+        p = acc;
+      }
+      op.apply(li, x0[u], x1[u], x2[u], p, fv[u]);
+    }
   }
 }
 
-template <typename T, int KIND, int SL, class Op>
+template <typename T, int KIND, int SL, int NT, class Op>
 __device__ __forceinline__ void box_step_k(bool md, const Box& bx, const T* L, int32_t r0, int32_t r1,
                                            int32_t r2, int32_t m0, int32_t m1, int32_t m2, int64_t o0,
                                            int64_t o1, int64_t o2, int pd, unsigned odd, int32_t s,
                                            T w0, T w1, T w2, Op& op)
 {
   if (md)
-    box_step<T, KIND, 0, true>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step<T, KIND, 0, true, NT>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2,
+                                   op);
   else
-    box_step<T, KIND, SL, false>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step<T, KIND, SL, false, NT>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1,
+                                     w2, op);
 }
 
 // runtime (uniform) kind / same-level / paradigm to the compiled step
-template <typename T, class Op>
+template <typename T, int NT, class Op>
 __device__ __forceinline__ void box_step_any(int kind, int sl, bool md, const Box& bx, const T* L,
                                              int32_t r0, int32_t r1, int32_t r2, int32_t m0,
                                              int32_t m1, int32_t m2, int64_t o0, int64_t o1,
@@ -155,24 +172,24 @@ __device__ __forceinline__ void box_step_any(int kind, int sl, bool md, const Bo
                                              T w2, Op& op)
 {
   if (kind == 0)
-    box_step_k<T, 0, 0>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 0, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
   else if (kind == 1 && sl)
-    box_step_k<T, 1, 1>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 1, 1, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
   else if (kind == 1)
-    box_step_k<T, 1, 0>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 1, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
   else if (sl)
-    box_step_k<T, 2, 1>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 2, 1, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
   else
-    box_step_k<T, 2, 0>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 2, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
 }
 
 // One level (stride s) with configuration c: all its steps, each followed by a
 // work-group barrier.  The box origin (o0, o1, o2) fixes the residues (the
-// lattice is global: coordinates o + c).  wq: MD weights [kind][odd][dim].
-template <typename T, class Op>
+// lattice is global: coordinates o + c).  wmd: MD weights [kind][odd set < 8][dim < 4].
+template <typename T, int NT, class Op>
 __device__ __forceinline__ void box_level(const hpez_interp& c, const Box& bx, T* L, int64_t o0,
-                                          int64_t o1, int64_t o2, int32_t s,
-                                          const double* __restrict__ wq, Op& op)
+                                          int64_t o1, int64_t o2, int32_t s, const double* wmd,
+                                          Op& op)
 {
   const int a0 = bx.a0, a1 = bx.a1, a2 = bx.a2;
   if (c.md) {
@@ -183,9 +200,9 @@ __device__ __forceinline__ void box_level(const hpez_interp& c, const Box& bx, T
         if ((int)__popc(odd) != cnt) continue;
         if (((odd & 1u) && !a0) || ((odd & 2u) && !a1) || ((odd & 4u) && !a2)) continue;
         const int32_t r0 = (odd & 1u) ? s : 0, r1 = (odd & 2u) ? s : 0, r2 = (odd & 4u) ? s : 0;
-        const double* w = wq + (c.kind * 16 + odd) * 4;
-        box_step_any<T>(c.kind, 0, true, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, -1, odd, s,
-                        (T)w[0], (T)w[1], (T)w[2], op);
+        const double* w = wmd + (c.kind * 8 + odd) * 4;
+        box_step_any<T, NT>(c.kind, 0, true, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, -1, odd, s,
+                            (T)w[0], (T)w[1], (T)w[2], op);
       }
       __syncthreads();
     }
@@ -218,8 +235,8 @@ __device__ __forceinline__ void box_level(const hpez_interp& c, const Box& bx, T
       if (pd == 0) { r0 = rh; m0 = mh; }
       if (pd == 1) { r1 = rh; m1 = mh; }
       if (pd == 2) { r2 = rh; m2 = mh; }
-      box_step_any<T>(c.kind, half, false, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, 0u, s,
-                      (T)0, (T)0, (T)0, op);
+      box_step_any<T, NT>(c.kind, half, false, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, 0u, s,
+                          (T)0, (T)0, (T)0, op);
       __syncthreads();
     }
     earlier |= 1u << pd;

@@ -7,6 +7,7 @@ namespace hpez {
 
 constexpr uint32_t kEncTab = 8192;   // codebook entries held in LDS by the encoder
 constexpr uint32_t kEncWords = 1026; // LDS words per chunk (1024 symbols x 32 bits + 2)
+constexpr uint32_t kDecLong = 8192;  // codes longer than the decode table kept in LDS
 
 struct EncodeArgs {
   uint64_t n;        // symbols
@@ -27,6 +28,8 @@ struct DecodeArgs {
   uint64_t nch;      // chunks
   uint64_t nbits;    // payload bits
   uint32_t chunk;
+  uint32_t long_first;       // index in sorted[] of the first code longer than kLutBits
+  uint32_t n_long;           // number of such codes (held in LDS when <= kDecLong)
   uint32_t pad;
   uint64_t lim[kLmax + 1];   // lim[l] = (first code of length l + count) << (32 - l)
   uint32_t base[kLmax + 1];  // offset of length l in sorted[] minus its first code (mod 2^32)
@@ -44,6 +47,13 @@ template <typename T>
 hipError_t launch_gather_unpred(const uint16_t* code, uint64_t n, uint32_t chunk, uint32_t* czero,
                                 uint64_t* zoff, uint64_t* tmp, const T* X, T* unpred, const Geom& g,
                                 hipStream_t st);
+// verbatim values scattered from stream order into W (decompress); a rank at or
+// beyond n_unpred sets *d_status
+template <typename T>
+hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chunk,
+                                  const uint32_t* czero, const uint64_t* zoff, const T* unpred,
+                                  uint64_t n_unpred, T* W, int* d_status, const Geom& g,
+                                  hipStream_t st);
 hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
                           const uint32_t* lut, const uint16_t* sorted, uint16_t* code,
                           uint32_t* czero, int* status, hipStream_t st);

@@ -80,28 +80,8 @@ hipError_t launch_minmax_final(double* d_part, int nblocks, double* d_out, hipSt
 // Huffman
 hipError_t launch_histogram(const uint16_t* code, uint64_t n, uint32_t* hist, uint32_t nsym,
                             uint32_t R, hipStream_t st);
-hipError_t launch_chunk_lengths(const uint16_t* code, uint64_t n, uint32_t chunk,
-                                const uint8_t* d_len, uint32_t* chunk_bits, uint32_t* chunk_zero,
-                                hipStream_t st);
 hipError_t launch_scan_u32_to_u64(const uint32_t* in, uint64_t n, uint64_t* out_excl,
                                   uint64_t* d_total, uint64_t* tmp, hipStream_t st);
-hipError_t launch_zero_words(uint32_t* words, const uint64_t* d_total_bits, hipStream_t st);
-template <typename T>
-hipError_t launch_encode(const uint16_t* code, uint64_t n, uint32_t chunk, const uint8_t* d_len,
-                         const uint32_t* d_cw, const uint64_t* bit_off, const uint64_t* zero_off,
-                         const uint32_t* chunk_bits, const uint32_t* chunk_zero, uint32_t* payload,
-                         uint16_t* out_chunk_bits, const T* X, T* out_unpred, const Geom& g,
-                         hipStream_t st);
 hipError_t launch_u16_to_u32(const uint16_t* in, uint64_t n, uint32_t* out, hipStream_t st);
-template <typename T>
-hipError_t launch_decode(const uint32_t* payload, uint64_t nbits, const uint64_t* bit_off,
-                         uint64_t n, uint32_t chunk, const uint32_t* d_lut, const uint32_t* d_first,
-                         const uint32_t* d_count, const uint32_t* d_offset, const uint16_t* d_sorted,
-                         uint16_t* code, uint32_t* chunk_zero, int* d_status, hipStream_t st);
-template <typename T>
-hipError_t launch_scatter_unpred(const uint16_t* code, uint64_t n, uint32_t chunk,
-                                 const uint32_t* chunk_zero, const uint64_t* zero_off,
-                                 const T* unpred, uint64_t n_unpred, T* W, int* d_status,
-                                 const Geom& g, hipStream_t st);
 
 }  // namespace hpez

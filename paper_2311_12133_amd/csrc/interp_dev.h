@@ -73,14 +73,17 @@ template <typename T>
 __device__ __forceinline__ uint32_t quantize(T x, T p, double inv2e, double twoe, double el,
                                              uint32_t R, T& xr)
 {
+  // evaluated without branches: both checks are computed and select the result
   const double t = ((double)x - (double)p) * inv2e;
   const double qf = floor(fabs(t) + 0.5);
-  if (!(qf < (double)R)) return 0;
+  const bool inr = qf < (double)R;
   const double q = t < 0 ? -qf : qf;
   const T r = (T)((double)p + q * twoe);
-  if (!(fabs((double)r - (double)x) <= el)) return 0;
-  xr = r;
-  return (uint32_t)((int64_t)q + (int64_t)R);
+  const bool ok = inr && fabs((double)r - (double)x) <= el;
+  xr = ok ? r : xr;
+  // |q| < R <= 2^15: the 32-bit conversion is exact; code 0 when not ok
+  const double qs = ok ? q : -(double)R;
+  return (uint32_t)((int32_t)qs + (int32_t)R);
 }
 
 // Stream (code) order: bricks of kBrick points per dimension, clipped at the
@@ -127,6 +130,31 @@ __host__ __device__ __forceinline__ void brick_coords(const int64_t* n, int64_t 
     r /= E[d];
   }
 }
+
+// Exact n / d for n, d < 2^16 (so n * d < 2^32) by multiply-high with
+// m = ceil(2^32 / d); d = 1 (m = 2^32 does not fit) is stored as 0.  Box
+// counts and extents never exceed 33 per dim, so every divisor is at most
+// kMagicMax and comes from a table in constant memory.
+constexpr uint32_t kMagicMax = 33 * 33 * 9;
+struct MagicTable {
+  uint32_t m[kMagicMax + 1];
+  constexpr MagicTable() : m()
+  {
+    for (uint32_t d = 2; d <= kMagicMax; d++) m[d] = (uint32_t)(0xFFFFFFFFull / d + 1);
+  }
+};
+__constant__ constexpr MagicTable kDivMagic{};
+struct Divisor {
+  uint32_t m;     // multiplier (0 for d = 1)
+  uint32_t pass;  // all ones for d = 1: the quotient is n itself
+};
+__device__ __forceinline__ Divisor fmagic(uint32_t d)
+{
+  const uint32_t m = kDivMagic.m[d];
+  return {m, m ? 0u : 0xFFFFFFFFu};
+}
+// branch-free: one multiply-high, one and, one add
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, Divisor d) { return __umulhi(n, d.m) + (n & d.pass); }
 
 // Histogram update for every lane with `valid`: lanes holding equal codes are
 // counted together (one atomic per distinct code in the wavefront), into the

@@ -7,15 +7,17 @@
 //   * faces: points with some active coordinate a multiple of B, with the
 //     level's global configuration.  A face point is never interpolated along
 //     the dimension that makes it a face, so every stencil stays inside its
-//     face plane.  Face values and codes live in compact per-family arrays
-//     (family d = the planes x_d = 0, B, 2B, ...; layout [plane][other dims],
-//     so every plane is contiguous);
+//     face plane.  Face values live in compact per-family arrays (family d =
+//     the planes x_d = 0, B, 2B, ...; layout [plane][other dims], so every
+//     plane is contiguous); face codes go straight to their stream positions
+//     and are counted there;
 //   * interiors: one work-group per block runs every level s < B for the
 //     block's own configuration, stencils clipped to the block's closed box.
 //     The box (B+1)^D lives in LDS and is updated in place: a cell holds the
 //     original value until its point is predicted, then the reconstruction.
-//     The work-group then writes the block's whole brick of codes (near-face
-//     codes copied from the face arrays) and histograms it.
+//     Work-groups are persistent (one per CU, blocks taken from a counter) and
+//     load the next block's box into registers while they compute the current
+//     one.
 
 #include "block_dev.h"
 #include "box_dev.h"
@@ -31,22 +33,28 @@ __device__ __forceinline__ int64_t face_index(const FaceGeo& f, int e, const int
   return i;
 }
 
-// write a face point's value (and code) into every family it belongs to
+// write a face point's value into every family it belongs to
 template <typename T>
-__device__ __forceinline__ void face_store(const FaceGeo& f, const Geom& g, const int64_t* x, T v,
-                                           uint16_t q, bool with_code)
+__device__ __forceinline__ void face_store(const FaceGeo& f, const Geom& g, const int64_t* x, T v)
 {
   for (int e = 0; e < 4; e++) {
     if (!g.act[e] || (x[e] & (f.B - 1))) continue;
-    const int64_t fi = face_index(f, e, x);
-    reinterpret_cast<T*>(f.val[e])[fi] = v;
-    if (with_code) f.code[e][fi] = q;
+    reinterpret_cast<T*>(f.val[e])[face_index(f, e, x)] = v;
   }
+}
+
+// the lowest family a face point belongs to (-1: not on a face)
+__device__ __forceinline__ int low_family(const FaceGeo& f, const Geom& g, const int64_t* x)
+{
+  for (int e = 0; e < 4; e++)
+    if (g.act[e] && (x[e] & (f.B - 1)) == 0) return e;
+  return -1;
 }
 
 // ---------------------------------------------------------------------------
 // points on the coarse grid of stride B (anchors and levels s >= B): copy the
-// working grid and codes into the face arrays
+// working grid into the face arrays (and, compressing, their codes into the
+// code array of their lowest family)
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) face_init_kernel(FaceGeo f, Geom g, Lattice lat,
                                                         const T* __restrict__ W,
@@ -57,8 +65,11 @@ __global__ void __launch_bounds__(256) face_init_kernel(FaceGeo f, Geom g, Latti
     int64_t x[4];
     lattice_point(lat, k, x);
     const int64_t idx = x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3];
-    const uint16_t q = MODE == 0 ? code[brick_pos(g.n, x)] : (uint16_t)0;
-    face_store<T>(f, g, x, W[idx], q, MODE == 0);
+    if (MODE == 0) {
+      const int e = low_family(f, g, x);
+      if (e >= 0) f.code[e][face_index(f, e, x)] = code[brick_pos(g.n, x)];
+    }
+    face_store<T>(f, g, x, W[idx]);
   }
 }
 
@@ -117,11 +128,12 @@ __global__ void __launch_bounds__(256) face_step_kernel(FaceStep a, FaceGeo f,
       const T xv = X[idx];
       T xr = xv;
       const uint32_t q = quantize<T>(xv, p, a.inv2e, a.twoe, a.el, a.R, xr);
-      face_store<T>(f, a.g, x, q ? xr : xv, (uint16_t)q, true);
+      f.code[d][fi] = (uint16_t)q;  // d is the point's lowest family
+      face_store<T>(f, a.g, x, xr);
     } else {
       const uint32_t q = code[brick_pos(a.g.n, x)];
-      const T v = q ? (T)((double)p + (double)((int64_t)q - (int64_t)a.R) * a.twoe) : out[idx];
-      face_store<T>(f, a.g, x, v, 0, false);
+      const T v = q ? (T)((double)p + (double)((int32_t)q - (int32_t)a.R) * a.twoe) : out[idx];
+      face_store<T>(f, a.g, x, v);
     }
   }
 }
@@ -167,136 +179,364 @@ __device__ __forceinline__ void block_geometry(const Geom& g, int64_t bi, const 
   bx.hi2 = k.Eb2 - 1;
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(1024) block_kernel(BlockArgs a, FaceGeo f, const T* __restrict__ X,
-                                                     uint16_t* __restrict__ code,
-                                                     const uint8_t* __restrict__ bcfg,
-                                                     const double* __restrict__ wq,
-                                                     uint32_t* __restrict__ hist, T* __restrict__ out)
+// four consecutive values; p is 16-byte aligned
+template <typename T>
+struct Quad {
+  T v[4];
+};
+__device__ __forceinline__ Quad<float> load_quad(const float* p)
 {
-  extern __shared__ unsigned char lds_raw[];
-  T* L = reinterpret_cast<T*>(lds_raw);
-  const int64_t bi = blockIdx.x;
-  Block3 bk;
-  Box bx;
-  block_geometry(a.g, bi, a.nb, bk, bx);
-  const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
-  // stream position of the brick's first point (all earlier bricks are full
-  // along the dims before the last partial one)
-  const uint64_t brick_base = (uint64_t)(bk.o0 * a.g.n[1] * a.g.n[2] + bk.Eb0 * bk.o1 * a.g.n[2] +
-                                         bk.Eb0 * bk.Eb1 * bk.o2);
-  const uint32_t nbrick = (uint32_t)bk.Eb0 * bk.Eb1 * bk.Eb2;
-  const uint32_t nbox = (uint32_t)bx.E0 * bx.b0;
-  const uint32_t mgb0 = fmagic((uint32_t)bx.b0), mgE2 = fmagic((uint32_t)bx.E2);
-  const int a0 = bx.a0, a1 = bx.a1, a2 = bx.a2;
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  return {{q.x, q.y, q.z, q.w}};
+}
+__device__ __forceinline__ Quad<double> load_quad(const double* p)
+{
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  return {{a.x, a.y, b.x, b.y}};
+}
 
-  // load: faces from the face arrays, interiors from X (compress)
-  const T* __restrict__ F0 = reinterpret_cast<const T*>(f.val[0]);
-  const T* __restrict__ F1 = reinterpret_cast<const T*>(f.val[1]);
-  const T* __restrict__ F2 = reinterpret_cast<const T*>(f.val[2]);
-  // eight loads in flight per lane before their LDS stores
-  constexpr int kU = 8;
-  for (uint32_t i0 = threadIdx.x; i0 < nbox; i0 += kU * blockDim.x) {
-    T v[kU];
+// per-point work of the compress schedule: quantize, emit the code, write the
+// reconstruction back, count the code
+template <typename T>
+struct CompressOp {
+  using Fetched = int;
+  T* L;
+  uint16_t* code;
+  uint32_t* lh;
+  uint32_t* hist;
+  uint64_t brick_base;
+  int32_t Eb1, Eb2;
+  uint32_t R, lo;
+  double el, inv2e, twoe;
+  uint32_t nR;  // codes equal to R (zero residual), counted per lane
+  __device__ __forceinline__ int fetch(int32_t, int32_t, int32_t, bool) const { return 0; }
+  __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, int)
+  {
+    const T xv = L[li];
+    T xr = xv;
+    const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
+    code[brick_base + (uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] = (uint16_t)q;
+    L[li] = xr;
+    // the most frequent code is counted in a register, the others in LDS
+    nR += q == R;
+    if (q != R) {
+      // distinct scopes keep the LDS and the global update apart (no generic pointer)
+      const uint32_t w = q - lo;
+      if (w < (uint32_t)kBlockHistWin)
+        __hip_atomic_fetch_add(&lh[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        __hip_atomic_fetch_add(&hist[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+};
+
+// per-point work of the decompress schedule: the code is fetched first, then
+// x' = p + q 2e_l, or the stored value for code 0
+template <typename T>
+struct DecompressOp {
+  using Fetched = uint32_t;
+  T* L;
+  const uint16_t* code;
+  const T* out;
+  uint64_t brick_base;
+  int64_t o0, o1, o2, st0, st1;
+  int32_t Eb1, Eb2;
+  uint32_t R;
+  double twoe;
+  __device__ __forceinline__ uint32_t fetch(int32_t x0, int32_t x1, int32_t x2, bool ok) const
+  {
+    return ok ? (uint32_t)code[brick_base + (uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] : 0u;
+  }
+  __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
+  {
+    L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
+              : out[(o0 + x0) * st0 + (o1 + x1) * st1 + (o2 + x2)];
+  }
+};
+
+// Box loading: rows along dim 2 in quads of four cells.  Face rows (c0 or c1
+// on a block face) come from the face arrays, cells c2 = 0 / 32 from the dim-2
+// faces, everything else from X (compress only).  Item `it` of a block is row
+// it / nq, quad it % nq.
+struct BoxItems {
+  int32_t E1, E2, nq;
+  uint32_t rowq, nitems;
+  Divisor mgr, mgq;
+};
+
+__device__ __forceinline__ BoxItems box_items(const Box& bx)
+{
+  BoxItems b;
+  b.E1 = bx.E1;
+  b.E2 = bx.E2;
+  b.nq = (bx.E2 + 3) >> 2;
+  b.rowq = (uint32_t)(bx.E1 * b.nq);
+  b.nitems = (uint32_t)bx.E0 * b.rowq;
+  b.mgr = fmagic(b.rowq);
+  b.mgq = fmagic((uint32_t)b.nq);
+  return b;
+}
+
+// the values of one item (cnt <= 4 cells; wr marks cells that are loaded)
+template <typename T, int MODE>
+__device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const T* __restrict__ X, int64_t st0,
+                                             int64_t st1, const Block3& bk, const Box& bx,
+                                             const BoxItems& bi, uint32_t it, bool vec,
+                                             int32_t& lbase, uint32_t& wr)
+{
+  Quad<T> v;
 #pragma unroll
-    for (int u = 0; u < kU; u++) {
-      const uint32_t i = i0 + u * blockDim.x;
-      v[u] = (T)0;
-      if (i >= nbox) continue;
-      const int32_t c0 = (int32_t)fdiv(i, mgb0);
-      const uint32_t rem = i - (uint32_t)c0 * bx.b0;
-      const int32_t c1 = (int32_t)fdiv(rem, mgE2);
-      const int32_t c2 = (int32_t)(rem - (uint32_t)c1 * bx.E2);
-      const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + c2;
-      if (a0 && (c0 == 0 || c0 == kBrick)) {
-        v[u] = F0[(x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2 * f.fs[0][2]];
-      } else if (a1 && (c1 == 0 || c1 == kBrick)) {
-        v[u] = F1[(x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2 * f.fs[1][2]];
-      } else if (a2 && (c2 == 0 || c2 == kBrick)) {
-        v[u] = F2[(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] + x1 * f.fs[2][1]];
-      } else if (MODE == 0) {
-        v[u] = X[x0 * st0 + x1 * st1 + x2];
+  for (int j = 0; j < 4; j++) v.v[j] = (T)0;
+  wr = 0;
+  lbase = 0;
+  if (it >= bi.nitems) return v;
+  const int32_t c0 = (int32_t)fdiv(it, bi.mgr);
+  const uint32_t rr = it - (uint32_t)c0 * bi.rowq;
+  const int32_t c1 = (int32_t)fdiv(rr, bi.mgq);
+  const int32_t cb = 4 * (int32_t)(rr - (uint32_t)c1 * bi.nq);
+  const int32_t cnt = bi.E2 - cb < 4 ? bi.E2 - cb : 4;
+  const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + cb;
+  lbase = (c0 * bi.E1 + c1) * bi.E2 + cb;
+  const bool face0 = bx.a0 && (c0 == 0 || c0 == kBrick);
+  const bool face1 = !face0 && bx.a1 && (c1 == 0 || c1 == kBrick);
+  const T* src = nullptr;
+  if (face0)
+    src = reinterpret_cast<const T*>(f.val[0]) + (x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2;
+  else if (face1)
+    src = reinterpret_cast<const T*>(f.val[1]) + (x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2;
+  else if (MODE == 0)
+    src = X + x0 * st0 + x1 * st1 + x2;
+  if (src) {
+    wr = (1u << cnt) - 1u;
+    if (vec && cnt == 4) {
+      v = load_quad(src);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (j < cnt) v.v[j] = src[j];
+    }
+  }
+  if (!face0 && !face1 && bx.a2 && (cb == 0 || cb == kBrick)) {
+    // the row's cell on a dim-2 face
+    v.v[0] = reinterpret_cast<const T*>(f.val[2])[(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] +
+                                                  x1 * f.fs[2][1]];
+    wr |= 1u;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_item(T* L, const Quad<T>& v, int32_t lbase, uint32_t wr)
+{
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+    if (wr >> j & 1u) L[lbase + j] = v.v[j];
+}
+
+// Persistent work-groups (one per CU): blocks are taken from a counter; for
+// float boxes the next block's loads are issued before the current block's
+// levels, so they complete while it computes.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlockThreads) block_kernel(BlockArgs a, FaceGeo f,
+                                                              const T* __restrict__ X,
+                                                              uint16_t* __restrict__ code,
+                                                              const uint8_t* __restrict__ bcfg,
+                                                              uint32_t* __restrict__ hist,
+                                                              T* __restrict__ out,
+                                                              uint32_t* __restrict__ ticket)
+{
+  constexpr int NT = kBlockThreads;
+  constexpr bool PREF = sizeof(T) == 4;
+  constexpr int UP = PREF ? (33 * 33 * 9 + NT - 1) / NT : 1;  // items per lane held across a block
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ uint32_t s_next;
+  T* L = reinterpret_cast<T*>(lds_raw);
+  const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
+  const uint64_t nbt = (uint64_t)(a.nb[0] * a.nb[1] * a.nb[2]);
+  const uint32_t lo = a.hist_lo;
+  // rows are 16-byte aligned in X, out and the face arrays (host-checked)
+  const bool vec = a.vec != 0;
+
+  if (threadIdx.x == 0) s_next = atomicAdd(ticket, 1u);
+  __syncthreads();
+  uint64_t bi = s_next;
+  Quad<T> pv[UP];
+  int32_t plb[UP];
+  uint32_t pwr[UP];
+  if (PREF && bi < nbt) {
+    Block3 bk;
+    Box bx;
+    block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
+    const BoxItems its = box_items(bx);
+#pragma unroll
+    for (int u = 0; u < UP; u++)
+      pv[u] = load_item<T, MODE>(f, X, st0, st1, bk, bx, its, threadIdx.x + u * NT, vec, plb[u], pwr[u]);
+  }
+
+  while (bi < nbt) {
+    __syncthreads();  // every lane has read s_next; the previous block is done with LDS
+    if (threadIdx.x == 0) s_next = atomicAdd(ticket, 1u);
+    Block3 bk;
+    Box bx;
+    block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
+    // stream position of the brick's first point (all earlier bricks are full
+    // along the dims before the last partial one)
+    const uint64_t brick_base = (uint64_t)(bk.o0 * a.g.n[1] * a.g.n[2] +
+                                           bk.Eb0 * bk.o1 * a.g.n[2] + bk.Eb0 * bk.Eb1 * bk.o2);
+    const uint32_t nbox = (uint32_t)bx.E0 * bx.b0;
+    uint32_t* lh = reinterpret_cast<uint32_t*>(lds_raw + ((nbox * sizeof(T) + 15) & ~(size_t)15));
+    const int32_t E1 = bx.E1, E2 = bx.E2, Eb1 = bk.Eb1, Eb2 = bk.Eb2;
+    if (MODE == 0)
+      for (uint32_t i = threadIdx.x; i < (uint32_t)kBlockHistWin; i += NT) lh[i] = 0;
+    // ---- the box into LDS
+    if (PREF) {
+#pragma unroll
+      for (int u = 0; u < UP; u++) store_item<T>(L, pv[u], plb[u], pwr[u]);
+    } else {
+      const BoxItems its = box_items(bx);
+      constexpr int UL = 4;
+      for (uint32_t ib = threadIdx.x; ib < its.nitems; ib += UL * NT) {
+        Quad<T> v[UL];
+        int32_t lb[UL];
+        uint32_t wr[UL];
+#pragma unroll
+        for (int u = 0; u < UL; u++)
+          v[u] = load_item<T, MODE>(f, X, st0, st1, bk, bx, its, ib + u * NT, vec, lb[u], wr[u]);
+#pragma unroll
+        for (int u = 0; u < UL; u++) store_item<T>(L, v[u], lb[u], wr[u]);
       }
     }
-#pragma unroll
-    for (int u = 0; u < kU; u++) {
-      const uint32_t i = i0 + u * blockDim.x;
-      if (i < nbox) L[i] = v[u];
-    }
-  }
-  __syncthreads();
-
-  const hpez_interp c = a.cand[bcfg[bi]];
-  const uint32_t R = a.R;
-  const int32_t Eb1 = bk.Eb1, Eb2 = bk.Eb2;
-  for (int l = a.L; l >= 1; l--) {
-    const int32_t s = 1 << (l - 1);
-    const double el = a.el_l[l], inv2e = a.inv2e_l[l], twoe = a.twoe_l[l];
+    // compress: the codes of the brick's own faces (c_d = 0 on an active dim)
+    // from the face code arrays; loaded now, stored and counted after the
+    // levels, so the loads complete while the block computes
+    constexpr int FC = MODE == 0 ? 3 : 1;  // face codes per lane (3 x 32 x 32 <= 3 NT)
+    uint32_t fcv[FC], fcd[FC];
+    bool fok[FC];
     if (MODE == 0) {
-      auto op = [&](int32_t li, int32_t x0, int32_t x1, int32_t x2, T p) {
-        const T xv = L[li];
-        T xr = xv;
-        const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
-        code[brick_base + (uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] = (uint16_t)q;
-        L[li] = q ? xr : xv;
-      };
-      box_level<T>(c, bx, L, bk.o0, bk.o1, bk.o2, s, wq, op);
+      const int32_t Eb0 = bk.Eb0;
+      const int32_t r0 = bx.a0, r1 = bx.a1;
+      const int32_t f0n = bx.a0 ? Eb1 * Eb2 : 0;
+      const int32_t f1n = bx.a1 ? (Eb0 - r0) * Eb2 : 0;
+      const int32_t f2n = bx.a2 ? (Eb0 - r0) * (Eb1 - r1) : 0;
+      const Divisor dE2 = fmagic((uint32_t)Eb2);
+      const Divisor dE1 = fmagic((uint32_t)(Eb1 - r1 > 0 ? Eb1 - r1 : 1));
+#pragma unroll
+      for (int u = 0; u < FC; u++) {
+        const int32_t j = (int32_t)threadIdx.x + u * NT;
+        fok[u] = j < f0n + f1n + f2n;
+        fcv[u] = 0;
+        fcd[u] = 0;
+        if (!fok[u]) continue;
+        if (j < f0n) {
+          const int32_t c1 = (int32_t)fdiv((uint32_t)j, dE2), c2 = j - c1 * Eb2;
+          fcd[u] = (uint32_t)(c1 * Eb2 + c2);
+          fcv[u] = f.code[0][(bk.o0 >> f.blog2) * f.plane[0] + (bk.o1 + c1) * f.fs[0][1] +
+                             (bk.o2 + c2) * f.fs[0][2]];
+        } else if (j < f0n + f1n) {
+          const int32_t jj = j - f0n;
+          const int32_t q = (int32_t)fdiv((uint32_t)jj, dE2);
+          const int32_t c0 = r0 + q, c2 = jj - q * Eb2;
+          fcd[u] = (uint32_t)(c0 * Eb1 * Eb2 + c2);
+          fcv[u] = f.code[1][(bk.o1 >> f.blog2) * f.plane[1] + (bk.o0 + c0) * f.fs[1][0] +
+                             (bk.o2 + c2) * f.fs[1][2]];
+        } else {
+          const int32_t jj = j - f0n - f1n;
+          const int32_t q = (int32_t)fdiv((uint32_t)jj, dE1);
+          const int32_t c0 = r0 + q, c1 = r1 + (jj - q * (Eb1 - r1));
+          fcd[u] = (uint32_t)((c0 * Eb1 + c1) * Eb2);
+          fcv[u] = f.code[2][(bk.o2 >> f.blog2) * f.plane[2] + (bk.o0 + c0) * f.fs[2][0] +
+                             (bk.o1 + c1) * f.fs[2][1]];
+        }
+      }
+    }
+    __syncthreads();
+    const uint64_t bn = s_next;
+    if (PREF && bn < nbt) {
+      // the next block's loads, in flight during this block's levels
+      Block3 bk2;
+      Box bx2;
+      block_geometry(a.g, (int64_t)bn, a.nb, bk2, bx2);
+      const BoxItems its2 = box_items(bx2);
+#pragma unroll
+      for (int u = 0; u < UP; u++)
+        pv[u] = load_item<T, MODE>(f, X, st0, st1, bk2, bx2, its2, threadIdx.x + u * NT, vec, plb[u],
+                                   pwr[u]);
+    }
+
+    // ---- the levels below B with the block's configuration
+    const hpez_interp c = a.cand[bcfg[bi]];
+    uint32_t nR = 0;
+    for (int l = a.L; l >= 1; l--) {
+      const int32_t s = 1 << (l - 1);
+      if (MODE == 0) {
+        CompressOp<T> op{L,  code, lh, hist, brick_base, Eb1, Eb2, a.R, lo, a.el_l[l], a.inv2e_l[l],
+                         a.twoe_l[l], 0u};
+        box_level<T, NT>(c, bx, L, bk.o0, bk.o1, bk.o2, s, a.wmd, op);
+        nR += op.nR;
+      } else {
+        DecompressOp<T> op{L, code, out, brick_base, bk.o0, bk.o1, bk.o2, st0, st1, Eb1, Eb2, a.R,
+                           a.twoe_l[l]};
+        box_level<T, NT>(c, bx, L, bk.o0, bk.o1, bk.o2, s, a.wmd, op);
+      }
+    }
+
+    if (MODE == 1) {
+      // the whole brick (interiors from the schedule, faces as loaded)
+      const uint32_t nq2 = (uint32_t)((Eb2 + 3) >> 2);
+      const uint32_t nitem = (uint32_t)(bk.Eb0 * Eb1) * nq2;
+      const Divisor mg = fmagic(nq2);
+      const Divisor mg1 = fmagic((uint32_t)Eb1);
+      for (uint32_t it = threadIdx.x; it < nitem; it += NT) {
+        const uint32_t r = fdiv(it, mg);
+        const uint32_t q = it - r * nq2;
+        const uint32_t c0 = fdiv(r, mg1);
+        const uint32_t c1 = r - c0 * (uint32_t)Eb1;
+        const int32_t cb = 4 * (int32_t)q;
+        const int32_t cnt = Eb2 - cb < 4 ? Eb2 - cb : 4;
+        T* dst = out + (bk.o0 + c0) * st0 + (bk.o1 + c1) * st1 + (bk.o2 + cb);
+        const int32_t lb = (int32_t)(c0 * E1 + c1) * E2 + cb;
+        if (vec && cnt == 4) {
+          if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(dst) =
+                make_float4((float)L[lb], (float)L[lb + 1], (float)L[lb + 2], (float)L[lb + 3]);
+          } else {
+            reinterpret_cast<double2*>(dst)[0] = make_double2((double)L[lb], (double)L[lb + 1]);
+            reinterpret_cast<double2*>(dst)[1] = make_double2((double)L[lb + 2], (double)L[lb + 3]);
+          }
+        } else {
+          for (int j = 0; j < cnt; j++) dst[j] = L[lb + j];
+        }
+      }
     } else {
-      auto op = [&](int32_t li, int32_t x0, int32_t x1, int32_t x2, T p) {
-        const uint32_t q = code[brick_base + (uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)];
-        L[li] = q ? (T)((double)p + (double)((int64_t)q - (int64_t)R) * twoe)
-                  : out[(bk.o0 + x0) * st0 + (bk.o1 + x1) * st1 + (bk.o2 + x2)];
-      };
-      box_level<T>(c, bx, L, bk.o0, bk.o1, bk.o2, s, wq, op);
+      // the face codes into the brick, counted with the others
+#pragma unroll
+      for (int u = 0; u < FC; u++) {
+        if (!fok[u]) continue;
+        code[brick_base + fcd[u]] = (uint16_t)fcv[u];
+        const uint32_t q = fcv[u];
+        nR += q == a.R;
+        if (q != a.R) {
+          const uint32_t w = q - lo;
+          if (w < (uint32_t)kBlockHistWin)
+            __hip_atomic_fetch_add(&lh[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          else
+            __hip_atomic_fetch_add(&hist[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      // codes equal to R: a wave sum, then one LDS atomic per wave
+      for (int o = 32; o > 0; o >>= 1) nR += __shfl_xor(nR, o, 64);
+      if ((threadIdx.x & 63) == 0 && nR) {
+        const uint32_t w = a.R - lo;
+        if (w < (uint32_t)kBlockHistWin) atomicAdd(&lh[w], nR);
+        else atomicAdd(&hist[a.R], nR);
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < kBlockHistWin; i += NT)
+        if (lh[i]) atomicAdd(&hist[lo + i], lh[i]);
     }
+    bi = bn;
   }
-
-  const uint32_t mgEb12 = fmagic((uint32_t)(bk.Eb1 * bk.Eb2)), mgEb2 = fmagic((uint32_t)bk.Eb2);
-  const uint32_t Eb12 = (uint32_t)(bk.Eb1 * bk.Eb2);
-  if (MODE == 1) {
-    // the whole brick (interiors from the schedule, near faces as loaded)
-    for (uint32_t i = threadIdx.x; i < nbrick; i += blockDim.x) {
-      const uint32_t c0 = fdiv(i, mgEb12);
-      const uint32_t rem = i - c0 * Eb12;
-      const uint32_t c1 = fdiv(rem, mgEb2);
-      const uint32_t c2 = rem - c1 * (uint32_t)bk.Eb2;
-      out[(bk.o0 + c0) * st0 + (bk.o1 + c1) * st1 + (bk.o2 + c2)] =
-          L[c0 * bx.b0 + c1 * bx.b1 + c2];
-    }
-    return;
-  }
-
-  // near-face codes of the brick, from the face arrays
-  for (uint32_t i = threadIdx.x; i < nbrick; i += blockDim.x) {
-    const uint32_t c0 = fdiv(i, mgEb12);
-    const uint32_t rem = i - c0 * Eb12;
-    const uint32_t c1 = fdiv(rem, mgEb2);
-    const uint32_t c2 = rem - c1 * (uint32_t)bk.Eb2;
-    const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + c2;
-    if (a0 && c0 == 0)
-      code[brick_base + i] = f.code[0][(x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2 * f.fs[0][2]];
-    else if (a1 && c1 == 0)
-      code[brick_base + i] = f.code[1][(x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2 * f.fs[1][2]];
-    else if (a2 && c2 == 0)
-      code[brick_base + i] = f.code[2][(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] + x1 * f.fs[2][1]];
-  }
-  __syncthreads();
-
-  // histogram of the brick's codes: a window around R in LDS (reusing the box)
-  uint32_t* h = reinterpret_cast<uint32_t*>(lds_raw);
-  for (int i = threadIdx.x; i < kBlockHistWin; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  const uint32_t lo = a.hist_lo;
-  // every lane of the work-group runs the same trip count (wave-level aggregation)
-  for (uint32_t i0 = 0; i0 < nbrick; i0 += blockDim.x) {
-    const uint32_t i = i0 + threadIdx.x;
-    const bool ok = i < nbrick;
-    const uint32_t q = ok ? code[brick_base + i] : 0u;
-    hist_add_wave(h, hist, lo, (uint32_t)kBlockHistWin, q, ok);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kBlockHistWin; i += blockDim.x)
-    if (h[i]) atomicAdd(&hist[lo + i], h[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,30 +588,30 @@ size_t block_lds_bytes(const Geom& g)
     const int64_t e = g.act[d] ? kBrick + 1 : kBrick;
     pts *= (size_t)(g.n[d] < e ? g.n[d] : e);
   }
-  size_t b = pts * sizeof(T);
-  const size_t hb = (size_t)kBlockHistWin * 4;
-  return b > hb ? b : hb;
+  return ((pts * sizeof(T) + 15) & ~(size_t)15) + (size_t)kBlockHistWin * 4;
 }
 
 template <typename T>
 hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint16_t* code,
-                         const uint8_t* d_bcfg, const double* d_wq, uint32_t* hist, T* out,
+                         const uint8_t* d_bcfg, uint32_t* hist, T* out, uint32_t* ticket, int n_cu,
                          int mode, hipStream_t st)
 {
   uint64_t nbt = 1;
   for (int d = 0; d < 4; d++) nbt *= (uint64_t)a.nb[d];
   if (!nbt) return hipSuccess;
   const size_t lds = block_lds_bytes<T>(a.g);
+  // one work-group per CU (the box takes the CU's LDS); blocks come from the ticket
+  const unsigned grid = (unsigned)(nbt < (uint64_t)n_cu ? nbt : (uint64_t)n_cu);
   if (mode == 0) {
     (void)hipFuncSetAttribute((const void*)block_kernel<T, 0>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((block_kernel<T, 0>), dim3((unsigned)nbt), dim3(1024), lds, st, a, f, X, code,
-                       d_bcfg, d_wq, hist, out);
+    hipLaunchKernelGGL((block_kernel<T, 0>), dim3(grid), dim3(kBlockThreads), lds, st, a, f, X, code,
+                       d_bcfg, hist, out, ticket);
   } else {
     (void)hipFuncSetAttribute((const void*)block_kernel<T, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((block_kernel<T, 1>), dim3((unsigned)nbt), dim3(1024), lds, st, a, f, X, code,
-                       d_bcfg, d_wq, hist, out);
+    hipLaunchKernelGGL((block_kernel<T, 1>), dim3(grid), dim3(kBlockThreads), lds, st, a, f, X, code,
+                       d_bcfg, hist, out, ticket);
   }
   return hipGetLastError();
 }
@@ -383,7 +623,7 @@ hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint1
                                           const T*, int, hipStream_t);                           \
   template size_t block_lds_bytes<T>(const Geom&);                                               \
   template hipError_t launch_blocks<T>(const BlockArgs&, const FaceGeo&, const T*, uint16_t*,     \
-                                       const uint8_t*, const double*, uint32_t*, T*, int,        \
+                                       const uint8_t*, uint32_t*, T*, uint32_t*, int, int,        \
                                        hipStream_t);
 INST(float)
 INST(double)

@@ -67,6 +67,34 @@ __device__ __forceinline__ uint64_t look_back(uint64_t* flags, uint64_t k, int l
 
 // bit count of one chunk (lane sums of `per` symbols, wave total); ent[]
 // receives the packed entries of the lane's symbols
+// the 16 codes of one lane of a full 1024-symbol chunk (32-byte aligned)
+struct Raw16 {
+  uint4 a, b;
+};
+__device__ __forceinline__ Raw16 raw_load(const uint16_t* __restrict__ code, uint64_t k, int lane)
+{
+  const uint4* p = reinterpret_cast<const uint4*>(code + k * 1024 + (uint64_t)lane * 16);
+  return {p[0], p[1]};
+}
+__device__ __forceinline__ uint32_t raw_entries(const EncodeArgs& a, const uint32_t* tab,
+                                                const uint32_t* __restrict__ gtab, const Raw16& r,
+                                                uint32_t* ent, uint32_t& lane_bits)
+{
+  const uint32_t w[8] = {r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.b.y, r.b.z, r.b.w};
+  uint32_t bits = 0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const uint32_t c = ((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) - a.smin;
+    const uint32_t e = a.lds_tab ? tab[c] : gtab[c];
+    ent[j] = e;
+    bits += e & 63u;
+  }
+  lane_bits = bits;
+  uint32_t t = bits;
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
 __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uint16_t* __restrict__ code,
                                                   const uint32_t* tab, const uint32_t* __restrict__ gtab,
                                                   uint64_t k, int lane, uint32_t* ent, uint32_t& lane_bits)
@@ -75,15 +103,29 @@ __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uin
   const uint64_t beg = k * a.chunk + (uint64_t)lane * per;
   const uint64_t cend = k * a.chunk + a.chunk < a.n ? k * a.chunk + a.chunk : a.n;
   uint32_t bits = 0;
-  for (uint32_t j = 0; j < per; j++) {
-    const uint64_t i = beg + j;
-    uint32_t e = 0;
-    if (i < cend) {
-      const uint32_t c = code[i] - a.smin;
-      e = a.lds_tab ? tab[c] : gtab[c];
+  if (per == 16 && k * a.chunk + a.chunk <= a.n) {
+    // the lane's 16 codes in two 16-byte loads (32-byte aligned run)
+    const uint4* p = reinterpret_cast<const uint4*>(code + beg);
+    const uint4 v0 = p[0], v1 = p[1];
+    const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const uint32_t c = ((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) - a.smin;
+      const uint32_t e = a.lds_tab ? tab[c] : gtab[c];
+      ent[j] = e;
+      bits += e & 63u;
     }
-    ent[j] = e;
-    bits += e & 63u;
+  } else {
+    for (uint32_t j = 0; j < per; j++) {
+      const uint64_t i = beg + j;
+      uint32_t e = 0;
+      if (i < cend) {
+        const uint32_t c = code[i] - a.smin;
+        e = a.lds_tab ? tab[c] : gtab[c];
+      }
+      ent[j] = e;
+      bits += e & 63u;
+    }
   }
   lane_bits = bits;
   uint32_t t = bits;
@@ -125,13 +167,32 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     const uint64_t k0 = part * kPart;
     const uint32_t np = (uint32_t)(a.nch - k0 < (uint64_t)kPart ? a.nch - k0 : (uint64_t)kPart);
     uint32_t ent[16];
+    // full 1024-symbol chunks: the next chunk's codes are loaded while the
+    // current one is processed
+    const bool fast = a.chunk == 1024 && (k0 + np) * 1024 <= a.n;
     // 1. chunk bit counts
-    for (uint32_t j = w; j < np; j += kEncWaves) {
-      uint32_t lb;
-      const uint32_t t = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
-      if (lane == 0) {
-        cbits[j] = t;
-        out_cb[k0 + j] = (uint16_t)t;
+    if (fast) {
+      Raw16 cur{};
+      if ((uint32_t)w < np) cur = raw_load(code, k0 + w, lane);
+      for (uint32_t j = w; j < np; j += kEncWaves) {
+        Raw16 nxt{};
+        if (j + kEncWaves < np) nxt = raw_load(code, k0 + j + kEncWaves, lane);
+        uint32_t lb;
+        const uint32_t t = raw_entries(a, tab, gtab, cur, ent, lb);
+        if (lane == 0) {
+          cbits[j] = t;
+          out_cb[k0 + j] = (uint16_t)t;
+        }
+        cur = nxt;
+      }
+    } else {
+      for (uint32_t j = w; j < np; j += kEncWaves) {
+        uint32_t lb;
+        const uint32_t t = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+        if (lane == 0) {
+          cbits[j] = t;
+          out_cb[k0 + j] = (uint16_t)t;
+        }
       }
     }
     __syncthreads();
@@ -158,9 +219,18 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     __syncthreads();
     // 3. pack each chunk
     const uint64_t pexcl = s_excl;
+    Raw16 cur{};
+    if (fast && (uint32_t)w < np) cur = raw_load(code, k0 + w, lane);
     for (uint32_t j = w; j < np; j += kEncWaves) {
-      uint32_t lb;
-      const uint32_t total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+      uint32_t lb, total;
+      if (fast) {
+        Raw16 nxt{};
+        if (j + kEncWaves < np) nxt = raw_load(code, k0 + j + kEncWaves, lane);
+        total = raw_entries(a, tab, gtab, cur, ent, lb);
+        cur = nxt;
+      } else {
+        total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+      }
       uint32_t incl = lb;
       for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(incl, o, 64);
@@ -282,27 +352,47 @@ hipError_t launch_encode1(const EncodeArgs& a, const uint16_t* code, uint32_t* w
 }
 
 // ---------------------------------------------------------------------------
-// verbatim values (code 0) in stream order: chunks with zeros walk their codes
-template <typename T>
-__global__ void __launch_bounds__(256) gather_unpred_kernel(const uint16_t* __restrict__ code, uint64_t n,
-                                                            uint32_t chunk, const uint32_t* __restrict__ czero,
-                                                            const uint64_t* __restrict__ zoff,
-                                                            const T* __restrict__ X, T* __restrict__ unpred,
-                                                            Geom g, uint64_t nch)
+// Verbatim values (code 0) in stream order.  One wavefront per chunk; chunks
+// without zeros return at once.  The lanes read 64 consecutive codes per round
+// and rank the zeros among them with a ballot, so the values move in order.
+// GATHER: X -> unpred (compress); otherwise unpred -> W (decompress, with the
+// rank checked against the stored count).
+template <typename T, bool GATHER>
+__global__ void __launch_bounds__(256) unpred_move_kernel(const uint16_t* __restrict__ code, uint64_t n,
+                                                          uint32_t chunk, const uint32_t* __restrict__ czero,
+                                                          const uint64_t* __restrict__ zoff,
+                                                          const T* __restrict__ src, T* __restrict__ dst,
+                                                          uint64_t n_unpred, int* __restrict__ status,
+                                                          Geom g, uint64_t nch)
 {
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t k = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= nch || czero[k] == 0) return;
+  const int lane = threadIdx.x & 63;
   const uint64_t beg = k * chunk;
   const uint64_t end = beg + chunk < n ? beg + chunk : n;
   uint64_t z = zoff[k];
-  for (uint64_t i = beg; i < end; i++) {
-    if (code[i] != 0) continue;
-    int64_t x[4];
-    brick_coords(g.n, (int64_t)i, x);
-    unpred[z++] = X[x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]];
+  for (uint64_t i0 = beg; i0 < end; i0 += 64) {
+    const uint64_t i = i0 + lane;
+    const bool zero = i < end && code[i] == 0;
+    const uint64_t m = __ballot(zero);
+    if (zero) {
+      const uint64_t r = z + (uint64_t)__popcll(m & ((1ull << lane) - 1));
+      int64_t x[4];
+      brick_coords(g.n, (int64_t)i, x);
+      const int64_t idx = x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3];
+      if (GATHER) {
+        dst[r] = src[idx];
+      } else if (r < n_unpred) {
+        dst[idx] = src[r];
+      } else {
+        atomicOr(status, 1);
+      }
+    }
+    z += (uint64_t)__popcll(m);
   }
 }
 
+// zeros per chunk: 16-byte loads of eight codes when the chunk allows
 __global__ void __launch_bounds__(256) count_zero_kernel(const uint16_t* __restrict__ code, uint64_t n,
                                                          uint32_t chunk, uint32_t* __restrict__ czero,
                                                          uint64_t nch)
@@ -313,7 +403,17 @@ __global__ void __launch_bounds__(256) count_zero_kernel(const uint16_t* __restr
   const uint64_t beg = k * chunk;
   const uint64_t end = beg + chunk < n ? beg + chunk : n;
   uint32_t z = 0;
-  for (uint64_t i = beg + lane; i < end; i += 64) z += code[i] == 0;
+  if (end - beg == chunk && chunk >= 512) {
+    // 8 codes per lane per round
+    for (uint64_t i = beg + (uint64_t)lane * 8; i < end; i += 512) {
+      const uint4 v = *reinterpret_cast<const uint4*>(code + i);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; j++) z += ((w[j] & 0xFFFFu) == 0) + ((w[j] >> 16) == 0);
+    }
+  } else {
+    for (uint64_t i = beg + lane; i < end; i += 64) z += code[i] == 0;
+  }
   for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
   if (lane == 0) czero[k] = z;
 }
@@ -337,16 +437,33 @@ hipError_t launch_gather_unpred(const uint16_t* code, uint64_t n, uint32_t chunk
   if (!nch) return hipSuccess;
   hipError_t e = launch_count_zeros(code, n, chunk, czero, zoff, tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((gather_unpred_kernel<T>), dim3((unsigned)((nch + 255) / 256)), dim3(256), 0, st,
-                     code, n, chunk, czero, zoff, X, unpred, g, nch);
+  hipLaunchKernelGGL((unpred_move_kernel<T, true>), dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st,
+                     code, n, chunk, czero, zoff, X, unpred, (uint64_t)0, (int*)nullptr, g, nch);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chunk,
+                                  const uint32_t* czero, const uint64_t* zoff, const T* unpred,
+                                  uint64_t n_unpred, T* W, int* d_status, const Geom& g,
+                                  hipStream_t st)
+{
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  if (!nch) return hipSuccess;
+  hipLaunchKernelGGL((unpred_move_kernel<T, false>), dim3((unsigned)((nch + 3) / 4)), dim3(256), 0,
+                     st, code, n, chunk, czero, zoff, unpred, W, n_unpred, d_status, g, nch);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // decode
 
-// symbol of the codeword at the top of the window; L = its length (0: invalid)
+// symbol of the codeword at the top of the window; L = its length (0: invalid).
+// Codes longer than the table are located by the canonical limits and read
+// from the LDS copy of their symbols (or the global one when too many).
+template <bool LONG_LDS>
 __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32_t* lut,
+                                               const uint16_t* slong,
                                                const uint16_t* __restrict__ sorted, uint32_t w,
                                                uint32_t& L)
 {
@@ -362,9 +479,11 @@ __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32
     return 0;
   }
   L = c;
-  return sorted[a.base[c] + (w >> (32 - c))];
+  const uint32_t idx = a.base[c] + (w >> (32 - c));
+  return LONG_LDS ? slong[idx - a.long_first] : sorted[idx];
 }
 
+template <bool LONG_LDS>
 __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32_t* __restrict__ words,
                                                       const uint64_t* __restrict__ bit_off,
                                                       const uint32_t* __restrict__ glut,
@@ -374,7 +493,10 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
                                                       int* __restrict__ status)
 {
   __shared__ uint32_t lut[1 << kLutBits];
+  __shared__ uint16_t slong[LONG_LDS ? kDecLong : 1];
   for (int i = threadIdx.x; i < (1 << kLutBits); i += blockDim.x) lut[i] = glut[i];
+  if (LONG_LDS)
+    for (uint32_t i = threadIdx.x; i < a.n_long; i += blockDim.x) slong[i] = sorted[a.long_first + i];
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0 && bit_off[a.nch] != a.nbits) atomicOr(status, 1);
@@ -388,17 +510,28 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     return;
   }
   const uint64_t nwords = (a.nbits + 31) / 32;
-  // 64-bit bit buffer, next bit at the top; `have` valid bits
+  if (nwords == 0) {
+    if (end > beg) atomicOr(status, 1);
+    czero[k] = 0;
+    return;
+  }
+  // 64-bit bit buffer, next bit at the top; `have` valid bits.  The word after
+  // the buffer is loaded one refill ahead, so its latency overlaps decoding:
+  // the load is unconditional (index clamped to the last word; bits past the
+  // payload are never part of a valid codeword) so nothing waits for it early.
+  const uint64_t wlast = nwords - 1;
   uint64_t wi = pos >> 5;
   uint64_t buf;
   int have;
   {
     const uint32_t skip = (uint32_t)(pos & 31);
-    const uint64_t w = wi < nwords ? words[wi] : 0;
+    const uint64_t w = words[wi < wlast ? wi : wlast];
     buf = (w << 32) << skip;
     have = 32 - (int)skip;
     wi++;
   }
+  uint32_t pre = words[wi < wlast ? wi : wlast];
+  wi++;
   uint32_t zeros = 0;
   bool bad = false;
   // chunks start at multiples of 64 symbols: eight codes per 16-byte store
@@ -409,13 +542,13 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     for (uint32_t t = 0; t < 8; t++) {
       if (t >= cnt || bad) break;
       if (have < 32) {
-        const uint64_t w = wi < nwords ? words[wi] : 0;
-        buf |= (w << 32) >> have;
+        buf |= ((uint64_t)pre << 32) >> have;
         have += 32;
+        pre = words[wi < wlast ? wi : wlast];
         wi++;
       }
       uint32_t L;
-      const uint32_t sym = decode_one(a, lut, sorted, (uint32_t)(buf >> 32), L);
+      const uint32_t sym = decode_one<LONG_LDS>(a, lut, slong, sorted, (uint32_t)(buf >> 32), L);
       if (!L) {
         bad = true;
         break;
@@ -448,11 +581,22 @@ hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint
                           uint32_t* czero, int* status, hipStream_t st)
 {
   if (!a.nch) return hipSuccess;
-  hipLaunchKernelGGL(decode2_kernel, dim3((unsigned)((a.nch + 255) / 256)), dim3(256), 0, st, a, words,
-                     bit_off, lut, sorted, code, czero, status);
+  const dim3 grid((unsigned)((a.nch + 255) / 256)), block(256);
+  if (a.n_long <= kDecLong)
+    hipLaunchKernelGGL(decode2_kernel<true>, grid, block, 0, st, a, words, bit_off, lut, sorted, code,
+                       czero, status);
+  else
+    hipLaunchKernelGGL(decode2_kernel<false>, grid, block, 0, st, a, words, bit_off, lut, sorted,
+                       code, czero, status);
   return hipGetLastError();
 }
 
+template hipError_t launch_scatter_unpred2<float>(const uint16_t*, uint64_t, uint32_t,
+                                                  const uint32_t*, const uint64_t*, const float*,
+                                                  uint64_t, float*, int*, const Geom&, hipStream_t);
+template hipError_t launch_scatter_unpred2<double>(const uint16_t*, uint64_t, uint32_t,
+                                                   const uint32_t*, const uint64_t*, const double*,
+                                                   uint64_t, double*, int*, const Geom&, hipStream_t);
 template hipError_t launch_gather_unpred<float>(const uint16_t*, uint64_t, uint32_t, uint32_t*,
                                                 uint64_t*, uint64_t*, const float*, float*,
                                                 const Geom&, hipStream_t);

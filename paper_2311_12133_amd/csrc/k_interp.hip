@@ -31,7 +31,7 @@ __device__ __forceinline__ void finish(T p, int64_t idx, int64_t cpos, const T* 
     W[idx] = q ? xr : x;
   } else {
     const uint32_t q = code[cpos];
-    if (q != 0) W[idx] = (T)((double)p + (double)((int64_t)q - (int64_t)R) * twoe);
+    if (q != 0) W[idx] = (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe);
   }
 }
 
@@ -230,23 +230,63 @@ hipError_t launch_anchors(const Geom& g, const Lattice& lat, const T* X, T* W, u
 }
 
 // min / max with a non-finite flag (value-range bound, Sec. 7.1.3)
+// value range (exact: min and max round nothing) and the non-finite check,
+// 16-byte loads, four in flight per lane; min/max in T, widened at the end
+template <typename T>
+__device__ __forceinline__ bool nonfinite(T v)
+{
+  return !(v - v == (T)0);  // inf - inf and nan - nan are nan
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ X, uint64_t n,
                                                      double* __restrict__ part, int* __restrict__ bad)
 {
   __shared__ double smn[256], smx[256];
-  double mn = INFINITY, mx = -INFINITY;
+  constexpr int V = 16 / sizeof(T);  // values per 16-byte load
+  if (n == 0) return;
+  T mn = X[0], mx = X[0];
   bool nf = false;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double v = (double)X[i];
-    if (!isfinite(v)) nf = true;
-    mn = fmin(mn, v);
-    mx = fmax(mx, v);
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+  const bool aligned = ((uintptr_t)X & 15) == 0;
+  const uint64_t nv = aligned ? n / V : 0;  // whole vectors
+  const uint4* Xv = reinterpret_cast<const uint4*>(X);
+  uint64_t i = tid;
+  for (; i + 3 * nthr < nv; i += 4 * nthr) {
+    uint4 r[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) r[u] = Xv[i + u * nthr];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const T* t = reinterpret_cast<const T*>(&r[u]);
+#pragma unroll
+      for (int j = 0; j < V; j++) {
+        nf |= nonfinite(t[j]);
+        mn = t[j] < mn ? t[j] : mn;
+        mx = t[j] > mx ? t[j] : mx;
+      }
+    }
+  }
+  for (; i < nv; i += nthr) {
+    const uint4 r = Xv[i];
+    const T* t = reinterpret_cast<const T*>(&r);
+#pragma unroll
+    for (int j = 0; j < V; j++) {
+      nf |= nonfinite(t[j]);
+      mn = t[j] < mn ? t[j] : mn;
+      mx = t[j] > mx ? t[j] : mx;
+    }
+  }
+  for (uint64_t k = nv * V + tid; k < n; k += nthr) {
+    const T v = X[k];
+    nf |= nonfinite(v);
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
   }
   if (nf) atomicOr(bad, 1);
-  smn[threadIdx.x] = mn;
-  smx[threadIdx.x] = mx;
+  smn[threadIdx.x] = (double)mn;
+  smx[threadIdx.x] = (double)mx;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {

@@ -255,15 +255,48 @@ __global__ void __launch_bounds__(256) trial_kernel_lds(TrialArgs a,
                    reinterpret_cast<uint32_t*>(lds_raw + ((a.box_cap * sizeof(T) + 15) & ~15ull)));
 }
 
+// per-point work of a trial: score the prediction error, quantize, write the
+// reconstruction back (and count the code)
+template <typename T, bool HIST>
+struct TrialOp {
+  using Fetched = int;
+  T* L;
+  uint32_t* lh;
+  uint32_t* hist;
+  uint32_t R, lo;
+  double el, inv2e, twoe, mul;
+  unsigned long long sc;
+  uint32_t nR;
+  __device__ __forceinline__ int fetch(int32_t, int32_t, int32_t, bool) const { return 0; }
+  __device__ __forceinline__ void apply(int32_t li, int32_t, int32_t, int32_t, T p, int)
+  {
+    const T xv = L[li];
+    const double t = fabs((double)xv - (double)p) * mul;
+    // below 2^32 the floor converts exactly through 32 bits
+    sc += (t < 4294967296.0) ? (unsigned long long)(uint32_t)floor(t) : 4294967296ull;
+    T xr = xv;
+    const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
+    L[li] = xr;
+    if (HIST) {
+      nR += q == R;
+      if (q != R) {
+        const uint32_t w = q - lo;
+        if (w < kTrialHistWin)
+          __hip_atomic_fetch_add(&lh[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_add(&hist[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+};
+
 // Trial of a region of at most three dims held entirely in LDS (original
 // values, then reconstructions in place), on the shared box schedule.
-template <typename T, bool HIST>
-__global__ void __launch_bounds__(1024) trial_box_kernel(TrialArgs a,
-                                                         const TrialBox* __restrict__ boxes,
-                                                         const T* __restrict__ X,
-                                                         const double* __restrict__ wq,
-                                                         unsigned long long* __restrict__ score,
-                                                         uint32_t* __restrict__ hist)
+template <typename T, bool HIST, int NT>
+__global__ void __launch_bounds__(NT) trial_box_kernel(TrialArgs a, const TrialBox* __restrict__ boxes,
+                                                       const T* __restrict__ X,
+                                                       unsigned long long* __restrict__ score,
+                                                       uint32_t* __restrict__ hist)
 {
   extern __shared__ unsigned char lds_raw[];
   __shared__ unsigned long long red[16];
@@ -286,10 +319,11 @@ __global__ void __launch_bounds__(1024) trial_box_kernel(TrialArgs a,
   bx.hi2 = bx.E2 - 1;
   // the region, row-major
   const uint32_t npts = (uint32_t)bx.E0 * bx.b0;
-  const uint32_t mgb0 = fmagic((uint32_t)bx.b0), mgE2 = fmagic((uint32_t)bx.E2);
+  const Divisor mgb0 = fmagic((uint32_t)bx.b0);
+  const Divisor mgE2 = fmagic((uint32_t)bx.E2);
   const int64_t st0 = a.fg.st[0], st1 = a.fg.st[1];
   const T* __restrict__ Xo = X + tb.o[0] * st0 + tb.o[1] * st1 + tb.o[2];
-  for (uint32_t i = threadIdx.x; i < npts; i += blockDim.x) {
+  for (uint32_t i = threadIdx.x; i < npts; i += NT) {
     const uint32_t c0 = fdiv(i, mgb0);
     const uint32_t rem = i - c0 * (uint32_t)bx.b0;
     const uint32_t c1 = fdiv(rem, mgE2);
@@ -297,27 +331,18 @@ __global__ void __launch_bounds__(1024) trial_box_kernel(TrialArgs a,
     L[i] = Xo[c0 * st0 + c1 * st1 + c2];
   }
   if (HIST)
-    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x) lh[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += NT) lh[i] = 0;
   __syncthreads();
-  const uint32_t R = a.R;
-  const double mul = a.score_mul;
   unsigned long long total_score = 0;
+  uint32_t nR = 0;
   for (int l = a.L; l >= 1; l--) {
     const int32_t s = 1 << (l - 1);
     const hpez_interp ip = a.tuned ? a.level[l - 1] : a.cand[cand];
-    const double el = a.el[l], inv2e = a.inv2e[l], twoe = a.twoe[l];
-    unsigned long long sc = 0;
-    auto op = [&](int32_t li, int32_t, int32_t, int32_t, T p) {
-      const T xv = L[li];
-      const double t = fabs((double)xv - (double)p) * mul;
-      sc += (t < 4294967296.0) ? (unsigned long long)floor(t) : 4294967296ull;
-      T xr = xv;
-      const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
-      L[li] = q ? xr : xv;
-      if (HIST) hist_add_wave(lh, hist, a.hist_lo, kTrialHistWin, q, true);
-    };
-    box_level<T>(ip, bx, L, 0, 0, 0, s, wq, op);
-    const unsigned long long v = block_sum_u64(sc, red);
+    TrialOp<T, HIST> op{L,         lh,          hist,         a.R,         a.hist_lo, a.el[l],
+                        a.inv2e[l], a.twoe[l], a.score_mul, 0ull,        0u};
+    box_level<T, NT>(ip, bx, L, 0, 0, 0, s, a.wmd, op);
+    nR += op.nR;
+    const unsigned long long v = block_sum_u64(op.sc, red);
     if (a.score_mode == 0) {
       if (threadIdx.x == 0 && v) atomicAdd(&score[cand * 16 + (l - 1)], v);
     } else {
@@ -327,10 +352,27 @@ __global__ void __launch_bounds__(1024) trial_box_kernel(TrialArgs a,
   if (a.score_mode == 1 && threadIdx.x == 0)
     score[(uint64_t)blockIdx.x * gridDim.y + cand] = total_score;
   if (HIST) {
+    for (int o = 32; o > 0; o >>= 1) nR += __shfl_xor(nR, o, 64);
+    if ((threadIdx.x & 63) == 0 && nR) {
+      const uint32_t w = a.R - a.hist_lo;
+      if (w < kTrialHistWin) atomicAdd(&lh[w], nR);
+      else atomicAdd(&hist[a.R], nR);
+    }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x)
+    for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += NT)
       if (lh[i]) atomicAdd(&hist[a.hist_lo + i], lh[i]);
   }
+}
+
+template <typename T, bool HIST, int NT>
+static void launch_box_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n_boxes,
+                              uint32_t n_cand, const T* X, unsigned long long* d_score,
+                              uint32_t* d_hist, size_t lds, hipStream_t st)
+{
+  (void)hipFuncSetAttribute((const void*)trial_box_kernel<T, HIST, NT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((trial_box_kernel<T, HIST, NT>), dim3(n_boxes, n_cand), dim3(NT), lds, st, a,
+                     d_boxes, X, d_score, d_hist);
 }
 
 template <typename T>
@@ -342,20 +384,20 @@ hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n
   const size_t box = (size_t)a.box_cap * sizeof(T);
   const size_t hb = d_hist ? (size_t)kTrialHistWin * 4 : 0;
   const size_t lds_all = ((box + 15) & ~(size_t)15) + hb;
-  if (a.fg.n[3] == 1 && lds_all <= kTrialBoxLdsBytes) {
+  // in-LDS regions: at most three dims, index arithmetic within the constant
+  // divisor table (every product of two extents <= kMagicMax) and 16 bits
+  if (a.fg.n[3] == 1 && lds_all <= kTrialBoxLdsBytes && a.box_cap < 65536 &&
+      (uint64_t)a.max_ext * (uint64_t)a.max_ext <= kMagicMax) {
     // regions of at most three dims in LDS: 1024 lanes for large regions
-    const unsigned threads = a.box_cap > 4096 ? 1024u : 256u;
-    if (d_hist) {
-      (void)hipFuncSetAttribute((const void*)trial_box_kernel<T, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
-      hipLaunchKernelGGL((trial_box_kernel<T, true>), dim3(n_boxes, n_cand), dim3(threads), lds_all,
-                         st, a, d_boxes, X, d_wq, d_score, d_hist);
-    } else {
-      (void)hipFuncSetAttribute((const void*)trial_box_kernel<T, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
-      hipLaunchKernelGGL((trial_box_kernel<T, false>), dim3(n_boxes, n_cand), dim3(threads),
-                         lds_all, st, a, d_boxes, X, d_wq, d_score, d_hist);
-    }
+    const bool big = a.box_cap > 4096;
+    if (d_hist && big)
+      launch_box_trials<T, true, 1024>(a, d_boxes, n_boxes, n_cand, X, d_score, d_hist, lds_all, st);
+    else if (d_hist)
+      launch_box_trials<T, true, 256>(a, d_boxes, n_boxes, n_cand, X, d_score, d_hist, lds_all, st);
+    else if (big)
+      launch_box_trials<T, false, 1024>(a, d_boxes, n_boxes, n_cand, X, d_score, d_hist, lds_all, st);
+    else
+      launch_box_trials<T, false, 256>(a, d_boxes, n_boxes, n_cand, X, d_score, d_hist, lds_all, st);
     return hipGetLastError();
   }
   if (box <= kTrialLdsBytes) {

@@ -135,6 +135,11 @@ void fill_levels(TrialArgs& a, double e, const hpez_config* Q)
     a.twoe[l] = 2.0 * el;
   }
   a.el[0] = a.inv2e[0] = a.twoe[0] = 0.0;
+  double wq[3 * 16 * 4];
+  md_table(Q, wq);
+  for (int k = 0; k < 3; k++)
+    for (int odd = 0; odd < 8; odd++)
+      for (int d = 0; d < 4; d++) a.wmd[(k * 8 + odd) * 4 + d] = wq[(k * 16 + odd) * 4 + d];
 }
 
 template <typename T>
@@ -160,6 +165,7 @@ int global_tune(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_
   a.L = Lb;
   a.R = Q->radius;
   a.box_cap = cap;
+  a.max_ext = (int32_t)std::min<int64_t>(B + 1, INT32_MAX);
   a.score_mul = 4096.0 / e;
   fill_levels(a, e, Q);
   for (int i = 0; i < kNCand; i++) a.cand[i] = cand[i];
@@ -267,6 +273,7 @@ int block_tune(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   a.R = Q->radius;
   a.score_mode = 1;
   a.box_cap = cap;
+  a.max_ext = (int32_t)side;
   a.score_mul = 4096.0 / e;
   fill_levels(a, e, Q);
   for (int i = 0; i < kNCand; i++) a.cand[i] = cand[i];

@@ -23,11 +23,14 @@ struct TrialArgs {
   int32_t tuned;       // 1: level[] per level; 0: candidate blockIdx.y on every level
   int32_t score_mode;  // 0: score[cand][level] summed over regions; 1: score[region][cand]
   uint32_t hist_lo;    // first code of the LDS histogram window
+  int32_t max_ext;     // largest region extent along any dim
+  int32_t pad2;
   uint64_t box_cap;    // points of the largest region (scratch stride)
   double score_mul;    // 4096 / e
   double el[17], inv2e[17], twoe[17];
   hpez_interp cand[16];
   hpez_interp level[16];
+  double wmd[3 * 8 * 4];  // MD weights [kind][odd set][dim] (Eq. 12), first three dims
 };
 
 #ifdef __HIPCC__
