@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--shape", default="512,512,512")
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (x3): the reference for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build measures "
@@ -68,6 +71,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {src.numel() * 4} bytes x3")
+        return
 
     from paper_2311_12133_amd import binding, fields
 
@@ -144,7 +156,8 @@ def main():
     per_launch_ms = st["ms"] / st["launches"]
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBPS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
+                    traffic=measured_traffic(name, shape),
                     avg_ms=round(per_launch_ms, 4), bytes_per_launch=int(per_launch_bytes))
     groups = {k: dict(ms_per_step=round(v["ms"] / args.steps, 4),
                       GBps=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
@@ -185,6 +198,45 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
+
+
+# Sources whose change invalidates a stored traffic measurement of a kernel group.
+TRAFFIC_SOURCES = {
+    "blocks_predict": ["k_block.hip", "box_dev.h", "interp_dev.h", "block_dev.h", "block.cpp"],
+    "blocks_reconstruct": ["k_block.hip", "box_dev.h", "interp_dev.h", "block_dev.h", "block.cpp"],
+}
+
+
+def sources_sha(names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2311_12133_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(group, shape):
+    """HBM bytes per launch of `group` from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary under profiles/ (scaled by the same counters on a plain copy), or
+    None when there is none for this workload or the kernel sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles",
+                        f"traffic_{group}_{'x'.join(map(str, shape))}_f32.txt")
+    if group not in TRAFFIC_SOURCES or not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != sources_sha(TRAFFIC_SOURCES[group]):
+        return None
+    try:
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(x, cfg, nbytes):

@@ -534,13 +534,16 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   wi++;
   uint32_t zeros = 0;
   bool bad = false;
-  // chunks start at multiples of 64 symbols: eight codes per 16-byte store
-  for (uint64_t i = beg; i < end && !bad; i += 8) {
-    const uint32_t cnt = end - i < 8 ? (uint32_t)(end - i) : 8u;
-    uint32_t pk0 = 0, pk1 = 0, pk2 = 0, pk3 = 0;
+  const uint32_t cnt_all = (uint32_t)(end - beg);
+  // Full groups of eight codes: no per-symbol count checks (an invalid
+  // codeword consumes one bit and marks the chunk bad; the bit count check at
+  // the end catches the rest).  Chunks start at multiples of 64 symbols, so
+  // every group is one 16-byte store.
+  const uint32_t ngroups = cnt_all / 8;
+  for (uint32_t gi = 0; gi < ngroups; gi++) {
+    uint32_t pk[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (uint32_t t = 0; t < 8; t++) {
-      if (t >= cnt || bad) break;
       if (have < 32) {
         buf |= ((uint64_t)pre << 32) >> have;
         have += 32;
@@ -548,29 +551,36 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
         wi++;
       }
       uint32_t L;
-      const uint32_t sym = decode_one<LONG_LDS>(a, lut, slong, sorted, (uint32_t)(buf >> 32), L);
-      if (!L) {
-        bad = true;
-        break;
-      }
+      uint32_t sym = decode_one<LONG_LDS>(a, lut, slong, sorted, (uint32_t)(buf >> 32), L);
+      bad |= L == 0;
+      L = L ? L : 1u;
       zeros += sym == 0;
       buf <<= L;
       have -= (int)L;
       pos += L;
-      const uint32_t v = sym << ((t & 1) * 16);
-      if (t < 2) pk0 |= v;
-      else if (t < 4) pk1 |= v;
-      else if (t < 6) pk2 |= v;
-      else pk3 |= v;
+      pk[t >> 1] |= sym << ((t & 1) * 16);
     }
-    if (cnt == 8) {
-      *reinterpret_cast<uint4*>(code + i) = make_uint4(pk0, pk1, pk2, pk3);
-    } else {
-      for (uint32_t t = 0; t < cnt; t++) {
-        const uint32_t wv = t < 2 ? pk0 : t < 4 ? pk1 : t < 6 ? pk2 : pk3;
-        code[i + t] = (uint16_t)(wv >> ((t & 1) * 16));
-      }
+    *reinterpret_cast<uint4*>(code + beg + 8 * gi) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+  }
+  // the tail of the last chunk of the field
+  for (uint32_t t = ngroups * 8; t < cnt_all && !bad; t++) {
+    if (have < 32) {
+      buf |= ((uint64_t)pre << 32) >> have;
+      have += 32;
+      pre = words[wi < wlast ? wi : wlast];
+      wi++;
     }
+    uint32_t L;
+    const uint32_t sym = decode_one<LONG_LDS>(a, lut, slong, sorted, (uint32_t)(buf >> 32), L);
+    if (!L) {
+      bad = true;
+      break;
+    }
+    zeros += sym == 0;
+    buf <<= L;
+    have -= (int)L;
+    pos += L;
+    code[beg + t] = (uint16_t)sym;
   }
   if (bad || pos != stop) atomicOr(status, 1);
   czero[k] = zeros;
