@@ -305,8 +305,8 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const T* __restri
     src = reinterpret_cast<const T*>(f.val[0]) + (x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2;
   else if (face1)
     src = reinterpret_cast<const T*>(f.val[1]) + (x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2;
-  else if (MODE == 0)
-    src = X + x0 * st0 + x1 * st1 + x2;
+  else if (MODE == 0 && cb < kBrick)
+    src = X + x0 * st0 + x1 * st1 + x2;  // (cell c2 = 32 is the next block's face value)
   if (src) {
     wr = (1u << cnt) - 1u;
     if (vec && cnt == 4) {
