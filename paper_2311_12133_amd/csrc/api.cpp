@@ -34,6 +34,8 @@ struct hpez_ctx {
   size_t ws_bytes = 0;
   uint8_t* pinned = nullptr;
   size_t pinned_bytes = 0;
+  uint8_t* pin_tab = nullptr;  // staging of the block phase's work tables
+  size_t pin_tab_bytes = 0;
   // kernel timing (hpez_profile_enable)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -615,6 +617,20 @@ int ensure_pinned(hpez_ctx* ctx, size_t bytes)
   return HPEZ_OK;
 }
 
+int ensure_pin_tab(hpez_ctx* ctx, size_t bytes)
+{
+  if (bytes <= ctx->pin_tab_bytes) return HPEZ_OK;
+  if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
+  ctx->pin_tab = nullptr;
+  ctx->pin_tab_bytes = 0;
+  if (hipHostMalloc((void**)&ctx->pin_tab, bytes, hipHostMallocDefault) != hipSuccess) {
+    ctx->pin_tab = nullptr;
+    return HPEZ_ENOMEM;
+  }
+  ctx->pin_tab_bytes = bytes;
+  return HPEZ_OK;
+}
+
 struct DevScope {
   int prev = -1;
   explicit DevScope(int dev)
@@ -786,6 +802,36 @@ Lattice anchor_lattice(const Geom& g, int anchor_log2)
   return make_lattice(g, r, m);
 }
 
+// Block-wise fast path of one field: face phase and per-block interiors.
+// Workspace: block_fast_bytes + block_tables_bound(1) from bw.
+template <typename T>
+int block_phase(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e, const T* X,
+                const T* Wg, uint16_t* code, const uint8_t* dbcfg, const double* h_wq,
+                uint32_t* hist, uint32_t lo, T* out, int mode, Bump& bw, hipStream_t st)
+{
+  BlockJobHost<T> J;
+  J.c = c;
+  J.g = g;
+  J.e = e;
+  J.X = X;
+  J.Wg = Wg;
+  J.code = code;
+  J.d_bcfg = dbcfg;
+  J.h_wq = h_wq;
+  J.hist = hist;
+  J.hist_lo = lo;
+  J.area = bw.take<uint8_t>(block_fast_bytes<T>(g));
+  J.out = out;
+  int rc = block_job_prepare<T>(ctx, J);
+  if (rc) return rc;
+  const size_t tb = block_jobs_table_bytes<T>(&J, 1);
+  if (tb > block_tables_bound<T>(1)) return HPEZ_EINVAL;
+  rc = ensure_pin_tab(ctx, tb);
+  if (rc) return rc;
+  void* dt = bw.take<uint8_t>(tb);
+  return run_block_jobs<T>(ctx, &J, 1, mode, dt, ctx->pin_tab, st);
+}
+
 template <typename T>
 int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_config* c,
                uint8_t* out, uint64_t cap, uint64_t* out_size, hipStream_t st)
@@ -795,7 +841,8 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
   const uint32_t nsym = 2 * c->radius;
   const uint64_t nb = n_blocks(d, c);
   const Geom g = make_geom(d, c->frozen_dim);
-  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 0) + block_fast_bytes<T>(g) + 256);
+  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 0) + block_fast_bytes<T>(g) +
+                             block_tables_bound<T>(1) + 512);
   if (rc) return rc;
   const size_t pin_need = (size_t)nsym * 4 + nsym + kHdrBytes + nb + 4096 + (size_t)nsym * 4;
   rc = ensure_pinned(ctx, pin_need);
@@ -892,9 +939,7 @@ int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
     // faces, then block interiors with the brick histogram fused in
     uint32_t lo = c->radius > kBlockHistWin / 2 ? c->radius - kBlockHistWin / 2 : 0;
     if (lo + kBlockHistWin > nsym) lo = nsym > (uint32_t)kBlockHistWin ? nsym - kBlockHistWin : 0;
-    void* area = bw.take<uint8_t>(block_fast_bytes<T>(g));
-    rc = run_block_fast<T>(ctx, c, g, e, X, W, code, dbcfg, dwq, h_wq, hist, lo, area, nullptr, 0,
-                           st);
+    rc = block_phase<T>(ctx, c, g, e, X, W, code, dbcfg, h_wq, hist, lo, nullptr, 0, bw, st);
     if (rc) return rc;
   }
 
@@ -958,7 +1003,8 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
   const uint64_t nb = Lo.n_blocks;
   const Geom g = make_geom(d, c->frozen_dim);
   int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 1) +
-                              (Lo.predictor == 1 ? N * 8 + 256 : 0) + block_fast_bytes<T>(g) + 256);
+                              (Lo.predictor == 1 ? N * 8 + 256 : 0) + block_fast_bytes<T>(g) +
+                              block_tables_bound<T>(1) + 512);
   if (rc) return rc;
   rc = ensure_pinned(ctx, (size_t)nsym + 4096 + nb + 64);
   if (rc) return rc;
@@ -1079,9 +1125,8 @@ int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, 
                      fast ? c->block_log2 : 0);
   if (rc) return rc;
   if (fast) {
-    void* area = bw.take<uint8_t>(block_fast_bytes<T>(g));
-    rc = run_block_fast<T>(ctx, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq,
-                           nullptr, 0, area, out, 1, st);
+    rc = block_phase<T>(ctx, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, h_wq, nullptr, 0,
+                        out, 1, bw, st);
     if (rc) return rc;
   }
   HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1120,6 +1165,7 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   DevScope ds(ctx->device);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }

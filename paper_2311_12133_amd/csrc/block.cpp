@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "block_dev.h"
 #include "hpez_host.h"
@@ -60,44 +62,46 @@ size_t block_fast_bytes(const Geom& g)
   size_t b = 0;
   for (int e = 0; e < 4; e++)
     b += ((elems[e] * sizeof(T) + 255) & ~(size_t)255) + ((elems[e] * 2 + 255) & ~(size_t)255);
-  return b + 1024;  // + the work counter of the block kernel
+  return b;
+}
+
+// face steps of one job: levels below B (5 for B = 32), at most 15 steps each
+constexpr size_t kMaxFaceSteps = kBrickLog2 * 15;
+
+template <typename T>
+size_t block_tables_bound(int n)
+{
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t ent = kMaxFaceSteps * (size_t)n;
+  return al(ent * sizeof(FaceEntry<T>)) + al((ent + kMaxFaceSteps) * 8) +
+         al(n * sizeof(BlockJobDev<T>)) + al((n + 1) * 8) + 256;
 }
 
 template <typename T>
-int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e, const T* X,
-                   const T* Wg, uint16_t* code, const uint8_t* d_bcfg, const double* d_wq,
-                   const double* h_wq, uint32_t* hist, uint32_t hist_lo, void* area, T* out,
-                   int mode, hipStream_t st)
+int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
 {
+  (void)ctx;
+  const Geom& g = J.g;
+  const hpez_config* c = J.c;
   const int64_t B = kBrick;
   int64_t elems[4];
-  FaceGeo f;
-  face_geometry(g, B, kBrickLog2, elems, &f);
-  uint8_t* p = (uint8_t*)area;
+  face_geometry(g, B, kBrickLog2, elems, &J.f);
+  uint8_t* p = (uint8_t*)J.area;
   for (int k = 0; k < 4; k++) {
     if (!elems[k]) continue;
-    f.val[k] = p;
+    J.f.val[k] = p;
     p += (elems[k] * sizeof(T) + 255) & ~(size_t)255;
-    f.code[k] = (uint16_t*)p;
+    J.f.code[k] = (uint16_t*)p;
     p += (elems[k] * 2 + 255) & ~(size_t)255;
   }
-  uint32_t* ticket = (uint32_t*)p;
-  // anchors and levels >= B: copy the coarse grid into the face arrays
-  int64_t r[4], m[4];
-  for (int k = 0; k < 4; k++) {
-    r[k] = 0;
-    m[k] = g.act[k] ? B : 1;
-  }
-  const Lattice coarse = make_lattice(g, r, m);
-  BCK(launch_face_init<T>(f, g, coarse, Wg, code, mode, st));
-
   const int Lb = c->block_log2;
   const int nact = n_active(g);
-  hipEvent_t ev = ctx_span_begin(ctx, st);
-  uint64_t face_pts = 0;
+  int64_t r[4], m[4];
+  J.face_pts = 0;
+  for (int l = 0; l <= 16; l++) J.steps[l].clear();
   for (int l = Lb; l >= 1; l--) {
     const int64_t s = (int64_t)1 << (l - 1);
-    const double el = level_eb(e, c->alpha, c->beta, l);
+    const double el = level_eb(J.e, c->alpha, c->beta, l);
     const hpez_interp& ip = c->level[l - 1];
     FaceStep a;
     std::memset(&a, 0, sizeof a);
@@ -109,8 +113,8 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
     a.inv2e = 1.0 / (2.0 * el);
     a.twoe = 2.0 * el;
     a.R = c->radius;
-    // one launch per step over every family whose planes the step touches
-    auto step = [&](const int64_t* rr, const int64_t* mm) -> int {
+    // one step over every family whose planes the step touches
+    auto step = [&](const int64_t* rr, const int64_t* mm) {
       for (int k = 0; k < 4; k++) {
         a.first[k] = rr[k];
         a.step[k] = mm[k];
@@ -127,9 +131,8 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
         }
         a.off[d + 1] = a.off[d] + tot;
       }
-      face_pts += a.off[4];
-      if (launch_face_step<T>(a, f, X, code, out, mode, st) != hipSuccess) return HPEZ_EDEVICE;
-      return HPEZ_OK;
+      J.face_pts += a.off[4];
+      J.steps[l].push_back(a);
     };
     if (ip.md) {
       for (int cnt = 1; cnt <= nact; cnt++)
@@ -144,9 +147,8 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
             else { r[k] = 0; m[k] = 2 * s; }
           }
           a.odd = odd;
-          for (int k = 0; k < 4; k++) a.wq[k] = h_wq[(ip.kind * 16 + odd) * 4 + k];
-          int rc = step(r, m);
-          if (rc) return rc;
+          for (int k = 0; k < 4; k++) a.wq[k] = J.h_wq[(ip.kind * 16 + odd) * 4 + k];
+          step(r, m);
         }
     } else {
       int pos[4] = {-1, -1, -1, -1}, np = 0;
@@ -170,38 +172,35 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
           m[pd] = 4 * s;
           r[pd] = s;
           a.sl = 0;
-          int rc = step(r, m);
-          if (rc) return rc;
+          step(r, m);
           r[pd] = 3 * s;
           a.sl = 1;
-          rc = step(r, m);
-          if (rc) return rc;
+          step(r, m);
           a.sl = 0;
         } else {
           a.sl = 0;
-          int rc = step(r, m);
-          if (rc) return rc;
+          step(r, m);
         }
       }
     }
   }
-  ctx_span_end(ctx, ev, mode == 0 ? "faces_predict" : "faces_reconstruct",
-               face_pts * (sizeof(T) + 2), st);
 
-  BlockArgs ba;
+  BlockArgs& ba = J.ba;
   std::memset(&ba, 0, sizeof ba);
   ba.g = g;
-  uint64_t npts = 1;
+  J.nblocks = 1;
+  J.npts = 1;
   for (int k = 0; k < 4; k++) {
     ba.nb[k] = (g.n[k] + B - 1) / B;
-    npts *= (uint64_t)g.n[k];
+    J.nblocks *= (uint64_t)ba.nb[k];
+    J.npts *= (uint64_t)g.n[k];
   }
   ba.L = Lb;
   ba.R = c->radius;
-  ba.hist_lo = hist_lo;
-  ba.vec = (g.n[2] % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)out % 16 == 0);
+  ba.hist_lo = J.hist_lo;
+  ba.vec = (g.n[2] % 4 == 0) && ((uintptr_t)J.X % 16 == 0) && ((uintptr_t)J.out % 16 == 0);
   for (int l = 1; l <= 16; l++) {
-    const double el = level_eb(e, c->alpha, c->beta, l);
+    const double el = level_eb(J.e, c->alpha, c->beta, l);
     ba.el_l[l] = el;
     ba.inv2e_l[l] = 1.0 / (2.0 * el);
     ba.twoe_l[l] = 2.0 * el;
@@ -209,15 +208,149 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
   for (uint32_t i = 0; i < c->n_cand && i < 16; i++) ba.cand[i] = c->cand[i];
   for (int k = 0; k < 3; k++)
     for (int odd = 0; odd < 8; odd++)
-      for (int d = 0; d < 4; d++) ba.wmd[(k * 8 + odd) * 4 + d] = h_wq[(k * 16 + odd) * 4 + d];
-  ev = ctx_span_begin(ctx, st);
+      for (int d = 0; d < 4; d++)
+        ba.wmd[(k * 8 + odd) * 4 + d] = J.h_wq[(k * 16 + odd) * 4 + d];
+  J.lds = block_lds_bytes<T>(g);
+  return HPEZ_OK;
+}
+
+// face-step launch geometry of a step: work-groups of 256 lanes
+static uint64_t face_wgs(uint64_t pts)
+{
+  uint64_t b = (pts + 255) / 256;
+  if (b > 65536) b = 65536;
+  return b;
+}
+
+template <typename T>
+size_t block_jobs_table_bytes(const BlockJobHost<T>* jobs, int n)
+{
+  size_t ent = 0, slots = 0;
+  for (int l = 1; l <= 16; l++) {
+    size_t mx = 0;
+    for (int j = 0; j < n; j++) mx = std::max(mx, jobs[j].steps[l].size());
+    slots += mx;
+    for (int j = 0; j < n; j++) ent += jobs[j].steps[l].size();
+  }
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  return al(ent * sizeof(FaceEntry<T>)) + al((ent + slots) * 8) + al(n * sizeof(BlockJobDev<T>)) +
+         al((n + 1) * 8) + 256;
+}
+
+template <typename T>
+int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* d_tables,
+                   uint8_t* h_tables, hipStream_t st)
+{
+  if (n <= 0) return HPEZ_OK;
+  // anchors and levels >= B: copy the coarse grid into the face arrays
+  for (int j = 0; j < n; j++) {
+    BlockJobHost<T>& J = jobs[j];
+    int64_t r[4], m[4];
+    for (int k = 0; k < 4; k++) {
+      r[k] = 0;
+      m[k] = J.g.act[k] ? kBrick : 1;
+    }
+    const Lattice coarse = make_lattice(J.g, r, m);
+    BCK(launch_face_init<T>(J.f, J.g, coarse, J.Wg, J.code, mode, st));
+  }
+
+  // every table of the launches below, built on the host and copied once
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t ent = 0, slots = 0;
+  int Lmax = 0;
+  for (int l = 1; l <= 16; l++) {
+    size_t mx = 0;
+    for (int j = 0; j < n; j++) {
+      mx = std::max(mx, jobs[j].steps[l].size());
+      ent += jobs[j].steps[l].size();
+    }
+    slots += mx;
+    if (mx) Lmax = l;
+  }
+  const size_t off_wg = al(ent * sizeof(FaceEntry<T>));
+  const size_t off_jobs = off_wg + al((ent + slots) * 8);
+  const size_t off_begin = off_jobs + al(n * sizeof(BlockJobDev<T>));
+  const size_t off_ticket = off_begin + al((n + 1) * 8);
+  const size_t bytes = off_ticket + 256;
+  std::memset(h_tables, 0, bytes);
+  FaceEntry<T>* he = (FaceEntry<T>*)h_tables;
+  uint64_t* hw = (uint64_t*)(h_tables + off_wg);
+  struct Launch {
+    size_t e0, w0;
+    int cnt;
+    uint64_t wgs;
+    bool narrow;
+  };
+  std::vector<Launch> launches;
+  size_t ei = 0, wi = 0;
+  uint64_t face_pts = 0;
+  for (int l = Lmax; l >= 1; l--) {
+    size_t mx = 0;
+    for (int j = 0; j < n; j++) mx = std::max(mx, jobs[j].steps[l].size());
+    for (size_t k = 0; k < mx; k++) {
+      Launch L{ei, wi, 0, 0, true};
+      for (int j = 0; j < n; j++) {
+        if (jobs[j].steps[l].size() <= k) continue;
+        const FaceStep& a = jobs[j].steps[l][k];
+        const uint64_t tot = a.off[4];
+        if (!tot) continue;
+        FaceEntry<T>& E = he[ei++];
+        E.a = a;
+        E.f = jobs[j].f;
+        E.X = jobs[j].X;
+        E.code = jobs[j].code;
+        E.out = jobs[j].out;
+        E.wg_begin = L.wgs;
+        E.wg_count = face_wgs(tot);
+        hw[wi++] = L.wgs;
+        L.wgs += E.wg_count;
+        L.narrow = L.narrow && tot < (1ull << 32);
+        L.cnt++;
+        face_pts += tot;
+      }
+      if (L.cnt) {
+        hw[wi++] = L.wgs;  // end marker
+        launches.push_back(L);
+      }
+    }
+  }
+  BlockJobDev<T>* hj = (BlockJobDev<T>*)(h_tables + off_jobs);
+  uint64_t* hb = (uint64_t*)(h_tables + off_begin);
+  uint64_t total_blocks = 0, npts = 0;
+  size_t lds = 0;
+  for (int j = 0; j < n; j++) {
+    hj[j].a = jobs[j].ba;
+    hj[j].f = jobs[j].f;
+    hj[j].X = jobs[j].X;
+    hj[j].code = jobs[j].code;
+    hj[j].bcfg = jobs[j].d_bcfg;
+    hj[j].hist = jobs[j].hist;
+    hj[j].out = jobs[j].out;
+    hj[j].block_begin = total_blocks;
+    hb[j] = total_blocks;
+    total_blocks += jobs[j].nblocks;
+    npts += jobs[j].npts;
+    lds = std::max(lds, jobs[j].lds);
+  }
+  hb[n] = total_blocks;
+  uint8_t* dt = (uint8_t*)d_tables;
+  BCK(hipMemcpyAsync(dt, h_tables, bytes, hipMemcpyHostToDevice, st));
+
+  hipEvent_t ev = ctx_span_begin(ctx, st);
+  for (const Launch& L : launches)
+    BCK(launch_face_steps<T>((const FaceEntry<T>*)dt + L.e0, (const uint64_t*)(dt + off_wg) + L.w0,
+                             L.cnt, L.wgs, L.narrow, mode, st));
+  ctx_span_end(ctx, ev, mode == 0 ? "faces_predict" : "faces_reconstruct",
+               face_pts * (sizeof(T) + 2), st);
+
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx_device(ctx)) !=
           hipSuccess ||
       n_cu <= 0)
     return HPEZ_EDEVICE;
-  BCK(hipMemsetAsync(ticket, 0, sizeof(uint32_t), st));
-  BCK(launch_blocks<T>(ba, f, X, code, d_bcfg, hist, out, ticket, n_cu, mode, st));
+  ev = ctx_span_begin(ctx, st);
+  BCK(launch_block_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
+                           n, total_blocks, lds, (uint32_t*)(dt + off_ticket), n_cu, mode, st));
   ctx_span_end(ctx, ev, mode == 0 ? "blocks_predict" : "blocks_reconstruct",
                npts * (sizeof(T) + 2), st);
   return HPEZ_OK;
@@ -226,9 +359,11 @@ int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e,
 #define INST(T)                                                                                  \
   template bool block_fast_ok<T>(const hpez_config*, const Geom&);                               \
   template size_t block_fast_bytes<T>(const Geom&);                                              \
-  template int run_block_fast<T>(hpez_ctx*, const hpez_config*, const Geom&, double, const T*,   \
-                                 const T*, uint16_t*, const uint8_t*, const double*,             \
-                                 const double*, uint32_t*, uint32_t, void*, T*, int, hipStream_t);
+  template size_t block_tables_bound<T>(int);                                                    \
+  template int block_job_prepare<T>(hpez_ctx*, BlockJobHost<T>&);                                \
+  template size_t block_jobs_table_bytes<T>(const BlockJobHost<T>*, int);                        \
+  template int run_block_jobs<T>(hpez_ctx*, BlockJobHost<T>*, int, int, void*, uint8_t*,         \
+                                 hipStream_t);
 INST(float)
 INST(double)
 

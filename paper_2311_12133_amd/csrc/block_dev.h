@@ -49,18 +49,45 @@ struct BlockArgs {
   hpez_interp cand[16];
 };
 
+// Work tables of the fused launches (many fields in one launch).  A face-step
+// entry owns work-groups [wg_begin, wg_begin + wg_count) of its launch; a block
+// job owns global block indices [block_begin, block_begin + nb0 nb1 nb2).
+template <typename T>
+struct FaceEntry {
+  FaceStep a;
+  FaceGeo f;
+  const T* X;
+  uint16_t* code;
+  const T* out;
+  uint64_t wg_begin, wg_count;
+};
+
+template <typename T>
+struct BlockJobDev {
+  BlockArgs a;
+  FaceGeo f;
+  const T* X;
+  uint16_t* code;
+  const uint8_t* bcfg;
+  uint32_t* hist;
+  T* out;
+  uint64_t block_begin;
+};
+
+// one fused face step: entries [0, n) of the device table, total work-groups
+template <typename T>
+hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_begin, int n,
+                             uint64_t total_wg, bool narrow, int mode, hipStream_t st);
+// the block phase of jobs [0, n): d_begin[j] = first global block index of job j
+// (d_begin[n] = total); lds = largest box of the jobs
+template <typename T>
+hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
+                             uint64_t total_blocks, size_t lds, uint32_t* ticket, int n_cu,
+                             int mode, hipStream_t st);
+
 template <typename T>
 hipError_t launch_face_init(const FaceGeo& f, const Geom& g, const Lattice& lat, const T* W,
                             const uint16_t* code, int mode, hipStream_t st);
 template <typename T>
-hipError_t launch_face_step(const FaceStep& a, const FaceGeo& f, const T* X, uint16_t* code,
-                            const T* out, int mode, hipStream_t st);
-template <typename T>
 size_t block_lds_bytes(const Geom& g);
-// ticket: one zeroed device word (work distribution); n_cu: compute units
-template <typename T>
-hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint16_t* code,
-                         const uint8_t* d_bcfg, uint32_t* hist, T* out, uint32_t* ticket, int n_cu,
-                         int mode, hipStream_t st);
-
 }  // namespace hpez

@@ -4,6 +4,9 @@
 
 #include <stdint.h>
 
+#include <vector>
+
+#include "block_dev.h"
 #include "hpez_internal.h"
 
 namespace hpez {
@@ -88,9 +91,41 @@ template <typename T>
 bool block_fast_ok(const hpez_config* c, const Geom& g);
 template <typename T>
 size_t block_fast_bytes(const Geom& g);
+
+// One field's block phase: face arrays in `area` (block_fast_bytes), the face
+// steps of every level below B, and the per-block kernel's arguments.
 template <typename T>
-int run_block_fast(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e, const T* X,
-                   const T* Wg, uint16_t* code, const uint8_t* d_bcfg, const double* d_wq,
-                   const double* h_wq, uint32_t* hist, uint32_t hist_lo, void* area, T* out,
-                   int mode, hipStream_t st);
+struct BlockJobHost {
+  // inputs
+  const hpez_config* c = nullptr;
+  Geom g;
+  double e = 0;
+  const T* X = nullptr;    // compress: the field
+  const T* Wg = nullptr;   // the grid holding anchors and levels >= B
+  uint16_t* code = nullptr;
+  const uint8_t* d_bcfg = nullptr;
+  const double* h_wq = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t hist_lo = 0;
+  void* area = nullptr;
+  T* out = nullptr;        // decompress: the field
+  // built by block_job_prepare
+  FaceGeo f;
+  BlockArgs ba;
+  std::vector<FaceStep> steps[17];
+  uint64_t nblocks = 0, npts = 0, face_pts = 0;
+  size_t lds = 0;
+};
+template <typename T>
+int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J);
+// device and pinned host bytes of the work tables of run_block_jobs
+template <typename T>
+size_t block_tables_bound(int n);  // any n jobs
+template <typename T>
+size_t block_jobs_table_bytes(const BlockJobHost<T>* jobs, int n);
+// face phase then block phase of jobs [0, n) in fused launches (mode 0
+// compress, 1 decompress); d_tables / h_tables: block_jobs_table_bytes each
+template <typename T>
+int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* d_tables,
+                   uint8_t* h_tables, hipStream_t st);
 }  // namespace hpez

@@ -33,6 +33,18 @@ __device__ __forceinline__ int64_t face_index(const FaceGeo& f, int e, const int
   return i;
 }
 
+// index of the last entry whose begin is <= x (begin ascending, begin[0] = 0)
+__device__ __forceinline__ int find_entry(const uint64_t* __restrict__ begin, int n, uint64_t x)
+{
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // write a face point's value into every family it belongs to
 template <typename T>
 __device__ __forceinline__ void face_store(const FaceGeo& f, const Geom& g, const int64_t* x, T v)
@@ -73,17 +85,24 @@ __global__ void __launch_bounds__(256) face_init_kernel(FaceGeo f, Geom g, Latti
   }
 }
 
-// one step of the face phase for every family it touches; I is the index
-// type (32-bit when the launch has fewer than 2^32 points)
+// one step of the face phase for every family it touches, for every entry of
+// the table (one entry per field); an entry owns a range of work-groups.  I is
+// the index type (32-bit when every entry has fewer than 2^32 points).
 template <typename T, int MODE, typename I>
-__global__ void __launch_bounds__(256) face_step_kernel(FaceStep a, FaceGeo f,
-                                                        const T* __restrict__ X,
-                                                        uint16_t* __restrict__ code,
-                                                        const T* __restrict__ out)
+__global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __restrict__ tab,
+                                                        const uint64_t* __restrict__ wg_begin,
+                                                        int n)
 {
+  const int ei = find_entry(wg_begin, n, blockIdx.x);
+  const FaceEntry<T>& E = tab[ei];
+  const FaceStep& a = E.a;
+  const FaceGeo& f = E.f;
+  const T* __restrict__ X = E.X;
+  uint16_t* __restrict__ code = E.code;
+  const T* __restrict__ out = E.out;
   const I total = (I)a.off[4];
-  const I stride = (I)gridDim.x * blockDim.x;
-  for (I k = (I)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+  const I stride = (I)E.wg_count * blockDim.x;
+  for (I k = (I)(blockIdx.x - E.wg_begin) * blockDim.x + threadIdx.x; k < total; k += stride) {
     int d = 0;
     if ((uint64_t)k >= a.off[1]) d = 1;
     if ((uint64_t)k >= a.off[2]) d = 2;
@@ -338,12 +357,9 @@ __device__ __forceinline__ void store_item(T* L, const Quad<T>& v, int32_t lbase
 // float boxes the next block's loads are issued before the current block's
 // levels, so they complete while it computes.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlockThreads) block_kernel(BlockArgs a, FaceGeo f,
-                                                              const T* __restrict__ X,
-                                                              uint16_t* __restrict__ code,
-                                                              const uint8_t* __restrict__ bcfg,
-                                                              uint32_t* __restrict__ hist,
-                                                              T* __restrict__ out,
+__global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<T>* __restrict__ jobs,
+                                                              const uint64_t* __restrict__ begin,
+                                                              int njobs,
                                                               uint32_t* __restrict__ ticket)
 {
   constexpr int NT = kBlockThreads;
@@ -352,31 +368,43 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(BlockArgs a, FaceG
   extern __shared__ unsigned char lds_raw[];
   __shared__ uint32_t s_next;
   T* L = reinterpret_cast<T*>(lds_raw);
-  const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
-  const uint64_t nbt = (uint64_t)(a.nb[0] * a.nb[1] * a.nb[2]);
-  const uint32_t lo = a.hist_lo;
-  // rows are 16-byte aligned in X, out and the face arrays (host-checked)
-  const bool vec = a.vec != 0;
+  const uint64_t nbt = begin[njobs];
 
   if (threadIdx.x == 0) s_next = atomicAdd(ticket, 1u);
   __syncthreads();
-  uint64_t bi = s_next;
+  uint64_t gbi = __builtin_amdgcn_readfirstlane(s_next);
   Quad<T> pv[UP];
   int32_t plb[UP];
   uint32_t pwr[UP];
-  if (PREF && bi < nbt) {
+  if (PREF && gbi < nbt) {
+    const int j = find_entry(begin, njobs, gbi);
+    const BlockJobDev<T>& J = jobs[j];
     Block3 bk;
     Box bx;
-    block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
+    block_geometry(J.a.g, (int64_t)(gbi - begin[j]), J.a.nb, bk, bx);
     const BoxItems its = box_items(bx);
 #pragma unroll
     for (int u = 0; u < UP; u++)
-      pv[u] = load_item<T, MODE>(f, X, st0, st1, bk, bx, its, threadIdx.x + u * NT, vec, plb[u], pwr[u]);
+      pv[u] = load_item<T, MODE>(J.f, J.X, J.a.g.st[0], J.a.g.st[1], bk, bx, its, threadIdx.x + u * NT,
+                                 J.a.vec != 0, plb[u], pwr[u]);
   }
 
-  while (bi < nbt) {
+  while (gbi < nbt) {
     __syncthreads();  // every lane has read s_next; the previous block is done with LDS
     if (threadIdx.x == 0) s_next = atomicAdd(ticket, 1u);
+    const int jb = find_entry(begin, njobs, gbi);
+    const BlockJobDev<T>& J = jobs[jb];
+    const BlockArgs& a = J.a;
+    const FaceGeo& f = J.f;
+    const T* __restrict__ X = J.X;
+    uint16_t* __restrict__ code = J.code;
+    uint32_t* __restrict__ hist = J.hist;
+    T* __restrict__ out = J.out;
+    const uint64_t bi = gbi - begin[jb];
+    const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
+    const uint32_t lo = a.hist_lo;
+    // rows are 16-byte aligned in X, out and the face arrays (host-checked)
+    const bool vec = a.vec != 0;
     Block3 bk;
     Box bx;
     block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
@@ -451,21 +479,23 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(BlockArgs a, FaceG
       }
     }
     __syncthreads();
-    const uint64_t bn = s_next;
+    const uint64_t bn = __builtin_amdgcn_readfirstlane(s_next);
     if (PREF && bn < nbt) {
       // the next block's loads, in flight during this block's levels
+      const int j2 = find_entry(begin, njobs, bn);
+      const BlockJobDev<T>& J2 = jobs[j2];
       Block3 bk2;
       Box bx2;
-      block_geometry(a.g, (int64_t)bn, a.nb, bk2, bx2);
+      block_geometry(J2.a.g, (int64_t)(bn - begin[j2]), J2.a.nb, bk2, bx2);
       const BoxItems its2 = box_items(bx2);
 #pragma unroll
       for (int u = 0; u < UP; u++)
-        pv[u] = load_item<T, MODE>(f, X, st0, st1, bk2, bx2, its2, threadIdx.x + u * NT, vec, plb[u],
-                                   pwr[u]);
+        pv[u] = load_item<T, MODE>(J2.f, J2.X, J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,
+                                   threadIdx.x + u * NT, J2.a.vec != 0, plb[u], pwr[u]);
     }
 
     // ---- the levels below B with the block's configuration
-    const hpez_interp c = a.cand[bcfg[bi]];
+    const hpez_interp c = a.cand[J.bcfg[bi]];
     uint32_t nR = 0;
     for (int l = a.L; l >= 1; l--) {
       const int32_t s = 1 << (l - 1);
@@ -535,7 +565,7 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(BlockArgs a, FaceG
       for (int i = threadIdx.x; i < kBlockHistWin; i += NT)
         if (lh[i]) atomicAdd(&hist[lo + i], lh[i]);
     }
-    bi = bn;
+    gbi = bn;
   }
 }
 
@@ -562,21 +592,19 @@ hipError_t launch_face_init(const FaceGeo& f, const Geom& g, const Lattice& lat,
 }
 
 template <typename T>
-hipError_t launch_face_step(const FaceStep& a, const FaceGeo& f, const T* X, uint16_t* code,
-                            const T* out, int mode, hipStream_t st)
+hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_begin, int n,
+                             uint64_t total_wg, bool narrow, int mode, hipStream_t st)
 {
-  const uint64_t total = a.off[4];
-  if (!total) return hipSuccess;
-  const dim3 grid(gridn(total)), block(256);
-  const bool narrow = total < (1ull << 32);
+  if (!total_wg || n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total_wg), block(256);
   if (mode == 0 && narrow)
-    hipLaunchKernelGGL((face_step_kernel<T, 0, uint32_t>), grid, block, 0, st, a, f, X, code, out);
+    hipLaunchKernelGGL((face_step_kernel<T, 0, uint32_t>), grid, block, 0, st, d_tab, d_wg_begin, n);
   else if (mode == 0)
-    hipLaunchKernelGGL((face_step_kernel<T, 0, uint64_t>), grid, block, 0, st, a, f, X, code, out);
+    hipLaunchKernelGGL((face_step_kernel<T, 0, uint64_t>), grid, block, 0, st, d_tab, d_wg_begin, n);
   else if (narrow)
-    hipLaunchKernelGGL((face_step_kernel<T, 1, uint32_t>), grid, block, 0, st, a, f, X, code, out);
+    hipLaunchKernelGGL((face_step_kernel<T, 1, uint32_t>), grid, block, 0, st, d_tab, d_wg_begin, n);
   else
-    hipLaunchKernelGGL((face_step_kernel<T, 1, uint64_t>), grid, block, 0, st, a, f, X, code, out);
+    hipLaunchKernelGGL((face_step_kernel<T, 1, uint64_t>), grid, block, 0, st, d_tab, d_wg_begin, n);
   return hipGetLastError();
 }
 
@@ -592,26 +620,23 @@ size_t block_lds_bytes(const Geom& g)
 }
 
 template <typename T>
-hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint16_t* code,
-                         const uint8_t* d_bcfg, uint32_t* hist, T* out, uint32_t* ticket, int n_cu,
-                         int mode, hipStream_t st)
+hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
+                             uint64_t total_blocks, size_t lds, uint32_t* ticket, int n_cu,
+                             int mode, hipStream_t st)
 {
-  uint64_t nbt = 1;
-  for (int d = 0; d < 4; d++) nbt *= (uint64_t)a.nb[d];
-  if (!nbt) return hipSuccess;
-  const size_t lds = block_lds_bytes<T>(a.g);
+  if (!total_blocks || n <= 0) return hipSuccess;
   // one work-group per CU (the box takes the CU's LDS); blocks come from the ticket
-  const unsigned grid = (unsigned)(nbt < (uint64_t)n_cu ? nbt : (uint64_t)n_cu);
+  const unsigned grid = (unsigned)(total_blocks < (uint64_t)n_cu ? total_blocks : (uint64_t)n_cu);
   if (mode == 0) {
     (void)hipFuncSetAttribute((const void*)block_kernel<T, 0>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((block_kernel<T, 0>), dim3(grid), dim3(kBlockThreads), lds, st, a, f, X, code,
-                       d_bcfg, hist, out, ticket);
+    hipLaunchKernelGGL((block_kernel<T, 0>), dim3(grid), dim3(kBlockThreads), lds, st, d_jobs, d_begin,
+                       n, ticket);
   } else {
     (void)hipFuncSetAttribute((const void*)block_kernel<T, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((block_kernel<T, 1>), dim3(grid), dim3(kBlockThreads), lds, st, a, f, X, code,
-                       d_bcfg, hist, out, ticket);
+    hipLaunchKernelGGL((block_kernel<T, 1>), dim3(grid), dim3(kBlockThreads), lds, st, d_jobs, d_begin,
+                       n, ticket);
   }
   return hipGetLastError();
 }
@@ -619,12 +644,11 @@ hipError_t launch_blocks(const BlockArgs& a, const FaceGeo& f, const T* X, uint1
 #define INST(T)                                                                                  \
   template hipError_t launch_face_init<T>(const FaceGeo&, const Geom&, const Lattice&, const T*, \
                                           const uint16_t*, int, hipStream_t);                    \
-  template hipError_t launch_face_step<T>(const FaceStep&, const FaceGeo&, const T*, uint16_t*,  \
-                                          const T*, int, hipStream_t);                           \
   template size_t block_lds_bytes<T>(const Geom&);                                               \
-  template hipError_t launch_blocks<T>(const BlockArgs&, const FaceGeo&, const T*, uint16_t*,     \
-                                       const uint8_t*, uint32_t*, T*, uint32_t*, int, int,        \
-                                       hipStream_t);
+  template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
+                                           size_t, uint32_t*, int, int, hipStream_t);             \
+  template hipError_t launch_face_steps<T>(const FaceEntry<T>*, const uint64_t*, int, uint64_t,   \
+                                           bool, int, hipStream_t);
 INST(float)
 INST(double)
 
