@@ -164,6 +164,21 @@ int hpez_compress(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
                   const hpez_config* cfg, void* d_out, uint64_t out_cap, uint64_t* out_size,
                   hipStream_t stream);
 
+/* Compress n fields in one call (many fields of uneven shapes and dtypes).
+ * Arrays have n entries: desc[i], cfg[i] (host structs), d_in[i] and d_out[i]
+ * (device pointers), out_cap[i]; out_sizes[i] (host) receives stream i's
+ * length, 0 if field i failed.  Every field goes through the same steps as in
+ * hpez_compress, so stream i is byte-identical to the plain call's; the batch
+ * shares one stream synchronization per phase among all fields, runs the
+ * per-block phase of all block-wise fields of a dtype in fused launches, and
+ * builds the Huffman codebooks (Sec. 4 step 4) on several host threads.
+ * Returns HPEZ_OK when every field succeeded, otherwise the error of the first
+ * failing field (by dtype group, then index); a device error ends the call.
+ * Device workspace is the sum of the fields' footprints. */
+int hpez_compress_batch(hpez_ctx* ctx, int n, const hpez_field_desc* desc,
+                        const void* const* d_in, const hpez_config* cfg, void* const* d_out,
+                        const uint64_t* out_cap, uint64_t* out_sizes, hipStream_t stream);
+
 /* Read the field description and size facts of a stream whose first bytes
  * (at least 512) are at h_hdr (host).  n_points / total_bytes may be NULL. */
 int hpez_inspect(const void* h_hdr, uint64_t n, hpez_field_desc* desc, uint64_t* n_points,
@@ -176,6 +191,17 @@ int hpez_inspect(const void* h_hdr, uint64_t n, hpez_field_desc* desc, uint64_t*
 int hpez_decompress(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_out,
                     uint64_t out_cap, hipStream_t stream);
 
+/* Decompress n streams in one call: d_in[i] (device, in_size[i] bytes) into
+ * d_out[i] (device, out_cap[i] bytes).  rcs[i] (host) receives stream i's own
+ * result (HPEZ_OK, HPEZ_ECORRUPT, HPEZ_ENOSPC).  Output i is bit-identical to
+ * hpez_decompress of stream i; headers are read with one synchronization and
+ * the per-block phase of all block-wise streams of a dtype runs in fused
+ * launches.  Returns HPEZ_OK when every stream succeeded, otherwise the first
+ * nonzero rcs[i]; a device error ends the call. */
+int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const uint64_t* in_size,
+                          void* const* d_out, const uint64_t* out_cap, int* rcs,
+                          hipStream_t stream);
+
 /* Auto-tune a configuration for the device field d_in (Sec. 6).  *out_cfg is
  * in/out: on entry its radius, chunk, alpha and beta are used (the rest is
  * ignored); on return it holds a complete configuration.  When block-wise
@@ -186,6 +212,18 @@ int hpez_decompress(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_o
 int hpez_tune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
               const hpez_tune_opts* opts, hpez_config* out_cfg, uint8_t* h_block_cfg,
               uint64_t block_cfg_cap, hipStream_t stream);
+
+/* Tune n fields in one call.  Arrays of n entries: desc[i], d_in[i] (device),
+ * opts[i], out_cfg[i] (in/out as in hpez_tune), h_block_cfg[i] (host buffer of
+ * block_cfg_cap[i] bytes, or NULL without block-wise tuning); rcs[i] receives
+ * field i's own result.  Field i's configuration and block choices are the
+ * same as hpez_tune's; the batch synchronizes once per tuning phase for all
+ * fields and runs the candidate trials of every field (Sec. 6.2, 6.3, 6.6) in
+ * fused launches.  Returns HPEZ_OK when every field succeeded, otherwise the
+ * first nonzero rcs[i]; a device error ends the call.  Synchronous. */
+int hpez_tune_batch(hpez_ctx* ctx, int n, const hpez_field_desc* desc, const void* const* d_in,
+                    const hpez_tune_opts* opts, hpez_config* out_cfg, uint8_t* const* h_block_cfg,
+                    const uint64_t* block_cfg_cap, int* rcs, hipStream_t stream);
 
 /* Device bytes the context needs for op (0 compress, 1 decompress, 2 tune) of
  * such a field, beyond the caller's input and output buffers.  Pure. */

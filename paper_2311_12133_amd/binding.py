@@ -60,7 +60,8 @@ class KernelStat(C.Structure):
 
 EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_default",
            "hpez_compress_bound", "hpez_compress", "hpez_inspect", "hpez_decompress",
-           "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read"]
+           "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read",
+           "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch"]
 
 _lib = None
 _lock = threading.Lock()
@@ -90,6 +91,12 @@ def lib():
             L.hpez_footprint.argtypes = [P(FieldDesc), P(Config), C.c_int, P(u64)]
             L.hpez_profile_enable.argtypes = [vp, C.c_int]
             L.hpez_profile_read.argtypes = [vp, P(KernelStat), C.c_int, P(C.c_int)]
+            L.hpez_compress_batch.argtypes = [vp, C.c_int, P(FieldDesc), P(vp), P(Config), P(vp),
+                                              P(u64), P(u64), vp]
+            L.hpez_decompress_batch.argtypes = [vp, C.c_int, P(vp), P(u64), P(vp), P(u64),
+                                                P(C.c_int), vp]
+            L.hpez_tune_batch.argtypes = [vp, C.c_int, P(FieldDesc), P(vp), P(TuneOpts),
+                                          P(Config), P(vp), P(u64), P(C.c_int), vp]
             _lib = L
     return _lib
 
@@ -256,13 +263,8 @@ def decompress(stream_t, stream=None, out=None):
     return out
 
 
-def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
-    """Run the auto-tuner on a CUDA tensor; returns a complete config dict."""
+def _tune_opts(opts: dict | None) -> TuneOpts:
     opts = opts or {}
-    dtype = _dtype_of(x)
-    keep = []
-    d = desc_from(tuple(x.shape), dtype, cfg["eb"], cfg["eb_mode"])
-    c = config_from(cfg, keep)
     o = TuneOpts()
     o.global_rate = opts.get("global_rate", 0.01)
     o.sub_rate = opts.get("sub_rate", 0.04)
@@ -272,16 +274,18 @@ def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
     o.allow_lorenzo = opts.get("allow_lorenzo", 1)
     o.block_wise = opts.get("block_wise", 1)
     o.anchor_log2 = opts.get("anchor_log2", 0)
-    B = 1 << o.block_log2
+    return o
+
+
+def _n_blocks(shape, block_log2: int) -> int:
+    B = 1 << block_log2
     nb = 1
-    for n in x.shape:
+    for n in shape:
         nb *= (n + B - 1) // B
-    bc = np.zeros(max(nb, 1), dtype=np.uint8)
-    out = Config()
-    rc = lib().hpez_tune(ctx(x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
-                         C.byref(o), C.byref(c), bc.ctypes.data_as(C.c_void_p), bc.size,
-                         _stream_ptr(stream))
-    _check(rc, "hpez_tune")
+    return nb
+
+
+def _tuned_dict(cfg: dict, c: Config, bc, nb: int) -> dict:
     res = dict(cfg)
     res["predictor"] = "lorenzo" if c.predictor == 1 else "interp"
     res["anchor_log2"] = int(c.anchor_log2)
@@ -291,6 +295,117 @@ def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
     res["levels"] = [interp_dict(c.level[i]) for i in range(16)]
     res["cand"] = [interp_dict(c.cand[i]) for i in range(c.n_cand)]
     res["block_cfg"] = bc[:nb].copy() if c.block_log2 else None
+    return res
+
+
+def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
+    """Run the auto-tuner on a CUDA tensor; returns a complete config dict."""
+    dtype = _dtype_of(x)
+    keep = []
+    d = desc_from(tuple(x.shape), dtype, cfg["eb"], cfg["eb_mode"])
+    c = config_from(cfg, keep)
+    o = _tune_opts(opts)
+    nb = _n_blocks(x.shape, o.block_log2)
+    bc = np.zeros(max(nb, 1), dtype=np.uint8)
+    rc = lib().hpez_tune(ctx(x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
+                         C.byref(o), C.byref(c), bc.ctypes.data_as(C.c_void_p), bc.size,
+                         _stream_ptr(stream))
+    _check(rc, "hpez_tune")
+    return _tuned_dict(cfg, c, bc, nb)
+
+
+def tune_batch(xs, cfgs, opts=None, stream=None) -> list:
+    """Tune many CUDA tensors in one call (trials of all fields in fused
+    launches).  opts: one dict for all fields or a list of dicts."""
+    n = len(xs)
+    if n == 0:
+        return []
+    dev = xs[0].device.index or 0
+    keep = []
+    D = (FieldDesc * n)()
+    Cs = (Config * n)()
+    O = (TuneOpts * n)()
+    ins = (C.c_void_p * n)()
+    bcs, bptr, bcap = [], (C.c_void_p * n)(), (C.c_uint64 * n)()
+    rcs = (C.c_int * n)()
+    nbs = []
+    for i, (x, cfg) in enumerate(zip(xs, cfgs)):
+        if not x.is_cuda or not x.is_contiguous() or (x.device.index or 0) != dev:
+            raise ValueError("fields must be contiguous tensors on one device")
+        D[i] = desc_from(tuple(x.shape), _dtype_of(x), cfg["eb"], cfg["eb_mode"])
+        Cs[i] = config_from(cfg, keep)
+        O[i] = _tune_opts(opts[i] if isinstance(opts, (list, tuple)) else opts)
+        ins[i] = x.data_ptr()
+        nb = _n_blocks(x.shape, O[i].block_log2)
+        nbs.append(nb)
+        bc = np.zeros(max(nb, 1), dtype=np.uint8)
+        bcs.append(bc)
+        bptr[i] = bc.ctypes.data
+        bcap[i] = bc.size
+    rc = lib().hpez_tune_batch(ctx(dev), n, D, ins, O, Cs, bptr, bcap, rcs, _stream_ptr(stream))
+    _check(rc, "hpez_tune_batch")
+    return [_tuned_dict(cfgs[i], Cs[i], bcs[i], nbs[i]) for i in range(n)]
+
+
+def compress_batch(xs, cfgs, stream=None, outs=None) -> list:
+    """Compress many CUDA tensors in one call; returns one uint8 CUDA tensor
+    per field (views of `outs` when given), each byte-identical to compress()."""
+    torch = _torch()
+    n = len(xs)
+    if n == 0:
+        return []
+    dev = xs[0].device.index or 0
+    keep = []
+    D = (FieldDesc * n)()
+    Cs = (Config * n)()
+    ins, optr = (C.c_void_p * n)(), (C.c_void_p * n)()
+    caps, sizes = (C.c_uint64 * n)(), (C.c_uint64 * n)()
+    bufs = []
+    for i, (x, cfg) in enumerate(zip(xs, cfgs)):
+        if not x.is_cuda or not x.is_contiguous() or (x.device.index or 0) != dev:
+            raise ValueError("fields must be contiguous tensors on one device")
+        D[i] = desc_from(tuple(x.shape) if x.dim() else (1,), _dtype_of(x), cfg["eb"],
+                         cfg["eb_mode"])
+        Cs[i] = config_from(cfg, keep)
+        cap = C.c_uint64()
+        _check(lib().hpez_compress_bound(C.byref(D[i]), C.byref(Cs[i]), C.byref(cap)),
+               "hpez_compress_bound")
+        o = outs[i] if outs is not None else torch.empty(cap.value, dtype=torch.uint8,
+                                                          device=x.device)
+        bufs.append(o)
+        ins[i] = x.data_ptr()
+        optr[i] = o.data_ptr()
+        caps[i] = o.numel()
+    rc = lib().hpez_compress_batch(ctx(dev), n, D, ins, Cs, optr, caps, sizes, _stream_ptr(stream))
+    _check(rc, "hpez_compress_batch")
+    return [bufs[i][: sizes[i]] for i in range(n)]
+
+
+def decompress_batch(streams, stream=None, outs=None) -> list:
+    """Decompress many uint8 CUDA tensors (streams) in one call."""
+    torch = _torch()
+    n = len(streams)
+    if n == 0:
+        return []
+    dev = streams[0].device.index or 0
+    # every header in one device-to-host copy
+    heads = torch.stack([torch.nn.functional.pad(s[:512], (0, max(0, 512 - min(512, s.numel()))))
+                         for s in streams]).cpu().numpy()
+    ins, optr = (C.c_void_p * n)(), (C.c_void_p * n)()
+    isz, caps = (C.c_uint64 * n)(), (C.c_uint64 * n)()
+    rcs = (C.c_int * n)()
+    res = []
+    for i, s in enumerate(streams):
+        info = inspect(heads[i].tobytes())
+        dt = torch.float64 if info["dtype"] == "f64" else torch.float32
+        o = outs[i] if outs is not None else torch.empty(info["dims"], dtype=dt, device=s.device)
+        res.append(o)
+        ins[i] = s.data_ptr()
+        isz[i] = s.numel()
+        optr[i] = o.data_ptr()
+        caps[i] = o.numel() * o.element_size()
+    rc = lib().hpez_decompress_batch(ctx(dev), n, ins, isz, optr, caps, rcs, _stream_ptr(stream))
+    _check(rc, "hpez_decompress_batch")
     return res
 
 

@@ -11,7 +11,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "hpez_internal.h"
@@ -646,31 +648,6 @@ struct DevScope {
   }
 };
 
-// Workspace needed by compress/decompress of N points.
-size_t ws_need(uint64_t N, uint64_t s, uint32_t R, uint32_t chunk, uint64_t nb, int op)
-{
-  const uint64_t nch = (N + chunk - 1) / chunk;
-  const uint64_t nsym = 2ull * R;
-  size_t b = 0;
-  auto add = [&](size_t v) { b += (v + 255) & ~(size_t)255; b += 256; };
-  if (op == 0) add(N * s);                 // W
-  add(N * 2);                              // codes
-  add(nsym * 4);                           // histogram
-  add(nsym);                               // lengths
-  add(nsym * 4);                           // codewords
-  add(nch * 4 * 2);                        // chunk bits, chunk zeros
-  add((nch + 1) * 8 * 2);                  // offsets (+ totals)
-  add(((nch + 1023) / 1024 + 1) * 8 * 2);  // scan tiles
-  add(2 * 1024 * 8 + 64);                  // min/max partials
-  add(N * s);                              // anchors staging (bounded by N)
-  add(nb + 16);                            // block configs
-  add(3 * 16 * 4 * 8);                     // MD weights
-  add((1u << kLutBits) * 4 + 4 * 34 * 4 + nsym * 2);  // decode tables
-  add(64);                                 // status
-  add(64);                                 // encoder ticket
-  return b;
-}
-
 // points of the grid of stride s (multiples of s on active dims)
 uint64_t grid_points(const Geom& g, int64_t s)
 {
@@ -802,342 +779,732 @@ Lattice anchor_lattice(const Geom& g, int anchor_log2)
   return make_lattice(g, r, m);
 }
 
-// Block-wise fast path of one field: face phase and per-block interiors.
-// Workspace: block_fast_bytes + block_tables_bound(1) from bw.
+// Block-wise fast path of several fields: face phase and per-block interiors
+// of every job in fused launches.  Tables come from bw (block_tables_bound).
 template <typename T>
-int block_phase(hpez_ctx* ctx, const hpez_config* c, const Geom& g, double e, const T* X,
-                const T* Wg, uint16_t* code, const uint8_t* dbcfg, const double* h_wq,
-                uint32_t* hist, uint32_t lo, T* out, int mode, Bump& bw, hipStream_t st)
+int block_phase(hpez_ctx* ctx, std::vector<BlockJobHost<T>>& jobs, int mode, Bump& bw,
+                hipStream_t st)
 {
-  BlockJobHost<T> J;
-  J.c = c;
-  J.g = g;
-  J.e = e;
-  J.X = X;
-  J.Wg = Wg;
-  J.code = code;
-  J.d_bcfg = dbcfg;
-  J.h_wq = h_wq;
-  J.hist = hist;
-  J.hist_lo = lo;
-  J.area = bw.take<uint8_t>(block_fast_bytes<T>(g));
-  J.out = out;
-  int rc = block_job_prepare<T>(ctx, J);
-  if (rc) return rc;
-  const size_t tb = block_jobs_table_bytes<T>(&J, 1);
-  if (tb > block_tables_bound<T>(1)) return HPEZ_EINVAL;
-  rc = ensure_pin_tab(ctx, tb);
+  if (jobs.empty()) return HPEZ_OK;
+  for (auto& J : jobs) {
+    const int rc = block_job_prepare<T>(ctx, J);
+    if (rc) return rc;
+  }
+  const int n = (int)jobs.size();
+  const size_t tb = block_jobs_table_bytes<T>(jobs.data(), n);
+  if (tb > block_tables_bound<T>(n)) return HPEZ_EINVAL;
+  int rc = ensure_pin_tab(ctx, tb);
   if (rc) return rc;
   void* dt = bw.take<uint8_t>(tb);
-  return run_block_jobs<T>(ctx, &J, 1, mode, dt, ctx->pin_tab, st);
+  return run_block_jobs<T>(ctx, jobs.data(), n, mode, dt, ctx->pin_tab, st);
+}
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Run fn(i) for i in [0, n) on up to 16 host threads (host-only work of
+// independent fields: codebooks, decode tables).
+template <typename F>
+void host_parallel(int n, F fn)
+{
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt > 16) nt = 16;
+  if (n <= 1 || nt <= 1) {
+    for (int i = 0; i < n; i++) fn(i);
+    return;
+  }
+  if ((int)nt > n) nt = (unsigned)n;
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; t++)
+    th.emplace_back([&]() {
+      for (int i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+// ---------------------------------------------------------------------------
+// Compression of one field as a job in phases (Sec. 4): error bound; anchors
+// and levels with quantization; histogram; codebook; stream assembly and
+// encode.  The plain call runs one job, the batch call many with one stream
+// synchronization per phase for all of them and the block phase of every
+// block-wise field in fused launches.  Each field takes the same steps either
+// way, so its stream is the same.
+template <typename T>
+struct CJob {
+  const hpez_field_desc* d = nullptr;
+  const T* X = nullptr;
+  const hpez_config* c = nullptr;
+  uint8_t* out = nullptr;
+  uint64_t cap = 0;
+  int rc = HPEZ_OK;
+  int kind = 0;  // 0 interpolation, 1 constant field (written), 2 Lorenzo (run after the rest)
+  uint64_t N = 0, nb = 0, nch = 0;
+  uint32_t nsym = 0;
+  Geom g;
+  Layout Lo;
+  bool fast = false;
+  uint32_t lo = 0;
+  double h_wq[3 * 16 * 4];
+  std::vector<uint32_t> cw;
+  // device workspace
+  T* W = nullptr;
+  uint16_t* code = nullptr;
+  uint32_t* hist = nullptr;
+  uint8_t* dlen = nullptr;
+  uint32_t* dcw = nullptr;
+  uint32_t* czero = nullptr;
+  uint64_t* boff = nullptr;
+  uint64_t* zoff = nullptr;
+  uint64_t* tmp2 = nullptr;
+  double* part = nullptr;
+  double* mm = nullptr;
+  int* bad = nullptr;
+  T* anc = nullptr;
+  uint8_t* dbcfg = nullptr;
+  double* dwq = nullptr;
+  uint32_t* ticket = nullptr;
+  void* area = nullptr;
+  // pinned host staging
+  uint32_t* h_hist = nullptr;
+  uint8_t* h_len = nullptr;
+  uint8_t* h_hdr = nullptr;
+  double* h_mm = nullptr;
+  int* h_bad = nullptr;
+  uint32_t* h_tab = nullptr;
+};
+
+constexpr int kMinmaxBlocks = 1024;
+
+template <typename T>
+void c_init(CJob<T>& J)
+{
+  J.N = points_of(J.d);
+  J.nsym = 2 * J.c->radius;
+  J.nb = n_blocks(J.d, J.c);
+  J.g = make_geom(J.d, J.c->frozen_dim);
+  J.nch = (J.N + J.c->chunk - 1) / J.c->chunk;
+  J.fast = J.c->predictor == HPEZ_INTERP && block_fast_ok<T>(J.c, J.g);
+  std::memset(&J.Lo, 0, sizeof J.Lo);
 }
 
 template <typename T>
-int compress_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_config* c,
-               uint8_t* out, uint64_t cap, uint64_t* out_size, hipStream_t st)
+size_t c_dev_bytes(const CJob<T>& J)
 {
-  const uint64_t N = points_of(d);
   const uint64_t s = sizeof(T);
-  const uint32_t nsym = 2 * c->radius;
-  const uint64_t nb = n_blocks(d, c);
-  const Geom g = make_geom(d, c->frozen_dim);
-  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 0) + block_fast_bytes<T>(g) +
-                             block_tables_bound<T>(1) + 512);
-  if (rc) return rc;
-  const size_t pin_need = (size_t)nsym * 4 + nsym + kHdrBytes + nb + 4096 + (size_t)nsym * 4;
-  rc = ensure_pinned(ctx, pin_need);
-  if (rc) return rc;
-  Bump bw{(uint8_t*)ctx->ws};
-  T* W = bw.take<T>(N);
-  uint16_t* code = bw.take<uint16_t>(N);
-  uint32_t* hist = bw.take<uint32_t>(nsym);
-  uint8_t* dlen = bw.take<uint8_t>(nsym);
-  uint32_t* dcw = bw.take<uint32_t>(nsym);
-  const uint64_t nch = (N + c->chunk - 1) / c->chunk;
-  uint32_t* cbits = bw.take<uint32_t>(nch + 1);
-  uint32_t* czero = bw.take<uint32_t>(nch + 1);
-  uint64_t* boff = bw.take<uint64_t>(nch + 1);
-  uint64_t* zoff = bw.take<uint64_t>(nch + 1);
-  uint64_t* tmp1 = bw.take<uint64_t>((nch + 1023) / 1024 + 1);
-  uint64_t* tmp2 = bw.take<uint64_t>((nch + 1023) / 1024 + 1);
-  double* part = bw.take<double>(2 * 1024);
-  double* mm = bw.take<double>(4);
-  int* bad = bw.take<int>(4);
-  T* anc = bw.take<T>(N);
-  uint8_t* dbcfg = bw.take<uint8_t>(nb + 16);
-  double* dwq = bw.take<double>(3 * 16 * 4);
-  uint32_t* ticket = bw.take<uint32_t>(16);
+  size_t b = al256(J.N * s) + al256(J.N * 2) + al256(J.nsym * 4) + al256(J.nsym) +
+             al256(J.nsym * 4) + al256((J.nch + 1) * 4) + 3 * al256((J.nch + 1) * 8) +
+             al256(2 * kMinmaxBlocks * 8) + al256(32) + al256(16) + al256(J.N * s) +
+             al256(J.nb + 16) + al256(3 * 16 * 4 * 8) + al256(64);
+  if (J.fast) b += al256(block_fast_bytes<T>(J.g));
+  return b + 256;
+}
 
-  uint8_t* pin = ctx->pinned;
-  uint32_t* h_hist = (uint32_t*)pin;
-  uint8_t* h_len = pin + (size_t)nsym * 4;
-  uint8_t* h_hdr = h_len + nsym;
-  double* h_mm = (double*)(h_hdr + kHdrBytes);
-  int* h_bad = (int*)(h_mm + 2);
-  uint32_t* h_tab = (uint32_t*)(pin + (((size_t)nsym * 5 + kHdrBytes + 64 + 63) & ~(size_t)63));
+template <typename T>
+size_t c_pin_bytes(const CJob<T>& J)
+{
+  return al256(J.nsym * 4) + al256(J.nsym) + al256(kHdrBytes) + al256(64) + al256(J.nsym * 4) + 256;
+}
 
-  // --- error bound (Sec. 7.1.3) and the non-finite check
-  const int mblocks = 1024;
-  HIPCK(hipMemsetAsync(bad, 0, sizeof(int), st));
+template <typename T>
+void c_take(CJob<T>& J, Bump& bw, Bump& pb)
+{
+  J.W = bw.take<T>(J.N);
+  J.code = bw.take<uint16_t>(J.N);
+  J.hist = bw.take<uint32_t>(J.nsym);
+  J.dlen = bw.take<uint8_t>(J.nsym);
+  J.dcw = bw.take<uint32_t>(J.nsym);
+  J.czero = bw.take<uint32_t>(J.nch + 1);
+  J.boff = bw.take<uint64_t>(J.nch + 1);
+  J.zoff = bw.take<uint64_t>(J.nch + 1);
+  J.tmp2 = bw.take<uint64_t>(J.nch + 1);
+  J.part = bw.take<double>(2 * kMinmaxBlocks);
+  J.mm = bw.take<double>(4);
+  J.bad = bw.take<int>(4);
+  J.anc = bw.take<T>(J.N);
+  J.dbcfg = bw.take<uint8_t>(J.nb + 16);
+  J.dwq = bw.take<double>(3 * 16 * 4);
+  J.ticket = bw.take<uint32_t>(16);
+  if (J.fast) J.area = bw.take<uint8_t>(block_fast_bytes<T>(J.g));
+  J.h_hist = pb.take<uint32_t>(J.nsym);
+  J.h_len = pb.take<uint8_t>(J.nsym);
+  J.h_hdr = pb.take<uint8_t>(kHdrBytes);
+  J.h_mm = pb.take<double>(2);
+  J.h_bad = (int*)(J.h_mm + 2);
+  J.h_tab = pb.take<uint32_t>(J.nsym);
+}
+
+// error bound (Sec. 7.1.3) and the non-finite check
+template <typename T>
+int c_minmax(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
+{
+  HIPCK(hipMemsetAsync(J.bad, 0, sizeof(int), st));
   {
-    Span sp(ctx, "minmax", N * s, st);
-    HIPCK(launch_minmax<T>(X, N, part, bad, mblocks, st));
-    HIPCK(launch_minmax_final(part, mblocks, mm, st));
+    Span sp(ctx, "minmax", J.N * sizeof(T), st);
+    HIPCK(launch_minmax<T>(J.X, J.N, J.part, J.bad, kMinmaxBlocks, st));
+    HIPCK(launch_minmax_final(J.part, kMinmaxBlocks, J.mm, st));
   }
-  HIPCK(hipMemcpyAsync(h_mm, mm, 16, hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(h_bad, bad, 4, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  if (*h_bad) return HPEZ_EINVAL;
-  double e;
-  Layout Lo;
-  std::memset(&Lo, 0, sizeof Lo);
-  Lo.n_blocks = nb;
+  HIPCK(hipMemcpyAsync(J.h_mm, J.mm, 16, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(J.h_bad, J.bad, 4, hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
+
+// after the minmax sync: e, then the predictor up to the block phase
+template <typename T>
+int c_predict(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
+{
+  const hpez_field_desc* d = J.d;
+  const hpez_config* c = J.c;
+  const uint64_t s = sizeof(T);
+  if (*J.h_bad) {
+    J.rc = HPEZ_EINVAL;
+    return HPEZ_OK;
+  }
+  Layout& Lo = J.Lo;
+  Lo.n_blocks = J.nb;
   Lo.sym_min = 1;
   Lo.sym_max = 0;
+  double e;
   if (d->eb_mode == HPEZ_REL) {
-    const double range = h_mm[1] - h_mm[0];
+    const double range = J.h_mm[1] - J.h_mm[0];
     if (range == 0) {
       // constant field: one value
+      J.kind = 1;
       Lo.predictor = 2;
       Lo.n_anchor = 1;
       Lo.e = 0;
       layout(&Lo, s);
-      if (Lo.total > cap) return HPEZ_ENOSPC;
-      write_header(h_hdr, d, c, Lo);
-      HIPCK(hipMemsetAsync(out, 0, Lo.total, st));
-      HIPCK(hipMemcpyAsync(out, h_hdr, kHdrBytes, hipMemcpyHostToDevice, st));
-      if (nb) HIPCK(hipMemcpyAsync(out + Lo.off_blocks, c->block_cfg, nb, hipMemcpyHostToDevice, st));
-      HIPCK(hipMemcpyAsync(out + Lo.off_anchor, X, s, hipMemcpyDeviceToDevice, st));
-      HIPCK(hipStreamSynchronize(st));
-      *out_size = Lo.total;
+      if (Lo.total > J.cap) {
+        J.rc = HPEZ_ENOSPC;
+        return HPEZ_OK;
+      }
+      write_header(J.h_hdr, d, c, Lo);
+      HIPCK(hipMemsetAsync(J.out, 0, Lo.total, st));
+      HIPCK(hipMemcpyAsync(J.out, J.h_hdr, kHdrBytes, hipMemcpyHostToDevice, st));
+      if (J.nb)
+        HIPCK(hipMemcpyAsync(J.out + Lo.off_blocks, c->block_cfg, J.nb, hipMemcpyHostToDevice, st));
+      HIPCK(hipMemcpyAsync(J.out + Lo.off_anchor, J.X, s, hipMemcpyDeviceToDevice, st));
       return HPEZ_OK;
     }
     e = d->eb * range;
   } else {
     e = d->eb;
   }
-  if (!(e > 0)) return HPEZ_EINVAL;
+  if (!(e > 0)) {
+    J.rc = HPEZ_EINVAL;
+    return HPEZ_OK;
+  }
   Lo.e = e;
   Lo.predictor = c->predictor;
-  if (c->predictor == HPEZ_LORENZO)
-    return lorenzo_compress<T>(ctx, d, X, c, e, out, cap, out_size, st);
-
-  // --- interpolation predictor + quantization (Sec. 5, Sec. 4 step 3)
-  double h_wq[3 * 16 * 4];
-  md_table(c, h_wq);
-  HIPCK(hipMemcpyAsync(dwq, h_wq, sizeof h_wq, hipMemcpyHostToDevice, st));
-  if (nb) HIPCK(hipMemcpyAsync(dbcfg, c->block_cfg, nb, hipMemcpyHostToDevice, st));
-  const Lattice al = anchor_lattice(g, c->anchor_log2);
+  if (c->predictor == HPEZ_LORENZO) {
+    J.kind = 2;
+    return HPEZ_OK;
+  }
+  // interpolation predictor + quantization (Sec. 5, Sec. 4 step 3)
+  md_table(c, J.h_wq);
+  HIPCK(hipMemcpyAsync(J.dwq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
+  if (J.nb) HIPCK(hipMemcpyAsync(J.dbcfg, c->block_cfg, J.nb, hipMemcpyHostToDevice, st));
+  const Lattice al = anchor_lattice(J.g, c->anchor_log2);
   Lo.n_anchor = al.total;
-  HIPCK(launch_anchors<T>(g, al, X, W, code, anc, c->radius, 0, st));
-  const bool fast = block_fast_ok<T>(c, g);
-  rc = run_levels<T>(ctx, d, c, g, e, X, W, code, dbcfg, dwq, h_wq, 0, st,
-                     fast ? c->block_log2 : 0);
+  HIPCK(launch_anchors<T>(J.g, al, J.X, J.W, J.code, J.anc, c->radius, 0, st));
+  const int rc = run_levels<T>(ctx, d, c, J.g, e, J.X, J.W, J.code, J.dbcfg, J.dwq, J.h_wq, 0, st,
+                               J.fast ? c->block_log2 : 0);
   if (rc) return rc;
-  HIPCK(hipMemsetAsync(hist, 0, (size_t)nsym * 4, st));
-  if (fast) {
+  HIPCK(hipMemsetAsync(J.hist, 0, (size_t)J.nsym * 4, st));
+  if (J.fast) {
     // faces, then block interiors with the brick histogram fused in
     uint32_t lo = c->radius > kBlockHistWin / 2 ? c->radius - kBlockHistWin / 2 : 0;
-    if (lo + kBlockHistWin > nsym) lo = nsym > (uint32_t)kBlockHistWin ? nsym - kBlockHistWin : 0;
-    rc = block_phase<T>(ctx, c, g, e, X, W, code, dbcfg, h_wq, hist, lo, nullptr, 0, bw, st);
-    if (rc) return rc;
+    if (lo + kBlockHistWin > J.nsym)
+      lo = J.nsym > (uint32_t)kBlockHistWin ? J.nsym - kBlockHistWin : 0;
+    J.lo = lo;
+  } else {
+    Span sp(ctx, "histogram", J.N * 2, st);
+    HIPCK(launch_histogram(J.code, J.N, J.hist, J.nsym, c->radius, st));
   }
-
-  // --- histogram and codebook (Sec. 4 step 4)
-  if (!fast) {
-    Span sp(ctx, "histogram", N * 2, st);
-    HIPCK(launch_histogram(code, N, hist, nsym, c->radius, st));
-  }
-  HIPCK(hipMemcpyAsync(h_hist, hist, (size_t)nsym * 4, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  rc = huffman_lengths(h_hist, nsym, h_len);
-  if (rc) return rc;
-  std::vector<uint32_t> cw(nsym);
-  canonical_codes(h_len, nsym, cw.data());
-  uint64_t bits = 0;
-  for (uint32_t k = 0; k < nsym; k++) bits += (uint64_t)h_hist[k] * h_len[k];
-  for (uint32_t k = 0; k < nsym; k++)
-    if (h_len[k]) { Lo.sym_min = k; break; }
-  for (uint32_t k = nsym; k-- > 0;)
-    if (h_len[k]) { Lo.sym_max = k; break; }
-  Lo.n_unpred = h_hist[0];
-  Lo.n_chunks = nch;
-  Lo.payload_bits = bits;
-  layout(&Lo, s);
-  if (Lo.total > cap) return HPEZ_ENOSPC;
-  write_header(h_hdr, d, c, Lo);
-  HIPCK(hipMemcpyAsync(dlen, h_len, nsym, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(dcw, cw.data(), (size_t)nsym * 4, hipMemcpyHostToDevice, st));
-
-  // --- assemble the stream
-  HIPCK(hipMemsetAsync(out, 0, Lo.total, st));
-  HIPCK(hipMemcpyAsync(out, h_hdr, kHdrBytes, hipMemcpyHostToDevice, st));
-  if (nb) HIPCK(hipMemcpyAsync(out + Lo.off_blocks, c->block_cfg, nb, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(out + Lo.off_anchor, anc, Lo.n_anchor * s, hipMemcpyDeviceToDevice, st));
-  if (Lo.sym_max >= Lo.sym_min)
-    HIPCK(hipMemcpyAsync(out + Lo.off_len, h_len + Lo.sym_min, Lo.sym_max - Lo.sym_min + 1,
-                         hipMemcpyHostToDevice, st));
-  if (Lo.n_unpred) {
-    // verbatim values in stream order (Sec. 4: unpredictable points)
-    Span sp(ctx, "gather_unpred", N * 2 + Lo.n_unpred * s * 2, st);
-    HIPCK(launch_gather_unpred<T>(code, N, c->chunk, czero, zoff, tmp2, X,
-                                  (T*)(out + Lo.off_unpred), g, st));
-  }
-  rc = encode_payload(ctx, code, N, c->chunk, h_len, cw.data(), Lo.sym_min, Lo.sym_max, dlen, dcw,
-                      hist, boff, ticket, h_tab, (uint32_t*)(out + Lo.off_payload),
-                      (uint16_t*)(out + Lo.off_chunks), st);
-  if (rc) return rc;
-  HIPCK(hipStreamSynchronize(st));
-  prof_collect(ctx);
-  *out_size = Lo.total;
   return HPEZ_OK;
 }
 
 template <typename T>
-int decompress_t(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, const Layout& Lo,
-                 const uint8_t* in, T* out, hipStream_t st)
+BlockJobHost<T> c_block_job(const CJob<T>& J)
 {
-  const uint64_t N = points_of(d);
+  BlockJobHost<T> B;
+  B.c = J.c;
+  B.g = J.g;
+  B.e = J.Lo.e;
+  B.X = J.X;
+  B.Wg = J.W;
+  B.code = J.code;
+  B.d_bcfg = J.dbcfg;
+  B.h_wq = J.h_wq;
+  B.hist = J.hist;
+  B.hist_lo = J.lo;
+  B.area = J.area;
+  B.out = nullptr;
+  return B;
+}
+
+// histogram and codebook (Sec. 4 step 4), on the host after the histogram sync
+template <typename T>
+void c_codebook(CJob<T>& J)
+{
+  const uint32_t nsym = J.nsym;
+  Layout& Lo = J.Lo;
+  int rc = huffman_lengths(J.h_hist, nsym, J.h_len);
+  if (rc) {
+    J.rc = rc;
+    return;
+  }
+  J.cw.resize(nsym);
+  canonical_codes(J.h_len, nsym, J.cw.data());
+  uint64_t bits = 0;
+  for (uint32_t k = 0; k < nsym; k++) bits += (uint64_t)J.h_hist[k] * J.h_len[k];
+  for (uint32_t k = 0; k < nsym; k++)
+    if (J.h_len[k]) { Lo.sym_min = k; break; }
+  for (uint32_t k = nsym; k-- > 0;)
+    if (J.h_len[k]) { Lo.sym_max = k; break; }
+  Lo.n_unpred = J.h_hist[0];
+  Lo.n_chunks = J.nch;
+  Lo.payload_bits = bits;
+  layout(&Lo, sizeof(T));
+  if (Lo.total > J.cap) {
+    J.rc = HPEZ_ENOSPC;
+    return;
+  }
+  write_header(J.h_hdr, J.d, J.c, Lo);
+}
+
+// assemble the stream
+template <typename T>
+int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
+{
+  const Layout& Lo = J.Lo;
+  const hpez_config* c = J.c;
   const uint64_t s = sizeof(T);
-  const uint32_t nsym = 2 * c->radius;
-  const uint64_t nb = Lo.n_blocks;
-  const Geom g = make_geom(d, c->frozen_dim);
-  int rc = ensure_ws(ctx, ws_need(N, s, c->radius, c->chunk, nb, 1) +
-                              (Lo.predictor == 1 ? N * 8 + 256 : 0) + block_fast_bytes<T>(g) +
-                              block_tables_bound<T>(1) + 512);
+  uint8_t* out = J.out;
+  HIPCK(hipMemcpyAsync(J.dlen, J.h_len, J.nsym, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(J.dcw, J.cw.data(), (size_t)J.nsym * 4, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemsetAsync(out, 0, Lo.total, st));
+  HIPCK(hipMemcpyAsync(out, J.h_hdr, kHdrBytes, hipMemcpyHostToDevice, st));
+  if (J.nb)
+    HIPCK(hipMemcpyAsync(out + Lo.off_blocks, c->block_cfg, J.nb, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(out + Lo.off_anchor, J.anc, Lo.n_anchor * s, hipMemcpyDeviceToDevice, st));
+  if (Lo.sym_max >= Lo.sym_min)
+    HIPCK(hipMemcpyAsync(out + Lo.off_len, J.h_len + Lo.sym_min, Lo.sym_max - Lo.sym_min + 1,
+                         hipMemcpyHostToDevice, st));
+  if (Lo.n_unpred) {
+    // verbatim values in stream order (Sec. 4: unpredictable points)
+    Span sp(ctx, "gather_unpred", J.N * 2 + Lo.n_unpred * s * 2, st);
+    HIPCK(launch_gather_unpred<T>(J.code, J.N, c->chunk, J.czero, J.zoff, J.tmp2, J.X,
+                                  (T*)(out + Lo.off_unpred), J.g, st));
+  }
+  return encode_payload(ctx, J.code, J.N, c->chunk, J.h_len, J.cw.data(), Lo.sym_min, Lo.sym_max,
+                        J.dlen, J.dcw, J.hist, J.boff, J.ticket, J.h_tab,
+                        (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), st);
+}
+
+// Compress jobs [0, n) of one dtype.  A job's own failure (non-finite input,
+// ENOSPC, ...) stays in its rc; device errors end the whole call.
+template <typename T>
+int compress_jobs(hpez_ctx* ctx, std::vector<CJob<T>>& jobs, hipStream_t st)
+{
+  const int n = (int)jobs.size();
+  if (!n) return HPEZ_OK;
+  size_t dev = 0, pin = 0;
+  int nfast = 0;
+  for (auto& J : jobs) {
+    c_init(J);
+    dev += c_dev_bytes(J);
+    pin += c_pin_bytes(J);
+    nfast += J.fast;
+  }
+  dev += al256(block_tables_bound<T>(nfast > 0 ? nfast : 1)) + 256;
+  int rc = ensure_ws(ctx, dev);
   if (rc) return rc;
-  rc = ensure_pinned(ctx, (size_t)nsym + 4096 + nb + 64);
+  rc = ensure_pinned(ctx, pin);
   if (rc) return rc;
   Bump bw{(uint8_t*)ctx->ws};
-  uint16_t* code = bw.take<uint16_t>(N);
-  const uint64_t nch = Lo.n_chunks;
-  uint32_t* cbits = bw.take<uint32_t>(nch + 1);
-  uint32_t* czero = bw.take<uint32_t>(nch + 1);
-  uint64_t* boff = bw.take<uint64_t>(nch + 1);
-  uint64_t* zoff = bw.take<uint64_t>(nch + 1);
-  uint64_t* tmp1 = bw.take<uint64_t>((nch + 1023) / 1024 + 1);
-  uint64_t* tmp2 = bw.take<uint64_t>((nch + 1023) / 1024 + 1);
-  double* dwq = bw.take<double>(3 * 16 * 4);
-  uint32_t* dlut = bw.take<uint32_t>(1u << kLutBits);
-  uint16_t* dsorted = bw.take<uint16_t>(nsym);
-  int* status = bw.take<int>(4);
-  uint8_t* pin = ctx->pinned;
-  uint8_t* h_len = pin;
-  uint8_t* h_bcfg = pin + nsym;
-  int* h_status = (int*)(pin + nsym + ((nb + 63) & ~63ull));
+  Bump pb{ctx->pinned};
+  for (auto& J : jobs) c_take(J, bw, pb);
 
-  if (Lo.predictor == 2) {
-    // constant field
-    HIPCK(hipMemcpyAsync(out, in + Lo.off_anchor, s, hipMemcpyDeviceToDevice, st));
-    // broadcast by doubling copies
-    uint64_t have = 1;
-    while (have < N) {
-      const uint64_t m = have < N - have ? have : N - have;
-      HIPCK(hipMemcpyAsync(out + have, out, m * s, hipMemcpyDeviceToDevice, st));
-      have += m;
-    }
-    HIPCK(hipStreamSynchronize(st));
-    return HPEZ_OK;
-  }
-  // code lengths and block configurations to the host
-  std::memset(h_len, 0, nsym);
-  if (Lo.sym_max >= Lo.sym_min)
-    HIPCK(hipMemcpyAsync(h_len + Lo.sym_min, in + Lo.off_len, Lo.sym_max - Lo.sym_min + 1,
-                         hipMemcpyDeviceToHost, st));
-  if (nb) HIPCK(hipMemcpyAsync(h_bcfg, in + Lo.off_blocks, nb, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  for (uint64_t b = 0; b < nb; b++)
-    if (h_bcfg[b] >= c->n_cand) return HPEZ_ECORRUPT;
-  uint64_t kraft = 0, used = 0;
-  for (uint32_t k = 0; k < nsym; k++) {
-    if (h_len[k] > kLmax) return HPEZ_ECORRUPT;
-    if (h_len[k]) {
-      kraft += 1ull << (kLmax - h_len[k]);
-      used++;
-    }
-  }
-  if (N > 0 && !(kraft == (1ull << kLmax) || (used == 1 && kraft == (1ull << (kLmax - 1)))))
-    return HPEZ_ECORRUPT;
-  std::vector<uint32_t> lut(1u << kLutBits);
-  std::vector<uint16_t> sorted(nsym);
-  DecodeArgs da;
-  std::memset(&da, 0, sizeof da);
-  da.n = N;
-  da.nch = nch;
-  da.nbits = Lo.payload_bits;
-  da.chunk = c->chunk;
-  decode_tables(h_len, nsym, lut.data(), sorted.data(), da.lim, da.base);
-  {
-    uint32_t nshort = 0, nused = 0;
-    for (uint32_t k = 0; k < nsym; k++) {
-      nused += h_len[k] != 0;
-      nshort += h_len[k] != 0 && h_len[k] <= kLutBits;
-    }
-    da.long_first = nshort;
-    da.n_long = nused - nshort;
-  }
-  HIPCK(hipMemcpyAsync(dlut, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(dsorted, sorted.data(), sorted.size() * 2, hipMemcpyHostToDevice, st));
-  double h_wq[3 * 16 * 4];
-  md_table(c, h_wq);
-  HIPCK(hipMemcpyAsync(dwq, h_wq, sizeof h_wq, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemsetAsync(status, 0, sizeof(int), st));
-  // chunk offsets, decode
-  {
-    Span sp(ctx, "decode_offsets", nch * 2, st);
-    HIPCK(launch_u16_to_u32((const uint16_t*)(in + Lo.off_chunks), nch, cbits, st));
-    HIPCK(launch_scan_u32_to_u64(cbits, nch, boff, boff + nch, tmp1, st));
-  }
-  {
-    Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
-    HIPCK(launch_decode2(da, (const uint32_t*)(in + Lo.off_payload), boff, dlut, dsorted, code,
-                         czero, status, st));
-  }
-  HIPCK(launch_scan_u32_to_u64(czero, nch, zoff, zoff + nch, tmp2, st));
-  uint64_t h_tot[2];
-  if (Lo.predictor == 1) {
-    // Lorenzo alternative: residuals, running sums, patches
-    long long* v = bw.take<long long>(N);
-    const Geom gl = make_geom(d, -1);
-    {
-      Span sp(ctx, "lorenzo_rebuild", N * (2 + s), st);
-      HIPCK(launch_lorenzo_rebuild<T>(code, gl, N, c->radius, c->chunk, czero, zoff,
-                                      (const long long*)(in + Lo.off_outl), Lo.n_outlier,
-                                      (const uint64_t*)(in + Lo.off_pidx),
-                                      (const T*)(in + Lo.off_pval), Lo.n_patch, 2.0 * Lo.e, v, out,
-                                      status, st));
-    }
-    HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCK(hipMemcpyAsync(&h_tot[0], zoff + nch, 8, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    prof_collect(ctx);
-    if (*h_status || h_tot[0] != Lo.n_outlier) return HPEZ_ECORRUPT;
-    return HPEZ_OK;
-  }
-  if (Lo.n_unpred)
-    HIPCK(launch_scatter_unpred2<T>(code, N, c->chunk, czero, zoff, (const T*)(in + Lo.off_unpred),
-                                    Lo.n_unpred, out, status, g, st));
-  const Lattice al = anchor_lattice(g, c->anchor_log2);
-  if (al.total != Lo.n_anchor) return HPEZ_ECORRUPT;
-  HIPCK(launch_anchors<T>(g, al, nullptr, out, code, (T*)(in + Lo.off_anchor), c->radius, 1, st));
-  const bool fast = block_fast_ok<T>(c, g);
-  rc = run_levels<T>(ctx, d, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, dwq, h_wq, 1, st,
-                     fast ? c->block_log2 : 0);
-  if (rc) return rc;
-  if (fast) {
-    rc = block_phase<T>(ctx, c, g, Lo.e, nullptr, out, code, in + Lo.off_blocks, h_wq, nullptr, 0,
-                        out, 1, bw, st);
+  for (auto& J : jobs) {
+    rc = c_minmax(ctx, J, st);
     if (rc) return rc;
   }
-  HIPCK(hipMemcpyAsync(h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(&h_tot[0], zoff + nch, 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  std::vector<BlockJobHost<T>> bj;
+  for (auto& J : jobs) {
+    rc = c_predict(ctx, J, st);
+    if (rc) return rc;
+    if (!J.rc && !J.kind && J.fast) bj.push_back(c_block_job(J));
+  }
+  rc = block_phase<T>(ctx, bj, 0, bw, st);
+  if (rc) return rc;
+  for (auto& J : jobs)
+    if (!J.rc && !J.kind)
+      HIPCK(hipMemcpyAsync(J.h_hist, J.hist, (size_t)J.nsym * 4, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  host_parallel(n, [&](int i) {
+    if (!jobs[i].rc && !jobs[i].kind) c_codebook(jobs[i]);
+  });
+  for (auto& J : jobs) {
+    if (J.rc || J.kind) continue;
+    rc = c_encode(ctx, J, st);
+    if (rc) return rc;
+  }
   HIPCK(hipStreamSynchronize(st));
   prof_collect(ctx);
-  if (*h_status) return HPEZ_ECORRUPT;
-  if (h_tot[0] != Lo.n_unpred) return HPEZ_ECORRUPT;
+  // the Lorenzo alternative (Sec. 6.5) runs per field after the rest
+  for (auto& J : jobs) {
+    if (J.rc || J.kind != 2) continue;
+    uint64_t sz = 0;
+    J.rc = lorenzo_compress<T>(ctx, J.d, J.X, J.c, J.Lo.e, J.out, J.cap, &sz, st);
+    if (J.rc == HPEZ_EDEVICE) return J.rc;
+    J.Lo.total = sz;
+  }
   return HPEZ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Decompression of one stream as a job in phases: header; code lengths and
+// block configurations; decode, verbatim values, anchors, levels; status.
+template <typename T>
+struct DJob {
+  const uint8_t* in = nullptr;
+  T* out = nullptr;
+  hpez_field_desc d;
+  hpez_config c;
+  Layout Lo;
+  int rc = HPEZ_OK;
+  uint64_t N = 0, nb = 0, nch = 0;
+  uint32_t nsym = 0;
+  Geom g;
+  bool fast = false;
+  double h_wq[3 * 16 * 4];
+  DecodeArgs da;
+  std::vector<uint32_t> lut;
+  std::vector<uint16_t> sorted;
+  // device workspace
+  uint16_t* code = nullptr;
+  uint32_t* cbits = nullptr;
+  uint32_t* czero = nullptr;
+  uint64_t* boff = nullptr;
+  uint64_t* zoff = nullptr;
+  uint64_t* tmp1 = nullptr;
+  uint64_t* tmp2 = nullptr;
+  double* dwq = nullptr;
+  uint32_t* dlut = nullptr;
+  uint16_t* dsorted = nullptr;
+  int* status = nullptr;
+  long long* lv = nullptr;
+  void* area = nullptr;
+  // pinned host staging
+  uint8_t* h_len = nullptr;
+  uint8_t* h_bcfg = nullptr;
+  int* h_status = nullptr;
+  uint64_t* h_tot = nullptr;
+};
+
+template <typename T>
+void d_init(DJob<T>& J)
+{
+  J.N = points_of(&J.d);
+  J.nsym = 2 * J.c.radius;
+  J.nb = J.Lo.n_blocks;
+  J.nch = J.Lo.n_chunks;
+  J.g = make_geom(&J.d, J.c.frozen_dim);
+  J.fast = J.Lo.predictor == HPEZ_INTERP && block_fast_ok<T>(&J.c, J.g);
+}
+
+template <typename T>
+size_t d_dev_bytes(const DJob<T>& J)
+{
+  size_t b = al256(J.N * 2) + 2 * al256((J.nch + 1) * 4) + 4 * al256((J.nch + 1) * 8) +
+             al256(3 * 16 * 4 * 8) + al256((size_t)4 << kLutBits) + al256(J.nsym * 2) + al256(16);
+  if (J.Lo.predictor == 1) b += al256(J.N * 8);
+  if (J.fast) b += al256(block_fast_bytes<T>(J.g));
+  return b + 256;
+}
+
+template <typename T>
+size_t d_pin_bytes(const DJob<T>& J)
+{
+  return al256(J.nsym) + al256(J.nb) + al256(16) + al256(16) + 256;
+}
+
+template <typename T>
+void d_take(DJob<T>& J, Bump& bw, Bump& pb)
+{
+  J.code = bw.take<uint16_t>(J.N);
+  J.cbits = bw.take<uint32_t>(J.nch + 1);
+  J.czero = bw.take<uint32_t>(J.nch + 1);
+  J.boff = bw.take<uint64_t>(J.nch + 1);
+  J.zoff = bw.take<uint64_t>(J.nch + 1);
+  J.tmp1 = bw.take<uint64_t>(J.nch + 1);
+  J.tmp2 = bw.take<uint64_t>(J.nch + 1);
+  J.dwq = bw.take<double>(3 * 16 * 4);
+  J.dlut = bw.take<uint32_t>(1u << kLutBits);
+  J.dsorted = bw.take<uint16_t>(J.nsym);
+  J.status = bw.take<int>(4);
+  if (J.Lo.predictor == 1) J.lv = bw.take<long long>(J.N);
+  if (J.fast) J.area = bw.take<uint8_t>(block_fast_bytes<T>(J.g));
+  J.h_len = pb.take<uint8_t>(J.nsym);
+  J.h_bcfg = pb.take<uint8_t>(J.nb);
+  J.h_status = pb.take<int>(4);
+  J.h_tot = pb.take<uint64_t>(2);
+}
+
+// constant field, or the copies of code lengths and block configurations
+template <typename T>
+int d_fetch(DJob<T>& J, hipStream_t st)
+{
+  const Layout& Lo = J.Lo;
+  const uint64_t s = sizeof(T);
+  if (Lo.predictor == 2) {
+    // constant field: broadcast by doubling copies
+    HIPCK(hipMemcpyAsync(J.out, J.in + Lo.off_anchor, s, hipMemcpyDeviceToDevice, st));
+    uint64_t have = 1;
+    while (have < J.N) {
+      const uint64_t m = have < J.N - have ? have : J.N - have;
+      HIPCK(hipMemcpyAsync(J.out + have, J.out, m * s, hipMemcpyDeviceToDevice, st));
+      have += m;
+    }
+    return HPEZ_OK;
+  }
+  std::memset(J.h_len, 0, J.nsym);
+  if (Lo.sym_max >= Lo.sym_min)
+    HIPCK(hipMemcpyAsync(J.h_len + Lo.sym_min, J.in + Lo.off_len, Lo.sym_max - Lo.sym_min + 1,
+                         hipMemcpyDeviceToHost, st));
+  if (J.nb) HIPCK(hipMemcpyAsync(J.h_bcfg, J.in + Lo.off_blocks, J.nb, hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
+
+// host: validate lengths and block configurations, build the decode tables
+template <typename T>
+void d_tables(DJob<T>& J)
+{
+  const uint32_t nsym = J.nsym;
+  for (uint64_t b = 0; b < J.nb; b++)
+    if (J.h_bcfg[b] >= J.c.n_cand) {
+      J.rc = HPEZ_ECORRUPT;
+      return;
+    }
+  uint64_t kraft = 0, used = 0;
+  for (uint32_t k = 0; k < nsym; k++) {
+    if (J.h_len[k] > kLmax) {
+      J.rc = HPEZ_ECORRUPT;
+      return;
+    }
+    if (J.h_len[k]) {
+      kraft += 1ull << (kLmax - J.h_len[k]);
+      used++;
+    }
+  }
+  if (J.N > 0 && !(kraft == (1ull << kLmax) || (used == 1 && kraft == (1ull << (kLmax - 1))))) {
+    J.rc = HPEZ_ECORRUPT;
+    return;
+  }
+  J.lut.resize(1u << kLutBits);
+  J.sorted.resize(nsym);
+  DecodeArgs& da = J.da;
+  std::memset(&da, 0, sizeof da);
+  da.n = J.N;
+  da.nch = J.nch;
+  da.nbits = J.Lo.payload_bits;
+  da.chunk = J.c.chunk;
+  decode_tables(J.h_len, nsym, J.lut.data(), J.sorted.data(), da.lim, da.base);
+  uint32_t nshort = 0, nused = 0;
+  for (uint32_t k = 0; k < nsym; k++) {
+    nused += J.h_len[k] != 0;
+    nshort += J.h_len[k] != 0 && J.h_len[k] <= kLutBits;
+  }
+  da.long_first = nshort;
+  da.n_long = nused - nshort;
+  md_table(&J.c, J.h_wq);
+}
+
+// decode, verbatim values, anchors and the levels down to the block phase
+template <typename T>
+int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
+{
+  const Layout& Lo = J.Lo;
+  const hpez_config* c = &J.c;
+  const uint8_t* in = J.in;
+  const uint64_t N = J.N, nch = J.nch;
+  const uint64_t s = sizeof(T);
+  HIPCK(hipMemcpyAsync(J.dlut, J.lut.data(), J.lut.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(J.dsorted, J.sorted.data(), J.sorted.size() * 2, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(J.dwq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemsetAsync(J.status, 0, sizeof(int), st));
+  {
+    Span sp(ctx, "decode_offsets", nch * 2, st);
+    HIPCK(launch_u16_to_u32((const uint16_t*)(in + Lo.off_chunks), nch, J.cbits, st));
+    HIPCK(launch_scan_u32_to_u64(J.cbits, nch, J.boff, J.boff + nch, J.tmp1, st));
+  }
+  {
+    Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
+    HIPCK(launch_decode2(J.da, (const uint32_t*)(in + Lo.off_payload), J.boff, J.dlut, J.dsorted,
+                         J.code, J.czero, J.status, st));
+  }
+  HIPCK(launch_scan_u32_to_u64(J.czero, nch, J.zoff, J.zoff + nch, J.tmp2, st));
+  if (Lo.predictor == 1) {
+    // Lorenzo alternative: residuals, running sums, patches
+    const Geom gl = make_geom(&J.d, -1);
+    Span sp(ctx, "lorenzo_rebuild", N * (2 + s), st);
+    HIPCK(launch_lorenzo_rebuild<T>(J.code, gl, N, c->radius, c->chunk, J.czero, J.zoff,
+                                    (const long long*)(in + Lo.off_outl), Lo.n_outlier,
+                                    (const uint64_t*)(in + Lo.off_pidx),
+                                    (const T*)(in + Lo.off_pval), Lo.n_patch, 2.0 * Lo.e, J.lv,
+                                    J.out, J.status, st));
+    return HPEZ_OK;
+  }
+  if (Lo.n_unpred)
+    HIPCK(launch_scatter_unpred2<T>(J.code, N, c->chunk, J.czero, J.zoff,
+                                    (const T*)(in + Lo.off_unpred), Lo.n_unpred, J.out, J.status,
+                                    J.g, st));
+  const Lattice al = anchor_lattice(J.g, c->anchor_log2);
+  if (al.total != Lo.n_anchor) {
+    J.rc = HPEZ_ECORRUPT;
+    return HPEZ_OK;
+  }
+  HIPCK(launch_anchors<T>(J.g, al, nullptr, J.out, J.code, (T*)(in + Lo.off_anchor), c->radius, 1,
+                          st));
+  return run_levels<T>(ctx, &J.d, c, J.g, Lo.e, nullptr, J.out, J.code, in + Lo.off_blocks, J.dwq,
+                       J.h_wq, 1, st, J.fast ? c->block_log2 : 0);
+}
+
+template <typename T>
+BlockJobHost<T> d_block_job(const DJob<T>& J)
+{
+  BlockJobHost<T> B;
+  B.c = &J.c;
+  B.g = J.g;
+  B.e = J.Lo.e;
+  B.X = nullptr;
+  B.Wg = J.out;
+  B.code = J.code;
+  B.d_bcfg = J.in + J.Lo.off_blocks;
+  B.h_wq = J.h_wq;
+  B.hist = nullptr;
+  B.hist_lo = 0;
+  B.area = J.area;
+  B.out = J.out;
+  return B;
+}
+
+// Decompress jobs [0, n) of one dtype whose headers are read (d, c, Lo).
+template <typename T>
+int decompress_jobs(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, hipStream_t st)
+{
+  const int n = (int)jobs.size();
+  if (!n) return HPEZ_OK;
+  size_t dev = 0, pin = 0;
+  int nfast = 0;
+  for (auto& J : jobs) {
+    d_init(J);
+    dev += d_dev_bytes(J);
+    pin += d_pin_bytes(J);
+    nfast += J.fast;
+  }
+  dev += al256(block_tables_bound<T>(nfast > 0 ? nfast : 1)) + 256;
+  int rc = ensure_ws(ctx, dev);
+  if (rc) return rc;
+  rc = ensure_pinned(ctx, pin);
+  if (rc) return rc;
+  Bump bw{(uint8_t*)ctx->ws};
+  Bump pb{ctx->pinned};
+  for (auto& J : jobs) d_take(J, bw, pb);
+  for (auto& J : jobs) {
+    rc = d_fetch(J, st);
+    if (rc) return rc;
+  }
+  HIPCK(hipStreamSynchronize(st));
+  host_parallel(n, [&](int i) {
+    if (jobs[i].Lo.predictor != 2) d_tables(jobs[i]);
+  });
+  std::vector<BlockJobHost<T>> bj;
+  for (auto& J : jobs) {
+    if (J.rc || J.Lo.predictor == 2) continue;
+    rc = d_decode(ctx, J, st);
+    if (rc) return rc;
+    if (!J.rc && J.fast && J.Lo.predictor == HPEZ_INTERP) bj.push_back(d_block_job(J));
+  }
+  rc = block_phase<T>(ctx, bj, 1, bw, st);
+  if (rc) return rc;
+  for (auto& J : jobs) {
+    if (J.rc || J.Lo.predictor == 2) continue;
+    HIPCK(hipMemcpyAsync(J.h_status, J.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(J.h_tot, J.zoff + J.nch, 8, hipMemcpyDeviceToHost, st));
+  }
+  HIPCK(hipStreamSynchronize(st));
+  prof_collect(ctx);
+  for (auto& J : jobs) {
+    if (J.rc || J.Lo.predictor == 2) continue;
+    const uint64_t want = J.Lo.predictor == 1 ? J.Lo.n_outlier : J.Lo.n_unpred;
+    if (*J.h_status || J.h_tot[0] != want) J.rc = HPEZ_ECORRUPT;
+  }
+  return HPEZ_OK;
+}
+
+// device bytes of one compress (op 0) or decompress (op 1) job, block tables included
+template <typename T>
+uint64_t job_footprint(const hpez_field_desc* d, const hpez_config* c, int op)
+{
+  const uint64_t extra = al256(block_tables_bound<T>(1)) + 256;
+  if (op == 0) {
+    CJob<T> J;
+    J.d = d;
+    J.c = c;
+    c_init(J);
+    return c_dev_bytes(J) + extra;
+  }
+  DJob<T> J;
+  J.d = *d;
+  J.c = *c;
+  std::memset(&J.Lo, 0, sizeof J.Lo);
+  J.Lo.predictor = c->predictor;
+  J.Lo.n_blocks = n_blocks(d, c);
+  J.Lo.n_chunks = (points_of(d) + c->chunk - 1) / c->chunk;
+  d_init(J);
+  return d_dev_bytes(J) + extra;
+}
+
+}  // namespace
+
+namespace {
+template <typename T>
+int compress_group(hpez_ctx* ctx, int n, const hpez_field_desc* d, const void* const* d_in,
+                   const hpez_config* c, void* const* d_out, const uint64_t* out_cap,
+                   uint64_t* out_sizes, const std::vector<int>& idx, int* first_rc,
+                   hipStream_t st)
+{
+  (void)n;
+  std::vector<CJob<T>> jobs(idx.size());
+  for (size_t k = 0; k < idx.size(); k++) {
+    const int i = idx[k];
+    jobs[k].d = &d[i];
+    jobs[k].X = (const T*)d_in[i];
+    jobs[k].c = &c[i];
+    jobs[k].out = (uint8_t*)d_out[i];
+    jobs[k].cap = out_cap[i];
+  }
+  const int rc = compress_jobs<T>(ctx, jobs, st);
+  if (rc) return rc;
+  for (size_t k = 0; k < idx.size(); k++) {
+    const int i = idx[k];
+    out_sizes[i] = jobs[k].rc ? 0 : jobs[k].Lo.total;
+    if (jobs[k].rc && !*first_rc) *first_rc = jobs[k].rc;
+  }
+  return HPEZ_OK;
+}
+
+template <typename T>
+int decompress_group(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, const std::vector<int>& idx,
+                     int* rcs, hipStream_t st)
+{
+  const int rc = decompress_jobs<T>(ctx, jobs, st);
+  if (rc) return rc;
+  for (size_t k = 0; k < idx.size(); k++) rcs[idx[k]] = jobs[k].rc;
+  return HPEZ_OK;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1212,9 +1579,17 @@ int hpez_compress_bound(const hpez_field_desc* d, const hpez_config* c, uint64_t
 int hpez_footprint(const hpez_field_desc* d, const hpez_config* c, int op, uint64_t* bytes)
 {
   if (check_desc(d) || !c || !bytes || op < 0 || op > 2) return HPEZ_EINVAL;
+  if (c->chunk < 64 || c->radius < 1 || c->radius > 32768) return HPEZ_EINVAL;
   const uint64_t N = points_of(d);
-  *bytes = ws_need(N, d->dtype ? 8 : 4, c->radius ? c->radius : 32768, c->chunk ? c->chunk : 1024,
-                   n_blocks(d, c), op == 1 ? 1 : 0);
+  if (op == 2) {
+    *bytes = tune_footprint(d, c);
+    return HPEZ_OK;
+  }
+  hpez_config cc = *c;
+  cc.block_cfg = nullptr;
+  if (d->dtype == HPEZ_F32) *bytes = job_footprint<float>(d, &cc, op);
+  else *bytes = job_footprint<double>(d, &cc, op);
+  (void)N;
   return HPEZ_OK;
 }
 
@@ -1222,17 +1597,35 @@ int hpez_compress(hpez_ctx* ctx, const hpez_field_desc* d, const void* d_in,
                   const hpez_config* c, void* d_out, uint64_t out_cap, uint64_t* out_size,
                   hipStream_t stream)
 {
-  if (!ctx || !d_in || !d_out || !out_size) return HPEZ_EINVAL;
-  int rc = check_desc(d);
-  if (rc) return rc;
-  rc = check_cfg(d, c, true);
-  if (rc) return rc;
+  if (!out_size) return HPEZ_EINVAL;
+  return hpez_compress_batch(ctx, 1, d, &d_in, c, &d_out, &out_cap, out_size, stream);
+}
+
+
+int hpez_compress_batch(hpez_ctx* ctx, int n, const hpez_field_desc* d,
+                        const void* const* d_in, const hpez_config* c, void* const* d_out,
+                        const uint64_t* out_cap, uint64_t* out_sizes, hipStream_t stream)
+{
+  if (!ctx || n < 0 || (n > 0 && (!d || !d_in || !c || !d_out || !out_cap || !out_sizes)))
+    return HPEZ_EINVAL;
+  for (int i = 0; i < n; i++) {
+    if (!d_in[i] || !d_out[i]) return HPEZ_EINVAL;
+    int rc = check_desc(&d[i]);
+    if (rc) return rc;
+    rc = check_cfg(&d[i], &c[i], true);
+    if (rc) return rc;
+    out_sizes[i] = 0;
+  }
   DevScope ds(ctx->device);
-  if (d->dtype == HPEZ_F32)
-    return compress_t<float>(ctx, d, (const float*)d_in, c, (uint8_t*)d_out, out_cap, out_size,
-                             stream);
-  return compress_t<double>(ctx, d, (const double*)d_in, c, (uint8_t*)d_out, out_cap, out_size,
-                            stream);
+  std::vector<int> f32, f64;
+  for (int i = 0; i < n; i++) (d[i].dtype == HPEZ_F32 ? f32 : f64).push_back(i);
+  int first = HPEZ_OK;
+  int rc = HPEZ_OK;
+  if (!f32.empty())
+    rc = compress_group<float>(ctx, n, d, d_in, c, d_out, out_cap, out_sizes, f32, &first, stream);
+  if (!rc && !f64.empty())
+    rc = compress_group<double>(ctx, n, d, d_in, c, d_out, out_cap, out_sizes, f64, &first, stream);
+  return rc ? rc : first;
 }
 
 int hpez_inspect(const void* h_hdr, uint64_t n, hpez_field_desc* desc, uint64_t* n_points,
@@ -1251,23 +1644,70 @@ int hpez_inspect(const void* h_hdr, uint64_t n, hpez_field_desc* desc, uint64_t*
 int hpez_decompress(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_out,
                     uint64_t out_cap, hipStream_t stream)
 {
-  if (!ctx || !d_in || !d_out) return HPEZ_EINVAL;
-  if (in_size < (uint64_t)kHdrBytes) return HPEZ_ECORRUPT;
+  int rc1 = HPEZ_OK;
+  const int rc = hpez_decompress_batch(ctx, 1, &d_in, &in_size, &d_out, &out_cap, &rc1, stream);
+  return rc ? rc : rc1;
+}
+
+int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const uint64_t* in_size,
+                          void* const* d_out, const uint64_t* out_cap, int* rcs,
+                          hipStream_t stream)
+{
+  if (!ctx || n < 0 || (n > 0 && (!d_in || !in_size || !d_out || !out_cap || !rcs)))
+    return HPEZ_EINVAL;
+  for (int i = 0; i < n; i++)
+    if (!d_in[i] || !d_out[i]) return HPEZ_EINVAL;
+  if (!n) return HPEZ_OK;
   DevScope ds(ctx->device);
-  uint8_t hdr[kHdrBytes];
-  HIPCK(hipMemcpyAsync(hdr, d_in, kHdrBytes, hipMemcpyDeviceToHost, stream));
-  HIPCK(hipStreamSynchronize(stream));
-  hpez_field_desc d;
-  hpez_config c;
-  Layout L;
-  int rc = read_header(hdr, in_size, &d, &c, &L);
+  // every header in one copy and one synchronization
+  int rc = ensure_pin_tab(ctx, (size_t)n * kHdrBytes);
   if (rc) return rc;
-  if (L.total > in_size) return HPEZ_ECORRUPT;
-  const uint64_t N = points_of(&d);
-  if (out_cap < N * (d.dtype ? 8 : 4)) return HPEZ_ENOSPC;
-  if (d.dtype == HPEZ_F32)
-    return decompress_t<float>(ctx, &d, &c, L, (const uint8_t*)d_in, (float*)d_out, stream);
-  return decompress_t<double>(ctx, &d, &c, L, (const uint8_t*)d_in, (double*)d_out, stream);
+  for (int i = 0; i < n; i++) {
+    rcs[i] = in_size[i] < (uint64_t)kHdrBytes ? HPEZ_ECORRUPT : HPEZ_OK;
+    if (!rcs[i])
+      HIPCK(hipMemcpyAsync(ctx->pin_tab + (size_t)i * kHdrBytes, d_in[i], kHdrBytes,
+                           hipMemcpyDeviceToHost, stream));
+  }
+  HIPCK(hipStreamSynchronize(stream));
+  std::vector<int> i32, i64;
+  std::vector<DJob<float>> j32;
+  std::vector<DJob<double>> j64;
+  for (int i = 0; i < n; i++) {
+    if (rcs[i]) continue;
+    hpez_field_desc dd;
+    hpez_config cc;
+    Layout L;
+    int r = read_header(ctx->pin_tab + (size_t)i * kHdrBytes, in_size[i], &dd, &cc, &L);
+    if (!r && L.total > in_size[i]) r = HPEZ_ECORRUPT;
+    if (!r && out_cap[i] < points_of(&dd) * (dd.dtype ? 8 : 4)) r = HPEZ_ENOSPC;
+    rcs[i] = r;
+    if (r) continue;
+    if (dd.dtype == HPEZ_F32) {
+      j32.emplace_back();
+      DJob<float>& J = j32.back();
+      J.in = (const uint8_t*)d_in[i];
+      J.out = (float*)d_out[i];
+      J.d = dd;
+      J.c = cc;
+      J.Lo = L;
+      i32.push_back(i);
+    } else {
+      j64.emplace_back();
+      DJob<double>& J = j64.back();
+      J.in = (const uint8_t*)d_in[i];
+      J.out = (double*)d_out[i];
+      J.d = dd;
+      J.c = cc;
+      J.Lo = L;
+      i64.push_back(i);
+    }
+  }
+  rc = decompress_group<float>(ctx, j32, i32, rcs, stream);
+  if (!rc) rc = decompress_group<double>(ctx, j64, i64, rcs, stream);
+  if (rc) return rc;
+  for (int i = 0; i < n; i++)
+    if (rcs[i]) return rcs[i];
+  return HPEZ_OK;
 }
 
 int hpez_profile_enable(hpez_ctx* ctx, int on)
@@ -1303,6 +1743,12 @@ uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc)
 {
   *rc = ensure_pinned(c, bytes);
   return *rc ? nullptr : c->pinned;
+}
+
+uint8_t* ctx_pin_tab(hpez_ctx* c, size_t bytes, int* rc)
+{
+  *rc = ensure_pin_tab(c, bytes);
+  return *rc ? nullptr : c->pin_tab;
 }
 
 int ctx_device(hpez_ctx* c) { return c->device; }

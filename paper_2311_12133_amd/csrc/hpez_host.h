@@ -35,6 +35,8 @@ void layout(Layout* L, uint64_t s);
 void write_header(uint8_t* h, const hpez_field_desc* d, const hpez_config* c, const Layout& L);
 int read_header(const uint8_t* h, uint64_t n, hpez_field_desc* d, hpez_config* c, Layout* L);
 int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
+// device bytes of a tuning run with the default options (admission)
+uint64_t tune_footprint(const hpez_field_desc* d, const hpez_config* c);
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw);
 // Canonical decoding tables: lut[2^kLutBits] (symbol << 8 | length, 0 for
 // longer codes), symbols sorted by (length, symbol), and per length the window
@@ -62,6 +64,8 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
 // context services (api.cpp)
 void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc);
 uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc);
+// pinned staging of launch tables, reused by every call (synchronized between uses)
+uint8_t* ctx_pin_tab(hpez_ctx* c, size_t bytes, int* rc);
 int ctx_device(hpez_ctx* c);
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
 void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);

@@ -291,28 +291,27 @@ struct TrialOp {
 };
 
 // Trial of a region of at most three dims held entirely in LDS (original
-// values, then reconstructions in place), on the shared box schedule.
+// values, then reconstructions in place), on the shared box schedule.  The
+// region is tb (index ib of n_cand-wide score rows), the candidate cand.
 template <typename T, bool HIST, int NT>
-__global__ void __launch_bounds__(NT) trial_box_kernel(TrialArgs a, const TrialBox* __restrict__ boxes,
-                                                       const T* __restrict__ X,
-                                                       unsigned long long* __restrict__ score,
-                                                       uint32_t* __restrict__ hist)
+__device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox& tb, uint32_t ib,
+                                              int cand, uint32_t n_cand, const T* __restrict__ X,
+                                              unsigned long long* __restrict__ score,
+                                              uint32_t* __restrict__ hist, unsigned char* lds_raw,
+                                              unsigned long long* red)
 {
-  extern __shared__ unsigned char lds_raw[];
-  __shared__ unsigned long long red[16];
   T* L = reinterpret_cast<T*>(lds_raw);
   uint32_t* lh = reinterpret_cast<uint32_t*>(lds_raw + ((a.box_cap * sizeof(T) + 15) & ~15ull));
-  const TrialBox tb = boxes[blockIdx.x];
-  const int cand = (int)blockIdx.y;
+  const int32_t frozen = a.frozen;
   Box bx;
   bx.E0 = (int32_t)tb.m[0];
   bx.E1 = (int32_t)tb.m[1];
   bx.E2 = (int32_t)tb.m[2];
   bx.b1 = bx.E2;
   bx.b0 = bx.E1 * bx.E2;
-  bx.a0 = bx.E0 > 1 && a.frozen != 0;
-  bx.a1 = bx.E1 > 1 && a.frozen != 1;
-  bx.a2 = bx.E2 > 1 && a.frozen != 2;
+  bx.a0 = bx.E0 > 1 && frozen != 0;
+  bx.a1 = bx.E1 > 1 && frozen != 1;
+  bx.a2 = bx.E2 > 1 && frozen != 2;
   bx.lo0 = bx.lo1 = bx.lo2 = 0;
   bx.hi0 = bx.E0 - 1;
   bx.hi1 = bx.E1 - 1;
@@ -330,38 +329,119 @@ __global__ void __launch_bounds__(NT) trial_box_kernel(TrialArgs a, const TrialB
     const uint32_t c2 = rem - c1 * (uint32_t)bx.E2;
     L[i] = Xo[c0 * st0 + c1 * st1 + c2];
   }
+  const uint32_t R = a.R, hist_lo = a.hist_lo;
   if (HIST)
     for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += NT) lh[i] = 0;
   __syncthreads();
   unsigned long long total_score = 0;
   uint32_t nR = 0;
+  const int score_mode = a.score_mode;
   for (int l = a.L; l >= 1; l--) {
     const int32_t s = 1 << (l - 1);
     const hpez_interp ip = a.tuned ? a.level[l - 1] : a.cand[cand];
-    TrialOp<T, HIST> op{L,         lh,          hist,         a.R,         a.hist_lo, a.el[l],
-                        a.inv2e[l], a.twoe[l], a.score_mul, 0ull,        0u};
+    TrialOp<T, HIST> op{L,         lh,          hist,         R,    hist_lo, a.el[l],
+                        a.inv2e[l], a.twoe[l], a.score_mul, 0ull, 0u};
     box_level<T, NT>(ip, bx, L, 0, 0, 0, s, a.wmd, op);
     nR += op.nR;
     const unsigned long long v = block_sum_u64(op.sc, red);
-    if (a.score_mode == 0) {
+    if (score_mode == 0) {
       if (threadIdx.x == 0 && v) atomicAdd(&score[cand * 16 + (l - 1)], v);
     } else {
       total_score += v;
     }
   }
-  if (a.score_mode == 1 && threadIdx.x == 0)
-    score[(uint64_t)blockIdx.x * gridDim.y + cand] = total_score;
+  if (score_mode == 1 && threadIdx.x == 0) score[(uint64_t)ib * n_cand + cand] = total_score;
   if (HIST) {
     for (int o = 32; o > 0; o >>= 1) nR += __shfl_xor(nR, o, 64);
     if ((threadIdx.x & 63) == 0 && nR) {
-      const uint32_t w = a.R - a.hist_lo;
+      const uint32_t w = R - hist_lo;
       if (w < kTrialHistWin) atomicAdd(&lh[w], nR);
-      else atomicAdd(&hist[a.R], nR);
+      else atomicAdd(&hist[R], nR);
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += NT)
-      if (lh[i]) atomicAdd(&hist[a.hist_lo + i], lh[i]);
+      if (lh[i]) atomicAdd(&hist[hist_lo + i], lh[i]);
   }
+}
+
+template <typename T, bool HIST, int NT>
+__global__ void __launch_bounds__(NT) trial_box_kernel(TrialArgs a, const TrialBox* __restrict__ boxes,
+                                                       const T* __restrict__ X,
+                                                       unsigned long long* __restrict__ score,
+                                                       uint32_t* __restrict__ hist)
+{
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ unsigned long long red[16];
+  trial_box_run<T, HIST, NT>(a, boxes[blockIdx.x], blockIdx.x, (int)blockIdx.y, gridDim.y, X, score,
+                             hist, lds_raw, red);
+}
+
+// index of the last entry whose begin is <= x (begin ascending, begin[0] = 0)
+__device__ __forceinline__ int trial_entry(const uint64_t* __restrict__ begin, int n, uint64_t x)
+{
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Every (region, candidate) trial of several tuning runs (fields, freeze
+// variants) in one launch: work-group w belongs to the entry whose range of
+// n_boxes * n_cand work-groups holds it.
+template <typename T, bool HIST, int NT>
+__global__ void __launch_bounds__(NT) trial_jobs_kernel(const TrialJob<T>* __restrict__ jobs,
+                                                        const uint64_t* __restrict__ wg_begin, int n)
+{
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ unsigned long long red[16];
+  const int j = trial_entry(wg_begin, n, blockIdx.x);
+  const TrialJob<T>& J = jobs[j];
+  const uint32_t nc = J.n_cand;
+  const uint32_t local = (uint32_t)(blockIdx.x - J.wg_begin);
+  const uint32_t ib = local / nc;
+  const int cand = (int)(local - ib * nc);
+  trial_box_run<T, HIST, NT>(J.a, J.boxes[ib], ib, cand, nc, J.X, J.score, J.hist, lds_raw, red);
+}
+
+template <typename T>
+bool trial_box_ok(const TrialArgs& a, bool hist)
+{
+  const size_t box = (size_t)a.box_cap * sizeof(T);
+  const size_t lds_all = ((box + 15) & ~(size_t)15) + (hist ? (size_t)kTrialHistWin * 4 : 0);
+  return a.fg.n[3] == 1 && lds_all <= kTrialBoxLdsBytes && a.box_cap < 65536 &&
+         (uint64_t)a.max_ext * (uint64_t)a.max_ext <= kMagicMax;
+}
+
+template <typename T>
+size_t trial_box_lds(const TrialArgs& a, bool hist)
+{
+  const size_t box = (size_t)a.box_cap * sizeof(T);
+  return ((box + 15) & ~(size_t)15) + (hist ? (size_t)kTrialHistWin * 4 : 0);
+}
+
+template <typename T, bool HIST, int NT>
+static void launch_jobs_t(const TrialJob<T>* d_jobs, const uint64_t* d_wg_begin, int n,
+                          uint64_t total_wg, size_t lds, hipStream_t st)
+{
+  (void)hipFuncSetAttribute((const void*)trial_jobs_kernel<T, HIST, NT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((trial_jobs_kernel<T, HIST, NT>), dim3((unsigned)total_wg), dim3(NT), lds, st,
+                     d_jobs, d_wg_begin, n);
+}
+
+template <typename T>
+hipError_t launch_trial_jobs(const TrialJob<T>* d_jobs, const uint64_t* d_wg_begin, int n,
+                             uint64_t total_wg, size_t lds, bool hist, bool big, hipStream_t st)
+{
+  if (!total_wg || n <= 0) return hipSuccess;
+  if (hist && big) launch_jobs_t<T, true, 1024>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else if (hist) launch_jobs_t<T, true, 256>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else if (big) launch_jobs_t<T, false, 1024>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else launch_jobs_t<T, false, 256>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  return hipGetLastError();
 }
 
 template <typename T, bool HIST, int NT>
@@ -485,6 +565,10 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
 #define INST(T)                                                                                 \
   template hipError_t launch_stats<T>(const T*, const Geom&, const Lattice&, double,            \
                                       unsigned long long*, hipStream_t);                        \
+  template hipError_t launch_trial_jobs<T>(const TrialJob<T>*, const uint64_t*, int, uint64_t,     \
+                                           size_t, bool, bool, hipStream_t);                     \
+  template bool trial_box_ok<T>(const TrialArgs&, bool);                                         \
+  template size_t trial_box_lds<T>(const TrialArgs&, bool);                                      \
   template hipError_t launch_trials<T>(const TrialArgs&, const TrialBox*, uint32_t, uint32_t,   \
                                        const T*, T*, const double*, unsigned long long*,        \
                                        uint32_t*, hipStream_t);                                 \

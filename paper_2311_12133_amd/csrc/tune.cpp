@@ -113,19 +113,6 @@ std::vector<TrialBox> global_boxes(const Geom& g, int64_t B, double rate, uint64
   return v;
 }
 
-struct Work {
-  TrialBox* boxes;
-  void* scratch;
-  size_t scratch_bytes;
-  unsigned long long* score;
-  unsigned long long* dummy;
-  uint32_t* hist;
-  int* flag;
-  double* wq;
-  unsigned long long* h_score;
-  uint32_t* h_hist;
-};
-
 void fill_levels(TrialArgs& a, double e, const hpez_config* Q)
 {
   for (int l = 1; l <= 16; l++) {
@@ -142,115 +129,504 @@ void fill_levels(TrialArgs& a, double e, const hpez_config* Q)
       for (int d = 0; d < 4; d++) a.wmd[(k * 8 + odd) * 4 + d] = wq[(k * 16 + odd) * 4 + d];
 }
 
-template <typename T>
-int global_tune(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_config* Q, double e,
-                const hpez_tune_opts* o, int frozen, const hpez_interp* cand, Work& w,
-                hpez_interp* level_out, double* H, hipStream_t st)
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Longest side of the block-wise sub-blocks (Sec. 6.6) for D active dims.
+int64_t sub_side(int64_t B, double rate, int D)
 {
-  const Geom g = make_geom(d, -1);
-  const int Lb = o->block_log2;
-  const int64_t B = (int64_t)1 << Lb;
-  uint64_t cap;
-  std::vector<TrialBox> bx = global_boxes(g, B, o->global_rate, &cap);
-  const uint32_t nbx = (uint32_t)bx.size();
-  const uint32_t nsym = 2 * Q->radius;
-  if ((size_t)nbx * kNCand * cap * sizeof(T) > w.scratch_bytes &&
-      cap * sizeof(T) > kTrialLdsBytes)
-    return HPEZ_ENOMEM;
-  TCK(hipMemcpyAsync(w.boxes, bx.data(), bx.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
-  TrialArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.fg = g;
-  a.frozen = frozen;
-  a.L = Lb;
-  a.R = Q->radius;
-  a.box_cap = cap;
-  a.max_ext = (int32_t)std::min<int64_t>(B + 1, INT32_MAX);
-  a.score_mul = 4096.0 / e;
-  fill_levels(a, e, Q);
-  for (int i = 0; i < kNCand; i++) a.cand[i] = cand[i];
-  TCK(hipMemsetAsync(w.score, 0, sizeof(unsigned long long) * kNCand * 16, st));
-  hipEvent_t ev = ctx_span_begin(ctx, st);
-  TCK(launch_trials<T>(a, w.boxes, nbx, kNCand, X, (T*)w.scratch, w.wq, w.score, nullptr, st));
-  ctx_span_end(ctx, ev, "tune_trials", (uint64_t)nbx * cap * sizeof(T), st);
-  TCK(hipMemcpyAsync(w.h_score, w.score, sizeof(unsigned long long) * kNCand * 16,
-                     hipMemcpyDeviceToHost, st));
-  TCK(hipStreamSynchronize(st));
-  int best[17];
-  for (int l = 1; l <= Lb; l++) {
-    best[l] = 0;
-    for (int ci = 1; ci < kNCand; ci++)
-      if (w.h_score[ci * 16 + l - 1] < w.h_score[best[l] * 16 + l - 1]) best[l] = ci;
+  int64_t side = (int64_t)std::floor((double)B * std::pow(rate, 1.0 / (double)D) + 0.5);
+  return std::min<int64_t>(std::max<int64_t>(side, 3), B);
+}
+
+// Global scratch for regions too large for LDS (the non-box trial kernels).
+size_t trial_scratch(const Geom& g, const hpez_tune_opts* o, size_t s, size_t n_global,
+                     uint64_t gcap, int64_t nbt)
+{
+  size_t scratch = gcap * s > kTrialLdsBytes ? n_global * kNCand * gcap * s : 0;
+  if (o->block_wise) {
+    // largest sub-block: fewest active dims (one frozen) gives the longest side
+    int big_dims = 0;
+    for (int k = 0; k < 4; k++) big_dims += g.n[k] > 1;
+    const int Dmin = n_active(g) > 1 ? n_active(g) - 1 : 1;
+    const int64_t side = sub_side((int64_t)1 << o->block_log2, o->sub_rate, Dmin);
+    uint64_t bcap_pts = 1;
+    for (int k = 0; k < big_dims; k++) bcap_pts *= (uint64_t)side;
+    if (bcap_pts * s > kTrialLdsBytes)
+      scratch = std::max(scratch, (size_t)nbt * kNCand * bcap_pts * s);
   }
-  a.tuned = 1;
-  a.hist_lo = trial_hist_lo(Q->radius);
-  for (int l = 1; l <= Lb; l++) a.level[l - 1] = cand[best[l]];
-  TCK(hipMemsetAsync(w.hist, 0, sizeof(uint32_t) * nsym, st));
-  TCK(hipMemsetAsync(w.dummy, 0, sizeof(unsigned long long) * 16, st));
-  TCK(launch_trials<T>(a, w.boxes, nbx, 1, X, (T*)w.scratch, w.wq, w.dummy, w.hist, st));
-  TCK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(uint32_t) * nsym, hipMemcpyDeviceToHost, st));
-  TCK(hipStreamSynchronize(st));
-  const int L = Q->anchor_log2;
-  for (int l = 1; l <= 16; l++) {
-    const int lb = l <= Lb ? l : Lb;
-    level_out[l - 1] = l <= L ? cand[best[lb]] : cand[0];
+  return scratch;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning of one field as a job in phases.  The plain call runs one job, the
+// batch call many, with one stream synchronization per phase for all of them
+// and the trials of every job in fused launches:
+//   1. value range;  2. Sec. 6.1 statistics;
+//   3. Sec. 6.2 / 6.3 candidate trials, unfrozen and frozen, and the Sec. 6.5
+//      Lorenzo trial;  4. the tuned trials' code histograms;
+//   5. Sec. 6.6 block-wise trials;  6. decisions.
+// Each job takes the same steps either way, so its decisions are the same.
+template <typename T>
+struct TJob {
+  const hpez_field_desc* d = nullptr;
+  const T* X = nullptr;
+  const hpez_tune_opts* o = nullptr;
+  hpez_config* cfg = nullptr;
+  uint8_t* h_bcfg = nullptr;
+  uint64_t bcap = 0;
+  int rc = HPEZ_OK;
+  bool done = false;  // finished early (constant field) or failed
+  hpez_config Q;
+  Geom g;
+  int64_t B = 0, nbt = 0;
+  uint64_t N = 0;
+  uint32_t nsym = 0;
+  double e = 0;
+  hpez_interp cand[kNCand];
+  std::vector<TrialBox> gb;  // global regions
+  uint64_t gcap = 0;
+  size_t scratch_bytes = 0;
+  int nvar = 1;  // global trial variants: unfrozen, then frozen at fcand
+  int fcand = -1;
+  bool stats = false;
+  int64_t count = 0;
+  TrialArgs ga[2];
+  hpez_interp lv[2][16];
+  double H[2] = {0, 0};
+  int frozen = -1;
+  bool lorenzo = false, lorenzo_trial = false;
+  bool blocks = false;
+  TrialArgs ba;
+  double h_wq[3 * 16 * 4];
+  // device
+  TrialBox* d_gb = nullptr;
+  TrialBox* d_bb = nullptr;
+  void* scratch = nullptr;
+  unsigned long long* score[2] = {nullptr, nullptr};
+  unsigned long long* bscore = nullptr;
+  unsigned long long* dummy = nullptr;
+  uint32_t* hist[3] = {nullptr, nullptr, nullptr};
+  int* flag = nullptr;
+  int* lflag = nullptr;
+  double* wq = nullptr;
+  double* part = nullptr;
+  double* mm = nullptr;
+  unsigned long long* sums = nullptr;
+  // pinned host staging
+  uint32_t* h_hist[3] = {nullptr, nullptr, nullptr};
+  unsigned long long* h_score[2] = {nullptr, nullptr};
+  unsigned long long* h_bscore = nullptr;
+  double* h_mm = nullptr;
+  int* h_bad = nullptr;
+  int* h_lflag = nullptr;
+  unsigned long long* h_sums = nullptr;
+};
+
+// validation and sizes; rc set for a bad request
+template <typename T>
+void t_init(TJob<T>& J)
+{
+  const hpez_field_desc* d = J.d;
+  const hpez_tune_opts* o = J.o;
+  hpez_config& Q = J.Q;
+  J.N = points_of(d);
+  std::memset(&Q, 0, sizeof Q);
+  Q.radius = J.cfg->radius;
+  Q.chunk = J.cfg->chunk;
+  Q.alpha = J.cfg->alpha;
+  Q.beta = J.cfg->beta;
+  Q.frozen_dim = -1;
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 4; j++) Q.md_w[k][j] = 1.0;
+  for (int i = 0; i < 16; i++)
+    for (int j = 0; j < 4; j++) {
+      Q.level[i].order[j] = (uint8_t)j;
+      Q.cand[i].order[j] = (uint8_t)j;
+    }
+  if (check_cfg(d, &Q, false) || o->block_log2 < 1 || o->block_log2 > 8 ||
+      !(o->global_rate > 0) || !(o->sub_rate > 0) || !(o->lorenzo_coef > 0)) {
+    J.rc = HPEZ_EINVAL;
+    J.done = true;
+    return;
   }
-  const int64_t A = (int64_t)1 << Q->anchor_log2;
-  *H = entropy_bits(w.h_hist, nsym) +
-       (double)anchor_count(d, frozen, A) * (double)sizeof(T) * 8.0 / (double)points_of(d);
-  return HPEZ_OK;
+  int big = 0;
+  for (int i = 0; i < d->ndims; i++) big += d->dims[i] > 1;
+  Q.anchor_log2 = o->anchor_log2 ? o->anchor_log2 : (big >= 3 ? 6 : big == 2 ? 7 : 8);
+  J.g = make_geom(d, -1);
+  J.B = (int64_t)1 << o->block_log2;
+  J.nbt = 1;
+  for (int k = 0; k < 4; k++) J.nbt *= (J.g.n[k] + J.B - 1) / J.B;
+  if (o->block_wise && (!J.h_bcfg || J.bcap < (uint64_t)J.nbt)) {
+    J.rc = HPEZ_EINVAL;
+    J.done = true;
+    return;
+  }
+  J.nsym = 2 * Q.radius;
+  candidate_list(d->ndims, J.cand);
+  J.gb = global_boxes(J.g, J.B, o->global_rate, &J.gcap);
+  J.scratch_bytes = trial_scratch(J.g, o, sizeof(T), J.gb.size(), J.gcap, J.nbt);
 }
 
 template <typename T>
-int lorenzo_tune(const hpez_field_desc* d, const T* X, const hpez_config* Q, double e,
-                 const hpez_tune_opts* o, Work& w, double* H, bool* supported, hipStream_t st)
+size_t t_dev_bytes(const TJob<T>& J)
 {
-  const Geom g = make_geom(d, -1);
-  const int64_t B = (int64_t)1 << o->block_log2;
-  uint64_t cap;
-  std::vector<TrialBox> bx = global_boxes(g, B, o->global_rate, &cap);
-  const uint32_t nsym = 2 * Q->radius;
-  TCK(hipMemcpyAsync(w.boxes, bx.data(), bx.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
-  TCK(hipMemsetAsync(w.hist, 0, sizeof(uint32_t) * nsym, st));
-  TCK(hipMemsetAsync(w.flag, 0, sizeof(int), st));
-  TCK(launch_lorenzo_trial<T>(g, w.boxes, (uint32_t)bx.size(), (uint32_t)cap, X, 1.0 / (2.0 * e),
-                              Q->radius, trial_hist_lo(Q->radius), w.hist, w.flag, st));
-  int h_flag = 0;
-  TCK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(uint32_t) * nsym, hipMemcpyDeviceToHost, st));
-  TCK(hipMemcpyAsync(&h_flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  TCK(hipStreamSynchronize(st));
-  *supported = h_flag == 0;
-  *H = entropy_bits(w.h_hist, nsym);
-  return HPEZ_OK;
+  if (J.done) return 0;
+  const size_t nb = (size_t)J.nbt;
+  return al256(J.gb.size() * sizeof(TrialBox)) + al256(nb * sizeof(TrialBox)) +
+         al256(J.scratch_bytes) + 2 * al256(kNCand * 16 * 8) + al256(nb * kNCand * 8) +
+         al256(16 * 8) + 3 * al256(J.nsym * 4) + 2 * al256(64) + al256(3 * 16 * 4 * 8) +
+         al256(2 * 1024 * 8) + al256(64) + al256(12 * 8) + 256;
 }
 
 template <typename T>
-int block_tune(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_config* Q, double e,
-               const hpez_tune_opts* o, int frozen, const hpez_interp* cand, Work& w,
-               uint8_t* h_bcfg, hipStream_t st)
+size_t t_pin_bytes(const TJob<T>& J)
 {
-  const Geom g = make_geom(d, -1);
-  const Geom gf = make_geom(d, frozen);
-  const int64_t B = (int64_t)1 << o->block_log2;
-  int64_t nb[4], nbt = 1;
+  if (J.done) return 0;
+  return 3 * al256(J.nsym * 4) + 2 * al256(kNCand * 16 * 8) + al256((size_t)J.nbt * kNCand * 8) +
+         al256(64) + al256(12 * 8) + 256;
+}
+
+struct Take {
+  uint8_t* base;
+  size_t off = 0;
+  template <typename U>
+  U* take(size_t count)
+  {
+    U* p = reinterpret_cast<U*>(base + off);
+    off += al256(count * sizeof(U));
+    return p;
+  }
+};
+
+template <typename T>
+void t_take(TJob<T>& J, Take& dw, Take& pw)
+{
+  if (J.done) return;
+  J.d_gb = dw.take<TrialBox>(J.gb.size());
+  J.d_bb = dw.take<TrialBox>((size_t)J.nbt);
+  J.scratch = dw.take<uint8_t>(J.scratch_bytes);
+  J.score[0] = dw.take<unsigned long long>(kNCand * 16);
+  J.score[1] = dw.take<unsigned long long>(kNCand * 16);
+  J.bscore = dw.take<unsigned long long>((size_t)J.nbt * kNCand);
+  J.dummy = dw.take<unsigned long long>(16);
+  for (int v = 0; v < 3; v++) J.hist[v] = dw.take<uint32_t>(J.nsym);
+  J.flag = dw.take<int>(16);
+  J.lflag = dw.take<int>(16);
+  J.wq = dw.take<double>(3 * 16 * 4);
+  J.part = dw.take<double>(2 * 1024);
+  J.mm = dw.take<double>(8);
+  J.sums = dw.take<unsigned long long>(12);
+  for (int v = 0; v < 3; v++) J.h_hist[v] = pw.take<uint32_t>(J.nsym);
+  J.h_score[0] = pw.take<unsigned long long>(kNCand * 16);
+  J.h_score[1] = pw.take<unsigned long long>(kNCand * 16);
+  J.h_bscore = pw.take<unsigned long long>((size_t)J.nbt * kNCand);
+  J.h_mm = pw.take<double>(8);
+  J.h_bad = (int*)(J.h_mm + 2);
+  J.h_lflag = (int*)(J.h_mm + 3);
+  J.h_sums = pw.take<unsigned long long>(12);
+}
+
+// phase 1: value range and the non-finite check
+template <typename T>
+int t_minmax(TJob<T>& J, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  TCK(hipMemsetAsync(J.flag, 0, sizeof(int), st));
+  TCK(launch_minmax<T>(J.X, J.N, J.part, J.flag, 1024, st));
+  TCK(launch_minmax_final(J.part, 1024, J.mm, st));
+  TCK(hipMemcpyAsync(J.h_mm, J.mm, 16, hipMemcpyDeviceToHost, st));
+  TCK(hipMemcpyAsync(J.h_bad, J.flag, 4, hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
+
+// phase 2: error bound, constant fields, Sec. 6.1 statistics
+template <typename T>
+int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  const hpez_field_desc* d = J.d;
+  if (*J.h_bad) {
+    J.rc = HPEZ_EINVAL;
+    J.done = true;
+    return HPEZ_OK;
+  }
+  bool constant = false;
+  if (d->eb_mode == HPEZ_REL) {
+    const double range = J.h_mm[1] - J.h_mm[0];
+    if (range == 0) constant = true;
+    J.e = d->eb * range;
+  } else {
+    J.e = d->eb;
+  }
+  if (constant) {
+    *J.cfg = J.Q;
+    J.cfg->n_cand = 0;
+    J.cfg->block_cfg = nullptr;
+    for (int l = 0; l < 16; l++) J.cfg->level[l] = J.cand[0];
+    J.done = true;
+    return HPEZ_OK;
+  }
+  if (!(J.e > 0)) {
+    J.rc = HPEZ_EINVAL;
+    J.done = true;
+    return HPEZ_OK;
+  }
+  Geom gs = J.g;
+  for (int k = 0; k < 4; k++)
+    if (gs.act[k] && gs.n[k] < 8) gs.act[k] = 0;
+  int any = 0;
+  for (int k = 0; k < 4; k++) any |= gs.act[k];
+  std::memset(J.h_sums, 0, 12 * 8);
+  J.count = 0;
+  if (!any) return HPEZ_OK;
+  Lattice lat;
+  lat.total = 1;
   for (int k = 0; k < 4; k++) {
-    nb[k] = (g.n[k] + B - 1) / B;
-    nbt *= nb[k];
+    const int64_t r = gs.act[k] ? 4 : 0, m = gs.act[k] ? 8 : 1;
+    const int64_t hi = gs.act[k] ? gs.n[k] - 4 : gs.n[k] - 1;
+    lat.first[k] = r;
+    lat.step[k] = m;
+    lat.cnt[k] = r <= hi ? (uint32_t)((hi - r) / m + 1) : 0;
+    lat.total *= lat.cnt[k];
   }
+  J.count = (int64_t)lat.total;
+  J.stats = true;
+  TCK(hipMemsetAsync(J.sums, 0, 12 * 8, st));
+  hipEvent_t ev = ctx_span_begin(ctx, st);
+  TCK(launch_stats<T>(J.X, gs, lat, 256.0 / J.e, J.sums, st));
+  ctx_span_end(ctx, ev, "tune_stats", lat.total * (1 + 4 * n_active(gs)) * sizeof(T), st);
+  TCK(hipMemcpyAsync(J.h_sums, J.sums, 12 * 8, hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
+
+// Trial launches of a phase: box-eligible entries of all jobs fused (one launch
+// per lane count), the others one by one.
+template <typename T>
+struct TrialBatch {
+  std::vector<TrialJob<T>> small, big;
+  struct Single {
+    TrialArgs a;
+    const TrialBox* boxes;
+    uint32_t n_boxes, n_cand;
+    const T* X;
+    T* scratch;
+    const double* wq;
+    unsigned long long* score;
+    uint32_t* hist;
+  };
+  std::vector<Single> single;
+};
+
+template <typename T>
+void t_add(TrialBatch<T>& tb, const TrialArgs& a, const TrialBox* boxes, uint32_t n_boxes,
+           uint32_t n_cand, const T* X, T* scratch, const double* wq, unsigned long long* score,
+           uint32_t* hist)
+{
+  if (!n_boxes || !n_cand) return;
+  if (trial_box_ok<T>(a, hist != nullptr)) {
+    TrialJob<T> j;
+    j.a = a;
+    j.boxes = boxes;
+    j.X = X;
+    j.score = score;
+    j.hist = hist;
+    j.n_boxes = n_boxes;
+    j.n_cand = n_cand;
+    j.wg_begin = 0;
+    (a.box_cap > 4096 ? tb.big : tb.small).push_back(j);
+  } else {
+    tb.single.push_back({a, boxes, n_boxes, n_cand, X, scratch, wq, score, hist});
+  }
+}
+
+// stage the tables through pinned memory (one copy) and launch
+template <typename T>
+int t_launch(hpez_ctx* ctx, TrialBatch<T>& tb, bool hist, uint8_t* d_tab, size_t tab_cap,
+             hipStream_t st)
+{
+  std::vector<TrialJob<T>>* groups[2] = {&tb.small, &tb.big};
+  size_t bytes = 0;
+  for (auto* gr : groups) bytes += al256(gr->size() * sizeof(TrialJob<T>)) + al256((gr->size() + 1) * 8);
+  if (bytes > tab_cap) return HPEZ_EINVAL;
+  if (bytes) {
+    int rc;
+    uint8_t* h = ctx_pin_tab(ctx, bytes, &rc);
+    if (rc) return rc;
+    size_t off = 0;
+    size_t offs[2][2];
+    uint64_t tot[2];
+    size_t lds[2];
+    for (int k = 0; k < 2; k++) {
+      auto& gr = *groups[k];
+      uint64_t w = 0;
+      lds[k] = 0;
+      uint64_t* wb = (uint64_t*)(h + off + al256(gr.size() * sizeof(TrialJob<T>)));
+      for (size_t i = 0; i < gr.size(); i++) {
+        gr[i].wg_begin = w;
+        wb[i] = w;
+        w += (uint64_t)gr[i].n_boxes * gr[i].n_cand;
+        lds[k] = std::max(lds[k], trial_box_lds<T>(gr[i].a, hist));
+      }
+      wb[gr.size()] = w;
+      std::memcpy(h + off, gr.data(), gr.size() * sizeof(TrialJob<T>));
+      offs[k][0] = off;
+      offs[k][1] = off + al256(gr.size() * sizeof(TrialJob<T>));
+      off = offs[k][1] + al256((gr.size() + 1) * 8);
+      tot[k] = w;
+    }
+    TCK(hipMemcpyAsync(d_tab, h, bytes, hipMemcpyHostToDevice, st));
+    for (int k = 0; k < 2; k++)
+      TCK(launch_trial_jobs<T>((const TrialJob<T>*)(d_tab + offs[k][0]),
+                               (const uint64_t*)(d_tab + offs[k][1]), (int)groups[k]->size(),
+                               tot[k], lds[k], hist, k == 1, st));
+  }
+  for (auto& s : tb.single)
+    TCK(launch_trials<T>(s.a, s.boxes, s.n_boxes, s.n_cand, s.X, s.scratch, s.wq, s.score, s.hist,
+                         st));
+  return HPEZ_OK;
+}
+
+// phase 3: weights (Eq. 12), the freeze candidate, global trials of both
+// variants (Sec. 6.2 / 6.3) and the Lorenzo trial (Sec. 6.5)
+template <typename T>
+int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  hpez_config& Q = J.Q;
+  const hpez_tune_opts* o = J.o;
+  double sigma2[3][4];
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 4; j++) {
+      const double s2 = J.count > 0 ? (double)J.h_sums[k * 4 + j] / (double)J.count : 1.0;
+      sigma2[k][j] = s2;
+      Q.md_w[k][j] = 1.0 / (s2 > 1.0 ? s2 : 1.0);
+    }
+  J.fcand = -1;
+  if (J.count > 0 && n_active(J.g) >= 2) {
+    for (int k = 0; k < 4; k++)
+      if (J.g.act[k] && J.g.n[k] >= 8 && (J.fcand < 0 || sigma2[0][k] > sigma2[0][J.fcand]))
+        J.fcand = k;
+  }
+  md_table(&Q, J.h_wq);
+  TCK(hipMemcpyAsync(J.wq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
+  TCK(hipMemcpyAsync(J.d_gb, J.gb.data(), J.gb.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
+  J.nvar = (o->allow_freeze && J.fcand >= 0) ? 2 : 1;
+  const uint32_t nbx = (uint32_t)J.gb.size();
+  for (int v = 0; v < J.nvar; v++) {
+    TrialArgs& a = J.ga[v];
+    std::memset(&a, 0, sizeof a);
+    a.fg = J.g;
+    a.frozen = v == 0 ? -1 : J.fcand;
+    a.L = o->block_log2;
+    a.R = Q.radius;
+    a.box_cap = J.gcap;
+    a.max_ext = (int32_t)std::min<int64_t>(J.B + 1, INT32_MAX);
+    a.score_mul = 4096.0 / J.e;
+    fill_levels(a, J.e, &Q);
+    for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
+    TCK(hipMemsetAsync(J.score[v], 0, sizeof(unsigned long long) * kNCand * 16, st));
+    t_add<T>(tb, a, J.d_gb, nbx, kNCand, J.X, (T*)J.scratch, J.wq, J.score[v], nullptr);
+  }
+  J.lorenzo_trial = o->allow_lorenzo != 0;
+  if (J.lorenzo_trial) {
+    TCK(hipMemsetAsync(J.hist[2], 0, sizeof(uint32_t) * J.nsym, st));
+    TCK(hipMemsetAsync(J.lflag, 0, sizeof(int), st));
+    TCK(launch_lorenzo_trial<T>(J.g, J.d_gb, nbx, (uint32_t)J.gcap, J.X, 1.0 / (2.0 * J.e), Q.radius,
+                                trial_hist_lo(Q.radius), J.hist[2], J.lflag, st));
+  }
+  return HPEZ_OK;
+}
+
+template <typename T>
+int t_global_copy(TJob<T>& J, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  for (int v = 0; v < J.nvar; v++)
+    TCK(hipMemcpyAsync(J.h_score[v], J.score[v], sizeof(unsigned long long) * kNCand * 16,
+                       hipMemcpyDeviceToHost, st));
+  if (J.lorenzo_trial) {
+    TCK(hipMemcpyAsync(J.h_hist[2], J.hist[2], sizeof(uint32_t) * J.nsym, hipMemcpyDeviceToHost, st));
+    TCK(hipMemcpyAsync(J.h_lflag, J.lflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  return HPEZ_OK;
+}
+
+// phase 4: per level the best candidate, then the tuned trials' histograms
+template <typename T>
+int t_hist(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  const int Lb = J.o->block_log2;
+  const int L = J.Q.anchor_log2;
+  for (int v = 0; v < J.nvar; v++) {
+    int best[17];
+    for (int l = 1; l <= Lb; l++) {
+      best[l] = 0;
+      for (int ci = 1; ci < kNCand; ci++)
+        if (J.h_score[v][ci * 16 + l - 1] < J.h_score[v][best[l] * 16 + l - 1]) best[l] = ci;
+    }
+    TrialArgs a = J.ga[v];
+    a.tuned = 1;
+    a.hist_lo = trial_hist_lo(J.Q.radius);
+    for (int l = 1; l <= Lb; l++) a.level[l - 1] = J.cand[best[l]];
+    for (int l = 1; l <= 16; l++) {
+      const int lb = l <= Lb ? l : Lb;
+      J.lv[v][l - 1] = l <= L ? J.cand[best[lb]] : J.cand[0];
+    }
+    TCK(hipMemsetAsync(J.hist[v], 0, sizeof(uint32_t) * J.nsym, st));
+    if (v == 0) TCK(hipMemsetAsync(J.dummy, 0, sizeof(unsigned long long) * 16, st));
+    t_add<T>(tb, a, J.d_gb, (uint32_t)J.gb.size(), 1, J.X, (T*)J.scratch, J.wq, J.dummy, J.hist[v]);
+  }
+  return HPEZ_OK;
+}
+
+template <typename T>
+int t_hist_copy(TJob<T>& J, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  for (int v = 0; v < J.nvar; v++)
+    TCK(hipMemcpyAsync(J.h_hist[v], J.hist[v], sizeof(uint32_t) * J.nsym, hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
+
+// phase 5: freeze and Lorenzo decisions, then the block-wise trials (Sec. 6.6)
+template <typename T>
+int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
+{
+  if (J.done) return HPEZ_OK;
+  const hpez_field_desc* d = J.d;
+  const hpez_tune_opts* o = J.o;
+  const int64_t A = (int64_t)1 << J.Q.anchor_log2;
+  for (int v = 0; v < J.nvar; v++) {
+    const int fz = v == 0 ? -1 : J.fcand;
+    J.H[v] = entropy_bits(J.h_hist[v], J.nsym) +
+             (double)anchor_count(d, fz, A) * (double)sizeof(T) * 8.0 / (double)points_of(d);
+  }
+  J.frozen = (J.nvar == 2 && J.H[1] < J.H[0]) ? J.fcand : -1;
+  const double Hbest = J.frozen >= 0 ? J.H[1] : J.H[0];
+  J.lorenzo = false;
+  if (J.lorenzo_trial) {
+    const double HL = entropy_bits(J.h_hist[2], J.nsym);
+    if (*J.h_lflag == 0 && o->lorenzo_coef * HL < Hbest) J.lorenzo = true;
+  }
+  J.blocks = !J.lorenzo && o->block_wise;
+  if (!J.blocks) return HPEZ_OK;
+  const Geom& g = J.g;
+  const Geom gf = make_geom(d, J.frozen);
+  const int64_t B = J.B;
+  int64_t nb[4];
+  for (int k = 0; k < 4; k++) nb[k] = (g.n[k] + B - 1) / B;
   const int nact = n_active(gf);
-  const int D = nact > 0 ? nact : 1;
-  int64_t side = (int64_t)std::floor((double)B * std::pow(o->sub_rate, 1.0 / (double)D) + 0.5);
-  if (side < 3) side = 3;
-  if (side > B) side = B;
+  const int64_t side = sub_side(B, o->sub_rate, nact > 0 ? nact : 1);
   int64_t As = 1;
   int al = 0;
   while (As * 2 <= side - 1) {
     As *= 2;
     al++;
   }
-  std::vector<TrialBox> bx((size_t)nbt);
+  std::vector<TrialBox> bx((size_t)J.nbt);
   uint64_t cap = 0;
-  for (int64_t bi = 0; bi < nbt; bi++) {
+  for (int64_t bi = 0; bi < J.nbt; bi++) {
     int64_t b[4];
     unravel(bi, nb, b);
     uint64_t pts = 1;
@@ -262,249 +638,224 @@ int block_tune(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_c
     }
     cap = std::max(cap, pts);
   }
-  if ((size_t)nbt * kNCand * cap * sizeof(T) > w.scratch_bytes && cap * sizeof(T) > kTrialLdsBytes)
+  if ((size_t)J.nbt * kNCand * cap * sizeof(T) > J.scratch_bytes && cap * sizeof(T) > kTrialLdsBytes)
     return HPEZ_ENOMEM;
-  TCK(hipMemcpyAsync(w.boxes, bx.data(), bx.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
-  TrialArgs a;
+  // the boxes are staged in the pinned block-score area, which is read only
+  // after this phase's synchronization
+  static_assert(sizeof(unsigned long long) * kNCand >= sizeof(TrialBox), "box staging");
+  std::memcpy(J.h_bscore, bx.data(), bx.size() * sizeof(TrialBox));
+  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, bx.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
+  TrialArgs& a = J.ba;
   std::memset(&a, 0, sizeof a);
   a.fg = g;
-  a.frozen = frozen;
+  a.frozen = J.frozen;
   a.L = al;
-  a.R = Q->radius;
+  a.R = J.Q.radius;
   a.score_mode = 1;
   a.box_cap = cap;
   a.max_ext = (int32_t)side;
-  a.score_mul = 4096.0 / e;
-  fill_levels(a, e, Q);
-  for (int i = 0; i < kNCand; i++) a.cand[i] = cand[i];
-  hipEvent_t ev = ctx_span_begin(ctx, st);
-  TCK(launch_trials<T>(a, w.boxes, (uint32_t)nbt, kNCand, X, (T*)w.scratch, w.wq, w.score, nullptr,
-                       st));
-  ctx_span_end(ctx, ev, "tune_block_trials", (uint64_t)nbt * cap * sizeof(T), st);
-  std::vector<unsigned long long> h((size_t)nbt * kNCand);
-  TCK(hipMemcpyAsync(h.data(), w.score, h.size() * sizeof(unsigned long long),
-                     hipMemcpyDeviceToHost, st));
-  TCK(hipStreamSynchronize(st));
-  for (int64_t bi = 0; bi < nbt; bi++) {
-    int besti = 0;
-    for (int ci = 1; ci < kNCand; ci++)
-      if (h[(size_t)bi * kNCand + ci] < h[(size_t)bi * kNCand + besti]) besti = ci;
-    h_bcfg[bi] = (uint8_t)besti;
-  }
+  a.score_mul = 4096.0 / J.e;
+  fill_levels(a, J.e, &J.Q);
+  for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
+  t_add<T>(tb, a, J.d_bb, (uint32_t)J.nbt, kNCand, J.X, (T*)J.scratch, J.wq, J.bscore, nullptr);
   return HPEZ_OK;
 }
 
 template <typename T>
-int tune_t(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_tune_opts* o,
-           hpez_config* cfg, uint8_t* h_bcfg, uint64_t bcap, hipStream_t st)
+int t_blocks_copy(TJob<T>& J, hipStream_t st)
 {
-  const uint64_t N = points_of(d);
-  hpez_config Q;
-  std::memset(&Q, 0, sizeof Q);
-  Q.radius = cfg->radius;
-  Q.chunk = cfg->chunk;
-  Q.alpha = cfg->alpha;
-  Q.beta = cfg->beta;
-  Q.frozen_dim = -1;
-  for (int k = 0; k < 3; k++)
-    for (int j = 0; j < 4; j++) Q.md_w[k][j] = 1.0;
-  for (int i = 0; i < 16; i++)
-    for (int j = 0; j < 4; j++) {
-      Q.level[i].order[j] = (uint8_t)j;
-      Q.cand[i].order[j] = (uint8_t)j;
-    }
-  if (check_cfg(d, &Q, false)) return HPEZ_EINVAL;
-  if (o->block_log2 < 1 || o->block_log2 > 8 || !(o->global_rate > 0) || !(o->sub_rate > 0) ||
-      !(o->lorenzo_coef > 0))
-    return HPEZ_EINVAL;
-  int big = 0;
-  for (int i = 0; i < d->ndims; i++) big += d->dims[i] > 1;
-  Q.anchor_log2 = o->anchor_log2 ? o->anchor_log2 : (big >= 3 ? 6 : big == 2 ? 7 : 8);
-  const Geom g = make_geom(d, -1);
-  const int64_t B = (int64_t)1 << o->block_log2;
-  int64_t nbt = 1;
-  for (int k = 0; k < 4; k++) nbt *= (g.n[k] + B - 1) / B;
-  if (o->block_wise && (!h_bcfg || bcap < (uint64_t)nbt)) return HPEZ_EINVAL;
-  const uint32_t nsym = 2 * Q.radius;
+  if (J.done || !J.blocks) return HPEZ_OK;
+  TCK(hipMemcpyAsync(J.h_bscore, J.bscore, (size_t)J.nbt * kNCand * sizeof(unsigned long long),
+                     hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
 
-  // workspace
-  uint64_t gcap;
-  const std::vector<TrialBox> gb = global_boxes(g, B, o->global_rate, &gcap);
-  const size_t nbox = std::max((size_t)nbt, gb.size());
-  size_t scratch = gcap * sizeof(T) > kTrialLdsBytes ? gb.size() * kNCand * gcap * sizeof(T) : 0;
-  if (o->block_wise) {
-    // largest sub-block: fewest active dims (one frozen) gives the longest side
-    int big_dims = 0;
-    for (int k = 0; k < 4; k++) big_dims += g.n[k] > 1;
-    const int Dmin = n_active(g) > 1 ? n_active(g) - 1 : 1;
-    int64_t side = (int64_t)std::floor((double)B * std::pow(o->sub_rate, 1.0 / (double)Dmin) + 0.5);
-    side = std::min<int64_t>(std::max<int64_t>(side, 3), B);
-    uint64_t bcap_pts = 1;
-    for (int k = 0; k < big_dims; k++) bcap_pts *= (uint64_t)side;
-    if (bcap_pts * sizeof(T) > kTrialLdsBytes)
-      scratch = std::max(scratch, (size_t)nbt * kNCand * bcap_pts * sizeof(T));
-  }
-  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  const size_t need = al(nbox * sizeof(TrialBox)) + al(scratch) +
-                      al(nbox * kNCand * sizeof(unsigned long long)) + al(16 * 8) +
-                      al(nsym * 4) + al(64) + al(3 * 16 * 4 * 8) + al(2 * 1024 * 8) + al(64) +
-                      al(12 * 8);
-  int rc;
-  uint8_t* base = (uint8_t*)ctx_ws(ctx, need, &rc);
-  if (rc) return rc;
-  uint8_t* pin = ctx_pin(ctx, nsym * 4 + kNCand * 16 * 8 + 4096, &rc);
-  if (rc) return rc;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    uint8_t* p = base + off;
-    off += al(bytes);
-    return p;
-  };
-  Work w;
-  w.boxes = (TrialBox*)take(nbox * sizeof(TrialBox));
-  w.scratch = take(scratch);
-  w.scratch_bytes = scratch;
-  w.score = (unsigned long long*)take(nbox * kNCand * sizeof(unsigned long long));
-  w.dummy = (unsigned long long*)take(16 * 8);
-  w.hist = (uint32_t*)take(nsym * 4);
-  w.flag = (int*)take(64);
-  w.wq = (double*)take(3 * 16 * 4 * 8);
-  double* part = (double*)take(2 * 1024 * 8);
-  double* mm = (double*)take(64);
-  unsigned long long* sums = (unsigned long long*)take(12 * 8);
-  w.h_hist = (uint32_t*)pin;
-  w.h_score = (unsigned long long*)(pin + nsym * 4);
-  double* h_mm = (double*)(pin + nsym * 4 + kNCand * 16 * 8);
-  int* h_bad = (int*)(h_mm + 2);
-  unsigned long long* h_sums = (unsigned long long*)(h_mm + 4);
-
-  // error bound
-  TCK(hipMemsetAsync(w.flag, 0, sizeof(int), st));
-  TCK(launch_minmax<T>(X, N, part, w.flag, 1024, st));
-  TCK(launch_minmax_final(part, 1024, mm, st));
-  TCK(hipMemcpyAsync(h_mm, mm, 16, hipMemcpyDeviceToHost, st));
-  TCK(hipMemcpyAsync(h_bad, w.flag, 4, hipMemcpyDeviceToHost, st));
-  TCK(hipStreamSynchronize(st));
-  if (*h_bad) return HPEZ_EINVAL;
-  double e;
-  bool constant = false;
-  if (d->eb_mode == HPEZ_REL) {
-    const double range = h_mm[1] - h_mm[0];
-    if (range == 0) constant = true;
-    e = d->eb * range;
-  } else {
-    e = d->eb;
-  }
-  hpez_interp cand[kNCand];
-  candidate_list(d->ndims, cand);
-  if (constant) {
-    *cfg = Q;
-    cfg->n_cand = 0;
-    cfg->block_cfg = nullptr;
-    for (int l = 0; l < 16; l++) cfg->level[l] = cand[0];
-    return HPEZ_OK;
-  }
-  if (!(e > 0)) return HPEZ_EINVAL;
-
-  // Sec. 6.1 statistics
-  Geom gs = g;
-  for (int k = 0; k < 4; k++)
-    if (gs.act[k] && gs.n[k] < 8) gs.act[k] = 0;
-  int any = 0;
-  for (int k = 0; k < 4; k++) any |= gs.act[k];
-  int64_t count = 0;
-  std::memset(h_sums, 0, 12 * 8);
-  if (any) {
-    int64_t r[4], m[4];
-    Lattice lat;
-    lat.total = 1;
-    for (int k = 0; k < 4; k++) {
-      r[k] = gs.act[k] ? 4 : 0;
-      m[k] = gs.act[k] ? 8 : 1;
-      const int64_t hi = gs.act[k] ? gs.n[k] - 4 : gs.n[k] - 1;
-      lat.first[k] = r[k];
-      lat.step[k] = m[k];
-      lat.cnt[k] = r[k] <= hi ? (uint32_t)((hi - r[k]) / m[k] + 1) : 0;
-      lat.total *= lat.cnt[k];
-    }
-    count = (int64_t)lat.total;
-    TCK(hipMemsetAsync(sums, 0, 12 * 8, st));
-    hipEvent_t ev = ctx_span_begin(ctx, st);
-    TCK(launch_stats<T>(X, gs, lat, 256.0 / e, sums, st));
-    ctx_span_end(ctx, ev, "tune_stats", lat.total * (1 + 4 * n_active(gs)) * sizeof(T), st);
-    TCK(hipMemcpyAsync(h_sums, sums, 12 * 8, hipMemcpyDeviceToHost, st));
-    TCK(hipStreamSynchronize(st));
-  }
-  double sigma2[3][4];
-  for (int k = 0; k < 3; k++)
-    for (int j = 0; j < 4; j++) {
-      const double s2 = count > 0 ? (double)h_sums[k * 4 + j] / (double)count : 1.0;
-      sigma2[k][j] = s2;
-      Q.md_w[k][j] = 1.0 / (s2 > 1.0 ? s2 : 1.0);
-    }
-  int fcand = -1;
-  if (count > 0 && n_active(g) >= 2) {
-    for (int k = 0; k < 4; k++)
-      if (g.act[k] && g.n[k] >= 8 && (fcand < 0 || sigma2[0][k] > sigma2[0][fcand])) fcand = k;
-  }
-  double h_wq[3 * 16 * 4];
-  md_table(&Q, h_wq);
-  TCK(hipMemcpyAsync(w.wq, h_wq, sizeof h_wq, hipMemcpyHostToDevice, st));
-
-  // Sec. 6.2 / 6.3
-  hpez_interp lv[2][16];
-  double H[2] = {0, 0};
-  rc = global_tune<T>(ctx, d, X, &Q, e, o, -1, cand, w, lv[0], &H[0], st);
-  if (rc) return rc;
-  int frozen = -1;
-  if (o->allow_freeze && fcand >= 0) {
-    rc = global_tune<T>(ctx, d, X, &Q, e, o, fcand, cand, w, lv[1], &H[1], st);
-    if (rc) return rc;
-    if (H[1] < H[0]) frozen = fcand;
-  }
-  const double Hbest = frozen >= 0 ? H[1] : H[0];
-  // Sec. 6.5
-  bool lorenzo = false;
-  if (o->allow_lorenzo) {
-    double HL = 0;
-    bool ok = true;
-    rc = lorenzo_tune<T>(d, X, &Q, e, o, w, &HL, &ok, st);
-    if (rc) return rc;
-    if (ok && o->lorenzo_coef * HL < Hbest) lorenzo = true;
-  }
-  hpez_config out = Q;
-  out.frozen_dim = (int8_t)(lorenzo ? -1 : frozen);
-  out.predictor = lorenzo ? HPEZ_LORENZO : HPEZ_INTERP;
-  for (int l = 0; l < 16; l++) out.level[l] = lv[frozen >= 0 ? 1 : 0][l];
+// phase 6: the configuration
+template <typename T>
+void t_finish(TJob<T>& J)
+{
+  if (J.done) return;
+  hpez_config out = J.Q;
+  out.frozen_dim = (int8_t)(J.lorenzo ? -1 : J.frozen);
+  out.predictor = J.lorenzo ? HPEZ_LORENZO : HPEZ_INTERP;
+  for (int l = 0; l < 16; l++) out.level[l] = J.lv[J.frozen >= 0 ? 1 : 0][l];
   out.n_cand = 0;
   out.block_cfg = nullptr;
-  // Sec. 6.6
-  if (!lorenzo && o->block_wise) {
-    rc = block_tune<T>(ctx, d, X, &Q, e, o, frozen, cand, w, h_bcfg, st);
-    if (rc) return rc;
-    out.block_log2 = o->block_log2;
+  if (J.blocks) {
+    for (int64_t bi = 0; bi < J.nbt; bi++) {
+      const unsigned long long* h = J.h_bscore + (size_t)bi * kNCand;
+      int besti = 0;
+      for (int ci = 1; ci < kNCand; ci++)
+        if (h[ci] < h[besti]) besti = ci;
+      J.h_bcfg[bi] = (uint8_t)besti;
+    }
+    out.block_log2 = J.o->block_log2;
     out.n_cand = kNCand;
-    for (int i = 0; i < kNCand; i++) out.cand[i] = cand[i];
-    out.block_cfg = h_bcfg;
+    for (int i = 0; i < kNCand; i++) out.cand[i] = J.cand[i];
+    out.block_cfg = J.h_bcfg;
   }
+  *J.cfg = out;
+}
+
+template <typename T>
+int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
+{
+  if (jobs.empty()) return HPEZ_OK;
+  size_t dev = 0, pin = 0;
+  for (auto& J : jobs) {
+    t_init(J);
+    dev += t_dev_bytes(J);
+    pin += t_pin_bytes(J);
+  }
+  // trial tables: two global variants per job is the most of any phase
+  const size_t tab_cap = al256(2 * jobs.size() * sizeof(TrialJob<T>)) + 2 * al256((2 * jobs.size() + 1) * 8) + 512;
+  dev += tab_cap;
+  int rc;
+  uint8_t* base = (uint8_t*)ctx_ws(ctx, dev, &rc);
+  if (rc) return rc;
+  uint8_t* pbase = ctx_pin(ctx, pin ? pin : 256, &rc);
+  if (rc) return rc;
+  Take dw{base}, pw{pbase};
+  uint8_t* d_tab = dw.take<uint8_t>(tab_cap);
+  for (auto& J : jobs) t_take(J, dw, pw);
+
+  for (auto& J : jobs)
+    if ((rc = t_minmax(J, st))) return rc;
+  TCK(hipStreamSynchronize(st));
+  bool any_stats = false;
+  for (auto& J : jobs) {
+    if ((rc = t_stats(ctx, J, st))) return rc;
+    any_stats |= J.stats;
+  }
+  if (any_stats) TCK(hipStreamSynchronize(st));
+  {
+    TrialBatch<T> tb;
+    for (auto& J : jobs)
+      if ((rc = t_global(J, tb, st))) return rc;
+    hipEvent_t ev = ctx_span_begin(ctx, st);
+    if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
+    uint64_t bytes = 0;
+    for (auto& J : jobs)
+      if (!J.done) bytes += (uint64_t)J.nvar * J.gb.size() * J.gcap * sizeof(T);
+    ctx_span_end(ctx, ev, "tune_trials", bytes, st);
+    for (auto& J : jobs)
+      if ((rc = t_global_copy(J, st))) return rc;
+  }
+  TCK(hipStreamSynchronize(st));
+  {
+    TrialBatch<T> tb;
+    for (auto& J : jobs)
+      if ((rc = t_hist(J, tb, st))) return rc;
+    if ((rc = t_launch(ctx, tb, true, d_tab, tab_cap, st))) return rc;
+    for (auto& J : jobs)
+      if ((rc = t_hist_copy(J, st))) return rc;
+  }
+  TCK(hipStreamSynchronize(st));
+  {
+    TrialBatch<T> tb;
+    for (auto& J : jobs)
+      if ((rc = t_blocks(J, tb, st))) return rc;
+    hipEvent_t ev = ctx_span_begin(ctx, st);
+    if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
+    uint64_t bytes = 0;
+    for (auto& J : jobs)
+      if (!J.done && J.blocks) bytes += (uint64_t)J.nbt * J.ba.box_cap * sizeof(T);
+    ctx_span_end(ctx, ev, "tune_block_trials", bytes, st);
+    for (auto& J : jobs)
+      if ((rc = t_blocks_copy(J, st))) return rc;
+  }
+  TCK(hipStreamSynchronize(st));
+  for (auto& J : jobs) t_finish(J);
   ctx_prof_collect(ctx);
-  *cfg = out;
+  return HPEZ_OK;
+}
+
+template <typename T>
+int tune_group(hpez_ctx* ctx, const hpez_field_desc* d, const void* const* d_in,
+               const hpez_tune_opts* o, hpez_config* cfg, uint8_t* const* h_bcfg,
+               const uint64_t* bcap, const std::vector<int>& idx, int* rcs, hipStream_t st)
+{
+  std::vector<TJob<T>> jobs(idx.size());
+  for (size_t k = 0; k < idx.size(); k++) {
+    const int i = idx[k];
+    jobs[k].d = &d[i];
+    jobs[k].X = (const T*)d_in[i];
+    jobs[k].o = &o[i];
+    jobs[k].cfg = &cfg[i];
+    jobs[k].h_bcfg = h_bcfg ? h_bcfg[i] : nullptr;
+    jobs[k].bcap = bcap ? bcap[i] : 0;
+  }
+  const int rc = tune_jobs<T>(ctx, jobs, st);
+  if (rc) return rc;
+  for (size_t k = 0; k < idx.size(); k++) rcs[idx[k]] = jobs[k].rc;
   return HPEZ_OK;
 }
 
 }  // namespace
+
+namespace hpez {
+// the tuner's device bytes for a field with the default options
+uint64_t tune_footprint(const hpez_field_desc* d, const hpez_config* c)
+{
+  hpez_tune_opts o;
+  std::memset(&o, 0, sizeof o);
+  o.global_rate = 0.01;
+  o.sub_rate = 0.04;
+  o.lorenzo_coef = 1.0;
+  o.block_log2 = 5;
+  o.block_wise = 1;
+  o.allow_freeze = 1;
+  o.allow_lorenzo = 1;
+  hpez_config q = *c;
+  uint8_t dummy = 0;
+  TJob<float> J;  // sizes scale with the element size below
+  J.d = d;
+  J.o = &o;
+  J.cfg = &q;
+  J.h_bcfg = &dummy;
+  J.bcap = ~0ull;
+  t_init(J);
+  const size_t s = d->dtype ? 8 : 4;
+  J.scratch_bytes = trial_scratch(J.g, &o, s, J.gb.size(), J.gcap, J.nbt);
+  return t_dev_bytes(J) + al256(2 * sizeof(TrialJob<double>)) + 2 * al256(3 * 8) + 512;
+}
+}  // namespace hpez
+
+extern "C" int hpez_tune_batch(hpez_ctx* ctx, int n, const hpez_field_desc* desc,
+                               const void* const* d_in, const hpez_tune_opts* opts,
+                               hpez_config* out_cfg, uint8_t* const* h_block_cfg,
+                               const uint64_t* block_cfg_cap, int* rcs, hipStream_t stream)
+{
+  if (!ctx || n < 0 || (n > 0 && (!desc || !d_in || !opts || !out_cfg || !rcs))) return HPEZ_EINVAL;
+  for (int i = 0; i < n; i++) {
+    if (!d_in[i]) return HPEZ_EINVAL;
+    const int rc = check_desc(&desc[i]);
+    if (rc) return rc;
+  }
+  if (!n) return HPEZ_OK;
+  DeviceGuard dg(ctx_device(ctx));
+  std::vector<int> f32, f64;
+  for (int i = 0; i < n; i++) (desc[i].dtype == HPEZ_F32 ? f32 : f64).push_back(i);
+  int rc = HPEZ_OK;
+  if (!f32.empty())
+    rc = tune_group<float>(ctx, desc, d_in, opts, out_cfg, h_block_cfg, block_cfg_cap, f32, rcs,
+                           stream);
+  if (!rc && !f64.empty())
+    rc = tune_group<double>(ctx, desc, d_in, opts, out_cfg, h_block_cfg, block_cfg_cap, f64, rcs,
+                            stream);
+  if (rc) return rc;
+  for (int i = 0; i < n; i++)
+    if (rcs[i]) return rcs[i];
+  return HPEZ_OK;
+}
 
 extern "C" int hpez_tune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
                          const hpez_tune_opts* opts, hpez_config* out_cfg, uint8_t* h_block_cfg,
                          uint64_t block_cfg_cap, hipStream_t stream)
 {
   if (!ctx || !desc || !d_in || !opts || !out_cfg) return HPEZ_EINVAL;
-  int rc = check_desc(desc);
-  if (rc) return rc;
-  DeviceGuard dg(ctx_device(ctx));
-  if (desc->dtype == HPEZ_F32)
-    return tune_t<float>(ctx, desc, (const float*)d_in, opts, out_cfg, h_block_cfg, block_cfg_cap,
-                         stream);
-  return tune_t<double>(ctx, desc, (const double*)d_in, opts, out_cfg, h_block_cfg, block_cfg_cap,
-                        stream);
+  int rc1 = HPEZ_OK;
+  const int rc =
+      hpez_tune_batch(ctx, 1, desc, &d_in, opts, out_cfg, &h_block_cfg, &block_cfg_cap, &rc1, stream);
+  return rc ? rc : rc1;
 }

@@ -33,6 +33,19 @@ struct TrialArgs {
   double wmd[3 * 8 * 4];  // MD weights [kind][odd set][dim] (Eq. 12), first three dims
 };
 
+// One tuning run's trials in a fused launch: n_boxes regions x n_cand
+// candidates, work-groups [wg_begin, wg_begin + n_boxes * n_cand) of the launch.
+template <typename T>
+struct TrialJob {
+  TrialArgs a;
+  const TrialBox* boxes;
+  const T* X;
+  unsigned long long* score;
+  uint32_t* hist;
+  uint32_t n_boxes, n_cand;
+  uint64_t wg_begin;
+};
+
 #ifdef __HIPCC__
 // Sum over the work-group; every thread receives the total.
 __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
@@ -56,6 +69,16 @@ template <typename T>
 hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n_boxes,
                          uint32_t n_cand, const T* X, T* scratch, const double* d_wq,
                          unsigned long long* d_score, uint32_t* d_hist, hipStream_t st);
+// regions that fit the in-LDS box kernel (the fused launches take only these)
+template <typename T>
+bool trial_box_ok(const TrialArgs& a, bool hist);
+template <typename T>
+size_t trial_box_lds(const TrialArgs& a, bool hist);
+// entries [0, n) of d_jobs in one launch of total_wg work-groups; lds = the
+// largest entry's trial_box_lds; big: regions of more than 4096 points
+template <typename T>
+hipError_t launch_trial_jobs(const TrialJob<T>* d_jobs, const uint64_t* d_wg_begin, int n,
+                             uint64_t total_wg, size_t lds, bool hist, bool big, hipStream_t st);
 template <typename T>
 hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_t n_boxes,
                                 uint32_t max_pts, const T* X, double inv2e, uint32_t R,
