@@ -60,6 +60,14 @@ def main():
     ap.add_argument("--shape", default="512,512,512")
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-plain measurement on the 48-field workload")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving measurement (Poisson request stream)")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (x3): the reference for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -163,6 +171,17 @@ def main():
                       GBps=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
 
+    batch = None
+    if not args.no_batch:
+        del out, rec
+        torch.cuda.empty_cache()
+        batch = batch_section(args, binding, fields, torch)
+
+    serving = None
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        serving = serving_section(args, binding, fields, torch, nbytes / comp_s / 1e9)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x, cfg_used, nbytes)
@@ -196,8 +215,211 @@ def main():
         "roofline": roofline,
         "kernel_groups": groups,
         "cpu_baseline": cpu,
+        "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(res))
+
+
+def batch_section(args, binding, fields, torch):
+    """Batched vs plain on the uneven 48-field workload: 16 x 100x500x500,
+    16 x 1800x3600, 16 x U[64,449]^3 float32 fields with E(k) ~ k^-5/3 spectra
+    (generated on the device), per-field relative bounds from {1e-2, 1e-3, 1e-4}.
+    Plain: per field hpez_tune then hpez_compress, one stream.  Batched:
+    hpez_tune_batch then hpez_compress_batch.  Decompression likewise.  The
+    streams of both forms are compared byte for byte on the device."""
+    shapes, ebs = fields.batch_shapes()
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    xs = [fields.gaussian_field_device(sh, -5.0 / 3.0, 4000 + i, dev, torch.float32)
+          for i, sh in enumerate(shapes)]
+    torch.cuda.synchronize()
+    nbytes = sum(x.numel() * 4 for x in xs)
+    log(f"batch workload: {len(xs)} fields, {nbytes / 1e9:.2f} GB, made in {time.time() - t0:.1f} s")
+    base = [base_config(sh, eb) for sh, eb in zip(shapes, ebs)]
+    caps = [binding.compress_bound(sh, "f32", b) for sh, b in zip(shapes, base)]
+    outs_p = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    outs_b = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    recs_p = [torch.empty_like(x) for x in xs]
+    recs_b = [torch.empty_like(x) for x in xs]
+
+    def plain():
+        ta = time.perf_counter()
+        ss = []
+        for x, b, o in zip(xs, base, outs_p):
+            c = binding.tune(x, b, TUNE_OPTS)
+            ss.append(binding.compress(x, c, out=o))
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for s, r in zip(ss, recs_p):
+            binding.decompress(s, out=r)
+        torch.cuda.synchronize()
+        return tb - ta, time.perf_counter() - tb, ss
+
+    def batched():
+        ta = time.perf_counter()
+        cs = binding.tune_batch(xs, base, TUNE_OPTS)
+        ss = binding.compress_batch(xs, cs, outs=outs_b)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        binding.decompress_batch(ss, outs=recs_b)
+        torch.cuda.synchronize()
+        return tb - ta, time.perf_counter() - tb, ss
+
+    plain()
+    batched()
+    binding.profile_enable(0, True)
+    batched()
+    stats = binding.profile_read(0)
+    binding.profile_enable(0, False)
+    groups = {k: dict(ms=round(v["ms"], 3),
+                      GBps=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
+              for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
+    tp, tb_ = [], []
+    for i in range(args.batch_steps):
+        tp.append(plain())
+        tb_.append(batched())
+        log(f"batch step {i}: plain tune+compress {tp[-1][0]*1e3:.1f} ms decompress "
+            f"{tp[-1][1]*1e3:.1f} ms | batched {tb_[-1][0]*1e3:.1f} ms / {tb_[-1][1]*1e3:.1f} ms")
+    sp, sb = tp[-1][2], tb_[-1][2]
+    same = all(a.numel() == b.numel() and bool(torch.equal(a, b)) for a, b in zip(sp, sb))
+    same_rec = all(bool(torch.equal(a.view(torch.int32), b.view(torch.int32)))
+                   for a, b in zip(recs_p, recs_b))
+    if not (same and same_rec):
+        raise SystemExit("batched results differ from the plain calls'")
+    med = lambda v: sorted(v)[len(v) // 2]
+    pc, pd = med([t[0] for t in tp]), med([t[1] for t in tp])
+    bc, bd = med([t[0] for t in tb_]), med([t[1] for t in tb_])
+    comp = sum(s.numel() for s in sb)
+    return {
+        "workload": "48 fields: 16x100x500x500, 16x1800x3600, 16xU[64,449]^3 float32, k^-5/3, "
+                    "rel eb from {1e-2,1e-3,1e-4}",
+        "fields": len(xs), "bytes": nbytes, "compression_ratio": round(nbytes / comp, 3),
+        "plain_tune_compress_ms": round(pc * 1e3, 2), "batched_tune_compress_ms": round(bc * 1e3, 2),
+        "speedup_tune_compress": round(pc / bc, 3),
+        "plain_decompress_ms": round(pd * 1e3, 2), "batched_decompress_ms": round(bd * 1e3, 2),
+        "speedup_decompress": round(pd / bd, 3),
+        "batched_tune_compress_GBps": round(nbytes / bc / 1e9, 2),
+        "batched_decompress_GBps": round(nbytes / bd / 1e9, 2),
+        "identical": True,
+        "kernel_groups_batched": groups,
+    }
+
+
+def serving_section(args, binding, fields, torch, compress_gbps):
+    """Serving: a Poisson stream of compress / decompress requests through the
+    continuous-batching server (paper_2311_12133_amd.serve).  Sizes log-uniform
+    in [1 MB, 2 GB], 2-D / 3-D half each with aspect ratios log-uniform in
+    [1/2, 2], float32 80 % / float64 20 %, relative bounds log-uniform in
+    [1e-6, 1e-2]; half the requests compress (auto-tuned) a new field, half
+    decompress a stream produced earlier in the run.  The arrival rate puts the
+    offered load at 0.7 x the measured plain compress rate.  Inputs are cut
+    from seeded device-resident master fields when a request arrives.  A
+    sample of served results is compared byte for byte with the same requests
+    run alone."""
+    import numpy as np
+    from paper_2311_12133_amd.serve import Request, Server
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(5005)
+    n = args.serve_requests
+    t0 = time.time()
+    # 2 GiB master fields with power-of-two sides; a request takes the leading
+    # corner of its shape (clamped to the master's sides)
+    master_shapes = {(torch.float32, 3): (512, 1024, 1024), (torch.float32, 2): (16384, 32768),
+                     (torch.float64, 3): (512, 512, 1024), (torch.float64, 2): (16384, 16384)}
+    masters = {}
+    for k, (key, shp) in enumerate(master_shapes.items()):
+        masters[key] = fields.gaussian_field_device(shp, -5.0 / 3.0, 7000 + k, dev, key[0])
+        torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    log(f"serving masters made in {time.time() - t0:.1f} s")
+
+    def shape_for(nbytes_req, nd, esz, m):
+        pts = max(64, nbytes_req // esz)
+        r = np.exp(rng.uniform(np.log(0.5), np.log(2.0), nd - 1))
+        base = (pts / np.prod(r)) ** (1.0 / nd)
+        dims = [base] + [base * v for v in r]
+        dims = [int(max(2, min(round(v), m.shape[i]))) for i, v in enumerate(dims)]
+        return tuple(dims)
+
+    mean_bytes = ((2 << 30) - (1 << 20)) / np.log((2 << 30) / (1 << 20))
+    lam = 0.7 * compress_gbps * 1e9 / mean_bytes
+    reqs, plan = [], []
+    t = 0.0
+    for i in range(n):
+        t += float(rng.exponential(1.0 / lam))
+        f64 = rng.uniform() < 0.2
+        dt, esz = (torch.float64, 8) if f64 else (torch.float32, 4)
+        nd = 2 if rng.uniform() < 0.5 else 3
+        size = int(np.exp(rng.uniform(np.log(1 << 20), np.log(2 << 30))))
+        shp = shape_for(size, nd, esz, masters[(dt, nd)])
+        eb = float(np.exp(rng.uniform(np.log(1e-6), np.log(1e-2))))
+        op = "compress" if (i < 4 or rng.uniform() < 0.5) else "decompress"
+        r = Request(rid=i, op=op, arrival=t, data=None,
+                    cfg=base_config(shp, eb) | {"dtype": "f64" if f64 else "f32"},
+                    tune=op == "compress", tune_opts=TUNE_OPTS if op == "compress" else None)
+        reqs.append(r)
+        plan.append((dt, nd, shp))
+    sample = set(int(v) for v in rng.choice(n, min(16, n), replace=False))
+    produced = []   # (stream, shape, dtype, cfg) of completed compressions
+    inputs = {}
+
+    def on_arrival(r):
+        dt, nd, shp = plan[r.rid]
+        if r.op == "compress":
+            m = masters[(dt, nd)]
+            r.data = m[tuple(slice(0, v) for v in shp)].contiguous()
+            torch.cuda.current_stream().synchronize()
+            if r.rid in sample:
+                inputs[r.rid] = r.data
+        else:
+            src = produced[int(rng.integers(0, len(produced)))] if produced else None
+            if src is None:   # nothing produced yet: compress one first, outside the clock
+                m = masters[(dt, nd)]
+                x = m[tuple(slice(0, v) for v in shp)].contiguous()
+                c = binding.tune(x, r.cfg, TUNE_OPTS)
+                src = (binding.compress(x, c).clone(), tuple(x.shape), x.dtype, c)
+                produced.append(src)
+            r.data, r.out_shape, r.out_dtype, r.cfg = src
+
+    def on_done(r):
+        if r.op == "compress" and not r.error:
+            produced.append((r.result, tuple(r.data.shape), r.data.dtype, r.config))
+            if len(produced) > 64:
+                produced.pop(0)
+        if r.rid not in sample:
+            r.data = None
+            if r.op == "decompress":
+                r.result = None
+
+    srv = Server(device=0, slots=args.serve_slots, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
+                 max_batch=16)
+    try:
+        st = srv.run(reqs, on_arrival=on_arrival, on_done=on_done)
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    # served == alone on the sample
+    checked = 0
+    for i in sorted(sample):
+        r = reqs[i]
+        if r.error:
+            continue
+        if r.op == "compress":
+            c = binding.tune(inputs[i], r.cfg, TUNE_OPTS)
+            ok = torch.equal(binding.compress(inputs[i], c), r.result)
+        else:
+            ok = torch.equal(binding.decompress(r.data).view(torch.uint8), r.result.view(torch.uint8))
+        if not ok:
+            raise SystemExit(f"served request {i} differs from the same request run alone")
+        checked += 1
+    st.update(rate_per_s=round(lam, 2), offered_GBps=round(lam * mean_bytes / 1e9, 2),
+              slots=args.serve_slots, hbm_budget_GB=args.serve_budget_gb,
+              identical_alone_checked=checked,
+              workload="Poisson stream, sizes log-uniform 1 MB-2 GB, 2-D/3-D, f32 80 % / f64 20 %, "
+                       "rel eb log-uniform [1e-6, 1e-2], 50 % tuned compress / 50 % decompress")
+    del masters
+    return st
 
 
 # Sources whose change invalidates a stored traffic measurement of a kernel group.

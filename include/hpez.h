@@ -146,6 +146,20 @@ const char* hpez_strerror(int code);
 int hpez_ctx_create(hpez_ctx** out, int device);
 void hpez_ctx_destroy(hpez_ctx* ctx);
 
+/* Free the context's device workspace (and its pinned staging) when larger
+ * than keep_bytes; the next call allocates again.  Call only between calls on
+ * the context (every entry point has finished its device work on return). */
+int hpez_ctx_trim(hpez_ctx* ctx, uint64_t keep_bytes);
+
+/* Cap the context's device workspace at max_workspace_bytes (0: no cap).  A
+ * call that needs more fails with HPEZ_ENOMEM before any device work, and the
+ * context stays usable: a server can bound each slot's memory and reject or
+ * retry such requests. */
+int hpez_ctx_set_limit(hpez_ctx* ctx, uint64_t max_workspace_bytes);
+
+/* Current device workspace of the context in bytes (host-only). */
+int hpez_ctx_workspace(const hpez_ctx* ctx, uint64_t* bytes);
+
 /* Default configuration for a field: interpolation, linear 1D style in natural
  * order on every level, anchor stride by dimension count, R = 32768,
  * chunk = 1024, alpha = beta = 1, unit MD weights, no block-wise, no freeze. */

@@ -61,7 +61,8 @@ class KernelStat(C.Structure):
 EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_default",
            "hpez_compress_bound", "hpez_compress", "hpez_inspect", "hpez_decompress",
            "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read",
-           "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch"]
+           "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch",
+           "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace"]
 
 _lib = None
 _lock = threading.Lock()
@@ -97,6 +98,9 @@ def lib():
                                                 P(C.c_int), vp]
             L.hpez_tune_batch.argtypes = [vp, C.c_int, P(FieldDesc), P(vp), P(TuneOpts),
                                           P(Config), P(vp), P(u64), P(C.c_int), vp]
+            L.hpez_ctx_trim.argtypes = [vp, u64]
+            L.hpez_ctx_set_limit.argtypes = [vp, u64]
+            L.hpez_ctx_workspace.argtypes = [vp, P(u64)]
             _lib = L
     return _lib
 
@@ -116,6 +120,56 @@ def ctx(device: int):
             _ctx[device] = p
         c = p
     return c
+
+
+class Context:
+    """A library context of its own (workspace, pinned staging), for callers
+    that drive several streams from several threads: one context per thread.
+    The calls below use a shared per-device context unless given one."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.ptr = C.c_void_p()
+        _check(lib().hpez_ctx_create(C.byref(self.ptr), device), "hpez_ctx_create")
+
+    def trim(self, keep_bytes: int = 0):
+        _check(lib().hpez_ctx_trim(self.ptr, int(keep_bytes)), "hpez_ctx_trim")
+
+    def set_limit(self, max_workspace_bytes: int):
+        _check(lib().hpez_ctx_set_limit(self.ptr, int(max_workspace_bytes)), "hpez_ctx_set_limit")
+
+    def workspace(self) -> int:
+        n = C.c_uint64()
+        _check(lib().hpez_ctx_workspace(self.ptr, C.byref(n)), "hpez_ctx_workspace")
+        return n.value
+
+    def close(self):
+        if self.ptr:
+            lib().hpez_ctx_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cx(context, device: int):
+    return context.ptr if context is not None else ctx(device)
+
+
+def footprint(dims, dtype: str, cfg: dict, op: str) -> int:
+    """Device bytes of the library's workspace for op ("compress",
+    "decompress", "tune") on such a field (hpez_footprint)."""
+    keep = []
+    d = desc_from(dims, dtype, cfg.get("eb", 1e-3), cfg.get("eb_mode", "rel"))
+    c = config_from(cfg, keep)
+    n = C.c_uint64()
+    _check(lib().hpez_footprint(C.byref(d), C.byref(c), {"compress": 0, "decompress": 1,
+                                                         "tune": 2}[op], C.byref(n)),
+           "hpez_footprint")
+    return n.value
 
 
 # ---------------------------------------------------------------------------
@@ -216,7 +270,7 @@ def compress_bound(dims, dtype: str, cfg: dict) -> int:
     return n.value
 
 
-def compress(x, cfg: dict, stream=None, out=None):
+def compress(x, cfg: dict, stream=None, out=None, context=None):
     """Compress a CUDA tensor (float32/float64, contiguous).  Returns a uint8 CUDA
     tensor holding the stream (a view of `out` when given)."""
     torch = _torch()
@@ -231,7 +285,7 @@ def compress(x, cfg: dict, stream=None, out=None):
     if out is None:
         out = torch.empty(cap.value, dtype=torch.uint8, device=x.device)
     n = C.c_uint64()
-    rc = lib().hpez_compress(ctx(x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
+    rc = lib().hpez_compress(_cx(context, x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
                              C.byref(c), C.c_void_p(out.data_ptr()), out.numel(), C.byref(n),
                              _stream_ptr(stream))
     _check(rc, "hpez_compress")
@@ -248,7 +302,7 @@ def inspect(header_bytes: bytes):
                 dtype="f64" if d.dtype else "f32", points=npts.value, total=tot.value)
 
 
-def decompress(stream_t, stream=None, out=None):
+def decompress(stream_t, stream=None, out=None, context=None):
     """Decompress a uint8 CUDA tensor holding a stream; returns the field."""
     torch = _torch()
     hdr = stream_t[:512].cpu().numpy().tobytes()
@@ -256,7 +310,8 @@ def decompress(stream_t, stream=None, out=None):
     dt = torch.float64 if info["dtype"] == "f64" else torch.float32
     if out is None:
         out = torch.empty(info["dims"], dtype=dt, device=stream_t.device)
-    rc = lib().hpez_decompress(ctx(stream_t.device.index or 0), C.c_void_p(stream_t.data_ptr()),
+    rc = lib().hpez_decompress(_cx(context, stream_t.device.index or 0),
+                               C.c_void_p(stream_t.data_ptr()),
                                stream_t.numel(), C.c_void_p(out.data_ptr()),
                                out.numel() * out.element_size(), _stream_ptr(stream))
     _check(rc, "hpez_decompress")
@@ -298,7 +353,7 @@ def _tuned_dict(cfg: dict, c: Config, bc, nb: int) -> dict:
     return res
 
 
-def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
+def tune(x, cfg: dict, opts: dict | None = None, stream=None, context=None) -> dict:
     """Run the auto-tuner on a CUDA tensor; returns a complete config dict."""
     dtype = _dtype_of(x)
     keep = []
@@ -307,14 +362,14 @@ def tune(x, cfg: dict, opts: dict | None = None, stream=None) -> dict:
     o = _tune_opts(opts)
     nb = _n_blocks(x.shape, o.block_log2)
     bc = np.zeros(max(nb, 1), dtype=np.uint8)
-    rc = lib().hpez_tune(ctx(x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
+    rc = lib().hpez_tune(_cx(context, x.device.index or 0), C.byref(d), C.c_void_p(x.data_ptr()),
                          C.byref(o), C.byref(c), bc.ctypes.data_as(C.c_void_p), bc.size,
                          _stream_ptr(stream))
     _check(rc, "hpez_tune")
     return _tuned_dict(cfg, c, bc, nb)
 
 
-def tune_batch(xs, cfgs, opts=None, stream=None) -> list:
+def tune_batch(xs, cfgs, opts=None, stream=None, context=None) -> list:
     """Tune many CUDA tensors in one call (trials of all fields in fused
     launches).  opts: one dict for all fields or a list of dicts."""
     n = len(xs)
@@ -342,12 +397,13 @@ def tune_batch(xs, cfgs, opts=None, stream=None) -> list:
         bcs.append(bc)
         bptr[i] = bc.ctypes.data
         bcap[i] = bc.size
-    rc = lib().hpez_tune_batch(ctx(dev), n, D, ins, O, Cs, bptr, bcap, rcs, _stream_ptr(stream))
+    rc = lib().hpez_tune_batch(_cx(context, dev), n, D, ins, O, Cs, bptr, bcap, rcs,
+                               _stream_ptr(stream))
     _check(rc, "hpez_tune_batch")
     return [_tuned_dict(cfgs[i], Cs[i], bcs[i], nbs[i]) for i in range(n)]
 
 
-def compress_batch(xs, cfgs, stream=None, outs=None) -> list:
+def compress_batch(xs, cfgs, stream=None, outs=None, context=None, sizes_out=None) -> list:
     """Compress many CUDA tensors in one call; returns one uint8 CUDA tensor
     per field (views of `outs` when given), each byte-identical to compress()."""
     torch = _torch()
@@ -376,12 +432,15 @@ def compress_batch(xs, cfgs, stream=None, outs=None) -> list:
         ins[i] = x.data_ptr()
         optr[i] = o.data_ptr()
         caps[i] = o.numel()
-    rc = lib().hpez_compress_batch(ctx(dev), n, D, ins, Cs, optr, caps, sizes, _stream_ptr(stream))
+    rc = lib().hpez_compress_batch(_cx(context, dev), n, D, ins, Cs, optr, caps, sizes,
+                                   _stream_ptr(stream))
+    if sizes_out is not None:
+        sizes_out[:] = [int(sizes[i]) for i in range(n)]
     _check(rc, "hpez_compress_batch")
     return [bufs[i][: sizes[i]] for i in range(n)]
 
 
-def decompress_batch(streams, stream=None, outs=None) -> list:
+def decompress_batch(streams, stream=None, outs=None, context=None, rcs_out=None) -> list:
     """Decompress many uint8 CUDA tensors (streams) in one call."""
     torch = _torch()
     n = len(streams)
@@ -404,7 +463,10 @@ def decompress_batch(streams, stream=None, outs=None) -> list:
         isz[i] = s.numel()
         optr[i] = o.data_ptr()
         caps[i] = o.numel() * o.element_size()
-    rc = lib().hpez_decompress_batch(ctx(dev), n, ins, isz, optr, caps, rcs, _stream_ptr(stream))
+    rc = lib().hpez_decompress_batch(_cx(context, dev), n, ins, isz, optr, caps, rcs,
+                                     _stream_ptr(stream))
+    if rcs_out is not None:
+        rcs_out[:] = [int(rcs[i]) for i in range(n)]
     _check(rc, "hpez_decompress_batch")
     return res
 

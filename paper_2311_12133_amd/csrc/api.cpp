@@ -38,6 +38,7 @@ struct hpez_ctx {
   size_t pinned_bytes = 0;
   uint8_t* pin_tab = nullptr;  // staging of the block phase's work tables
   size_t pin_tab_bytes = 0;
+  size_t ws_limit = 0;  // 0: no cap on the workspace
   // kernel timing (hpez_profile_enable)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -593,10 +594,12 @@ struct Bump {
 int ensure_ws(hpez_ctx* ctx, size_t bytes)
 {
   if (bytes <= ctx->ws_bytes) return HPEZ_OK;
+  if (ctx->ws_limit && bytes > ctx->ws_limit) return HPEZ_ENOMEM;
   if (ctx->ws) (void)hipFree(ctx->ws);
   ctx->ws = nullptr;
   ctx->ws_bytes = 0;
-  const size_t want = bytes + (bytes >> 4);
+  size_t want = bytes + (bytes >> 4);
+  if (ctx->ws_limit && want > ctx->ws_limit) want = ctx->ws_limit;
   if (hipMalloc(&ctx->ws, want) != hipSuccess) {
     ctx->ws = nullptr;
     return HPEZ_ENOMEM;
@@ -1535,6 +1538,37 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
+}
+
+int hpez_ctx_trim(hpez_ctx* ctx, uint64_t keep_bytes)
+{
+  if (!ctx) return HPEZ_EINVAL;
+  DevScope ds(ctx->device);
+  if (ctx->ws && ctx->ws_bytes > keep_bytes) {
+    if (hipFree(ctx->ws) != hipSuccess) return HPEZ_EDEVICE;
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  if (ctx->pinned && ctx->pinned_bytes > keep_bytes) {
+    (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+  }
+  return HPEZ_OK;
+}
+
+int hpez_ctx_set_limit(hpez_ctx* ctx, uint64_t max_workspace_bytes)
+{
+  if (!ctx) return HPEZ_EINVAL;
+  ctx->ws_limit = (size_t)max_workspace_bytes;
+  return HPEZ_OK;
+}
+
+int hpez_ctx_workspace(const hpez_ctx* ctx, uint64_t* bytes)
+{
+  if (!ctx || !bytes) return HPEZ_EINVAL;
+  *bytes = ctx->ws_bytes;
+  return HPEZ_OK;
 }
 
 int hpez_config_default(const hpez_field_desc* d, hpez_config* c)

@@ -60,6 +60,56 @@ def gaussian_field(shape, slope: float, rng: np.random.Generator) -> np.ndarray:
     return g
 
 
+def _pow2_size(n: int) -> int:
+    """Smallest power of two >= n."""
+    m = 1
+    while m < n:
+        m *= 2
+    return m
+
+
+def gaussian_field_device(shape, slope: float, seed: int, device, dtype=None):
+    """The same construction as gaussian_field, on a torch device (float64 FFTs)
+    with torch's seeded normal generator: for workloads too large to synthesise
+    on the host within a benchmark run.  The field is synthesised on the
+    smallest enclosing grid with power-of-two sides (transform sizes with
+    precompiled kernels) and cropped; the crop of a stationary field has the
+    same spectrum.  Deterministic
+    for a given seed and device type; its values differ from gaussian_field's."""
+    import torch
+    want = tuple(int(s) for s in shape)
+    shape = tuple(_pow2_size(s) for s in want)
+    D = len(shape)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + int(seed))
+    noise = torch.randn(shape, generator=gen, dtype=torch.float64, device=device)
+    spec = torch.fft.rfftn(noise)
+    del noise
+    k2 = None
+    for ax, n in enumerate(shape):
+        if ax == D - 1:
+            f = torch.fft.rfftfreq(n, dtype=torch.float64, device=device) * n
+        else:
+            f = torch.fft.fftfreq(n, dtype=torch.float64, device=device) * n
+        sh = [1] * D
+        sh[ax] = f.numel()
+        term = f.reshape(sh) ** 2
+        k2 = term if k2 is None else k2 + term
+    gamma = (slope - (D - 1)) / 2.0
+    amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (gamma / 2.0), torch.zeros_like(k2))
+    del k2
+    spec *= amp
+    del amp
+    g = torch.fft.irfftn(spec, s=shape, dim=tuple(range(D)))
+    del spec
+    g = g[tuple(slice(0, n) for n in want)].contiguous()
+    g -= g.mean()
+    sd = g.std(unbiased=False)
+    if sd > 0:
+        g /= sd
+    return g if dtype is None else g.to(dtype)
+
+
 def fronts(shape, count: int, width: float, amp: float, rng: np.random.Generator) -> np.ndarray:
     """Sum of `count` tanh fronts amp * tanh(n.(x - c) / width) with random unit
     normals n and centres c uniform in the box (float64)."""
