@@ -10,6 +10,25 @@
 
 namespace hpez {
 
+// Pointers into device global memory.  Accesses through them compile to
+// global_* instructions.  Through a generic pointer the compiler must emit
+// flat_* instructions (e.g. for pointers read from a table in memory), and a
+// flat access also counts against the LDS wait counter: every later LDS wait
+// would then wait for outstanding global loads and stores as well.
+#define HPEZ_GLOBAL __attribute__((address_space(1)))
+#ifdef __HIPCC__
+template <typename T>
+__device__ __forceinline__ HPEZ_GLOBAL T* gmem(T* p)
+{
+  return (HPEZ_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const HPEZ_GLOBAL T* gmem(const T* p)
+{
+  return (const HPEZ_GLOBAL T*)p;
+}
+#endif
+
 template <typename T>
 struct SplineK;
 template <>

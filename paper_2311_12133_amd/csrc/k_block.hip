@@ -51,7 +51,7 @@ __device__ __forceinline__ void face_store(const FaceGeo& f, const Geom& g, cons
 {
   for (int e = 0; e < 4; e++) {
     if (!g.act[e] || (x[e] & (f.B - 1))) continue;
-    reinterpret_cast<T*>(f.val[e])[face_index(f, e, x)] = v;
+    gmem(reinterpret_cast<T*>(f.val[e]))[face_index(f, e, x)] = v;
   }
 }
 
@@ -97,9 +97,9 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
   const FaceEntry<T>& E = tab[ei];
   const FaceStep& a = E.a;
   const FaceGeo& f = E.f;
-  const T* __restrict__ X = E.X;
-  uint16_t* __restrict__ code = E.code;
-  const T* __restrict__ out = E.out;
+  const HPEZ_GLOBAL T* __restrict__ X = gmem(E.X);
+  const HPEZ_GLOBAL uint16_t* __restrict__ code = gmem(E.code);
+  const HPEZ_GLOBAL T* __restrict__ out = gmem(E.out);
   const I total = (I)a.off[4];
   const I stride = (I)E.wg_count * blockDim.x;
   for (I k = (I)(blockIdx.x - E.wg_begin) * blockDim.x + threadIdx.x; k < total; k += stride) {
@@ -124,18 +124,20 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
     for (int e = 0; e < 3; e++)
       if (e < d && a.g.act[e] && (x[e] & (f.B - 1)) == 0) skip = true;  // belongs to family e
     if (skip) continue;
-    const T* __restrict__ F = reinterpret_cast<const T*>(f.val[d]);
+    const HPEZ_GLOBAL T* __restrict__ F = gmem(reinterpret_cast<const T*>(f.val[d]));
     const int64_t fi = face_index(f, d, x);
     T p;
     if (!a.md) {
       const int e = a.pdim;
-      p = spline<T, T>(F, fi, a.s * f.fs[d][e], x[e], a.s, 0, a.g.n[e] - 1, a.kind, a.sl);
+      p = spline<T, HPEZ_GLOBAL T>(F, fi, a.s * f.fs[d][e], x[e], a.s, 0, a.g.n[e] - 1, a.kind,
+                                   a.sl);
     } else {
       bool first = true;
       T acc = (T)0;
       for (int e = 0; e < 4; e++) {
         if (!(a.odd >> e & 1u)) continue;
-        const T pe = spline<T, T>(F, fi, a.s * f.fs[d][e], x[e], a.s, 0, a.g.n[e] - 1, a.kind, 0);
+        const T pe = spline<T, HPEZ_GLOBAL T>(F, fi, a.s * f.fs[d][e], x[e], a.s, 0, a.g.n[e] - 1,
+                                              a.kind, 0);
         const T term = (T)a.wq[e] * pe;
         acc = first ? term : acc + term;
         first = false;
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
       const T xv = X[idx];
       T xr = xv;
       const uint32_t q = quantize<T>(xv, p, a.inv2e, a.twoe, a.el, a.R, xr);
-      f.code[d][fi] = (uint16_t)q;  // d is the point's lowest family
+      gmem(f.code[d])[fi] = (uint16_t)q;  // d is the point's lowest family
       face_store<T>(f, a.g, x, xr);
     } else {
       const uint32_t q = code[brick_pos(a.g.n, x)];
@@ -203,15 +205,20 @@ template <typename T>
 struct Quad {
   T v[4];
 };
-__device__ __forceinline__ Quad<float> load_quad(const float* p)
+// plain vector types (no class constructors, so loads and stores work through
+// address-space qualified pointers)
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ Quad<float> load_quad(const HPEZ_GLOBAL float* p)
 {
-  const float4 q = *reinterpret_cast<const float4*>(p);
+  const vf4 q = *reinterpret_cast<const HPEZ_GLOBAL vf4*>(p);
   return {{q.x, q.y, q.z, q.w}};
 }
-__device__ __forceinline__ Quad<double> load_quad(const double* p)
+__device__ __forceinline__ Quad<double> load_quad(const HPEZ_GLOBAL double* p)
 {
-  const double2 a = reinterpret_cast<const double2*>(p)[0];
-  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  const vd2 a = reinterpret_cast<const HPEZ_GLOBAL vd2*>(p)[0];
+  const vd2 b = reinterpret_cast<const HPEZ_GLOBAL vd2*>(p)[1];
   return {{a.x, a.y, b.x, b.y}};
 }
 
@@ -221,10 +228,9 @@ template <typename T>
 struct CompressOp {
   using Fetched = int;
   T* L;
-  uint16_t* code;
+  HPEZ_GLOBAL uint16_t* code;  // the brick's codes
   uint32_t* lh;
-  uint32_t* hist;
-  uint64_t brick_base;
+  HPEZ_GLOBAL uint32_t* hist;
   int32_t Eb1, Eb2;
   uint32_t R, lo;
   double el, inv2e, twoe;
@@ -235,7 +241,7 @@ struct CompressOp {
     const T xv = L[li];
     T xr = xv;
     const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
-    code[brick_base + (uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] = (uint16_t)q;
+    code[(uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] = (uint16_t)q;
     L[li] = xr;
     // the most frequent code is counted in a register, the others in LDS
     nR += q == R;
@@ -256,16 +262,15 @@ template <typename T>
 struct DecompressOp {
   using Fetched = uint32_t;
   T* L;
-  const uint16_t* code;
-  const T* out;
-  uint64_t brick_base;
+  const HPEZ_GLOBAL uint16_t* code;  // the brick's codes
+  const HPEZ_GLOBAL T* out;
   int64_t o0, o1, o2, st0, st1;
   int32_t Eb1, Eb2;
   uint32_t R;
   double twoe;
   __device__ __forceinline__ uint32_t fetch(int32_t x0, int32_t x1, int32_t x2, bool ok) const
   {
-    return ok ? (uint32_t)code[brick_base + (uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] : 0u;
+    return ok ? (uint32_t)code[(uint32_t)((x0 * Eb1 + x1) * Eb2 + x2)] : 0u;
   }
   __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
   {
@@ -299,7 +304,7 @@ __device__ __forceinline__ BoxItems box_items(const Box& bx)
 
 // the values of one item (cnt <= 4 cells; wr marks cells that are loaded)
 template <typename T, int MODE>
-__device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const T* __restrict__ X, int64_t st0,
+__device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL T* __restrict__ X, int64_t st0,
                                              int64_t st1, const Block3& bk, const Box& bx,
                                              const BoxItems& bi, uint32_t it, bool vec,
                                              int32_t& lbase, uint32_t& wr)
@@ -319,11 +324,11 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const T* __restri
   lbase = (c0 * bi.E1 + c1) * bi.E2 + cb;
   const bool face0 = bx.a0 && (c0 == 0 || c0 == kBrick);
   const bool face1 = !face0 && bx.a1 && (c1 == 0 || c1 == kBrick);
-  const T* src = nullptr;
+  const HPEZ_GLOBAL T* src = nullptr;
   if (face0)
-    src = reinterpret_cast<const T*>(f.val[0]) + (x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2;
+    src = gmem(reinterpret_cast<const T*>(f.val[0])) + (x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2;
   else if (face1)
-    src = reinterpret_cast<const T*>(f.val[1]) + (x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2;
+    src = gmem(reinterpret_cast<const T*>(f.val[1])) + (x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2;
   else if (MODE == 0 && cb < kBrick)
     src = X + x0 * st0 + x1 * st1 + x2;  // (cell c2 = 32 is the next block's face value)
   if (src) {
@@ -338,8 +343,8 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const T* __restri
   }
   if (!face0 && !face1 && bx.a2 && (cb == 0 || cb == kBrick)) {
     // the row's cell on a dim-2 face
-    v.v[0] = reinterpret_cast<const T*>(f.val[2])[(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] +
-                                                  x1 * f.fs[2][1]];
+    v.v[0] = gmem(reinterpret_cast<const T*>(f.val[2]))[(x2 >> f.blog2) * f.plane[2] +
+                                                        x0 * f.fs[2][0] + x1 * f.fs[2][1]];
     wr |= 1u;
   }
   return v;
@@ -385,8 +390,8 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
     const BoxItems its = box_items(bx);
 #pragma unroll
     for (int u = 0; u < UP; u++)
-      pv[u] = load_item<T, MODE>(J.f, J.X, J.a.g.st[0], J.a.g.st[1], bk, bx, its, threadIdx.x + u * NT,
-                                 J.a.vec != 0, plb[u], pwr[u]);
+      pv[u] = load_item<T, MODE>(J.f, gmem(J.X), J.a.g.st[0], J.a.g.st[1], bk, bx, its,
+                                 threadIdx.x + u * NT, J.a.vec != 0, plb[u], pwr[u]);
   }
 
   while (gbi < nbt) {
@@ -396,10 +401,10 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
     const BlockJobDev<T>& J = jobs[jb];
     const BlockArgs& a = J.a;
     const FaceGeo& f = J.f;
-    const T* __restrict__ X = J.X;
-    uint16_t* __restrict__ code = J.code;
-    uint32_t* __restrict__ hist = J.hist;
-    T* __restrict__ out = J.out;
+    const HPEZ_GLOBAL T* __restrict__ X = gmem(J.X);
+    HPEZ_GLOBAL uint16_t* __restrict__ code = gmem(J.code);
+    HPEZ_GLOBAL uint32_t* __restrict__ hist = gmem(J.hist);
+    HPEZ_GLOBAL T* __restrict__ out = gmem(J.out);
     const uint64_t bi = gbi - begin[jb];
     const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
     const uint32_t lo = a.hist_lo;
@@ -459,21 +464,21 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         if (j < f0n) {
           const int32_t c1 = (int32_t)fdiv((uint32_t)j, dE2), c2 = j - c1 * Eb2;
           fcd[u] = (uint32_t)(c1 * Eb2 + c2);
-          fcv[u] = f.code[0][(bk.o0 >> f.blog2) * f.plane[0] + (bk.o1 + c1) * f.fs[0][1] +
+          fcv[u] = gmem(f.code[0])[(bk.o0 >> f.blog2) * f.plane[0] + (bk.o1 + c1) * f.fs[0][1] +
                              (bk.o2 + c2) * f.fs[0][2]];
         } else if (j < f0n + f1n) {
           const int32_t jj = j - f0n;
           const int32_t q = (int32_t)fdiv((uint32_t)jj, dE2);
           const int32_t c0 = r0 + q, c2 = jj - q * Eb2;
           fcd[u] = (uint32_t)(c0 * Eb1 * Eb2 + c2);
-          fcv[u] = f.code[1][(bk.o1 >> f.blog2) * f.plane[1] + (bk.o0 + c0) * f.fs[1][0] +
+          fcv[u] = gmem(f.code[1])[(bk.o1 >> f.blog2) * f.plane[1] + (bk.o0 + c0) * f.fs[1][0] +
                              (bk.o2 + c2) * f.fs[1][2]];
         } else {
           const int32_t jj = j - f0n - f1n;
           const int32_t q = (int32_t)fdiv((uint32_t)jj, dE1);
           const int32_t c0 = r0 + q, c1 = r1 + (jj - q * (Eb1 - r1));
           fcd[u] = (uint32_t)((c0 * Eb1 + c1) * Eb2);
-          fcv[u] = f.code[2][(bk.o2 >> f.blog2) * f.plane[2] + (bk.o0 + c0) * f.fs[2][0] +
+          fcv[u] = gmem(f.code[2])[(bk.o2 >> f.blog2) * f.plane[2] + (bk.o0 + c0) * f.fs[2][0] +
                              (bk.o1 + c1) * f.fs[2][1]];
         }
       }
@@ -490,22 +495,22 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
       const BoxItems its2 = box_items(bx2);
 #pragma unroll
       for (int u = 0; u < UP; u++)
-        pv[u] = load_item<T, MODE>(J2.f, J2.X, J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,
+        pv[u] = load_item<T, MODE>(J2.f, gmem(J2.X), J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,
                                    threadIdx.x + u * NT, J2.a.vec != 0, plb[u], pwr[u]);
     }
 
     // ---- the levels below B with the block's configuration
-    const hpez_interp c = a.cand[J.bcfg[bi]];
+    const hpez_interp c = a.cand[gmem(J.bcfg)[bi]];
     uint32_t nR = 0;
     for (int l = a.L; l >= 1; l--) {
       const int32_t s = 1 << (l - 1);
       if (MODE == 0) {
-        CompressOp<T> op{L,  code, lh, hist, brick_base, Eb1, Eb2, a.R, lo, a.el_l[l], a.inv2e_l[l],
+        CompressOp<T> op{L,  code + brick_base, lh, hist, Eb1, Eb2, a.R, lo, a.el_l[l], a.inv2e_l[l],
                          a.twoe_l[l], 0u};
         box_level<T, NT>(c, bx, L, bk.o0, bk.o1, bk.o2, s, a.wmd, op);
         nR += op.nR;
       } else {
-        DecompressOp<T> op{L, code, out, brick_base, bk.o0, bk.o1, bk.o2, st0, st1, Eb1, Eb2, a.R,
+        DecompressOp<T> op{L, code + brick_base, out, bk.o0, bk.o1, bk.o2, st0, st1, Eb1, Eb2, a.R,
                            a.twoe_l[l]};
         box_level<T, NT>(c, bx, L, bk.o0, bk.o1, bk.o2, s, a.wmd, op);
       }
@@ -524,15 +529,17 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         const uint32_t c1 = r - c0 * (uint32_t)Eb1;
         const int32_t cb = 4 * (int32_t)q;
         const int32_t cnt = Eb2 - cb < 4 ? Eb2 - cb : 4;
-        T* dst = out + (bk.o0 + c0) * st0 + (bk.o1 + c1) * st1 + (bk.o2 + cb);
+        HPEZ_GLOBAL T* dst = out + (bk.o0 + c0) * st0 + (bk.o1 + c1) * st1 + (bk.o2 + cb);
         const int32_t lb = (int32_t)(c0 * E1 + c1) * E2 + cb;
         if (vec && cnt == 4) {
           if constexpr (sizeof(T) == 4) {
-            *reinterpret_cast<float4*>(dst) =
-                make_float4((float)L[lb], (float)L[lb + 1], (float)L[lb + 2], (float)L[lb + 3]);
+            const vf4 v = {(float)L[lb], (float)L[lb + 1], (float)L[lb + 2], (float)L[lb + 3]};
+            *reinterpret_cast<HPEZ_GLOBAL vf4*>(dst) = v;
           } else {
-            reinterpret_cast<double2*>(dst)[0] = make_double2((double)L[lb], (double)L[lb + 1]);
-            reinterpret_cast<double2*>(dst)[1] = make_double2((double)L[lb + 2], (double)L[lb + 3]);
+            const vd2 v0 = {(double)L[lb], (double)L[lb + 1]};
+            const vd2 v1 = {(double)L[lb + 2], (double)L[lb + 3]};
+            reinterpret_cast<HPEZ_GLOBAL vd2*>(dst)[0] = v0;
+            reinterpret_cast<HPEZ_GLOBAL vd2*>(dst)[1] = v1;
           }
         } else {
           for (int j = 0; j < cnt; j++) dst[j] = L[lb + j];
@@ -559,11 +566,11 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
       if ((threadIdx.x & 63) == 0 && nR) {
         const uint32_t w = a.R - lo;
         if (w < (uint32_t)kBlockHistWin) atomicAdd(&lh[w], nR);
-        else atomicAdd(&hist[a.R], nR);
+        else __hip_atomic_fetch_add(&hist[a.R], nR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
       for (int i = threadIdx.x; i < kBlockHistWin; i += NT)
-        if (lh[i]) atomicAdd(&hist[lo + i], lh[i]);
+        if (lh[i]) __hip_atomic_fetch_add(&hist[lo + i], lh[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     gbi = bn;
   }

@@ -262,7 +262,7 @@ struct TrialOp {
   using Fetched = int;
   T* L;
   uint32_t* lh;
-  uint32_t* hist;
+  HPEZ_GLOBAL uint32_t* hist;
   uint32_t R, lo;
   double el, inv2e, twoe, mul;
   unsigned long long sc;
@@ -295,10 +295,11 @@ struct TrialOp {
 // region is tb (index ib of n_cand-wide score rows), the candidate cand.
 template <typename T, bool HIST, int NT>
 __device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox& tb, uint32_t ib,
-                                              int cand, uint32_t n_cand, const T* __restrict__ X,
-                                              unsigned long long* __restrict__ score,
-                                              uint32_t* __restrict__ hist, unsigned char* lds_raw,
-                                              unsigned long long* red)
+                                              int cand, uint32_t n_cand,
+                                              const HPEZ_GLOBAL T* __restrict__ X,
+                                              HPEZ_GLOBAL unsigned long long* __restrict__ score,
+                                              HPEZ_GLOBAL uint32_t* __restrict__ hist,
+                                              unsigned char* lds_raw, unsigned long long* red)
 {
   T* L = reinterpret_cast<T*>(lds_raw);
   uint32_t* lh = reinterpret_cast<uint32_t*>(lds_raw + ((a.box_cap * sizeof(T) + 15) & ~15ull));
@@ -321,7 +322,7 @@ __device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox
   const Divisor mgb0 = fmagic((uint32_t)bx.b0);
   const Divisor mgE2 = fmagic((uint32_t)bx.E2);
   const int64_t st0 = a.fg.st[0], st1 = a.fg.st[1];
-  const T* __restrict__ Xo = X + tb.o[0] * st0 + tb.o[1] * st1 + tb.o[2];
+  const HPEZ_GLOBAL T* __restrict__ Xo = X + tb.o[0] * st0 + tb.o[1] * st1 + tb.o[2];
   for (uint32_t i = threadIdx.x; i < npts; i += NT) {
     const uint32_t c0 = fdiv(i, mgb0);
     const uint32_t rem = i - c0 * (uint32_t)bx.b0;
@@ -345,7 +346,9 @@ __device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox
     nR += op.nR;
     const unsigned long long v = block_sum_u64(op.sc, red);
     if (score_mode == 0) {
-      if (threadIdx.x == 0 && v) atomicAdd(&score[cand * 16 + (l - 1)], v);
+      if (threadIdx.x == 0 && v)
+        __hip_atomic_fetch_add(&score[cand * 16 + (l - 1)], v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     } else {
       total_score += v;
     }
@@ -356,11 +359,13 @@ __device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox
     if ((threadIdx.x & 63) == 0 && nR) {
       const uint32_t w = R - hist_lo;
       if (w < kTrialHistWin) atomicAdd(&lh[w], nR);
-      else atomicAdd(&hist[R], nR);
+      else __hip_atomic_fetch_add(&hist[R], nR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += NT)
-      if (lh[i]) atomicAdd(&hist[hist_lo + i], lh[i]);
+      if (lh[i])
+        __hip_atomic_fetch_add(&hist[hist_lo + i], lh[i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -372,8 +377,8 @@ __global__ void __launch_bounds__(NT) trial_box_kernel(TrialArgs a, const TrialB
 {
   extern __shared__ unsigned char lds_raw[];
   __shared__ unsigned long long red[16];
-  trial_box_run<T, HIST, NT>(a, boxes[blockIdx.x], blockIdx.x, (int)blockIdx.y, gridDim.y, X, score,
-                             hist, lds_raw, red);
+  trial_box_run<T, HIST, NT>(a, boxes[blockIdx.x], blockIdx.x, (int)blockIdx.y, gridDim.y, gmem(X),
+                             gmem(score), gmem(hist), lds_raw, red);
 }
 
 // index of the last entry whose begin is <= x (begin ascending, begin[0] = 0)
@@ -403,7 +408,8 @@ __global__ void __launch_bounds__(NT) trial_jobs_kernel(const TrialJob<T>* __res
   const uint32_t local = (uint32_t)(blockIdx.x - J.wg_begin);
   const uint32_t ib = local / nc;
   const int cand = (int)(local - ib * nc);
-  trial_box_run<T, HIST, NT>(J.a, J.boxes[ib], ib, cand, nc, J.X, J.score, J.hist, lds_raw, red);
+  trial_box_run<T, HIST, NT>(J.a, J.boxes[ib], ib, cand, nc, gmem(J.X), gmem(J.score),
+                             gmem(J.hist), lds_raw, red);
 }
 
 template <typename T>
