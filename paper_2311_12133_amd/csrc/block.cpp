@@ -62,6 +62,11 @@ size_t block_fast_bytes(const Geom& g)
   size_t b = 0;
   for (int e = 0; e < 4; e++)
     b += ((elems[e] * sizeof(T) + 255) & ~(size_t)255) + ((elems[e] * 2 + 255) & ~(size_t)255);
+  // the coarse levels' lattice values and codes, kCoarseCells per block
+  uint64_t nb = 1;
+  for (int k = 0; k < 4; k++) nb *= (uint64_t)((g.n[k] + kBrick - 1) / kBrick);
+  b += ((nb * kCoarseCells * sizeof(T) + 255) & ~(size_t)255) +
+       ((nb * kCoarseCells * 2 + 255) & ~(size_t)255);
   return b;
 }
 
@@ -93,6 +98,14 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
     p += (elems[k] * sizeof(T) + 255) & ~(size_t)255;
     J.f.code[k] = (uint16_t*)p;
     p += (elems[k] * 2 + 255) & ~(size_t)255;
+  }
+  {
+    uint64_t nb = 1;
+    for (int k = 0; k < 4; k++) nb *= (uint64_t)((g.n[k] + kBrick - 1) / kBrick);
+    J.cval = (T*)p;
+    p += (nb * kCoarseCells * sizeof(T) + 255) & ~(size_t)255;
+    J.ccode = (uint16_t*)p;
+    p += (nb * kCoarseCells * 2 + 255) & ~(size_t)255;
   }
   const int Lb = c->block_log2;
   const int nact = n_active(g);
@@ -326,6 +339,8 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
     hj[j].bcfg = jobs[j].d_bcfg;
     hj[j].hist = jobs[j].hist;
     hj[j].out = jobs[j].out;
+    hj[j].cval = jobs[j].cval;
+    hj[j].ccode = jobs[j].ccode;
     hj[j].block_begin = total_blocks;
     hb[j] = total_blocks;
     total_blocks += jobs[j].nblocks;
@@ -342,6 +357,13 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
                              L.cnt, L.wgs, L.narrow, mode, st));
   ctx_span_end(ctx, ev, mode == 0 ? "faces_predict" : "faces_reconstruct",
                face_pts * (sizeof(T) + 2), st);
+
+  // the coarse levels of every block on the block lattices
+  ev = ctx_span_begin(ctx, st);
+  BCK(launch_coarse_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
+                            n, total_blocks, mode, st));
+  ctx_span_end(ctx, ev, mode == 0 ? "coarse_predict" : "coarse_reconstruct",
+               total_blocks * 729ull * (sizeof(T) + 2), st);
 
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx_device(ctx)) !=

@@ -7,6 +7,10 @@ namespace hpez {
 
 constexpr int kBlockHistWin = 4096;  // LDS histogram window of the block kernel
 constexpr int kBlockThreads = 1024;  // work-group size of the block kernel
+// coarse levels on the block lattice: levels above kCoarseL (strides >= 4);
+// a block's lattice has at most 9 x 9 x 32 cells (one inactive dim of 32)
+constexpr int kCoarseL = 2;
+constexpr int kCoarseCells = 9 * 9 * 32;
 
 // Compact face arrays: family e holds the planes x_e = 0, B, 2B, ... with layout
 // [plane][other dims row-major]; index = (x_e / B) * plane[e] + sum_k x_k fs[e][k].
@@ -71,6 +75,8 @@ struct BlockJobDev {
   const uint8_t* bcfg;
   uint32_t* hist;
   T* out;
+  T* cval;          // per block kCoarseCells lattice values (coarse levels' output)
+  uint16_t* ccode;  // per block kCoarseCells lattice codes (compress)
   uint64_t block_begin;
 };
 
@@ -85,6 +91,10 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
                              uint64_t total_blocks, size_t lds, uint32_t* ticket, int n_cu,
                              int mode, hipStream_t st);
 
+// the coarse levels of every block of jobs [0, n) on the block lattices
+template <typename T>
+hipError_t launch_coarse_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
+                              uint64_t total_blocks, int mode, hipStream_t st);
 template <typename T>
 hipError_t launch_face_init(const FaceGeo& f, const Geom& g, const Lattice& lat, const T* W,
                             const uint16_t* code, int mode, hipStream_t st);

@@ -115,6 +115,8 @@ struct BlockJobHost {
   T* out = nullptr;        // decompress: the field
   // built by block_job_prepare
   FaceGeo f;
+  T* cval = nullptr;          // coarse levels' lattice values (in area)
+  uint16_t* ccode = nullptr;  // coarse levels' lattice codes (in area)
   BlockArgs ba;
   std::vector<FaceStep> steps[17];
   uint64_t nblocks = 0, npts = 0, face_pts = 0;

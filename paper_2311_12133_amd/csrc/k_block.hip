@@ -279,6 +279,139 @@ struct DecompressOp {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Coarse levels of the blocks (s >= kCoarseS) on each block's lattice: the box
+// cells whose coordinates are multiples of 4 along every active dim (all cells
+// along an inactive one).  In lattice coordinates (cell / 4 on active dims) a
+// level of stride s is a level of stride s / 4 with the same neighbours and the
+// same boundary ladder (last = floor((E - 1) / 4)), so the box schedule runs on
+// the lattice unchanged.  A block's lattice is small (at most 9 x 9 x 32
+// cells), so one wave takes a block and many blocks share a CU; the block
+// kernel then starts at level kCoarseL.  Output per block: the lattice values
+// (reconstructed) and, compressing, the codes of the lattice points.
+
+// lattice cells of a box: active dims (E - 1) / 4 + 1, inactive dims E
+__device__ __forceinline__ void lattice_box(const Box& bx, Box& lb)
+{
+  lb.E0 = bx.a0 ? (bx.E0 - 1) / 4 + 1 : bx.E0;
+  lb.E1 = bx.a1 ? (bx.E1 - 1) / 4 + 1 : bx.E1;
+  lb.E2 = bx.a2 ? (bx.E2 - 1) / 4 + 1 : bx.E2;
+  lb.b1 = lb.E2;
+  lb.b0 = lb.E1 * lb.E2;
+  lb.a0 = bx.a0;
+  lb.a1 = bx.a1;
+  lb.a2 = bx.a2;
+  lb.lo0 = bx.lo0;
+  lb.lo1 = bx.lo1;
+  lb.lo2 = bx.lo2;
+  lb.hi0 = bx.a0 ? bx.hi0 / 4 : bx.hi0;
+  lb.hi1 = bx.a1 ? bx.hi1 / 4 : bx.hi1;
+  lb.hi2 = bx.a2 ? bx.hi2 / 4 : bx.hi2;
+}
+
+template <typename T>
+struct CoarseCompressOp {
+  using Fetched = int;
+  T* L;
+  HPEZ_GLOBAL uint16_t* ccode;  // the block's lattice codes, lattice order
+  uint32_t R;
+  double el, inv2e, twoe;
+  __device__ __forceinline__ int fetch(int32_t, int32_t, int32_t, bool) const { return 0; }
+  __device__ __forceinline__ void apply(int32_t li, int32_t, int32_t, int32_t, T p, int)
+  {
+    const T xv = L[li];
+    T xr = xv;
+    const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
+    ccode[li] = (uint16_t)q;
+    L[li] = xr;
+  }
+};
+
+template <typename T>
+struct CoarseDecompressOp {
+  using Fetched = uint32_t;
+  T* L;
+  const HPEZ_GLOBAL uint16_t* code;  // the brick's codes
+  const HPEZ_GLOBAL T* out;
+  int64_t o0, o1, o2, st0, st1;
+  int32_t Eb1, Eb2;
+  int32_t k0, k1, k2;  // cells per lattice step (4 active, 1 inactive)
+  uint32_t R;
+  double twoe;
+  __device__ __forceinline__ uint32_t fetch(int32_t x0, int32_t x1, int32_t x2, bool ok) const
+  {
+    return ok ? (uint32_t)code[(uint32_t)((x0 * k0 * Eb1 + x1 * k1) * Eb2 + x2 * k2)] : 0u;
+  }
+  __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
+  {
+    L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
+              : out[(o0 + x0 * k0) * st0 + (o1 + x1 * k1) * st1 + (o2 + x2 * k2)];
+  }
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(64) coarse_kernel(const BlockJobDev<T>* __restrict__ jobs,
+                                                    const uint64_t* __restrict__ begin, int njobs)
+{
+  __shared__ T L[kCoarseCells];
+  const uint64_t gbi = blockIdx.x;
+  const int jb = find_entry(begin, njobs, gbi);
+  const BlockJobDev<T>& J = jobs[jb];
+  const BlockArgs& a = J.a;
+  const FaceGeo& f = J.f;
+  const uint64_t bi = gbi - begin[jb];
+  Block3 bk;
+  Box bx, lb;
+  block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
+  lattice_box(bx, lb);
+  const int32_t k0 = bx.a0 ? 4 : 1, k1 = bx.a1 ? 4 : 1, k2 = bx.a2 ? 4 : 1;
+  const uint32_t n = (uint32_t)(lb.E0 * lb.b0);
+  const Divisor mb0 = fmagic((uint32_t)lb.b0), mE2 = fmagic((uint32_t)lb.E2);
+  const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
+  const HPEZ_GLOBAL T* __restrict__ X = gmem(J.X);
+  // the lattice: face cells from the face arrays, the others from X (compress)
+  for (uint32_t i = threadIdx.x; i < n; i += 64) {
+    const uint32_t q0 = fdiv(i, mb0);
+    const uint32_t r = i - q0 * (uint32_t)lb.b0;
+    const uint32_t q1 = fdiv(r, mE2);
+    const int32_t c0 = (int32_t)q0 * k0, c1 = (int32_t)q1 * k1,
+                  c2 = (int32_t)(r - q1 * (uint32_t)lb.E2) * k2;
+    const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + c2;
+    T v = (T)0;
+    if (bx.a0 && (c0 == 0 || c0 == kBrick))
+      v = gmem(reinterpret_cast<const T*>(f.val[0]))[(x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] +
+                                                     x2];
+    else if (bx.a1 && (c1 == 0 || c1 == kBrick))
+      v = gmem(reinterpret_cast<const T*>(f.val[1]))[(x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] +
+                                                     x2];
+    else if (bx.a2 && (c2 == 0 || c2 == kBrick))
+      v = gmem(reinterpret_cast<const T*>(f.val[2]))[(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] +
+                                                     x1 * f.fs[2][1]];
+    else if (MODE == 0)
+      v = X[x0 * st0 + x1 * st1 + x2];
+    L[i] = v;
+  }
+  __syncthreads();
+  const hpez_interp c = a.cand[gmem(J.bcfg)[bi]];
+  const int64_t p0 = bk.o0 / k0, p1 = bk.o1 / k1, p2 = bk.o2 / k2;  // lattice origin
+  const uint64_t brick_base = (uint64_t)(bk.o0 * a.g.n[1] * a.g.n[2] +
+                                         bk.Eb0 * bk.o1 * a.g.n[2] + bk.Eb0 * bk.Eb1 * bk.o2);
+  for (int l = a.L; l > kCoarseL; l--) {
+    const int32_t s = 1 << (l - 1 - 2);  // lattice stride
+    if (MODE == 0) {
+      CoarseCompressOp<T> op{L, gmem(J.ccode) + bi * kCoarseCells, a.R, a.el_l[l], a.inv2e_l[l],
+                             a.twoe_l[l]};
+      box_level<T, 64>(c, lb, L, p0, p1, p2, s, a.wmd, op);
+    } else {
+      CoarseDecompressOp<T> op{L,  gmem(J.code) + brick_base, gmem(J.out), bk.o0, bk.o1, bk.o2,
+                               st0, st1, bk.Eb1, bk.Eb2, k0, k1, k2, a.R, a.twoe_l[l]};
+      box_level<T, 64>(c, lb, L, p0, p1, p2, s, a.wmd, op);
+    }
+  }
+  HPEZ_GLOBAL T* cv = gmem(J.cval) + bi * kCoarseCells;
+  for (uint32_t i = threadIdx.x; i < n; i += 64) cv[i] = L[i];
+}
+
 // Box loading: rows along dim 2 in quads of four cells.  Face rows (c0 or c1
 // on a block face) come from the face arrays, cells c2 = 0 / 32 from the dim-2
 // faces, everything else from X (compress only).  Item `it` of a block is row
@@ -440,6 +573,23 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         for (int u = 0; u < UL; u++) store_item<T>(L, v[u], lb[u], wr[u]);
       }
     }
+    // the lattice cells hold the coarse levels' results
+    __syncthreads();
+    Box lb;
+    lattice_box(bx, lb);
+    const int32_t lk0 = bx.a0 ? 4 : 1, lk1 = bx.a1 ? 4 : 1, lk2 = bx.a2 ? 4 : 1;
+    const uint32_t nlat = (uint32_t)(lb.E0 * lb.b0);
+    const Divisor mlb0 = fmagic((uint32_t)lb.b0), mlE2 = fmagic((uint32_t)lb.E2);
+    {
+      const HPEZ_GLOBAL T* cv = gmem(J.cval) + bi * kCoarseCells;
+      for (uint32_t i = threadIdx.x; i < nlat; i += NT) {
+        const uint32_t q0 = fdiv(i, mlb0);
+        const uint32_t r = i - q0 * (uint32_t)lb.b0;
+        const uint32_t q1 = fdiv(r, mlE2);
+        const uint32_t q2 = r - q1 * (uint32_t)lb.E2;
+        L[((int32_t)q0 * lk0 * E1 + (int32_t)q1 * lk1) * E2 + (int32_t)q2 * lk2] = cv[i];
+      }
+    }
     // compress: the codes of the brick's own faces (c_d = 0 on an active dim)
     // from the face code arrays; loaded now, stored and counted after the
     // levels, so the loads complete while the block computes
@@ -502,7 +652,7 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
     // ---- the levels below B with the block's configuration
     const hpez_interp c = a.cand[gmem(J.bcfg)[bi]];
     uint32_t nR = 0;
-    for (int l = a.L; l >= 1; l--) {
+    for (int l = a.L < kCoarseL ? a.L : kCoarseL; l >= 1; l--) {
       const int32_t s = 1 << (l - 1);
       if (MODE == 0) {
         CompressOp<T> op{L,  code + brick_base, lh, hist, Eb1, Eb2, a.R, lo, a.el_l[l], a.inv2e_l[l],
@@ -552,6 +702,26 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         if (!fok[u]) continue;
         code[brick_base + fcd[u]] = (uint16_t)fcv[u];
         const uint32_t q = fcv[u];
+        nR += q == a.R;
+        if (q != a.R) {
+          const uint32_t w = q - lo;
+          if (w < (uint32_t)kBlockHistWin)
+            __hip_atomic_fetch_add(&lh[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          else
+            __hip_atomic_fetch_add(&hist[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      // the lattice points' codes (coarse levels) into the brick, counted too
+      const HPEZ_GLOBAL uint16_t* cc = gmem(J.ccode) + bi * kCoarseCells;
+      for (uint32_t i = threadIdx.x; i < nlat; i += NT) {
+        const uint32_t q0 = fdiv(i, mlb0);
+        const uint32_t r = i - q0 * (uint32_t)lb.b0;
+        const uint32_t q1 = fdiv(r, mlE2);
+        const int32_t i0 = (int32_t)q0, i1 = (int32_t)q1, i2 = (int32_t)(r - q1 * (uint32_t)lb.E2);
+        if (i0 < lb.lo0 || i0 > lb.hi0 || i1 < lb.lo1 || i1 > lb.hi1 || i2 < lb.lo2 || i2 > lb.hi2)
+          continue;
+        const uint32_t q = cc[i];
+        code[brick_base + (uint32_t)((i0 * lk0 * Eb1 + i1 * lk1) * Eb2 + i2 * lk2)] = (uint16_t)q;
         nR += q == a.R;
         if (q != a.R) {
           const uint32_t w = q - lo;
@@ -616,6 +786,20 @@ hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_beg
 }
 
 template <typename T>
+hipError_t launch_coarse_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
+                              uint64_t total_blocks, int mode, hipStream_t st)
+{
+  if (!total_blocks || n <= 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL((coarse_kernel<T, 0>), dim3((unsigned)total_blocks), dim3(64), 0, st, d_jobs,
+                       d_begin, n);
+  else
+    hipLaunchKernelGGL((coarse_kernel<T, 1>), dim3((unsigned)total_blocks), dim3(64), 0, st, d_jobs,
+                       d_begin, n);
+  return hipGetLastError();
+}
+
+template <typename T>
 size_t block_lds_bytes(const Geom& g)
 {
   size_t pts = 1;
@@ -652,6 +836,8 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
   template hipError_t launch_face_init<T>(const FaceGeo&, const Geom&, const Lattice&, const T*, \
                                           const uint16_t*, int, hipStream_t);                    \
   template size_t block_lds_bytes<T>(const Geom&);                                               \
+  template hipError_t launch_coarse_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
+                                            int, hipStream_t);                                     \
   template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
                                            size_t, uint32_t*, int, int, hipStream_t);             \
   template hipError_t launch_face_steps<T>(const FaceEntry<T>*, const uint64_t*, int, uint64_t,   \
