@@ -305,10 +305,11 @@ def inspect(header_bytes: bytes):
 def decompress(stream_t, stream=None, out=None, context=None):
     """Decompress a uint8 CUDA tensor holding a stream; returns the field."""
     torch = _torch()
-    hdr = stream_t[:512].cpu().numpy().tobytes()
-    info = inspect(hdr + b"\0" * max(0, 512 - len(hdr)))
-    dt = torch.float64 if info["dtype"] == "f64" else torch.float32
     if out is None:
+        # the field's shape and dtype from the header (the library checks out's size)
+        hdr = stream_t[:512].cpu().numpy().tobytes()
+        info = inspect(hdr + b"\0" * max(0, 512 - len(hdr)))
+        dt = torch.float64 if info["dtype"] == "f64" else torch.float32
         out = torch.empty(info["dims"], dtype=dt, device=stream_t.device)
     rc = lib().hpez_decompress(_cx(context, stream_t.device.index or 0),
                                C.c_void_p(stream_t.data_ptr()),
@@ -447,17 +448,22 @@ def decompress_batch(streams, stream=None, outs=None, context=None, rcs_out=None
     if n == 0:
         return []
     dev = streams[0].device.index or 0
-    # every header in one device-to-host copy
-    heads = torch.stack([torch.nn.functional.pad(s[:512], (0, max(0, 512 - min(512, s.numel()))))
-                         for s in streams]).cpu().numpy()
+    heads = None
+    if outs is None:
+        # every header in one device-to-host copy, for the output shapes
+        heads = torch.stack([torch.nn.functional.pad(s[:512], (0, max(0, 512 - min(512, s.numel()))))
+                             for s in streams]).cpu().numpy()
     ins, optr = (C.c_void_p * n)(), (C.c_void_p * n)()
     isz, caps = (C.c_uint64 * n)(), (C.c_uint64 * n)()
     rcs = (C.c_int * n)()
     res = []
     for i, s in enumerate(streams):
-        info = inspect(heads[i].tobytes())
-        dt = torch.float64 if info["dtype"] == "f64" else torch.float32
-        o = outs[i] if outs is not None else torch.empty(info["dims"], dtype=dt, device=s.device)
+        if outs is not None:
+            o = outs[i]
+        else:
+            info = inspect(heads[i].tobytes())
+            dt = torch.float64 if info["dtype"] == "f64" else torch.float32
+            o = torch.empty(info["dims"], dtype=dt, device=s.device)
         res.append(o)
         ins[i] = s.data_ptr()
         isz[i] = s.numel()

@@ -39,6 +39,8 @@ struct hpez_ctx {
   uint8_t* pin_tab = nullptr;  // staging of the block phase's work tables
   size_t pin_tab_bytes = 0;
   size_t ws_limit = 0;  // 0: no cap on the workspace
+  uint8_t* pin_pre = nullptr;  // first bytes of the streams being decompressed
+  size_t pin_pre_bytes = 0;
   // kernel timing (hpez_profile_enable)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -402,27 +404,29 @@ int read_header(const uint8_t* h, uint64_t n, hpez_field_desc* d, hpez_config* c
 int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len)
 {
   std::memset(len, 0, nsym);
+  // only the used symbols take part (the halving below keeps a count >= 1)
+  uint32_t lo = 0;
+  while (lo < nsym && !hist[lo]) lo++;
+  if (lo == nsym) return HPEZ_OK;
+  uint32_t hi = nsym - 1;
+  while (!hist[hi]) hi--;
   struct Leaf {
     uint64_t w;
     uint32_t sym;
   };
-  std::vector<uint64_t> cnt(nsym);
-  for (uint32_t i = 0; i < nsym; i++) cnt[i] = hist[i];
-  std::vector<Leaf> leaves;
-  for (uint32_t i = 0; i < nsym; i++)
-    if (cnt[i]) leaves.push_back({cnt[i], i});
-  const size_t K = leaves.size();
-  if (K == 0) return HPEZ_OK;
+  std::vector<Leaf> used;
+  for (uint32_t i = lo; i <= hi; i++)
+    if (hist[i]) used.push_back({hist[i], i});
+  const size_t K = used.size();
   if (K == 1) {
-    len[leaves[0].sym] = 1;
+    len[used[0].sym] = 1;
     return HPEZ_OK;
   }
+  std::vector<Leaf> leaves(K);
   std::vector<uint64_t> w(2 * K);
   std::vector<uint32_t> left(K), right(K), depth(2 * K);
   for (;;) {
-    leaves.clear();
-    for (uint32_t i = 0; i < nsym; i++)
-      if (cnt[i]) leaves.push_back({cnt[i], i});
+    leaves = used;
     std::sort(leaves.begin(), leaves.end(), [](const Leaf& a, const Leaf& b) {
       return a.w != b.w ? a.w < b.w : a.sym < b.sym;
     });
@@ -457,16 +461,21 @@ int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len)
       for (size_t i = 0; i < K; i++) len[leaves[i].sym] = (uint8_t)depth[i];
       return HPEZ_OK;
     }
-    for (uint32_t i = 0; i < nsym; i++)
-      if (cnt[i]) cnt[i] = (cnt[i] + 1) >> 1;
+    for (Leaf& l : used) l.w = (l.w + 1) >> 1;
   }
 }
 
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw)
 {
+  canonical_codes_range(len, 0, nsym, cw);
+}
+
+// the same for symbols [lo, hi) (len is zero outside); cw is written there only
+void canonical_codes_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* cw)
+{
   // count per length, then first codeword per length, then assign in symbol order
   uint32_t nl[kLmax + 1] = {0};
-  for (uint32_t s = 0; s < nsym; s++)
+  for (uint32_t s = lo; s < hi; s++)
     if (len[s]) nl[len[s]]++;
   uint64_t next[kLmax + 2] = {0};
   uint64_t code = 0;
@@ -480,7 +489,7 @@ void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw)
     prev = l;
     any = true;
   }
-  for (uint32_t s = 0; s < nsym; s++) cw[s] = len[s] ? (uint32_t)next[len[s]]++ : 0;
+  for (uint32_t s = lo; s < hi; s++) cw[s] = len[s] ? (uint32_t)next[len[s]]++ : 0;
 }
 
 int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
@@ -525,8 +534,15 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
 void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint16_t* sorted,
                    uint64_t* lim, uint32_t* base)
 {
+  decode_tables_range(len, 0, nsym, lut, sorted, lim, base);
+}
+
+// the same for symbols [lo, hi) (len is zero outside)
+void decode_tables_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
+                         uint16_t* sorted, uint64_t* lim, uint32_t* base)
+{
   uint64_t count[kLmax + 2] = {0}, next[kLmax + 2] = {0}, offset[kLmax + 2] = {0};
-  for (uint32_t s = 0; s < nsym; s++)
+  for (uint32_t s = lo; s < hi; s++)
     if (len[s]) count[len[s]]++;
   // canonical first code per length, lengths without codes included
   for (int l = 2; l <= kLmax; l++) next[l] = (next[l - 1] + count[l - 1]) << 1;
@@ -540,7 +556,7 @@ void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint16_t* s
   std::memset(lut, 0, sizeof(uint32_t) << kLutBits);
   uint64_t fill[kLmax + 2];
   for (int l = 0; l <= kLmax + 1; l++) fill[l] = 0;
-  for (uint32_t s = 0; s < nsym; s++) {
+  for (uint32_t s = lo; s < hi; s++) {
     const int l = len[s];
     if (!l) continue;
     const uint64_t rank = fill[l]++;
@@ -619,6 +635,20 @@ int ensure_pinned(hpez_ctx* ctx, size_t bytes)
     return HPEZ_ENOMEM;
   }
   ctx->pinned_bytes = bytes;
+  return HPEZ_OK;
+}
+
+int ensure_pin_pre(hpez_ctx* ctx, size_t bytes)
+{
+  if (bytes <= ctx->pin_pre_bytes) return HPEZ_OK;
+  if (ctx->pin_pre) (void)hipHostFree(ctx->pin_pre);
+  ctx->pin_pre = nullptr;
+  ctx->pin_pre_bytes = 0;
+  if (hipHostMalloc((void**)&ctx->pin_pre, bytes, hipHostMallocDefault) != hipSuccess) {
+    ctx->pin_pre = nullptr;
+    return HPEZ_ENOMEM;
+  }
+  ctx->pin_pre_bytes = bytes;
   return HPEZ_OK;
 }
 
@@ -804,6 +834,9 @@ int block_phase(hpez_ctx* ctx, std::vector<BlockJobHost<T>>& jobs, int mode, Bum
 
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// bytes of each stream read with its header when decompressing
+constexpr uint64_t kPrefixBytes = 64 * 1024;
+
 // Run fn(i) for i in [0, n) on up to 16 host threads (host-only work of
 // independent fields: codebooks, decode tables).
 template <typename F>
@@ -848,7 +881,7 @@ struct CJob {
   bool fast = false;
   uint32_t lo = 0;
   double h_wq[3 * 16 * 4];
-  std::vector<uint32_t> cw;
+  uint32_t maxlen = 0;  // longest code length
   // device workspace
   T* W = nullptr;
   uint16_t* code = nullptr;
@@ -874,6 +907,7 @@ struct CJob {
   double* h_mm = nullptr;
   int* h_bad = nullptr;
   uint32_t* h_tab = nullptr;
+  uint32_t* h_cw = nullptr;
 };
 
 constexpr int kMinmaxBlocks = 1024;
@@ -905,7 +939,8 @@ size_t c_dev_bytes(const CJob<T>& J)
 template <typename T>
 size_t c_pin_bytes(const CJob<T>& J)
 {
-  return al256(J.nsym * 4) + al256(J.nsym) + al256(kHdrBytes) + al256(64) + al256(J.nsym * 4) + 256;
+  return al256(J.nsym * 4) + al256(J.nsym) + al256(kHdrBytes) + al256(64) + 2 * al256(J.nsym * 4) +
+         256;
 }
 
 template <typename T>
@@ -934,6 +969,7 @@ void c_take(CJob<T>& J, Bump& bw, Bump& pb)
   J.h_mm = pb.take<double>(2);
   J.h_bad = (int*)(J.h_mm + 2);
   J.h_tab = pb.take<uint32_t>(J.nsym);
+  J.h_cw = pb.take<uint32_t>(J.nsym);
 }
 
 // error bound (Sec. 7.1.3) and the non-finite check
@@ -1056,14 +1092,19 @@ void c_codebook(CJob<T>& J)
     J.rc = rc;
     return;
   }
-  J.cw.resize(nsym);
-  canonical_codes(J.h_len, nsym, J.cw.data());
-  uint64_t bits = 0;
-  for (uint32_t k = 0; k < nsym; k++) bits += (uint64_t)J.h_hist[k] * J.h_len[k];
   for (uint32_t k = 0; k < nsym; k++)
     if (J.h_len[k]) { Lo.sym_min = k; break; }
   for (uint32_t k = nsym; k-- > 0;)
     if (J.h_len[k]) { Lo.sym_max = k; break; }
+  uint64_t bits = 0;
+  J.maxlen = 0;
+  if (Lo.sym_max >= Lo.sym_min) {
+    canonical_codes_range(J.h_len, Lo.sym_min, Lo.sym_max + 1, J.h_cw);
+    for (uint32_t k = Lo.sym_min; k <= Lo.sym_max; k++) {
+      bits += (uint64_t)J.h_hist[k] * J.h_len[k];
+      J.maxlen = std::max<uint32_t>(J.maxlen, J.h_len[k]);
+    }
+  }
   Lo.n_unpred = J.h_hist[0];
   Lo.n_chunks = J.nch;
   Lo.payload_bits = bits;
@@ -1083,8 +1124,13 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   const hpez_config* c = J.c;
   const uint64_t s = sizeof(T);
   uint8_t* out = J.out;
-  HIPCK(hipMemcpyAsync(J.dlen, J.h_len, J.nsym, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(J.dcw, J.cw.data(), (size_t)J.nsym * 4, hipMemcpyHostToDevice, st));
+  if (J.maxlen > 26) {
+    // the encoder's unpacked path reads the full length and codeword tables
+    for (uint32_t k = 0; k < J.nsym; k++)
+      if (k < Lo.sym_min || k > Lo.sym_max) J.h_cw[k] = 0;
+    HIPCK(hipMemcpyAsync(J.dlen, J.h_len, J.nsym, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(J.dcw, J.h_cw, (size_t)J.nsym * 4, hipMemcpyHostToDevice, st));
+  }
   HIPCK(hipMemsetAsync(out, 0, Lo.total, st));
   HIPCK(hipMemcpyAsync(out, J.h_hdr, kHdrBytes, hipMemcpyHostToDevice, st));
   if (J.nb)
@@ -1099,7 +1145,7 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
     HIPCK(launch_gather_unpred<T>(J.code, J.N, c->chunk, J.czero, J.zoff, J.tmp2, J.X,
                                   (T*)(out + Lo.off_unpred), J.g, st));
   }
-  return encode_payload(ctx, J.code, J.N, c->chunk, J.h_len, J.cw.data(), Lo.sym_min, Lo.sym_max,
+  return encode_payload(ctx, J.code, J.N, c->chunk, J.h_len, J.h_cw, Lo.sym_min, Lo.sym_max,
                         J.dlen, J.dcw, J.hist, J.boff, J.ticket, J.h_tab,
                         (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), st);
 }
@@ -1183,8 +1229,10 @@ struct DJob {
   bool fast = false;
   double h_wq[3 * 16 * 4];
   DecodeArgs da;
-  std::vector<uint32_t> lut;
-  std::vector<uint16_t> sorted;
+  uint32_t nused = 0;  // symbols with a code
+  // the first bytes of the stream (host copy), or null
+  const uint8_t* h_prefix = nullptr;
+  uint64_t prefix_len = 0;
   // device workspace
   uint16_t* code = nullptr;
   uint32_t* cbits = nullptr;
@@ -1204,6 +1252,8 @@ struct DJob {
   uint8_t* h_bcfg = nullptr;
   int* h_status = nullptr;
   uint64_t* h_tot = nullptr;
+  uint32_t* h_lut = nullptr;
+  uint16_t* h_sorted = nullptr;
 };
 
 template <typename T>
@@ -1230,7 +1280,8 @@ size_t d_dev_bytes(const DJob<T>& J)
 template <typename T>
 size_t d_pin_bytes(const DJob<T>& J)
 {
-  return al256(J.nsym) + al256(J.nb) + al256(16) + al256(16) + 256;
+  return al256(J.nsym) + al256(J.nb) + al256(16) + al256(16) + al256((size_t)4 << kLutBits) +
+         al256(J.nsym * 2) + 256;
 }
 
 template <typename T>
@@ -1253,11 +1304,15 @@ void d_take(DJob<T>& J, Bump& bw, Bump& pb)
   J.h_bcfg = pb.take<uint8_t>(J.nb);
   J.h_status = pb.take<int>(4);
   J.h_tot = pb.take<uint64_t>(2);
+  J.h_lut = pb.take<uint32_t>(1u << kLutBits);
+  J.h_sorted = pb.take<uint16_t>(J.nsym);
 }
 
 // constant field, or the copies of code lengths and block configurations
+// (from the host prefix of the stream when they lie in it; *dev is set when a
+// device copy was needed)
 template <typename T>
-int d_fetch(DJob<T>& J, hipStream_t st)
+int d_fetch(DJob<T>& J, hipStream_t st, bool* dev)
 {
   const Layout& Lo = J.Lo;
   const uint64_t s = sizeof(T);
@@ -1273,11 +1328,21 @@ int d_fetch(DJob<T>& J, hipStream_t st)
     return HPEZ_OK;
   }
   std::memset(J.h_len, 0, J.nsym);
+  auto fetch = [&](void* dst, uint64_t off, uint64_t bytes) -> int {
+    if (!bytes) return HPEZ_OK;
+    if (J.h_prefix && off + bytes <= J.prefix_len) {
+      std::memcpy(dst, J.h_prefix + off, bytes);
+      return HPEZ_OK;
+    }
+    *dev = true;
+    HIPCK(hipMemcpyAsync(dst, J.in + off, bytes, hipMemcpyDeviceToHost, st));
+    return HPEZ_OK;
+  };
+  int rc = HPEZ_OK;
   if (Lo.sym_max >= Lo.sym_min)
-    HIPCK(hipMemcpyAsync(J.h_len + Lo.sym_min, J.in + Lo.off_len, Lo.sym_max - Lo.sym_min + 1,
-                         hipMemcpyDeviceToHost, st));
-  if (J.nb) HIPCK(hipMemcpyAsync(J.h_bcfg, J.in + Lo.off_blocks, J.nb, hipMemcpyDeviceToHost, st));
-  return HPEZ_OK;
+    rc = fetch(J.h_len + Lo.sym_min, Lo.off_len, Lo.sym_max - Lo.sym_min + 1);
+  if (!rc && J.nb) rc = fetch(J.h_bcfg, Lo.off_blocks, J.nb);
+  return rc;
 }
 
 // host: validate lengths and block configurations, build the decode tables
@@ -1291,7 +1356,10 @@ void d_tables(DJob<T>& J)
       return;
     }
   uint64_t kraft = 0, used = 0;
-  for (uint32_t k = 0; k < nsym; k++) {
+  const uint32_t lo = J.Lo.sym_max >= J.Lo.sym_min ? J.Lo.sym_min : 0;
+  const uint32_t hi = J.Lo.sym_max >= J.Lo.sym_min ? J.Lo.sym_max + 1 : 0;
+  (void)nsym;
+  for (uint32_t k = lo; k < hi; k++) {
     if (J.h_len[k] > kLmax) {
       J.rc = HPEZ_ECORRUPT;
       return;
@@ -1305,20 +1373,19 @@ void d_tables(DJob<T>& J)
     J.rc = HPEZ_ECORRUPT;
     return;
   }
-  J.lut.resize(1u << kLutBits);
-  J.sorted.resize(nsym);
   DecodeArgs& da = J.da;
   std::memset(&da, 0, sizeof da);
   da.n = J.N;
   da.nch = J.nch;
   da.nbits = J.Lo.payload_bits;
   da.chunk = J.c.chunk;
-  decode_tables(J.h_len, nsym, J.lut.data(), J.sorted.data(), da.lim, da.base);
+  decode_tables_range(J.h_len, lo, hi, J.h_lut, J.h_sorted, da.lim, da.base);
   uint32_t nshort = 0, nused = 0;
-  for (uint32_t k = 0; k < nsym; k++) {
+  for (uint32_t k = lo; k < hi; k++) {
     nused += J.h_len[k] != 0;
     nshort += J.h_len[k] != 0 && J.h_len[k] <= kLutBits;
   }
+  J.nused = nused;
   da.long_first = nshort;
   da.n_long = nused - nshort;
   md_table(&J.c, J.h_wq);
@@ -1333,8 +1400,9 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   const uint8_t* in = J.in;
   const uint64_t N = J.N, nch = J.nch;
   const uint64_t s = sizeof(T);
-  HIPCK(hipMemcpyAsync(J.dlut, J.lut.data(), J.lut.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(J.dsorted, J.sorted.data(), J.sorted.size() * 2, hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(J.dlut, J.h_lut, (size_t)4 << kLutBits, hipMemcpyHostToDevice, st));
+  if (J.nused)
+    HIPCK(hipMemcpyAsync(J.dsorted, J.h_sorted, (size_t)J.nused * 2, hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(J.dwq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
   HIPCK(hipMemsetAsync(J.status, 0, sizeof(int), st));
   {
@@ -1415,11 +1483,12 @@ int decompress_jobs(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, hipStream_t st)
   Bump bw{(uint8_t*)ctx->ws};
   Bump pb{ctx->pinned};
   for (auto& J : jobs) d_take(J, bw, pb);
+  bool need_sync = false;
   for (auto& J : jobs) {
-    rc = d_fetch(J, st);
+    rc = d_fetch(J, st, &need_sync);
     if (rc) return rc;
   }
-  HIPCK(hipStreamSynchronize(st));
+  if (need_sync) HIPCK(hipStreamSynchronize(st));
   host_parallel(n, [&](int i) {
     if (jobs[i].Lo.predictor != 2) d_tables(jobs[i]);
   });
@@ -1536,6 +1605,7 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
+  if (ctx->pin_pre) (void)hipHostFree(ctx->pin_pre);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -1693,14 +1763,16 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
     if (!d_in[i] || !d_out[i]) return HPEZ_EINVAL;
   if (!n) return HPEZ_OK;
   DevScope ds(ctx->device);
-  // every header in one copy and one synchronization
-  int rc = ensure_pin_tab(ctx, (size_t)n * kHdrBytes);
+  // every stream's first kPrefixBytes (header, and usually the block
+  // configurations and code lengths) in one synchronization
+  int rc = ensure_pin_pre(ctx, (size_t)n * kPrefixBytes);
   if (rc) return rc;
   for (int i = 0; i < n; i++) {
     rcs[i] = in_size[i] < (uint64_t)kHdrBytes ? HPEZ_ECORRUPT : HPEZ_OK;
     if (!rcs[i])
-      HIPCK(hipMemcpyAsync(ctx->pin_tab + (size_t)i * kHdrBytes, d_in[i], kHdrBytes,
-                           hipMemcpyDeviceToHost, stream));
+      HIPCK(hipMemcpyAsync(ctx->pin_pre + (size_t)i * kPrefixBytes, d_in[i],
+                           std::min<uint64_t>(in_size[i], kPrefixBytes), hipMemcpyDeviceToHost,
+                           stream));
   }
   HIPCK(hipStreamSynchronize(stream));
   std::vector<int> i32, i64;
@@ -1711,7 +1783,7 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
     hpez_field_desc dd;
     hpez_config cc;
     Layout L;
-    int r = read_header(ctx->pin_tab + (size_t)i * kHdrBytes, in_size[i], &dd, &cc, &L);
+    int r = read_header(ctx->pin_pre + (size_t)i * kPrefixBytes, in_size[i], &dd, &cc, &L);
     if (!r && L.total > in_size[i]) r = HPEZ_ECORRUPT;
     if (!r && out_cap[i] < points_of(&dd) * (dd.dtype ? 8 : 4)) r = HPEZ_ENOSPC;
     rcs[i] = r;
@@ -1720,6 +1792,8 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
       j32.emplace_back();
       DJob<float>& J = j32.back();
       J.in = (const uint8_t*)d_in[i];
+      J.h_prefix = ctx->pin_pre + (size_t)i * kPrefixBytes;
+      J.prefix_len = std::min<uint64_t>(in_size[i], kPrefixBytes);
       J.out = (float*)d_out[i];
       J.d = dd;
       J.c = cc;
@@ -1729,6 +1803,8 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
       j64.emplace_back();
       DJob<double>& J = j64.back();
       J.in = (const uint8_t*)d_in[i];
+      J.h_prefix = ctx->pin_pre + (size_t)i * kPrefixBytes;
+      J.prefix_len = std::min<uint64_t>(in_size[i], kPrefixBytes);
       J.out = (double*)d_out[i];
       J.d = dd;
       J.c = cc;

@@ -38,6 +38,9 @@ int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
 // device bytes of a tuning run with the default options (admission)
 uint64_t tune_footprint(const hpez_field_desc* d, const hpez_config* c);
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint32_t* cw);
+void canonical_codes_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* cw);
+void decode_tables_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
+                         uint16_t* sorted, uint64_t* lim, uint32_t* base);
 // Canonical decoding tables: lut[2^kLutBits] (symbol << 8 | length, 0 for
 // longer codes), symbols sorted by (length, symbol), and per length the window
 // limit lim[l] and base[l] (kLmax + 1 entries each, index 0 unused).
