@@ -20,6 +20,7 @@ namespace hpez {
   } while (0)
 
 constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kPlaneLdsBytes = 150 * 1024;  // a plane lattice in the plane kernel
 
 template <typename T>
 bool block_fast_ok(const hpez_config* c, const Geom& g)
@@ -79,7 +80,8 @@ size_t block_tables_bound(int n)
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const size_t ent = kMaxFaceSteps * (size_t)n;
   return al(ent * sizeof(FaceEntry<T>)) + al((ent + kMaxFaceSteps) * 8) +
-         al(n * sizeof(BlockJobDev<T>)) + al((n + 1) * 8) + 256;
+         al(n * sizeof(BlockJobDev<T>)) + al((n + 1) * 8) + 256 +
+         al(3 * (size_t)n * sizeof(PlaneJob<T>)) + al((3 * (size_t)n + 1) * 8);
 }
 
 template <typename T>
@@ -112,7 +114,54 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
   int64_t r[4], m[4];
   J.face_pts = 0;
   for (int l = 0; l <= 16; l++) J.steps[l].clear();
+  // coarse face levels on whole planes when every plane's lattice fits
+  J.npj = 0;
+  J.plane_lds = 0;
+  J.planes = Lb > kCoarseL;
+  for (int d = 0; d < 3 && J.planes; d++) {
+    if (!g.act[d]) continue;
+    int64_t E[3];
+    for (int e = 0; e < 3; e++) E[e] = e == d ? 1 : (g.act[e] ? (g.n[e] - 1) / 4 + 1 : g.n[e]);
+    const int64_t cells = E[0] * E[1] * E[2];
+    // step row counts c1 * c2 stay within the division table: one of the
+    // plane's active dims is halved in every step
+    int64_t c12 = E[1] * E[2];
+    if (d == 1) c12 = E[2];
+    else if (d == 2) c12 = E[1];
+    else {
+      int64_t best = 0;
+      if (g.act[1]) best = std::max(best, ((E[1] + 1) / 2) * E[2]);
+      if (g.act[2]) best = std::max(best, E[1] * ((E[2] + 1) / 2));
+      c12 = best;
+    }
+    if ((size_t)cells * sizeof(T) > kPlaneLdsBytes || c12 > (int64_t)kMagicMax ||
+        E[0] > (int64_t)kMagicMax || E[1] > (int64_t)kMagicMax || E[2] > (int64_t)kMagicMax) {
+      J.planes = false;
+      break;
+    }
+    PlaneJob<T>& P = J.pj[J.npj++];
+    std::memset(&P, 0, sizeof P);
+    P.g = g;
+    P.d = d;
+    P.Ltop = Lb;
+    for (int e = 0; e < 3; e++) P.E[e] = (int32_t)E[e];
+    P.R = c->radius;
+    for (int l = 1; l <= 16; l++) {
+      const double el = level_eb(J.e, c->alpha, c->beta, l);
+      P.el_l[l] = el;
+      P.inv2e_l[l] = 1.0 / (2.0 * el);
+      P.twoe_l[l] = 2.0 * el;
+    }
+    for (int k = 0; k < 3; k++)
+      for (int odd = 0; odd < 8; odd++)
+        for (int e = 0; e < 4; e++) P.wmd[(k * 8 + odd) * 4 + e] = J.h_wq[(k * 16 + odd) * 4 + e];
+    for (int l = 0; l < 16; l++) P.level[l] = c->level[l];
+    P.wg_begin = (uint64_t)((g.n[d] - 1) / B + 1);  // planes (the launch offset is set later)
+    J.plane_lds = std::max(J.plane_lds, (size_t)cells * sizeof(T));
+  }
+  if (!J.planes) J.npj = 0;
   for (int l = Lb; l >= 1; l--) {
+    if (J.planes && l > kCoarseL) continue;
     const int64_t s = (int64_t)1 << (l - 1);
     const double el = level_eb(J.e, c->alpha, c->beta, l);
     const hpez_interp& ip = c->level[l - 1];
@@ -247,7 +296,7 @@ size_t block_jobs_table_bytes(const BlockJobHost<T>* jobs, int n)
   }
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   return al(ent * sizeof(FaceEntry<T>)) + al((ent + slots) * 8) + al(n * sizeof(BlockJobDev<T>)) +
-         al((n + 1) * 8) + 256;
+         al((n + 1) * 8) + 256 + al(3 * (size_t)n * sizeof(PlaneJob<T>)) + al((3 * (size_t)n + 1) * 8);
 }
 
 template <typename T>
@@ -284,7 +333,9 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   const size_t off_jobs = off_wg + al((ent + slots) * 8);
   const size_t off_begin = off_jobs + al(n * sizeof(BlockJobDev<T>));
   const size_t off_ticket = off_begin + al((n + 1) * 8);
-  const size_t bytes = off_ticket + 256;
+  const size_t off_planes = off_ticket + 256;
+  const size_t off_pwg = off_planes + al(3 * (size_t)n * sizeof(PlaneJob<T>));
+  const size_t bytes = off_pwg + al((3 * (size_t)n + 1) * 8);
   std::memset(h_tables, 0, bytes);
   FaceEntry<T>* he = (FaceEntry<T>*)h_tables;
   uint64_t* hw = (uint64_t*)(h_tables + off_wg);
@@ -348,10 +399,34 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
     lds = std::max(lds, jobs[j].lds);
   }
   hb[n] = total_blocks;
+  PlaneJob<T>* hp = (PlaneJob<T>*)(h_tables + off_planes);
+  uint64_t* hpw = (uint64_t*)(h_tables + off_pwg);
+  int np = 0;
+  uint64_t plane_wgs = 0;
+  size_t plane_lds = 0;
+  for (int j = 0; j < n; j++) {
+    for (int k = 0; k < jobs[j].npj; k++) {
+      PlaneJob<T> P = jobs[j].pj[k];
+      const uint64_t planes = P.wg_begin;
+      P.f = jobs[j].f;
+      P.X = jobs[j].X;
+      P.code = jobs[j].code;
+      P.out = jobs[j].out;
+      P.wg_begin = plane_wgs;
+      hp[np] = P;
+      hpw[np] = plane_wgs;
+      np++;
+      plane_wgs += planes;
+    }
+    plane_lds = std::max(plane_lds, jobs[j].plane_lds);
+  }
+  hpw[np] = plane_wgs;
   uint8_t* dt = (uint8_t*)d_tables;
   BCK(hipMemcpyAsync(dt, h_tables, bytes, hipMemcpyHostToDevice, st));
 
   hipEvent_t ev = ctx_span_begin(ctx, st);
+  BCK(launch_planes<T>((const PlaneJob<T>*)(dt + off_planes), (const uint64_t*)(dt + off_pwg), np,
+                       plane_wgs, plane_lds, mode, st));
   for (const Launch& L : launches)
     BCK(launch_face_steps<T>((const FaceEntry<T>*)dt + L.e0, (const uint64_t*)(dt + off_wg) + L.w0,
                              L.cnt, L.wgs, L.narrow, mode, st));

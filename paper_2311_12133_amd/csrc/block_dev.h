@@ -80,6 +80,30 @@ struct BlockJobDev {
   uint64_t block_begin;
 };
 
+// The coarse face levels (s >= 4) of one family of one field: one work-group
+// per plane x_d = B p, the plane's lattice (every 4th point along its active
+// dims) in LDS.  Work-groups [wg_begin, wg_begin + planes) of the launch.
+template <typename T>
+struct PlaneJob {
+  Geom g;
+  FaceGeo f;
+  const T* X;
+  const uint16_t* code;  // decompress: the codes (stream order)
+  const T* out;          // decompress: the field (verbatim values)
+  int32_t d;             // family: the planes' normal dim
+  int32_t Ltop;          // first level (log2 B)
+  int32_t E[3];          // lattice extents (1 along d)
+  uint32_t R;
+  double el_l[17], inv2e_l[17], twoe_l[17];
+  double wmd[3 * 8 * 4];
+  hpez_interp level[16];  // the global configuration per level
+  uint64_t wg_begin;
+};
+
+template <typename T>
+hipError_t launch_planes(const PlaneJob<T>* d_tab, const uint64_t* d_wg_begin, int n,
+                         uint64_t total_wg, size_t lds, int mode, hipStream_t st);
+
 // one fused face step: entries [0, n) of the device table, total work-groups
 template <typename T>
 hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_begin, int n,

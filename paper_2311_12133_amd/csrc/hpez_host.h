@@ -120,6 +120,10 @@ struct BlockJobHost {
   FaceGeo f;
   T* cval = nullptr;          // coarse levels' lattice values (in area)
   uint16_t* ccode = nullptr;  // coarse levels' lattice codes (in area)
+  bool planes = false;        // coarse face levels in the plane kernel
+  PlaneJob<T> pj[3];          // one per active family (wg_begin: the plane count)
+  int npj = 0;
+  size_t plane_lds = 0;
   BlockArgs ba;
   std::vector<FaceStep> steps[17];
   uint64_t nblocks = 0, npts = 0, face_pts = 0;

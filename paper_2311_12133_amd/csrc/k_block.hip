@@ -160,6 +160,151 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
 }
 
 // ---------------------------------------------------------------------------
+// Coarse face levels on whole planes.  A point of a face plane is predicted from
+// points of the same plane (its odd dims lie in the plane), so a plane is a 2D
+// problem; its levels s >= 4 use only the plane's lattice (every 4th point
+// along active dims), which for planes up to a few hundred points per side
+// fits one work-group's LDS.  The plane box spans the whole plane, so the
+// stencils' ends are the field's ends as in the face steps.  Points on lines
+// shared with a lower family are computed in both planes (same neighbours,
+// same values); each plane writes its own family's face array, and codes only
+// of the points whose lowest family it is.
+
+template <typename T>
+struct PlaneCompressOp {
+  using Fetched = int;
+  T* L;
+  const FaceGeo* f;
+  const Geom* g;
+  int32_t d;
+  int64_t xd;  // the plane's coordinate along d
+  int32_t k0, k1, k2;
+  uint32_t R;
+  double el, inv2e, twoe;
+  __device__ __forceinline__ int fetch(int32_t, int32_t, int32_t, bool) const { return 0; }
+  __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, int)
+  {
+    const T xv = L[li];
+    T xr = xv;
+    const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
+    L[li] = xr;
+    int64_t x[4] = {(int64_t)x0 * k0, (int64_t)x1 * k1, (int64_t)x2 * k2, 0};
+    x[d] = xd;
+    if (low_family(*f, *g, x) == d) gmem(f->code[d])[face_index(*f, d, x)] = (uint16_t)q;
+  }
+};
+
+template <typename T>
+struct PlaneDecompressOp {
+  using Fetched = uint32_t;
+  T* L;
+  const Geom* g;
+  const HPEZ_GLOBAL uint16_t* code;
+  const HPEZ_GLOBAL T* out;
+  int32_t d;
+  int64_t xd;
+  int32_t k0, k1, k2;
+  uint32_t R;
+  double twoe;
+  __device__ __forceinline__ void pos(int32_t x0, int32_t x1, int32_t x2, int64_t* x) const
+  {
+    x[0] = (int64_t)x0 * k0;
+    x[1] = (int64_t)x1 * k1;
+    x[2] = (int64_t)x2 * k2;
+    x[3] = 0;
+    x[d] = xd;
+  }
+  __device__ __forceinline__ uint32_t fetch(int32_t x0, int32_t x1, int32_t x2, bool ok) const
+  {
+    if (!ok) return 0u;
+    int64_t x[4];
+    pos(x0, x1, x2, x);
+    return (uint32_t)code[brick_pos(g->n, x)];
+  }
+  __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
+  {
+    if (q) {
+      L[li] = (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe);
+    } else {
+      int64_t x[4];
+      pos(x0, x1, x2, x);
+      L[li] = out[x[0] * g->st[0] + x[1] * g->st[1] + x[2] * g->st[2] + x[3]];
+    }
+  }
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlockThreads) plane_kernel(const PlaneJob<T>* __restrict__ tab,
+                                                              const uint64_t* __restrict__ wg_begin,
+                                                              int n)
+{
+  constexpr int NT = kBlockThreads;
+  extern __shared__ unsigned char lds_raw[];
+  T* L = reinterpret_cast<T*>(lds_raw);
+  const int j = find_entry(wg_begin, n, blockIdx.x);
+  const PlaneJob<T>& J = tab[j];
+  const Geom& g = J.g;
+  const FaceGeo& f = J.f;
+  const int32_t d = J.d;
+  const int64_t xd = (int64_t)(blockIdx.x - J.wg_begin) << f.blog2;
+  Box lb;
+  lb.E0 = J.E[0];
+  lb.E1 = J.E[1];
+  lb.E2 = J.E[2];
+  lb.b1 = lb.E2;
+  lb.b0 = lb.E1 * lb.E2;
+  lb.a0 = d != 0 && g.act[0];
+  lb.a1 = d != 1 && g.act[1];
+  lb.a2 = d != 2 && g.act[2];
+  lb.lo0 = lb.lo1 = lb.lo2 = 0;
+  lb.hi0 = lb.E0 - 1;
+  lb.hi1 = lb.E1 - 1;
+  lb.hi2 = lb.E2 - 1;
+  const int32_t k0 = lb.a0 ? 4 : 1, k1 = lb.a1 ? 4 : 1, k2 = lb.a2 ? 4 : 1;
+  const uint32_t ncell = (uint32_t)(lb.E0 * lb.b0);
+  const HPEZ_GLOBAL T* F = gmem(reinterpret_cast<const T*>(f.val[d]));
+  const HPEZ_GLOBAL T* X = gmem(J.X);
+  // the lattice: points of the coarse grid (multiples of B) from the face
+  // array, the others from X (compress) or predicted (decompress)
+  for (uint32_t i = threadIdx.x; i < ncell; i += NT) {
+    const uint32_t q0 = i / (uint32_t)lb.b0;
+    const uint32_t r = i - q0 * (uint32_t)lb.b0;
+    const uint32_t q1 = r / (uint32_t)lb.E2;
+    int64_t x[4] = {(int64_t)q0 * k0, (int64_t)q1 * k1, (int64_t)(r - q1 * (uint32_t)lb.E2) * k2, 0};
+    x[d] = xd;
+    bool grid = true;
+    for (int e = 0; e < 3; e++)
+      if (g.act[e] && (x[e] & (f.B - 1))) grid = false;
+    T v = (T)0;
+    if (grid) v = F[face_index(f, d, x)];
+    else if (MODE == 0) v = X[x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]];
+    L[i] = v;
+  }
+  __syncthreads();
+  for (int l = J.Ltop; l > kCoarseL; l--) {
+    const int32_t s = 1 << (l - 1 - 2);  // lattice stride
+    const hpez_interp& c = J.level[l - 1];
+    if (MODE == 0) {
+      PlaneCompressOp<T> op{L,  &f, &g, d, xd, k0, k1, k2, J.R, J.el_l[l], J.inv2e_l[l],
+                            J.twoe_l[l]};
+      box_level<T, NT>(c, lb, L, 0, 0, 0, s, J.wmd, op);
+    } else {
+      PlaneDecompressOp<T> op{L, &g, gmem(J.code), gmem(J.out), d, xd, k0, k1, k2, J.R, J.twoe_l[l]};
+      box_level<T, NT>(c, lb, L, 0, 0, 0, s, J.wmd, op);
+    }
+  }
+  HPEZ_GLOBAL T* Fw = gmem(reinterpret_cast<T*>(f.val[d]));
+  for (uint32_t i = threadIdx.x; i < ncell; i += NT) {
+    const uint32_t q0 = i / (uint32_t)lb.b0;
+    const uint32_t r = i - q0 * (uint32_t)lb.b0;
+    const uint32_t q1 = r / (uint32_t)lb.E2;
+    int64_t x[4] = {(int64_t)q0 * k0, (int64_t)q1 * k1, (int64_t)(r - q1 * (uint32_t)lb.E2) * k2, 0};
+    x[d] = xd;
+    Fw[face_index(f, d, x)] = L[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // interiors: one work-group per block, the whole schedule below B in LDS.
 // The grid has at most three dims here (dims 0..2; dim 3 has size 1).
 
@@ -800,6 +945,25 @@ hipError_t launch_coarse_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_be
 }
 
 template <typename T>
+hipError_t launch_planes(const PlaneJob<T>* d_tab, const uint64_t* d_wg_begin, int n,
+                         uint64_t total_wg, size_t lds, int mode, hipStream_t st)
+{
+  if (!total_wg || n <= 0) return hipSuccess;
+  if (mode == 0) {
+    (void)hipFuncSetAttribute((const void*)plane_kernel<T, 0>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((plane_kernel<T, 0>), dim3((unsigned)total_wg), dim3(kBlockThreads), lds, st,
+                       d_tab, d_wg_begin, n);
+  } else {
+    (void)hipFuncSetAttribute((const void*)plane_kernel<T, 1>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((plane_kernel<T, 1>), dim3((unsigned)total_wg), dim3(kBlockThreads), lds, st,
+                       d_tab, d_wg_begin, n);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 size_t block_lds_bytes(const Geom& g)
 {
   size_t pts = 1;
@@ -836,6 +1000,8 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
   template hipError_t launch_face_init<T>(const FaceGeo&, const Geom&, const Lattice&, const T*, \
                                           const uint16_t*, int, hipStream_t);                    \
   template size_t block_lds_bytes<T>(const Geom&);                                               \
+  template hipError_t launch_planes<T>(const PlaneJob<T>*, const uint64_t*, int, uint64_t, size_t,  \
+                                       int, hipStream_t);                                         \
   template hipError_t launch_coarse_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
                                             int, hipStream_t);                                     \
   template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
