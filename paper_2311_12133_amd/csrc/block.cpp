@@ -20,6 +20,22 @@ namespace hpez {
   } while (0)
 
 constexpr size_t kLdsLimit = 160 * 1024;
+
+// Division of any 32-bit n by d >= 2 as (t + ((n - t) >> 1)) >> (l - 1),
+// t = mulhi(m, n), l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1
+// (Granlund and Montgomery, round-up multiplier); d <= 1 gives shift -1.
+static void div_magic32(uint32_t d, uint32_t* m, int32_t* sh)
+{
+  if (d <= 1) {
+    *m = 0;
+    *sh = -1;
+    return;
+  }
+  int l = 0;
+  while ((1ull << l) < d) l++;
+  *m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  *sh = l - 1;
+}
 constexpr size_t kPlaneLdsBytes = 150 * 1024;  // a plane lattice in the plane kernel
 
 template <typename T>
@@ -145,6 +161,8 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
     P.d = d;
     P.Ltop = Lb;
     for (int e = 0; e < 3; e++) P.E[e] = (int32_t)E[e];
+    div_magic32((uint32_t)(E[1] * E[2]), &P.mg_b0, &P.sh_b0);
+    div_magic32((uint32_t)E[2], &P.mg_e2, &P.sh_e2);
     P.R = c->radius;
     for (int l = 1; l <= 16; l++) {
       const double el = level_eb(J.e, c->alpha, c->beta, l);
@@ -181,6 +199,7 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
         a.first[k] = rr[k];
         a.step[k] = mm[k];
         a.cnt[k] = rr[k] <= g.n[k] - 1 ? (uint32_t)((g.n[k] - 1 - rr[k]) / mm[k] + 1) : 0;
+        div_magic32(a.cnt[k], &a.mg[k], &a.msh[k]);
       }
       a.off[0] = 0;
       for (int d = 0; d < 4; d++) {

@@ -32,6 +32,8 @@ struct FaceStep {
   Geom g;
   int64_t first[4], step[4];
   uint32_t cnt[4];
+  uint32_t mg[4];   // magic multipliers for division by cnt (32-bit indices)
+  int32_t msh[4];   // their shifts (-1: cnt <= 1)
   uint64_t off[5];
   int32_t kind, md, sl, pdim;
   uint32_t odd;
@@ -93,6 +95,8 @@ struct PlaneJob {
   int32_t d;             // family: the planes' normal dim
   int32_t Ltop;          // first level (log2 B)
   int32_t E[3];          // lattice extents (1 along d)
+  uint32_t mg_b0, mg_e2;  // magic multipliers / shifts for cell index / (E1 E2) and / E2
+  int32_t sh_b0, sh_e2;
   uint32_t R;
   double el_l[17], inv2e_l[17], twoe_l[17];
   double wmd[3 * 8 * 4];

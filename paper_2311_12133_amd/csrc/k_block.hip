@@ -114,7 +114,18 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
     for (int e = 3; e >= 0; e--) {
       if (e == d) continue;
       const I c = (I)a.cnt[e];
-      const I q = r / c;
+      I q;
+      if constexpr (sizeof(I) == 4) {
+        // r / c with the step's magic multiplier (uniform branch on the shift)
+        if (a.msh[e] < 0) {
+          q = r;
+        } else {
+          const uint32_t t = __umulhi(a.mg[e], (uint32_t)r);
+          q = (t + (((uint32_t)r - t) >> 1)) >> a.msh[e];
+        }
+      } else {
+        q = r / c;
+      }
       x[e] = a.first[e] + (int64_t)(r - q * c) * a.step[e];
       r = q;
     }
@@ -169,6 +180,14 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
 // shared with a lower family are computed in both planes (same neighbours,
 // same values); each plane writes its own family's face array, and codes only
 // of the points whose lowest family it is.
+
+// n / d with a host-computed magic multiplier (shift -1: d <= 1)
+__device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t m, int32_t sh)
+{
+  if (sh < 0) return n;
+  const uint32_t t = __umulhi(m, n);
+  return (t + ((n - t) >> 1)) >> sh;
+}
 
 template <typename T>
 struct PlaneCompressOp {
@@ -267,9 +286,9 @@ __global__ void __launch_bounds__(kBlockThreads) plane_kernel(const PlaneJob<T>*
   // the lattice: points of the coarse grid (multiples of B) from the face
   // array, the others from X (compress) or predicted (decompress)
   for (uint32_t i = threadIdx.x; i < ncell; i += NT) {
-    const uint32_t q0 = i / (uint32_t)lb.b0;
+    const uint32_t q0 = div_magic(i, J.mg_b0, J.sh_b0);
     const uint32_t r = i - q0 * (uint32_t)lb.b0;
-    const uint32_t q1 = r / (uint32_t)lb.E2;
+    const uint32_t q1 = div_magic(r, J.mg_e2, J.sh_e2);
     int64_t x[4] = {(int64_t)q0 * k0, (int64_t)q1 * k1, (int64_t)(r - q1 * (uint32_t)lb.E2) * k2, 0};
     x[d] = xd;
     bool grid = true;
@@ -295,9 +314,9 @@ __global__ void __launch_bounds__(kBlockThreads) plane_kernel(const PlaneJob<T>*
   }
   HPEZ_GLOBAL T* Fw = gmem(reinterpret_cast<T*>(f.val[d]));
   for (uint32_t i = threadIdx.x; i < ncell; i += NT) {
-    const uint32_t q0 = i / (uint32_t)lb.b0;
+    const uint32_t q0 = div_magic(i, J.mg_b0, J.sh_b0);
     const uint32_t r = i - q0 * (uint32_t)lb.b0;
-    const uint32_t q1 = r / (uint32_t)lb.E2;
+    const uint32_t q1 = div_magic(r, J.mg_e2, J.sh_e2);
     int64_t x[4] = {(int64_t)q0 * k0, (int64_t)q1 * k1, (int64_t)(r - q1 * (uint32_t)lb.E2) * k2, 0};
     x[d] = xd;
     Fw[face_index(f, d, x)] = L[i];
