@@ -568,6 +568,51 @@ void decode_tables_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t*
   }
 }
 
+uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
+                          uint32_t* sub, uint32_t cap)
+{
+  // canonical codewords as in decode_tables_range: by length, then symbol
+  uint64_t count[kLmax + 2] = {0}, next[kLmax + 2] = {0};
+  for (uint32_t s = lo; s < hi; s++)
+    if (len[s]) count[len[s]]++;
+  for (int l = 2; l <= kLmax; l++) next[l] = (next[l - 1] + count[l - 1]) << 1;
+  uint8_t lmax[1u << kLutBits];
+  std::memset(lmax, 0, sizeof lmax);
+  uint64_t fill[kLmax + 2];
+  for (int l = 0; l <= kLmax + 1; l++) fill[l] = next[l];
+  for (uint32_t s = lo; s < hi; s++) {
+    const int l = len[s];
+    if (!l) continue;
+    const uint64_t cw = fill[l]++;
+    if (l <= kLutBits) continue;
+    const uint32_t pre = (uint32_t)(cw >> (l - kLutBits));
+    if (l > lmax[pre]) lmax[pre] = (uint8_t)l;
+  }
+  uint32_t off[1u << kLutBits];
+  uint64_t total = 0;
+  for (uint32_t p = 0; p < (1u << kLutBits); p++) {
+    off[p] = (uint32_t)total;
+    if (lmax[p]) total += 1ull << (lmax[p] - kLutBits);
+  }
+  if (total == 0 || total > cap) return 0;
+  std::memset(sub, 0, (size_t)total * 4);  // entries no codeword covers decode as invalid
+  for (int l = 0; l <= kLmax + 1; l++) fill[l] = next[l];
+  for (uint32_t s = lo; s < hi; s++) {
+    const int l = len[s];
+    if (!l) continue;
+    const uint64_t cw = fill[l]++;
+    if (l <= kLutBits) continue;
+    const uint32_t pre = (uint32_t)(cw >> (l - kLutBits));
+    const int lm = lmax[pre];
+    const uint64_t rest = cw & ((1ull << (l - kLutBits)) - 1);
+    const uint64_t first = off[pre] + (rest << (lm - l));
+    for (uint64_t j = 0; j < (1ull << (lm - l)); j++) sub[first + j] = (s << 8) | (uint32_t)l;
+  }
+  for (uint32_t p = 0; p < (1u << kLutBits); p++)
+    if (lmax[p]) lut[p] = (off[p] << 8) | 0x80u | (uint32_t)(lmax[p] - kLutBits);
+  return (uint32_t)total;
+}
+
 // MD weight table: [kind][odd set][dim] = md_w[kind][d] / sum over the odd set
 // (ascending dims), Eq. (12).
 void md_table(const hpez_config* c, double* wq)
@@ -1244,6 +1289,7 @@ struct DJob {
   double* dwq = nullptr;
   uint32_t* dlut = nullptr;
   uint16_t* dsorted = nullptr;
+  uint32_t* dsub = nullptr;
   int* status = nullptr;
   long long* lv = nullptr;
   void* area = nullptr;
@@ -1254,6 +1300,7 @@ struct DJob {
   uint64_t* h_tot = nullptr;
   uint32_t* h_lut = nullptr;
   uint16_t* h_sorted = nullptr;
+  uint32_t* h_sub = nullptr;
 };
 
 template <typename T>
@@ -1271,7 +1318,8 @@ template <typename T>
 size_t d_dev_bytes(const DJob<T>& J)
 {
   size_t b = al256(J.N * 2) + 2 * al256((J.nch + 1) * 4) + 4 * al256((J.nch + 1) * 8) +
-             al256(3 * 16 * 4 * 8) + al256((size_t)4 << kLutBits) + al256(J.nsym * 2) + al256(16);
+             al256(3 * 16 * 4 * 8) + al256((size_t)4 << kLutBits) + al256(J.nsym * 2) + al256(16) +
+             al256((size_t)kDecSub * 4);
   if (J.Lo.predictor == 1) b += al256(J.N * 8);
   if (J.fast) b += al256(block_fast_bytes<T>(J.g));
   return b + 256;
@@ -1281,7 +1329,7 @@ template <typename T>
 size_t d_pin_bytes(const DJob<T>& J)
 {
   return al256(J.nsym) + al256(J.nb) + al256(16) + al256(16) + al256((size_t)4 << kLutBits) +
-         al256(J.nsym * 2) + 256;
+         al256(J.nsym * 2) + al256((size_t)kDecSub * 4) + 256;
 }
 
 template <typename T>
@@ -1297,6 +1345,7 @@ void d_take(DJob<T>& J, Bump& bw, Bump& pb)
   J.dwq = bw.take<double>(3 * 16 * 4);
   J.dlut = bw.take<uint32_t>(1u << kLutBits);
   J.dsorted = bw.take<uint16_t>(J.nsym);
+  J.dsub = bw.take<uint32_t>(kDecSub);
   J.status = bw.take<int>(4);
   if (J.Lo.predictor == 1) J.lv = bw.take<long long>(J.N);
   if (J.fast) J.area = bw.take<uint8_t>(block_fast_bytes<T>(J.g));
@@ -1306,6 +1355,7 @@ void d_take(DJob<T>& J, Bump& bw, Bump& pb)
   J.h_tot = pb.take<uint64_t>(2);
   J.h_lut = pb.take<uint32_t>(1u << kLutBits);
   J.h_sorted = pb.take<uint16_t>(J.nsym);
+  J.h_sub = pb.take<uint32_t>(kDecSub);
 }
 
 // constant field, or the copies of code lengths and block configurations
@@ -1388,6 +1438,8 @@ void d_tables(DJob<T>& J)
   J.nused = nused;
   da.long_first = nshort;
   da.n_long = nused - nshort;
+  // long codes by second-level tables when they fit (the first level is updated)
+  da.n_sub = da.n_long ? decode_subtables(J.h_len, lo, hi, J.h_lut, J.h_sub, kDecSub) : 0;
   md_table(&J.c, J.h_wq);
 }
 
@@ -1403,6 +1455,8 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   HIPCK(hipMemcpyAsync(J.dlut, J.h_lut, (size_t)4 << kLutBits, hipMemcpyHostToDevice, st));
   if (J.nused)
     HIPCK(hipMemcpyAsync(J.dsorted, J.h_sorted, (size_t)J.nused * 2, hipMemcpyHostToDevice, st));
+  if (J.da.n_sub)
+    HIPCK(hipMemcpyAsync(J.dsub, J.h_sub, (size_t)J.da.n_sub * 4, hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(J.dwq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
   HIPCK(hipMemsetAsync(J.status, 0, sizeof(int), st));
   {
@@ -1413,7 +1467,7 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   {
     Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
     HIPCK(launch_decode2(J.da, (const uint32_t*)(in + Lo.off_payload), J.boff, J.dlut, J.dsorted,
-                         J.code, J.czero, J.status, st));
+                         J.dsub, J.code, J.czero, J.status, st));
   }
   HIPCK(launch_scan_u32_to_u64(J.czero, nch, J.zoff, J.zoff + nch, J.tmp2, st));
   if (Lo.predictor == 1) {

@@ -8,6 +8,7 @@ namespace hpez {
 constexpr uint32_t kEncTab = 8192;   // codebook entries held in LDS by the encoder
 constexpr uint32_t kEncWords = 1026; // LDS words per chunk (1024 symbols x 32 bits + 2)
 constexpr uint32_t kDecLong = 8192;  // codes longer than the decode table kept in LDS
+constexpr uint32_t kDecSub = 8192;   // second-level decode table entries (LDS)
 
 struct EncodeArgs {
   uint64_t n;        // symbols
@@ -30,7 +31,7 @@ struct DecodeArgs {
   uint32_t chunk;
   uint32_t long_first;       // index in sorted[] of the first code longer than kLutBits
   uint32_t n_long;           // number of such codes (held in LDS when <= kDecLong)
-  uint32_t pad;
+  uint32_t n_sub;            // second-level table entries (0: none; long codes by limits)
   uint64_t lim[kLmax + 1];   // lim[l] = (first code of length l + count) << (32 - l)
   uint32_t base[kLmax + 1];  // offset of length l in sorted[] minus its first code (mod 2^32)
 };
@@ -54,8 +55,17 @@ hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chu
                                   const uint32_t* czero, const uint64_t* zoff, const T* unpred,
                                   uint64_t n_unpred, T* W, int* d_status, const Geom& g,
                                   hipStream_t st);
+// second-level tables of the codes longer than kLutBits: every kLutBits-bit
+// prefix that starts such codes gets a table indexed by the next lmax - kLutBits
+// bits (lmax: its longest code), and its first-level entry becomes
+// (table offset << 8) | 0x80 | (lmax - kLutBits).  Returns the entries used, or
+// 0 (tables not built, first level unchanged) when they would exceed cap.
+uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
+                          uint32_t* sub, uint32_t cap);
+
 hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
-                          const uint32_t* lut, const uint16_t* sorted, uint16_t* code,
+                          const uint32_t* lut, const uint16_t* sorted, const uint32_t* sub,
+                          uint16_t* code,
                           uint32_t* czero, int* status, hipStream_t st);
 
 }  // namespace hpez

@@ -67,23 +67,38 @@ __device__ __forceinline__ uint64_t look_back(uint64_t* flags, uint64_t k, int l
 
 // bit count of one chunk (lane sums of `per` symbols, wave total); ent[]
 // receives the packed entries of the lane's symbols
-// the 16 codes of one lane of a full 1024-symbol chunk (32-byte aligned)
-struct Raw16 {
-  uint4 a, b;
+// the PER codes of one lane of a full chunk of 64 PER symbols (PER 8 or 16;
+// 16-byte aligned runs)
+template <int PER>
+struct RawN {
+  uint4 v[PER / 8];
 };
-__device__ __forceinline__ Raw16 raw_load(const uint16_t* __restrict__ code, uint64_t k, int lane)
+template <int PER>
+__device__ __forceinline__ RawN<PER> raw_load(const uint16_t* __restrict__ code, uint64_t k, int lane)
 {
-  const uint4* p = reinterpret_cast<const uint4*>(code + k * 1024 + (uint64_t)lane * 16);
-  return {p[0], p[1]};
+  const uint4* p = reinterpret_cast<const uint4*>(code + k * (64 * PER) + (uint64_t)lane * PER);
+  RawN<PER> r;
+#pragma unroll
+  for (int q = 0; q < PER / 8; q++) r.v[q] = p[q];
+  return r;
 }
+template <int PER>
 __device__ __forceinline__ uint32_t raw_entries(const EncodeArgs& a, const uint32_t* tab,
-                                                const uint32_t* __restrict__ gtab, const Raw16& r,
-                                                uint32_t* ent, uint32_t& lane_bits)
+                                                const uint32_t* __restrict__ gtab,
+                                                const RawN<PER>& r, uint32_t* ent,
+                                                uint32_t& lane_bits)
 {
-  const uint32_t w[8] = {r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.b.y, r.b.z, r.b.w};
+  uint32_t w[PER / 2];
+#pragma unroll
+  for (int q = 0; q < PER / 8; q++) {
+    w[4 * q] = r.v[q].x;
+    w[4 * q + 1] = r.v[q].y;
+    w[4 * q + 2] = r.v[q].z;
+    w[4 * q + 3] = r.v[q].w;
+  }
   uint32_t bits = 0;
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
+  for (int j = 0; j < PER; j++) {
     const uint32_t c = ((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) - a.smin;
     const uint32_t e = a.lds_tab ? tab[c] : gtab[c];
     ent[j] = e;
@@ -141,6 +156,7 @@ __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uin
 // payload).  The codebook window lives in LDS once per work-group.
 constexpr int kPart = 64;  // chunks per partition
 
+template <int PER>
 __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16_t* __restrict__ code,
                                                       uint32_t* __restrict__ words,
                                                       uint16_t* __restrict__ out_cb,
@@ -167,18 +183,18 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     const uint64_t k0 = part * kPart;
     const uint32_t np = (uint32_t)(a.nch - k0 < (uint64_t)kPart ? a.nch - k0 : (uint64_t)kPart);
     uint32_t ent[16];
-    // full 1024-symbol chunks: the next chunk's codes are loaded while the
-    // current one is processed
-    const bool fast = a.chunk == 1024 && (k0 + np) * 1024 <= a.n;
+    // full chunks of 64 PER symbols: the next chunk's codes are loaded while
+    // the current one is processed
+    const bool fast = a.chunk == 64 * PER && (k0 + np) * (64 * PER) <= a.n;
     // 1. chunk bit counts
     if (fast) {
-      Raw16 cur{};
-      if ((uint32_t)w < np) cur = raw_load(code, k0 + w, lane);
+      RawN<PER> cur{};
+      if ((uint32_t)w < np) cur = raw_load<PER>(code, k0 + w, lane);
       for (uint32_t j = w; j < np; j += kEncWaves) {
-        Raw16 nxt{};
-        if (j + kEncWaves < np) nxt = raw_load(code, k0 + j + kEncWaves, lane);
+        RawN<PER> nxt{};
+        if (j + kEncWaves < np) nxt = raw_load<PER>(code, k0 + j + kEncWaves, lane);
         uint32_t lb;
-        const uint32_t t = raw_entries(a, tab, gtab, cur, ent, lb);
+        const uint32_t t = raw_entries<PER>(a, tab, gtab, cur, ent, lb);
         if (lane == 0) {
           cbits[j] = t;
           out_cb[k0 + j] = (uint16_t)t;
@@ -219,14 +235,14 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     __syncthreads();
     // 3. pack each chunk
     const uint64_t pexcl = s_excl;
-    Raw16 cur{};
-    if (fast && (uint32_t)w < np) cur = raw_load(code, k0 + w, lane);
+    RawN<PER> cur{};
+    if (fast && (uint32_t)w < np) cur = raw_load<PER>(code, k0 + w, lane);
     for (uint32_t j = w; j < np; j += kEncWaves) {
       uint32_t lb, total;
       if (fast) {
-        Raw16 nxt{};
-        if (j + kEncWaves < np) nxt = raw_load(code, k0 + j + kEncWaves, lane);
-        total = raw_entries(a, tab, gtab, cur, ent, lb);
+        RawN<PER> nxt{};
+        if (j + kEncWaves < np) nxt = raw_load<PER>(code, k0 + j + kEncWaves, lane);
+        total = raw_entries<PER>(a, tab, gtab, cur, ent, lb);
         cur = nxt;
       } else {
         total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
@@ -340,8 +356,12 @@ hipError_t launch_encode1(const EncodeArgs& a, const uint16_t* code, uint32_t* w
     // persistent grid: a few work-groups per CU, each taking partitions in order
     const uint64_t want = (a.nch + kPart - 1) / kPart;
     const unsigned grid = (unsigned)(want < 1024 ? want : 1024);
-    hipLaunchKernelGGL(encode1_kernel, dim3(grid), dim3(64 * kEncWaves), 0, st, a, code, words,
-                       out_cb, flags, ticket, packed);
+    if (a.chunk == 512)
+      hipLaunchKernelGGL(encode1_kernel<8>, dim3(grid), dim3(64 * kEncWaves), 0, st, a, code, words,
+                         out_cb, flags, ticket, packed);
+    else
+      hipLaunchKernelGGL(encode1_kernel<16>, dim3(grid), dim3(64 * kEncWaves), 0, st, a, code,
+                         words, out_cb, flags, ticket, packed);
   } else {
     const uint64_t want = (a.nch + kEncWaves - 1) / kEncWaves;
     const unsigned grid = (unsigned)(want < 2048 ? want : 2048);
@@ -461,14 +481,26 @@ hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chu
 // symbol of the codeword at the top of the window; L = its length (0: invalid).
 // Codes longer than the table are located by the canonical limits and read
 // from the LDS copy of their symbols (or the global one when too many).
-template <bool LONG_LDS>
+// MODE 0: codes longer than the first-level table by the canonical limits,
+// their symbols in LDS; 1: the same with the symbols in global memory; 2:
+// second-level tables in LDS (a prefix without a code has entry 0).
+template <int MODE>
 __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32_t* lut,
                                                const uint16_t* slong,
-                                               const uint16_t* __restrict__ sorted, uint32_t w,
-                                               uint32_t& L)
+                                               const uint16_t* __restrict__ sorted,
+                                               const uint32_t* subl, uint32_t w, uint32_t& L)
 {
   const uint32_t e = lut[w >> (32 - kLutBits)];
   L = e & 0xFFu;
+  if (MODE == 2) {
+    if (L & 0x80u) {
+      const uint32_t k = L & 0x7Fu;
+      const uint32_t e2 = subl[(e >> 8) + ((w << kLutBits) >> (32 - k))];
+      L = e2 & 0xFFu;
+      return e2 >> 8;
+    }
+    return e >> 8;
+  }
   if (L) return e >> 8;
   // longer than the table: count the limits at or below w (they are sorted)
   uint32_t c = kLutBits + 1;
@@ -480,23 +512,27 @@ __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32
   }
   L = c;
   const uint32_t idx = a.base[c] + (w >> (32 - c));
-  return LONG_LDS ? slong[idx - a.long_first] : sorted[idx];
+  return MODE == 0 ? slong[idx - a.long_first] : sorted[idx];
 }
 
-template <bool LONG_LDS>
+template <int MODE>
 __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32_t* __restrict__ words,
                                                       const uint64_t* __restrict__ bit_off,
                                                       const uint32_t* __restrict__ glut,
                                                       const uint16_t* __restrict__ sorted,
+                                                      const uint32_t* __restrict__ gsub,
                                                       uint16_t* __restrict__ code,
                                                       uint32_t* __restrict__ czero,
                                                       int* __restrict__ status)
 {
   __shared__ uint32_t lut[1 << kLutBits];
-  __shared__ uint16_t slong[LONG_LDS ? kDecLong : 1];
+  __shared__ uint16_t slong[MODE == 0 ? kDecLong : 1];
+  __shared__ uint32_t subl[MODE == 2 ? kDecSub : 1];
   for (int i = threadIdx.x; i < (1 << kLutBits); i += blockDim.x) lut[i] = glut[i];
-  if (LONG_LDS)
+  if (MODE == 0)
     for (uint32_t i = threadIdx.x; i < a.n_long; i += blockDim.x) slong[i] = sorted[a.long_first + i];
+  if (MODE == 2)
+    for (uint32_t i = threadIdx.x; i < a.n_sub; i += blockDim.x) subl[i] = gsub[i];
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0 && bit_off[a.nch] != a.nbits) atomicOr(status, 1);
@@ -551,7 +587,7 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
         wi++;
       }
       uint32_t L;
-      uint32_t sym = decode_one<LONG_LDS>(a, lut, slong, sorted, (uint32_t)(buf >> 32), L);
+      uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, (uint32_t)(buf >> 32), L);
       bad |= L == 0;
       L = L ? L : 1u;
       zeros += sym == 0;
@@ -571,7 +607,7 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
       wi++;
     }
     uint32_t L;
-    const uint32_t sym = decode_one<LONG_LDS>(a, lut, slong, sorted, (uint32_t)(buf >> 32), L);
+    const uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, (uint32_t)(buf >> 32), L);
     if (!L) {
       bad = true;
       break;
@@ -587,16 +623,19 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
 }
 
 hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
-                          const uint32_t* lut, const uint16_t* sorted, uint16_t* code,
-                          uint32_t* czero, int* status, hipStream_t st)
+                          const uint32_t* lut, const uint16_t* sorted, const uint32_t* sub,
+                          uint16_t* code, uint32_t* czero, int* status, hipStream_t st)
 {
   if (!a.nch) return hipSuccess;
   const dim3 grid((unsigned)((a.nch + 255) / 256)), block(256);
-  if (a.n_long <= kDecLong)
-    hipLaunchKernelGGL(decode2_kernel<true>, grid, block, 0, st, a, words, bit_off, lut, sorted, code,
-                       czero, status);
+  if (a.n_sub && a.n_sub <= kDecSub)
+    hipLaunchKernelGGL(decode2_kernel<2>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
+                       code, czero, status);
+  else if (a.n_long <= kDecLong)
+    hipLaunchKernelGGL(decode2_kernel<0>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
+                       code, czero, status);
   else
-    hipLaunchKernelGGL(decode2_kernel<false>, grid, block, 0, st, a, words, bit_off, lut, sorted,
+    hipLaunchKernelGGL(decode2_kernel<1>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
                        code, czero, status);
   return hipGetLastError();
 }
