@@ -440,13 +440,15 @@ static void launch_jobs_t(const TrialJob<T>* d_jobs, const uint64_t* d_wg_begin,
 
 template <typename T>
 hipError_t launch_trial_jobs(const TrialJob<T>* d_jobs, const uint64_t* d_wg_begin, int n,
-                             uint64_t total_wg, size_t lds, bool hist, bool big, hipStream_t st)
+                             uint64_t total_wg, size_t lds, bool hist, int lanes, hipStream_t st)
 {
   if (!total_wg || n <= 0) return hipSuccess;
-  if (hist && big) launch_jobs_t<T, true, 1024>(d_jobs, d_wg_begin, n, total_wg, lds, st);
-  else if (hist) launch_jobs_t<T, true, 256>(d_jobs, d_wg_begin, n, total_wg, lds, st);
-  else if (big) launch_jobs_t<T, false, 1024>(d_jobs, d_wg_begin, n, total_wg, lds, st);
-  else launch_jobs_t<T, false, 256>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  if (hist && lanes == 1024) launch_jobs_t<T, true, 1024>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else if (hist && lanes == 256) launch_jobs_t<T, true, 256>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else if (hist) launch_jobs_t<T, true, 64>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else if (lanes == 1024) launch_jobs_t<T, false, 1024>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else if (lanes == 256) launch_jobs_t<T, false, 256>(d_jobs, d_wg_begin, n, total_wg, lds, st);
+  else launch_jobs_t<T, false, 64>(d_jobs, d_wg_begin, n, total_wg, lds, st);
   return hipGetLastError();
 }
 
@@ -572,7 +574,7 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
   template hipError_t launch_stats<T>(const T*, const Geom&, const Lattice&, double,            \
                                       unsigned long long*, hipStream_t);                        \
   template hipError_t launch_trial_jobs<T>(const TrialJob<T>*, const uint64_t*, int, uint64_t,     \
-                                           size_t, bool, bool, hipStream_t);                     \
+                                           size_t, bool, int, hipStream_t);                      \
   template bool trial_box_ok<T>(const TrialArgs&, bool);                                         \
   template size_t trial_box_lds<T>(const TrialArgs&, bool);                                      \
   template hipError_t launch_trials<T>(const TrialArgs&, const TrialBox*, uint32_t, uint32_t,   \

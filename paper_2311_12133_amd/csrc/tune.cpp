@@ -403,7 +403,7 @@ int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
 // per lane count), the others one by one.
 template <typename T>
 struct TrialBatch {
-  std::vector<TrialJob<T>> small, big;
+  std::vector<TrialJob<T>> grp[3];  // by lanes per work-group: 64, 256, 1024
   struct Single {
     TrialArgs a;
     const TrialBox* boxes;
@@ -433,7 +433,8 @@ void t_add(TrialBatch<T>& tb, const TrialArgs& a, const TrialBox* boxes, uint32_
     j.n_boxes = n_boxes;
     j.n_cand = n_cand;
     j.wg_begin = 0;
-    (a.box_cap > 4096 ? tb.big : tb.small).push_back(j);
+    const int lanes = trial_lanes(a.box_cap);
+    tb.grp[lanes == 64 ? 0 : lanes == 256 ? 1 : 2].push_back(j);
   } else {
     tb.single.push_back({a, boxes, n_boxes, n_cand, X, scratch, wq, score, hist});
   }
@@ -444,7 +445,8 @@ template <typename T>
 int t_launch(hpez_ctx* ctx, TrialBatch<T>& tb, bool hist, uint8_t* d_tab, size_t tab_cap,
              hipStream_t st)
 {
-  std::vector<TrialJob<T>>* groups[2] = {&tb.small, &tb.big};
+  std::vector<TrialJob<T>>* groups[3] = {&tb.grp[0], &tb.grp[1], &tb.grp[2]};
+  const int lanes_of[3] = {64, 256, 1024};
   size_t bytes = 0;
   for (auto* gr : groups) bytes += al256(gr->size() * sizeof(TrialJob<T>)) + al256((gr->size() + 1) * 8);
   if (bytes > tab_cap) return HPEZ_EINVAL;
@@ -453,10 +455,10 @@ int t_launch(hpez_ctx* ctx, TrialBatch<T>& tb, bool hist, uint8_t* d_tab, size_t
     uint8_t* h = ctx_pin_tab(ctx, bytes, &rc);
     if (rc) return rc;
     size_t off = 0;
-    size_t offs[2][2];
-    uint64_t tot[2];
-    size_t lds[2];
-    for (int k = 0; k < 2; k++) {
+    size_t offs[3][2];
+    uint64_t tot[3];
+    size_t lds[3];
+    for (int k = 0; k < 3; k++) {
       auto& gr = *groups[k];
       uint64_t w = 0;
       lds[k] = 0;
@@ -475,10 +477,10 @@ int t_launch(hpez_ctx* ctx, TrialBatch<T>& tb, bool hist, uint8_t* d_tab, size_t
       tot[k] = w;
     }
     TCK(hipMemcpyAsync(d_tab, h, bytes, hipMemcpyHostToDevice, st));
-    for (int k = 0; k < 2; k++)
+    for (int k = 0; k < 3; k++)
       TCK(launch_trial_jobs<T>((const TrialJob<T>*)(d_tab + offs[k][0]),
                                (const uint64_t*)(d_tab + offs[k][1]), (int)groups[k]->size(),
-                               tot[k], lds[k], hist, k == 1, st));
+                               tot[k], lds[k], hist, lanes_of[k], st));
   }
   for (auto& s : tb.single)
     TCK(launch_trials<T>(s.a, s.boxes, s.n_boxes, s.n_cand, s.X, s.scratch, s.wq, s.score, s.hist,
@@ -708,7 +710,8 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     pin += t_pin_bytes(J);
   }
   // trial tables: two global variants per job is the most of any phase
-  const size_t tab_cap = al256(2 * jobs.size() * sizeof(TrialJob<T>)) + 2 * al256((2 * jobs.size() + 1) * 8) + 512;
+  const size_t tab_cap = al256(2 * jobs.size() * sizeof(TrialJob<T>)) * 3 +
+                         3 * al256((2 * jobs.size() + 1) * 8) + 512;
   dev += tab_cap;
   int rc;
   uint8_t* base = (uint8_t*)ctx_ws(ctx, dev, &rc);
@@ -817,7 +820,7 @@ uint64_t tune_footprint(const hpez_field_desc* d, const hpez_config* c)
   t_init(J);
   const size_t s = d->dtype ? 8 : 4;
   J.scratch_bytes = trial_scratch(J.g, &o, s, J.gb.size(), J.gcap, J.nbt);
-  return t_dev_bytes(J) + al256(2 * sizeof(TrialJob<double>)) + 2 * al256(3 * 8) + 512;
+  return t_dev_bytes(J) + 3 * al256(2 * sizeof(TrialJob<double>)) + 3 * al256(3 * 8) + 512;
 }
 }  // namespace hpez
 

@@ -74,11 +74,14 @@ template <typename T>
 bool trial_box_ok(const TrialArgs& a, bool hist);
 template <typename T>
 size_t trial_box_lds(const TrialArgs& a, bool hist);
-// entries [0, n) of d_jobs in one launch of total_wg work-groups; lds = the
-// largest entry's trial_box_lds; big: regions of more than 4096 points
+// entries [0, n) of d_jobs in one launch of total_wg work-groups of `lanes`
+// threads (64, 256 or 1024, by region size); lds = the largest entry's
+// trial_box_lds
 template <typename T>
 hipError_t launch_trial_jobs(const TrialJob<T>* d_jobs, const uint64_t* d_wg_begin, int n,
-                             uint64_t total_wg, size_t lds, bool hist, bool big, hipStream_t st);
+                             uint64_t total_wg, size_t lds, bool hist, int lanes, hipStream_t st);
+// lanes per trial work-group for a region of box_cap points
+inline int trial_lanes(uint64_t box_cap) { return box_cap > 4096 ? 1024 : box_cap > 1536 ? 256 : 64; }
 template <typename T>
 hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_t n_boxes,
                                 uint32_t max_pts, const T* X, double inv2e, uint32_t R,
