@@ -41,6 +41,7 @@ struct hpez_ctx {
   size_t ws_limit = 0;  // 0: no cap on the workspace
   uint8_t* pin_pre = nullptr;  // first bytes of the streams being decompressed
   size_t pin_pre_bytes = 0;
+  hipEvent_t ev_sync = nullptr;  // host waits for part of a stream's work
   // kernel timing (hpez_profile_enable)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -927,6 +928,8 @@ struct CJob {
   uint32_t lo = 0;
   double h_wq[3 * 16 * 4];
   uint32_t maxlen = 0;  // longest code length
+  bool early = false;   // verbatim values gathered before the codebook
+  uint64_t off_unpred = 0;
   // device workspace
   T* W = nullptr;
   uint16_t* code = nullptr;
@@ -1161,6 +1164,30 @@ void c_codebook(CJob<T>& J)
   write_header(J.h_hdr, J.d, J.c, Lo);
 }
 
+// Verbatim values (Sec. 4: unpredictable points) into their section while the
+// host builds the codebook: the section's offset depends only on the block
+// configurations and anchors.  Needs room for every point to be verbatim (the
+// count is known only after the histogram); the rest of the stream, padding
+// included, is zeroed around it.
+template <typename T>
+int c_gather_early(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
+{
+  const uint64_t s = sizeof(T);
+  Layout t = J.Lo;
+  t.n_unpred = t.n_outlier = t.n_patch = t.n_chunks = t.payload_bits = 0;
+  t.sym_min = 1;
+  t.sym_max = 0;
+  layout(&t, s);
+  if (J.cap < t.off_unpred + J.N * s) return HPEZ_OK;
+  J.early = true;
+  J.off_unpred = t.off_unpred;
+  HIPCK(hipMemsetAsync(J.out, 0, t.off_unpred, st));
+  Span sp(ctx, "gather_unpred", J.N * 2, st);
+  HIPCK(launch_gather_unpred<T>(J.code, J.N, J.c->chunk, J.czero, J.zoff, J.tmp2, J.X,
+                                (T*)(J.out + t.off_unpred), J.g, st));
+  return HPEZ_OK;
+}
+
 // assemble the stream
 template <typename T>
 int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
@@ -1176,7 +1203,13 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
     HIPCK(hipMemcpyAsync(J.dlen, J.h_len, J.nsym, hipMemcpyHostToDevice, st));
     HIPCK(hipMemcpyAsync(J.dcw, J.h_cw, (size_t)J.nsym * 4, hipMemcpyHostToDevice, st));
   }
-  HIPCK(hipMemsetAsync(out, 0, Lo.total, st));
+  if (J.early) {
+    if (Lo.off_unpred != J.off_unpred) return HPEZ_EINVAL;
+    const uint64_t vend = Lo.off_unpred + Lo.n_unpred * s;
+    HIPCK(hipMemsetAsync(out + vend, 0, Lo.total - vend, st));
+  } else {
+    HIPCK(hipMemsetAsync(out, 0, Lo.total, st));
+  }
   HIPCK(hipMemcpyAsync(out, J.h_hdr, kHdrBytes, hipMemcpyHostToDevice, st));
   if (J.nb)
     HIPCK(hipMemcpyAsync(out + Lo.off_blocks, c->block_cfg, J.nb, hipMemcpyHostToDevice, st));
@@ -1184,7 +1217,7 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   if (Lo.sym_max >= Lo.sym_min)
     HIPCK(hipMemcpyAsync(out + Lo.off_len, J.h_len + Lo.sym_min, Lo.sym_max - Lo.sym_min + 1,
                          hipMemcpyHostToDevice, st));
-  if (Lo.n_unpred) {
+  if (Lo.n_unpred && !J.early) {
     // verbatim values in stream order (Sec. 4: unpredictable points)
     Span sp(ctx, "gather_unpred", J.N * 2 + Lo.n_unpred * s * 2, st);
     HIPCK(launch_gather_unpred<T>(J.code, J.N, c->chunk, J.czero, J.zoff, J.tmp2, J.X,
@@ -1235,7 +1268,13 @@ int compress_jobs(hpez_ctx* ctx, std::vector<CJob<T>>& jobs, hipStream_t st)
   for (auto& J : jobs)
     if (!J.rc && !J.kind)
       HIPCK(hipMemcpyAsync(J.h_hist, J.hist, (size_t)J.nsym * 4, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
+  // the histograms are on the host once ev_sync completes; the verbatim values
+  // are gathered meanwhile
+  if (!ctx->ev_sync) HIPCK(hipEventCreateWithFlags(&ctx->ev_sync, hipEventDisableTiming));
+  HIPCK(hipEventRecord(ctx->ev_sync, st));
+  for (auto& J : jobs)
+    if (!J.rc && !J.kind && (rc = c_gather_early(ctx, J, st))) return rc;
+  HIPCK(hipEventSynchronize(ctx->ev_sync));
   host_parallel(n, [&](int i) {
     if (!jobs[i].rc && !jobs[i].kind) c_codebook(jobs[i]);
   });
@@ -1660,6 +1699,7 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
   if (ctx->pin_pre) (void)hipHostFree(ctx->pin_pre);
+  if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
