@@ -148,13 +148,85 @@ __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uin
   return t;
 }
 
+// Packs one chunk whose first bit is global bit `excl`: the wave assembles the
+// chunk in its LDS buffer B (local bit 0 is global bit excl & ~31) and writes it
+// as whole 32-bit words; the two words the chunk may share with its neighbours
+// are OR-ed atomically into the zeroed payload.  A lane whose run fits in 128
+// bits builds it in registers and ORs at most four words into B; a longer run
+// falls back to one or two LDS ORs per codeword.
+__device__ __forceinline__ void pack_chunk(uint32_t* B, uint32_t* __restrict__ words, uint64_t excl,
+                                           uint32_t total, uint32_t lb, const uint32_t* ent,
+                                           uint32_t per, int lane)
+{
+  uint32_t incl = lb;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t lane_off = incl - lb;
+  const uint32_t sh = (uint32_t)(excl & 31);
+  const uint32_t nw = (sh + total + 31) / 32;
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t i = lane; i < nw + 1; i += 64) B[i] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t pos = sh + lane_off;
+  const uint32_t off0 = pos & 31;
+  if (off0 + lb <= 128) {
+    unsigned __int128 acc = 0;
+    for (uint32_t jj = 0; jj < per; jj++) {
+      const uint32_t e = ent[jj];
+      acc = (acc << (e & 63u)) | (unsigned __int128)(e >> 6);
+    }
+    if (lb) {
+      acc <<= 128 - off0 - lb;
+      const uint32_t wi = pos >> 5;
+      const uint32_t nwl = (off0 + lb + 31) >> 5;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++) {
+        const uint32_t v = (uint32_t)(acc >> (96 - 32 * q));
+        if (q < nwl && v) atomicOr(&B[wi + q], v);
+      }
+    }
+  } else {
+    for (uint32_t jj = 0; jj < per; jj++) {
+      const uint32_t e = ent[jj];
+      const uint32_t L = e & 63u;
+      if (L) {
+        const uint32_t cw = e >> 6;
+        const uint32_t wi = pos >> 5, off = pos & 31;
+        const uint64_t v = (uint64_t)cw << (64 - L - off);
+        const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+        if (hi) atomicOr(&B[wi], hi);
+        if (lo) atomicOr(&B[wi + 1], lo);
+        pos += L;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint64_t w0 = excl >> 5;
+  for (uint32_t i = lane; i < nw; i += 64) {
+    const uint32_t v = B[i];
+    if (i == 0 || i == nw - 1) {
+      if (v) atomicOr(&words[w0 + i], v);
+    } else {
+      words[w0 + i] = v;
+    }
+  }
+}
+
 // Persistent work-groups take partitions of kPart chunks in ticket order.  A
 // partition's chunk bit counts are summed in LDS, one decoupled look-back per
-// partition gives its bit offset, then each wave packs its chunks: codewords
-// are assembled in LDS and written as whole 32-bit words (the two words a
-// chunk shares with its neighbours are OR-ed atomically into the zeroed
-// payload).  The codebook window lives in LDS once per work-group.
-constexpr int kPart = 64;  // chunks per partition
+// partition gives its bit offset, then each wave packs its chunks.  Full
+// partitions keep each wave's kEncCpw chunks of codes in registers from the
+// counting pass to the packing pass, so the codes are read from memory once;
+// the ragged last partition reads them again.  The codebook window lives in
+// LDS once per work-group.
+constexpr int kEncCpw = 8;                   // chunks per wave and partition
+constexpr int kPart = kEncWaves * kEncCpw;   // chunks per partition
 
 template <int PER>
 __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16_t* __restrict__ code,
@@ -175,6 +247,7 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     for (uint32_t i = threadIdx.x; i < a.ntab; i += blockDim.x) tab[i] = gtab[i];
   const uint64_t nparts = (a.nch + kPart - 1) / kPart;
   uint32_t* B = buf[w];
+  const uint32_t per = a.chunk / 64;
   for (;;) {
     if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
     __syncthreads();
@@ -183,23 +256,22 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     const uint64_t k0 = part * kPart;
     const uint32_t np = (uint32_t)(a.nch - k0 < (uint64_t)kPart ? a.nch - k0 : (uint64_t)kPart);
     uint32_t ent[16];
-    // full chunks of 64 PER symbols: the next chunk's codes are loaded while
-    // the current one is processed
-    const bool fast = a.chunk == 64 * PER && (k0 + np) * (64 * PER) <= a.n;
+    // full chunks of 64 PER symbols, all of them complete
+    const bool fast = a.chunk == 64 * PER && np == (uint32_t)kPart && (k0 + np) * (64 * PER) <= a.n;
+    RawN<PER> raw[kEncCpw];
     // 1. chunk bit counts
     if (fast) {
-      RawN<PER> cur{};
-      if ((uint32_t)w < np) cur = raw_load<PER>(code, k0 + w, lane);
-      for (uint32_t j = w; j < np; j += kEncWaves) {
-        RawN<PER> nxt{};
-        if (j + kEncWaves < np) nxt = raw_load<PER>(code, k0 + j + kEncWaves, lane);
+#pragma unroll
+      for (int c = 0; c < kEncCpw; c++) raw[c] = raw_load<PER>(code, k0 + w + c * kEncWaves, lane);
+#pragma unroll
+      for (int c = 0; c < kEncCpw; c++) {
+        const uint32_t j = w + c * kEncWaves;
         uint32_t lb;
-        const uint32_t t = raw_entries<PER>(a, tab, gtab, cur, ent, lb);
+        const uint32_t t = raw_entries<PER>(a, tab, gtab, raw[c], ent, lb);
         if (lane == 0) {
           cbits[j] = t;
           out_cb[k0 + j] = (uint16_t)t;
         }
-        cur = nxt;
       }
     } else {
       for (uint32_t j = w; j < np; j += kEncWaves) {
@@ -235,59 +307,19 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
     __syncthreads();
     // 3. pack each chunk
     const uint64_t pexcl = s_excl;
-    RawN<PER> cur{};
-    if (fast && (uint32_t)w < np) cur = raw_load<PER>(code, k0 + w, lane);
-    for (uint32_t j = w; j < np; j += kEncWaves) {
-      uint32_t lb, total;
-      if (fast) {
-        RawN<PER> nxt{};
-        if (j + kEncWaves < np) nxt = raw_load<PER>(code, k0 + j + kEncWaves, lane);
-        total = raw_entries<PER>(a, tab, gtab, cur, ent, lb);
-        cur = nxt;
-      } else {
-        total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+    if (fast) {
+#pragma unroll
+      for (int c = 0; c < kEncCpw; c++) {
+        const uint32_t j = w + c * kEncWaves;
+        uint32_t lb;
+        const uint32_t total = raw_entries<PER>(a, tab, gtab, raw[c], ent, lb);
+        pack_chunk(B, words, pexcl + cbits[j], total, lb, ent, PER, lane);
       }
-      uint32_t incl = lb;
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      const uint32_t lane_off = incl - lb;
-      const uint64_t excl = pexcl + cbits[j];
-      // assemble in LDS: local bit 0 is global bit (excl & ~31)
-      const uint32_t sh = (uint32_t)(excl & 31);
-      const uint32_t nw = (sh + total + 31) / 32;
-      __builtin_amdgcn_wave_barrier();
-      for (uint32_t i = lane; i < nw + 1; i += 64) B[i] = 0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      uint32_t pos = sh + lane_off;
-      const uint32_t per = a.chunk / 64;
-      for (uint32_t jj = 0; jj < per; jj++) {
-        const uint32_t e = ent[jj];
-        const uint32_t L = e & 63u;
-        if (L) {
-          const uint32_t cw = e >> 6;
-          const uint32_t wi = pos >> 5, off = pos & 31;
-          const uint64_t v = (uint64_t)cw << (64 - L - off);
-          const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
-          if (hi) atomicOr(&B[wi], hi);
-          if (lo) atomicOr(&B[wi + 1], lo);
-          pos += L;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const uint64_t w0 = excl >> 5;
-      for (uint32_t i = lane; i < nw; i += 64) {
-        const uint32_t v = B[i];
-        if (i == 0 || i == nw - 1) {
-          if (v) atomicOr(&words[w0 + i], v);
-        } else {
-          words[w0 + i] = v;
-        }
+    } else {
+      for (uint32_t j = w; j < np; j += kEncWaves) {
+        uint32_t lb;
+        const uint32_t total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
+        pack_chunk(B, words, pexcl + cbits[j], total, lb, ent, per, lane);
       }
     }
     __syncthreads();
