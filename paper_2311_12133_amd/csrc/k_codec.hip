@@ -547,6 +547,8 @@ __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32
   return MODE == 0 ? slong[idx - a.long_first] : sorted[idx];
 }
 
+constexpr uint32_t kDecRing = 16;  // LDS ring slots per decoding lane (a power of two)
+
 template <int MODE>
 __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32_t* __restrict__ words,
                                                       const uint64_t* __restrict__ bit_off,
@@ -560,6 +562,7 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   __shared__ uint32_t lut[1 << kLutBits];
   __shared__ uint16_t slong[MODE == 0 ? kDecLong : 1];
   __shared__ uint32_t subl[MODE == 2 ? kDecSub : 1];
+  __shared__ uint32_t ring[kDecRing * 256];
   for (int i = threadIdx.x; i < (1 << kLutBits); i += blockDim.x) lut[i] = glut[i];
   if (MODE == 0)
     for (uint32_t i = threadIdx.x; i < a.n_long; i += blockDim.x) slong[i] = sorted[a.long_first + i];
@@ -583,23 +586,56 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     czero[k] = 0;
     return;
   }
-  // 64-bit bit buffer, next bit at the top; `have` valid bits.  The word after
-  // the buffer is loaded one refill ahead, so its latency overlaps decoding:
-  // the load is unconditional (index clamped to the last word; bits past the
-  // payload are never part of a valid codeword) so nothing waits for it early.
+  // 64-bit bit buffer, next bit at the top; `have` valid bits; `pre` holds the
+  // payload word rd, the next one to enter the buffer.  Each lane's words pass
+  // through its own LDS ring of kDecRing slots (words rd..wr-1, one slot
+  // column per thread, so the ring accesses of a wave are bank-conflict free).
+  // The ring is topped up in blocks of four words at group boundaries from
+  // global loads issued one block ahead, so decoding waits on LDS only.
+  // Indexes past the payload are clamped to its last word (those bits are
+  // never part of a valid codeword).
   const uint64_t wlast = nwords - 1;
-  uint64_t wi = pos >> 5;
+  uint32_t* R = ring + threadIdx.x;
+  auto gw = [&](uint64_t i) { return words[i < wlast ? i : wlast]; };
+  uint64_t rd = pos >> 5;
+  uint64_t wr = rd;
   uint64_t buf;
   int have;
+  uint32_t pre;
   {
+    uint32_t x[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) x[q] = gw(wr + q);
+#pragma unroll
+    for (int q = 0; q < 12; q++) R[((wr + q) & (kDecRing - 1)) * 256] = x[q];
+    wr += 12;
     const uint32_t skip = (uint32_t)(pos & 31);
-    const uint64_t w = words[wi < wlast ? wi : wlast];
-    buf = (w << 32) << skip;
+    buf = ((uint64_t)x[0] << 32) << skip;
     have = 32 - (int)skip;
-    wi++;
+    rd++;
+    pre = x[1];
   }
-  uint32_t pre = words[wi < wlast ? wi : wlast];
-  wi++;
+  uint32_t st0 = gw(wr), st1 = gw(wr + 1), st2 = gw(wr + 2), st3 = gw(wr + 3);
+  // a group of eight symbols moves at most eight words into the buffer and
+  // reads `pre` one word further: nine words must be in the ring
+  auto top_up = [&]() {
+    if (wr + 4 <= rd + kDecRing) {
+      R[(wr & (kDecRing - 1)) * 256] = st0;
+      R[((wr + 1) & (kDecRing - 1)) * 256] = st1;
+      R[((wr + 2) & (kDecRing - 1)) * 256] = st2;
+      R[((wr + 3) & (kDecRing - 1)) * 256] = st3;
+      wr += 4;
+      st0 = gw(wr), st1 = gw(wr + 1), st2 = gw(wr + 2), st3 = gw(wr + 3);
+    }
+    while (wr < rd + 9) {
+      R[(wr & (kDecRing - 1)) * 256] = st0;
+      R[((wr + 1) & (kDecRing - 1)) * 256] = st1;
+      R[((wr + 2) & (kDecRing - 1)) * 256] = st2;
+      R[((wr + 3) & (kDecRing - 1)) * 256] = st3;
+      wr += 4;
+      st0 = gw(wr), st1 = gw(wr + 1), st2 = gw(wr + 2), st3 = gw(wr + 3);
+    }
+  };
   uint32_t zeros = 0;
   bool bad = false;
   const uint32_t cnt_all = (uint32_t)(end - beg);
@@ -609,14 +645,15 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   // every group is one 16-byte store.
   const uint32_t ngroups = cnt_all / 8;
   for (uint32_t gi = 0; gi < ngroups; gi++) {
+    top_up();
     uint32_t pk[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (uint32_t t = 0; t < 8; t++) {
       if (have < 32) {
         buf |= ((uint64_t)pre << 32) >> have;
         have += 32;
-        pre = words[wi < wlast ? wi : wlast];
-        wi++;
+        rd++;
+        pre = R[(rd & (kDecRing - 1)) * 256];
       }
       uint32_t L;
       uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, (uint32_t)(buf >> 32), L);
@@ -630,13 +667,14 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     }
     *reinterpret_cast<uint4*>(code + beg + 8 * gi) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
   }
-  // the tail of the last chunk of the field
+  // the tail of the last chunk of the field (fewer than eight symbols)
+  top_up();
   for (uint32_t t = ngroups * 8; t < cnt_all && !bad; t++) {
     if (have < 32) {
       buf |= ((uint64_t)pre << 32) >> have;
       have += 32;
-      pre = words[wi < wlast ? wi : wlast];
-      wi++;
+      rd++;
+      pre = R[(rd & (kDecRing - 1)) * 256];
     }
     uint32_t L;
     const uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, (uint32_t)(buf >> 32), L);
