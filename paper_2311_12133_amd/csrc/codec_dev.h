@@ -8,7 +8,9 @@ namespace hpez {
 constexpr uint32_t kEncTab = 8192;   // codebook entries held in LDS by the encoder
 constexpr uint32_t kEncWords = 1026; // LDS words per chunk (1024 symbols x 32 bits + 2)
 constexpr uint32_t kDecLong = 8192;  // codes longer than the decode table kept in LDS
-constexpr uint32_t kDecSub = 8192;   // second-level decode table entries (LDS)
+// second-level decode table entries (LDS; with the first level and the input
+// rings, two decoding work-groups still fit in one CU's 160 KiB)
+constexpr uint32_t kDecSub = 12160;
 
 struct EncodeArgs {
   uint64_t n;        // symbols

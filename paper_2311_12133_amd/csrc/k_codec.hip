@@ -520,7 +520,8 @@ template <int MODE>
 __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32_t* lut,
                                                const uint16_t* slong,
                                                const uint16_t* __restrict__ sorted,
-                                               const uint32_t* subl, uint32_t w, uint32_t& L)
+                                               const uint32_t* subl, const uint32_t* sbase,
+                                               uint32_t w, uint32_t& L)
 {
   const uint32_t e = lut[w >> (32 - kLutBits)];
   L = e & 0xFFu;
@@ -543,7 +544,7 @@ __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32
     return 0;
   }
   L = c;
-  const uint32_t idx = a.base[c] + (w >> (32 - c));
+  const uint32_t idx = sbase[c] + (w >> (32 - c));
   return MODE == 0 ? slong[idx - a.long_first] : sorted[idx];
 }
 
@@ -563,6 +564,10 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   __shared__ uint16_t slong[MODE == 0 ? kDecLong : 1];
   __shared__ uint32_t subl[MODE == 2 ? kDecSub : 1];
   __shared__ uint32_t ring[kDecRing * 256];
+  // per-length offsets, indexed by a computed length (an LDS read instead of
+  // a load from the kernel arguments)
+  __shared__ uint32_t sbase[MODE == 2 ? 1 : kLmax + 1];
+  if (MODE != 2 && threadIdx.x <= (unsigned)kLmax) sbase[threadIdx.x] = a.base[threadIdx.x];
   for (int i = threadIdx.x; i < (1 << kLutBits); i += blockDim.x) lut[i] = glut[i];
   if (MODE == 0)
     for (uint32_t i = threadIdx.x; i < a.n_long; i += blockDim.x) slong[i] = sorted[a.long_first + i];
@@ -656,7 +661,7 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
         pre = R[(rd & (kDecRing - 1)) * 256];
       }
       uint32_t L;
-      uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, (uint32_t)(buf >> 32), L);
+      uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, sbase, (uint32_t)(buf >> 32), L);
       bad |= L == 0;
       L = L ? L : 1u;
       zeros += sym == 0;
@@ -677,7 +682,7 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
       pre = R[(rd & (kDecRing - 1)) * 256];
     }
     uint32_t L;
-    const uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, (uint32_t)(buf >> 32), L);
+    const uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, sbase, (uint32_t)(buf >> 32), L);
     if (!L) {
       bad = true;
       break;
