@@ -654,12 +654,13 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     uint32_t pk[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (uint32_t t = 0; t < 8; t++) {
-      if (have < 32) {
-        buf |= ((uint64_t)pre << 32) >> have;
-        have += 32;
-        rd++;
-        pre = R[(rd & (kDecRing - 1)) * 256];
-      }
+      // refill without a branch: the ring read of the next word is issued at
+      // every step, beside the table lookup
+      const bool need = have < 32;
+      buf |= need ? ((uint64_t)pre << 32) >> (have & 31) : 0ull;
+      have += need ? 32 : 0;
+      rd += need ? 1 : 0;
+      pre = R[(rd & (kDecRing - 1)) * 256];
       uint32_t L;
       uint32_t sym = decode_one<MODE>(a, lut, slong, sorted, subl, sbase, (uint32_t)(buf >> 32), L);
       bad |= L == 0;
