@@ -587,7 +587,8 @@ uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t
     const uint64_t cw = fill[l]++;
     if (l <= kLutBits) continue;
     const uint32_t pre = (uint32_t)(cw >> (l - kLutBits));
-    if (l > lmax[pre]) lmax[pre] = (uint8_t)l;
+    const int lc = l < kLutBits + kDecSubBits ? l : kLutBits + kDecSubBits;
+    if (lc > lmax[pre]) lmax[pre] = (uint8_t)lc;
   }
   uint32_t off[1u << kLutBits];
   uint64_t total = 0;
@@ -605,6 +606,7 @@ uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t
     if (l <= kLutBits) continue;
     const uint32_t pre = (uint32_t)(cw >> (l - kLutBits));
     const int lm = lmax[pre];
+    if (l > lm) continue;  // beyond the table depth: by the limits
     const uint64_t rest = cw & ((1ull << (l - kLutBits)) - 1);
     const uint64_t first = off[pre] + (rest << (lm - l));
     for (uint64_t j = 0; j < (1ull << (lm - l)); j++) sub[first + j] = (s << 8) | (uint32_t)l;

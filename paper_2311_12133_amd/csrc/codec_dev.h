@@ -8,9 +8,13 @@ namespace hpez {
 constexpr uint32_t kEncTab = 8192;   // codebook entries held in LDS by the encoder
 constexpr uint32_t kEncWords = 1026; // LDS words per chunk (1024 symbols x 32 bits + 2)
 constexpr uint32_t kDecLong = 8192;  // codes longer than the decode table kept in LDS
-// second-level decode table entries (LDS; with the first level and the input
-// rings, two decoding work-groups still fit in one CU's 160 KiB)
-constexpr uint32_t kDecSub = 12160;
+// second-level decode table entries (LDS; with the first level, the symbols of
+// the long codes and the input rings, two decoding work-groups still fit in
+// one CU's 160 KiB)
+constexpr uint32_t kDecSub = 8064;
+// index bits of one second-level table at most: codes longer than kLutBits +
+// kDecSubBits are found by the canonical limits instead
+constexpr int kDecSubBits = 9;
 
 struct EncodeArgs {
   uint64_t n;        // symbols
@@ -58,10 +62,12 @@ hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chu
                                   uint64_t n_unpred, T* W, int* d_status, const Geom& g,
                                   hipStream_t st);
 // second-level tables of the codes longer than kLutBits: every kLutBits-bit
-// prefix that starts such codes gets a table indexed by the next lmax - kLutBits
-// bits (lmax: its longest code), and its first-level entry becomes
-// (table offset << 8) | 0x80 | (lmax - kLutBits).  Returns the entries used, or
-// 0 (tables not built, first level unchanged) when they would exceed cap.
+// prefix that starts such codes gets a table indexed by the next
+// k = min(lmax - kLutBits, kDecSubBits) bits (lmax: its longest code), and its
+// first-level entry becomes (table offset << 8) | 0x80 | k.  Entries of codes
+// longer than kLutBits + k stay 0 (found by the canonical limits).  Returns the
+// entries used, or 0 (tables not built, first level unchanged) when they would
+// exceed cap.
 uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
                           uint32_t* sub, uint32_t cap);
 

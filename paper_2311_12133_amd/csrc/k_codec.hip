@@ -515,7 +515,9 @@ hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chu
 // from the LDS copy of their symbols (or the global one when too many).
 // MODE 0: codes longer than the first-level table by the canonical limits,
 // their symbols in LDS; 1: the same with the symbols in global memory; 2:
-// second-level tables in LDS (a prefix without a code has entry 0).
+// second-level tables in LDS first (a prefix without a code has entry 0), the
+// limits for codes longer than the second level (their symbols in LDS when
+// they fit).
 template <int MODE>
 __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32_t* lut,
                                                const uint16_t* slong,
@@ -526,13 +528,12 @@ __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32
   const uint32_t e = lut[w >> (32 - kLutBits)];
   L = e & 0xFFu;
   if (MODE == 2) {
-    if (L & 0x80u) {
-      const uint32_t k = L & 0x7Fu;
-      const uint32_t e2 = subl[(e >> 8) + ((w << kLutBits) >> (32 - k))];
-      L = e2 & 0xFFu;
-      return e2 >> 8;
-    }
-    return e >> 8;
+    if (!(L & 0x80u)) return e >> 8;
+    const uint32_t k = L & 0x7Fu;
+    const uint32_t e2 = subl[(e >> 8) + ((w << kLutBits) >> (32 - k))];
+    L = e2 & 0xFFu;
+    if (L) return e2 >> 8;
+    // longer than the second level (or no code): by the limits below
   }
   if (L) return e >> 8;
   // longer than the table: count the limits at or below w (they are sorted)
@@ -545,7 +546,8 @@ __device__ __forceinline__ uint32_t decode_one(const DecodeArgs& a, const uint32
   }
   L = c;
   const uint32_t idx = sbase[c] + (w >> (32 - c));
-  return MODE == 0 ? slong[idx - a.long_first] : sorted[idx];
+  if (MODE == 0 || (MODE == 2 && a.n_long <= kDecLong)) return slong[idx - a.long_first];
+  return sorted[idx];
 }
 
 constexpr uint32_t kDecRing = 16;  // LDS ring slots per decoding lane (a power of two)
@@ -561,15 +563,15 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
                                                       int* __restrict__ status)
 {
   __shared__ uint32_t lut[1 << kLutBits];
-  __shared__ uint16_t slong[MODE == 0 ? kDecLong : 1];
+  __shared__ uint16_t slong[MODE != 1 ? kDecLong : 1];
   __shared__ uint32_t subl[MODE == 2 ? kDecSub : 1];
   __shared__ uint32_t ring[kDecRing * 256];
   // per-length offsets, indexed by a computed length (an LDS read instead of
   // a load from the kernel arguments)
-  __shared__ uint32_t sbase[MODE == 2 ? 1 : kLmax + 1];
-  if (MODE != 2 && threadIdx.x <= (unsigned)kLmax) sbase[threadIdx.x] = a.base[threadIdx.x];
+  __shared__ uint32_t sbase[kLmax + 1];
+  if (threadIdx.x <= (unsigned)kLmax) sbase[threadIdx.x] = a.base[threadIdx.x];
   for (int i = threadIdx.x; i < (1 << kLutBits); i += blockDim.x) lut[i] = glut[i];
-  if (MODE == 0)
+  if (MODE == 0 || (MODE == 2 && a.n_long <= kDecLong))
     for (uint32_t i = threadIdx.x; i < a.n_long; i += blockDim.x) slong[i] = sorted[a.long_first + i];
   if (MODE == 2)
     for (uint32_t i = threadIdx.x; i < a.n_sub; i += blockDim.x) subl[i] = gsub[i];
@@ -704,6 +706,7 @@ hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint
 {
   if (!a.nch) return hipSuccess;
   const dim3 grid((unsigned)((a.nch + 255) / 256)), block(256);
+  // built second-level tables rewrite first-level entries: mode 2 reads them
   if (a.n_sub && a.n_sub <= kDecSub)
     hipLaunchKernelGGL(decode2_kernel<2>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
                        code, czero, status);
