@@ -18,6 +18,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--shape 512,512,512]
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -27,6 +29,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+
+
+@contextlib.contextmanager
+def paused_gc():
+    """Python's cyclic garbage collector paused over a timed region, as timeit
+    does: a full collection of this process's objects (torch, numpy) takes
+    tens of milliseconds and would land inside whichever library call happened
+    to allocate the object that triggered it."""
+    gc.collect()
+    gc.freeze()
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+        gc.unfreeze()
 
 
 def log(*a):
@@ -133,13 +153,14 @@ def main():
             f"decompress {r[2]*1e3:.2f} ms ratio {nbytes / r[3]:.2f}")
 
     binding.profile_enable(0, True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    times = []
-    for i in range(args.steps):
-        times.append(step())
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
+    with paused_gc():
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        times = []
+        for i in range(args.steps):
+            times.append(step())
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
     stats = binding.profile_read(0)
     binding.profile_enable(0, False)
     log(f"timed {args.steps} steps in {t_total:.3f} s")
@@ -277,8 +298,9 @@ def batch_section(args, binding, fields, torch):
               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
     tp, tb_ = [], []
     for i in range(args.batch_steps):
-        tp.append(plain())
-        tb_.append(batched())
+        with paused_gc():
+            tp.append(plain())
+            tb_.append(batched())
         log(f"batch step {i}: plain tune+compress {tp[-1][0]*1e3:.1f} ms decompress "
             f"{tp[-1][1]*1e3:.1f} ms | batched {tb_[-1][0]*1e3:.1f} ms / {tb_[-1][1]*1e3:.1f} ms")
     sp, sb = tp[-1][2], tb_[-1][2]
@@ -395,7 +417,8 @@ def serving_section(args, binding, fields, torch, compress_gbps):
     srv = Server(device=0, slots=args.serve_slots, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
                  max_batch=16)
     try:
-        st = srv.run(reqs, on_arrival=on_arrival, on_done=on_done)
+        with paused_gc():
+            st = srv.run(reqs, on_arrival=on_arrival, on_done=on_done)
     finally:
         srv.close()
     torch.cuda.synchronize()
