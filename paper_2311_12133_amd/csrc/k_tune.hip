@@ -570,6 +570,30 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) hist_nonzero_kernel(const uint32_t* __restrict__ hist,
+                                                           uint32_t nsym, uint32_t* __restrict__ count,
+                                                           uint32_t* __restrict__ pairs, uint32_t cap)
+{
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsym) return;
+  const uint32_t c = hist[k];
+  if (!c) return;
+  const uint32_t i = atomicAdd(count, 1u);
+  if (i < cap) {
+    pairs[2 * i] = k;
+    pairs[2 * i + 1] = c;
+  }
+}
+
+hipError_t launch_hist_nonzero(const uint32_t* d_hist, uint32_t nsym, uint32_t* d_count,
+                               uint32_t* d_pairs, uint32_t cap, hipStream_t st)
+{
+  if (!nsym) return hipSuccess;
+  hipLaunchKernelGGL(hist_nonzero_kernel, dim3((nsym + 255) / 256), dim3(256), 0, st, d_hist, nsym,
+                     d_count, d_pairs, cap);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                                 \
   template hipError_t launch_stats<T>(const T*, const Geom&, const Lattice&, double,            \
                                       unsigned long long*, hipStream_t);                        \

@@ -65,6 +65,21 @@ double entropy_bits(const uint32_t* h, uint32_t nsym)
   return acc / (double)n;
 }
 
+// the same estimate from the nonzero bins as (bin, count) pairs in any order:
+// sorted by bin, the sums run over the same terms in the same order
+double entropy_bits_pairs(const uint32_t* pairs, uint32_t n)
+{
+  std::vector<std::pair<uint32_t, uint32_t>> v(n);
+  for (uint32_t i = 0; i < n; i++) v[i] = {pairs[2 * i], pairs[2 * i + 1]};
+  std::sort(v.begin(), v.end());
+  uint64_t tot = 0;
+  for (const auto& b : v) tot += b.second;
+  if (tot == 0) return 0.0;
+  double acc = 0.0;
+  for (const auto& b : v) acc += (double)b.second * std::log2((double)tot / (double)b.second);
+  return acc / (double)tot;
+}
+
 int64_t anchor_count(const hpez_field_desc* d, int frozen, int64_t A)
 {
   int64_t c = 1;
@@ -206,7 +221,8 @@ struct TJob {
   unsigned long long* bscore = nullptr;
   unsigned long long* dummy = nullptr;
   uint32_t* hist[3] = {nullptr, nullptr, nullptr};
-  int* flag = nullptr;
+  uint32_t* nz[3] = {nullptr, nullptr, nullptr};  // nonzero (bin, count) pairs per histogram
+  int* flag = nullptr;  // [0] non-finite input, [4 + v] pair count of histogram v
   int* lflag = nullptr;
   double* wq = nullptr;
   double* part = nullptr;
@@ -214,6 +230,8 @@ struct TJob {
   unsigned long long* sums = nullptr;
   // pinned host staging
   uint32_t* h_hist[3] = {nullptr, nullptr, nullptr};
+  uint32_t* h_nz[3] = {nullptr, nullptr, nullptr};
+  uint32_t* h_nzn = nullptr;  // the three pair counts
   unsigned long long* h_score[2] = {nullptr, nullptr};
   unsigned long long* h_bscore = nullptr;
   double* h_mm = nullptr;
@@ -274,7 +292,8 @@ size_t t_dev_bytes(const TJob<T>& J)
   const size_t nb = (size_t)J.nbt;
   return al256(J.gb.size() * sizeof(TrialBox)) + al256(nb * sizeof(TrialBox)) +
          al256(J.scratch_bytes) + 2 * al256(kNCand * 16 * 8) + al256(nb * kNCand * 8) +
-         al256(16 * 8) + 3 * al256(J.nsym * 4) + 2 * al256(64) + al256(3 * 16 * 4 * 8) +
+         al256(16 * 8) + 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + 2 * al256(64) +
+         al256(3 * 16 * 4 * 8) +
          al256(2 * 1024 * 8) + al256(64) + al256(12 * 8) + 256;
 }
 
@@ -282,8 +301,8 @@ template <typename T>
 size_t t_pin_bytes(const TJob<T>& J)
 {
   if (J.done) return 0;
-  return 3 * al256(J.nsym * 4) + 2 * al256(kNCand * 16 * 8) + al256((size_t)J.nbt * kNCand * 8) +
-         al256(64) + al256(12 * 8) + 256;
+  return 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + al256(16) + 2 * al256(kNCand * 16 * 8) +
+         al256((size_t)J.nbt * kNCand * 8) + al256(64) + al256(12 * 8) + 256;
 }
 
 struct Take {
@@ -310,6 +329,7 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.bscore = dw.take<unsigned long long>((size_t)J.nbt * kNCand);
   J.dummy = dw.take<unsigned long long>(16);
   for (int v = 0; v < 3; v++) J.hist[v] = dw.take<uint32_t>(J.nsym);
+  for (int v = 0; v < 3; v++) J.nz[v] = dw.take<uint32_t>(2 * kNzCap);
   J.flag = dw.take<int>(16);
   J.lflag = dw.take<int>(16);
   J.wq = dw.take<double>(3 * 16 * 4);
@@ -317,6 +337,8 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.mm = dw.take<double>(8);
   J.sums = dw.take<unsigned long long>(12);
   for (int v = 0; v < 3; v++) J.h_hist[v] = pw.take<uint32_t>(J.nsym);
+  for (int v = 0; v < 3; v++) J.h_nz[v] = pw.take<uint32_t>(2 * kNzCap);
+  J.h_nzn = pw.take<uint32_t>(4);
   J.h_score[0] = pw.take<unsigned long long>(kNCand * 16);
   J.h_score[1] = pw.take<unsigned long long>(kNCand * 16);
   J.h_bscore = pw.take<unsigned long long>((size_t)J.nbt * kNCand);
@@ -331,7 +353,7 @@ template <typename T>
 int t_minmax(TJob<T>& J, hipStream_t st)
 {
   if (J.done) return HPEZ_OK;
-  TCK(hipMemsetAsync(J.flag, 0, sizeof(int), st));
+  TCK(hipMemsetAsync(J.flag, 0, 16 * sizeof(int), st));
   TCK(launch_minmax<T>(J.X, J.N, J.part, J.flag, 1024, st));
   TCK(launch_minmax_final(J.part, 1024, J.mm, st));
   TCK(hipMemcpyAsync(J.h_mm, J.mm, 16, hipMemcpyDeviceToHost, st));
@@ -539,6 +561,33 @@ int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
   return HPEZ_OK;
 }
 
+// histogram v to the host as its nonzero (bin, count) pairs
+template <typename T>
+hipError_t t_nonzero_copy(TJob<T>& J, int v, hipStream_t st)
+{
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(J.flag) + 4 + v;
+  hipError_t e = launch_hist_nonzero(J.hist[v], J.nsym, cnt, J.nz[v], kNzCap, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(J.h_nz[v], J.nz[v], (size_t)kNzCap * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(J.h_nzn + v, cnt, 4, hipMemcpyDeviceToHost, st);
+  return e;
+}
+
+// entropy of histogram v from its pairs (after the phase's synchronization);
+// the whole histogram is read when the pairs overflowed
+template <typename T>
+int t_entropy(TJob<T>& J, int v, hipStream_t st, double* H)
+{
+  if (J.h_nzn[v] <= kNzCap) {
+    *H = entropy_bits_pairs(J.h_nz[v], J.h_nzn[v]);
+    return HPEZ_OK;
+  }
+  TCK(hipMemcpyAsync(J.h_hist[v], J.hist[v], sizeof(uint32_t) * J.nsym, hipMemcpyDeviceToHost, st));
+  TCK(hipStreamSynchronize(st));
+  *H = entropy_bits(J.h_hist[v], J.nsym);
+  return HPEZ_OK;
+}
+
 template <typename T>
 int t_global_copy(TJob<T>& J, hipStream_t st)
 {
@@ -547,7 +596,7 @@ int t_global_copy(TJob<T>& J, hipStream_t st)
     TCK(hipMemcpyAsync(J.h_score[v], J.score[v], sizeof(unsigned long long) * kNCand * 16,
                        hipMemcpyDeviceToHost, st));
   if (J.lorenzo_trial) {
-    TCK(hipMemcpyAsync(J.h_hist[2], J.hist[2], sizeof(uint32_t) * J.nsym, hipMemcpyDeviceToHost, st));
+    TCK(t_nonzero_copy(J, 2, st));
     TCK(hipMemcpyAsync(J.h_lflag, J.lflag, sizeof(int), hipMemcpyDeviceToHost, st));
   }
   return HPEZ_OK;
@@ -586,8 +635,7 @@ template <typename T>
 int t_hist_copy(TJob<T>& J, hipStream_t st)
 {
   if (J.done) return HPEZ_OK;
-  for (int v = 0; v < J.nvar; v++)
-    TCK(hipMemcpyAsync(J.h_hist[v], J.hist[v], sizeof(uint32_t) * J.nsym, hipMemcpyDeviceToHost, st));
+  for (int v = 0; v < J.nvar; v++) TCK(t_nonzero_copy(J, v, st));
   return HPEZ_OK;
 }
 
@@ -599,16 +647,19 @@ int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
   const hpez_field_desc* d = J.d;
   const hpez_tune_opts* o = J.o;
   const int64_t A = (int64_t)1 << J.Q.anchor_log2;
+  int rc;
   for (int v = 0; v < J.nvar; v++) {
     const int fz = v == 0 ? -1 : J.fcand;
-    J.H[v] = entropy_bits(J.h_hist[v], J.nsym) +
-             (double)anchor_count(d, fz, A) * (double)sizeof(T) * 8.0 / (double)points_of(d);
+    double Hv;
+    if ((rc = t_entropy(J, v, st, &Hv))) return rc;
+    J.H[v] = Hv + (double)anchor_count(d, fz, A) * (double)sizeof(T) * 8.0 / (double)points_of(d);
   }
   J.frozen = (J.nvar == 2 && J.H[1] < J.H[0]) ? J.fcand : -1;
   const double Hbest = J.frozen >= 0 ? J.H[1] : J.H[0];
   J.lorenzo = false;
   if (J.lorenzo_trial) {
-    const double HL = entropy_bits(J.h_hist[2], J.nsym);
+    double HL;
+    if ((rc = t_entropy(J, 2, st, &HL))) return rc;
     if (*J.h_lflag == 0 && o->lorenzo_coef * HL < Hbest) J.lorenzo = true;
   }
   J.blocks = !J.lorenzo && o->block_wise;

@@ -87,6 +87,13 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
                                 uint32_t max_pts, const T* X, double inv2e, uint32_t R,
                                 uint32_t hist_lo, uint32_t* d_hist, int* d_unsupported,
                                 hipStream_t st);
+// The nonzero bins of a histogram as (bin, count) pairs, in no particular
+// order, for the host's entropy estimate: *d_count (zeroed by the caller)
+// receives their number; pairs beyond cap are dropped (the caller then reads
+// the whole histogram).
+constexpr uint32_t kNzCap = 2048;
+hipError_t launch_hist_nonzero(const uint32_t* d_hist, uint32_t nsym, uint32_t* d_count,
+                               uint32_t* d_pairs, uint32_t cap, hipStream_t st);
 // first code of a kTrialHistWin-wide window centred on R inside [0, 2R)
 inline uint32_t trial_hist_lo(uint32_t R)
 {
