@@ -530,6 +530,33 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
   return HPEZ_OK;
 }
 
+// The encoder alone, its packed codebook already on the device and its flags
+// and ticket already zero (codewords of at most 26 bits).
+int encode_payload_packed(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
+                          uint32_t sym_min, uint32_t sym_max, const uint32_t* d_tab,
+                          uint64_t* d_flags, uint32_t* d_ticket, uint32_t* payload,
+                          uint16_t* chunks, hipStream_t st)
+{
+  const uint64_t nch = (N + chunk - 1) / chunk;
+  if (!nch) return HPEZ_OK;
+  if (sym_max < sym_min) return HPEZ_EINVAL;
+  EncodeArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.n = N;
+  a.nch = nch;
+  a.chunk = chunk;
+  a.smin = sym_min;
+  a.ntab = sym_max - sym_min + 1;
+  a.lds_tab = a.ntab <= kEncTab;
+  a.packed_ok = true;
+  hipEvent_t ev = ctx_span_begin(ctx, st);
+  if (launch_encode1(a, code, payload, chunks, d_flags, d_ticket, d_tab, nullptr, nullptr, st) !=
+      hipSuccess)
+    return HPEZ_EDEVICE;
+  ctx_span_end(ctx, ev, "encode", N * 2, st);
+  return HPEZ_OK;
+}
+
 // Decode tables: 12-bit lookup (sym << 8 | len) plus per-length first code,
 // count and offset into the (length, symbol)-sorted symbol list.
 void decode_tables(const uint8_t* len, uint32_t nsym, uint32_t* lut, uint16_t* sorted,
@@ -950,7 +977,9 @@ struct CJob {
   double* dwq = nullptr;
   uint32_t* ticket = nullptr;
   void* area = nullptr;
+  uint8_t* d_stage = nullptr;  // device copy of h_stage
   // pinned host staging
+  uint8_t* h_stage = nullptr;  // header, block configurations, code lengths, codebook
   uint32_t* h_hist = nullptr;
   uint8_t* h_len = nullptr;
   uint8_t* h_hdr = nullptr;
@@ -974,6 +1003,14 @@ void c_init(CJob<T>& J)
   std::memset(&J.Lo, 0, sizeof J.Lo);
 }
 
+// staging of the stream's small sections: header and block configurations,
+// code lengths and the packed codebook, each part padded to 8 bytes
+template <typename T>
+size_t c_stage_bytes(const CJob<T>& J)
+{
+  return kHdrBytes + J.nb + 8 + J.nsym + 8 + (size_t)J.nsym * 4 + 64;
+}
+
 template <typename T>
 size_t c_dev_bytes(const CJob<T>& J)
 {
@@ -981,7 +1018,7 @@ size_t c_dev_bytes(const CJob<T>& J)
   size_t b = al256(J.N * s) + al256(J.N * 2) + al256(J.nsym * 4) + al256(J.nsym) +
              al256(J.nsym * 4) + al256((J.nch + 1) * 4) + 3 * al256((J.nch + 1) * 8) +
              al256(2 * kMinmaxBlocks * 8) + al256(32) + al256(16) + al256(J.N * s) +
-             al256(J.nb + 16) + al256(3 * 16 * 4 * 8) + al256(64);
+             al256(J.nb + 16) + al256(3 * 16 * 4 * 8) + al256(64) + al256(c_stage_bytes(J));
   if (J.fast) b += al256(block_fast_bytes<T>(J.g));
   return b + 256;
 }
@@ -990,7 +1027,7 @@ template <typename T>
 size_t c_pin_bytes(const CJob<T>& J)
 {
   return al256(J.nsym * 4) + al256(J.nsym) + al256(kHdrBytes) + al256(64) + 2 * al256(J.nsym * 4) +
-         256;
+         al256(c_stage_bytes(J)) + 256;
 }
 
 template <typename T>
@@ -1013,6 +1050,8 @@ void c_take(CJob<T>& J, Bump& bw, Bump& pb)
   J.dwq = bw.take<double>(3 * 16 * 4);
   J.ticket = bw.take<uint32_t>(16);
   if (J.fast) J.area = bw.take<uint8_t>(block_fast_bytes<T>(J.g));
+  J.d_stage = bw.take<uint8_t>(c_stage_bytes(J));
+  J.h_stage = pb.take<uint8_t>(c_stage_bytes(J));
   J.h_hist = pb.take<uint32_t>(J.nsym);
   J.h_len = pb.take<uint8_t>(J.nsym);
   J.h_hdr = pb.take<uint8_t>(kHdrBytes);
@@ -1204,6 +1243,46 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
       if (k < Lo.sym_min || k > Lo.sym_max) J.h_cw[k] = 0;
     HIPCK(hipMemcpyAsync(J.dlen, J.h_len, J.nsym, hipMemcpyHostToDevice, st));
     HIPCK(hipMemcpyAsync(J.dcw, J.h_cw, (size_t)J.nsym * 4, hipMemcpyHostToDevice, st));
+  }
+  if (J.early && J.maxlen <= 26 && ((uintptr_t)out & 7) == 0 && Lo.sym_max >= Lo.sym_min) {
+    // the small sections, the zero fill after the verbatim values and the
+    // encoder's flags in one upload and one launch
+    if (Lo.off_unpred != J.off_unpred) return HPEZ_EINVAL;
+    const uint64_t vend = Lo.off_unpred + Lo.n_unpred * s;
+    const uint64_t nlen = Lo.sym_max - Lo.sym_min + 1;
+    const uint64_t a0 = Lo.off_anchor;               // header + block configurations, padded
+    const uint64_t a1 = Lo.off_chunks - Lo.off_len;  // code lengths, padded
+    const uint64_t ntab = nlen;
+    uint8_t* h = J.h_stage;
+    std::memset(h, 0, a0 + a1);
+    std::memcpy(h, J.h_hdr, kHdrBytes);
+    if (J.nb) std::memcpy(h + kHdrBytes, c->block_cfg, J.nb);
+    std::memcpy(h + a0, J.h_len + Lo.sym_min, nlen);
+    uint32_t* tab = reinterpret_cast<uint32_t*>(h + a0 + a1);
+    for (uint64_t k = 0; k < ntab; k++) {
+      const uint32_t sy = Lo.sym_min + (uint32_t)k;
+      tab[k] = J.h_len[sy] ? (J.h_cw[sy] << 6 | J.h_len[sy]) : 0u;
+    }
+    HIPCK(hipMemcpyAsync(J.d_stage, h, a0 + a1 + ntab * 4, hipMemcpyHostToDevice, st));
+    const uint64_t vz = (vend + 7) & ~7ull;
+    ByteSegs sg;
+    std::memset(&sg, 0, sizeof sg);
+    auto add = [&](uint8_t* dst, const uint8_t* src, uint64_t n) {
+      if (n) sg.s[sg.count++] = ByteSeg{dst, src, n};
+    };
+    add(out, J.d_stage, a0);
+    add(out + Lo.off_anchor, reinterpret_cast<const uint8_t*>(J.anc), Lo.n_anchor * s);
+    add(out + vend, nullptr, (vz < Lo.off_len ? vz : Lo.off_len) - vend);
+    if (vz < Lo.off_len) add(out + vz, nullptr, Lo.off_len - vz);
+    add(out + Lo.off_len, J.d_stage + a0, a1);
+    add(out + Lo.off_chunks, nullptr, Lo.total - Lo.off_chunks);
+    add(reinterpret_cast<uint8_t*>(J.boff), nullptr, J.nch * 8);
+    add(reinterpret_cast<uint8_t*>(J.ticket), nullptr, 4);
+    HIPCK(launch_byte_segs(sg, st));
+    return encode_payload_packed(ctx, J.code, J.N, c->chunk, Lo.sym_min, Lo.sym_max,
+                                 reinterpret_cast<const uint32_t*>(J.d_stage + a0 + a1), J.boff,
+                                 J.ticket, (uint32_t*)(out + Lo.off_payload),
+                                 (uint16_t*)(out + Lo.off_chunks), st);
   }
   if (J.early) {
     if (Lo.off_unpred != J.off_unpred) return HPEZ_EINVAL;

@@ -46,6 +46,20 @@ hipError_t launch_encode1(const EncodeArgs& a, const uint16_t* code, uint32_t* w
                           uint16_t* out_cb, uint64_t* flags, uint32_t* ticket,
                           const uint32_t* packed, const uint8_t* len, const uint32_t* cw,
                           hipStream_t st);
+// Up to kMaxSegs copies or zero fills in one launch: segment i writes n bytes
+// at dst from src, or zeros when src is null.  dst and src 8-byte aligned.
+constexpr int kMaxSegs = 8;
+struct ByteSeg {
+  uint8_t* dst;
+  const uint8_t* src;
+  uint64_t n;
+};
+struct ByteSegs {
+  ByteSeg s[kMaxSegs];
+  int count;
+};
+hipError_t launch_byte_segs(const ByteSegs& a, hipStream_t st);
+
 // per-chunk counts of code 0 and their exclusive scan (zoff[nch] = total)
 hipError_t launch_count_zeros(const uint16_t* code, uint64_t n, uint32_t chunk, uint32_t* czero,
                               uint64_t* zoff, uint64_t* tmp, hipStream_t st);

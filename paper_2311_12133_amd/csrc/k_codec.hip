@@ -16,6 +16,8 @@
 // window with the per-length limits of the canonical code (uniform values, no
 // table walk); codes are packed eight at a time into 16-byte stores.
 
+#include <algorithm>
+
 #include "codec_dev.h"
 #include "interp_dev.h"
 
@@ -376,6 +378,36 @@ __global__ void __launch_bounds__(256) encode1_wide_kernel(EncodeArgs a, const u
       pos += L;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// copies and fills of the stream's small sections in one launch (grid y: the
+// segment); 8-byte words, then the last n % 8 bytes one by one
+
+__global__ void __launch_bounds__(256) byte_segs_kernel(ByteSegs a)
+{
+  const ByteSeg g = a.s[blockIdx.y];
+  const uint64_t nw = g.n / 8;
+  uint64_t* __restrict__ d = reinterpret_cast<uint64_t*>(g.dst);
+  const uint64_t* __restrict__ sp = reinterpret_cast<const uint64_t*>(g.src);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride)
+    d[i] = sp ? sp[i] : 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < (g.n & 7)) {
+    const uint64_t k = nw * 8 + threadIdx.x;
+    g.dst[k] = g.src ? g.src[k] : (uint8_t)0;
+  }
+}
+
+hipError_t launch_byte_segs(const ByteSegs& a, hipStream_t st)
+{
+  if (a.count <= 0) return hipSuccess;
+  uint64_t most = 0;
+  for (int i = 0; i < a.count; i++) most = std::max<uint64_t>(most, a.s[i].n / 8);
+  uint64_t gx = (most + 255) / 256;
+  gx = gx < 1 ? 1 : (gx > 1024 ? 1024 : gx);
+  hipLaunchKernelGGL(byte_segs_kernel, dim3((unsigned)gx, (unsigned)a.count), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_encode1(const EncodeArgs& a, const uint16_t* code, uint32_t* words,

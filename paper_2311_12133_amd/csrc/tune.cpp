@@ -238,6 +238,8 @@ struct TJob {
   int* h_bad = nullptr;
   int* h_lflag = nullptr;
   unsigned long long* h_sums = nullptr;
+  double* h_wqp = nullptr;    // staging of h_wq
+  TrialBox* h_gbp = nullptr;  // staging of gb
 };
 
 // validation and sizes; rc set for a bad request
@@ -302,7 +304,8 @@ size_t t_pin_bytes(const TJob<T>& J)
 {
   if (J.done) return 0;
   return 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + al256(16) + 2 * al256(kNCand * 16 * 8) +
-         al256((size_t)J.nbt * kNCand * 8) + al256(64) + al256(12 * 8) + 256;
+         al256((size_t)J.nbt * kNCand * 8) + al256(64) + al256(12 * 8) + al256(3 * 16 * 4 * 8) +
+         al256(J.gb.size() * sizeof(TrialBox)) + 256;
 }
 
 struct Take {
@@ -346,6 +349,8 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.h_bad = (int*)(J.h_mm + 2);
   J.h_lflag = (int*)(J.h_mm + 3);
   J.h_sums = pw.take<unsigned long long>(12);
+  J.h_wqp = pw.take<double>(3 * 16 * 4);
+  J.h_gbp = pw.take<TrialBox>(J.gb.size());
 }
 
 // phase 1: value range and the non-finite check
@@ -353,7 +358,12 @@ template <typename T>
 int t_minmax(TJob<T>& J, hipStream_t st)
 {
   if (J.done) return HPEZ_OK;
-  TCK(hipMemsetAsync(J.flag, 0, 16 * sizeof(int), st));
+  // every accumulator and flag of the call (trial scores, histograms, pair
+  // counts, flags, statistics sums) lies between score[0] and the end of sums
+  // in the workspace: one clear for all of them
+  uint8_t* z0 = reinterpret_cast<uint8_t*>(J.score[0]);
+  uint8_t* z1 = reinterpret_cast<uint8_t*>(J.sums + 12);
+  TCK(hipMemsetAsync(z0, 0, (size_t)(z1 - z0), st));
   TCK(launch_minmax<T>(J.X, J.N, J.part, J.flag, 1024, st));
   TCK(launch_minmax_final(J.part, 1024, J.mm, st));
   TCK(hipMemcpyAsync(J.h_mm, J.mm, 16, hipMemcpyDeviceToHost, st));
@@ -413,7 +423,6 @@ int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
   }
   J.count = (int64_t)lat.total;
   J.stats = true;
-  TCK(hipMemsetAsync(J.sums, 0, 12 * 8, st));
   hipEvent_t ev = ctx_span_begin(ctx, st);
   TCK(launch_stats<T>(J.X, gs, lat, 256.0 / J.e, J.sums, st));
   ctx_span_end(ctx, ev, "tune_stats", lat.total * (1 + 4 * n_active(gs)) * sizeof(T), st);
@@ -532,8 +541,10 @@ int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
         J.fcand = k;
   }
   md_table(&Q, J.h_wq);
-  TCK(hipMemcpyAsync(J.wq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
-  TCK(hipMemcpyAsync(J.d_gb, J.gb.data(), J.gb.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
+  std::memcpy(J.h_wqp, J.h_wq, sizeof J.h_wq);
+  std::memcpy(J.h_gbp, J.gb.data(), J.gb.size() * sizeof(TrialBox));
+  TCK(hipMemcpyAsync(J.wq, J.h_wqp, sizeof J.h_wq, hipMemcpyHostToDevice, st));
+  TCK(hipMemcpyAsync(J.d_gb, J.h_gbp, J.gb.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
   J.nvar = (o->allow_freeze && J.fcand >= 0) ? 2 : 1;
   const uint32_t nbx = (uint32_t)J.gb.size();
   for (int v = 0; v < J.nvar; v++) {
@@ -548,13 +559,10 @@ int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
     a.score_mul = 4096.0 / J.e;
     fill_levels(a, J.e, &Q);
     for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
-    TCK(hipMemsetAsync(J.score[v], 0, sizeof(unsigned long long) * kNCand * 16, st));
     t_add<T>(tb, a, J.d_gb, nbx, kNCand, J.X, (T*)J.scratch, J.wq, J.score[v], nullptr);
   }
   J.lorenzo_trial = o->allow_lorenzo != 0;
   if (J.lorenzo_trial) {
-    TCK(hipMemsetAsync(J.hist[2], 0, sizeof(uint32_t) * J.nsym, st));
-    TCK(hipMemsetAsync(J.lflag, 0, sizeof(int), st));
     TCK(launch_lorenzo_trial<T>(J.g, J.d_gb, nbx, (uint32_t)J.gcap, J.X, 1.0 / (2.0 * J.e), Q.radius,
                                 trial_hist_lo(Q.radius), J.hist[2], J.lflag, st));
   }
@@ -624,8 +632,6 @@ int t_hist(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
       const int lb = l <= Lb ? l : Lb;
       J.lv[v][l - 1] = l <= L ? J.cand[best[lb]] : J.cand[0];
     }
-    TCK(hipMemsetAsync(J.hist[v], 0, sizeof(uint32_t) * J.nsym, st));
-    if (v == 0) TCK(hipMemsetAsync(J.dummy, 0, sizeof(unsigned long long) * 16, st));
     t_add<T>(tb, a, J.d_gb, (uint32_t)J.gb.size(), 1, J.X, (T*)J.scratch, J.wq, J.dummy, J.hist[v]);
   }
   return HPEZ_OK;
