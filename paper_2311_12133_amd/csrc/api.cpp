@@ -980,6 +980,7 @@ struct CJob {
   uint8_t* d_stage = nullptr;  // device copy of h_stage
   // pinned host staging
   uint8_t* h_stage = nullptr;  // header, block configurations, code lengths, codebook
+  uint8_t* h_up = nullptr;     // block configurations and MD weights (layout of dbcfg)
   uint32_t* h_hist = nullptr;
   uint8_t* h_len = nullptr;
   uint8_t* h_hdr = nullptr;
@@ -1018,7 +1019,7 @@ size_t c_dev_bytes(const CJob<T>& J)
   size_t b = al256(J.N * s) + al256(J.N * 2) + al256(J.nsym * 4) + al256(J.nsym) +
              al256(J.nsym * 4) + al256((J.nch + 1) * 4) + 3 * al256((J.nch + 1) * 8) +
              al256(2 * kMinmaxBlocks * 8) + al256(32) + al256(16) + al256(J.N * s) +
-             al256(J.nb + 16) + al256(3 * 16 * 4 * 8) + al256(64) + al256(c_stage_bytes(J));
+             al256(al256(J.nb + 16) + 3 * 16 * 4 * 8) + al256(64) + al256(c_stage_bytes(J));
   if (J.fast) b += al256(block_fast_bytes<T>(J.g));
   return b + 256;
 }
@@ -1027,7 +1028,7 @@ template <typename T>
 size_t c_pin_bytes(const CJob<T>& J)
 {
   return al256(J.nsym * 4) + al256(J.nsym) + al256(kHdrBytes) + al256(64) + 2 * al256(J.nsym * 4) +
-         al256(c_stage_bytes(J)) + 256;
+         al256(c_stage_bytes(J)) + al256(al256(J.nb + 16) + 3 * 16 * 4 * 8) + 256;
 }
 
 template <typename T>
@@ -1046,12 +1047,14 @@ void c_take(CJob<T>& J, Bump& bw, Bump& pb)
   J.mm = bw.take<double>(4);
   J.bad = bw.take<int>(4);
   J.anc = bw.take<T>(J.N);
-  J.dbcfg = bw.take<uint8_t>(J.nb + 16);
-  J.dwq = bw.take<double>(3 * 16 * 4);
+  // block configurations, then the MD weights: one upload (h_up)
+  J.dbcfg = bw.take<uint8_t>(al256(J.nb + 16) + sizeof J.h_wq);
+  J.dwq = reinterpret_cast<double*>(J.dbcfg + al256(J.nb + 16));
   J.ticket = bw.take<uint32_t>(16);
   if (J.fast) J.area = bw.take<uint8_t>(block_fast_bytes<T>(J.g));
   J.d_stage = bw.take<uint8_t>(c_stage_bytes(J));
   J.h_stage = pb.take<uint8_t>(c_stage_bytes(J));
+  J.h_up = pb.take<uint8_t>(al256(J.nb + 16) + sizeof J.h_wq);
   J.h_hist = pb.take<uint32_t>(J.nsym);
   J.h_len = pb.take<uint8_t>(J.nsym);
   J.h_hdr = pb.take<uint8_t>(kHdrBytes);
@@ -1129,8 +1132,10 @@ int c_predict(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   }
   // interpolation predictor + quantization (Sec. 5, Sec. 4 step 3)
   md_table(c, J.h_wq);
-  HIPCK(hipMemcpyAsync(J.dwq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
-  if (J.nb) HIPCK(hipMemcpyAsync(J.dbcfg, c->block_cfg, J.nb, hipMemcpyHostToDevice, st));
+  if (J.nb) std::memcpy(J.h_up, c->block_cfg, J.nb);
+  std::memcpy(J.h_up + al256(J.nb + 16), J.h_wq, sizeof J.h_wq);
+  HIPCK(hipMemcpyAsync(J.dbcfg, J.h_up, al256(J.nb + 16) + sizeof J.h_wq, hipMemcpyHostToDevice,
+                       st));
   const Lattice al = anchor_lattice(J.g, c->anchor_log2);
   Lo.n_anchor = al.total;
   HIPCK(launch_anchors<T>(J.g, al, J.X, J.W, J.code, J.anc, c->radius, 0, st));
@@ -1406,6 +1411,10 @@ struct DJob {
   uint64_t* zoff = nullptr;
   uint64_t* tmp1 = nullptr;
   uint64_t* tmp2 = nullptr;
+  // one region uploaded at once (dtabs): status, MD weights, first-level
+  // table, second-level tables, sorted symbols
+  uint8_t* dtabs = nullptr;
+  uint64_t tabs_len = 0;
   double* dwq = nullptr;
   uint32_t* dlut = nullptr;
   uint16_t* dsorted = nullptr;
@@ -1421,7 +1430,17 @@ struct DJob {
   uint32_t* h_lut = nullptr;
   uint16_t* h_sorted = nullptr;
   uint32_t* h_sub = nullptr;
+  uint8_t* h_tabs = nullptr;  // host image of dtabs
 };
+
+// offsets in the decode table region
+constexpr uint64_t kTabWq = 16, kTabLut = kTabWq + 3 * 16 * 4 * 8,
+                   kTabSub = kTabLut + ((uint64_t)4 << kLutBits);
+template <typename T>
+uint64_t d_tabs_bytes(const DJob<T>& J)
+{
+  return kTabSub + (uint64_t)kDecSub * 4 + (uint64_t)J.nsym * 2 + 16;
+}
 
 template <typename T>
 void d_init(DJob<T>& J)
@@ -1438,8 +1457,7 @@ template <typename T>
 size_t d_dev_bytes(const DJob<T>& J)
 {
   size_t b = al256(J.N * 2) + 2 * al256((J.nch + 1) * 4) + 4 * al256((J.nch + 1) * 8) +
-             al256(3 * 16 * 4 * 8) + al256((size_t)4 << kLutBits) + al256(J.nsym * 2) + al256(16) +
-             al256((size_t)kDecSub * 4);
+             al256(d_tabs_bytes(J));
   if (J.Lo.predictor == 1) b += al256(J.N * 8);
   if (J.fast) b += al256(block_fast_bytes<T>(J.g));
   return b + 256;
@@ -1448,8 +1466,8 @@ size_t d_dev_bytes(const DJob<T>& J)
 template <typename T>
 size_t d_pin_bytes(const DJob<T>& J)
 {
-  return al256(J.nsym) + al256(J.nb) + al256(16) + al256(16) + al256((size_t)4 << kLutBits) +
-         al256(J.nsym * 2) + al256((size_t)kDecSub * 4) + 256;
+  return al256(J.nsym) + al256(J.nb) + al256(16) + al256(16) + al256(J.nsym * 2) +
+         al256(d_tabs_bytes(J)) + 256;
 }
 
 template <typename T>
@@ -1462,20 +1480,22 @@ void d_take(DJob<T>& J, Bump& bw, Bump& pb)
   J.zoff = bw.take<uint64_t>(J.nch + 1);
   J.tmp1 = bw.take<uint64_t>(J.nch + 1);
   J.tmp2 = bw.take<uint64_t>(J.nch + 1);
-  J.dwq = bw.take<double>(3 * 16 * 4);
-  J.dlut = bw.take<uint32_t>(1u << kLutBits);
-  J.dsorted = bw.take<uint16_t>(J.nsym);
-  J.dsub = bw.take<uint32_t>(kDecSub);
-  J.status = bw.take<int>(4);
+  J.dtabs = bw.take<uint8_t>(d_tabs_bytes(J));
+  J.status = reinterpret_cast<int*>(J.dtabs);
+  J.dwq = reinterpret_cast<double*>(J.dtabs + kTabWq);
+  J.dlut = reinterpret_cast<uint32_t*>(J.dtabs + kTabLut);
+  J.dsub = reinterpret_cast<uint32_t*>(J.dtabs + kTabSub);
+  J.dsorted = nullptr;  // placed after the used second-level entries (d_tables)
   if (J.Lo.predictor == 1) J.lv = bw.take<long long>(J.N);
   if (J.fast) J.area = bw.take<uint8_t>(block_fast_bytes<T>(J.g));
   J.h_len = pb.take<uint8_t>(J.nsym);
   J.h_bcfg = pb.take<uint8_t>(J.nb);
   J.h_status = pb.take<int>(4);
   J.h_tot = pb.take<uint64_t>(2);
-  J.h_lut = pb.take<uint32_t>(1u << kLutBits);
+  J.h_tabs = pb.take<uint8_t>(d_tabs_bytes(J));
+  J.h_lut = reinterpret_cast<uint32_t*>(J.h_tabs + kTabLut);
+  J.h_sub = reinterpret_cast<uint32_t*>(J.h_tabs + kTabSub);
   J.h_sorted = pb.take<uint16_t>(J.nsym);
-  J.h_sub = pb.take<uint32_t>(kDecSub);
 }
 
 // constant field, or the copies of code lengths and block configurations
@@ -1561,6 +1581,13 @@ void d_tables(DJob<T>& J)
   // long codes by second-level tables when they fit (the first level is updated)
   da.n_sub = da.n_long ? decode_subtables(J.h_len, lo, hi, J.h_lut, J.h_sub, kDecSub) : 0;
   md_table(&J.c, J.h_wq);
+  // the region's image: status 0, weights, tables, then the sorted symbols
+  std::memset(J.h_tabs, 0, kTabWq);
+  std::memcpy(J.h_tabs + kTabWq, J.h_wq, sizeof J.h_wq);
+  const uint64_t so = kTabSub + (uint64_t)da.n_sub * 4;
+  std::memcpy(J.h_tabs + so, J.h_sorted, (size_t)J.nused * 2);
+  J.dsorted = reinterpret_cast<uint16_t*>(J.dtabs + so);
+  J.tabs_len = so + (uint64_t)J.nused * 2;
 }
 
 // decode, verbatim values, anchors and the levels down to the block phase
@@ -1572,13 +1599,7 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   const uint8_t* in = J.in;
   const uint64_t N = J.N, nch = J.nch;
   const uint64_t s = sizeof(T);
-  HIPCK(hipMemcpyAsync(J.dlut, J.h_lut, (size_t)4 << kLutBits, hipMemcpyHostToDevice, st));
-  if (J.nused)
-    HIPCK(hipMemcpyAsync(J.dsorted, J.h_sorted, (size_t)J.nused * 2, hipMemcpyHostToDevice, st));
-  if (J.da.n_sub)
-    HIPCK(hipMemcpyAsync(J.dsub, J.h_sub, (size_t)J.da.n_sub * 4, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemcpyAsync(J.dwq, J.h_wq, sizeof J.h_wq, hipMemcpyHostToDevice, st));
-  HIPCK(hipMemsetAsync(J.status, 0, sizeof(int), st));
+  HIPCK(hipMemcpyAsync(J.dtabs, J.h_tabs, J.tabs_len, hipMemcpyHostToDevice, st));
   {
     Span sp(ctx, "decode_offsets", nch * 2, st);
     HIPCK(launch_u16_to_u32((const uint16_t*)(in + Lo.off_chunks), nch, J.cbits, st));
