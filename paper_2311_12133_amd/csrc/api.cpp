@@ -1405,16 +1405,14 @@ struct DJob {
   uint64_t prefix_len = 0;
   // device workspace
   uint16_t* code = nullptr;
-  uint32_t* cbits = nullptr;
   uint32_t* czero = nullptr;
-  uint64_t* boff = nullptr;
   uint64_t* zoff = nullptr;
-  uint64_t* tmp1 = nullptr;
   uint64_t* tmp2 = nullptr;
   // one region uploaded at once (dtabs): status, MD weights, first-level
   // table, second-level tables, sorted symbols
   uint8_t* dtabs = nullptr;
   uint64_t tabs_len = 0;
+  uint64_t* tflags = nullptr;  // the decoder's look-back flags (in dtabs, zeroed)
   double* dwq = nullptr;
   uint32_t* dlut = nullptr;
   uint16_t* dsorted = nullptr;
@@ -1439,7 +1437,7 @@ constexpr uint64_t kTabWq = 16, kTabLut = kTabWq + 3 * 16 * 4 * 8,
 template <typename T>
 uint64_t d_tabs_bytes(const DJob<T>& J)
 {
-  return kTabSub + (uint64_t)kDecSub * 4 + (uint64_t)J.nsym * 2 + 16;
+  return kTabSub + (uint64_t)kDecSub * 4 + (uint64_t)J.nsym * 2 + 16 + ((J.nch + 255) / 256) * 8;
 }
 
 template <typename T>
@@ -1456,7 +1454,7 @@ void d_init(DJob<T>& J)
 template <typename T>
 size_t d_dev_bytes(const DJob<T>& J)
 {
-  size_t b = al256(J.N * 2) + 2 * al256((J.nch + 1) * 4) + 4 * al256((J.nch + 1) * 8) +
+  size_t b = al256(J.N * 2) + al256((J.nch + 1) * 4) + 2 * al256((J.nch + 1) * 8) +
              al256(d_tabs_bytes(J));
   if (J.Lo.predictor == 1) b += al256(J.N * 8);
   if (J.fast) b += al256(block_fast_bytes<T>(J.g));
@@ -1474,11 +1472,8 @@ template <typename T>
 void d_take(DJob<T>& J, Bump& bw, Bump& pb)
 {
   J.code = bw.take<uint16_t>(J.N);
-  J.cbits = bw.take<uint32_t>(J.nch + 1);
   J.czero = bw.take<uint32_t>(J.nch + 1);
-  J.boff = bw.take<uint64_t>(J.nch + 1);
   J.zoff = bw.take<uint64_t>(J.nch + 1);
-  J.tmp1 = bw.take<uint64_t>(J.nch + 1);
   J.tmp2 = bw.take<uint64_t>(J.nch + 1);
   J.dtabs = bw.take<uint8_t>(d_tabs_bytes(J));
   J.status = reinterpret_cast<int*>(J.dtabs);
@@ -1587,7 +1582,11 @@ void d_tables(DJob<T>& J)
   const uint64_t so = kTabSub + (uint64_t)da.n_sub * 4;
   std::memcpy(J.h_tabs + so, J.h_sorted, (size_t)J.nused * 2);
   J.dsorted = reinterpret_cast<uint16_t*>(J.dtabs + so);
-  J.tabs_len = so + (uint64_t)J.nused * 2;
+  const uint64_t fo = (so + (uint64_t)J.nused * 2 + 7) & ~7ull;
+  const uint64_t nfl = (J.nch + 255) / 256;
+  std::memset(J.h_tabs + fo, 0, nfl * 8);
+  J.tflags = reinterpret_cast<uint64_t*>(J.dtabs + fo);
+  J.tabs_len = fo + nfl * 8;
 }
 
 // decode, verbatim values, anchors and the levels down to the block phase
@@ -1601,13 +1600,9 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   const uint64_t s = sizeof(T);
   HIPCK(hipMemcpyAsync(J.dtabs, J.h_tabs, J.tabs_len, hipMemcpyHostToDevice, st));
   {
-    Span sp(ctx, "decode_offsets", nch * 2, st);
-    HIPCK(launch_u16_to_u32((const uint16_t*)(in + Lo.off_chunks), nch, J.cbits, st));
-    HIPCK(launch_scan_u32_to_u64(J.cbits, nch, J.boff, J.boff + nch, J.tmp1, st));
-  }
-  {
     Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
-    HIPCK(launch_decode2(J.da, (const uint32_t*)(in + Lo.off_payload), J.boff, J.dlut, J.dsorted,
+    HIPCK(launch_decode2(J.da, (const uint32_t*)(in + Lo.off_payload),
+                         (const uint16_t*)(in + Lo.off_chunks), J.tflags, J.dlut, J.dsorted,
                          J.dsub, J.code, J.czero, J.status, st));
   }
   HIPCK(launch_scan_u32_to_u64(J.czero, nch, J.zoff, J.zoff + nch, J.tmp2, st));

@@ -85,9 +85,12 @@ hipError_t launch_scatter_unpred2(const uint16_t* code, uint64_t n, uint32_t chu
 uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
                           uint32_t* sub, uint32_t cap);
 
-hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
-                          const uint32_t* lut, const uint16_t* sorted, const uint32_t* sub,
-                          uint16_t* code,
-                          uint32_t* czero, int* status, hipStream_t st);
+// cbits: the stream's per-chunk bit counts; tflags: one word per 256 chunks,
+// zeroed; status[0] is set on a decoding error, status[1] (zeroed) is the
+// work-groups' ticket counter
+hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint16_t* cbits,
+                          uint64_t* tflags, const uint32_t* lut, const uint16_t* sorted,
+                          const uint32_t* sub, uint16_t* code, uint32_t* czero, int* status,
+                          hipStream_t st);
 
 }  // namespace hpez

@@ -586,7 +586,8 @@ constexpr uint32_t kDecRing = 16;  // LDS ring slots per decoding lane (a power 
 
 template <int MODE>
 __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32_t* __restrict__ words,
-                                                      const uint64_t* __restrict__ bit_off,
+                                                      const uint16_t* __restrict__ cbits,
+                                                      uint64_t* __restrict__ tflags,
                                                       const uint32_t* __restrict__ glut,
                                                       const uint16_t* __restrict__ sorted,
                                                       const uint32_t* __restrict__ gsub,
@@ -607,14 +608,46 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     for (uint32_t i = threadIdx.x; i < a.n_long; i += blockDim.x) slong[i] = sorted[a.long_first + i];
   if (MODE == 2)
     for (uint32_t i = threadIdx.x; i < a.n_sub; i += blockDim.x) subl[i] = gsub[i];
+  // Chunk bit offsets: work-groups take tiles of 256 chunks in ticket order
+  // (status[1] is the ticket), scan the tile's bit counts and find the tile's
+  // offset by decoupled look-back over the tiles before it (tflags, zeroed).
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_wsum[4];
+  __shared__ uint64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(reinterpret_cast<uint32_t*>(status) + 1, 1u);
   __syncthreads();
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k == 0 && bit_off[a.nch] != a.nbits) atomicOr(status, 1);
+  const uint64_t tile = s_tile;
+  const uint64_t k = tile * 256 + threadIdx.x;
+  const uint32_t cnt = k < a.nch ? (uint32_t)cbits[k] : 0u;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t incl = cnt;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wv; w++) before += s_wsum[w];
+  if (wv == 0) {
+    const uint64_t agg = (uint64_t)s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    uint64_t excl = 0;
+    if (tile == 0) {
+      if (lane == 0) flag_store(&tflags[0], kFlagIncl | agg);
+    } else {
+      if (lane == 0) flag_store(&tflags[tile], kFlagAgg | agg);
+      excl = look_back(tflags, tile, lane);
+      if (lane == 0) flag_store(&tflags[tile], kFlagIncl | (excl + agg));
+    }
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
   if (k >= a.nch) return;
   const uint64_t beg = k * a.chunk;
   const uint64_t end = beg + a.chunk < a.n ? beg + a.chunk : a.n;
-  uint64_t pos = bit_off[k];
-  const uint64_t stop = bit_off[k + 1];
+  uint64_t pos = s_excl + before + (incl - cnt);
+  const uint64_t stop = pos + cnt;
+  if (k == a.nch - 1 && stop != a.nbits) atomicOr(status, 1);
   if (stop > a.nbits || pos > stop) {
     atomicOr(status, 1);
     return;
@@ -732,21 +765,22 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   czero[k] = zeros;
 }
 
-hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint64_t* bit_off,
-                          const uint32_t* lut, const uint16_t* sorted, const uint32_t* sub,
-                          uint16_t* code, uint32_t* czero, int* status, hipStream_t st)
+hipError_t launch_decode2(const DecodeArgs& a, const uint32_t* words, const uint16_t* cbits,
+                          uint64_t* tflags, const uint32_t* lut, const uint16_t* sorted,
+                          const uint32_t* sub, uint16_t* code, uint32_t* czero, int* status,
+                          hipStream_t st)
 {
   if (!a.nch) return hipSuccess;
   const dim3 grid((unsigned)((a.nch + 255) / 256)), block(256);
   // built second-level tables rewrite first-level entries: mode 2 reads them
   if (a.n_sub && a.n_sub <= kDecSub)
-    hipLaunchKernelGGL(decode2_kernel<2>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
+    hipLaunchKernelGGL(decode2_kernel<2>, grid, block, 0, st, a, words, cbits, tflags, lut, sorted, sub,
                        code, czero, status);
   else if (a.n_long <= kDecLong)
-    hipLaunchKernelGGL(decode2_kernel<0>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
+    hipLaunchKernelGGL(decode2_kernel<0>, grid, block, 0, st, a, words, cbits, tflags, lut, sorted, sub,
                        code, czero, status);
   else
-    hipLaunchKernelGGL(decode2_kernel<1>, grid, block, 0, st, a, words, bit_off, lut, sorted, sub,
+    hipLaunchKernelGGL(decode2_kernel<1>, grid, block, 0, st, a, words, cbits, tflags, lut, sorted, sub,
                        code, czero, status);
   return hipGetLastError();
 }
