@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import struct
 import threading
 
 import numpy as np
@@ -186,21 +187,28 @@ def desc_from(dims, dtype: str, eb: float, eb_mode: str) -> FieldDesc:
     return d
 
 
-def _fill_interp(dst: Interp, src):
+_NO_INTERP = bytes((0, 0, 0, 0, 1, 2, 3, 0))
+
+
+def _interp_bytes(src) -> bytes:
+    """The 8 bytes of an hpez_interp (kind, md, same_level, order[4], pad)."""
     if src is None:
-        dst.kind = dst.md = dst.same_level = 0
-        for j in range(4):
-            dst.order[j] = j
-        dst.pad = 0
-        return
-    dst.kind = int(src["kind"])
-    dst.md = int(src.get("md", 0))
-    dst.same_level = int(src.get("same_level", 0))
-    order = list(src.get("order", (0, 1, 2, 3)))
-    order = order + [j for j in range(4) if j not in order]
-    for j in range(4):
-        dst.order[j] = order[j]
-    dst.pad = 0
+        return _NO_INTERP
+    order = src.get("order", (0, 1, 2, 3))
+    if len(order) != 4:
+        order = list(order)
+        order = order + [j for j in range(4) if j not in order]
+    return bytes((int(src["kind"]), int(src.get("md", 0)), int(src.get("same_level", 0)),
+                  *(int(v) for v in order), 0))
+
+
+def _fill_interp(dst: Interp, src):
+    C.memmove(C.addressof(dst), _interp_bytes(src), 8)
+
+
+_LEVEL_OFF = Config.level.offset
+_CAND_OFF = Config.cand.offset
+_MDW_OFF = Config.md_w.offset
 
 
 def config_from(cfg: dict, keep: list) -> Config:
@@ -213,17 +221,22 @@ def config_from(cfg: dict, keep: list) -> Config:
     c.chunk = int(cfg.get("chunk", 1024))
     c.alpha = float(cfg.get("alpha", 1.0))
     c.beta = float(cfg.get("beta", 1.0))
-    mw = cfg.get("md_w", [[1.0] * 4] * 3)
-    for k in range(3):
-        for d in range(4):
-            c.md_w[k][d] = float(mw[k][d])
+    mw = cfg.get("md_w")
+    if mw is not None:
+        C.memmove(C.addressof(c) + _MDW_OFF,
+                  struct.pack("12d", *(float(mw[k][d]) for k in range(3) for d in range(4))), 96)
+    else:
+        C.memmove(C.addressof(c) + _MDW_OFF, struct.pack("12d", *([1.0] * 12)), 96)
+    # the level and candidate tables are written as bytes (one copy each)
     levels = cfg["levels"]
-    for i in range(16):
-        _fill_interp(c.level[i], levels[i] if i < len(levels) else levels[-1])
+    lv = [_interp_bytes(x) for x in levels[:16]]
+    lv += [lv[-1]] * (16 - len(lv))
+    C.memmove(C.addressof(c) + _LEVEL_OFF, b"".join(lv), 128)
     cand = cfg.get("cand", [])
     c.n_cand = len(cand)
-    for i in range(16):
-        _fill_interp(c.cand[i], cand[i] if i < len(cand) else None)
+    cb = [_interp_bytes(x) for x in cand[:16]]
+    cb += [_NO_INTERP] * (16 - len(cb))
+    C.memmove(C.addressof(c) + _CAND_OFF, b"".join(cb), 128)
     bc = cfg.get("block_cfg")
     if bc is not None:
         arr = np.ascontiguousarray(np.asarray(bc, dtype=np.uint8))
@@ -233,8 +246,14 @@ def config_from(cfg: dict, keep: list) -> Config:
 
 
 def interp_dict(s: Interp) -> dict:
-    return dict(kind=int(s.kind), md=int(s.md), same_level=int(s.same_level),
-                order=tuple(int(v) for v in s.order))
+    b = bytes(s)
+    return dict(kind=b[0], md=b[1], same_level=b[2], order=tuple(b[3:7]))
+
+
+def _interp_dicts(c: Config, off: int, n: int) -> list:
+    b = C.string_at(C.addressof(c) + off, 8 * n)
+    return [dict(kind=b[8 * i], md=b[8 * i + 1], same_level=b[8 * i + 2],
+                 order=tuple(b[8 * i + 3:8 * i + 7])) for i in range(n)]
 
 
 def _torch():
@@ -347,9 +366,10 @@ def _tuned_dict(cfg: dict, c: Config, bc, nb: int) -> dict:
     res["anchor_log2"] = int(c.anchor_log2)
     res["frozen_dim"] = int(c.frozen_dim)
     res["block_log2"] = int(c.block_log2)
-    res["md_w"] = [[float(c.md_w[k][dd]) for dd in range(4)] for k in range(3)]
-    res["levels"] = [interp_dict(c.level[i]) for i in range(16)]
-    res["cand"] = [interp_dict(c.cand[i]) for i in range(c.n_cand)]
+    w = struct.unpack("12d", C.string_at(C.addressof(c) + _MDW_OFF, 96))
+    res["md_w"] = [list(w[4 * k:4 * k + 4]) for k in range(3)]
+    res["levels"] = _interp_dicts(c, _LEVEL_OFF, 16)
+    res["cand"] = _interp_dicts(c, _CAND_OFF, c.n_cand)
     res["block_cfg"] = bc[:nb].copy() if c.block_log2 else None
     return res
 

@@ -958,6 +958,7 @@ struct CJob {
   double h_wq[3 * 16 * 4];
   uint32_t maxlen = 0;  // longest code length
   bool early = false;   // verbatim values gathered before the codebook
+  bool xface = false;   // face arrays prefilled with the field's values
   uint64_t off_unpred = 0;
   // device workspace
   T* W = nullptr;
@@ -1071,7 +1072,16 @@ int c_minmax(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   HIPCK(hipMemsetAsync(J.bad, 0, sizeof(int), st));
   {
     Span sp(ctx, "minmax", J.N * sizeof(T), st);
-    HIPCK(launch_minmax<T>(J.X, J.N, J.part, J.bad, kMinmaxBlocks, st));
+    if (J.fast && J.g.n[2] >= 64) {
+      // (rows along dim 2 long enough for a wave each) the block path's face
+      // steps then read the face points' values from the compact face arrays
+      // instead of strided rows of the field
+      HIPCK(launch_minmax_faces<T>(J.X, J.g, block_face_arrays<T>(J.g, J.area), J.part, J.bad,
+                                   kMinmaxBlocks, st));
+      J.xface = true;
+    } else {
+      HIPCK(launch_minmax<T>(J.X, J.N, J.part, J.bad, kMinmaxBlocks, st));
+    }
     HIPCK(launch_minmax_final(J.part, kMinmaxBlocks, J.mm, st));
   }
   HIPCK(hipMemcpyAsync(J.h_mm, J.mm, 16, hipMemcpyDeviceToHost, st));
@@ -1164,6 +1174,7 @@ BlockJobHost<T> c_block_job(const CJob<T>& J)
   B.g = J.g;
   B.e = J.Lo.e;
   B.X = J.X;
+  B.xface = J.xface;
   B.Wg = J.W;
   B.code = J.code;
   B.d_bcfg = J.dbcfg;
@@ -1413,6 +1424,7 @@ struct DJob {
   uint8_t* dtabs = nullptr;
   uint64_t tabs_len = 0;
   uint64_t* tflags = nullptr;  // the decoder's look-back flags (in dtabs, zeroed)
+  bool fcode2 = false;  // the decoder wrote family 2's codes to the face code array
   double* dwq = nullptr;
   uint32_t* dlut = nullptr;
   uint16_t* dsorted = nullptr;
@@ -1599,6 +1611,20 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   const uint64_t N = J.N, nch = J.nch;
   const uint64_t s = sizeof(T);
   HIPCK(hipMemcpyAsync(J.dtabs, J.h_tabs, J.tabs_len, hipMemcpyHostToDevice, st));
+  // every brick full and one chunk per brick slab: the decoder also writes the
+  // codes of the face planes x2 = 0 (mod 32) to family 2's compact code array
+  J.da.f2code = nullptr;
+  const int64_t Bk = (int64_t)1 << kBrickLog2;
+  if (J.fast && J.c.chunk == 1024 && Bk == 32 && J.g.n[3] == 1 && J.g.act[2] &&
+      J.g.n[0] % Bk == 0 && J.g.n[1] % Bk == 0 && J.g.n[2] % Bk == 0) {
+    const FaceGeo f = block_face_arrays<T>(J.g, J.area);
+    J.da.f2code = f.code[2];
+    J.da.f2_plane = (uint64_t)f.plane[2];
+    J.da.f2_n1 = (uint32_t)J.g.n[1];
+    J.da.nbk1 = (uint32_t)(J.g.n[1] / Bk);
+    J.da.nbk2 = (uint32_t)(J.g.n[2] / Bk);
+    J.fcode2 = true;
+  }
   {
     Span sp(ctx, "decode", N * 2 + (Lo.payload_bits + 7) / 8, st);
     HIPCK(launch_decode2(J.da, (const uint32_t*)(in + Lo.off_payload),
@@ -1647,6 +1673,7 @@ BlockJobHost<T> d_block_job(const DJob<T>& J)
   B.hist = nullptr;
   B.hist_lo = 0;
   B.area = J.area;
+  B.fcode2 = J.fcode2;
   B.out = J.out;
   return B;
 }

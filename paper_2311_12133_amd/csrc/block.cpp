@@ -101,6 +101,23 @@ size_t block_tables_bound(int n)
 }
 
 template <typename T>
+FaceGeo block_face_arrays(const Geom& g, void* area)
+{
+  int64_t elems[4];
+  FaceGeo f;
+  face_geometry(g, kBrick, kBrickLog2, elems, &f);
+  uint8_t* p = (uint8_t*)area;
+  for (int k = 0; k < 4; k++) {
+    if (!elems[k]) continue;
+    f.val[k] = p;
+    p += (elems[k] * sizeof(T) + 255) & ~(size_t)255;
+    f.code[k] = (uint16_t*)p;
+    p += (elems[k] * 2 + 255) & ~(size_t)255;
+  }
+  return f;
+}
+
+template <typename T>
 int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
 {
   (void)ctx;
@@ -109,12 +126,11 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
   const int64_t B = kBrick;
   int64_t elems[4];
   face_geometry(g, B, kBrickLog2, elems, &J.f);
+  J.f = block_face_arrays<T>(g, J.area);
   uint8_t* p = (uint8_t*)J.area;
   for (int k = 0; k < 4; k++) {
     if (!elems[k]) continue;
-    J.f.val[k] = p;
     p += (elems[k] * sizeof(T) + 255) & ~(size_t)255;
-    J.f.code[k] = (uint16_t*)p;
     p += (elems[k] * 2 + 255) & ~(size_t)255;
   }
   {
@@ -383,6 +399,8 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
         E.X = jobs[j].X;
         E.code = jobs[j].code;
         E.out = jobs[j].out;
+        E.xface = jobs[j].xface ? 1 : 0;
+        E.fcode2 = jobs[j].fcode2 ? 1 : 0;
         E.wg_begin = L.wgs;
         E.wg_count = face_wgs(tot);
         hw[wi++] = L.wgs;
@@ -477,6 +495,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   template size_t block_fast_bytes<T>(const Geom&);                                              \
   template size_t block_tables_bound<T>(int);                                                    \
   template int block_job_prepare<T>(hpez_ctx*, BlockJobHost<T>&);                                \
+  template FaceGeo block_face_arrays<T>(const Geom&, void*);                                    \
   template size_t block_jobs_table_bytes<T>(const BlockJobHost<T>*, int);                        \
   template int run_block_jobs<T>(hpez_ctx*, BlockJobHost<T>*, int, int, void*, uint8_t*,         \
                                  hipStream_t);

@@ -38,6 +38,12 @@ struct DecodeArgs {
   uint32_t long_first;       // index in sorted[] of the first code longer than kLutBits
   uint32_t n_long;           // number of such codes (held in LDS when <= kDecLong)
   uint32_t n_sub;            // second-level table entries (0: none; long codes by limits)
+  // optional: codes of the points on the face planes x2 = 0 (mod 32) also go to
+  // a compact array (every brick full, chunks of 1024 = one 32 x 32 slab of a
+  // brick): index b2 * f2_plane + x0 * f2_n1 + x1; null when not used
+  uint16_t* f2code;
+  uint64_t f2_plane;
+  uint32_t f2_n1, nbk1, nbk2;
   uint64_t lim[kLmax + 1];   // lim[l] = (first code of length l + count) << (32 - l)
   uint32_t base[kLmax + 1];  // offset of length l in sorted[] minus its first code (mod 2^32)
 };

@@ -108,6 +108,8 @@ struct BlockJobHost {
   Geom g;
   double e = 0;
   const T* X = nullptr;    // compress: the field
+  bool xface = false;      // compress: face arrays prefilled with the field's values
+  bool fcode2 = false;     // decompress: family 2's codes in f.code[2] (from the decoder)
   const T* Wg = nullptr;   // the grid holding anchors and levels >= B
   uint16_t* code = nullptr;
   const uint8_t* d_bcfg = nullptr;
@@ -131,6 +133,9 @@ struct BlockJobHost {
 };
 template <typename T>
 int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J);
+// the face arrays' layout in a block phase area (block_fast_bytes)
+template <typename T>
+FaceGeo block_face_arrays(const Geom& g, void* area);
 // device and pinned host bytes of the work tables of run_block_jobs
 template <typename T>
 size_t block_tables_bound(int n);  // any n jobs

@@ -85,6 +85,137 @@ __global__ void __launch_bounds__(256) face_init_kernel(FaceGeo f, Geom g, Latti
   }
 }
 
+template <typename T>
+__device__ __forceinline__ bool face_nonfinite(T v)
+{
+  return !(v - v == (T)0);
+}
+
+// Value range plus face prefill: one wave per row along dim 2 (rows of the
+// planes x0 = const and x1 = const are contiguous in those families' arrays;
+// the points with x2 on the face lattice go to family 2's array).  The range
+// is reduced exactly as minmax_kernel does.
+template <typename T>
+__global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__ X, Geom g, FaceGeo f,
+                                                           double* __restrict__ part,
+                                                           int* __restrict__ bad)
+{
+  __shared__ double smn[256], smx[256];
+  T mn = X[0], mx = X[0];
+  bool nf = false;
+  const int lane = threadIdx.x & 63;
+  const uint64_t n1 = (uint64_t)g.n[1];
+  const int64_t n2 = g.n[2];
+  const uint64_t nrows = (uint64_t)g.n[0] * n1;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t Bm = f.B - 1;
+  const bool vec = (n2 & 3) == 0 && ((uintptr_t)X & 15) == 0;
+  if (vec && n2 <= 128 * (int64_t)(16 / sizeof(T))) {
+    // rows of at most two vectors per lane: each wave takes 4 consecutive rows and
+    // loads all of its vectors of them before using any (8 loads in flight)
+    constexpr int V = 16 / sizeof(T);
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    for (uint64_t r0 = wave * 4; r0 < nrows; r0 += nwaves * 4) {
+      T t[4][2][V];
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int64_t i = ((int64_t)lane + 64 * h) * V;
+          if (r0 + u < nrows && i < n2)
+            *reinterpret_cast<u4*>(t[u][h]) =
+                *reinterpret_cast<const HPEZ_GLOBAL u4*>(gmem(X) + (r0 + u) * (uint64_t)n2 + i);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint64_t r = r0 + u;
+        if (r >= nrows) break;
+        int64_t x[4] = {(int64_t)(r / n1), (int64_t)(r % n1), 0, 0};
+        HPEZ_GLOBAL T* d0 = (g.act[0] && (x[0] & Bm) == 0)
+                                ? gmem(reinterpret_cast<T*>(f.val[0])) + face_index(f, 0, x) : nullptr;
+        HPEZ_GLOBAL T* d1 = (g.act[1] && (x[1] & Bm) == 0)
+                                ? gmem(reinterpret_cast<T*>(f.val[1])) + face_index(f, 1, x) : nullptr;
+        HPEZ_GLOBAL T* d2 =
+            g.act[2] ? gmem(reinterpret_cast<T*>(f.val[2])) + face_index(f, 2, x) : nullptr;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int64_t i = ((int64_t)lane + 64 * h) * V;
+          if (i >= n2) continue;
+#pragma unroll
+          for (int j = 0; j < V; j++) {
+            nf |= face_nonfinite(t[u][h][j]);
+            mn = t[u][h][j] < mn ? t[u][h][j] : mn;
+            mx = t[u][h][j] > mx ? t[u][h][j] : mx;
+          }
+          if (d0) *reinterpret_cast<HPEZ_GLOBAL u4*>(d0 + i) = *reinterpret_cast<const u4*>(t[u][h]);
+          if (d1) *reinterpret_cast<HPEZ_GLOBAL u4*>(d1 + i) = *reinterpret_cast<const u4*>(t[u][h]);
+          if (d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = t[u][h][0];
+        }
+      }
+    }
+  } else
+  for (uint64_t r = wave; r < nrows; r += nwaves) {
+    int64_t x[4] = {(int64_t)(r / n1), (int64_t)(r % n1), 0, 0};
+    HPEZ_GLOBAL T* d0 = (g.act[0] && (x[0] & Bm) == 0)
+                            ? gmem(reinterpret_cast<T*>(f.val[0])) + face_index(f, 0, x) : nullptr;
+    HPEZ_GLOBAL T* d1 = (g.act[1] && (x[1] & Bm) == 0)
+                            ? gmem(reinterpret_cast<T*>(f.val[1])) + face_index(f, 1, x) : nullptr;
+    HPEZ_GLOBAL T* d2 = g.act[2] ? gmem(reinterpret_cast<T*>(f.val[2])) + face_index(f, 2, x) : nullptr;
+    const HPEZ_GLOBAL T* row = gmem(X) + r * (uint64_t)n2;
+    if (vec) {
+      constexpr int V = 16 / sizeof(T);
+      for (int64_t i = (int64_t)lane * V; i < n2; i += 64 * V) {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        T t[V];
+        *reinterpret_cast<u4*>(t) = *reinterpret_cast<const HPEZ_GLOBAL u4*>(row + i);
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          nf |= face_nonfinite(t[j]);
+          mn = t[j] < mn ? t[j] : mn;
+          mx = t[j] > mx ? t[j] : mx;
+        }
+        if (d0) *reinterpret_cast<HPEZ_GLOBAL u4*>(d0 + i) = *reinterpret_cast<const u4*>(t);
+        if (d1) *reinterpret_cast<HPEZ_GLOBAL u4*>(d1 + i) = *reinterpret_cast<const u4*>(t);
+        if (d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = t[0];
+      }
+    } else {
+      for (int64_t i = lane; i < n2; i += 64) {
+        const T v = row[i];
+        nf |= face_nonfinite(v);
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+        if (d0) d0[i] = v;
+        if (d1) d1[i] = v;
+        if (d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = v;
+      }
+    }
+  }
+  if (nf) atomicOr(bad, 1);
+  smn[threadIdx.x] = (double)mn;
+  smx[threadIdx.x] = (double)mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + w]);
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smn[0];
+    part[2 * blockIdx.x + 1] = smx[0];
+  }
+}
+
+template <typename T>
+hipError_t launch_minmax_faces(const T* X, const Geom& g, const FaceGeo& f, double* part, int* bad,
+                               int nblocks, hipStream_t st)
+{
+  hipLaunchKernelGGL((minmax_faces_kernel<T>), dim3(nblocks), dim3(256), 0, st, X, g, f, part, bad);
+  return hipGetLastError();
+}
+
 // one step of the face phase for every family it touches, for every entry of
 // the table (one entry per field); an entry owns a range of work-groups.  I is
 // the index type (32-bit when every entry has fewer than 2^32 points).
@@ -157,13 +288,14 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
     }
     const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
     if (MODE == 0) {
-      const T xv = X[idx];
+      const T xv = E.xface ? F[fi] : X[idx];
       T xr = xv;
       const uint32_t q = quantize<T>(xv, p, a.inv2e, a.twoe, a.el, a.R, xr);
       gmem(f.code[d])[fi] = (uint16_t)q;  // d is the point's lowest family
       face_store<T>(f, a.g, x, xr);
     } else {
-      const uint32_t q = code[brick_pos(a.g.n, x)];
+      const uint32_t q = (d == 2 && E.fcode2) ? (uint32_t)gmem(f.code[2])[fi]
+                                              : (uint32_t)code[brick_pos(a.g.n, x)];
       const T v = q ? (T)((double)p + (double)((int32_t)q - (int32_t)a.R) * a.twoe) : out[idx];
       face_store<T>(f, a.g, x, v);
     }
@@ -1026,7 +1158,9 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
   template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
                                            size_t, uint32_t*, int, int, hipStream_t);             \
   template hipError_t launch_face_steps<T>(const FaceEntry<T>*, const uint64_t*, int, uint64_t,   \
-                                           bool, int, hipStream_t);
+                                           bool, int, hipStream_t);                               \
+  template hipError_t launch_minmax_faces<T>(const T*, const Geom&, const FaceGeo&, double*, int*, \
+                                             int, hipStream_t);
 INST(float)
 INST(double)
 

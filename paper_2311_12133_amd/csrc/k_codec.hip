@@ -716,6 +716,16 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
   // the end catches the rest).  Chunks start at multiples of 64 symbols, so
   // every group is one 16-byte store.
   const uint32_t ngroups = cnt_all / 8;
+  // the chunk is the slab c0 of brick b: its codes with c2 = 0 start every
+  // fourth group (c1 = group / 4) and are contiguous in the compact array
+  uint64_t f2base = 0;
+  unsigned __int128 f2acc = 0;
+  if (a.f2code) {
+    const uint32_t b = (uint32_t)(k >> 5), c0 = (uint32_t)(k & 31);
+    const uint32_t b2 = b % a.nbk2, b01 = b / a.nbk2;
+    const uint32_t b1 = b01 % a.nbk1, b0 = b01 / a.nbk1;
+    f2base = (uint64_t)b2 * a.f2_plane + (uint64_t)(b0 * 32 + c0) * a.f2_n1 + b1 * 32;
+  }
   for (uint32_t gi = 0; gi < ngroups; gi++) {
     top_up();
     uint32_t pk[4] = {0u, 0u, 0u, 0u};
@@ -739,6 +749,12 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
       pk[t >> 1] |= sym << ((t & 1) * 16);
     }
     *reinterpret_cast<uint4*>(code + beg + 8 * gi) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    if (a.f2code && (gi & 3) == 0) {
+      // eight of them (c1 = 8m .. 8m + 7) collected, then one 16-byte store
+      f2acc = (f2acc >> 16) | ((unsigned __int128)(pk[0] & 0xFFFFu) << 112);
+      if ((gi & 31) == 28)
+        *reinterpret_cast<unsigned __int128*>(a.f2code + f2base + (gi >> 2) - 7) = f2acc;
+    }
   }
   // the tail of the last chunk of the field (fewer than eight symbols)
   top_up();
