@@ -958,7 +958,7 @@ struct CJob {
   double h_wq[3 * 16 * 4];
   uint32_t maxlen = 0;  // longest code length
   bool early = false;   // verbatim values gathered before the codebook
-  bool xface = false;   // face arrays prefilled with the field's values
+  bool xface = false;   // family 2's face array prefilled with the field's values
   uint64_t off_unpred = 0;
   // device workspace
   T* W = nullptr;
@@ -1072,10 +1072,10 @@ int c_minmax(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   HIPCK(hipMemsetAsync(J.bad, 0, sizeof(int), st));
   {
     Span sp(ctx, "minmax", J.N * sizeof(T), st);
-    if (J.fast && J.g.n[2] >= 64) {
+    if (J.fast && J.g.n[2] >= 64 && (uint64_t)J.g.n[0] * (uint64_t)J.g.n[1] < (1ull << 32)) {
       // (rows along dim 2 long enough for a wave each) the block path's face
-      // steps then read the face points' values from the compact face arrays
-      // instead of strided rows of the field
+      // steps then read the values of the face points with x2 on the face
+      // lattice from family 2's compact array instead of strided rows
       HIPCK(launch_minmax_faces<T>(J.X, J.g, block_face_arrays<T>(J.g, J.area), J.part, J.bad,
                                    kMinmaxBlocks, st));
       J.xface = true;

@@ -66,7 +66,7 @@ struct FaceEntry {
   uint16_t* code;
   const T* out;
   uint64_t wg_begin, wg_count;
-  int32_t xface;   // compress: the face arrays hold the original values (minmax_faces)
+  int32_t xface;   // compress: family 2's face array holds the original values (minmax_faces)
   int32_t fcode2;  // decompress: f.code[2] holds the codes of family 2 (the decoder's copy)
 };
 
@@ -126,8 +126,9 @@ template <typename T>
 hipError_t launch_coarse_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
                               uint64_t total_blocks, int mode, hipStream_t st);
 // Value range (per-block partials and the non-finite flag, as launch_minmax)
-// and, in the same pass over the field, the original value of every face
-// point into each face array it belongs to.  Up to three dims (n[3] == 1).
+// and, in the same pass over the field, the original values of the points of
+// the face planes normal to dim 2 into that family's face array.  Up to three
+// dims (n[3] == 1), rows along dim 2, fewer than 2^32 rows.
 template <typename T>
 hipError_t launch_minmax_faces(const T* X, const Geom& g, const FaceGeo& f, double* part, int* bad,
                                int nblocks, hipStream_t st);

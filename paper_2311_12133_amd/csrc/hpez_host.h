@@ -108,7 +108,7 @@ struct BlockJobHost {
   Geom g;
   double e = 0;
   const T* X = nullptr;    // compress: the field
-  bool xface = false;      // compress: face arrays prefilled with the field's values
+  bool xface = false;      // compress: family 2's face array prefilled with the field's values
   bool fcode2 = false;     // decompress: family 2's codes in f.code[2] (from the decoder)
   const T* Wg = nullptr;   // the grid holding anchors and levels >= B
   uint16_t* code = nullptr;

@@ -91,10 +91,11 @@ __device__ __forceinline__ bool face_nonfinite(T v)
   return !(v - v == (T)0);
 }
 
-// Value range plus face prefill: one wave per row along dim 2 (rows of the
-// planes x0 = const and x1 = const are contiguous in those families' arrays;
-// the points with x2 on the face lattice go to family 2's array).  The range
-// is reduced exactly as minmax_kernel does.
+// Value range plus face prefill: waves take rows along dim 2; the points with
+// x2 on the face lattice (one per 32 values of a row, so a strided read for
+// the face steps) go to family 2's face array.  The planes normal to dims 0
+// and 1 are contiguous in the field and stay there.  The range is reduced
+// exactly as minmax_kernel does.
 template <typename T>
 __global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__ X, Geom g, FaceGeo f,
                                                            double* __restrict__ part,
@@ -111,6 +112,9 @@ __global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t Bm = f.B - 1;
   const bool vec = (n2 & 3) == 0 && ((uintptr_t)X & 15) == 0;
+  // four consecutive rows share x0 and their x1 are 4k .. 4k + 3: family 2's
+  // values of the four rows are adjacent in its array (one 4-value store)
+  const bool quad = (n1 & 3) == 0 && g.act[2];
   if (vec && n2 <= 128 * (int64_t)(16 / sizeof(T))) {
     // rows of at most two vectors per lane: each wave takes 4 consecutive rows and
     // loads all of its vectors of them before using any (8 loads in flight)
@@ -127,15 +131,22 @@ __global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__
             *reinterpret_cast<u4*>(t[u][h]) =
                 *reinterpret_cast<const HPEZ_GLOBAL u4*>(gmem(X) + (r0 + u) * (uint64_t)n2 + i);
         }
+      // row coordinates: with n1 a multiple of 4 the four rows share x0 and
+      // x1 steps by one (one 32-bit division per four rows; rows < 2^32)
+      const uint32_t r0q = (uint32_t)r0 / (uint32_t)n1;
+      const uint32_t r0r = (uint32_t)r0 - r0q * (uint32_t)n1;
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const uint64_t r = r0 + u;
         if (r >= nrows) break;
-        int64_t x[4] = {(int64_t)(r / n1), (int64_t)(r % n1), 0, 0};
-        HPEZ_GLOBAL T* d0 = (g.act[0] && (x[0] & Bm) == 0)
-                                ? gmem(reinterpret_cast<T*>(f.val[0])) + face_index(f, 0, x) : nullptr;
-        HPEZ_GLOBAL T* d1 = (g.act[1] && (x[1] & Bm) == 0)
-                                ? gmem(reinterpret_cast<T*>(f.val[1])) + face_index(f, 1, x) : nullptr;
+        int64_t x[4] = {0, 0, 0, 0};
+        if (quad) {
+          x[0] = r0q;
+          x[1] = r0r + u;
+        } else {
+          x[0] = (uint32_t)r / (uint32_t)n1;
+          x[1] = (uint32_t)r - (uint32_t)x[0] * (uint32_t)n1;
+        }
         HPEZ_GLOBAL T* d2 =
             g.act[2] ? gmem(reinterpret_cast<T*>(f.val[2])) + face_index(f, 2, x) : nullptr;
 #pragma unroll
@@ -148,19 +159,41 @@ __global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__
             mn = t[u][h][j] < mn ? t[u][h][j] : mn;
             mx = t[u][h][j] > mx ? t[u][h][j] : mx;
           }
-          if (d0) *reinterpret_cast<HPEZ_GLOBAL u4*>(d0 + i) = *reinterpret_cast<const u4*>(t[u][h]);
-          if (d1) *reinterpret_cast<HPEZ_GLOBAL u4*>(d1 + i) = *reinterpret_cast<const u4*>(t[u][h]);
-          if (d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = t[u][h][0];
+          if (!quad && d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = t[u][h][0];
+        }
+      }
+      if (quad && r0 + 3 < nrows) {
+        int64_t x[4] = {(int64_t)r0q, (int64_t)r0r, 0, 0};
+        HPEZ_GLOBAL T* d2 = gmem(reinterpret_cast<T*>(f.val[2])) + face_index(f, 2, x);
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int64_t i = ((int64_t)lane + 64 * h) * V;
+          if (i >= n2 || (i & Bm)) continue;
+          T q[4] = {t[0][h][0], t[1][h][0], t[2][h][0], t[3][h][0]};
+          HPEZ_GLOBAL T* dst = d2 + (i >> f.blog2) * f.plane[2];
+          if (sizeof(T) == 4) {
+            *reinterpret_cast<HPEZ_GLOBAL u4*>(dst) = *reinterpret_cast<const u4*>(q);
+          } else {
+            *reinterpret_cast<HPEZ_GLOBAL u4*>(dst) = *reinterpret_cast<const u4*>(q);
+            *reinterpret_cast<HPEZ_GLOBAL u4*>(dst + 2) = *reinterpret_cast<const u4*>(q + 2);
+          }
+        }
+      } else if (quad) {
+        // the last rows of the field (fewer than four)
+        for (int u = 0; u < 4 && r0 + u < nrows; u++) {
+          int64_t x[4] = {(int64_t)r0q, (int64_t)r0r + u, 0, 0};
+          HPEZ_GLOBAL T* d2 = gmem(reinterpret_cast<T*>(f.val[2])) + face_index(f, 2, x);
+#pragma unroll
+          for (int h = 0; h < 2; h++) {
+            const int64_t i = ((int64_t)lane + 64 * h) * V;
+            if (i < n2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = t[u][h][0];
+          }
         }
       }
     }
   } else
   for (uint64_t r = wave; r < nrows; r += nwaves) {
     int64_t x[4] = {(int64_t)(r / n1), (int64_t)(r % n1), 0, 0};
-    HPEZ_GLOBAL T* d0 = (g.act[0] && (x[0] & Bm) == 0)
-                            ? gmem(reinterpret_cast<T*>(f.val[0])) + face_index(f, 0, x) : nullptr;
-    HPEZ_GLOBAL T* d1 = (g.act[1] && (x[1] & Bm) == 0)
-                            ? gmem(reinterpret_cast<T*>(f.val[1])) + face_index(f, 1, x) : nullptr;
     HPEZ_GLOBAL T* d2 = g.act[2] ? gmem(reinterpret_cast<T*>(f.val[2])) + face_index(f, 2, x) : nullptr;
     const HPEZ_GLOBAL T* row = gmem(X) + r * (uint64_t)n2;
     if (vec) {
@@ -175,8 +208,6 @@ __global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__
           mn = t[j] < mn ? t[j] : mn;
           mx = t[j] > mx ? t[j] : mx;
         }
-        if (d0) *reinterpret_cast<HPEZ_GLOBAL u4*>(d0 + i) = *reinterpret_cast<const u4*>(t);
-        if (d1) *reinterpret_cast<HPEZ_GLOBAL u4*>(d1 + i) = *reinterpret_cast<const u4*>(t);
         if (d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = t[0];
       }
     } else {
@@ -185,8 +216,6 @@ __global__ void __launch_bounds__(256) minmax_faces_kernel(const T* __restrict__
         nf |= face_nonfinite(v);
         mn = v < mn ? v : mn;
         mx = v > mx ? v : mx;
-        if (d0) d0[i] = v;
-        if (d1) d1[i] = v;
         if (d2 && (i & Bm) == 0) d2[(i >> f.blog2) * f.plane[2]] = v;
       }
     }
@@ -288,7 +317,7 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
     }
     const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
     if (MODE == 0) {
-      const T xv = E.xface ? F[fi] : X[idx];
+      const T xv = (d == 2 && E.xface) ? F[fi] : X[idx];
       T xr = xv;
       const uint32_t q = quantize<T>(xv, p, a.inv2e, a.twoe, a.el, a.R, xr);
       gmem(f.code[d])[fi] = (uint16_t)q;  // d is the point's lowest family
