@@ -416,7 +416,16 @@ int huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len)
     uint32_t sym;
   };
   std::vector<Leaf> used;
-  for (uint32_t i = lo; i <= hi; i++)
+  // zero bins skipped four at a time
+  uint32_t i = lo;
+  for (; i + 4 <= hi + 1; i += 4) {
+    uint64_t w[2];
+    std::memcpy(w, hist + i, 16);
+    if (!(w[0] | w[1])) continue;
+    for (uint32_t j = 0; j < 4; j++)
+      if (hist[i + j]) used.push_back({hist[i + j], i + j});
+  }
+  for (; i <= hi; i++)
     if (hist[i]) used.push_back({hist[i], i});
   const size_t K = used.size();
   if (K == 1) {
@@ -476,8 +485,7 @@ void canonical_codes_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_
 {
   // count per length, then first codeword per length, then assign in symbol order
   uint32_t nl[kLmax + 1] = {0};
-  for (uint32_t s = lo; s < hi; s++)
-    if (len[s]) nl[len[s]]++;
+  for_used(len, lo, hi, [&](uint32_t s) { nl[len[s]]++; });
   uint64_t next[kLmax + 2] = {0};
   uint64_t code = 0;
   int prev = 0;
@@ -490,7 +498,8 @@ void canonical_codes_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_
     prev = l;
     any = true;
   }
-  for (uint32_t s = lo; s < hi; s++) cw[s] = len[s] ? (uint32_t)next[len[s]]++ : 0;
+  std::memset(cw + lo, 0, (size_t)(hi - lo) * 4);
+  for_used(len, lo, hi, [&](uint32_t s) { cw[s] = (uint32_t)next[len[s]]++; });
 }
 
 int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
@@ -512,11 +521,13 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
   a.lds_tab = a.ntab <= kEncTab;
   // packed entries (codeword << 6 | length) need codewords of at most 26 bits
   uint32_t maxlen = 0;
-  for (uint32_t k = sym_min; k <= sym_max; k++) maxlen = std::max<uint32_t>(maxlen, h_len[k]);
+  for_used(h_len, sym_min, sym_max + 1,
+           [&](uint32_t k) { maxlen = std::max<uint32_t>(maxlen, h_len[k]); });
   a.packed_ok = maxlen <= 26;
   if (a.packed_ok) {
-    for (uint32_t k = 0; k < a.ntab; k++)
-      h_tab[k] = h_len[sym_min + k] ? (h_cw[sym_min + k] << 6 | h_len[sym_min + k]) : 0u;
+    std::memset(h_tab, 0, (size_t)a.ntab * 4);
+    for_used(h_len, sym_min, sym_max + 1,
+             [&](uint32_t k) { h_tab[k - sym_min] = h_cw[k] << 6 | h_len[k]; });
     if (hipMemcpyAsync(d_tab, h_tab, (size_t)a.ntab * 4, hipMemcpyHostToDevice, st) != hipSuccess)
       return HPEZ_EDEVICE;
   }
@@ -570,8 +581,7 @@ void decode_tables_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t*
                          uint16_t* sorted, uint64_t* lim, uint32_t* base)
 {
   uint64_t count[kLmax + 2] = {0}, next[kLmax + 2] = {0}, offset[kLmax + 2] = {0};
-  for (uint32_t s = lo; s < hi; s++)
-    if (len[s]) count[len[s]]++;
+  for_used(len, lo, hi, [&](uint32_t s) { count[len[s]]++; });
   // canonical first code per length, lengths without codes included
   for (int l = 2; l <= kLmax; l++) next[l] = (next[l - 1] + count[l - 1]) << 1;
   for (int l = 2; l <= kLmax; l++) offset[l] = offset[l - 1] + count[l - 1];
@@ -584,16 +594,15 @@ void decode_tables_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t*
   std::memset(lut, 0, sizeof(uint32_t) << kLutBits);
   uint64_t fill[kLmax + 2];
   for (int l = 0; l <= kLmax + 1; l++) fill[l] = 0;
-  for (uint32_t s = lo; s < hi; s++) {
+  for_used(len, lo, hi, [&](uint32_t s) {
     const int l = len[s];
-    if (!l) continue;
     const uint64_t rank = fill[l]++;
     sorted[offset[l] + rank] = (uint16_t)s;
     if (l <= kLutBits) {
       const uint64_t first = (next[l] + rank) << (kLutBits - l);
       for (uint64_t j = 0; j < (1ull << (kLutBits - l)); j++) lut[first + j] = (s << 8) | (uint32_t)l;
     }
-  }
+  });
 }
 
 uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t* lut,
@@ -601,22 +610,20 @@ uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t
 {
   // canonical codewords as in decode_tables_range: by length, then symbol
   uint64_t count[kLmax + 2] = {0}, next[kLmax + 2] = {0};
-  for (uint32_t s = lo; s < hi; s++)
-    if (len[s]) count[len[s]]++;
+  for_used(len, lo, hi, [&](uint32_t s) { count[len[s]]++; });
   for (int l = 2; l <= kLmax; l++) next[l] = (next[l - 1] + count[l - 1]) << 1;
   uint8_t lmax[1u << kLutBits];
   std::memset(lmax, 0, sizeof lmax);
   uint64_t fill[kLmax + 2];
   for (int l = 0; l <= kLmax + 1; l++) fill[l] = next[l];
-  for (uint32_t s = lo; s < hi; s++) {
+  for_used(len, lo, hi, [&](uint32_t s) {
     const int l = len[s];
-    if (!l) continue;
     const uint64_t cw = fill[l]++;
-    if (l <= kLutBits) continue;
+    if (l <= kLutBits) return;
     const uint32_t pre = (uint32_t)(cw >> (l - kLutBits));
     const int lc = l < kLutBits + kDecSubBits ? l : kLutBits + kDecSubBits;
     if (lc > lmax[pre]) lmax[pre] = (uint8_t)lc;
-  }
+  });
   uint32_t off[1u << kLutBits];
   uint64_t total = 0;
   for (uint32_t p = 0; p < (1u << kLutBits); p++) {
@@ -626,18 +633,17 @@ uint32_t decode_subtables(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_t
   if (total == 0 || total > cap) return 0;
   std::memset(sub, 0, (size_t)total * 4);  // entries no codeword covers decode as invalid
   for (int l = 0; l <= kLmax + 1; l++) fill[l] = next[l];
-  for (uint32_t s = lo; s < hi; s++) {
+  for_used(len, lo, hi, [&](uint32_t s) {
     const int l = len[s];
-    if (!l) continue;
     const uint64_t cw = fill[l]++;
-    if (l <= kLutBits) continue;
+    if (l <= kLutBits) return;
     const uint32_t pre = (uint32_t)(cw >> (l - kLutBits));
     const int lm = lmax[pre];
-    if (l > lm) continue;  // beyond the table depth: by the limits
+    if (l > lm) return;  // beyond the table depth: by the limits
     const uint64_t rest = cw & ((1ull << (l - kLutBits)) - 1);
     const uint64_t first = off[pre] + (rest << (lm - l));
     for (uint64_t j = 0; j < (1ull << (lm - l)); j++) sub[first + j] = (s << 8) | (uint32_t)l;
-  }
+  });
   for (uint32_t p = 0; p < (1u << kLutBits); p++)
     if (lmax[p]) lut[p] = (off[p] << 8) | 0x80u | (uint32_t)(lmax[p] - kLutBits);
   return (uint32_t)total;
@@ -1205,10 +1211,10 @@ void c_codebook(CJob<T>& J)
   J.maxlen = 0;
   if (Lo.sym_max >= Lo.sym_min) {
     canonical_codes_range(J.h_len, Lo.sym_min, Lo.sym_max + 1, J.h_cw);
-    for (uint32_t k = Lo.sym_min; k <= Lo.sym_max; k++) {
+    for_used(J.h_len, Lo.sym_min, Lo.sym_max + 1, [&](uint32_t k) {
       bits += (uint64_t)J.h_hist[k] * J.h_len[k];
       J.maxlen = std::max<uint32_t>(J.maxlen, J.h_len[k]);
-    }
+    });
   }
   Lo.n_unpred = J.h_hist[0];
   Lo.n_chunks = J.nch;
@@ -1275,10 +1281,9 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
     if (J.nb) std::memcpy(h + kHdrBytes, c->block_cfg, J.nb);
     std::memcpy(h + a0, J.h_len + Lo.sym_min, nlen);
     uint32_t* tab = reinterpret_cast<uint32_t*>(h + a0 + a1);
-    for (uint64_t k = 0; k < ntab; k++) {
-      const uint32_t sy = Lo.sym_min + (uint32_t)k;
-      tab[k] = J.h_len[sy] ? (J.h_cw[sy] << 6 | J.h_len[sy]) : 0u;
-    }
+    std::memset(tab, 0, ntab * 4);
+    for_used(J.h_len, Lo.sym_min, Lo.sym_max + 1,
+             [&](uint32_t sy) { tab[sy - Lo.sym_min] = J.h_cw[sy] << 6 | J.h_len[sy]; });
     HIPCK(hipMemcpyAsync(J.d_stage, h, a0 + a1 + ntab * 4, hipMemcpyHostToDevice, st));
     const uint64_t vz = (vend + 7) & ~7ull;
     ByteSegs sg;
@@ -1556,15 +1561,18 @@ void d_tables(DJob<T>& J)
   const uint32_t lo = J.Lo.sym_max >= J.Lo.sym_min ? J.Lo.sym_min : 0;
   const uint32_t hi = J.Lo.sym_max >= J.Lo.sym_min ? J.Lo.sym_max + 1 : 0;
   (void)nsym;
-  for (uint32_t k = lo; k < hi; k++) {
+  bool too_long = false;
+  for_used(J.h_len, lo, hi, [&](uint32_t k) {
     if (J.h_len[k] > kLmax) {
-      J.rc = HPEZ_ECORRUPT;
+      too_long = true;
       return;
     }
-    if (J.h_len[k]) {
-      kraft += 1ull << (kLmax - J.h_len[k]);
-      used++;
-    }
+    kraft += 1ull << (kLmax - J.h_len[k]);
+    used++;
+  });
+  if (too_long) {
+    J.rc = HPEZ_ECORRUPT;
+    return;
   }
   if (J.N > 0 && !(kraft == (1ull << kLmax) || (used == 1 && kraft == (1ull << (kLmax - 1))))) {
     J.rc = HPEZ_ECORRUPT;
@@ -1578,10 +1586,10 @@ void d_tables(DJob<T>& J)
   da.chunk = J.c.chunk;
   decode_tables_range(J.h_len, lo, hi, J.h_lut, J.h_sorted, da.lim, da.base);
   uint32_t nshort = 0, nused = 0;
-  for (uint32_t k = lo; k < hi; k++) {
-    nused += J.h_len[k] != 0;
-    nshort += J.h_len[k] != 0 && J.h_len[k] <= kLutBits;
-  }
+  for_used(J.h_len, lo, hi, [&](uint32_t k) {
+    nused++;
+    nshort += J.h_len[k] <= kLutBits;
+  });
   J.nused = nused;
   da.long_first = nshort;
   da.n_long = nused - nshort;

@@ -2,6 +2,8 @@
 // Huffman codebook, geometry).  Not part of the public ABI.
 #pragma once
 
+#include <cstring>
+
 #include <stdint.h>
 
 #include <vector>
@@ -63,6 +65,25 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
 template <typename T>
 int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const hpez_config* c,
                      double e, uint8_t* out, uint64_t cap, uint64_t* out_size, hipStream_t st);
+
+// fn(s) for every s in [lo, hi) with len[s] != 0, in increasing order; runs of
+// zero lengths are skipped eight at a time (a code uses few of its symbols)
+template <typename F>
+inline void for_used(const uint8_t* len, uint32_t lo, uint32_t hi, F fn)
+{
+  uint32_t s = lo;
+  for (; s < hi && (s & 7u); s++)
+    if (len[s]) fn(s);
+  for (; s + 8 <= hi; s += 8) {
+    uint64_t w;
+    std::memcpy(&w, len + s, 8);
+    if (!w) continue;
+    for (uint32_t j = 0; j < 8; j++)
+      if (len[s + j]) fn(s + j);
+  }
+  for (; s < hi; s++)
+    if (len[s]) fn(s);
+}
 
 // context services (api.cpp)
 void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc);

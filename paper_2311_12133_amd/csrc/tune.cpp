@@ -683,7 +683,10 @@ int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
     As *= 2;
     al++;
   }
-  std::vector<TrialBox> bx((size_t)J.nbt);
+  // the boxes are built in the pinned block-score area (read only after this
+  // phase's synchronization)
+  static_assert(sizeof(unsigned long long) * kNCand >= sizeof(TrialBox), "box staging");
+  TrialBox* bx = reinterpret_cast<TrialBox*>(J.h_bscore);
   uint64_t cap = 0;
   for (int64_t bi = 0; bi < J.nbt; bi++) {
     int64_t b[4];
@@ -699,11 +702,8 @@ int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
   }
   if ((size_t)J.nbt * kNCand * cap * sizeof(T) > J.scratch_bytes && cap * sizeof(T) > kTrialLdsBytes)
     return HPEZ_ENOMEM;
-  // the boxes are staged in the pinned block-score area, which is read only
-  // after this phase's synchronization
-  static_assert(sizeof(unsigned long long) * kNCand >= sizeof(TrialBox), "box staging");
-  std::memcpy(J.h_bscore, bx.data(), bx.size() * sizeof(TrialBox));
-  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, bx.size() * sizeof(TrialBox), hipMemcpyHostToDevice, st));
+  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, (size_t)J.nbt * sizeof(TrialBox), hipMemcpyHostToDevice,
+                     st));
   TrialArgs& a = J.ba;
   std::memset(&a, 0, sizeof a);
   a.fg = g;
