@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) stats_kernel(const T* __restrict__ X, Geo
     for (int d = 0; d < 4; d++) {
       if (!g.act[d]) continue;
       const unsigned long long v = block_sum_u64(acc[k][d], red);
-      if (threadIdx.x == 0 && v) atomicAdd(&sums[k * 4 + d], v);
+      if (threadIdx.x == 0 && v) atomicAdd(&sums[(blockIdx.x % kStatSlots) * 12 + k * 4 + d], v);
     }
 }
 

@@ -296,7 +296,7 @@ size_t t_dev_bytes(const TJob<T>& J)
          al256(J.scratch_bytes) + 2 * al256(kNCand * 16 * 8) + al256(nb * kNCand * 8) +
          al256(16 * 8) + 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + 2 * al256(64) +
          al256(3 * 16 * 4 * 8) +
-         al256(2 * 1024 * 8) + al256(64) + al256(12 * 8) + 256;
+         al256(2 * 1024 * 8) + al256(64) + al256(12 * 8 * kStatSlots) + 256;
 }
 
 template <typename T>
@@ -304,7 +304,8 @@ size_t t_pin_bytes(const TJob<T>& J)
 {
   if (J.done) return 0;
   return 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + al256(16) + 2 * al256(kNCand * 16 * 8) +
-         al256((size_t)J.nbt * kNCand * 8) + al256(64) + al256(12 * 8) + al256(3 * 16 * 4 * 8) +
+         al256((size_t)J.nbt * kNCand * 8) + al256(64) + al256(12 * 8 * kStatSlots) +
+         al256(3 * 16 * 4 * 8) +
          al256(J.gb.size() * sizeof(TrialBox)) + 256;
 }
 
@@ -338,7 +339,7 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.wq = dw.take<double>(3 * 16 * 4);
   J.part = dw.take<double>(2 * 1024);
   J.mm = dw.take<double>(8);
-  J.sums = dw.take<unsigned long long>(12);
+  J.sums = dw.take<unsigned long long>(12 * kStatSlots);
   for (int v = 0; v < 3; v++) J.h_hist[v] = pw.take<uint32_t>(J.nsym);
   for (int v = 0; v < 3; v++) J.h_nz[v] = pw.take<uint32_t>(2 * kNzCap);
   J.h_nzn = pw.take<uint32_t>(4);
@@ -348,7 +349,7 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.h_mm = pw.take<double>(8);
   J.h_bad = (int*)(J.h_mm + 2);
   J.h_lflag = (int*)(J.h_mm + 3);
-  J.h_sums = pw.take<unsigned long long>(12);
+  J.h_sums = pw.take<unsigned long long>(12 * kStatSlots);
   J.h_wqp = pw.take<double>(3 * 16 * 4);
   J.h_gbp = pw.take<TrialBox>(J.gb.size());
 }
@@ -362,7 +363,7 @@ int t_minmax(TJob<T>& J, hipStream_t st)
   // counts, flags, statistics sums) lies between score[0] and the end of sums
   // in the workspace: one clear for all of them
   uint8_t* z0 = reinterpret_cast<uint8_t*>(J.score[0]);
-  uint8_t* z1 = reinterpret_cast<uint8_t*>(J.sums + 12);
+  uint8_t* z1 = reinterpret_cast<uint8_t*>(J.sums + 12 * kStatSlots);
   TCK(hipMemsetAsync(z0, 0, (size_t)(z1 - z0), st));
   TCK(launch_minmax<T>(J.X, J.N, J.part, J.flag, 1024, st));
   TCK(launch_minmax_final(J.part, 1024, J.mm, st));
@@ -408,7 +409,7 @@ int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
     if (gs.act[k] && gs.n[k] < 8) gs.act[k] = 0;
   int any = 0;
   for (int k = 0; k < 4; k++) any |= gs.act[k];
-  std::memset(J.h_sums, 0, 12 * 8);
+  std::memset(J.h_sums, 0, 12 * 8 * kStatSlots);
   J.count = 0;
   if (!any) return HPEZ_OK;
   Lattice lat;
@@ -426,7 +427,7 @@ int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
   hipEvent_t ev = ctx_span_begin(ctx, st);
   TCK(launch_stats<T>(J.X, gs, lat, 256.0 / J.e, J.sums, st));
   ctx_span_end(ctx, ev, "tune_stats", lat.total * (1 + 4 * n_active(gs)) * sizeof(T), st);
-  TCK(hipMemcpyAsync(J.h_sums, J.sums, 12 * 8, hipMemcpyDeviceToHost, st));
+  TCK(hipMemcpyAsync(J.h_sums, J.sums, 12 * 8 * kStatSlots, hipMemcpyDeviceToHost, st));
   return HPEZ_OK;
 }
 
@@ -530,7 +531,9 @@ int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
   double sigma2[3][4];
   for (int k = 0; k < 3; k++)
     for (int j = 0; j < 4; j++) {
-      const double s2 = J.count > 0 ? (double)J.h_sums[k * 4 + j] / (double)J.count : 1.0;
+      unsigned long long sum = 0;
+      for (int c = 0; c < kStatSlots; c++) sum += J.h_sums[c * 12 + k * 4 + j];
+      const double s2 = J.count > 0 ? (double)sum / (double)J.count : 1.0;
       sigma2[k][j] = s2;
       Q.md_w[k][j] = 1.0 / (s2 > 1.0 ? s2 : 1.0);
     }

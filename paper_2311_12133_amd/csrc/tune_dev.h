@@ -62,6 +62,10 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
 }
 #endif
 
+// d_sums: kStatSlots copies of the 12 sums (zeroed); work-group w adds into
+// copy w % kStatSlots, so the atomics of many work-groups do not all meet on
+// the same 12 words.  The caller adds the copies (integers: exact in any order).
+constexpr int kStatSlots = 64;
 template <typename T>
 hipError_t launch_stats(const T* X, const Geom& g, const Lattice& lat, double mul,
                         unsigned long long* d_sums, hipStream_t st);
