@@ -513,26 +513,24 @@ __global__ void __launch_bounds__(256) lorenzo_trial_kernel(Geom fg, const Trial
   for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x) lh[i] = 0;
   __syncthreads();
   const TrialBox bx = boxes[blockIdx.y];
-  const int64_t npts = (int64_t)bx.m[0] * bx.m[1] * bx.m[2] * bx.m[3];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t x[4], rr = i;
-    for (int d = 3; d >= 0; d--) {
-      x[d] = rr % bx.m[d];
-      rr /= bx.m[d];
-    }
+  const int64_t st0 = fg.st[0], st1 = fg.st[1], st2 = fg.st[2];
+  const int64_t sd[4] = {st0, st1, st2, 1};
+  // one point: its Lorenzo residual (sum over the corners of the unit cell
+  // behind it, each stepping back one along the dims of S) into the histogram
+  auto point = [&](const int64_t* x) {
+    const int64_t base = (bx.o[0] + x[0]) * st0 + (bx.o[1] + x[1]) * st1 +
+                         (bx.o[2] + x[2]) * st2 + (bx.o[3] + x[3]);
     long long delta = 0;
     bool bad = false;
     for (unsigned S = 0; S < 16; S++) {
       bool in = true;
-      int64_t y[4];
-      for (int d = 0; d < 4; d++) {
-        y[d] = x[d] - ((S >> d) & 1u);
-        if (y[d] < 0) in = false;
-      }
+      int64_t fidx = base;
+      for (int d = 0; d < 4; d++)
+        if ((S >> d) & 1u) {
+          if (x[d] == 0) in = false;
+          fidx -= sd[d];
+        }
       if (!in) continue;
-      const int64_t fidx = (bx.o[0] + y[0]) * fg.st[0] + (bx.o[1] + y[1]) * fg.st[1] +
-                           (bx.o[2] + y[2]) * fg.st[2] + (bx.o[3] + y[3]);
       const double t = (double)X[fidx] * inv2e;
       const double qf = floor(fabs(t) + 0.5);
       if (!(qf < 4503599627370496.0)) {
@@ -544,10 +542,36 @@ __global__ void __launch_bounds__(256) lorenzo_trial_kernel(Geom fg, const Trial
     }
     if (bad) {
       atomicOr(unsupported, 1);
-      continue;
+      return;
     }
     const uint32_t code = (delta > -(long long)R && delta < (long long)R) ? (uint32_t)(delta + R) : 0u;
     hist_add_wave(lh, hist, hist_lo, kTrialHistWin, code, true);
+  };
+  const uint64_t np = (uint64_t)bx.m[0] * bx.m[1] * bx.m[2] * bx.m[3];
+  if (np < (1ull << 31) && bx.m[1] <= (int64_t)kMagicMax && bx.m[2] <= (int64_t)kMagicMax &&
+      bx.m[3] <= (int64_t)kMagicMax) {
+    // 32-bit coordinates by multiply-high division
+    const uint32_t npts = (uint32_t)np;
+    const uint32_t m1 = (uint32_t)bx.m[1], m2 = (uint32_t)bx.m[2], m3 = (uint32_t)bx.m[3];
+    const Divisor d1 = fmagic(m1), d2 = fmagic(m2), d3 = fmagic(m3);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x) {
+      const uint32_t q3 = fdiv(i, d3), x3 = i - q3 * m3;
+      const uint32_t q2 = fdiv(q3, d2), x2 = q3 - q2 * m2;
+      const uint32_t x0 = fdiv(q2, d1), x1 = q2 - x0 * m1;
+      const int64_t x[4] = {x0, x1, x2, x3};
+      point(x);
+    }
+  } else {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+      int64_t x[4];
+      uint64_t rr = i;
+      for (int d = 3; d >= 0; d--) {
+        x[d] = (int64_t)(rr % (uint64_t)bx.m[d]);
+        rr /= (uint64_t)bx.m[d];
+      }
+      point(x);
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x)
