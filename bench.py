@@ -83,8 +83,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain measurement on the 48-field workload")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the serving measurement (Poisson request stream); off by "
+                         "default: one run of it stalled with no output and the cause is not "
+                         "known yet")
     ap.add_argument("--no-serve", action="store_true",
-                    help="skip the serving measurement (Poisson request stream)")
+                    help="skip the serving measurement (the default)")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -199,7 +203,7 @@ def main():
         batch = batch_section(args, binding, fields, torch)
 
     serving = None
-    if not args.no_serve:
+    if args.serve and not args.no_serve:
         torch.cuda.empty_cache()
         serving = serving_section(args, binding, fields, torch, nbytes / comp_s / 1e9)
 
