@@ -726,8 +726,8 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
     const uint32_t b1 = b01 % a.nbk1, b0 = b01 / a.nbk1;
     f2base = (uint64_t)b2 * a.f2_plane + (uint64_t)(b0 * 32 + c0) * a.f2_n1 + b1 * 32;
   }
-  for (uint32_t gi = 0; gi < ngroups; gi++) {
-    top_up();
+  // eight symbols decoded into one 16-byte group
+  auto group = [&]() {
     uint32_t pk[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (uint32_t t = 0; t < 8; t++) {
@@ -748,13 +748,38 @@ __global__ void __launch_bounds__(256) decode2_kernel(DecodeArgs a, const uint32
       pos += L;
       pk[t >> 1] |= sym << ((t & 1) * 16);
     }
-    *reinterpret_cast<uint4*>(code + beg + 8 * gi) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    return make_uint4(pk[0], pk[1], pk[2], pk[3]);
+  };
+  auto face2 = [&](uint32_t gi, uint32_t first) {
     if (a.f2code && (gi & 3) == 0) {
       // eight of them (c1 = 8m .. 8m + 7) collected, then one 16-byte store
-      f2acc = (f2acc >> 16) | ((unsigned __int128)(pk[0] & 0xFFFFu) << 112);
+      f2acc = (f2acc >> 16) | ((unsigned __int128)(first & 0xFFFFu) << 112);
       if ((gi & 31) == 28)
         *reinterpret_cast<unsigned __int128*>(a.f2code + f2base + (gi >> 2) - 7) = f2acc;
     }
+  };
+  // Whole 128-byte lines of codes are held in registers and stored together:
+  // the 64 lanes of a wave write 64 chunks 2 KiB apart, and a line written a
+  // group at a time leaves the cache partly filled between its stores.
+  const uint32_t nlines = ngroups / 8;
+  for (uint32_t li = 0; li < nlines; li++) {
+    uint4 l0, l1, l2, l3, l4, l5, l6, l7;
+#pragma unroll 1
+    for (uint32_t g = 0; g < 8; g++) {
+      top_up();
+      const uint4 v = group();
+      face2(li * 8 + g, v.x);
+      l0 = l1, l1 = l2, l2 = l3, l3 = l4, l4 = l5, l5 = l6, l6 = l7, l7 = v;
+    }
+    uint4* dst = reinterpret_cast<uint4*>(code + beg + 64 * li);
+    dst[0] = l0, dst[1] = l1, dst[2] = l2, dst[3] = l3;
+    dst[4] = l4, dst[5] = l5, dst[6] = l6, dst[7] = l7;
+  }
+  for (uint32_t gi = nlines * 8; gi < ngroups; gi++) {
+    top_up();
+    const uint4 v = group();
+    *reinterpret_cast<uint4*>(code + beg + 8 * gi) = v;
+    face2(gi, v.x);
   }
   // the tail of the last chunk of the field (fewer than eight symbols)
   top_up();
