@@ -42,6 +42,10 @@ struct hpez_ctx {
   uint8_t* pin_pre = nullptr;  // first bytes of the streams being decompressed
   size_t pin_pre_bytes = 0;
   hipEvent_t ev_sync = nullptr;  // host waits for part of a stream's work
+  // second stream for work that can overlap the caller's stream, with the
+  // events that fork it from and join it back to that stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // kernel timing (hpez_profile_enable)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -1832,6 +1836,9 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
   if (ctx->pin_pre) (void)hipHostFree(ctx->pin_pre);
   if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -2088,6 +2095,34 @@ uint8_t* ctx_pin_tab(hpez_ctx* c, size_t bytes, int* rc)
 }
 
 int ctx_device(hpez_ctx* c) { return c->device; }
+
+hipStream_t ctx_fork(hpez_ctx* c, hipStream_t st)
+{
+  if (!c->side) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+      c->ev_fork = nullptr;
+      (void)hipStreamDestroy(s);
+      return nullptr;
+    }
+    c->side = s;
+  }
+  if (hipEventRecord(c->ev_fork, st) != hipSuccess ||
+      hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess)
+    return nullptr;
+  return c->side;
+}
+
+int ctx_join(hpez_ctx* c, hipStream_t st)
+{
+  if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
+      hipStreamWaitEvent(st, c->ev_join, 0) != hipSuccess)
+    return HPEZ_EDEVICE;
+  return HPEZ_OK;
+}
 
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st)
 {

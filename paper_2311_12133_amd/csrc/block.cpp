@@ -464,18 +464,26 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   hipEvent_t ev = ctx_span_begin(ctx, st);
   BCK(launch_planes<T>((const PlaneJob<T>*)(dt + off_planes), (const uint64_t*)(dt + off_pwg), np,
                        plane_wgs, plane_lds, mode, st));
+  // The coarse levels of every block on the block lattices need only the
+  // planes' lattice points; the face steps fill the other face points.  The
+  // two write disjoint arrays, so the coarse levels run on the second stream
+  // beside the face steps.
+  hipStream_t cs = launches.empty() ? st : ctx_fork(ctx, st);
+  if (!cs) cs = st;
+  hipEvent_t evc = ctx_span_begin(ctx, cs);
+  BCK(launch_coarse_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
+                            n, total_blocks, mode, cs));
+  ctx_span_end(ctx, evc, mode == 0 ? "coarse_predict" : "coarse_reconstruct",
+               total_blocks * 729ull * (sizeof(T) + 2), cs);
   for (const Launch& L : launches)
     BCK(launch_face_steps<T>((const FaceEntry<T>*)dt + L.e0, (const uint64_t*)(dt + off_wg) + L.w0,
                              L.cnt, L.wgs, L.narrow, mode, st));
   ctx_span_end(ctx, ev, mode == 0 ? "faces_predict" : "faces_reconstruct",
                face_pts * (sizeof(T) + 2), st);
-
-  // the coarse levels of every block on the block lattices
-  ev = ctx_span_begin(ctx, st);
-  BCK(launch_coarse_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
-                            n, total_blocks, mode, st));
-  ctx_span_end(ctx, ev, mode == 0 ? "coarse_predict" : "coarse_reconstruct",
-               total_blocks * 729ull * (sizeof(T) + 2), st);
+  if (cs != st) {
+    const int rc = ctx_join(ctx, st);
+    if (rc) return rc;
+  }
 
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx_device(ctx)) !=

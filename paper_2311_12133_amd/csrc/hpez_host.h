@@ -91,6 +91,11 @@ uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc);
 // pinned staging of launch tables, reused by every call (synchronized between uses)
 uint8_t* ctx_pin_tab(hpez_ctx* c, size_t bytes, int* rc);
 int ctx_device(hpez_ctx* c);
+// The context's second stream, made to wait for the work queued so far on st
+// (nullptr on failure: the caller then queues everything on st).  ctx_join
+// makes st wait for what was queued on the second stream since.
+hipStream_t ctx_fork(hpez_ctx* c, hipStream_t st);
+int ctx_join(hpez_ctx* c, hipStream_t st);
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
 void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);
 void ctx_prof_collect(hpez_ctx* c);

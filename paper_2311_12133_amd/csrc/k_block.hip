@@ -446,19 +446,33 @@ __global__ void __launch_bounds__(kBlockThreads) plane_kernel(const PlaneJob<T>*
   const HPEZ_GLOBAL T* X = gmem(J.X);
   // the lattice: points of the coarse grid (multiples of B) from the face
   // array, the others from X (compress) or predicted (decompress)
-  for (uint32_t i = threadIdx.x; i < ncell; i += NT) {
-    const uint32_t q0 = div_magic(i, J.mg_b0, J.sh_b0);
-    const uint32_t r = i - q0 * (uint32_t)lb.b0;
-    const uint32_t q1 = div_magic(r, J.mg_e2, J.sh_e2);
-    int64_t x[4] = {(int64_t)q0 * k0, (int64_t)q1 * k1, (int64_t)(r - q1 * (uint32_t)lb.E2) * k2, 0};
-    x[d] = xd;
-    bool grid = true;
-    for (int e = 0; e < 3; e++)
-      if (g.act[e] && (x[e] & (f.B - 1))) grid = false;
-    T v = (T)0;
-    if (grid) v = F[face_index(f, d, x)];
-    else if (MODE == 0) v = X[x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]];
-    L[i] = v;
+  // (a lane's loads are all issued before the first of them is waited for)
+  constexpr int UC = 8;
+  for (uint32_t ib = 0; ib < ncell; ib += UC * NT) {
+    T v[UC];
+#pragma unroll
+    for (int u = 0; u < UC; u++) {
+      const uint32_t i = ib + u * NT + threadIdx.x;
+      const uint32_t ii = i < ncell ? i : 0u;
+      const uint32_t q0 = div_magic(ii, J.mg_b0, J.sh_b0);
+      const uint32_t r = ii - q0 * (uint32_t)lb.b0;
+      const uint32_t q1 = div_magic(r, J.mg_e2, J.sh_e2);
+      int64_t x[4] = {(int64_t)q0 * k0, (int64_t)q1 * k1, (int64_t)(r - q1 * (uint32_t)lb.E2) * k2,
+                      0};
+      x[d] = xd;
+      bool grid = true;
+      for (int e = 0; e < 3; e++)
+        if (g.act[e] && (x[e] & (f.B - 1))) grid = false;
+      const HPEZ_GLOBAL T* src = grid ? F + face_index(f, d, x)
+                                      : X + (x[0] * g.st[0] + x[1] * g.st[1] + x[2] * g.st[2] + x[3]);
+      const bool ok = i < ncell && (grid || MODE == 0);
+      v[u] = ok ? *src : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < UC; u++) {
+      const uint32_t i = ib + u * NT + threadIdx.x;
+      if (i < ncell) L[i] = v[u];
+    }
   }
   __syncthreads();
   for (int l = J.Ltop; l > kCoarseL; l--) {
@@ -544,6 +558,19 @@ __device__ __forceinline__ Quad<double> load_quad(const HPEZ_GLOBAL double* p)
 {
   const vd2 a = reinterpret_cast<const HPEZ_GLOBAL vd2*>(p)[0];
   const vd2 b = reinterpret_cast<const HPEZ_GLOBAL vd2*>(p)[1];
+  return {{a.x, a.y, b.x, b.y}};
+}
+// the same with the streaming hint: the field is read once, and its lines
+// should leave the cache before the partly written code lines do
+__device__ __forceinline__ Quad<float> load_quad_once(const HPEZ_GLOBAL float* p)
+{
+  const vf4 q = __builtin_nontemporal_load(reinterpret_cast<const HPEZ_GLOBAL vf4*>(p));
+  return {{q.x, q.y, q.z, q.w}};
+}
+__device__ __forceinline__ Quad<double> load_quad_once(const HPEZ_GLOBAL double* p)
+{
+  const vd2 a = __builtin_nontemporal_load(reinterpret_cast<const HPEZ_GLOBAL vd2*>(p));
+  const vd2 b = __builtin_nontemporal_load(reinterpret_cast<const HPEZ_GLOBAL vd2*>(p) + 1);
   return {{a.x, a.y, b.x, b.y}};
 }
 
@@ -694,27 +721,43 @@ __global__ void __launch_bounds__(64) coarse_kernel(const BlockJobDev<T>* __rest
   const Divisor mb0 = fmagic((uint32_t)lb.b0), mE2 = fmagic((uint32_t)lb.E2);
   const int64_t st0 = a.g.st[0], st1 = a.g.st[1];
   const HPEZ_GLOBAL T* __restrict__ X = gmem(J.X);
-  // the lattice: face cells from the face arrays, the others from X (compress)
-  for (uint32_t i = threadIdx.x; i < n; i += 64) {
-    const uint32_t q0 = fdiv(i, mb0);
-    const uint32_t r = i - q0 * (uint32_t)lb.b0;
-    const uint32_t q1 = fdiv(r, mE2);
-    const int32_t c0 = (int32_t)q0 * k0, c1 = (int32_t)q1 * k1,
-                  c2 = (int32_t)(r - q1 * (uint32_t)lb.E2) * k2;
-    const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + c2;
-    T v = (T)0;
-    if (bx.a0 && (c0 == 0 || c0 == kBrick))
-      v = gmem(reinterpret_cast<const T*>(f.val[0]))[(x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] +
-                                                     x2];
-    else if (bx.a1 && (c1 == 0 || c1 == kBrick))
-      v = gmem(reinterpret_cast<const T*>(f.val[1]))[(x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] +
-                                                     x2];
-    else if (bx.a2 && (c2 == 0 || c2 == kBrick))
-      v = gmem(reinterpret_cast<const T*>(f.val[2]))[(x2 >> f.blog2) * f.plane[2] + x0 * f.fs[2][0] +
-                                                     x1 * f.fs[2][1]];
-    else if (MODE == 0)
-      v = X[x0 * st0 + x1 * st1 + x2];
-    L[i] = v;
+  // the lattice: face cells from the face arrays, the others from X (compress);
+  // a lane's loads are all issued before the first of them is waited for
+  constexpr int UC = 12;
+  for (uint32_t ib = 0; ib < n; ib += UC * 64) {
+    T v[UC];
+#pragma unroll
+    for (int u = 0; u < UC; u++) {
+      const uint32_t i = ib + u * 64 + threadIdx.x;
+      const uint32_t ii = i < n ? i : 0u;
+      const uint32_t q0 = fdiv(ii, mb0);
+      const uint32_t r = ii - q0 * (uint32_t)lb.b0;
+      const uint32_t q1 = fdiv(r, mE2);
+      const int32_t c0 = (int32_t)q0 * k0, c1 = (int32_t)q1 * k1,
+                    c2 = (int32_t)(r - q1 * (uint32_t)lb.E2) * k2;
+      const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + c2;
+      const HPEZ_GLOBAL T* src = X + (x0 * st0 + x1 * st1 + x2);
+      bool ok = i < n && MODE == 0;
+      if (bx.a0 && (c0 == 0 || c0 == kBrick)) {
+        src = gmem(reinterpret_cast<const T*>(f.val[0])) + ((x0 >> f.blog2) * f.plane[0] +
+                                                            x1 * f.fs[0][1] + x2);
+        ok = i < n;
+      } else if (bx.a1 && (c1 == 0 || c1 == kBrick)) {
+        src = gmem(reinterpret_cast<const T*>(f.val[1])) + ((x1 >> f.blog2) * f.plane[1] +
+                                                            x0 * f.fs[1][0] + x2);
+        ok = i < n;
+      } else if (bx.a2 && (c2 == 0 || c2 == kBrick)) {
+        src = gmem(reinterpret_cast<const T*>(f.val[2])) + ((x2 >> f.blog2) * f.plane[2] +
+                                                            x0 * f.fs[2][0] + x1 * f.fs[2][1]);
+        ok = i < n;
+      }
+      v[u] = ok ? *src : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < UC; u++) {
+      const uint32_t i = ib + u * 64 + threadIdx.x;
+      if (i < n) L[i] = v[u];
+    }
   }
   __syncthreads();
   const hpez_interp c = a.cand[gmem(J.bcfg)[bi]];
@@ -783,15 +826,20 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL
   const bool face0 = bx.a0 && (c0 == 0 || c0 == kBrick);
   const bool face1 = !face0 && bx.a1 && (c1 == 0 || c1 == kBrick);
   const HPEZ_GLOBAL T* src = nullptr;
+  bool once = false;
   if (face0)
     src = gmem(reinterpret_cast<const T*>(f.val[0])) + (x0 >> f.blog2) * f.plane[0] + x1 * f.fs[0][1] + x2;
   else if (face1)
     src = gmem(reinterpret_cast<const T*>(f.val[1])) + (x1 >> f.blog2) * f.plane[1] + x0 * f.fs[1][0] + x2;
-  else if (MODE == 0 && cb < kBrick)
+  else if (MODE == 0 && cb < kBrick) {
     src = X + x0 * st0 + x1 * st1 + x2;  // (cell c2 = 32 is the next block's face value)
+    once = true;
+  }
   if (src) {
     wr = (1u << cnt) - 1u;
-    if (vec && cnt == 4) {
+    if (vec && cnt == 4 && once) {
+      v = load_quad_once(src);
+    } else if (vec && cnt == 4) {
       v = load_quad(src);
     } else {
 #pragma unroll
