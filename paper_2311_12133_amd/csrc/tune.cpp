@@ -69,14 +69,41 @@ double entropy_bits(const uint32_t* h, uint32_t nsym)
 // sorted by bin, the sums run over the same terms in the same order
 double entropy_bits_pairs(const uint32_t* pairs, uint32_t n)
 {
-  std::vector<std::pair<uint32_t, uint32_t>> v(n);
-  for (uint32_t i = 0; i < n; i++) v[i] = {pairs[2 * i], pairs[2 * i + 1]};
-  std::sort(v.begin(), v.end());
+  // the sum runs over the bins in increasing order; the bins are distinct and
+  // below 2^16 (codes are 16-bit), so two 8-bit radix passes sort the pairs
+  std::vector<uint32_t> a(pairs, pairs + 2 * (size_t)n), b(2 * (size_t)n);
+  bool small = true;
+  for (uint32_t i = 0; i < n; i++) small = small && a[2 * i] < 65536u;
+  if (small) {
+    for (int pass = 0; pass < 2; pass++) {
+      const int sh = 8 * pass;
+      uint32_t cnt[257] = {0};
+      for (uint32_t i = 0; i < n; i++) cnt[((a[2 * i] >> sh) & 255u) + 1]++;
+      for (int k = 0; k < 256; k++) cnt[k + 1] += cnt[k];
+      for (uint32_t i = 0; i < n; i++) {
+        const uint32_t d = cnt[(a[2 * i] >> sh) & 255u]++;
+        b[2 * d] = a[2 * i];
+        b[2 * d + 1] = a[2 * i + 1];
+      }
+      a.swap(b);
+    }
+  } else {
+    std::vector<std::pair<uint32_t, uint32_t>> v(n);
+    for (uint32_t i = 0; i < n; i++) v[i] = {a[2 * i], a[2 * i + 1]};
+    std::sort(v.begin(), v.end());
+    for (uint32_t i = 0; i < n; i++) {
+      a[2 * i] = v[i].first;
+      a[2 * i + 1] = v[i].second;
+    }
+  }
   uint64_t tot = 0;
-  for (const auto& b : v) tot += b.second;
+  for (uint32_t i = 0; i < n; i++) tot += a[2 * i + 1];
   if (tot == 0) return 0.0;
   double acc = 0.0;
-  for (const auto& b : v) acc += (double)b.second * std::log2((double)tot / (double)b.second);
+  for (uint32_t i = 0; i < n; i++) {
+    const double c = (double)a[2 * i + 1];
+    acc += c * std::log2((double)tot / c);
+  }
   return acc / (double)tot;
 }
 
@@ -211,6 +238,8 @@ struct TJob {
   int frozen = -1;
   bool lorenzo = false, lorenzo_trial = false;
   bool blocks = false;
+  bool spec = false;  // block trials already queued on the second stream
+  double HL = 0.0;     // entropy of the Lorenzo trial's codes
   TrialArgs ba;
   double h_wq[3 * 16 * 4];
   // device
@@ -475,7 +504,7 @@ void t_add(TrialBatch<T>& tb, const TrialArgs& a, const TrialBox* boxes, uint32_
 // stage the tables through pinned memory (one copy) and launch
 template <typename T>
 int t_launch(hpez_ctx* ctx, TrialBatch<T>& tb, bool hist, uint8_t* d_tab, size_t tab_cap,
-             hipStream_t st)
+             hipStream_t st, uint8_t* h_stage = nullptr)
 {
   std::vector<TrialJob<T>>* groups[3] = {&tb.grp[0], &tb.grp[1], &tb.grp[2]};
   const int lanes_of[3] = {64, 256, 1024};
@@ -484,8 +513,8 @@ int t_launch(hpez_ctx* ctx, TrialBatch<T>& tb, bool hist, uint8_t* d_tab, size_t
   if (bytes > tab_cap) return HPEZ_EINVAL;
   if (bytes) {
     int rc;
-    uint8_t* h = ctx_pin_tab(ctx, bytes, &rc);
-    if (rc) return rc;
+    uint8_t* h = h_stage ? h_stage : ctx_pin_tab(ctx, bytes, &rc);
+    if (!h_stage && rc) return rc;
     size_t off = 0;
     size_t offs[3][2];
     uint64_t tot[3];
@@ -565,10 +594,16 @@ int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
     t_add<T>(tb, a, J.d_gb, nbx, kNCand, J.X, (T*)J.scratch, J.wq, J.score[v], nullptr);
   }
   J.lorenzo_trial = o->allow_lorenzo != 0;
-  if (J.lorenzo_trial) {
-    TCK(launch_lorenzo_trial<T>(J.g, J.d_gb, nbx, (uint32_t)J.gcap, J.X, 1.0 / (2.0 * J.e), Q.radius,
-                                trial_hist_lo(Q.radius), J.hist[2], J.lflag, st));
-  }
+  return HPEZ_OK;
+}
+
+template <typename T>
+int t_lorenzo(TJob<T>& J, hipStream_t st)
+{
+  if (J.done || !J.lorenzo_trial) return HPEZ_OK;
+  TCK(launch_lorenzo_trial<T>(J.g, J.d_gb, (uint32_t)J.gb.size(), (uint32_t)J.gcap, J.X,
+                              1.0 / (2.0 * J.e), J.Q.radius, trial_hist_lo(J.Q.radius), J.hist[2],
+                              J.lflag, st));
   return HPEZ_OK;
 }
 
@@ -649,6 +684,83 @@ int t_hist_copy(TJob<T>& J, hipStream_t st)
 }
 
 // phase 5: freeze and Lorenzo decisions, then the block-wise trials (Sec. 6.6)
+// the block-wise trials of variant `frozen`: boxes staged in the pinned
+// block-score area (read only after the phase's synchronization) and queued for
+// upload on st, arguments in J.ba.  Nothing is queued when `need_tables` is set
+// and the trials would not run from the job tables (they would use the shared
+// scratch area); *ok tells which.
+template <typename T>
+int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool need_tables,
+                 bool* ok)
+{
+  const hpez_field_desc* d = J.d;
+  const hpez_tune_opts* o = J.o;
+  *ok = false;
+  const Geom& g = J.g;
+  const Geom gf = make_geom(d, frozen);
+  const int64_t B = J.B;
+  int64_t nb[4];
+  for (int k = 0; k < 4; k++) nb[k] = (g.n[k] + B - 1) / B;
+  const int nact = n_active(gf);
+  const int64_t side = sub_side(B, o->sub_rate, nact > 0 ? nact : 1);
+  int64_t As = 1;
+  int al = 0;
+  while (As * 2 <= side - 1) {
+    As *= 2;
+    al++;
+  }
+  static_assert(sizeof(unsigned long long) * kNCand >= sizeof(TrialBox), "box staging");
+  TrialBox* bx = reinterpret_cast<TrialBox*>(J.h_bscore);
+  uint64_t cap = 0;
+  for (int64_t bi = 0; bi < J.nbt; bi++) {
+    int64_t b[4];
+    unravel(bi, nb, b);
+    uint64_t pts = 1;
+    for (int k = 0; k < 4; k++) {
+      const int64_t ext = g.n[k] - b[k] * B < B ? g.n[k] - b[k] * B : B;
+      bx[bi].m[k] = g.n[k] > 1 ? (side < ext ? side : ext) : 1;
+      bx[bi].o[k] = b[k] * B + (ext - bx[bi].m[k]) / 2;
+      pts *= (uint64_t)bx[bi].m[k];
+    }
+    cap = std::max(cap, pts);
+  }
+  if ((size_t)J.nbt * kNCand * cap * sizeof(T) > J.scratch_bytes && cap * sizeof(T) > kTrialLdsBytes)
+    return need_tables ? HPEZ_OK : HPEZ_ENOMEM;
+  TrialArgs& a = J.ba;
+  std::memset(&a, 0, sizeof a);
+  a.fg = g;
+  a.frozen = frozen;
+  a.L = al;
+  a.R = J.Q.radius;
+  a.score_mode = 1;
+  a.box_cap = cap;
+  a.max_ext = (int32_t)side;
+  a.score_mul = 4096.0 / J.e;
+  fill_levels(a, J.e, &J.Q);
+  for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
+  if (need_tables && !trial_box_ok<T>(a, false)) return HPEZ_OK;
+  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, (size_t)J.nbt * sizeof(TrialBox), hipMemcpyHostToDevice,
+                     st));
+  t_add<T>(tb, a, J.d_bb, (uint32_t)J.nbt, kNCand, J.X, (T*)J.scratch, J.wq, J.bscore, nullptr);
+  *ok = true;
+  return HPEZ_OK;
+}
+
+// Block-wise trials queued ahead on the second stream.  With one global
+// variant (no freeze candidate) they depend only on the statistics phase: the
+// later phases decide only whether their scores are used (not when the Lorenzo
+// predictor wins).
+template <typename T>
+int t_blocks_ahead(TJob<T>& J, TrialBatch<T>& tb, hipStream_t side)
+{
+  if (J.done || J.nvar != 1 || !J.o->block_wise || !J.nbt) return HPEZ_OK;
+  bool ok = false;
+  const int rc = t_block_args(J, -1, tb, side, true, &ok);
+  if (rc) return rc;
+  J.spec = ok;
+  return HPEZ_OK;
+}
+
 template <typename T>
 int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
 {
@@ -666,67 +778,17 @@ int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
   J.frozen = (J.nvar == 2 && J.H[1] < J.H[0]) ? J.fcand : -1;
   const double Hbest = J.frozen >= 0 ? J.H[1] : J.H[0];
   J.lorenzo = false;
-  if (J.lorenzo_trial) {
-    double HL;
-    if ((rc = t_entropy(J, 2, st, &HL))) return rc;
-    if (*J.h_lflag == 0 && o->lorenzo_coef * HL < Hbest) J.lorenzo = true;
-  }
+  if (J.lorenzo_trial && *J.h_lflag == 0 && o->lorenzo_coef * J.HL < Hbest) J.lorenzo = true;
   J.blocks = !J.lorenzo && o->block_wise;
-  if (!J.blocks) return HPEZ_OK;
-  const Geom& g = J.g;
-  const Geom gf = make_geom(d, J.frozen);
-  const int64_t B = J.B;
-  int64_t nb[4];
-  for (int k = 0; k < 4; k++) nb[k] = (g.n[k] + B - 1) / B;
-  const int nact = n_active(gf);
-  const int64_t side = sub_side(B, o->sub_rate, nact > 0 ? nact : 1);
-  int64_t As = 1;
-  int al = 0;
-  while (As * 2 <= side - 1) {
-    As *= 2;
-    al++;
-  }
-  // the boxes are built in the pinned block-score area (read only after this
-  // phase's synchronization)
-  static_assert(sizeof(unsigned long long) * kNCand >= sizeof(TrialBox), "box staging");
-  TrialBox* bx = reinterpret_cast<TrialBox*>(J.h_bscore);
-  uint64_t cap = 0;
-  for (int64_t bi = 0; bi < J.nbt; bi++) {
-    int64_t b[4];
-    unravel(bi, nb, b);
-    uint64_t pts = 1;
-    for (int k = 0; k < 4; k++) {
-      const int64_t ext = g.n[k] - b[k] * B < B ? g.n[k] - b[k] * B : B;
-      bx[bi].m[k] = g.n[k] > 1 ? (side < ext ? side : ext) : 1;
-      bx[bi].o[k] = b[k] * B + (ext - bx[bi].m[k]) / 2;
-      pts *= (uint64_t)bx[bi].m[k];
-    }
-    cap = std::max(cap, pts);
-  }
-  if ((size_t)J.nbt * kNCand * cap * sizeof(T) > J.scratch_bytes && cap * sizeof(T) > kTrialLdsBytes)
-    return HPEZ_ENOMEM;
-  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, (size_t)J.nbt * sizeof(TrialBox), hipMemcpyHostToDevice,
-                     st));
-  TrialArgs& a = J.ba;
-  std::memset(&a, 0, sizeof a);
-  a.fg = g;
-  a.frozen = J.frozen;
-  a.L = al;
-  a.R = J.Q.radius;
-  a.score_mode = 1;
-  a.box_cap = cap;
-  a.max_ext = (int32_t)side;
-  a.score_mul = 4096.0 / J.e;
-  fill_levels(a, J.e, &J.Q);
-  for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
-  t_add<T>(tb, a, J.d_bb, (uint32_t)J.nbt, kNCand, J.X, (T*)J.scratch, J.wq, J.bscore, nullptr);
-  return HPEZ_OK;
+  if (!J.blocks || J.spec) return HPEZ_OK;
+  bool ok = false;
+  return t_block_args(J, J.frozen, tb, st, false, &ok);
 }
 
 template <typename T>
 int t_blocks_copy(TJob<T>& J, hipStream_t st)
 {
-  if (J.done || !J.blocks) return HPEZ_OK;
+  if (J.done || !J.blocks || J.spec) return HPEZ_OK;
   TCK(hipMemcpyAsync(J.h_bscore, J.bscore, (size_t)J.nbt * kNCand * sizeof(unsigned long long),
                      hipMemcpyDeviceToHost, st));
   return HPEZ_OK;
@@ -772,15 +834,30 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
   // trial tables: two global variants per job is the most of any phase
   const size_t tab_cap = al256(2 * jobs.size() * sizeof(TrialJob<T>)) * 3 +
                          3 * al256((2 * jobs.size() + 1) * 8) + 512;
-  dev += tab_cap;
+  // (a second table, device and pinned staging, for the block trials queued ahead)
+  dev += 2 * tab_cap;
+  pin += tab_cap;
   int rc;
   uint8_t* base = (uint8_t*)ctx_ws(ctx, dev, &rc);
   if (rc) return rc;
-  uint8_t* pbase = ctx_pin(ctx, pin ? pin : 256, &rc);
+  uint8_t* pbase = ctx_pin(ctx, pin, &rc);
   if (rc) return rc;
   Take dw{base}, pw{pbase};
   uint8_t* d_tab = dw.take<uint8_t>(tab_cap);
+  uint8_t* d_tab2 = dw.take<uint8_t>(tab_cap);
+  uint8_t* h_tab2 = pw.take<uint8_t>(tab_cap);
   for (auto& J : jobs) t_take(J, dw, pw);
+  // whatever way this function returns, the caller's stream waits for the
+  // work queued on the second stream
+  struct Join {
+    hpez_ctx* c;
+    hipStream_t st;
+    bool on = false;
+    ~Join()
+    {
+      if (on) (void)ctx_join(c, st);
+    }
+  } join{ctx, st};
 
   for (auto& J : jobs)
     if ((rc = t_minmax(J, st))) return rc;
@@ -795,6 +872,27 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     TrialBatch<T> tb;
     for (auto& J : jobs)
       if ((rc = t_global(J, tb, st))) return rc;
+    bool ahead = false;
+    for (auto& J : jobs) ahead |= !J.done && J.nvar == 1 && J.o->block_wise && J.nbt > 0;
+    hipStream_t side = ahead ? ctx_fork(ctx, st) : nullptr;
+    if (side) {
+      join.on = true;
+      TrialBatch<T> sb;
+      for (auto& J : jobs)
+        if ((rc = t_blocks_ahead(J, sb, side))) return rc;
+      hipEvent_t evb = ctx_span_begin(ctx, side);
+      if ((rc = t_launch(ctx, sb, false, d_tab2, tab_cap, side, h_tab2))) return rc;
+      uint64_t bb = 0;
+      for (auto& J : jobs)
+        if (J.spec) {
+          bb += (uint64_t)J.nbt * J.ba.box_cap * sizeof(T);
+          TCK(hipMemcpyAsync(J.h_bscore, J.bscore, (size_t)J.nbt * kNCand * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, side));
+        }
+      ctx_span_end(ctx, evb, "tune_block_trials", bb, side);
+    }
+    for (auto& J : jobs)
+      if ((rc = t_lorenzo(J, st))) return rc;
     hipEvent_t ev = ctx_span_begin(ctx, st);
     if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
     uint64_t bytes = 0;
@@ -812,6 +910,10 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     if ((rc = t_launch(ctx, tb, true, d_tab, tab_cap, st))) return rc;
     for (auto& J : jobs)
       if ((rc = t_hist_copy(J, st))) return rc;
+    // the Lorenzo trial's entropy (its pairs arrived with the last phase)
+    // while the device runs this one
+    for (auto& J : jobs)
+      if (!J.done && J.lorenzo_trial && (rc = t_entropy(J, 2, st, &J.HL))) return rc;
   }
   TCK(hipStreamSynchronize(st));
   {
@@ -822,10 +924,14 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
     uint64_t bytes = 0;
     for (auto& J : jobs)
-      if (!J.done && J.blocks) bytes += (uint64_t)J.nbt * J.ba.box_cap * sizeof(T);
+      if (!J.done && J.blocks && !J.spec) bytes += (uint64_t)J.nbt * J.ba.box_cap * sizeof(T);
     ctx_span_end(ctx, ev, "tune_block_trials", bytes, st);
     for (auto& J : jobs)
       if ((rc = t_blocks_copy(J, st))) return rc;
+  }
+  if (join.on) {
+    join.on = false;
+    if ((rc = ctx_join(ctx, st))) return rc;
   }
   TCK(hipStreamSynchronize(st));
   for (auto& J : jobs) t_finish(J);
@@ -880,7 +986,7 @@ uint64_t tune_footprint(const hpez_field_desc* d, const hpez_config* c)
   t_init(J);
   const size_t s = d->dtype ? 8 : 4;
   J.scratch_bytes = trial_scratch(J.g, &o, s, J.gb.size(), J.gcap, J.nbt);
-  return t_dev_bytes(J) + 3 * al256(2 * sizeof(TrialJob<double>)) + 3 * al256(3 * 8) + 512;
+  return t_dev_bytes(J) + 2 * (3 * al256(2 * sizeof(TrialJob<double>)) + 3 * al256(3 * 8) + 512);
 }
 }  // namespace hpez
 

@@ -45,6 +45,12 @@ CASES = [
      dict(global_rate=0.3)),
     ("2d", lambda: fields.turbulence_field((300, 257), 3), 1e-3, dict(global_rate=0.2)),
     ("constant", lambda: np.full((20, 30, 40), 1.5, np.float32), 1e-3, dict()),
+    # one global variant: the block-wise trials are queued ahead of the later
+    # phases' decisions (kept when the interpolator wins, dropped otherwise)
+    ("nofreeze-blocks", lambda: fields.fronts_field((64, 96, 80)), 1e-3,
+     dict(global_rate=0.2, allow_freeze=0)),
+    ("nofreeze-lorenzo", lambda: fields.random_field((48, 40, 56), 9, np.float32, "rough"), 1e-4,
+     dict(global_rate=0.3, lorenzo_coef=0.5, allow_freeze=0)),
 ]
 
 
