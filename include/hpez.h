@@ -142,7 +142,11 @@ typedef struct hpez_ctx hpez_ctx;
 const char* hpez_strerror(int code);
 
 /* Create a context bound to GPU `device`; it owns a growable device workspace
- * and the per-device scratch state.  Destroy releases everything. */
+ * and the per-device scratch state.  On first use it also creates a second
+ * HIP stream (default priority) for work that can overlap the caller's
+ * stream; that work is forked from and joined back to the caller's stream with
+ * events inside each call, so ordering on the caller's stream is as if
+ * everything ran there.  Destroy releases everything. */
 int hpez_ctx_create(hpez_ctx** out, int device);
 void hpez_ctx_destroy(hpez_ctx* ctx);
 
