@@ -198,3 +198,31 @@ def test_block_fast_2d_f64(torch_cuda):
     bc = (np.arange(nb) * 3 % 11).astype(np.uint8)
     roundtrip(torch_cuda, x, make_cfg(x.shape, dtype="f64", eb=1e-4, anchor_log2=7, block_log2=5,
                                       cand=cand, block_cfg=bc, kind="nat", md=1), "fast 2d f64")
+
+
+def test_caller_stream(torch_cuda):
+    """Every call on a caller-created stream (not the current one): the work the
+    library queues on its own second stream (coarse block levels, block-wise
+    tuner trials) is ordered by that stream; results equal the oracle's."""
+    torch = torch_cuda
+    from paper_2311_12133_amd import binding
+    shape = (96, 64, 128)
+    x = fields.fronts_field(shape)
+    print(f"[case] caller stream shape={shape}", flush=True)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    opts = dict(global_rate=0.2, allow_freeze=0)
+    cfg = make_cfg(shape, eb=1e-3)
+    ref_cfg, _ = O.tune(x, cfg, opts)
+    with torch.cuda.stream(st):
+        got_cfg = binding.tune(xt, cfg, opts, stream=st)
+        s = binding.compress(xt, got_cfg, stream=st)
+        y = binding.decompress(s, stream=st)
+    st.synchronize()
+    for k in ("predictor", "frozen_dim", "levels", "cand"):
+        assert got_cfg[k] == ref_cfg[k], k
+    assert np.array_equal(got_cfg["block_cfg"], ref_cfg["block_cfg"])
+    ref = O.compress(x, ref_cfg)
+    assert s.cpu().numpy().tobytes() == ref
+    assert np.array_equal(y.cpu().numpy().view(np.uint8), O.decompress(ref).view(np.uint8))
