@@ -97,6 +97,8 @@ def lib():
         L.orc_stats.argtypes = [vp, P(Params), C.c_double, vp, P(i64)]
         L.orc_tune.argtypes = [vp, P(Params), P(TuneOpts), P(Params), vp, P(TuneReport)]
         L.orc_candidates.argtypes = [C.c_int, vp]
+        L.orc_entropy_bits.argtypes = [vp, C.c_uint32]
+        L.orc_entropy_bits.restype = C.c_double
         L.orc_stream_order.argtypes = [P(u64), C.c_int, vp]
         _lib = L
     return _lib
@@ -368,6 +370,13 @@ def tune(x: np.ndarray, cfg: dict, opts: dict):
                   H=(rep.H[0], rep.H[1]), H_lorenzo=rep.H_lorenzo, frozen=rep.frozen,
                   lorenzo=rep.lorenzo)
     return out, report
+
+
+def entropy_bits(hist) -> float:
+    """The tuner's size estimate (Sec. 6.3 / 6.5): bits per symbol of a code
+    histogram."""
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return float(lib().orc_entropy_bits(_ptr(h), h.size))
 
 
 def stream_order(dims) -> np.ndarray:

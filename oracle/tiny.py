@@ -56,6 +56,10 @@ class Tiny:
         self.strides = [int(np.prod(self.shape[d + 1:])) for d in range(4)]
         self.rng = random.Random(seed)
         self.K6, self.K40, self.K62 = _consts(self.T)
+        # optional tuner score (Sec. 6.2): per level, the sum of
+        # floor(|x - p| * 4096 / e) over the predicted points, capped at 2^32
+        self.score = None
+        self.level = 0
 
     def idx(self, c):
         return sum(c[d] * self.strides[d] for d in range(4))
@@ -126,6 +130,10 @@ class Tiny:
                 self.W[i] = self.T(float(p) + float(q - self.R) * self.twoe)
         else:
             xv = self.x[i]
+            if self.score is not None:
+                u = abs(float(xv) - float(p)) * (4096.0 / self.e)
+                self.score[self.level] = self.score.get(self.level, 0) + (
+                    math.floor(u) if u < 4294967296.0 else 4294967296)
             t = (float(xv) - float(p)) * self.inv2e
             qf = math.floor(abs(t) + 0.5) if math.isfinite(t) else math.inf
             ok = qf < self.R
@@ -209,6 +217,7 @@ class Tiny:
         ghi = [n[d] - 1 for d in range(4)]
         for l in range(L, 0, -1):
             s = 1 << (l - 1)
+            self.level = l
             self.el = level_eb(self.e, cfg.get("alpha", 1.0), cfg.get("beta", 1.0), l)
             self.inv2e = 1.0 / (2.0 * self.el)
             self.twoe = 2.0 * self.el
