@@ -21,20 +21,12 @@ namespace hpez {
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
-// Division of any 32-bit n by d >= 2 as (t + ((n - t) >> 1)) >> (l - 1),
-// t = mulhi(m, n), l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1
-// (Granlund and Montgomery, round-up multiplier); d <= 1 gives shift -1.
+// exact division multipliers for the kernels' index arithmetic (xmagic)
 static void div_magic32(uint32_t d, uint32_t* m, int32_t* sh)
 {
-  if (d <= 1) {
-    *m = 0;
-    *sh = -1;
-    return;
-  }
-  int l = 0;
-  while ((1ull << l) < d) l++;
-  *m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
-  *sh = l - 1;
+  const XDivisor x = xmagic(d);
+  *m = x.m;
+  *sh = x.sh;
 }
 constexpr size_t kPlaneLdsBytes = 150 * 1024;  // a plane lattice in the plane kernel
 

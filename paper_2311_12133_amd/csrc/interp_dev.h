@@ -175,6 +175,29 @@ __device__ __forceinline__ Divisor fmagic(uint32_t d)
 // branch-free: one multiply-high, one and, one add
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, Divisor d) { return __umulhi(n, d.m) + (n & d.pass); }
 
+// Exact n / d for every 32-bit n and d >= 1 (Granlund and Montgomery's
+// round-up multiplier with a shift): q = (t + ((n - t) >> 1)) >> (l - 1) with
+// t = mulhi(m, n), l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1; d <= 1
+// passes n through (shift -1).  The multiplier needs one 64-bit division, so it
+// is made once per work-group or on the host.
+struct XDivisor {
+  uint32_t m;
+  int32_t sh;
+};
+__host__ __device__ __forceinline__ XDivisor xmagic(uint32_t d)
+{
+  if (d <= 1) return {0u, -1};
+  int l = 0;
+  while ((1ull << l) < d) l++;
+  return {(uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1), l - 1};
+}
+__host__ __device__ __forceinline__ uint32_t xdiv(uint32_t n, XDivisor d)
+{
+  if (d.sh < 0) return n;
+  const uint32_t t = (uint32_t)(((uint64_t)d.m * n) >> 32);  // multiply-high
+  return (t + ((n - t) >> 1)) >> d.sh;
+}
+
 // Histogram update for every lane with `valid`: lanes holding equal codes are
 // counted together (one atomic per distinct code in the wavefront), into the
 // LDS window [lo, lo + win) or the global table outside it.

@@ -342,12 +342,10 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
 // same values); each plane writes its own family's face array, and codes only
 // of the points whose lowest family it is.
 
-// n / d with a host-computed magic multiplier (shift -1: d <= 1)
+// n / d with a host-computed exact multiplier (shift -1: d <= 1)
 __device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t m, int32_t sh)
 {
-  if (sh < 0) return n;
-  const uint32_t t = __umulhi(m, n);
-  return (t + ((n - t) >> 1)) >> sh;
+  return xdiv(n, XDivisor{m, sh});
 }
 
 template <typename T>

@@ -548,16 +548,16 @@ __global__ void __launch_bounds__(256) lorenzo_trial_kernel(Geom fg, const Trial
     hist_add_wave(lh, hist, hist_lo, kTrialHistWin, code, true);
   };
   const uint64_t np = (uint64_t)bx.m[0] * bx.m[1] * bx.m[2] * bx.m[3];
-  if (np < (1ull << 31) && bx.m[1] <= (int64_t)kMagicMax && bx.m[2] <= (int64_t)kMagicMax &&
-      bx.m[3] <= (int64_t)kMagicMax) {
-    // 32-bit coordinates by multiply-high division
+  if (np <= (1ull << 31)) {
+    // 32-bit coordinates by exact multiply-high division (index + grid stride
+    // stays below 2^32)
     const uint32_t npts = (uint32_t)np;
     const uint32_t m1 = (uint32_t)bx.m[1], m2 = (uint32_t)bx.m[2], m3 = (uint32_t)bx.m[3];
-    const Divisor d1 = fmagic(m1), d2 = fmagic(m2), d3 = fmagic(m3);
+    const XDivisor d1 = xmagic(m1), d2 = xmagic(m2), d3 = xmagic(m3);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x) {
-      const uint32_t q3 = fdiv(i, d3), x3 = i - q3 * m3;
-      const uint32_t q2 = fdiv(q3, d2), x2 = q3 - q2 * m2;
-      const uint32_t x0 = fdiv(q2, d1), x1 = q2 - x0 * m1;
+      const uint32_t q3 = xdiv(i, d3), x3 = i - q3 * m3;
+      const uint32_t q2 = xdiv(q3, d2), x2 = q3 - q2 * m2;
+      const uint32_t x0 = xdiv(q2, d1), x1 = q2 - x0 * m1;
       const int64_t x[4] = {x0, x1, x2, x3};
       point(x);
     }

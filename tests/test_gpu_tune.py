@@ -51,6 +51,10 @@ CASES = [
      dict(global_rate=0.2, allow_freeze=0)),
     ("nofreeze-lorenzo", lambda: fields.random_field((48, 40, 56), 9, np.float32, "rough"), 1e-4,
      dict(global_rate=0.3, lorenzo_coef=0.5, allow_freeze=0)),
+    # blocks of 256: one 257^3 region of 17M points, whose Lorenzo-trial
+    # coordinates need the exact division for dividends beyond 2^24
+    ("blocks256", lambda: fields.fronts_field((257, 260, 258)), 1e-3,
+     dict(global_rate=1.0, sub_rate=0.04, block_log2=8)),
 ]
 
 
