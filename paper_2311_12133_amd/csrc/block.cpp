@@ -359,8 +359,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   const size_t off_wg = al(ent * sizeof(FaceEntry<T>));
   const size_t off_jobs = off_wg + al((ent + slots) * 8);
   const size_t off_begin = off_jobs + al(n * sizeof(BlockJobDev<T>));
-  const size_t off_ticket = off_begin + al((n + 1) * 8);
-  const size_t off_planes = off_ticket + 256;
+  const size_t off_planes = off_begin + al((n + 1) * 8);
   const size_t off_pwg = off_planes + al(3 * (size_t)n * sizeof(PlaneJob<T>));
   const size_t bytes = off_pwg + al((3 * (size_t)n + 1) * 8);
   std::memset(h_tables, 0, bytes);
@@ -484,7 +483,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
     return HPEZ_EDEVICE;
   ev = ctx_span_begin(ctx, st);
   BCK(launch_block_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
-                           n, total_blocks, lds, (uint32_t*)(dt + off_ticket), n_cu, mode, st));
+                           n, total_blocks, lds, n_cu, mode, st));
   ctx_span_end(ctx, ev, mode == 0 ? "blocks_predict" : "blocks_reconstruct",
                npts * (sizeof(T) + 2), st);
   return HPEZ_OK;

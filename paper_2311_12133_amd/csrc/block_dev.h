@@ -118,7 +118,7 @@ hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_beg
 // (d_begin[n] = total); lds = largest box of the jobs
 template <typename T>
 hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
-                             uint64_t total_blocks, size_t lds, uint32_t* ticket, int n_cu,
+                             uint64_t total_blocks, size_t lds, int n_cu,
                              int mode, hipStream_t st);
 
 // the coarse levels of every block of jobs [0, n) on the block lattices

@@ -21,6 +21,7 @@
 
 #include "block_dev.h"
 #include "box_dev.h"
+#include "fblock_dev.h"
 #include "interp_dev.h"
 
 namespace hpez {
@@ -806,6 +807,7 @@ template <typename T, int MODE>
 __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL T* __restrict__ X, int64_t st0,
                                              int64_t st1, const Block3& bk, const Box& bx,
                                              const BoxItems& bi, uint32_t it, bool vec,
+                                             bool fast, const HPEZ_GLOBAL uint16_t* bcode,
                                              int32_t& lbase, uint32_t& wr)
 {
   Quad<T> v;
@@ -820,7 +822,8 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL
   const int32_t cb = 4 * (int32_t)(rr - (uint32_t)c1 * bi.nq);
   const int32_t cnt = bi.E2 - cb < 4 ? bi.E2 - cb : 4;
   const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + cb;
-  lbase = (c0 * bi.E1 + c1) * bi.E2 + cb;
+  // row-major box, or the parity-split slots of a full block (cb even)
+  lbase = fast ? fslot(c0) * kFP0 + fslot(c1) * kFP1 + (cb >> 1) : (c0 * bi.E1 + c1) * bi.E2 + cb;
   const bool face0 = bx.a0 && (c0 == 0 || c0 == kBrick);
   const bool face1 = !face0 && bx.a1 && (c1 == 0 || c1 == kBrick);
   const HPEZ_GLOBAL T* src = nullptr;
@@ -832,6 +835,15 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL
   else if (MODE == 0 && cb < kBrick) {
     src = X + x0 * st0 + x1 * st1 + x2;  // (cell c2 = 32 is the next block's face value)
     once = true;
+  }
+  if (MODE == 1 && fast && !src && cb < kBrick) {
+    // decompressing a full block: the interior rows' cells take the points'
+    // codes (as raw bits) until the points are reconstructed
+    const uint64_t cw =
+        *reinterpret_cast<const HPEZ_GLOBAL uint64_t*>(bcode + (c0 * kBrick + c1) * kBrick + cb);
+#pragma unroll
+    for (int j = 0; j < 4; j++) v.v[j] = (T)__uint_as_float((uint32_t)(cw >> (16 * j)) & 0xFFFFu);
+    wr = 0xFu;
   }
   if (src) {
     wr = (1u << cnt) - 1u;
@@ -855,36 +867,69 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL
 }
 
 template <typename T>
-__device__ __forceinline__ void store_item(T* L, const Quad<T>& v, int32_t lbase, uint32_t wr)
+__device__ __forceinline__ void store_item(T* L, const Quad<T>& v, int32_t lbase, uint32_t wr,
+                                           bool fast)
 {
+  // full blocks: cells cb, cb + 2 at even slots cb / 2, cb / 2 + 1; cb + 1, cb + 3
+  // at odd slots 17 + cb / 2, 18 + cb / 2
 #pragma unroll
   for (int j = 0; j < 4; j++)
-    if (wr >> j & 1u) L[lbase + j] = v.v[j];
+    if (wr >> j & 1u) L[lbase + (fast ? (j >> 1) + 17 * (j & 1) : j)] = v.v[j];
+}
+
+// stream position of a brick's first point (all earlier bricks are full along
+// the dims before the last partial one)
+__device__ __forceinline__ uint64_t brick_start(const Geom& g, const Block3& bk)
+{
+  return (uint64_t)(bk.o0 * g.n[1] * g.n[2] + bk.Eb0 * bk.o1 * g.n[2] + bk.Eb0 * bk.Eb1 * bk.o2);
+}
+
+// a block whose levels below the lattice take the full-block schedule
+__device__ __forceinline__ bool full_block(const Block3& bk, const Box& bx)
+{
+  return bx.a0 && bx.a1 && bx.a2 && bk.Eb0 == kBrick && bk.Eb1 == kBrick && bk.Eb2 == kBrick;
+}
+
+// the LDS histogram window of job J into its histogram
+template <typename T>
+__device__ __forceinline__ void hist_flush(const uint32_t* lh, const BlockJobDev<T>& J, int nt)
+{
+  HPEZ_GLOBAL uint32_t* hist = gmem(J.hist);
+  const uint32_t lo = J.a.hist_lo;
+  for (int i = threadIdx.x; i < kBlockHistWin; i += nt)
+    if (lh[i]) __hip_atomic_fetch_add(&hist[lo + i], lh[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Persistent work-groups (one per CU): blocks are taken from a counter; for
 // float boxes the next block's loads are issued before the current block's
 // levels, so they complete while it computes.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<T>* __restrict__ jobs,
+__global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobDev<T>* __restrict__ jobs,
                                                               const uint64_t* __restrict__ begin,
                                                               int njobs,
-                                                              uint32_t* __restrict__ ticket)
+                                                              uint32_t lh_off)
 {
   constexpr int NT = kBlockThreads;
   constexpr bool PREF = sizeof(T) == 4;
   constexpr int UP = PREF ? (33 * 33 * 9 + NT - 1) / NT : 1;  // items per lane held across a block
   extern __shared__ unsigned char lds_raw[];
-  __shared__ uint32_t s_next;
   T* L = reinterpret_cast<T*>(lds_raw);
   const uint64_t nbt = begin[njobs];
+  // compress: the LDS histogram window sits after the largest box of the
+  // launch and accumulates every block of one job the work-group takes;
+  // its counts reach the job's histogram when the work-group moves to
+  // another job or ends (one flush per work-group instead of one per block)
+  uint32_t* lh = reinterpret_cast<uint32_t*>(lds_raw + lh_off);
+  int hjob = -1;
 
-  if (threadIdx.x == 0) s_next = atomicAdd(ticket, 1u);
-  __syncthreads();
-  uint64_t gbi = __builtin_amdgcn_readfirstlane(s_next);
+  // blocks are dealt round-robin: work-group w takes w, w + G, w + 2G, ...
+  // (G work-groups; blocks cost about the same, and no counter round trip
+  // stands between two blocks)
+  uint64_t gbi = blockIdx.x;
   Quad<T> pv[UP];
   int32_t plb[UP];
   uint32_t pwr[UP];
+  T pcv = (T)0;  // the lane's first lattice value of the next block
   if (PREF && gbi < nbt) {
     const int j = find_entry(begin, njobs, gbi);
     const BlockJobDev<T>& J = jobs[j];
@@ -892,15 +937,20 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
     Box bx;
     block_geometry(J.a.g, (int64_t)(gbi - begin[j]), J.a.nb, bk, bx);
     const BoxItems its = box_items(bx);
+    const bool fast1 = full_block(bk, bx);
 #pragma unroll
     for (int u = 0; u < UP; u++)
       pv[u] = load_item<T, MODE>(J.f, gmem(J.X), J.a.g.st[0], J.a.g.st[1], bk, bx, its,
-                                 threadIdx.x + u * NT, J.a.vec != 0, plb[u], pwr[u]);
+                                 threadIdx.x + u * NT, J.a.vec != 0, fast1,
+                                 gmem(J.code) + brick_start(J.a.g, bk), plb[u], pwr[u]);
+    Box lb1;
+    lattice_box(bx, lb1);
+    if (threadIdx.x < (uint32_t)(lb1.E0 * lb1.b0))
+      pcv = gmem(J.cval)[(gbi - begin[j]) * kCoarseCells + threadIdx.x];
   }
 
   while (gbi < nbt) {
-    __syncthreads();  // every lane has read s_next; the previous block is done with LDS
-    if (threadIdx.x == 0) s_next = atomicAdd(ticket, 1u);
+    __syncthreads();  // the previous block is done with LDS
     const int jb = find_entry(begin, njobs, gbi);
     const BlockJobDev<T>& J = jobs[jb];
     const BlockArgs& a = J.a;
@@ -917,19 +967,25 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
     Block3 bk;
     Box bx;
     block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
+    const bool fast = PREF && full_block(bk, bx);
     // stream position of the brick's first point (all earlier bricks are full
     // along the dims before the last partial one)
-    const uint64_t brick_base = (uint64_t)(bk.o0 * a.g.n[1] * a.g.n[2] +
-                                           bk.Eb0 * bk.o1 * a.g.n[2] + bk.Eb0 * bk.Eb1 * bk.o2);
-    const uint32_t nbox = (uint32_t)bx.E0 * bx.b0;
-    uint32_t* lh = reinterpret_cast<uint32_t*>(lds_raw + ((nbox * sizeof(T) + 15) & ~(size_t)15));
+    const uint64_t brick_base = brick_start(a.g, bk);
+    // a full block's slots span 33 per dim whatever its box extents
+    const uint32_t nbox = fast ? (uint32_t)(33 * kFP0) : (uint32_t)bx.E0 * bx.b0;  // <= lh_off / sizeof(T)
+    (void)nbox;
     const int32_t E1 = bx.E1, E2 = bx.E2, Eb1 = bk.Eb1, Eb2 = bk.Eb2;
-    if (MODE == 0)
+    if (MODE == 0 && jb != hjob) {
+      // the window holds another job's counts: flush them (each lane its own
+      // entries, so no barrier between the flush and the clear)
+      if (hjob >= 0) hist_flush(lh, jobs[hjob], NT);
       for (uint32_t i = threadIdx.x; i < (uint32_t)kBlockHistWin; i += NT) lh[i] = 0;
+      hjob = jb;
+    }
     // ---- the box into LDS
     if (PREF) {
 #pragma unroll
-      for (int u = 0; u < UP; u++) store_item<T>(L, pv[u], plb[u], pwr[u]);
+      for (int u = 0; u < UP; u++) store_item<T>(L, pv[u], plb[u], pwr[u], fast);
     } else {
       const BoxItems its = box_items(bx);
       constexpr int UL = 4;
@@ -939,9 +995,10 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         uint32_t wr[UL];
 #pragma unroll
         for (int u = 0; u < UL; u++)
-          v[u] = load_item<T, MODE>(f, X, st0, st1, bk, bx, its, ib + u * NT, vec, lb[u], wr[u]);
+          v[u] = load_item<T, MODE>(f, X, st0, st1, bk, bx, its, ib + u * NT, vec, false, nullptr,
+                                    lb[u], wr[u]);
 #pragma unroll
-        for (int u = 0; u < UL; u++) store_item<T>(L, v[u], lb[u], wr[u]);
+        for (int u = 0; u < UL; u++) store_item<T>(L, v[u], lb[u], wr[u], false);
       }
     }
     // the lattice cells hold the coarse levels' results
@@ -958,7 +1015,11 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         const uint32_t r = i - q0 * (uint32_t)lb.b0;
         const uint32_t q1 = fdiv(r, mlE2);
         const uint32_t q2 = r - q1 * (uint32_t)lb.E2;
-        L[((int32_t)q0 * lk0 * E1 + (int32_t)q1 * lk1) * E2 + (int32_t)q2 * lk2] = cv[i];
+        T v;
+        if (PREF && i == threadIdx.x) v = pcv;  // prefetched with the box
+        else v = cv[i];
+        L[fast ? 2 * ((int32_t)q0 * kFP0 + (int32_t)q1 * kFP1 + (int32_t)q2)
+               : ((int32_t)q0 * lk0 * E1 + (int32_t)q1 * lk1) * E2 + (int32_t)q2 * lk2] = v;
       }
     }
     // compress: the codes of the brick's own faces (c_d = 0 on an active dim)
@@ -1005,7 +1066,7 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
       }
     }
     __syncthreads();
-    const uint64_t bn = __builtin_amdgcn_readfirstlane(s_next);
+    const uint64_t bn = gbi + gridDim.x;
     if (PREF && bn < nbt) {
       // the next block's loads, in flight during this block's levels
       const int j2 = find_entry(begin, njobs, bn);
@@ -1014,15 +1075,38 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
       Box bx2;
       block_geometry(J2.a.g, (int64_t)(bn - begin[j2]), J2.a.nb, bk2, bx2);
       const BoxItems its2 = box_items(bx2);
+      const bool fast2 = full_block(bk2, bx2);
 #pragma unroll
       for (int u = 0; u < UP; u++)
         pv[u] = load_item<T, MODE>(J2.f, gmem(J2.X), J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,
-                                   threadIdx.x + u * NT, J2.a.vec != 0, plb[u], pwr[u]);
+                                   threadIdx.x + u * NT, J2.a.vec != 0, fast2,
+                                   gmem(J2.code) + brick_start(J2.a.g, bk2), plb[u], pwr[u]);
+      Box lb2;
+      lattice_box(bx2, lb2);
+      if (threadIdx.x < (uint32_t)(lb2.E0 * lb2.b0))
+        pcv = gmem(J2.cval)[(bn - begin[j2]) * kCoarseCells + threadIdx.x];
     }
+    // compress: the lane's first lattice code, stored after the levels
+    uint32_t pcc = 0;
+    if (MODE == 0 && threadIdx.x < nlat) pcc = gmem(J.ccode)[bi * kCoarseCells + threadIdx.x];
 
     // ---- the levels below B with the block's configuration
     const hpez_interp c = a.cand[gmem(J.bcfg)[bi]];
     uint32_t nR = 0;
+    if constexpr (PREF) {
+      if (fast) {
+        FBlock<T> fb{L,         code + brick_base, out,       lh,  hist, bk.o0, bk.o1, bk.o2, st0, st1,
+                     bx.E0 - 1, bx.E1 - 1,         bx.E2 - 1, a.R, lo,   0.0,   0.0,   0.0,   0u};
+        for (int l = a.L < kCoarseL ? a.L : kCoarseL; l >= 1; l--) {
+          fb.el = a.el_l[l];
+          fb.inv2e = a.inv2e_l[l];
+          fb.twoe = a.twoe_l[l];
+          flevel<T, MODE, NT>(c, fb, 1 << (l - 1), a.wmd);
+        }
+        nR = fb.nR;
+      }
+    }
+    if (!fast)
     for (int l = a.L < kCoarseL ? a.L : kCoarseL; l >= 1; l--) {
       const int32_t s = 1 << (l - 1);
       if (MODE == 0) {
@@ -1051,8 +1135,22 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         const int32_t cb = 4 * (int32_t)q;
         const int32_t cnt = Eb2 - cb < 4 ? Eb2 - cb : 4;
         HPEZ_GLOBAL T* dst = out + (bk.o0 + c0) * st0 + (bk.o1 + c1) * st1 + (bk.o2 + cb);
-        const int32_t lb = (int32_t)(c0 * E1 + c1) * E2 + cb;
-        if (vec && cnt == 4) {
+        const int32_t lb = fast ? fslot((int32_t)c0) * kFP0 + fslot((int32_t)c1) * kFP1 + (cb >> 1)
+                                : (int32_t)(c0 * E1 + c1) * E2 + cb;
+        if (fast) {
+          // a full brick row: four cells at the even and odd slots of cb
+          const T v0 = L[lb], v1 = L[lb + 17], v2 = L[lb + 1], v3 = L[lb + 18];
+          if constexpr (sizeof(T) == 4) {
+            if (vec) {
+              *reinterpret_cast<HPEZ_GLOBAL vf4*>(dst) = vf4{v0, v1, v2, v3};
+              continue;
+            }
+          }
+          dst[0] = v0;
+          dst[1] = v1;
+          dst[2] = v2;
+          dst[3] = v3;
+        } else if (vec && cnt == 4) {
           if constexpr (sizeof(T) == 4) {
             const vf4 v = {(float)L[lb], (float)L[lb + 1], (float)L[lb + 2], (float)L[lb + 3]};
             *reinterpret_cast<HPEZ_GLOBAL vf4*>(dst) = v;
@@ -1091,7 +1189,7 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         const int32_t i0 = (int32_t)q0, i1 = (int32_t)q1, i2 = (int32_t)(r - q1 * (uint32_t)lb.E2);
         if (i0 < lb.lo0 || i0 > lb.hi0 || i1 < lb.lo1 || i1 > lb.hi1 || i2 < lb.lo2 || i2 > lb.hi2)
           continue;
-        const uint32_t q = cc[i];
+        const uint32_t q = i == threadIdx.x ? pcc : cc[i];
         code[brick_base + (uint32_t)((i0 * lk0 * Eb1 + i1 * lk1) * Eb2 + i2 * lk2)] = (uint16_t)q;
         nR += q == a.R;
         if (q != a.R) {
@@ -1109,11 +1207,12 @@ __global__ void __launch_bounds__(kBlockThreads) block_kernel(const BlockJobDev<
         if (w < (uint32_t)kBlockHistWin) atomicAdd(&lh[w], nR);
         else __hip_atomic_fetch_add(&hist[a.R], nR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < kBlockHistWin; i += NT)
-        if (lh[i]) __hip_atomic_fetch_add(&hist[lo + i], lh[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     gbi = bn;
+  }
+  if (MODE == 0 && hjob >= 0) {
+    __syncthreads();
+    hist_flush(lh, jobs[hjob], NT);
   }
 }
 
@@ -1197,27 +1296,34 @@ size_t block_lds_bytes(const Geom& g)
     const int64_t e = g.act[d] ? kBrick + 1 : kBrick;
     pts *= (size_t)(g.n[d] < e ? g.n[d] : e);
   }
+  // float fields with full blocks hold them in the 33^3 slot layout
+  if (sizeof(T) == 4 && g.act[0] && g.act[1] && g.act[2] && g.n[0] >= kBrick &&
+      g.n[1] >= kBrick && g.n[2] >= kBrick)
+    pts = (size_t)33 * kFP0;
   return ((pts * sizeof(T) + 15) & ~(size_t)15) + (size_t)kBlockHistWin * 4;
 }
 
 template <typename T>
 hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
-                             uint64_t total_blocks, size_t lds, uint32_t* ticket, int n_cu,
+                             uint64_t total_blocks, size_t lds, int n_cu,
                              int mode, hipStream_t st)
 {
   if (!total_blocks || n <= 0) return hipSuccess;
-  // one work-group per CU (the box takes the CU's LDS); blocks come from the ticket
+  // one work-group per CU (the box takes the CU's LDS), blocks dealt round-robin;
+  // the histogram window takes the last kBlockHistWin words
+  if (lds < (size_t)kBlockHistWin * 4) return hipErrorInvalidValue;
+  const uint32_t lh_off = (uint32_t)(lds - (size_t)kBlockHistWin * 4);
   const unsigned grid = (unsigned)(total_blocks < (uint64_t)n_cu ? total_blocks : (uint64_t)n_cu);
   if (mode == 0) {
     (void)hipFuncSetAttribute((const void*)block_kernel<T, 0>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((block_kernel<T, 0>), dim3(grid), dim3(kBlockThreads), lds, st, d_jobs, d_begin,
-                       n, ticket);
+                       n, lh_off);
   } else {
     (void)hipFuncSetAttribute((const void*)block_kernel<T, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((block_kernel<T, 1>), dim3(grid), dim3(kBlockThreads), lds, st, d_jobs, d_begin,
-                       n, ticket);
+                       n, lh_off);
   }
   return hipGetLastError();
 }
@@ -1231,7 +1337,7 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
   template hipError_t launch_coarse_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
                                             int, hipStream_t);                                     \
   template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
-                                           size_t, uint32_t*, int, int, hipStream_t);             \
+                                           size_t, int, int, hipStream_t);                        \
   template hipError_t launch_face_steps<T>(const FaceEntry<T>*, const uint64_t*, int, uint64_t,   \
                                            bool, int, hipStream_t);                               \
   template hipError_t launch_minmax_faces<T>(const T*, const Geom&, const FaceGeo&, double*, int*, \
