@@ -220,6 +220,22 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
                           void* const* d_out, const uint64_t* out_cap, int* rcs,
                           hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hpez_decompress on GPU
+ * `device` with no allocation.  The device workspace is the library's static
+ * 64 MiB per-GPU array (held by every GPU the library runs on until the
+ * process ends); host staging is static too, and every kernel runs on
+ * `stream` (no second stream).  d_in (in_size bytes) and d_out (out_cap
+ * bytes) are caller device memory on `device`, as in hpez_decompress, whose
+ * output this matches bit for bit.  A stream whose decompression needs more
+ * workspace than the array fails with HPEZ_ENOMEM before any kernel runs
+ * (hpez_footprint with op 1 gives the need).  Calls on one GPU share its
+ * array and its staging: they must not overlap (serialize them, e.g. on one
+ * stream from one thread); the call clears what must start at zero.
+ * Synchronises `stream` like hpez_decompress. */
+int hpez_decompress_noalloc(int device, const void* d_in, uint64_t in_size, void* d_out,
+                            uint64_t out_cap, hipStream_t stream);
+
 /* Auto-tune a configuration for the device field d_in (Sec. 6).  *out_cfg is
  * in/out: on entry its radius, chunk, alpha and beta are used (the rest is
  * ignored); on return it holds a complete configuration.  When block-wise

@@ -63,7 +63,7 @@ EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_
            "hpez_compress_bound", "hpez_compress", "hpez_inspect", "hpez_decompress",
            "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read",
            "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch",
-           "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace"]
+           "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc"]
 
 _lib = None
 _lock = threading.Lock()
@@ -89,6 +89,7 @@ def lib():
             L.hpez_compress.argtypes = [vp, P(FieldDesc), vp, P(Config), vp, u64, P(u64), vp]
             L.hpez_inspect.argtypes = [vp, u64, P(FieldDesc), P(u64), P(u64)]
             L.hpez_decompress.argtypes = [vp, vp, u64, vp, u64, vp]
+            L.hpez_decompress_noalloc.argtypes = [C.c_int, vp, u64, vp, u64, vp]
             L.hpez_tune.argtypes = [vp, P(FieldDesc), vp, P(TuneOpts), P(Config), vp, u64, vp]
             L.hpez_footprint.argtypes = [P(FieldDesc), P(Config), C.c_int, P(u64)]
             L.hpez_profile_enable.argtypes = [vp, C.c_int]
@@ -335,6 +336,16 @@ def decompress(stream_t, stream=None, out=None, context=None):
                                stream_t.numel(), C.c_void_p(out.data_ptr()),
                                out.numel() * out.element_size(), _stream_ptr(stream))
     _check(rc, "hpez_decompress")
+    return out
+
+
+def decompress_noalloc(stream_t, out, stream=None):
+    """hpez_decompress_noalloc: decompress into the caller's `out` with the
+    library's static per-GPU workspace (no allocation in the call)."""
+    rc = lib().hpez_decompress_noalloc(stream_t.device.index or 0, C.c_void_p(stream_t.data_ptr()),
+                                       stream_t.numel(), C.c_void_p(out.data_ptr()),
+                                       out.numel() * out.element_size(), _stream_ptr(stream))
+    _check(rc, "hpez_decompress_noalloc")
     return out
 
 

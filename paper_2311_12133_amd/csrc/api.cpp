@@ -39,6 +39,10 @@ struct hpez_ctx {
   uint8_t* pin_tab = nullptr;  // staging of the block phase's work tables
   size_t pin_tab_bytes = 0;
   size_t ws_limit = 0;  // 0: no cap on the workspace
+  // a fixed context (hpez_decompress_noalloc): workspace and host staging are
+  // given at set-up and never grown; a call that needs more fails with
+  // HPEZ_ENOMEM before any device work, and no second stream is created
+  bool fixed = false;
   uint8_t* pin_pre = nullptr;  // first bytes of the streams being decompressed
   size_t pin_pre_bytes = 0;
   hipEvent_t ev_sync = nullptr;  // host waits for part of a stream's work
@@ -695,6 +699,7 @@ struct Bump {
 int ensure_ws(hpez_ctx* ctx, size_t bytes)
 {
   if (bytes <= ctx->ws_bytes) return HPEZ_OK;
+  if (ctx->fixed) return HPEZ_ENOMEM;
   if (ctx->ws_limit && bytes > ctx->ws_limit) return HPEZ_ENOMEM;
   if (ctx->ws) (void)hipFree(ctx->ws);
   ctx->ws = nullptr;
@@ -712,6 +717,7 @@ int ensure_ws(hpez_ctx* ctx, size_t bytes)
 int ensure_pinned(hpez_ctx* ctx, size_t bytes)
 {
   if (bytes <= ctx->pinned_bytes) return HPEZ_OK;
+  if (ctx->fixed) return HPEZ_ENOMEM;
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   ctx->pinned = nullptr;
   ctx->pinned_bytes = 0;
@@ -726,6 +732,7 @@ int ensure_pinned(hpez_ctx* ctx, size_t bytes)
 int ensure_pin_pre(hpez_ctx* ctx, size_t bytes)
 {
   if (bytes <= ctx->pin_pre_bytes) return HPEZ_OK;
+  if (ctx->fixed) return HPEZ_ENOMEM;
   if (ctx->pin_pre) (void)hipHostFree(ctx->pin_pre);
   ctx->pin_pre = nullptr;
   ctx->pin_pre_bytes = 0;
@@ -740,6 +747,7 @@ int ensure_pin_pre(hpez_ctx* ctx, size_t bytes)
 int ensure_pin_tab(hpez_ctx* ctx, size_t bytes)
 {
   if (bytes <= ctx->pin_tab_bytes) return HPEZ_OK;
+  if (ctx->fixed) return HPEZ_ENOMEM;
   if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
   ctx->pin_tab = nullptr;
   ctx->pin_tab_bytes = 0;
@@ -2098,6 +2106,7 @@ int ctx_device(hpez_ctx* c) { return c->device; }
 
 hipStream_t ctx_fork(hpez_ctx* c, hipStream_t st)
 {
+  if (c->fixed) return nullptr;  // everything on the caller's stream
   if (!c->side) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
@@ -2140,5 +2149,32 @@ void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, h
 }
 
 void ctx_prof_collect(hpez_ctx* c) { prof_collect(c); }
+
+// Host staging of the fixed contexts: plain static arrays (pageable), one set
+// per device, so a fixed context never allocates.
+constexpr size_t kFixedPinned = 4u << 20;
+constexpr size_t kFixedPinTab = 1u << 20;
+static uint8_t g_fixed_pinned[kFixedDevices][kFixedPinned];
+static uint8_t g_fixed_pin_tab[kFixedDevices][kFixedPinTab];
+static uint8_t g_fixed_pin_pre[kFixedDevices][kPrefixBytes];
+static hpez_ctx g_fixed_ctx[kFixedDevices];
+
+int decompress_fixed(int device, void* ws, size_t ws_bytes, const void* d_in, uint64_t in_size,
+                     void* d_out, uint64_t out_cap, hipStream_t stream)
+{
+  if (device < 0 || device >= kFixedDevices || !ws) return HPEZ_EINVAL;
+  hpez_ctx* c = &g_fixed_ctx[device];
+  c->device = device;
+  c->fixed = true;
+  c->ws = ws;
+  c->ws_bytes = ws_bytes;
+  c->pinned = g_fixed_pinned[device];
+  c->pinned_bytes = kFixedPinned;
+  c->pin_tab = g_fixed_pin_tab[device];
+  c->pin_tab_bytes = kFixedPinTab;
+  c->pin_pre = g_fixed_pin_pre[device];
+  c->pin_pre_bytes = kPrefixBytes;
+  return hpez_decompress(c, d_in, in_size, d_out, out_cap, stream);
+}
 
 }  // namespace hpez

@@ -99,6 +99,12 @@ int ctx_join(hpez_ctx* c, hipStream_t st);
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
 void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);
 void ctx_prof_collect(hpez_ctx* c);
+// hpez_decompress on the device's fixed context: workspace `ws` (ws_bytes,
+// device memory owned by the caller), static host staging, no second stream;
+// requests beyond either give HPEZ_ENOMEM.  Calls on one device share it.
+constexpr int kFixedDevices = 8;
+int decompress_fixed(int device, void* ws, size_t ws_bytes, const void* d_in, uint64_t in_size,
+                     void* d_out, uint64_t out_cap, hipStream_t stream);
 
 // Scope guard that makes the context's device current.
 struct DeviceGuard {
