@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain measurement on the 48-field workload")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the float64 copy of the field (compress / decompress roofline runs)")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving measurement (Poisson request stream); off by "
                          "default: one run of it stalled with no output and the cause is not "
@@ -196,6 +198,22 @@ def main():
                       GBps=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
 
+    # whole-call roofline fractions: algorithmic bytes per point of one call
+    # (compress: read the field s B, write and re-read the codes 2 + 2 B, write
+    # the payload b/8 B; decompress the same in reverse) over the call time
+    bpv = size * 8 / x.size
+    alg_pt = 4 + 2 + 2 + bpv / 8
+    calls = dict(bytes_per_point=round(alg_pt, 3),
+                 compress_frac=round(x.size * alg_pt / comp_s / 1e9 / HBM_PEAK_GBPS, 4),
+                 decompress_frac=round(x.size * alg_pt / dec_s / 1e9 / HBM_PEAK_GBPS, 4))
+
+    f64 = None
+    if not args.no_f64:
+        del out, rec
+        torch.cuda.empty_cache()
+        f64 = f64_section(args, binding, fields, torch, shape)
+        out = rec = None
+
     batch = None
     if not args.no_batch:
         del out, rec
@@ -238,12 +256,77 @@ def main():
         "bits_per_value": round(size * 8 / x.size, 4),
         "max_err_over_eb": round(err / e, 6),
         "roofline": roofline,
+        "calls_roofline": calls,
         "kernel_groups": groups,
+        "f64": f64,
         "cpu_baseline": cpu,
         "batch": batch,
         "serving": serving,
     }
     print(json.dumps(res))
+
+
+def f64_section(args, binding, fields, torch, shape):
+    """The float64 copy of the benchmark field (computed in float64), relative
+    bound 1e-3, tuned: compress and decompress timed separately, each with its
+    whole-call roofline fraction (algorithmic bytes 8 + 2 + 2 + b/8 per point)
+    and its dominant kernel group."""
+    import numpy as np
+    t0 = time.time()
+    x = fields.lognormal_field(shape, dtype=np.float64)
+    dev = torch.device("cuda", 0)
+    xt = torch.from_numpy(x).to(dev)
+    log(f"float64 field ready in {time.time() - t0:.1f} s")
+    cfg0 = dict(base_config(shape, args.eb), dtype="f64")
+    cfg = binding.tune(xt, cfg0, TUNE_OPTS)
+    out = torch.empty(binding.compress_bound(shape, "f64", cfg), dtype=torch.uint8, device=dev)
+    rec = torch.empty_like(xt)
+    for _ in range(2):
+        s = binding.compress(xt, cfg, out=out)
+        binding.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    tc = td = 0.0
+    binding.profile_enable(0, True)
+    with paused_gc():
+        for _ in range(steps):
+            ta = time.perf_counter()
+            s = binding.compress(xt, cfg, out=out)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            binding.decompress(s, out=rec)
+            torch.cuda.synchronize()
+            tc += tb - ta
+            td += time.perf_counter() - tb
+    stats = binding.profile_read(0)
+    binding.profile_enable(0, False)
+    tc /= steps
+    td /= steps
+    e = args.eb * (float(x.max()) - float(x.min()))
+    err = (rec - xt).abs().max().item()
+    if not err <= e:
+        raise SystemExit(f"float64: error bound violated: {err} > {e}")
+    size = int(s.numel())
+    bpv = size * 8 / x.size
+    alg_pt = 8 + 2 + 2 + bpv / 8
+    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    res = dict(workload=f"lognormal {'x'.join(map(str, shape))} float64 (computed in float64), "
+                        f"rel eb {args.eb:g}, tuned",
+               steps=steps, compress_ms=round(tc * 1e3, 3), decompress_ms=round(td * 1e3, 3),
+               compress_GBps=round(x.nbytes / tc / 1e9, 3),
+               decompress_GBps=round(x.nbytes / td / 1e9, 3),
+               compression_ratio=round(x.nbytes / size, 3), bits_per_value=round(bpv, 4),
+               bytes_per_point=round(alg_pt, 3),
+               compress_frac=round(x.size * alg_pt / tc / 1e9 / HBM_PEAK_GBPS, 4),
+               decompress_frac=round(x.size * alg_pt / td / 1e9 / HBM_PEAK_GBPS, 4),
+               max_err_over_eb=round(err / e, 6),
+               dominant=dict(kernel=dom[0], ms_per_step=round(dom[1]["ms"] / steps, 4)),
+               kernel_groups={k: round(v["ms"] / steps, 4)
+                              for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]})
+    log(f"float64: compress {tc*1e3:.2f} ms decompress {td*1e3:.2f} ms ratio {x.nbytes / size:.2f}")
+    del xt, out, rec
+    torch.cuda.empty_cache()
+    return res
 
 
 def batch_section(args, binding, fields, torch):

@@ -170,6 +170,38 @@ def test_lorenzo(torch_cuda, dtype):
         assert int(np.frombuffer(s[472:480], np.uint64)[0]) > 10
 
 
+def fibonacci_walk(nsym: int, seed: int) -> np.ndarray:
+    """A 1-D walk whose first-order differences take nsym values with
+    Fibonacci counts F_1..F_nsym (the most frequent difference 0, then +1, -1,
+    +2, ...), shuffled with a seeded generator.  With the Lorenzo predictor at
+    an absolute bound of 1/2 (bins of width 1) the codes are exactly the
+    differences, so their Huffman tree is a chain as deep as the alphabet."""
+    f = [1, 1]
+    while len(f) < nsym:
+        f.append(f[-1] + f[-2])
+    counts = np.array(f[:nsym][::-1], dtype=np.int64)
+    vals = np.array([0] + [(k + 1) // 2 * (1 if k % 2 else -1) for k in range(1, nsym)])
+    d = np.repeat(vals, counts)
+    np.random.Generator(np.random.PCG64(2311121330 + 77 + nsym)).shuffle(d)
+    x = np.cumsum(d)
+    assert np.abs(x).max() < 2 ** 24  # exact in float32
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("nsym,maxlen", [(33, 32), (34, 17)])
+def test_huffman_long_codes(torch_cuda, nsym, maxlen):
+    """Huffman edge cases of Sec. 4 step 4: 33 Fibonacci-distributed symbols give
+    codewords of the full 32 bits (the decoder's path beyond its lookup tables);
+    34 exceed the 32-bit limit and force the halving rebuild, which leaves 17."""
+    x = fibonacci_walk(nsym, 0)
+    f = [1, 1]
+    while len(f) < nsym:
+        f.append(f[-1] + f[-2])
+    assert int(O.huff_lengths(np.array(f[:nsym], np.uint32)).max()) == maxlen
+    roundtrip(torch_cuda, x, make_cfg(x.shape, eb=0.5, eb_mode="abs", predictor="lorenzo"),
+              f"huffman {nsym} Fibonacci symbols ({x.size} points)")
+
+
 FAST_SHAPES = [(64, 64, 64), (65, 33, 97), (96, 31, 130), (33, 64, 1), (200, 161), (1, 77, 64),
                (40, 40, 40)]
 
