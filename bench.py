@@ -69,7 +69,7 @@ def base_config(shape, eb):
 
 
 TUNE_OPTS = dict(global_rate=0.01, sub_rate=0.04, lorenzo_coef=1.0, block_log2=5,
-                 allow_freeze=1, allow_lorenzo=1, block_wise=1)
+                 allow_freeze=1, allow_lorenzo=1, block_wise=1, tune_ab=1)
 
 
 def main():

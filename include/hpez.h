@@ -123,7 +123,15 @@ typedef struct {
  *   lorenzo_coef multiplies the Lorenzo bit-rate estimate (Sec. 6.5);
  *   block_log2   tuning block side (the paper uses 32, i.e. 5);
  *   allow_freeze, allow_lorenzo, block_wise  enable Sec. 6.3 / 6.5 / 6.6;
- *   anchor_log2  0 for the default (64 for 3+ dims, 128 for 2, 256 for 1). */
+ *   anchor_log2  0 for the default (64 for 3+ dims, 128 for 2, 256 for 1);
+ *   tune_ab      tune the level-wise bound of Eq. (15) (Sec. 6.4): when the
+ *                interpolation predictor is kept, the tuned configuration is
+ *                run on the global regions under each (alpha, beta) of the grid
+ *                (1, 1), {1.25, 1.5, 1.75, 2} x {1.5, 2, 3, 4}, and the pair with
+ *                the best rate-distortion score (quality in dB against e minus
+ *                20 log10(2) dB per estimated bit) is returned in out_cfg and
+ *                used by the block-wise trials; otherwise the caller's alpha and
+ *                beta are kept. */
 typedef struct {
   double global_rate;
   double sub_rate;
@@ -133,7 +141,8 @@ typedef struct {
   uint8_t allow_lorenzo;
   uint8_t block_wise;
   uint8_t anchor_log2;
-  uint8_t pad[3];
+  uint8_t tune_ab;
+  uint8_t pad[2];
 } hpez_tune_opts;
 
 typedef struct hpez_ctx hpez_ctx;

@@ -58,14 +58,17 @@ class TuneOpts(C.Structure):
     _fields_ = [("global_rate", C.c_double), ("sub_rate", C.c_double),
                 ("lorenzo_coef", C.c_double), ("block_log2", C.c_uint8),
                 ("allow_freeze", C.c_uint8), ("allow_lorenzo", C.c_uint8),
-                ("block_wise", C.c_uint8), ("anchor_log2", C.c_uint8), ("pad", C.c_uint8 * 3)]
+                ("block_wise", C.c_uint8), ("anchor_log2", C.c_uint8), ("tune_ab", C.c_uint8),
+                ("pad", C.c_uint8 * 2)]
 
 
 class TuneReport(C.Structure):
     _fields_ = [("sigma2", (C.c_double * 4) * 3), ("count", C.c_int64),
                 ("freeze_candidate", C.c_int), ("global_score", ((C.c_uint64 * 16) * 11) * 2),
                 ("H", C.c_double * 2), ("H_lorenzo", C.c_double), ("frozen", C.c_int),
-                ("lorenzo", C.c_int)]
+                ("lorenzo", C.c_int), ("ab_alpha", C.c_double * 17), ("ab_beta", C.c_double * 17),
+                ("ab_score", C.c_double * 17), ("ab_sq", C.c_uint64 * 17),
+                ("ab_rate", C.c_double * 17), ("ab_choice", C.c_int)]
 
 
 _lib = None
@@ -343,6 +346,7 @@ def tune(x: np.ndarray, cfg: dict, opts: dict):
     o.allow_lorenzo = opts.get("allow_lorenzo", 1)
     o.block_wise = opts.get("block_wise", 1)
     o.anchor_log2 = opts.get("anchor_log2", 0)
+    o.tune_ab = opts.get("tune_ab", 0)
     outp = Params()
     B = 1 << o.block_log2
     nb = 1
@@ -362,13 +366,17 @@ def tune(x: np.ndarray, cfg: dict, opts: dict):
     out["levels"] = [interp_from_struct(outp.level[i]) for i in range(16)]
     out["cand"] = [interp_from_struct(outp.cand[i]) for i in range(outp.n_cand)]
     out["block_cfg"] = bc[:nb].copy() if outp.block_log2 else None
+    out["alpha"] = float(outp.alpha)
+    out["beta"] = float(outp.beta)
     report = dict(sigma2=np.array([[rep.sigma2[k][d] for d in range(4)] for k in range(3)]),
                   count=rep.count, freeze_candidate=rep.freeze_candidate,
                   global_score=np.array([[[rep.global_score[f][c][l] for l in range(16)]
                                           for c in range(11)] for f in range(2)],
                                         dtype=np.uint64),
                   H=(rep.H[0], rep.H[1]), H_lorenzo=rep.H_lorenzo, frozen=rep.frozen,
-                  lorenzo=rep.lorenzo)
+                  lorenzo=rep.lorenzo, ab_alpha=list(rep.ab_alpha), ab_beta=list(rep.ab_beta),
+                  ab_score=list(rep.ab_score), ab_sq=list(rep.ab_sq), ab_rate=list(rep.ab_rate),
+                  ab_choice=rep.ab_choice)
     return out, report
 
 

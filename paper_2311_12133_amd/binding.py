@@ -51,7 +51,8 @@ class TuneOpts(C.Structure):
     _fields_ = [("global_rate", C.c_double), ("sub_rate", C.c_double),
                 ("lorenzo_coef", C.c_double), ("block_log2", C.c_uint8),
                 ("allow_freeze", C.c_uint8), ("allow_lorenzo", C.c_uint8),
-                ("block_wise", C.c_uint8), ("anchor_log2", C.c_uint8), ("pad", C.c_uint8 * 3)]
+                ("block_wise", C.c_uint8), ("anchor_log2", C.c_uint8), ("tune_ab", C.c_uint8),
+                ("pad", C.c_uint8 * 2)]
 
 
 class KernelStat(C.Structure):
@@ -360,6 +361,7 @@ def _tune_opts(opts: dict | None) -> TuneOpts:
     o.allow_lorenzo = opts.get("allow_lorenzo", 1)
     o.block_wise = opts.get("block_wise", 1)
     o.anchor_log2 = opts.get("anchor_log2", 0)
+    o.tune_ab = opts.get("tune_ab", 0)
     return o
 
 
@@ -382,6 +384,8 @@ def _tuned_dict(cfg: dict, c: Config, bc, nb: int) -> dict:
     res["levels"] = _interp_dicts(c, _LEVEL_OFF, 16)
     res["cand"] = _interp_dicts(c, _CAND_OFF, c.n_cand)
     res["block_cfg"] = bc[:nb].copy() if c.block_log2 else None
+    res["alpha"] = float(c.alpha)
+    res["beta"] = float(c.beta)
     return res
 
 

@@ -76,7 +76,7 @@ __device__ void trial_step(const TrialArgs& a, const TrialBox& bx, const int64_t
                            const T* __restrict__ X, P* W, const int64_t* r, const int64_t* m,
                            int kind, int md, int sl, int pd, unsigned odd, int64_t s, int level,
                            const double* __restrict__ wq, unsigned long long& score,
-                           uint32_t* __restrict__ hist, uint32_t* lh)
+                           uint32_t* __restrict__ hist, uint32_t* lh, unsigned long long& sq)
 {
   uint32_t cnt[4];
   uint64_t total = 1;
@@ -117,6 +117,10 @@ __device__ void trial_step(const TrialArgs& a, const TrialBox& bx, const int64_t
     T xr = xv;
     const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, a.R, xr);
     W[idx] = q ? xr : xv;
+    if (a.score_mode == 2) {
+      const double u = ((double)xv - (double)xr) * a.inv_e;
+      sq += (unsigned long long)floor(u * u * 4294967296.0);
+    }
     if (hist) hist_add_wave(lh, hist, a.hist_lo, kTrialHistWin, q, true);
   }
 }
@@ -158,7 +162,7 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
     }
   }
   __syncthreads();
-  unsigned long long total_score = 0;
+  unsigned long long total_score = 0, sq = 0;
   for (int l = a.L; l >= 1; l--) {
     const int64_t s = (int64_t)1 << (l - 1);
     const hpez_interp ip = a.tuned ? a.level[l - 1] : a.cand[cand];
@@ -176,7 +180,7 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
             else if (odd >> d & 1u) { r[d] = s; m[d] = 2 * s; }
             else { r[d] = 0; m[d] = 2 * s; }
           }
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 1, 0, -1, odd, s, l, wq, sc, hist, lh);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 1, 0, -1, odd, s, l, wq, sc, hist, lh, sq);
         }
         __syncthreads();
       }
@@ -199,12 +203,12 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
         if (ip.kind != 0 && ip.same_level) {
           m[pd] = 4 * s;
           r[pd] = s;
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh, sq);
           __syncthreads();
           r[pd] = 3 * s;
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 1, pd, 0, s, l, wq, sc, hist, lh);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 1, pd, 0, s, l, wq, sc, hist, lh, sq);
         } else {
-          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh);
+          trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh, sq);
         }
         __syncthreads();
       }
@@ -217,6 +221,10 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
     }
   }
   if (a.score_mode == 1 && threadIdx.x == 0) score[(uint64_t)blockIdx.x * gridDim.y + cand] = total_score;
+  if (a.score_mode == 2) {
+    const unsigned long long v = block_sum_u64(sq, red);
+    if (threadIdx.x == 0 && v) atomicAdd(&score[0], v);
+  }
   if (hist) {
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += blockDim.x)
@@ -267,6 +275,8 @@ struct TrialOp {
   double el, inv2e, twoe, mul;
   unsigned long long sc;
   uint32_t nR;
+  double inv_e;  // > 0: accumulate the distortion of Sec. 6.4 into sq
+  unsigned long long sq;
   __device__ __forceinline__ int fetch(int32_t, int32_t, int32_t, bool) const { return 0; }
   __device__ __forceinline__ void apply(int32_t li, int32_t, int32_t, int32_t, T p, int)
   {
@@ -277,6 +287,10 @@ struct TrialOp {
     T xr = xv;
     const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
     L[li] = xr;
+    if (inv_e > 0.0) {
+      const double u = ((double)xv - (double)xr) * inv_e;
+      sq += (unsigned long long)floor(u * u * 4294967296.0);
+    }
     if (HIST) {
       nR += q == R;
       if (q != R) {
@@ -334,16 +348,18 @@ __device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox
   if (HIST)
     for (uint32_t i = threadIdx.x; i < kTrialHistWin; i += NT) lh[i] = 0;
   __syncthreads();
-  unsigned long long total_score = 0;
+  unsigned long long total_score = 0, total_sq = 0;
   uint32_t nR = 0;
   const int score_mode = a.score_mode;
   for (int l = a.L; l >= 1; l--) {
     const int32_t s = 1 << (l - 1);
     const hpez_interp ip = a.tuned ? a.level[l - 1] : a.cand[cand];
-    TrialOp<T, HIST> op{L,         lh,          hist,         R,    hist_lo, a.el[l],
-                        a.inv2e[l], a.twoe[l], a.score_mul, 0ull, 0u};
+    TrialOp<T, HIST> op{L,           lh,        hist,        R,    hist_lo, a.el[l],
+                        a.inv2e[l],  a.twoe[l], a.score_mul, 0ull, 0u,
+                        score_mode == 2 ? a.inv_e : 0.0, 0ull};
     box_level<T, NT>(ip, bx, L, 0, 0, 0, s, a.wmd, op);
     nR += op.nR;
+    total_sq += op.sq;
     const unsigned long long v = block_sum_u64(op.sc, red);
     if (score_mode == 0) {
       if (threadIdx.x == 0 && v)
@@ -354,6 +370,11 @@ __device__ __forceinline__ void trial_box_run(const TrialArgs& a, const TrialBox
     }
   }
   if (score_mode == 1 && threadIdx.x == 0) score[(uint64_t)ib * n_cand + cand] = total_score;
+  if (score_mode == 2) {
+    const unsigned long long v = block_sum_u64(total_sq, red);
+    if (threadIdx.x == 0 && v)
+      __hip_atomic_fetch_add(&score[0], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (HIST) {
     for (int o = 32; o > 0; o >>= 1) nR += __shfl_xor(nR, o, 64);
     if ((threadIdx.x & 63) == 0 && nR) {

@@ -241,6 +241,17 @@ struct TJob {
   bool spec = false;  // block trials already queued on the second stream
   double HL = 0.0;     // entropy of the Lorenzo trial's codes
   TrialArgs ba;
+  // Sec. 6.4: the (alpha, beta) trials (when tune_ab)
+  bool ab = false;      // the trials run for this job
+  int nab = 0;          // grid pairs with workspace (kNAB when tune_ab, else 0)
+  unsigned long long* absq = nullptr;   // per pair: the distortion
+  uint32_t* abhist = nullptr;           // per pair: the codes' histogram (nsym bins)
+  uint32_t* abnz = nullptr;             // per pair: its nonzero (bin, count) pairs
+  uint32_t* abnzn = nullptr;            // per pair: the pair count
+  unsigned long long* h_absq = nullptr;
+  uint32_t* h_abnz = nullptr;
+  uint32_t* h_abnzn = nullptr;
+  uint32_t* h_abhist = nullptr;         // one histogram, read when the pairs overflow
   double h_wq[3 * 16 * 4];
   // device
   TrialBox* d_gb = nullptr;
@@ -270,6 +281,20 @@ struct TJob {
   double* h_wqp = nullptr;    // staging of h_wq
   TrialBox* h_gbp = nullptr;  // staging of gb
 };
+
+// The (alpha, beta) grid of Sec. 6.4 (Eq. 15): (1, 1) first, then alpha-major
+// over {1.25, 1.5, 1.75, 2} x {1.5, 2, 3, 4}.
+constexpr int kNAB = 17;
+void ab_pair(int c, double* alpha, double* beta)
+{
+  static const double av[4] = {1.25, 1.5, 1.75, 2.0}, bv[4] = {1.5, 2.0, 3.0, 4.0};
+  if (c == 0) {
+    *alpha = *beta = 1.0;
+    return;
+  }
+  *alpha = av[(c - 1) / 4];
+  *beta = bv[(c - 1) % 4];
+}
 
 // validation and sizes; rc set for a bad request
 template <typename T>
@@ -311,6 +336,7 @@ void t_init(TJob<T>& J)
     return;
   }
   J.nsym = 2 * Q.radius;
+  J.nab = o->tune_ab ? kNAB : 0;
   candidate_list(d->ndims, J.cand);
   J.gb = global_boxes(J.g, J.B, o->global_rate, &J.gcap);
   J.scratch_bytes = trial_scratch(J.g, o, sizeof(T), J.gb.size(), J.gcap, J.nbt);
@@ -325,7 +351,9 @@ size_t t_dev_bytes(const TJob<T>& J)
          al256(J.scratch_bytes) + 2 * al256(kNCand * 16 * 8) + al256(nb * kNCand * 8) +
          al256(16 * 8) + 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + 2 * al256(64) +
          al256(3 * 16 * 4 * 8) +
-         al256(2 * 1024 * 8) + al256(64) + al256(12 * 8 * kStatSlots) + 256;
+         al256(2 * 1024 * 8) + al256(64) + al256(12 * 8 * kStatSlots) + 256 +
+         al256((size_t)J.nab * 8) + al256((size_t)J.nab * J.nsym * 4) +
+         al256((size_t)J.nab * 2 * kNzCap * 4) + al256((size_t)J.nab * 4);
 }
 
 template <typename T>
@@ -335,7 +363,9 @@ size_t t_pin_bytes(const TJob<T>& J)
   return 3 * al256(J.nsym * 4) + 3 * al256(kNzCap * 8) + al256(16) + 2 * al256(kNCand * 16 * 8) +
          al256((size_t)J.nbt * kNCand * 8) + al256(64) + al256(12 * 8 * kStatSlots) +
          al256(3 * 16 * 4 * 8) +
-         al256(J.gb.size() * sizeof(TrialBox)) + 256;
+         al256(J.gb.size() * sizeof(TrialBox)) + 256 + al256((size_t)J.nab * 8) +
+         al256((size_t)J.nab * 2 * kNzCap * 4) + al256((size_t)J.nab * 4) +
+         (J.nab ? al256((size_t)J.nsym * 4) : 0);
 }
 
 struct Take {
@@ -361,6 +391,10 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.score[1] = dw.take<unsigned long long>(kNCand * 16);
   J.bscore = dw.take<unsigned long long>((size_t)J.nbt * kNCand);
   J.dummy = dw.take<unsigned long long>(16);
+  J.absq = dw.take<unsigned long long>((size_t)J.nab);
+  J.abhist = dw.take<uint32_t>((size_t)J.nab * J.nsym);
+  J.abnz = dw.take<uint32_t>((size_t)J.nab * 2 * kNzCap);
+  J.abnzn = dw.take<uint32_t>((size_t)J.nab);
   for (int v = 0; v < 3; v++) J.hist[v] = dw.take<uint32_t>(J.nsym);
   for (int v = 0; v < 3; v++) J.nz[v] = dw.take<uint32_t>(2 * kNzCap);
   J.flag = dw.take<int>(16);
@@ -381,6 +415,10 @@ void t_take(TJob<T>& J, Take& dw, Take& pw)
   J.h_sums = pw.take<unsigned long long>(12 * kStatSlots);
   J.h_wqp = pw.take<double>(3 * 16 * 4);
   J.h_gbp = pw.take<TrialBox>(J.gb.size());
+  J.h_absq = pw.take<unsigned long long>((size_t)J.nab);
+  J.h_abnz = pw.take<uint32_t>((size_t)J.nab * 2 * kNzCap);
+  J.h_abnzn = pw.take<uint32_t>((size_t)J.nab);
+  if (J.nab) J.h_abhist = pw.take<uint32_t>(J.nsym);
 }
 
 // phase 1: value range and the non-finite check
@@ -753,7 +791,7 @@ int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool
 template <typename T>
 int t_blocks_ahead(TJob<T>& J, TrialBatch<T>& tb, hipStream_t side)
 {
-  if (J.done || J.nvar != 1 || !J.o->block_wise || !J.nbt) return HPEZ_OK;
+  if (J.done || J.nvar != 1 || !J.o->block_wise || !J.nbt || J.nab) return HPEZ_OK;
   bool ok = false;
   const int rc = t_block_args(J, -1, tb, side, true, &ok);
   if (rc) return rc;
@@ -761,8 +799,9 @@ int t_blocks_ahead(TJob<T>& J, TrialBatch<T>& tb, hipStream_t side)
   return HPEZ_OK;
 }
 
+// phase 5: the freeze (Sec. 6.3) and Lorenzo (Sec. 6.5) decisions
 template <typename T>
-int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
+int t_decide(TJob<T>& J, hipStream_t st)
 {
   if (J.done) return HPEZ_OK;
   const hpez_field_desc* d = J.d;
@@ -780,7 +819,96 @@ int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
   J.lorenzo = false;
   if (J.lorenzo_trial && *J.h_lflag == 0 && o->lorenzo_coef * J.HL < Hbest) J.lorenzo = true;
   J.blocks = !J.lorenzo && o->block_wise;
-  if (!J.blocks || J.spec) return HPEZ_OK;
+  J.ab = !J.lorenzo && J.nab > 0;
+  return HPEZ_OK;
+}
+
+// phase 6 (tune_ab): the tuned configuration under every (alpha, beta) pair
+// of the grid on the global regions (Sec. 6.4, Eq. 15), each pair a trial job
+// of its own (its level bounds), its codes' histogram and its distortion
+template <typename T>
+int t_ab(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
+{
+  if (J.done || !J.ab) return HPEZ_OK;
+  const int v = J.frozen >= 0 ? 1 : 0;
+  const int Lb = J.o->block_log2;
+  for (int c = 0; c < kNAB; c++) {
+    TrialArgs a = J.ga[v];
+    a.tuned = 1;
+    a.score_mode = 2;
+    a.inv_e = 1.0 / J.e;
+    a.hist_lo = trial_hist_lo(J.Q.radius);
+    for (int l = 1; l <= Lb; l++) a.level[l - 1] = J.lv[v][l - 1];
+    hpez_config q = J.Q;
+    ab_pair(c, &q.alpha, &q.beta);
+    fill_levels(a, J.e, &q);
+    t_add<T>(tb, a, J.d_gb, (uint32_t)J.gb.size(), 1, J.X, (T*)J.scratch, J.wq, J.absq + c,
+             J.abhist + (size_t)c * J.nsym);
+  }
+  return HPEZ_OK;
+}
+
+template <typename T>
+int t_ab_copy(TJob<T>& J, hipStream_t st)
+{
+  if (J.done || !J.ab) return HPEZ_OK;
+  for (int c = 0; c < kNAB; c++)
+    TCK(launch_hist_nonzero(J.abhist + (size_t)c * J.nsym, J.nsym, J.abnzn + c,
+                            J.abnz + (size_t)c * 2 * kNzCap, kNzCap, st));
+  TCK(hipMemcpyAsync(J.h_abnz, J.abnz, (size_t)kNAB * 2 * kNzCap * 4, hipMemcpyDeviceToHost, st));
+  TCK(hipMemcpyAsync(J.h_abnzn, J.abnzn, (size_t)kNAB * 4, hipMemcpyDeviceToHost, st));
+  TCK(hipMemcpyAsync(J.h_absq, J.absq, (size_t)kNAB * 8, hipMemcpyDeviceToHost, st));
+  return HPEZ_OK;
+}
+
+// the pair with the best rate-distortion score: rate = code entropy plus the
+// verbatim bits of unpredictable points (code 0) per predicted point, quality
+// -10 log10((D + 1) / (n 2^32)) in dB against e, score = quality - 20 log10(2)
+// dB per bit (the high-rate slope of a uniform quantizer); ties keep the
+// earlier pair
+template <typename T>
+int t_ab_decide(TJob<T>& J, hipStream_t st)
+{
+  if (J.done || !J.ab) return HPEZ_OK;
+  int best = 0;
+  double best_score = 0.0;
+  for (int c = 0; c < kNAB; c++) {
+    const uint32_t* pairs = J.h_abnz + (size_t)c * 2 * kNzCap;
+    const uint32_t np = J.h_abnzn[c];
+    uint64_t n = 0, zero = 0;
+    double H;
+    if (np <= kNzCap) {
+      for (uint32_t i = 0; i < np; i++) {
+        n += pairs[2 * i + 1];
+        if (pairs[2 * i] == 0) zero = pairs[2 * i + 1];
+      }
+      H = entropy_bits_pairs(pairs, np);
+    } else {
+      TCK(hipMemcpyAsync(J.h_abhist, J.abhist + (size_t)c * J.nsym, sizeof(uint32_t) * J.nsym,
+                         hipMemcpyDeviceToHost, st));
+      TCK(hipStreamSynchronize(st));
+      for (uint32_t k = 0; k < J.nsym; k++) n += J.h_abhist[k];
+      zero = J.h_abhist[0];
+      H = entropy_bits(J.h_abhist, J.nsym);
+    }
+    const double rate = n ? H + (double)zero * (double)sizeof(T) * 8.0 / (double)n : 0.0;
+    const double quality =
+        n ? -10.0 * std::log10(((double)J.h_absq[c] + 1.0) / ((double)n * 4294967296.0)) : 0.0;
+    const double score = quality - 20.0 * std::log10(2.0) * rate;
+    if (c == 0 || score > best_score) {
+      best = c;
+      best_score = score;
+    }
+  }
+  ab_pair(best, &J.Q.alpha, &J.Q.beta);
+  return HPEZ_OK;
+}
+
+// phase 7: the block-wise trials (Sec. 6.6) with the final level bounds
+template <typename T>
+int t_blocks(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
+{
+  if (J.done || !J.blocks || J.spec) return HPEZ_OK;
   bool ok = false;
   return t_block_args(J, J.frozen, tb, st, false, &ok);
 }
@@ -831,9 +959,12 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     dev += t_dev_bytes(J);
     pin += t_pin_bytes(J);
   }
-  // trial tables: two global variants per job is the most of any phase
-  const size_t tab_cap = al256(2 * jobs.size() * sizeof(TrialJob<T>)) * 3 +
-                         3 * al256((2 * jobs.size() + 1) * 8) + 512;
+  // trial tables: two global variants per job, or the (alpha, beta) grid, is
+  // the most of any phase
+  size_t per_job = 2;
+  for (auto& J : jobs) per_job = std::max<size_t>(per_job, (size_t)J.nab);
+  const size_t tab_cap = al256(per_job * jobs.size() * sizeof(TrialJob<T>)) * 3 +
+                         3 * al256((per_job * jobs.size() + 1) * 8) + 512;
   // (a second table, device and pinned staging, for the block trials queued ahead)
   dev += 2 * tab_cap;
   pin += tab_cap;
@@ -873,7 +1004,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     for (auto& J : jobs)
       if ((rc = t_global(J, tb, st))) return rc;
     bool ahead = false;
-    for (auto& J : jobs) ahead |= !J.done && J.nvar == 1 && J.o->block_wise && J.nbt > 0;
+    for (auto& J : jobs) ahead |= !J.done && J.nvar == 1 && J.o->block_wise && J.nbt > 0 && !J.nab;
     hipStream_t side = ahead ? ctx_fork(ctx, st) : nullptr;
     if (side) {
       join.on = true;
@@ -916,6 +1047,27 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
       if (!J.done && J.lorenzo_trial && (rc = t_entropy(J, 2, st, &J.HL))) return rc;
   }
   TCK(hipStreamSynchronize(st));
+  bool any_ab = false;
+  for (auto& J : jobs) {
+    if ((rc = t_decide(J, st))) return rc;
+    any_ab |= !J.done && J.ab;
+  }
+  if (any_ab) {
+    TrialBatch<T> tb;
+    for (auto& J : jobs)
+      if ((rc = t_ab(J, tb, st))) return rc;
+    hipEvent_t ev = ctx_span_begin(ctx, st);
+    if ((rc = t_launch(ctx, tb, true, d_tab, tab_cap, st))) return rc;
+    uint64_t bytes = 0;
+    for (auto& J : jobs)
+      if (!J.done && J.ab) bytes += (uint64_t)kNAB * J.gb.size() * J.gcap * sizeof(T);
+    ctx_span_end(ctx, ev, "tune_ab_trials", bytes, st);
+    for (auto& J : jobs)
+      if ((rc = t_ab_copy(J, st))) return rc;
+    TCK(hipStreamSynchronize(st));
+    for (auto& J : jobs)
+      if ((rc = t_ab_decide(J, st))) return rc;
+  }
   {
     TrialBatch<T> tb;
     for (auto& J : jobs)

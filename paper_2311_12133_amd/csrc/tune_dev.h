@@ -21,12 +21,15 @@ struct TrialArgs {
   int32_t L;           // anchor_log2 of the region
   uint32_t R;
   int32_t tuned;       // 1: level[] per level; 0: candidate blockIdx.y on every level
-  int32_t score_mode;  // 0: score[cand][level] summed over regions; 1: score[region][cand]
+  int32_t score_mode;  // 0: score[cand][level] summed over regions; 1: score[region][cand];
+                       // 2: score[0] += the distortion of Sec. 6.4 (sum of
+                       //    floor(((x - x') * inv_e)^2 * 2^32) over predicted points)
   uint32_t hist_lo;    // first code of the LDS histogram window
   int32_t max_ext;     // largest region extent along any dim
   int32_t pad2;
   uint64_t box_cap;    // points of the largest region (scratch stride)
   double score_mul;    // 4096 / e
+  double inv_e;        // 1 / e (score_mode 2)
   double el[17], inv2e[17], twoe[17];
   hpez_interp cand[16];
   hpez_interp level[16];

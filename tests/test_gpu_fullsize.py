@@ -23,7 +23,7 @@ from paper_2311_12133_amd import fields
 pytestmark = pytest.mark.gpu
 
 TUNE = dict(global_rate=0.01, sub_rate=0.04, lorenzo_coef=1.0, block_log2=5, allow_freeze=1,
-            allow_lorenzo=1, block_wise=1)
+            allow_lorenzo=1, block_wise=1, tune_ab=1)  # the options bench.py times
 
 
 @pytest.fixture(scope="module")

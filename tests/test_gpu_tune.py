@@ -25,6 +25,11 @@ def torch_cuda():
     return torch
 
 
+def lognormal_2d(shape, seed):
+    g = fields.gaussian_field(shape, -5.0 / 3.0, np.random.default_rng(seed))
+    return np.exp(1.5 * g).astype(np.float32)
+
+
 def anisotropic(n=64, seed=1):
     rng = np.random.default_rng(seed)
     base = fields.gaussian_field((n, n), -3.0, rng)
@@ -55,6 +60,16 @@ CASES = [
     # coordinates need the exact division for dividends beyond 2^24
     ("blocks256", lambda: fields.fronts_field((257, 260, 258)), 1e-3,
      dict(global_rate=1.0, sub_rate=0.04, block_log2=8)),
+    # level-wise bound tuning (Sec. 6.4): a pair other than (1, 1) is chosen and
+    # the block-wise trials then run with its level bounds
+    ("ab-lognormal-3d", lambda: fields.lognormal_field((96, 96, 96)), 1e-3,
+     dict(global_rate=0.2, tune_ab=1)),
+    ("ab-lognormal-2d", lambda: lognormal_2d((70, 100), 0), 1e-4,
+     dict(global_rate=0.3, tune_ab=1)),
+    ("ab-f64-fronts", lambda: fields.fronts_field((40, 70, 66)).astype(np.float64), 1e-3,
+     dict(global_rate=0.3, tune_ab=1)),
+    ("ab-blocks256", lambda: fields.lognormal_field((129, 130, 140)), 1e-3,
+     dict(global_rate=1.0, block_log2=7, tune_ab=1)),
 ]
 
 
@@ -68,7 +83,8 @@ def test_tune_matches_oracle(torch_cuda, name, make, eb, opts):
     ref, rep = O.tune(x, cfg, opts)
     xt = torch_cuda.from_numpy(x).cuda()
     got = binding.tune(xt, cfg, opts)
-    for k in ("predictor", "anchor_log2", "frozen_dim", "block_log2", "md_w", "levels", "cand"):
+    for k in ("predictor", "anchor_log2", "frozen_dim", "block_log2", "md_w", "levels", "cand",
+              "alpha", "beta"):
         assert got[k] == ref[k], (k, got[k], ref[k])
     if ref["block_cfg"] is None:
         assert got["block_cfg"] is None

@@ -250,3 +250,77 @@ def test_block_choice_brute_force(shape, sub_rate):
     assert not np.array_equal(worst, want)
     # more than one candidate is chosen across the blocks
     assert len(set(want.tolist())) > 1
+
+
+# ---------------------------------------------------------------------------
+# level-wise error bounds (Sec. 6.4, Eq. 15): (alpha, beta) tuning
+
+AB_GRID = [(1.0, 1.0)] + [(a, b) for a in (1.25, 1.5, 1.75, 2.0) for b in (1.5, 2.0, 3.0, 4.0)]
+
+
+def lognormal_2d(shape, seed):
+    g = fields.gaussian_field(shape, -5.0 / 3.0, np.random.default_rng(seed))
+    return np.exp(1.5 * g).astype(np.float32)
+
+
+@pytest.mark.parametrize("make,eb,radius,nontrivial", [
+    (lambda: lognormal_2d((70, 100), 0), 1e-4, 32768, True),
+    (lambda: fields.fronts_field((70, 100)), 1e-3, 64, False),
+])
+def test_alpha_beta_brute_force(make, eb, radius, nontrivial):
+    """Every (alpha, beta) pair's rate, distortion and score, recomputed from
+    trial compressions of the sampled boxes with the twin under the tuned
+    per-level configuration and the pair's level bounds (Eq. 15): rate =
+    entropy of the codes + verbatim bits of the unpredictable points per
+    predicted point, D = sum floor(((x - x') / e)^2 2^32), score =
+    -10 log10((D + 1) / (n 2^32)) - 20 log10(2) rate; the chosen pair is the
+    first maximum.  One field picks a pair other than (1, 1), the other has
+    unpredictable points (radius 64), so the rate's verbatim term counts."""
+    x = make()
+    shape = x.shape
+    rate = 0.3
+    cfg = make_cfg(shape, eb=eb, radius=radius)
+    e, _ = O.error_bound(x, cfg)
+    out, rep = O.tune(x, cfg, dict(global_rate=rate, block_wise=0, allow_freeze=0,
+                                   allow_lorenzo=0, tune_ab=1))
+    assert [(a, b) for a, b in zip(rep["ab_alpha"], rep["ab_beta"])] == AB_GRID
+    Lb = 5
+    boxes = [x[sl] for sl in sampled_boxes(shape, 32, rate)]
+    scores, unpred = [], 0
+    for c, (a, b) in enumerate(AB_GRID):
+        hist = np.zeros(2 * radius, np.int64)
+        sq = 0
+        for box in boxes:
+            tc = dict(cfg, dims=tuple(box.shape), anchor_log2=Lb, levels=out["levels"],
+                      block_log2=0, frozen_dim=-1, alpha=a, beta=b, md_w=out["md_w"])
+            t = Tiny(box, tc, e)
+            code, W = t.compress()
+            pred = np.ones(box.size, bool)
+            pred[t.anchors()] = False
+            hist += np.bincount(code[pred].astype(np.int64), minlength=2 * radius)
+            inv_e = 1.0 / e
+            for xv, wv in zip(box.reshape(-1)[pred], W[pred]):
+                u = (float(xv) - float(wv)) * inv_e
+                sq += math.floor(u * u * 4294967296.0)
+        n = int(hist.sum())
+        r = np_entropy(hist) + hist[0] * 4 * 8.0 / n
+        score = -10.0 * math.log10((sq + 1.0) / (n * 4294967296.0)) - 20.0 * math.log10(2.0) * r
+        assert rep["ab_sq"][c] == sq, (c, rep["ab_sq"][c], sq)
+        assert abs(rep["ab_rate"][c] - r) <= 1e-12 * max(1.0, r), c
+        assert abs(rep["ab_score"][c] - score) <= 1e-9 * max(1.0, abs(score)), c
+        scores.append(score)
+        unpred += int(hist[0])
+    best = int(np.argmax(scores))  # first maximum: ties to the earlier pair
+    assert rep["ab_choice"] == best
+    assert (out["alpha"], out["beta"]) == AB_GRID[best]
+    assert (best != 0) == nontrivial
+    if radius < 1000:
+        assert unpred > 0
+
+
+def test_alpha_beta_off_keeps_caller_values():
+    """Without tune_ab the caller's alpha and beta pass through unchanged."""
+    x = fields.fronts_field((40, 50, 36))
+    cfg = make_cfg(x.shape, eb=1e-3, alpha=1.5, beta=3.0)
+    out, rep = O.tune(x, cfg, dict(global_rate=0.3, block_wise=0))
+    assert (out["alpha"], out["beta"]) == (1.5, 3.0) and rep["ab_choice"] == -1
