@@ -512,9 +512,9 @@ void canonical_codes_range(const uint8_t* len, uint32_t lo, uint32_t hi, uint32_
 
 int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
                    const uint8_t* h_len, const uint32_t* h_cw, uint32_t sym_min, uint32_t sym_max,
-                   const uint8_t* dlen, const uint32_t* dcw, uint32_t* d_tab, uint64_t* d_flags,
-                   uint32_t* d_ticket, uint32_t* h_tab, uint32_t* payload, uint16_t* chunks,
-                   hipStream_t st)
+                   const uint8_t* dlen, const uint32_t* dcw, uint32_t* d_tab, uint32_t tab_words,
+                   uint64_t* d_flags, uint32_t* d_ticket, uint32_t* h_tab, uint32_t* payload,
+                   uint16_t* chunks, hipStream_t st)
 {
   const uint64_t nch = (N + chunk - 1) / chunk;
   if (!nch) return HPEZ_OK;
@@ -527,16 +527,28 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
   a.smin = sym_min;
   a.ntab = sym_max - sym_min + 1;
   a.lds_tab = a.ntab <= kEncTab;
-  // packed entries (codeword << 6 | length) need codewords of at most 26 bits
-  uint32_t maxlen = 0;
-  for_used(h_len, sym_min, sym_max + 1,
-           [&](uint32_t k) { maxlen = std::max<uint32_t>(maxlen, h_len[k]); });
-  a.packed_ok = maxlen <= 26;
+  // packed entries: codeword << 6 | length up to 26 bits, longer codewords
+  // escaped into a long table placed after the packed one (both must fit the
+  // tab_words of d_tab and h_tab, else the unpacked path takes the full tables)
+  uint32_t nlong = 0;
+  for_used(h_len, sym_min, sym_max + 1, [&](uint32_t k) { nlong += h_len[k] > 26; });
+  const uint64_t loff = ((uint64_t)a.ntab + 1) & ~1ull;  // 8-byte aligned, in words
+  a.packed_ok = loff + 2 * (uint64_t)nlong <= tab_words;
   if (a.packed_ok) {
-    std::memset(h_tab, 0, (size_t)a.ntab * 4);
-    for_used(h_len, sym_min, sym_max + 1,
-             [&](uint32_t k) { h_tab[k - sym_min] = h_cw[k] << 6 | h_len[k]; });
-    if (hipMemcpyAsync(d_tab, h_tab, (size_t)a.ntab * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+    std::memset(h_tab, 0, (size_t)loff * 4);
+    uint64_t* lt = reinterpret_cast<uint64_t*>(h_tab + loff);
+    uint32_t il = 0;
+    for_used(h_len, sym_min, sym_max + 1, [&](uint32_t k) {
+      if (h_len[k] <= 26) {
+        h_tab[k - sym_min] = h_cw[k] << 6 | h_len[k];
+      } else {
+        lt[il] = (uint64_t)h_cw[k] << 6 | h_len[k];
+        h_tab[k - sym_min] = il++ << 6 | 63u;
+      }
+    });
+    a.ltab = nlong ? reinterpret_cast<const uint64_t*>(d_tab + loff) : nullptr;
+    if (hipMemcpyAsync(d_tab, h_tab, (size_t)(loff + 2 * (uint64_t)nlong) * 4,
+                       hipMemcpyHostToDevice, st) != hipSuccess)
       return HPEZ_EDEVICE;
   }
   if (hipMemsetAsync(d_flags, 0, nch * 8, st) != hipSuccess) return HPEZ_EDEVICE;
@@ -549,12 +561,13 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
   return HPEZ_OK;
 }
 
-// The encoder alone, its packed codebook already on the device and its flags
-// and ticket already zero (codewords of at most 26 bits).
+// The encoder alone, its packed codebook (and long table d_ltab when a
+// codeword exceeds 26 bits, else nullptr) already on the device and its flags
+// and ticket already zero.
 int encode_payload_packed(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
                           uint32_t sym_min, uint32_t sym_max, const uint32_t* d_tab,
-                          uint64_t* d_flags, uint32_t* d_ticket, uint32_t* payload,
-                          uint16_t* chunks, hipStream_t st)
+                          const uint64_t* d_ltab, uint64_t* d_flags, uint32_t* d_ticket,
+                          uint32_t* payload, uint16_t* chunks, hipStream_t st)
 {
   const uint64_t nch = (N + chunk - 1) / chunk;
   if (!nch) return HPEZ_OK;
@@ -568,6 +581,7 @@ int encode_payload_packed(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint3
   a.ntab = sym_max - sym_min + 1;
   a.lds_tab = a.ntab <= kEncTab;
   a.packed_ok = true;
+  a.ltab = d_ltab;
   hipEvent_t ev = ctx_span_begin(ctx, st);
   if (launch_encode1(a, code, payload, chunks, d_flags, d_ticket, d_tab, nullptr, nullptr, st) !=
       hipSuccess)
@@ -1271,14 +1285,22 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   const hpez_config* c = J.c;
   const uint64_t s = sizeof(T);
   uint8_t* out = J.out;
-  if (J.maxlen > 26) {
-    // the encoder's unpacked path reads the full length and codeword tables
+  // codewords above 26 bits go to a long table after the packed one
+  uint32_t nlong = 0;
+  if (J.maxlen > 26)
+    for_used(J.h_len, Lo.sym_min, Lo.sym_max + 1, [&](uint32_t k) { nlong += J.h_len[k] > 26; });
+  const uint64_t ntab = Lo.sym_max >= Lo.sym_min ? Lo.sym_max - Lo.sym_min + 1 : 0;
+  const uint64_t loff = (ntab + 1) & ~1ull;  // words, 8-byte aligned
+  if (loff + 2 * (uint64_t)nlong > J.nsym) {
+    // no room for the long table: the encoder's unpacked path reads the full
+    // length and codeword tables
     for (uint32_t k = 0; k < J.nsym; k++)
       if (k < Lo.sym_min || k > Lo.sym_max) J.h_cw[k] = 0;
     HIPCK(hipMemcpyAsync(J.dlen, J.h_len, J.nsym, hipMemcpyHostToDevice, st));
     HIPCK(hipMemcpyAsync(J.dcw, J.h_cw, (size_t)J.nsym * 4, hipMemcpyHostToDevice, st));
   }
-  if (J.early && J.maxlen <= 26 && ((uintptr_t)out & 7) == 0 && Lo.sym_max >= Lo.sym_min) {
+  if (J.early && loff + 2 * (uint64_t)nlong <= J.nsym && ((uintptr_t)out & 7) == 0 &&
+      Lo.sym_max >= Lo.sym_min) {
     // the small sections, the zero fill after the verbatim values and the
     // encoder's flags in one upload and one launch
     if (Lo.off_unpred != J.off_unpred) return HPEZ_EINVAL;
@@ -1286,17 +1308,25 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
     const uint64_t nlen = Lo.sym_max - Lo.sym_min + 1;
     const uint64_t a0 = Lo.off_anchor;               // header + block configurations, padded
     const uint64_t a1 = Lo.off_chunks - Lo.off_len;  // code lengths, padded
-    const uint64_t ntab = nlen;
     uint8_t* h = J.h_stage;
     std::memset(h, 0, a0 + a1);
     std::memcpy(h, J.h_hdr, kHdrBytes);
     if (J.nb) std::memcpy(h + kHdrBytes, c->block_cfg, J.nb);
     std::memcpy(h + a0, J.h_len + Lo.sym_min, nlen);
     uint32_t* tab = reinterpret_cast<uint32_t*>(h + a0 + a1);
-    std::memset(tab, 0, ntab * 4);
-    for_used(J.h_len, Lo.sym_min, Lo.sym_max + 1,
-             [&](uint32_t sy) { tab[sy - Lo.sym_min] = J.h_cw[sy] << 6 | J.h_len[sy]; });
-    HIPCK(hipMemcpyAsync(J.d_stage, h, a0 + a1 + ntab * 4, hipMemcpyHostToDevice, st));
+    uint64_t* lt = reinterpret_cast<uint64_t*>(tab + loff);
+    std::memset(tab, 0, loff * 4);
+    uint32_t il = 0;
+    for_used(J.h_len, Lo.sym_min, Lo.sym_max + 1, [&](uint32_t sy) {
+      if (J.h_len[sy] <= 26) {
+        tab[sy - Lo.sym_min] = J.h_cw[sy] << 6 | J.h_len[sy];
+      } else {
+        lt[il] = (uint64_t)J.h_cw[sy] << 6 | J.h_len[sy];
+        tab[sy - Lo.sym_min] = il++ << 6 | 63u;
+      }
+    });
+    HIPCK(hipMemcpyAsync(J.d_stage, h, a0 + a1 + (loff + 2 * (uint64_t)nlong) * 4,
+                         hipMemcpyHostToDevice, st));
     const uint64_t vz = (vend + 7) & ~7ull;
     ByteSegs sg;
     std::memset(&sg, 0, sizeof sg);
@@ -1313,8 +1343,11 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
     add(reinterpret_cast<uint8_t*>(J.ticket), nullptr, 4);
     HIPCK(launch_byte_segs(sg, st));
     return encode_payload_packed(ctx, J.code, J.N, c->chunk, Lo.sym_min, Lo.sym_max,
-                                 reinterpret_cast<const uint32_t*>(J.d_stage + a0 + a1), J.boff,
-                                 J.ticket, (uint32_t*)(out + Lo.off_payload),
+                                 reinterpret_cast<const uint32_t*>(J.d_stage + a0 + a1),
+                                 nlong ? reinterpret_cast<const uint64_t*>(J.d_stage + a0 + a1 +
+                                                                           loff * 4)
+                                       : nullptr,
+                                 J.boff, J.ticket, (uint32_t*)(out + Lo.off_payload),
                                  (uint16_t*)(out + Lo.off_chunks), st);
   }
   if (J.early) {
@@ -1338,7 +1371,7 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
                                   (T*)(out + Lo.off_unpred), J.g, st));
   }
   return encode_payload(ctx, J.code, J.N, c->chunk, J.h_len, J.h_cw, Lo.sym_min, Lo.sym_max,
-                        J.dlen, J.dcw, J.hist, J.boff, J.ticket, J.h_tab,
+                        J.dlen, J.dcw, J.hist, J.nsym, J.boff, J.ticket, J.h_tab,
                         (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), st);
 }
 

@@ -23,8 +23,12 @@ struct EncodeArgs {
   uint32_t smin;     // first symbol of the packed table
   uint32_t ntab;     // entries of the packed table (smax - smin + 1)
   int32_t lds_tab;   // the packed table fits in LDS
-  int32_t packed_ok; // every codeword fits the packed entry (length <= 26)
+  int32_t packed_ok; // every symbol has a packed entry (below)
   int32_t pad;
+  // Packed entry: codeword << 6 | length for codewords of at most 26 bits;
+  // longer ones (up to 32 bits) are escaped as index << 6 | 63 into ltab,
+  // whose entries are codeword << 6 | length (nullptr when there are none).
+  const uint64_t* ltab;
 };
 
 // Canonical-code decoding state.  A 32-bit window w (next bits, first bit in

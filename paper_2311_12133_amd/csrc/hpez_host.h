@@ -57,9 +57,9 @@ void md_table(const hpez_config* c, double* wq);
 // h_tab (2R words) pinned host scratch.
 int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chunk,
                    const uint8_t* h_len, const uint32_t* h_cw, uint32_t sym_min, uint32_t sym_max,
-                   const uint8_t* dlen, const uint32_t* dcw, uint32_t* d_tab, uint64_t* d_flags,
-                   uint32_t* d_ticket, uint32_t* h_tab, uint32_t* payload, uint16_t* chunks,
-                   hipStream_t st);
+                   const uint8_t* dlen, const uint32_t* dcw, uint32_t* d_tab, uint32_t tab_words,
+                   uint64_t* d_flags, uint32_t* d_ticket, uint32_t* h_tab, uint32_t* payload,
+                   uint16_t* chunks, hipStream_t st);
 
 // Lorenzo alternative (lorenzo.cpp): compress after the error bound is known
 template <typename T>

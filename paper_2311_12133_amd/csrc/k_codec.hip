@@ -67,6 +67,13 @@ __device__ __forceinline__ uint64_t look_back(uint64_t* flags, uint64_t k, int l
   }
 }
 
+// the length of a packed entry (escaped long codewords from the long table)
+__device__ __forceinline__ uint32_t ent_len(uint32_t e, const uint64_t* __restrict__ ltab)
+{
+  const uint32_t L = e & 63u;
+  return L == 63u ? (uint32_t)(ltab[e >> 6] & 63u) : L;
+}
+
 // bit count of one chunk (lane sums of `per` symbols, wave total); ent[]
 // receives the packed entries of the lane's symbols
 // the PER codes of one lane of a full chunk of 64 PER symbols (PER 8 or 16;
@@ -104,7 +111,7 @@ __device__ __forceinline__ uint32_t raw_entries(const EncodeArgs& a, const uint3
     const uint32_t c = ((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) - a.smin;
     const uint32_t e = a.lds_tab ? tab[c] : gtab[c];
     ent[j] = e;
-    bits += e & 63u;
+    bits += ent_len(e, a.ltab);
   }
   lane_bits = bits;
   uint32_t t = bits;
@@ -130,7 +137,7 @@ __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uin
       const uint32_t c = ((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) - a.smin;
       const uint32_t e = a.lds_tab ? tab[c] : gtab[c];
       ent[j] = e;
-      bits += e & 63u;
+      bits += ent_len(e, a.ltab);
     }
   } else {
     for (uint32_t j = 0; j < per; j++) {
@@ -141,7 +148,7 @@ __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uin
         e = a.lds_tab ? tab[c] : gtab[c];
       }
       ent[j] = e;
-      bits += e & 63u;
+      bits += ent_len(e, a.ltab);
     }
   }
   lane_bits = bits;
@@ -158,7 +165,7 @@ __device__ __forceinline__ uint32_t chunk_entries(const EncodeArgs& a, const uin
 // falls back to one or two LDS ORs per codeword.
 __device__ __forceinline__ void pack_chunk(uint32_t* B, uint32_t* __restrict__ words, uint64_t excl,
                                            uint32_t total, uint32_t lb, const uint32_t* ent,
-                                           uint32_t per, int lane)
+                                           uint32_t per, int lane, const uint64_t* __restrict__ ltab)
 {
   uint32_t incl = lb;
   for (int o = 1; o < 64; o <<= 1) {
@@ -179,7 +186,9 @@ __device__ __forceinline__ void pack_chunk(uint32_t* B, uint32_t* __restrict__ w
     unsigned __int128 acc = 0;
     for (uint32_t jj = 0; jj < per; jj++) {
       const uint32_t e = ent[jj];
-      acc = (acc << (e & 63u)) | (unsigned __int128)(e >> 6);
+      uint64_t le = e;
+      if ((e & 63u) == 63u) le = ltab[e >> 6];
+      acc = (acc << (le & 63u)) | (unsigned __int128)(le >> 6);
     }
     if (lb) {
       acc <<= 128 - off0 - lb;
@@ -194,11 +203,13 @@ __device__ __forceinline__ void pack_chunk(uint32_t* B, uint32_t* __restrict__ w
   } else {
     for (uint32_t jj = 0; jj < per; jj++) {
       const uint32_t e = ent[jj];
-      const uint32_t L = e & 63u;
+      uint64_t le = e;
+      if ((e & 63u) == 63u) le = ltab[e >> 6];
+      const uint32_t L = (uint32_t)(le & 63u);
       if (L) {
-        const uint32_t cw = e >> 6;
+        const uint64_t cw = le >> 6;
         const uint32_t wi = pos >> 5, off = pos & 31;
-        const uint64_t v = (uint64_t)cw << (64 - L - off);
+        const uint64_t v = cw << (64 - L - off);
         const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
         if (hi) atomicOr(&B[wi], hi);
         if (lo) atomicOr(&B[wi + 1], lo);
@@ -315,13 +326,13 @@ __global__ void __launch_bounds__(256) encode1_kernel(EncodeArgs a, const uint16
         const uint32_t j = w + c * kEncWaves;
         uint32_t lb;
         const uint32_t total = raw_entries<PER>(a, tab, gtab, raw[c], ent, lb);
-        pack_chunk(B, words, pexcl + cbits[j], total, lb, ent, PER, lane);
+        pack_chunk(B, words, pexcl + cbits[j], total, lb, ent, PER, lane, a.ltab);
       }
     } else {
       for (uint32_t j = w; j < np; j += kEncWaves) {
         uint32_t lb;
         const uint32_t total = chunk_entries(a, code, tab, gtab, k0 + j, lane, ent, lb);
-        pack_chunk(B, words, pexcl + cbits[j], total, lb, ent, per, lane);
+        pack_chunk(B, words, pexcl + cbits[j], total, lb, ent, per, lane, a.ltab);
       }
     }
     __syncthreads();

@@ -119,7 +119,7 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
                        hipMemcpyHostToDevice, st));
   LCK(launch_count_zeros(code, N, c->chunk, czero, zoff, t3, st));
   rc = encode_payload(ctx, code, N, c->chunk, h_len, cw.data(), Lo.sym_min, Lo.sym_max, dlen, dcw,
-                      hist, boff, (uint32_t*)bad, h_tab, (uint32_t*)(out + Lo.off_payload),
+                      hist, nsym, boff, (uint32_t*)bad, h_tab, (uint32_t*)(out + Lo.off_payload),
                       (uint16_t*)(out + Lo.off_chunks), st);
   if (rc) return rc;
   LCK(launch_lorenzo_gather<T>(X, g, N, a, code, czero, zoff, pcount, poff,
