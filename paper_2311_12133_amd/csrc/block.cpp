@@ -137,7 +137,10 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
   const int nact = n_active(g);
   int64_t r[4], m[4];
   J.face_pts = 0;
-  for (int l = 0; l <= 16; l++) J.steps[l].clear();
+  for (int l = 0; l <= 16; l++) {
+    J.steps[l].clear();
+    J.sgrp[l].clear();
+  }
   // coarse face levels on whole planes when every plane's lattice fits
   J.npj = 0;
   J.plane_lds = 0;
@@ -201,7 +204,9 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
     a.inv2e = 1.0 / (2.0 * el);
     a.twoe = 2.0 * el;
     a.R = c->radius;
-    // one step over every family whose planes the step touches
+    // one step over every family whose planes the step touches; steps of one
+    // group have no point in common and read none of each other's points
+    int grp = 0;
     auto step = [&](const int64_t* rr, const int64_t* mm) {
       for (int k = 0; k < 4; k++) {
         a.first[k] = rr[k];
@@ -222,6 +227,7 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
       }
       J.face_pts += a.off[4];
       J.steps[l].push_back(a);
+      J.sgrp[l].push_back(grp);
     };
     if (ip.md) {
       for (int cnt = 1; cnt <= nact; cnt++)
@@ -237,6 +243,7 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
           }
           a.odd = odd;
           for (int k = 0; k < 4; k++) a.wq[k] = J.h_wq[(ip.kind * 16 + odd) * 4 + k];
+          grp = cnt - 1;  // Sec. 5.4.1: one sub-step per number of odd coordinates
           step(r, m);
         }
     } else {
@@ -257,17 +264,21 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
         }
         a.pdim = pd;
         a.odd = 0;
+        // 1D passes (and their same-level halves) depend on each other
         if (ip.kind != 0 && ip.same_level) {
           m[pd] = 4 * s;
           r[pd] = s;
           a.sl = 0;
+          grp = 2 * k;
           step(r, m);
           r[pd] = 3 * s;
           a.sl = 1;
+          grp = 2 * k + 1;
           step(r, m);
           a.sl = 0;
         } else {
           a.sl = 0;
+          grp = k;
           step(r, m);
         }
       }
@@ -375,12 +386,15 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   size_t ei = 0, wi = 0;
   uint64_t face_pts = 0;
   for (int l = Lmax; l >= 1; l--) {
-    size_t mx = 0;
-    for (int j = 0; j < n; j++) mx = std::max(mx, jobs[j].steps[l].size());
-    for (size_t k = 0; k < mx; k++) {
+    // one launch per step group, over every job's steps of that group
+    int ng = 0;
+    for (int j = 0; j < n; j++)
+      if (!jobs[j].sgrp[l].empty()) ng = std::max(ng, jobs[j].sgrp[l].back() + 1);
+    for (int gi = 0; gi < ng; gi++) {
       Launch L{ei, wi, 0, 0, true};
-      for (int j = 0; j < n; j++) {
-        if (jobs[j].steps[l].size() <= k) continue;
+      for (int j = 0; j < n; j++)
+      for (size_t k = 0; k < jobs[j].steps[l].size(); k++) {
+        if (jobs[j].sgrp[l][k] != gi) continue;
         const FaceStep& a = jobs[j].steps[l][k];
         const uint64_t tot = a.off[4];
         if (!tot) continue;

@@ -124,8 +124,6 @@ struct FBlock {
   uint32_t nR;
 };
 
-constexpr int kFU = 4;  // points per lane in flight
-
 // Linear stencil of an interior point (x + s <= last along its dim, so the
 // first rung of the ladder applies): Eq. (2).
 template <typename T>
@@ -134,17 +132,17 @@ __device__ __forceinline__ T flin(const T* L, int32_t li, const FOff& o)
   return (L[li + o.b] + L[li + o.c]) * (T)0.5;
 }
 
-// One step: the points whose dim-d coordinate is of class cls_d at stride s;
+// One step: the points whose dim-d coordinate is of class cls_d at stride S;
 // pd >= 0 a 1D pass along pd, else multi-dimensional over the odd set `odd`
 // with weights w0..w2 summed left to right (ascending dims).  INNER: every
 // stencil dim of the step has its far face in the box (last = 32), so every
 // point has its c neighbour.  Decompressing, each cell of an interior point
 // holds its code (loaded with the box) until the point is reconstructed.
-template <typename T, int KIND, int SL, bool MD, int MODE, int NT, bool INNER>
-__device__ __forceinline__ void fstep(FBlock<T>& fb, int s, int cls0, int cls1, int cls2, int pd,
+template <typename T, int KIND, int SL, bool MD, int MODE, int NT, bool INNER, int S>
+__device__ __forceinline__ void fstep(FBlock<T>& fb, int cls0, int cls1, int cls2, int pd,
                                       unsigned odd, T w0, T w1, T w2)
 {
-  const FRange r0 = frange(cls0, s), r1 = frange(cls1, s), r2 = frange(cls2, s);
+  const FRange r0 = frange(cls0, S), r1 = frange(cls1, S), r2 = frange(cls2, S);
   const int32_t l12 = r1.l + r2.l;
   const int32_t t = (int32_t)threadIdx.x;
   const int32_t i2 = t & ((1 << r2.l) - 1);
@@ -163,7 +161,7 @@ __device__ __forceinline__ void fstep(FBlock<T>& fb, int s, int cls0, int cls1, 
   const int32_t cb12 = c1 * 32 + c2;
   // plain values (a select between fields of fb would keep fb in memory)
   const int32_t last0 = fb.last0, last1 = fb.last1, last2 = fb.last2;
-  const FOff f0 = foff(s, kFP0), f1 = foff(s, kFP1), f2 = foff(s, 1);
+  const FOff f0 = foff(S, kFP0), f1 = foff(S, kFP1), f2 = foff(S, 1);
   const FOff fp = pd == 0 ? f0 : (pd == 1 ? f1 : f2);
   const int32_t lastp = pd == 0 ? last0 : (pd == 1 ? last1 : last2);
   const int32_t r0f = r0.f, r0t = r0.t;
@@ -172,59 +170,57 @@ __device__ __forceinline__ void fstep(FBlock<T>& fb, int s, int cls0, int cls1, 
   const uint32_t R = fb.R, lo = fb.lo;
   const double el = fb.el, inv2e = fb.inv2e, twoe = fb.twoe;
   uint32_t nR = 0;
-  for (; i0 < n0; i0 += kFU * di0) {
-#pragma unroll
-    for (int u = 0; u < kFU; u++) {
-      const int32_t ii = i0 + u * di0;
-      if (ii >= n0 || (gap0 && ii == 15)) continue;
-      const int32_t s0 = r0f + ii * r0t;
-      const int32_t li = s0 * kFP0 + base12;
-      const int32_t c0 = fcoord(s0);
-      T p;
-      if (!MD) {
-        const int32_t xd = pd == 0 ? c0 : (pd == 1 ? c1 : c2);
-        p = (INNER && KIND == 0) ? flin<T>(L, li, fp) : fstencil<T, KIND, SL>(L, li, fp, xd, s, lastp);
-      } else {
-        bool first = true;
-        T acc = (T)0;
-        if (odd & 1u) {
-          acc = w0 * ((INNER && KIND == 0) ? flin<T>(L, li, f0)
-                                           : fstencil<T, KIND, 0>(L, li, f0, c0, s, last0));
-          first = false;
-        }
-        if (odd & 2u) {
-          const T v = w1 * ((INNER && KIND == 0) ? flin<T>(L, li, f1)
-                                                 : fstencil<T, KIND, 0>(L, li, f1, c1, s, last1));
-          acc = first ? v : acc + v;
-          first = false;
-        }
-        if (odd & 4u) {
-          const T v = w2 * ((INNER && KIND == 0) ? flin<T>(L, li, f2)
-                                                 : fstencil<T, KIND, 0>(L, li, f2, c2, s, last2));
-          acc = first ? v : acc + v;
-        }
-        p = acc;
+  // one point per round: the registers of more points in flight cost more
+  // than their overlapped LDS latency gains (a work-group fills the CU)
+  for (; i0 < n0; i0 += di0) {
+    if (gap0 && i0 == 15) continue;
+    const int32_t s0 = r0f + i0 * r0t;
+    const int32_t li = s0 * kFP0 + base12;
+    const int32_t c0 = fcoord(s0);
+    T p;
+    if (!MD) {
+      const int32_t xd = pd == 0 ? c0 : (pd == 1 ? c1 : c2);
+      p = (INNER && KIND == 0) ? flin<T>(L, li, fp) : fstencil<T, KIND, SL>(L, li, fp, xd, S, lastp);
+    } else {
+      bool first = true;
+      T acc = (T)0;
+      if (odd & 1u) {
+        acc = w0 * ((INNER && KIND == 0) ? flin<T>(L, li, f0)
+                                         : fstencil<T, KIND, 0>(L, li, f0, c0, S, last0));
+        first = false;
       }
-      if (MODE == 0) {
-        const T xv = L[li];
-        T xr = xv;
-        const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
-        fb.code[(uint32_t)(c0 * 1024 + cb12)] = (uint16_t)q;
-        L[li] = xr;
-        nR += q == R;
-        if (q != R) {
-          const uint32_t w = q - lo;
-          if (w < (uint32_t)kBlockHistWin)
-            __hip_atomic_fetch_add(&fb.lh[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          else
-            __hip_atomic_fetch_add(&fb.hist[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      } else {
-        static_assert(MODE == 0 || sizeof(T) == 4, "codes held in float cells");
-        const uint32_t q = __float_as_uint((float)L[li]);
-        L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
-                  : fb.out[(fb.o0 + c0) * fb.st0 + (fb.o1 + c1) * fb.st1 + (fb.o2 + c2)];
+      if (odd & 2u) {
+        const T v = w1 * ((INNER && KIND == 0) ? flin<T>(L, li, f1)
+                                               : fstencil<T, KIND, 0>(L, li, f1, c1, S, last1));
+        acc = first ? v : acc + v;
+        first = false;
       }
+      if (odd & 4u) {
+        const T v = w2 * ((INNER && KIND == 0) ? flin<T>(L, li, f2)
+                                               : fstencil<T, KIND, 0>(L, li, f2, c2, S, last2));
+        acc = first ? v : acc + v;
+      }
+      p = acc;
+    }
+    if (MODE == 0) {
+      const T xv = L[li];
+      T xr = xv;
+      const uint32_t q = quantize<T>(xv, p, inv2e, twoe, el, R, xr);
+      fb.code[(uint32_t)(c0 * 1024 + cb12)] = (uint16_t)q;
+      L[li] = xr;
+      nR += q == R;
+      if (q != R) {
+        const uint32_t w = q - lo;
+        if (w < (uint32_t)kBlockHistWin)
+          __hip_atomic_fetch_add(&fb.lh[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_add(&fb.hist[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {
+      static_assert(MODE == 0 || sizeof(T) == 4, "codes held in float cells");
+      const uint32_t q = __float_as_uint((float)L[li]);
+      L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
+                : fb.out[(fb.o0 + c0) * fb.st0 + (fb.o1 + c1) * fb.st1 + (fb.o2 + c2)];
     }
   }
   fb.nR += nR;
@@ -232,39 +228,39 @@ __device__ __forceinline__ void fstep(FBlock<T>& fb, int s, int cls0, int cls1, 
 
 // runtime kind / same-level / paradigm to the compiled step; linear steps whose
 // stencil dims all reach their far face take the interior form
-template <typename T, int MODE, int NT>
-__device__ __forceinline__ void fstep_any(FBlock<T>& fb, int kind, int sl, bool md, int s, int c0,
-                                          int c1, int c2, int pd, unsigned odd, T w0, T w1, T w2)
+template <typename T, int MODE, int NT, int S>
+__device__ __forceinline__ void fstep_any(FBlock<T>& fb, int kind, int sl, bool md, int c0, int c1,
+                                          int c2, int pd, unsigned odd, T w0, T w1, T w2)
 {
   const unsigned dims = md ? odd : (1u << pd);
   const bool inner = (!(dims & 1u) || fb.last0 == 32) && (!(dims & 2u) || fb.last1 == 32) &&
                      (!(dims & 4u) || fb.last2 == 32);
   if (md) {
-    if (kind == 0 && inner) fstep<T, 0, 0, true, MODE, NT, true>(fb, s, c0, c1, c2, -1, odd, w0, w1, w2);
-    else if (kind == 0) fstep<T, 0, 0, true, MODE, NT, false>(fb, s, c0, c1, c2, -1, odd, w0, w1, w2);
-    else if (kind == 1) fstep<T, 1, 0, true, MODE, NT, false>(fb, s, c0, c1, c2, -1, odd, w0, w1, w2);
-    else fstep<T, 2, 0, true, MODE, NT, false>(fb, s, c0, c1, c2, -1, odd, w0, w1, w2);
+    if (kind == 0 && inner) fstep<T, 0, 0, true, MODE, NT, true, S>(fb, c0, c1, c2, -1, odd, w0, w1, w2);
+    else if (kind == 0) fstep<T, 0, 0, true, MODE, NT, false, S>(fb, c0, c1, c2, -1, odd, w0, w1, w2);
+    else if (kind == 1) fstep<T, 1, 0, true, MODE, NT, false, S>(fb, c0, c1, c2, -1, odd, w0, w1, w2);
+    else fstep<T, 2, 0, true, MODE, NT, false, S>(fb, c0, c1, c2, -1, odd, w0, w1, w2);
     return;
   }
-  if (kind == 0 && inner) fstep<T, 0, 0, false, MODE, NT, true>(fb, s, c0, c1, c2, pd, 0u, w0, w1, w2);
-  else if (kind == 0) fstep<T, 0, 0, false, MODE, NT, false>(fb, s, c0, c1, c2, pd, 0u, w0, w1, w2);
-  else if (kind == 1 && sl) fstep<T, 1, 1, false, MODE, NT, false>(fb, s, c0, c1, c2, pd, 0u, w0, w1, w2);
-  else if (kind == 1) fstep<T, 1, 0, false, MODE, NT, false>(fb, s, c0, c1, c2, pd, 0u, w0, w1, w2);
-  else if (sl) fstep<T, 2, 1, false, MODE, NT, false>(fb, s, c0, c1, c2, pd, 0u, w0, w1, w2);
-  else fstep<T, 2, 0, false, MODE, NT, false>(fb, s, c0, c1, c2, pd, 0u, w0, w1, w2);
+  if (kind == 0 && inner) fstep<T, 0, 0, false, MODE, NT, true, S>(fb, c0, c1, c2, pd, 0u, w0, w1, w2);
+  else if (kind == 0) fstep<T, 0, 0, false, MODE, NT, false, S>(fb, c0, c1, c2, pd, 0u, w0, w1, w2);
+  else if (kind == 1 && sl) fstep<T, 1, 1, false, MODE, NT, false, S>(fb, c0, c1, c2, pd, 0u, w0, w1, w2);
+  else if (kind == 1) fstep<T, 1, 0, false, MODE, NT, false, S>(fb, c0, c1, c2, pd, 0u, w0, w1, w2);
+  else if (sl) fstep<T, 2, 1, false, MODE, NT, false, S>(fb, c0, c1, c2, pd, 0u, w0, w1, w2);
+  else fstep<T, 2, 0, false, MODE, NT, false, S>(fb, c0, c1, c2, pd, 0u, w0, w1, w2);
 }
 
-// One level (stride s = 2 or 1) of a full block with configuration c, each
+// One level (stride S = 2 or 1) of a full block with configuration c, each
 // step followed by a work-group barrier (as box_level).
-template <typename T, int MODE, int NT>
-__device__ __forceinline__ void flevel(const hpez_interp& c, FBlock<T>& fb, int s, const double* wmd)
+template <typename T, int MODE, int NT, int S>
+__device__ __forceinline__ void flevel(const hpez_interp& c, FBlock<T>& fb, const double* wmd)
 {
   if (c.md) {
     for (int cnt = 1; cnt <= 3; cnt++) {
       for (unsigned odd = 1; odd < 8; odd++) {
         if ((int)__popc(odd) != cnt) continue;
         const double* w = wmd + (c.kind * 8 + odd) * 4;
-        fstep_any<T, MODE, NT>(fb, c.kind, 0, true, s, (odd & 1u) ? kOdd : kEven,
+        fstep_any<T, MODE, NT, S>(fb, c.kind, 0, true, (odd & 1u) ? kOdd : kEven,
                                (odd & 2u) ? kOdd : kEven, (odd & 4u) ? kOdd : kEven, -1, odd,
                                (T)w[0], (T)w[1], (T)w[2]);
       }
@@ -292,7 +288,7 @@ __device__ __forceinline__ void flevel(const hpez_interp& c, FBlock<T>& fb, int 
       const int cl0 = pd == 0 ? pc : ((earlier & 1u) ? kAny : kEven);
       const int cl1 = pd == 1 ? pc : ((earlier & 2u) ? kAny : kEven);
       const int cl2 = pd == 2 ? pc : ((earlier & 4u) ? kAny : kEven);
-      fstep_any<T, MODE, NT>(fb, c.kind, half, false, s, cl0, cl1, cl2, pd, 0u, (T)0, (T)0, (T)0);
+      fstep_any<T, MODE, NT, S>(fb, c.kind, half, false, cl0, cl1, cl2, pd, 0u, (T)0, (T)0, (T)0);
       __syncthreads();
     }
     earlier |= 1u << pd;

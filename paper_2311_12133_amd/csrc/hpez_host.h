@@ -160,6 +160,9 @@ struct BlockJobHost {
   size_t plane_lds = 0;
   BlockArgs ba;
   std::vector<FaceStep> steps[17];
+  // per step its group: consecutive steps of a level with the same group are
+  // independent (the odd sets of one multi-dimensional sub-step) and share a launch
+  std::vector<int> sgrp[17];
   uint64_t nblocks = 0, npts = 0, face_pts = 0;
   size_t lds = 0;
 };

@@ -1101,7 +1101,8 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
           fb.el = a.el_l[l];
           fb.inv2e = a.inv2e_l[l];
           fb.twoe = a.twoe_l[l];
-          flevel<T, MODE, NT>(c, fb, 1 << (l - 1), a.wmd);
+          if (l == 2) flevel<T, MODE, NT, 2>(c, fb, a.wmd);
+          else flevel<T, MODE, NT, 1>(c, fb, a.wmd);
         }
         nR = fb.nR;
       }
