@@ -272,6 +272,86 @@ int hpez_tune_batch(hpez_ctx* ctx, int n, const hpez_field_desc* desc, const voi
  * such a field, beyond the caller's input and output buffers.  Pure. */
 int hpez_footprint(const hpez_field_desc* desc, const hpez_config* cfg, int op, uint64_t* bytes);
 
+/* Quality of a reconstruction xr of the field x: the functions M of the
+ * requirement M(X, X') >= m0 in Sec. 3.1, Eq. (1).
+ *   value_range  L = max(x) - min(x);
+ *   max_abs_err  max |x - xr|;
+ *   mse, psnr    mean (x - xr)^2 and 20 log10(L) - 10 log10(mse) (+inf when
+ *                mse = 0, -inf when L = 0 < mse);
+ *   ssim         mean over windows of the structural similarity
+ *                ((2 mx my + C1)(2 sxy + C2)) / ((mx^2 + my^2 + C1)(sx^2 + sy^2 + C2)),
+ *                C1 = (0.01 L)^2, C2 = (0.03 L)^2 (L taken as 1 when 0),
+ *                population moments, uniform weights; windows are boxes of side
+ *                w along every dim of size > 1 (a dim shorter than w is one
+ *                window wide), without overlap from the origin; the partial
+ *                windows at the far ends are left out (n_windows counts the
+ *                others).
+ * All sums are float64 in an order fixed by the sizes alone, so repeated
+ * evaluations give the same bits. */
+typedef struct {
+  uint64_t n;
+  uint64_t n_windows;
+  double value_range;
+  double max_abs_err;
+  double mse;
+  double psnr;
+  double ssim;
+} hpez_quality;
+
+enum { HPEZ_METRIC_PSNR = 0, HPEZ_METRIC_SSIM = 1 };
+
+/* Evaluate hpez_quality of d_xr against d_x (device arrays of desc's dtype and
+ * dims; desc's bound fields are ignored).  ssim_window: window side w (0 = 8,
+ * at most 64).  HPEZ_EINVAL for non-finite values.  Synchronous. */
+int hpez_quality_eval(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_x, const void* d_xr,
+                      uint32_t ssim_window, hpez_quality* out, hipStream_t stream);
+
+/* Options of hpez_fit_eb.
+ *   metric            HPEZ_METRIC_PSNR or HPEZ_METRIC_SSIM (target < 1);
+ *   target            m0: the reconstruction must reach metric >= m0;
+ *   steps_per_octave  G of the bound grid e_k = L 2^(k / G) (0 = 64);
+ *   max_iter          compressions at most (0 = 12, at most 64);
+ *   ssim_window       as in hpez_quality_eval (0 = 8). */
+typedef struct {
+  int32_t metric;
+  uint32_t steps_per_octave;
+  double target;
+  uint32_t max_iter;
+  uint32_t ssim_window;
+} hpez_fit_opts;
+
+/* Result of hpez_fit_eb: e (absolute bound, 0 when no tried bound met the
+ * target), the quality and stream size of the compression at e, the number of
+ * compressions run, and e_hi, the smallest tried bound that missed the target
+ * (+inf when none did). */
+typedef struct {
+  double e;
+  double e_hi;
+  hpez_quality quality;
+  uint64_t bytes;
+  uint32_t iterations;
+  uint32_t pad;
+} hpez_fit_result;
+
+/* The largest error bound on the grid e_k = L 2^(k / G) (L = value range of
+ * the field) found whose compression of d_in under cfg meets the quality
+ * requirement of Eq. (1), M(X, X') >= m0 (the compression ratio grows with
+ * the bound, so this is the ratio-optimal bound for the requirement).  Search:
+ * k starts at the model guess (PSNR: uniform errors on [-e, e], MSE = e^2 / 3;
+ * SSIM: e = L / 1000); each step compresses and decompresses the whole field
+ * at e_k on the device and measures the metric; met targets raise the floor
+ * k_lo, missed ones lower the ceiling k_hi; the next k is the model step
+ * (PSNR: 20 dB per decade of e; SSIM: deficit 1 - SSIM as e^2; at least one
+ * step, at most four octaves) until both exist, then floor((k_lo + k_hi) / 2);
+ * it ends when k_hi - k_lo <= 1 or after max_iter compressions.  desc's bound
+ * fields are ignored (the compressions use absolute bounds); cfg as in
+ * hpez_compress.  A constant field gives e = 0 (any bound reproduces it).
+ * Allocates two device buffers for the trial stream and reconstruction.
+ * Synchronous. */
+int hpez_fit_eb(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
+                const hpez_config* cfg, const hpez_fit_opts* opts, hpez_fit_result* res,
+                hipStream_t stream);
+
 /* Per-kernel timing (tracing aid).  While enabled, every kernel group the
  * context launches is bracketed by HIP events on its stream; each entry point
  * folds the elapsed times into per-name totals before returning.  `bytes` is

@@ -55,6 +55,22 @@ class TuneOpts(C.Structure):
                 ("pad", C.c_uint8 * 2)]
 
 
+class Quality(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("n_windows", C.c_uint64), ("value_range", C.c_double),
+                ("max_abs_err", C.c_double), ("mse", C.c_double), ("psnr", C.c_double),
+                ("ssim", C.c_double)]
+
+
+class FitOpts(C.Structure):
+    _fields_ = [("metric", C.c_int32), ("steps_per_octave", C.c_uint32), ("target", C.c_double),
+                ("max_iter", C.c_uint32), ("ssim_window", C.c_uint32)]
+
+
+class FitResult(C.Structure):
+    _fields_ = [("e", C.c_double), ("e_hi", C.c_double), ("quality", Quality),
+                ("bytes", C.c_uint64), ("iterations", C.c_uint32), ("pad", C.c_uint32)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("bytes", C.c_uint64),
                 ("total_ms", C.c_double)]
@@ -64,7 +80,8 @@ EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_
            "hpez_compress_bound", "hpez_compress", "hpez_inspect", "hpez_decompress",
            "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read",
            "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch",
-           "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc"]
+           "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc",
+           "hpez_quality_eval", "hpez_fit_eb"]
 
 _lib = None
 _lock = threading.Lock()
@@ -104,6 +121,9 @@ def lib():
             L.hpez_ctx_trim.argtypes = [vp, u64]
             L.hpez_ctx_set_limit.argtypes = [vp, u64]
             L.hpez_ctx_workspace.argtypes = [vp, P(u64)]
+            L.hpez_quality_eval.argtypes = [vp, P(FieldDesc), vp, vp, C.c_uint32, P(Quality), vp]
+            L.hpez_fit_eb.argtypes = [vp, P(FieldDesc), vp, P(Config), P(FitOpts), P(FitResult),
+                                      vp]
             _lib = L
     return _lib
 
@@ -510,6 +530,50 @@ def decompress_batch(streams, stream=None, outs=None, context=None, rcs_out=None
         rcs_out[:] = [int(rcs[i]) for i in range(n)]
     _check(rc, "hpez_decompress_batch")
     return res
+
+
+def _quality_dict(q: Quality) -> dict:
+    return dict(n=q.n, value_range=q.value_range, max_abs_err=q.max_abs_err, mse=q.mse,
+                psnr=q.psnr, ssim=q.ssim, n_windows=q.n_windows)
+
+
+def quality(x, xr, window: int = 8, stream=None, context=None) -> dict:
+    """hpez_quality_eval: value range, max error, MSE, PSNR and windowed SSIM of
+    the device reconstruction xr of the device field x (Sec. 3.1, Eq. 1)."""
+    if not (x.is_cuda and xr.is_cuda and x.is_contiguous() and xr.is_contiguous()):
+        raise ValueError("x and xr must be contiguous device tensors")
+    if x.shape != xr.shape or x.dtype != xr.dtype:
+        raise ValueError("x and xr differ in shape or dtype")
+    d = desc_from(tuple(x.shape) if x.dim() else (1,), _dtype_of(x), 1.0, "abs")
+    q = Quality()
+    _check(lib().hpez_quality_eval(_cx(context, x.device.index or 0), C.byref(d),
+                                   C.c_void_p(x.data_ptr()), C.c_void_p(xr.data_ptr()), window,
+                                   C.byref(q), _stream_ptr(stream)), "hpez_quality_eval")
+    return _quality_dict(q)
+
+
+def fit_eb(x, cfg: dict, metric: str, target: float, steps_per_octave: int = 64,
+           max_iter: int = 12, window: int = 8, stream=None, context=None) -> dict:
+    """hpez_fit_eb: the largest bound e = L 2^(k / G) found whose compression of
+    x under cfg reaches metric ("psnr" or "ssim") >= target.  Returns e, e_hi,
+    the quality and stream size at e, and the number of compressions."""
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous device tensor")
+    keep = []
+    d = desc_from(tuple(x.shape) if x.dim() else (1,), _dtype_of(x), 1.0, "abs")
+    c = config_from(cfg, keep)
+    o = FitOpts()
+    o.metric = {"psnr": 0, "ssim": 1}[metric]
+    o.steps_per_octave = steps_per_octave
+    o.target = target
+    o.max_iter = max_iter
+    o.ssim_window = window
+    r = FitResult()
+    _check(lib().hpez_fit_eb(_cx(context, x.device.index or 0), C.byref(d),
+                             C.c_void_p(x.data_ptr()), C.byref(c), C.byref(o), C.byref(r),
+                             _stream_ptr(stream)), "hpez_fit_eb")
+    return dict(e=r.e, e_hi=r.e_hi, quality=_quality_dict(r.quality), bytes=r.bytes,
+                iterations=r.iterations)
 
 
 def profile_enable(device: int = 0, on: bool = True):

@@ -615,12 +615,17 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
   return hipGetLastError();
 }
 
+// histogram blockIdx.y of a set: its bins at hist + y nsym, its count at
+// count[y], its pairs at pairs + y 2 cap
 __global__ void __launch_bounds__(256) hist_nonzero_kernel(const uint32_t* __restrict__ hist,
                                                            uint32_t nsym, uint32_t* __restrict__ count,
                                                            uint32_t* __restrict__ pairs, uint32_t cap)
 {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nsym) return;
+  hist += (size_t)blockIdx.y * nsym;
+  count += blockIdx.y;
+  pairs += (size_t)blockIdx.y * 2 * cap;
   const uint32_t c = hist[k];
   if (!c) return;
   const uint32_t i = atomicAdd(count, 1u);
@@ -636,6 +641,16 @@ hipError_t launch_hist_nonzero(const uint32_t* d_hist, uint32_t nsym, uint32_t* 
   if (!nsym) return hipSuccess;
   hipLaunchKernelGGL(hist_nonzero_kernel, dim3((nsym + 255) / 256), dim3(256), 0, st, d_hist, nsym,
                      d_count, d_pairs, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_nonzero_set(const uint32_t* d_hist, uint32_t nsym, uint32_t n,
+                                   uint32_t* d_count, uint32_t* d_pairs, uint32_t cap,
+                                   hipStream_t st)
+{
+  if (!nsym || !n) return hipSuccess;
+  hipLaunchKernelGGL(hist_nonzero_kernel, dim3((nsym + 255) / 256, n), dim3(256), 0, st, d_hist,
+                     nsym, d_count, d_pairs, cap);
   return hipGetLastError();
 }
 

@@ -852,9 +852,7 @@ template <typename T>
 int t_ab_copy(TJob<T>& J, hipStream_t st)
 {
   if (J.done || !J.ab) return HPEZ_OK;
-  for (int c = 0; c < kNAB; c++)
-    TCK(launch_hist_nonzero(J.abhist + (size_t)c * J.nsym, J.nsym, J.abnzn + c,
-                            J.abnz + (size_t)c * 2 * kNzCap, kNzCap, st));
+  TCK(launch_hist_nonzero_set(J.abhist, J.nsym, kNAB, J.abnzn, J.abnz, kNzCap, st));
   TCK(hipMemcpyAsync(J.h_abnz, J.abnz, (size_t)kNAB * 2 * kNzCap * 4, hipMemcpyDeviceToHost, st));
   TCK(hipMemcpyAsync(J.h_abnzn, J.abnzn, (size_t)kNAB * 4, hipMemcpyDeviceToHost, st));
   TCK(hipMemcpyAsync(J.h_absq, J.absq, (size_t)kNAB * 8, hipMemcpyDeviceToHost, st));

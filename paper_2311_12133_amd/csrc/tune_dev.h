@@ -101,6 +101,11 @@ hipError_t launch_lorenzo_trial(const Geom& fg, const TrialBox* d_boxes, uint32_
 constexpr uint32_t kNzCap = 2048;
 hipError_t launch_hist_nonzero(const uint32_t* d_hist, uint32_t nsym, uint32_t* d_count,
                                uint32_t* d_pairs, uint32_t cap, hipStream_t st);
+// the same for n histograms stored back to back (nsym bins each): counts
+// d_count[0, n), pairs of histogram i at d_pairs + 2 cap i
+hipError_t launch_hist_nonzero_set(const uint32_t* d_hist, uint32_t nsym, uint32_t n,
+                                   uint32_t* d_count, uint32_t* d_pairs, uint32_t cap,
+                                   hipStream_t st);
 // first code of a kTrialHistWin-wide window centred on R inside [0, 2R)
 inline uint32_t trial_hist_lo(uint32_t R)
 {
