@@ -177,6 +177,18 @@ def main():
     if not err <= e:
         raise SystemExit(f"error bound violated: {err} > {e}")
 
+    # quality of the last reconstruction (Eq. 1's M): PSNR and SSIM on the device,
+    # outside the timed steps
+    qual = binding.quality(xt, rec)
+    torch.cuda.synchronize()
+    tq = time.perf_counter()
+    for _ in range(3):
+        binding.quality(xt, rec)
+    q_ms = (time.perf_counter() - tq) / 3 * 1e3
+    quality = dict(psnr=round(qual["psnr"], 4), ssim=round(qual["ssim"], 8),
+                   max_err_over_eb=round(qual["max_abs_err"] / e, 6), ssim_window=8,
+                   eval_ms=round(q_ms, 3), eval_GBps=round(2 * nbytes / (q_ms * 1e-3) / 1e9, 1))
+
     tune_s = sum(t[0] for t in times) / len(times)
     comp_s = sum(t[1] for t in times) / len(times)
     dec_s = sum(t[2] for t in times) / len(times)
@@ -255,6 +267,7 @@ def main():
         "compression_ratio": round(nbytes / size, 3),
         "bits_per_value": round(size * 8 / x.size, 4),
         "max_err_over_eb": round(err / e, 6),
+        "quality": quality,
         "roofline": roofline,
         "calls_roofline": calls,
         "kernel_groups": groups,
@@ -534,8 +547,10 @@ def serving_section(args, binding, fields, torch, compress_gbps):
 
 # Sources whose change invalidates a stored traffic measurement of a kernel group.
 TRAFFIC_SOURCES = {
-    "blocks_predict": ["k_block.hip", "box_dev.h", "interp_dev.h", "block_dev.h", "block.cpp"],
-    "blocks_reconstruct": ["k_block.hip", "box_dev.h", "interp_dev.h", "block_dev.h", "block.cpp"],
+    "blocks_predict": ["k_block.hip", "box_dev.h", "fblock_dev.h", "interp_dev.h", "block_dev.h",
+                       "block.cpp"],
+    "blocks_reconstruct": ["k_block.hip", "box_dev.h", "fblock_dev.h", "interp_dev.h",
+                           "block_dev.h", "block.cpp"],
 }
 
 

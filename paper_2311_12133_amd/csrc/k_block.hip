@@ -802,30 +802,64 @@ __device__ __forceinline__ BoxItems box_items(const Box& bx)
   return b;
 }
 
-// the values of one item (cnt <= 4 cells; wr marks cells that are loaded)
+// Where item `it` of a box goes: its cells (box row c0, c1, cells cb .. cb +
+// cnt - 1 along dim 2), their LDS base, and which of them are loaded (wr):
+// face cells from the face arrays, interior cells from the field (compress,
+// cell 32 excluded: the next block's face) or from the codes (decompressing
+// a full block), and the row's dim-2 face cell.
+struct ItemPos {
+  int32_t c0, c1, cb, cnt;
+  int32_t lbase;
+  uint32_t wr;
+  bool face0, face1, face2;
+};
+
+template <int MODE>
+__device__ __forceinline__ ItemPos item_pos(const Box& bx, const BoxItems& bi, uint32_t it, bool fast)
+{
+  ItemPos p;
+  p.wr = 0;
+  p.lbase = 0;
+  p.c0 = p.c1 = p.cb = p.cnt = 0;
+  p.face0 = p.face1 = p.face2 = false;
+  if (it >= bi.nitems) return p;
+  p.c0 = (int32_t)fdiv(it, bi.mgr);
+  const uint32_t rr = it - (uint32_t)p.c0 * bi.rowq;
+  p.c1 = (int32_t)fdiv(rr, bi.mgq);
+  p.cb = 4 * (int32_t)(rr - (uint32_t)p.c1 * bi.nq);
+  p.cnt = bi.E2 - p.cb < 4 ? bi.E2 - p.cb : 4;
+  // row-major box, or the parity-split slots of a full block (cb even)
+  p.lbase = fast ? fslot(p.c0) * kFP0 + fslot(p.c1) * kFP1 + (p.cb >> 1)
+                 : (p.c0 * bi.E1 + p.c1) * bi.E2 + p.cb;
+  p.face0 = bx.a0 && (p.c0 == 0 || p.c0 == kBrick);
+  p.face1 = !p.face0 && bx.a1 && (p.c1 == 0 || p.c1 == kBrick);
+  p.face2 = !p.face0 && !p.face1 && bx.a2 && (p.cb == 0 || p.cb == kBrick);
+  const bool interior = !p.face0 && !p.face1 && p.cb < kBrick;
+  if (p.face0 || p.face1 || (MODE == 0 && interior)) p.wr = (1u << p.cnt) - 1u;
+  else if (MODE == 1 && fast && interior) p.wr = 0xFu;
+  if (p.face2) p.wr |= 1u;
+  return p;
+}
+
+// the values of one item (cnt <= 4 cells; the cells item_pos marks) and, in
+// pos, its LDS base (below 33^3 < 2^16) with the loaded-cell mask at bit 16:
+// one register per item held until the store
 template <typename T, int MODE>
 __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL T* __restrict__ X, int64_t st0,
                                              int64_t st1, const Block3& bk, const Box& bx,
                                              const BoxItems& bi, uint32_t it, bool vec,
                                              bool fast, const HPEZ_GLOBAL uint16_t* bcode,
-                                             int32_t& lbase, uint32_t& wr)
+                                             uint32_t& pos)
 {
   Quad<T> v;
 #pragma unroll
   for (int j = 0; j < 4; j++) v.v[j] = (T)0;
-  wr = 0;
-  lbase = 0;
-  if (it >= bi.nitems) return v;
-  const int32_t c0 = (int32_t)fdiv(it, bi.mgr);
-  const uint32_t rr = it - (uint32_t)c0 * bi.rowq;
-  const int32_t c1 = (int32_t)fdiv(rr, bi.mgq);
-  const int32_t cb = 4 * (int32_t)(rr - (uint32_t)c1 * bi.nq);
-  const int32_t cnt = bi.E2 - cb < 4 ? bi.E2 - cb : 4;
+  const ItemPos p = item_pos<MODE>(bx, bi, it, fast);
+  pos = (uint32_t)p.lbase | p.wr << 16;
+  if (!p.wr) return v;
+  const int32_t c0 = p.c0, c1 = p.c1, cb = p.cb, cnt = p.cnt;
   const int64_t x0 = bk.o0 + c0, x1 = bk.o1 + c1, x2 = bk.o2 + cb;
-  // row-major box, or the parity-split slots of a full block (cb even)
-  lbase = fast ? fslot(c0) * kFP0 + fslot(c1) * kFP1 + (cb >> 1) : (c0 * bi.E1 + c1) * bi.E2 + cb;
-  const bool face0 = bx.a0 && (c0 == 0 || c0 == kBrick);
-  const bool face1 = !face0 && bx.a1 && (c1 == 0 || c1 == kBrick);
+  const bool face0 = p.face0, face1 = p.face1;
   const HPEZ_GLOBAL T* src = nullptr;
   bool once = false;
   if (face0)
@@ -843,10 +877,8 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL
         *reinterpret_cast<const HPEZ_GLOBAL uint64_t*>(bcode + (c0 * kBrick + c1) * kBrick + cb);
 #pragma unroll
     for (int j = 0; j < 4; j++) v.v[j] = (T)__uint_as_float((uint32_t)(cw >> (16 * j)) & 0xFFFFu);
-    wr = 0xFu;
   }
   if (src) {
-    wr = (1u << cnt) - 1u;
     if (vec && cnt == 4 && once) {
       v = load_quad_once(src);
     } else if (vec && cnt == 4) {
@@ -857,19 +889,20 @@ __device__ __forceinline__ Quad<T> load_item(const FaceGeo& f, const HPEZ_GLOBAL
         if (j < cnt) v.v[j] = src[j];
     }
   }
-  if (!face0 && !face1 && bx.a2 && (cb == 0 || cb == kBrick)) {
+  if (p.face2) {
     // the row's cell on a dim-2 face
     v.v[0] = gmem(reinterpret_cast<const T*>(f.val[2]))[(x2 >> f.blog2) * f.plane[2] +
                                                         x0 * f.fs[2][0] + x1 * f.fs[2][1]];
-    wr |= 1u;
   }
   return v;
 }
 
 template <typename T>
-__device__ __forceinline__ void store_item(T* L, const Quad<T>& v, int32_t lbase, uint32_t wr,
-                                           bool fast)
+__device__ __forceinline__ void store_item(T* L, const Quad<T>& v, uint32_t pos, bool fast)
 {
+  // pos as load_item gives it
+  const int32_t lbase = (int32_t)(pos & 0xFFFFu);
+  const uint32_t wr = pos >> 16;
   // full blocks: cells cb, cb + 2 at even slots cb / 2, cb / 2 + 1; cb + 1, cb + 3
   // at odd slots 17 + cb / 2, 18 + cb / 2
 #pragma unroll
@@ -927,8 +960,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
   // stands between two blocks)
   uint64_t gbi = blockIdx.x;
   Quad<T> pv[UP];
-  int32_t plb[UP];
-  uint32_t pwr[UP];
+  uint32_t ppos[UP];
   T pcv = (T)0;  // the lane's first lattice value of the next block
   if (PREF && gbi < nbt) {
     const int j = find_entry(begin, njobs, gbi);
@@ -942,7 +974,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     for (int u = 0; u < UP; u++)
       pv[u] = load_item<T, MODE>(J.f, gmem(J.X), J.a.g.st[0], J.a.g.st[1], bk, bx, its,
                                  threadIdx.x + u * NT, J.a.vec != 0, fast1,
-                                 gmem(J.code) + brick_start(J.a.g, bk), plb[u], pwr[u]);
+                                 gmem(J.code) + brick_start(J.a.g, bk), ppos[u]);
     Box lb1;
     lattice_box(bx, lb1);
     if (threadIdx.x < (uint32_t)(lb1.E0 * lb1.b0))
@@ -985,20 +1017,19 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     // ---- the box into LDS
     if (PREF) {
 #pragma unroll
-      for (int u = 0; u < UP; u++) store_item<T>(L, pv[u], plb[u], pwr[u], fast);
+      for (int u = 0; u < UP; u++) store_item<T>(L, pv[u], ppos[u], fast);
     } else {
       const BoxItems its = box_items(bx);
       constexpr int UL = 4;
       for (uint32_t ib = threadIdx.x; ib < its.nitems; ib += UL * NT) {
         Quad<T> v[UL];
-        int32_t lb[UL];
-        uint32_t wr[UL];
+        uint32_t pos[UL];
 #pragma unroll
         for (int u = 0; u < UL; u++)
           v[u] = load_item<T, MODE>(f, X, st0, st1, bk, bx, its, ib + u * NT, vec, false, nullptr,
-                                    lb[u], wr[u]);
+                                    pos[u]);
 #pragma unroll
-        for (int u = 0; u < UL; u++) store_item<T>(L, v[u], lb[u], wr[u], false);
+        for (int u = 0; u < UL; u++) store_item<T>(L, v[u], pos[u], false);
       }
     }
     // the lattice cells hold the coarse levels' results
@@ -1080,7 +1111,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
       for (int u = 0; u < UP; u++)
         pv[u] = load_item<T, MODE>(J2.f, gmem(J2.X), J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,
                                    threadIdx.x + u * NT, J2.a.vec != 0, fast2,
-                                   gmem(J2.code) + brick_start(J2.a.g, bk2), plb[u], pwr[u]);
+                                   gmem(J2.code) + brick_start(J2.a.g, bk2), ppos[u]);
       Box lb2;
       lattice_box(bx2, lb2);
       if (threadIdx.x < (uint32_t)(lb2.E0 * lb2.b0))
