@@ -57,8 +57,11 @@ enum { HPEZ_LINEAR = 0, HPEZ_CUBIC_NAK = 1, HPEZ_CUBIC_NATURAL = 2 };
  *               2 natural cubic Eq. (8);
  *   md          0: one dimension at a time (1D style); 1: multi-dimensional
  *               interpolation, Eq. (9), Sec. 5.3;
- *   same_level  cubic, 1D style: split every pass in two, the second half
- *               using the same-level stencils Eq. (13)/(14), Sec. 5.4.2;
+ *   same_level  cubic: split every pass (1D style: points at s, then 3s mod 4s
+ *               along the pass dim) or every multi-dimensional sub-step
+ *               (checkerboard colour 0, then 1: the parity of the sum over the
+ *               odd dims of (x_d - s) / 2s) in two, the second half using the
+ *               same-level stencils Eq. (13)/(14), Sec. 5.4.2;
  *   order       1D style: the dimension of each pass, first pass first; the
  *               first ndims entries must be a permutation of 0..ndims-1. */
 typedef struct {

@@ -119,7 +119,7 @@ class Tiny:
             acc = None
             for d in range(4):
                 if odd >> d & 1:
-                    t = wt[d] * self.stencil(i, s * self.strides[d], c[d], s, lo[d], hi[d], ip["kind"], 0)
+                    t = wt[d] * self.stencil(i, s * self.strides[d], c[d], s, lo[d], hi[d], ip["kind"], sl)
                     acc = t if acc is None else acc + t
             p = acc
         else:
@@ -178,8 +178,20 @@ class Tiny:
                     for d in range(4):
                         if act[d]:
                             r[d], m[d] = (s, 2 * s) if odd >> d & 1 else (0, 2 * s)
-                    for c in self.lattice(r, m, rlo, rhi, filt, B):
-                        self.visit(c, ip, -1, odd, 0, s, lo, hi, mode)
+                    pts = self.lattice(r, m, rlo, rhi, filt, B)
+                    if ip["kind"] != 0 and ip["same_level"]:
+                        # same-level halves (Sec. 5.4.2 extended to MD): the
+                        # checkerboard of sum (x_d - s) / 2s over the odd dims;
+                        # colour 0 first, regular stencils, then colour 1 with
+                        # the same-level stencils
+                        colour = lambda c: sum((c[d] - s) // (2 * s) for d in dims) % 2
+                        for half in (0, 1):
+                            for c in pts:
+                                if colour(c) == half:
+                                    self.visit(c, ip, -1, odd, half, s, lo, hi, mode)
+                    else:
+                        for c in pts:
+                            self.visit(c, ip, -1, odd, 0, s, lo, hi, mode)
             return
         order = [d for d in ip["order"] if d < 4 and act[d]]
         seen = []

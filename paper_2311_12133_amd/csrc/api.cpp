@@ -844,7 +844,19 @@ int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, co
           a.lat = make_lattice(g, r, m);
           a.odd = odd;
           for (int dd = 0; dd < 4; dd++) a.wq[dd] = h_wq[(ip.kind * 16 + odd) * 4 + dd];
-          HIPCK(launch_step<T>(a, X, W, code, mode, st));
+          if (ip.kind != 0 && ip.same_level) {
+            // same-level cubic inside MD: checkerboard colour 0, then colour 1
+            // with the same-level stencils
+            for (int half = 0; half < 2; half++) {
+              a.sl = half;
+              a.mdhalf = 1 + half;
+              HIPCK(launch_step<T>(a, X, W, code, mode, st));
+            }
+            a.sl = 0;
+            a.mdhalf = 0;
+          } else {
+            HIPCK(launch_step<T>(a, X, W, code, mode, st));
+          }
         }
     } else {
       int pos[4] = {-1, -1, -1, -1}, np = 0;

@@ -243,8 +243,21 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
           }
           a.odd = odd;
           for (int k = 0; k < 4; k++) a.wq[k] = J.h_wq[(ip.kind * 16 + odd) * 4 + k];
-          grp = cnt - 1;  // Sec. 5.4.1: one sub-step per number of odd coordinates
-          step(r, m);
+          if (ip.kind != 0 && ip.same_level) {
+            // same-level cubic inside MD: the sub-step's checkerboard colour 0,
+            // then colour 1 with the same-level stencils (a later group)
+            for (int half = 0; half < 2; half++) {
+              a.sl = half;
+              a.mdhalf = 1 + half;
+              grp = 2 * (cnt - 1) + half;
+              step(r, m);
+            }
+            a.sl = 0;
+            a.mdhalf = 0;
+          } else {
+            grp = cnt - 1;  // Sec. 5.4.1: one sub-step per number of odd coordinates
+            step(r, m);
+          }
         }
     } else {
       int pos[4] = {-1, -1, -1, -1}, np = 0;

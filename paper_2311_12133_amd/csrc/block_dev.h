@@ -41,6 +41,8 @@ struct FaceStep {
   double wq[4];
   int64_t s;
   double el, inv2e, twoe;
+  int32_t mdhalf;  // multi-dimensional same-level: 0 all points, 1 + c only colour c
+  int32_t pad;
 };
 
 struct BlockArgs {

@@ -74,8 +74,11 @@ __device__ __forceinline__ T stencil_box(const T* L, int32_t li, int32_t sd, int
 
 // One step: every cell with c_d == r_d (mod m_d), c_d in [lo_d, hi_d], for the
 // three dims.  pd >= 0: 1D prediction along pd; pd < 0: multi-dimensional over
-// the odd set `odd` with weights w0..w2 (sum left to right, Eq. 12).  NT is the
-// work-group size.  The points of a step are independent, so each lane takes
+// the odd set `odd` with weights w0..w2 (sum left to right, Eq. 12); with
+// colour >= 0 only the points of that checkerboard colour (the parity of
+// sum (x_d - s) / 2s over the odd dims, global coordinates x = o + c), SL
+// then giving the stencil of that half (Sec. 5.4.2 carried over to MD).  NT is
+// the work-group size.  The points of a step are independent, so each lane takes
 // kU of them at once: op.fetch(x0, x1, x2) for all of them first (global loads
 // in flight together), then the predictions and op.apply(li, x0, x1, x2, p, f).
 constexpr int kU = 4;
@@ -84,8 +87,9 @@ template <typename T, int KIND, int SL, bool MD, int NT, class Op>
 __device__ __forceinline__ void box_step(const Box& bx, const T* L, int32_t r0, int32_t r1,
                                          int32_t r2, int32_t m0, int32_t m1, int32_t m2,
                                          int64_t o0, int64_t o1, int64_t o2, int pd, unsigned odd,
-                                         int32_t s, T w0, T w1, T w2, Op& op)
+                                         int32_t s, T w0, T w1, T w2, Op& op, int colour)
 {
+  const int lg2s = 31 - __clz(2 * s);
   const int32_t f0 = first_in(o0, bx.lo0, r0, m0), f1 = first_in(o1, bx.lo1, r1, m1),
                 f2 = first_in(o2, bx.lo2, r2, m2);
   const int32_t c0 = f0 <= bx.hi0 ? ((bx.hi0 - f0) >> (31 - __clz(m0))) + 1 : 0;
@@ -121,6 +125,12 @@ __device__ __forceinline__ void box_step(const Box& bx, const T* L, int32_t r0, 
 #pragma unroll
     for (int u = 0; u < kU; u++) {
       if (kb + u * NT + threadIdx.x >= total) continue;
+      if (MD && colour >= 0) {
+        const int64_t c = ((odd & 1u) ? ((o0 + x0[u]) >> lg2s) : 0) +
+                          ((odd & 2u) ? ((o1 + x1[u]) >> lg2s) : 0) +
+                          ((odd & 4u) ? ((o2 + x2[u]) >> lg2s) : 0);
+        if ((int)(c & 1) != colour) continue;
+      }
       const int32_t li = x0[u] * B0 + x1[u] * B1 + x2[u];
       T p;
       if (!MD) {
@@ -130,16 +140,16 @@ __device__ __forceinline__ void box_step(const Box& bx, const T* L, int32_t r0, 
         bool first = true;
         T acc = (T)0;
         if (odd & 1u) {
-          acc = w0 * stencil_box<T, KIND, 0>(L, li, s * B0, x0[u], s, L0);
+          acc = w0 * stencil_box<T, KIND, SL>(L, li, s * B0, x0[u], s, L0);
           first = false;
         }
         if (odd & 2u) {
-          const T t = w1 * stencil_box<T, KIND, 0>(L, li, s * B1, x1[u], s, L1);
+          const T t = w1 * stencil_box<T, KIND, SL>(L, li, s * B1, x1[u], s, L1);
           acc = first ? t : acc + t;
           first = false;
         }
         if (odd & 4u) {
-          const T t = w2 * stencil_box<T, KIND, 0>(L, li, s, x2[u], s, L2);
+          const T t = w2 * stencil_box<T, KIND, SL>(L, li, s, x2[u], s, L2);
           acc = first ? t : acc + t;
         }
         p = acc;
@@ -153,14 +163,14 @@ template <typename T, int KIND, int SL, int NT, class Op>
 __device__ __forceinline__ void box_step_k(bool md, const Box& bx, const T* L, int32_t r0, int32_t r1,
                                            int32_t r2, int32_t m0, int32_t m1, int32_t m2, int64_t o0,
                                            int64_t o1, int64_t o2, int pd, unsigned odd, int32_t s,
-                                           T w0, T w1, T w2, Op& op)
+                                           T w0, T w1, T w2, Op& op, int colour)
 {
   if (md)
-    box_step<T, KIND, 0, true, NT>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2,
-                                   op);
+    box_step<T, KIND, SL, true, NT>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1,
+                                    w2, op, colour);
   else
     box_step<T, KIND, SL, false, NT>(bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1,
-                                     w2, op);
+                                     w2, op, -1);
 }
 
 // runtime (uniform) kind / same-level / paradigm to the compiled step
@@ -169,18 +179,23 @@ __device__ __forceinline__ void box_step_any(int kind, int sl, bool md, const Bo
                                              int32_t r0, int32_t r1, int32_t r2, int32_t m0,
                                              int32_t m1, int32_t m2, int64_t o0, int64_t o1,
                                              int64_t o2, int pd, unsigned odd, int32_t s, T w0, T w1,
-                                             T w2, Op& op)
+                                             T w2, Op& op, int colour = -1)
 {
   if (kind == 0)
-    box_step_k<T, 0, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 0, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op,
+                            colour);
   else if (kind == 1 && sl)
-    box_step_k<T, 1, 1, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 1, 1, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op,
+                            colour);
   else if (kind == 1)
-    box_step_k<T, 1, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 1, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op,
+                            colour);
   else if (sl)
-    box_step_k<T, 2, 1, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 2, 1, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op,
+                            colour);
   else
-    box_step_k<T, 2, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op);
+    box_step_k<T, 2, 0, NT>(md, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, pd, odd, s, w0, w1, w2, op,
+                            colour);
 }
 
 // One level (stride s) with configuration c: all its steps, each followed by a
@@ -193,18 +208,23 @@ __device__ __forceinline__ void box_level(const hpez_interp& c, const Box& bx, T
 {
   const int a0 = bx.a0, a1 = bx.a1, a2 = bx.a2;
   if (c.md) {
+    // with same-level cubic each sub-step runs in two halves by checkerboard
+    // colour, the second with the same-level stencils
     const int nact = a0 + a1 + a2;
     const int32_t m0 = a0 ? 2 * s : 1, m1 = a1 ? 2 * s : 1, m2 = a2 ? 2 * s : 1;
+    const bool halves = c.kind != 0 && c.same_level;
     for (int cnt = 1; cnt <= nact; cnt++) {
-      for (unsigned odd = 1; odd < 8; odd++) {
-        if ((int)__popc(odd) != cnt) continue;
-        if (((odd & 1u) && !a0) || ((odd & 2u) && !a1) || ((odd & 4u) && !a2)) continue;
-        const int32_t r0 = (odd & 1u) ? s : 0, r1 = (odd & 2u) ? s : 0, r2 = (odd & 4u) ? s : 0;
-        const double* w = wmd + (c.kind * 8 + odd) * 4;
-        box_step_any<T, NT>(c.kind, 0, true, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, -1, odd, s,
-                            (T)w[0], (T)w[1], (T)w[2], op);
+      for (int half = 0; half < (halves ? 2 : 1); half++) {
+        for (unsigned odd = 1; odd < 8; odd++) {
+          if ((int)__popc(odd) != cnt) continue;
+          if (((odd & 1u) && !a0) || ((odd & 2u) && !a1) || ((odd & 4u) && !a2)) continue;
+          const int32_t r0 = (odd & 1u) ? s : 0, r1 = (odd & 2u) ? s : 0, r2 = (odd & 4u) ? s : 0;
+          const double* w = wmd + (c.kind * 8 + odd) * 4;
+          box_step_any<T, NT>(c.kind, half, true, bx, L, r0, r1, r2, m0, m1, m2, o0, o1, o2, -1, odd,
+                              s, (T)w[0], (T)w[1], (T)w[2], op, halves ? half : -1);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     return;
   }

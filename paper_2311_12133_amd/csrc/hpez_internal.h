@@ -46,6 +46,7 @@ struct StepArgs {
   double wq[4];       // normalised MD weights for this odd set (double, cast to T on use)
   double el, inv2e, twoe;
   uint32_t R;
+  int32_t mdhalf;     // multi-dimensional same-level: 0 all points, 1 + c only colour c
 };
 
 // Interior points of every block at one level, one step index of each block's

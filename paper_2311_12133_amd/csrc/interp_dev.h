@@ -85,6 +85,19 @@ __device__ __forceinline__ T spline(const P* __restrict__ W, int64_t idx, int64_
   return b;
 }
 
+// Checkerboard colour of a point of a multi-dimensional sub-step with odd set
+// `odd` at stride s (a power of two): the parity of sum (x_d - s) / 2s over the
+// odd dims.  Same-level cubic inside MD (Sec. 5.4.2) predicts colour 0 with the
+// regular stencils, then colour 1 with the same-level ones (its neighbours at
+// +-2s along an odd dim have colour 0).
+__device__ __forceinline__ int md_colour(const int64_t* x, unsigned odd, int64_t s)
+{
+  int64_t t = 0;
+  for (int d = 0; d < 4; d++)
+    if (odd >> d & 1u) t += x[d] / (2 * s);
+  return (int)(t & 1);
+}
+
 // Linear-scale quantization (Sec. 4, step 3): bins of width 2 e_l, rounding
 // half away from zero, radius R, double arithmetic; the value the decompressor
 // will rebuild must meet the bound or the point is stored verbatim (code 0).

@@ -296,6 +296,7 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
     for (int e = 0; e < 3; e++)
       if (e < d && a.g.act[e] && (x[e] & (f.B - 1)) == 0) skip = true;  // belongs to family e
     if (skip) continue;
+    if (a.md && a.mdhalf && md_colour(x, a.odd, a.s) != a.mdhalf - 1) continue;
     const HPEZ_GLOBAL T* __restrict__ F = gmem(reinterpret_cast<const T*>(f.val[d]));
     const int64_t fi = face_index(f, d, x);
     T p;
@@ -309,7 +310,7 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
       for (int e = 0; e < 4; e++) {
         if (!(a.odd >> e & 1u)) continue;
         const T pe = spline<T, HPEZ_GLOBAL T>(F, fi, a.s * f.fs[d][e], x[e], a.s, 0, a.g.n[e] - 1,
-                                              a.kind, 0);
+                                              a.kind, a.sl);
         const T term = (T)a.wq[e] * pe;
         acc = first ? term : acc + term;
         first = false;
@@ -917,10 +918,13 @@ __device__ __forceinline__ uint64_t brick_start(const Geom& g, const Block3& bk)
   return (uint64_t)(bk.o0 * g.n[1] * g.n[2] + bk.Eb0 * bk.o1 * g.n[2] + bk.Eb0 * bk.Eb1 * bk.o2);
 }
 
-// a block whose levels below the lattice take the full-block schedule
-__device__ __forceinline__ bool full_block(const Block3& bk, const Box& bx)
+// a block whose levels below the lattice take the full-block schedule: a
+// 32^3 brick with all dims active whose configuration is not
+// multi-dimensional same-level cubic (those take the row-major box)
+__device__ __forceinline__ bool full_block(const Block3& bk, const Box& bx, const hpez_interp& c)
 {
-  return bx.a0 && bx.a1 && bx.a2 && bk.Eb0 == kBrick && bk.Eb1 == kBrick && bk.Eb2 == kBrick;
+  return bx.a0 && bx.a1 && bx.a2 && bk.Eb0 == kBrick && bk.Eb1 == kBrick && bk.Eb2 == kBrick &&
+         !(c.md && c.same_level && c.kind != 0);
 }
 
 // the LDS histogram window of job J into its histogram
@@ -969,7 +973,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     Box bx;
     block_geometry(J.a.g, (int64_t)(gbi - begin[j]), J.a.nb, bk, bx);
     const BoxItems its = box_items(bx);
-    const bool fast1 = full_block(bk, bx);
+    const bool fast1 = full_block(bk, bx, J.a.cand[gmem(J.bcfg)[gbi - begin[j]]]);
 #pragma unroll
     for (int u = 0; u < UP; u++)
       pv[u] = load_item<T, MODE>(J.f, gmem(J.X), J.a.g.st[0], J.a.g.st[1], bk, bx, its,
@@ -999,7 +1003,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     Block3 bk;
     Box bx;
     block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
-    const bool fast = PREF && full_block(bk, bx);
+    const bool fast = PREF && full_block(bk, bx, a.cand[gmem(J.bcfg)[bi]]);
     // stream position of the brick's first point (all earlier bricks are full
     // along the dims before the last partial one)
     const uint64_t brick_base = brick_start(a.g, bk);
@@ -1106,7 +1110,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
       Box bx2;
       block_geometry(J2.a.g, (int64_t)(bn - begin[j2]), J2.a.nb, bk2, bx2);
       const BoxItems its2 = box_items(bx2);
-      const bool fast2 = full_block(bk2, bx2);
+      const bool fast2 = full_block(bk2, bx2, J2.a.cand[gmem(J2.bcfg)[bn - begin[j2]]]);
 #pragma unroll
       for (int u = 0; u < UP; u++)
         pv[u] = load_item<T, MODE>(J2.f, gmem(J2.X), J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,

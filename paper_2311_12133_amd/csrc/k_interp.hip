@@ -50,6 +50,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
         if (a.g.act[d] && x[d] % a.B == 0) face = true;
       if (!face) continue;
     }
+    if (a.md && a.mdhalf && md_colour(x, a.odd, a.s) != a.mdhalf - 1) continue;
     const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
     T p;
     if (!a.md) {
@@ -60,7 +61,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
       T acc = (T)0;
       for (int d = 0; d < 4; d++) {
         if (!(a.odd >> d & 1u)) continue;
-        const T pd = spline<T, T>(W, idx, a.s * a.g.st[d], x[d], a.s, 0, a.g.n[d] - 1, a.kind, 0);
+        const T pd = spline<T, T>(W, idx, a.s * a.g.st[d], x[d], a.s, 0, a.g.n[d] - 1, a.kind, a.sl);
         const T term = (T)a.wq[d] * pd;
         acc = first ? term : acc + term;
         first = false;
@@ -74,7 +75,8 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
 // Step index of a level point under a configuration: 1D style, 2 * pass + half
 // (the pass is the last dimension in pass order whose coordinate is an odd
 // multiple of s; the half is 1 for coordinates at 3s mod 4s with same-level
-// cubic); multi-dimensional, the number of odd coordinates minus one.
+// cubic); multi-dimensional, 2 * (number of odd coordinates - 1) + half (the
+// half is the checkerboard colour with same-level cubic).
 __device__ __forceinline__ int step_of(const hpez_interp& c, const int32_t* act, const int64_t* x,
                                        int64_t s, unsigned* odd_out, int* pdim_out, int* half_out)
 {
@@ -84,8 +86,9 @@ __device__ __forceinline__ int step_of(const hpez_interp& c, const int32_t* act,
   *odd_out = odd;
   if (c.md) {
     *pdim_out = -1;
-    *half_out = 0;
-    return __popc(odd) - 1;
+    const int half = (c.kind != 0 && c.same_level) ? md_colour(x, odd, s) : 0;
+    *half_out = half;
+    return 2 * (__popc(odd) - 1) + half;
   }
   int pass = -1, pd = -1, k = 0;
   bool seen[4] = {false, false, false, false};
@@ -145,7 +148,7 @@ __global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const 
       T acc = (T)0;
       for (int d = 0; d < 4; d++) {
         if (!(odd >> d & 1u)) continue;
-        const T pdv = spline<T, T>(W, idx, a.s * a.g.st[d], x[d], a.s, lo[d], hi[d], c.kind, 0);
+        const T pdv = spline<T, T>(W, idx, a.s * a.g.st[d], x[d], a.s, lo[d], hi[d], c.kind, half);
         const T term = (T)wq[(c.kind * 16 + odd) * 4 + d] * pdv;
         acc = first ? term : acc + term;
         first = false;

@@ -11,7 +11,7 @@ import sys
 import numpy as np
 import pytest
 
-from cfgs import candidates, make_cfg
+from cfgs import candidates, interp, make_cfg
 from oracle import oracle as O
 from paper_2311_12133_amd import fields
 
@@ -60,6 +60,7 @@ KW = [
     dict(kind="lin", md=1), dict(kind="nak", md=1), dict(kind="nat", md=1),
     dict(kind="nak", same_level=1), dict(kind="nat", same_level=1),
     dict(kind="nak", order=(2, 0, 1)), dict(kind="nat", order=(1, 2, 0), same_level=1),
+    dict(kind="nak", md=1, same_level=1), dict(kind="nat", md=1, same_level=1),
 ]
 
 
@@ -258,3 +259,40 @@ def test_caller_stream(torch_cuda):
     ref = O.compress(x, ref_cfg)
     assert s.cpu().numpy().tobytes() == ref
     assert np.array_equal(y.cpu().numpy().view(np.uint8), O.decompress(ref).view(np.uint8))
+
+
+MDSL_SHAPES = [(1000,), (257, 129), (37, 70, 129), (9, 17, 33, 5)]
+
+
+@pytest.mark.parametrize("shape", MDSL_SHAPES, ids=["x".join(map(str, s)) for s in MDSL_SHAPES])
+def test_md_same_level_global(torch_cuda, shape):
+    """Same-level cubic inside multi-dimensional sub-steps (Sec. 5.4.2): the
+    global step kernels on 1-4-D ragged grids."""
+    x = fields.random_field(shape, len(shape) * 3 + 1, np.float32, "mixed")
+    for kind in ("nak", "nat"):
+        cfg = make_cfg(shape, eb=1e-3, kind=kind, md=1, same_level=1)
+        roundtrip(torch_cuda, x, cfg, f"md+sl {shape} {kind}")
+
+
+MDSL_BLOCK = [((64, 64, 64), "f32", 32), ((70, 66, 97), "f32", 32), ((70, 66, 97), "f64", 32),
+              ((45, 38, 41), "f32", 8), ((200, 161), "f32", 32)]
+
+
+@pytest.mark.parametrize("shape,dt,B", MDSL_BLOCK,
+                         ids=["x".join(map(str, s)) + f"-{d}-B{b}" for s, d, b in MDSL_BLOCK])
+def test_md_same_level_blocks(torch_cuda, shape, dt, B):
+    """Same-level MD on every block path: the face steps and planes (global
+    level configuration), the coarse block lattice, the full-block schedule
+    (float32 32^3 bricks), the row-major box (float64, partial bricks) and the
+    generic per-level block steps (B = 8)."""
+    nd = len(shape)
+    cand = candidates(nd) + [interp("nak", 1, 1, ndims=nd), interp("nat", 1, 1, ndims=nd)]
+    nb = int(np.prod([(s + B - 1) // B for s in shape]))
+    bc = np.random.default_rng(nb).integers(0, len(cand), nb).astype(np.uint8)
+    x = fields.random_field(shape, nb, np.float32 if dt == "f32" else np.float64, "mixed")
+    al = 6 if nd >= 3 else 7
+    if B == 8:
+        al = 4
+    cfg = make_cfg(shape, dtype=dt, eb=1e-3, kind="nat", md=1, same_level=1, anchor_log2=al,
+                   block_log2=int(np.log2(B)), cand=cand, block_cfg=bc)
+    roundtrip(torch_cuda, x, cfg, f"md+sl blocks {shape} {dt} B={B}")

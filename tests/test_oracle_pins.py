@@ -392,3 +392,68 @@ def test_stats_closed_form():
     assert sums[1][0] == 0
     assert sums[2][0] == cnt * math.floor(0.2 * 256) ** 2
     assert (sums[:, 1:3] == 0).all()
+
+
+# -- same-level cubic inside multi-dimensional interpolation (Sec. 5.4.2, last
+# sentence: the split into two half steps carried over to MD sub-steps)
+
+def _level_and_odd(x, shape):
+    """Stride s of a non-anchor point and its odd dims (coordinate 0 is a
+    multiple of every stride)."""
+    tz = min((int(v) & -int(v)).bit_length() - 1 for v in x if v) if any(x) else None
+    s = 1 << tz
+    odd = [d for d, v in enumerate(x) if shape[d] > 1 and (v // s) % 2 == 1]
+    return s, odd
+
+
+@pytest.mark.parametrize("shape", [(65,), (33, 41), (33, 33, 33)])
+def test_md_same_level_halves_by_quartic_residuals(shape):
+    """f = sum_d x_d^4.  For a quartic with leading coefficient 1 the Lagrange
+    error of the 4-node stencil is the product of the node offsets: 9 s^4 for
+    the regular not-a-knot nodes (+-s, +-3s), 4 s^4 for the same-level nodes
+    (+-s, +-2s).  With unit MD weights every point of a sub-step has the error
+    of the half it belongs to, so the codes show which points took the
+    same-level stencils: checkerboard colour 1, parity of sum (x_d - s) / 2s over
+    the odd dims; colour 0 the regular ones."""
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    x = sum(g ** 4 for g in grids)
+    cfg = make_cfg(shape, dtype="f64", eb=0.25, eb_mode="abs", kind="nak", md=True,
+                   same_level=True, anchor_log2=4 if len(shape) > 1 else 5)
+    r = O.interp_codes(x, cfg, 0.25)
+    code = r["code"].astype(np.int64) - 32768
+    seen = {0: 0, 1: 0}
+    for pt in itertools.product(*[range(n) for n in shape]):
+        if not any(pt):
+            continue
+        s, odd = _level_and_odd(pt, shape)
+        if s > 4 or not odd:
+            continue
+        if any(pt[d] - 3 * s < 0 or pt[d] + 3 * s > shape[d] - 1 for d in odd):
+            continue  # a boundary fallback
+        colour = sum((pt[d] - s) // (2 * s) for d in odd) % 2
+        want = (4 if colour else 9) * s ** 4
+        assert code[pt] * 0.5 == want, (pt, s, odd, colour, code[pt])
+        seen[colour] += 1
+    assert seen[0] > 0 and seen[1] > 0
+
+
+def test_md_same_level_one_dim_is_the_1d_split():
+    """With one active dim the MD halves are the 1D ones (s and 3s mod 4s)."""
+    x = fields.random_field((300,), 7, np.float32, "mixed")
+    for kind in ("nak", "nat"):
+        a = O.interp_codes(x, make_cfg((300,), kind=kind, md=True, same_level=True), 1e-3)
+        b = O.interp_codes(x, make_cfg((300,), kind=kind, md=False, same_level=True), 1e-3)
+        assert np.array_equal(a["code"], b["code"]) and np.array_equal(a["W"], b["W"])
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 34), (70, 66), (17, 9, 10, 6)])
+@pytest.mark.parametrize("kind", ["nak", "nat"])
+def test_md_same_level_bound(shape, kind):
+    x = fields.random_field(shape, 3, np.float32, "mixed")
+    cfg = make_cfg(shape, kind=kind, md=True, same_level=True, eb=1e-3)
+    y = O.decompress(O.compress(x, cfg))
+    e, _ = O.error_bound(x, cfg)
+    assert np.abs(x.astype(np.float64) - y).max() <= e
+    # and it differs from plain MD (the same-level halves are used)
+    z = O.decompress(O.compress(x, make_cfg(shape, kind=kind, md=True, eb=1e-3)))
+    assert not np.array_equal(y, z)
