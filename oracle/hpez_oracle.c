@@ -62,7 +62,9 @@ typedef struct {
 
 /* Everything the compressor needs besides the data. */
 typedef struct {
-  uint8_t dtype;       /* 0 float32, 1 float64 */
+  uint8_t dtype;       /* 0 float32, 1 float64; integers 2 uint8, 3 uint16, 4 int16, 5 int32:
+                          the method runs in double on their values (the caller passes
+                          doubles) with reconstructions rounded to integers */
   uint8_t ndims;       /* 1..4 */
   uint8_t eb_mode;     /* 0 absolute, 1 value-range relative */
   uint8_t predictor;   /* 0 interpolation, 1 Lorenzo */
@@ -133,20 +135,23 @@ static double level_eb(double e, double alpha, double beta, int l)
  * round half away from zero, radius R, arithmetic in double, and a post-check
  * that sends a point to the verbatim list when the value the decompressor
  * will rebuild misses the bound (or any quantity is not finite). */
+/* Integer fields (rnd): the rebuilt value is rounded to the nearest integer
+ * (ties to even) before the check, so the working grid holds integers. */
 #define QUANT_BODY(T)                                                          \
   double t = ((double)x - (double)p) * inv2e;                                  \
   double qf = floor(fabs(t) + 0.5);                                            \
   if (!(qf < (double)R)) return 0;                                             \
   double q = t < 0 ? -qf : qf;                                                 \
-  T xr = (T)((double)p + q * twoe);                                            \
+  double v = (double)p + q * twoe;                                             \
+  T xr = (T)(rnd ? rint(v) : v);                                               \
   if (!(fabs((double)xr - (double)x) <= el)) return 0;                         \
   *xr_out = xr;                                                                \
   return (uint16_t)((int64_t)q + (int64_t)R);
 
 static uint16_t quantize_f(float x, float p, double inv2e, double twoe, double el, uint32_t R,
-                           float* xr_out) { QUANT_BODY(float) }
+                           int rnd, float* xr_out) { QUANT_BODY(float) }
 static uint16_t quantize_d(double x, double p, double inv2e, double twoe, double el, uint32_t R,
-                           double* xr_out) { QUANT_BODY(double) }
+                           int rnd, double* xr_out) { QUANT_BODY(double) }
 
 /* ------------------------------------------------------------------ */
 /* type-generic core: instantiated for float and double                */

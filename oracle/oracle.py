@@ -22,6 +22,11 @@ SOURCES = ["hpez_oracle.c", "oracle_core.inc", "oracle_huffman.inc", "oracle_str
 ORC_OK, ORC_EINVAL, ORC_ENOMEM, ORC_ECORRUPT, ORC_ENOSPC, ORC_EUNSUPPORTED, ORC_ESCHEDULE = (
     0, -1, -2, -4, -5, -6, -7)
 
+# dtype codes; integer fields run the method in float64 on their values, with
+# reconstructions rounded to integers, and are returned in their own type
+DTYPES = {"f32": 0, "f64": 1, "u8": 2, "u16": 3, "i16": 4, "i32": 5}
+INT_NP = {"u8": np.uint8, "u16": np.uint16, "i16": np.int16, "i32": np.int32}
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc: scalar C11, no FP contraction, no fast-math."""
@@ -121,7 +126,7 @@ def params_from_cfg(cfg: dict, keep=None) -> Params:
     """Neutral config dict -> oracle parameter block.  ``keep`` collects arrays
     whose memory the block points into."""
     p = Params()
-    p.dtype = {"f32": 0, "f64": 1}[cfg["dtype"]]
+    p.dtype = DTYPES[cfg["dtype"]]
     dims = list(cfg["dims"])
     p.ndims = len(dims)
     for d in range(4):
@@ -178,6 +183,7 @@ def interp_from_struct(s: Interp) -> dict:
 
 
 def _np_dtype(cfg):
+    """The type the method computes in (integers: float64)."""
     return np.float32 if cfg["dtype"] == "f32" else np.float64
 
 
@@ -201,18 +207,25 @@ def inspect(stream: bytes):
     rc = lib().orc_inspect(_ptr(buf), len(stream), dims, C.byref(dt), C.byref(nd), C.byref(tot))
     if rc:
         raise OracleError(rc, "inspect")
-    return dict(dims=tuple(int(dims[d]) for d in range(nd.value)),
-                dtype="f64" if dt.value else "f32", total=int(tot.value))
+    name = {v: k for k, v in DTYPES.items()}[dt.value]
+    return dict(dims=tuple(int(dims[d]) for d in range(nd.value)), dtype=name,
+                total=int(tot.value))
 
 
 def decompress(stream: bytes) -> np.ndarray:
+    """The reconstruction, in the field's own dtype (integer fields: the
+    integer-valued float64 reconstruction clamped to the type's range)."""
     info = inspect(stream)
-    dt = np.float64 if info["dtype"] == "f64" else np.float32
+    dt = np.float32 if info["dtype"] == "f32" else np.float64
     out = np.zeros(int(np.prod(info["dims"])), dtype=dt)
     buf = np.frombuffer(stream, dtype=np.uint8)
     rc = lib().orc_decompress(_ptr(buf), len(stream), _ptr(out), out.nbytes)
     if rc:
         raise OracleError(rc, "decompress")
+    it = INT_NP.get(info["dtype"])
+    if it is not None:
+        lim = np.iinfo(it)
+        out = np.clip(out, lim.min, lim.max).astype(it)
     return out.reshape(info["dims"])
 
 

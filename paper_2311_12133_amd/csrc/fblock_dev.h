@@ -219,7 +219,7 @@ __device__ __forceinline__ void fstep(FBlock<T>& fb, int cls0, int cls1, int cls
     } else {
       static_assert(MODE == 0 || sizeof(T) == 4, "codes held in float cells");
       const uint32_t q = __float_as_uint((float)L[li]);
-      L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
+      L[li] = q ? recon<T>(p, (double)((int32_t)q - (int32_t)R), twoe)
                 : fb.out[(fb.o0 + c0) * fb.st0 + (fb.o1 + c1) * fb.st1 + (fb.o2 + c2)];
     }
   }

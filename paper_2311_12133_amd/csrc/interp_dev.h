@@ -98,9 +98,22 @@ __device__ __forceinline__ int md_colour(const int64_t* x, unsigned odd, int64_t
   return (int)(t & 1);
 }
 
+// The value rebuilt from prediction p and quantization index qd: p + qd 2e_l
+// in double.  A negative twoe marks an integer field (the method then runs in
+// double on the integer values): the value is rounded to the nearest integer
+// (ties to even), so the working grid holds exactly what the integer output
+// will.
+template <typename T>
+__device__ __forceinline__ T recon(T p, double qd, double twoe)
+{
+  const double v = (double)p + qd * fabs(twoe);
+  return (T)(twoe < 0 ? rint(v) : v);
+}
+
 // Linear-scale quantization (Sec. 4, step 3): bins of width 2 e_l, rounding
 // half away from zero, radius R, double arithmetic; the value the decompressor
-// will rebuild must meet the bound or the point is stored verbatim (code 0).
+// will rebuild (recon) must meet the bound or the point is stored verbatim
+// (code 0).
 template <typename T>
 __device__ __forceinline__ uint32_t quantize(T x, T p, double inv2e, double twoe, double el,
                                              uint32_t R, T& xr)
@@ -110,7 +123,7 @@ __device__ __forceinline__ uint32_t quantize(T x, T p, double inv2e, double twoe
   const double qf = floor(fabs(t) + 0.5);
   const bool inr = qf < (double)R;
   const double q = t < 0 ? -qf : qf;
-  const T r = (T)((double)p + q * twoe);
+  const T r = recon<T>(p, q, twoe);
   const bool ok = inr && fabs((double)r - (double)x) <= el;
   xr = ok ? r : xr;
   // |q| < R <= 2^15: the 32-bit conversion is exact; code 0 when not ok

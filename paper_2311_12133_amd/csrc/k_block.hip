@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(256) face_step_kernel(const FaceEntry<T>* __re
     } else {
       const uint32_t q = (d == 2 && E.fcode2) ? (uint32_t)gmem(f.code[2])[fi]
                                               : (uint32_t)code[brick_pos(a.g.n, x)];
-      const T v = q ? (T)((double)p + (double)((int32_t)q - (int32_t)a.R) * a.twoe) : out[idx];
+      const T v = q ? recon<T>(p, (double)((int32_t)q - (int32_t)a.R), a.twoe) : out[idx];
       face_store<T>(f, a.g, x, v);
     }
   }
@@ -404,7 +404,7 @@ struct PlaneDecompressOp {
   __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
   {
     if (q) {
-      L[li] = (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe);
+      L[li] = recon<T>(p, (double)((int32_t)q - (int32_t)R), twoe);
     } else {
       int64_t x[4];
       pos(x0, x1, x2, x);
@@ -626,7 +626,7 @@ struct DecompressOp {
   }
   __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
   {
-    L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
+    L[li] = q ? recon<T>(p, (double)((int32_t)q - (int32_t)R), twoe)
               : out[(o0 + x0) * st0 + (o1 + x1) * st1 + (o2 + x2)];
   }
 };
@@ -696,7 +696,7 @@ struct CoarseDecompressOp {
   }
   __device__ __forceinline__ void apply(int32_t li, int32_t x0, int32_t x1, int32_t x2, T p, uint32_t q)
   {
-    L[li] = q ? (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe)
+    L[li] = q ? recon<T>(p, (double)((int32_t)q - (int32_t)R), twoe)
               : out[(o0 + x0 * k0) * st0 + (o1 + x1 * k1) * st1 + (o2 + x2 * k2)];
   }
 };

@@ -31,7 +31,7 @@ __device__ __forceinline__ void finish(T p, int64_t idx, int64_t cpos, const T* 
     W[idx] = q ? xr : x;
   } else {
     const uint32_t q = code[cpos];
-    if (q != 0) W[idx] = (T)((double)p + (double)((int32_t)q - (int32_t)R) * twoe);
+    if (q != 0) W[idx] = recon<T>(p, (double)((int32_t)q - (int32_t)R), twoe);
   }
 }
 

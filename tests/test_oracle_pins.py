@@ -457,3 +457,69 @@ def test_md_same_level_bound(shape, kind):
     # and it differs from plain MD (the same-level halves are used)
     z = O.decompress(O.compress(x, make_cfg(shape, kind=kind, md=True, eb=1e-3)))
     assert not np.array_equal(y, z)
+
+
+# -- integer fields (the paper's integer datasets): the method in float64 on the
+# integer values, reconstructions rounded to integers, output in the field's type
+
+INT_TYPES = [("u8", np.uint8), ("u16", np.uint16), ("i16", np.int16), ("i32", np.int32)]
+
+
+def _int_field(shape, npdt, seed=4, span=None):
+    rng = np.random.default_rng(seed)
+    g = fields.gaussian_field(shape, -5.0 / 3.0, rng)
+    g = (g - g.min()) / (g.max() - g.min())
+    lim = np.iinfo(npdt)
+    lo = float(lim.min) if span is None else 0.0
+    hi = float(lim.max) if span is None else float(span)
+    return np.round(lo + g * (hi - lo)).astype(npdt)
+
+
+@pytest.mark.parametrize("name,npdt", INT_TYPES)
+@pytest.mark.parametrize("eb", [0.3, 1.0, 3.5, 40.0])
+def test_integer_fields_bound_and_integral(name, npdt, eb):
+    x = _int_field((30, 41, 17), npdt, span=None if name != "i32" else 1 << 20)
+    cfg = make_cfg(x.shape, dtype=name, eb=eb, eb_mode="abs", kind="nat", md=True)
+    r = O.interp_codes(x, cfg, eb)
+    W = r["W"]
+    assert np.all(W == np.round(W)), "the working grid holds integers"
+    assert np.abs(W - x.astype(np.float64)).max() <= eb
+    y = O.decompress(O.compress(x, cfg))
+    assert y.dtype == npdt and y.shape == x.shape
+    err = np.abs(y.astype(np.int64) - x.astype(np.int64)).max()
+    assert err <= eb
+    if eb < 0.5:
+        assert err == 0, "below half a unit the reconstruction is exact"
+
+
+def test_integer_linear_ramp_is_predicted_exactly():
+    # an even-step integer ramp: every linear midpoint is an integer, so every
+    # prediction is exact (all codes R) and the field comes back unchanged
+    # (sides 2^k + 1 with anchors every 32: every point has both neighbours)
+    x = (np.add.outer(np.arange(65) * 4, np.arange(33) * 2) + 7).astype(np.int32)
+    cfg = make_cfg(x.shape, dtype="i32", eb=0.4, eb_mode="abs", kind="lin", anchor_log2=5)
+    r = O.interp_codes(x, cfg, 0.4)
+    assert np.all(r["code"] == 32768)
+    assert np.array_equal(O.decompress(O.compress(x, cfg)), x)
+
+
+def test_integer_clamp_at_type_range():
+    # values at the ends of uint8 with a wide bound: reconstructions outside
+    # [0, 255] come back clamped, still within the bound
+    rng = np.random.default_rng(2)
+    x = np.where(rng.uniform(size=(40, 40)) < 0.5, 0, 255).astype(np.uint8)
+    x[:, :20] = 255
+    cfg = make_cfg(x.shape, dtype="u8", eb=6.0, eb_mode="abs", kind="nak")
+    y = O.decompress(O.compress(x, cfg))
+    assert np.abs(y.astype(np.int64) - x.astype(np.int64)).max() <= 6
+
+
+def test_integer_fields_keep_interpolation():
+    x = _int_field((40, 36, 30), np.int16)
+    cfg = make_cfg(x.shape, dtype="i16", eb=2.0, eb_mode="abs", predictor="lorenzo")
+    with pytest.raises(O.OracleError) as ei:
+        O.compress(x, cfg)
+    assert ei.value.code == O.ORC_EUNSUPPORTED
+    noise = np.random.default_rng(0).integers(-3000, 3000, size=(40, 36, 30)).astype(np.int16)
+    out, rep = O.tune(noise, make_cfg(noise.shape, dtype="i16", eb=1e-3), dict(block_log2=5))
+    assert out["predictor"] == "interp" and not rep["lorenzo"]
