@@ -47,7 +47,14 @@ enum {
   HPEZ_EUNSUPPORTED = -6 /* valid request this build does not handle */
 };
 
-enum { HPEZ_F32 = 0, HPEZ_F64 = 1 };
+/* Field types.  Integer fields (the paper's integer datasets) run the method in
+ * float64 on their values, each rebuilt value rounded to the nearest integer
+ * (ties to even) before the bound check, and are reconstructed in their own
+ * type (clamped to its range, which keeps the bound); their streams store
+ * anchors and verbatim values as float64.  They use the interpolation
+ * predictor only (HPEZ_LORENZO gives HPEZ_EUNSUPPORTED; the tuner does not try
+ * it). */
+enum { HPEZ_F32 = 0, HPEZ_F64 = 1, HPEZ_U8 = 2, HPEZ_U16 = 3, HPEZ_I16 = 4, HPEZ_I32 = 5 };
 enum { HPEZ_ABS = 0, HPEZ_REL = 1 };
 enum { HPEZ_INTERP = 0, HPEZ_LORENZO = 1 };
 enum { HPEZ_LINEAR = 0, HPEZ_CUBIC_NAK = 1, HPEZ_CUBIC_NATURAL = 2 };
@@ -72,7 +79,7 @@ typedef struct {
   uint8_t pad;
 } hpez_interp;
 
-/* The field: dtype HPEZ_F32/HPEZ_F64, 1..4 dims (row-major), and the error
+/* The field: dtype (HPEZ_F32 ... HPEZ_I32), 1..4 dims (row-major), and the error
  * bound: absolute (eb = e) or value-range relative (e = eb * (max - min),
  * Sec. 7.1.3).  eb > 0 and finite.  The product of dims must be below 2^32. */
 typedef struct {
@@ -241,7 +248,8 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
  * bytes) are caller device memory on `device`, as in hpez_decompress, whose
  * output this matches bit for bit.  A stream whose decompression needs more
  * workspace than the array fails with HPEZ_ENOMEM before any kernel runs
- * (hpez_footprint with op 1 gives the need).  Calls on one GPU share its
+ * (hpez_footprint with op 1 gives the need; integer streams, which need a
+ * float64 copy of the field, always fail so).  Calls on one GPU share its
  * array and its staging: they must not overlap (serialize them, e.g. on one
  * stream from one thread); the call clears what must start at zero.
  * Synchronises `stream` like hpez_decompress. */

@@ -200,7 +200,7 @@ def footprint(dims, dtype: str, cfg: dict, op: str) -> int:
 
 def desc_from(dims, dtype: str, eb: float, eb_mode: str) -> FieldDesc:
     d = FieldDesc()
-    d.dtype = {"f32": 0, "f64": 1}[dtype]
+    d.dtype = DTYPES[dtype]
     d.ndims = len(dims)
     for i in range(4):
         d.dims[i] = int(dims[i]) if i < len(dims) else 1
@@ -290,13 +290,23 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+# field types (integer fields: the method runs in float64 on their values)
+DTYPES = {"f32": 0, "f64": 1, "u8": 2, "u16": 3, "i16": 4, "i32": 5}
+DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
+
+
+def _torch_dtype(name: str):
+    torch = _torch()
+    return {"f32": torch.float32, "f64": torch.float64, "u8": torch.uint8, "u16": torch.uint16,
+            "i16": torch.int16, "i32": torch.int32}[name]
+
+
 def _dtype_of(t) -> str:
     torch = _torch()
-    if t.dtype == torch.float32:
-        return "f32"
-    if t.dtype == torch.float64:
-        return "f64"
-    raise TypeError("hpez compresses float32 or float64 tensors")
+    for name in DTYPES:
+        if t.dtype == _torch_dtype(name):
+            return name
+    raise TypeError("hpez compresses float32, float64, uint8, uint16, int16 or int32 tensors")
 
 
 # ---------------------------------------------------------------------------
@@ -340,7 +350,7 @@ def inspect(header_bytes: bytes):
     _check(lib().hpez_inspect(buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(d), C.byref(npts),
                               C.byref(tot)), "hpez_inspect")
     return dict(dims=tuple(int(d.dims[i]) for i in range(d.ndims)),
-                dtype="f64" if d.dtype else "f32", points=npts.value, total=tot.value)
+                dtype=DTYPE_NAMES[d.dtype], points=npts.value, total=tot.value)
 
 
 def decompress(stream_t, stream=None, out=None, context=None):
@@ -350,7 +360,7 @@ def decompress(stream_t, stream=None, out=None, context=None):
         # the field's shape and dtype from the header (the library checks out's size)
         hdr = stream_t[:512].cpu().numpy().tobytes()
         info = inspect(hdr + b"\0" * max(0, 512 - len(hdr)))
-        dt = torch.float64 if info["dtype"] == "f64" else torch.float32
+        dt = _torch_dtype(info["dtype"])
         out = torch.empty(info["dims"], dtype=dt, device=stream_t.device)
     rc = lib().hpez_decompress(_cx(context, stream_t.device.index or 0),
                                C.c_void_p(stream_t.data_ptr()),
@@ -517,7 +527,7 @@ def decompress_batch(streams, stream=None, outs=None, context=None, rcs_out=None
             o = outs[i]
         else:
             info = inspect(heads[i].tobytes())
-            dt = torch.float64 if info["dtype"] == "f64" else torch.float32
+            dt = _torch_dtype(info["dtype"])
             o = torch.empty(info["dims"], dtype=dt, device=s.device)
         res.append(o)
         ins[i] = s.data_ptr()

@@ -46,6 +46,8 @@ struct hpez_ctx {
   uint8_t* pin_pre = nullptr;  // first bytes of the streams being decompressed
   size_t pin_pre_bytes = 0;
   hipEvent_t ev_sync = nullptr;  // host waits for part of a stream's work
+  void* aux = nullptr;           // integer fields' float64 copies (ctx_aux)
+  size_t aux_bytes = 0;
   // second stream for work that can overlap the caller's stream, with the
   // events that fork it from and join it back to that stream
   hipStream_t side = nullptr;
@@ -147,7 +149,7 @@ uint64_t points_of(const hpez_field_desc* d)
 
 int check_desc(const hpez_field_desc* d)
 {
-  if (!d || d->dtype > 1 || d->ndims < 1 || d->ndims > 4 || d->eb_mode > 1) return HPEZ_EINVAL;
+  if (!d || d->dtype > HPEZ_I32 || d->ndims < 1 || d->ndims > 4 || d->eb_mode > 1) return HPEZ_EINVAL;
   if (!(d->eb > 0) || !std::isfinite(d->eb)) return HPEZ_EINVAL;
   uint64_t n = 1;
   for (int i = 0; i < d->ndims; i++) {
@@ -173,6 +175,7 @@ int check_cfg(const hpez_field_desc* d, const hpez_config* c, bool need_blocks)
 {
   if (!c) return HPEZ_EINVAL;
   if (c->predictor > 1 || c->anchor_log2 > 16 || c->block_log2 > 15) return HPEZ_EINVAL;
+  if (c->predictor == HPEZ_LORENZO && dtype_int(d->dtype)) return HPEZ_EUNSUPPORTED;
   if (c->radius < 1 || c->radius > 32768) return HPEZ_EINVAL;
   if (c->chunk < 64 || c->chunk > 1024 || (c->chunk & (c->chunk - 1))) return HPEZ_EINVAL;
   if (!(c->alpha >= 1.0) || !(c->beta >= 1.0)) return HPEZ_EINVAL;
@@ -813,7 +816,7 @@ int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, co
                              : (l == 1 ? "reconstruct_l1" : "reconstruct_coarse"),
               pts * (sizeof(T) + 2), st);
     const double el = level_eb(e, c->alpha, c->beta, l);
-    const double inv2e = 1.0 / (2.0 * el), twoe = 2.0 * el;
+    const double inv2e = 1.0 / (2.0 * el), twoe = twoe_of(el, d->dtype);
     const hpez_interp& ip = c->level[l - 1];
     const bool blocks = B > 0 && s < B;
     StepArgs a;
@@ -1227,6 +1230,7 @@ BlockJobHost<T> c_block_job(const CJob<T>& J)
   B.hist_lo = J.lo;
   B.area = J.area;
   B.out = nullptr;
+  B.dtype = J.d->dtype;
   return B;
 }
 
@@ -1740,6 +1744,7 @@ BlockJobHost<T> d_block_job(const DJob<T>& J)
   B.area = J.area;
   B.fcode2 = J.fcode2;
   B.out = J.out;
+  B.dtype = J.d.dtype;
   return B;
 }
 
@@ -1824,6 +1829,27 @@ uint64_t job_footprint(const hpez_field_desc* d, const hpez_config* c, int op)
 }  // namespace
 
 namespace {
+// Integer fields of a batch: their values as float64 in the context's
+// auxiliary buffer; in[i] is redirected there.
+int int_inputs(hpez_ctx* ctx, int n, const hpez_field_desc* d, const void** in, hipStream_t st)
+{
+  size_t aux = 0;
+  for (int i = 0; i < n; i++)
+    if (dtype_int(d[i].dtype)) aux += al256(points_of(&d[i]) * 8);
+  if (!aux) return HPEZ_OK;
+  int rc = HPEZ_OK;
+  uint8_t* p = (uint8_t*)ctx_aux(ctx, aux, &rc);
+  if (rc) return rc;
+  for (int i = 0; i < n; i++) {
+    if (!dtype_int(d[i].dtype)) continue;
+    const uint64_t N = points_of(&d[i]);
+    if (launch_int_to_f64(in[i], d[i].dtype, (double*)p, N, st) != hipSuccess) return HPEZ_EDEVICE;
+    in[i] = p;
+    p += al256(N * 8);
+  }
+  return HPEZ_OK;
+}
+
 template <typename T>
 int compress_group(hpez_ctx* ctx, int n, const hpez_field_desc* d, const void* const* d_in,
                    const hpez_config* c, void* const* d_out, const uint64_t* out_cap,
@@ -1885,6 +1911,7 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   if (!ctx) return;
   DevScope ds(ctx->device);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->aux) (void)hipFree(ctx->aux);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pin_tab) (void)hipHostFree(ctx->pin_tab);
   if (ctx->pin_pre) (void)hipHostFree(ctx->pin_pre);
@@ -1904,6 +1931,11 @@ int hpez_ctx_trim(hpez_ctx* ctx, uint64_t keep_bytes)
     if (hipFree(ctx->ws) != hipSuccess) return HPEZ_EDEVICE;
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
+  }
+  if (ctx->aux && ctx->aux_bytes > keep_bytes) {
+    if (hipFree(ctx->aux) != hipSuccess) return HPEZ_EDEVICE;
+    ctx->aux = nullptr;
+    ctx->aux_bytes = 0;
   }
   if (ctx->pinned && ctx->pinned_bytes > keep_bytes) {
     (void)hipHostFree(ctx->pinned);
@@ -1971,15 +2003,17 @@ int hpez_footprint(const hpez_field_desc* d, const hpez_config* c, int op, uint6
   if (check_desc(d) || !c || !bytes || op < 0 || op > 2) return HPEZ_EINVAL;
   if (c->chunk < 64 || c->radius < 1 || c->radius > 32768) return HPEZ_EINVAL;
   const uint64_t N = points_of(d);
+  // integer fields: plus their float64 copy (the context's auxiliary buffer)
+  const uint64_t aux = dtype_int(d->dtype) ? al256(N * 8) : 0;
   if (op == 2) {
-    *bytes = tune_footprint(d, c);
+    *bytes = tune_footprint(d, c) + aux;
     return HPEZ_OK;
   }
   hpez_config cc = *c;
   cc.block_cfg = nullptr;
   if (d->dtype == HPEZ_F32) *bytes = job_footprint<float>(d, &cc, op);
   else *bytes = job_footprint<double>(d, &cc, op);
-  (void)N;
+  *bytes += aux;
   return HPEZ_OK;
 }
 
@@ -2007,14 +2041,19 @@ int hpez_compress_batch(hpez_ctx* ctx, int n, const hpez_field_desc* d,
     out_sizes[i] = 0;
   }
   DevScope ds(ctx->device);
+  // integer fields: their values as float64 (the method runs in double on them)
+  std::vector<const void*> in(d_in, d_in + n);
+  int rc = int_inputs(ctx, n, d, in.data(), stream);
+  if (rc) return rc;
   std::vector<int> f32, f64;
   for (int i = 0; i < n; i++) (d[i].dtype == HPEZ_F32 ? f32 : f64).push_back(i);
   int first = HPEZ_OK;
-  int rc = HPEZ_OK;
   if (!f32.empty())
-    rc = compress_group<float>(ctx, n, d, d_in, c, d_out, out_cap, out_sizes, f32, &first, stream);
+    rc = compress_group<float>(ctx, n, d, in.data(), c, d_out, out_cap, out_sizes, f32, &first,
+                               stream);
   if (!rc && !f64.empty())
-    rc = compress_group<double>(ctx, n, d, d_in, c, d_out, out_cap, out_sizes, f64, &first, stream);
+    rc = compress_group<double>(ctx, n, d, in.data(), c, d_out, out_cap, out_sizes, f64, &first,
+                                stream);
   return rc ? rc : first;
 }
 
@@ -2071,7 +2110,7 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
     Layout L;
     int r = read_header(ctx->pin_pre + (size_t)i * kPrefixBytes, in_size[i], &dd, &cc, &L);
     if (!r && L.total > in_size[i]) r = HPEZ_ECORRUPT;
-    if (!r && out_cap[i] < points_of(&dd) * (dd.dtype ? 8 : 4)) r = HPEZ_ENOSPC;
+    if (!r && out_cap[i] < points_of(&dd) * dtype_size(dd.dtype)) r = HPEZ_ENOSPC;
     rcs[i] = r;
     if (r) continue;
     if (dd.dtype == HPEZ_F32) {
@@ -2091,16 +2130,38 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
       J.in = (const uint8_t*)d_in[i];
       J.h_prefix = ctx->pin_pre + (size_t)i * kPrefixBytes;
       J.prefix_len = std::min<uint64_t>(in_size[i], kPrefixBytes);
-      J.out = (double*)d_out[i];
+      J.out = (double*)d_out[i];  // integer fields: set to a float64 buffer below
       J.d = dd;
       J.c = cc;
       J.Lo = L;
       i64.push_back(i);
     }
   }
+  // integer streams decode into float64 buffers (aux), then to their type
+  size_t aux = 0;
+  for (auto& J : j64)
+    if (dtype_int(J.d.dtype)) aux += al256(points_of(&J.d) * 8);
+  uint8_t* ap = nullptr;
+  if (aux) {
+    ap = (uint8_t*)ctx_aux(ctx, aux, &rc);
+    if (rc) return rc;
+  }
+  std::vector<void*> int_out(j64.size(), nullptr);
+  for (size_t k = 0; k < j64.size(); k++) {
+    DJob<double>& J = j64[k];
+    if (!dtype_int(J.d.dtype)) continue;
+    int_out[k] = (void*)J.out;
+    J.out = (double*)ap;
+    ap += al256(points_of(&J.d) * 8);
+  }
   rc = decompress_group<float>(ctx, j32, i32, rcs, stream);
   if (!rc) rc = decompress_group<double>(ctx, j64, i64, rcs, stream);
   if (rc) return rc;
+  for (size_t k = 0; k < j64.size(); k++) {
+    if (!int_out[k] || rcs[i64[k]]) continue;
+    HIPCK(launch_f64_to_int(j64[k].out, j64[k].d.dtype, int_out[k], points_of(&j64[k].d), stream));
+  }
+  if (aux) HIPCK(hipStreamSynchronize(stream));
   for (int i = 0; i < n; i++)
     if (rcs[i]) return rcs[i];
   return HPEZ_OK;
@@ -2128,6 +2189,26 @@ int hpez_profile_read(hpez_ctx* ctx, hpez_kernel_stat* out, int cap, int* n)
 
 // helpers for the other translation units of the runtime
 namespace hpez {
+
+void* ctx_aux(hpez_ctx* c, size_t bytes, int* rc)
+{
+  *rc = HPEZ_OK;
+  if (c->aux_bytes >= bytes) return c->aux;
+  if (c->fixed) {
+    *rc = HPEZ_ENOMEM;
+    return nullptr;
+  }
+  if (c->aux) (void)hipFree(c->aux);
+  c->aux = nullptr;
+  c->aux_bytes = 0;
+  if (hipMalloc(&c->aux, bytes) != hipSuccess) {
+    c->aux = nullptr;
+    *rc = HPEZ_ENOMEM;
+    return nullptr;
+  }
+  c->aux_bytes = bytes;
+  return c->aux;
+}
 
 void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc)
 {

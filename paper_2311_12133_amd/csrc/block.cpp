@@ -179,7 +179,7 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
       const double el = level_eb(J.e, c->alpha, c->beta, l);
       P.el_l[l] = el;
       P.inv2e_l[l] = 1.0 / (2.0 * el);
-      P.twoe_l[l] = 2.0 * el;
+      P.twoe_l[l] = twoe_of(el, J.dtype);
     }
     for (int k = 0; k < 3; k++)
       for (int odd = 0; odd < 8; odd++)
@@ -202,7 +202,7 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
     a.s = s;
     a.el = el;
     a.inv2e = 1.0 / (2.0 * el);
-    a.twoe = 2.0 * el;
+    a.twoe = twoe_of(el, J.dtype);
     a.R = c->radius;
     // one step over every family whose planes the step touches; steps of one
     // group have no point in common and read none of each other's points
@@ -316,7 +316,7 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
     const double el = level_eb(J.e, c->alpha, c->beta, l);
     ba.el_l[l] = el;
     ba.inv2e_l[l] = 1.0 / (2.0 * el);
-    ba.twoe_l[l] = 2.0 * el;
+    ba.twoe_l[l] = twoe_of(el, J.dtype);
   }
   for (uint32_t i = 0; i < c->n_cand && i < 16; i++) ba.cand[i] = c->cand[i];
   for (int k = 0; k < 3; k++)

@@ -85,6 +85,21 @@ inline void for_used(const uint8_t* len, uint32_t lo, uint32_t hi, F fn)
     if (len[s]) fn(s);
 }
 
+// field types: integer fields run in double (the stream's anchors and
+// verbatim values are double too); a negative 2e_l marks them for the kernels
+inline bool dtype_int(int dt) { return dt >= HPEZ_U8; }
+inline size_t dtype_size(int dt)
+{
+  return dt == HPEZ_F32 ? 4 : dt == HPEZ_F64 ? 8 : dt == HPEZ_U8 ? 1 : dt == HPEZ_I32 ? 4 : 2;
+}
+inline double twoe_of(double el, int dt) { return (dtype_int(dt) ? -2.0 : 2.0) * el; }
+// values of integer field types to double and back (clamped), on the stream
+hipError_t launch_int_to_f64(const void* in, int dt, double* out, uint64_t n, hipStream_t st);
+hipError_t launch_f64_to_int(const double* in, int dt, void* out, uint64_t n, hipStream_t st);
+// the context's auxiliary device buffer (integer fields' float64 copies),
+// grown on demand, separate from the workspace
+void* ctx_aux(hpez_ctx* c, size_t bytes, int* rc);
+
 // context services (api.cpp)
 void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc);
 uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc);
@@ -143,6 +158,7 @@ struct BlockJobHost {
   bool xface = false;      // compress: family 2's face array prefilled with the field's values
   bool fcode2 = false;     // decompress: family 2's codes in f.code[2] (from the decoder)
   const T* Wg = nullptr;   // the grid holding anchors and levels >= B
+  int dtype = 0;           // the field's type (integer fields: rounded reconstructions)
   uint16_t* code = nullptr;
   const uint8_t* d_bcfg = nullptr;
   const double* h_wq = nullptr;

@@ -223,13 +223,16 @@ hipError_t launch_ssim(const T* x, const T* xr, const SsimGeom& g, double* d_win
   return hipGetLastError();
 }
 
-template hipError_t launch_quality_sums<float>(const float*, const float*, uint64_t, double*,
-                                               double*, hipStream_t);
-template hipError_t launch_quality_sums<double>(const double*, const double*, uint64_t, double*,
-                                                double*, hipStream_t);
-template hipError_t launch_ssim<float>(const float*, const float*, const SsimGeom&, double*,
-                                       double*, double*, hipStream_t);
-template hipError_t launch_ssim<double>(const double*, const double*, const SsimGeom&, double*,
-                                        double*, double*, hipStream_t);
+#define QINST(T)                                                                              \
+  template hipError_t launch_quality_sums<T>(const T*, const T*, uint64_t, double*, double*,     \
+                                             hipStream_t);                                       \
+  template hipError_t launch_ssim<T>(const T*, const T*, const SsimGeom&, double*, double*,       \
+                                     double*, hipStream_t);
+QINST(float)
+QINST(double)
+QINST(uint8_t)
+QINST(uint16_t)
+QINST(int16_t)
+QINST(int32_t)
 
 }  // namespace hpez

@@ -30,7 +30,7 @@ namespace {
 
 int check_shape(const hpez_field_desc* d)
 {
-  if (!d || d->dtype > 1 || d->ndims < 1 || d->ndims > 4) return HPEZ_EINVAL;
+  if (!d || d->dtype > HPEZ_I32 || d->ndims < 1 || d->ndims > 4) return HPEZ_EINVAL;
   uint64_t n = 1;
   for (int i = 0; i < d->ndims; i++) {
     if (d->dims[i] < 1 || d->dims[i] >= (1ull << 32)) return HPEZ_EINVAL;
@@ -164,9 +164,21 @@ int hpez_quality_eval(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_
   if (g.cells > (1u << 24)) return HPEZ_EINVAL;
   DeviceGuard dg(ctx_device(ctx));
   std::memset(out, 0, sizeof *out);
-  return desc->dtype == HPEZ_F32
-             ? eval_t<float>(ctx, desc, (const float*)d_x, (const float*)d_xr, w, out, stream)
-             : eval_t<double>(ctx, desc, (const double*)d_x, (const double*)d_xr, w, out, stream);
+  switch (desc->dtype) {
+    case HPEZ_F32:
+      return eval_t<float>(ctx, desc, (const float*)d_x, (const float*)d_xr, w, out, stream);
+    case HPEZ_F64:
+      return eval_t<double>(ctx, desc, (const double*)d_x, (const double*)d_xr, w, out, stream);
+    case HPEZ_U8:
+      return eval_t<uint8_t>(ctx, desc, (const uint8_t*)d_x, (const uint8_t*)d_xr, w, out, stream);
+    case HPEZ_U16:
+      return eval_t<uint16_t>(ctx, desc, (const uint16_t*)d_x, (const uint16_t*)d_xr, w, out,
+                              stream);
+    case HPEZ_I16:
+      return eval_t<int16_t>(ctx, desc, (const int16_t*)d_x, (const int16_t*)d_xr, w, out, stream);
+    default:
+      return eval_t<int32_t>(ctx, desc, (const int32_t*)d_x, (const int32_t*)d_xr, w, out, stream);
+  }
 }
 
 int hpez_fit_eb(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
@@ -202,7 +214,7 @@ int hpez_fit_eb(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
   uint64_t cap = 0;
   rc = hpez_compress_bound(&dd, cfg, &cap);
   if (rc) return rc;
-  const uint64_t N = npoints(desc), s = desc->dtype == HPEZ_F32 ? 4 : 8;
+  const uint64_t N = npoints(desc), s = dtype_size(desc->dtype);
   void* d_z = nullptr;
   void* d_xr = nullptr;
   if (hipMalloc(&d_z, cap) != hipSuccess) return HPEZ_ENOMEM;

@@ -155,13 +155,13 @@ std::vector<TrialBox> global_boxes(const Geom& g, int64_t B, double rate, uint64
   return v;
 }
 
-void fill_levels(TrialArgs& a, double e, const hpez_config* Q)
+void fill_levels(TrialArgs& a, double e, const hpez_config* Q, int dtype)
 {
   for (int l = 1; l <= 16; l++) {
     const double el = level_eb(e, Q->alpha, Q->beta, l);
     a.el[l] = el;
     a.inv2e[l] = 1.0 / (2.0 * el);
-    a.twoe[l] = 2.0 * el;
+    a.twoe[l] = twoe_of(el, dtype);
   }
   a.el[0] = a.inv2e[0] = a.twoe[0] = 0.0;
   double wq[3 * 16 * 4];
@@ -627,11 +627,11 @@ int t_global(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
     a.box_cap = J.gcap;
     a.max_ext = (int32_t)std::min<int64_t>(J.B + 1, INT32_MAX);
     a.score_mul = 4096.0 / J.e;
-    fill_levels(a, J.e, &Q);
+    fill_levels(a, J.e, &Q, J.d->dtype);
     for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
     t_add<T>(tb, a, J.d_gb, nbx, kNCand, J.X, (T*)J.scratch, J.wq, J.score[v], nullptr);
   }
-  J.lorenzo_trial = o->allow_lorenzo != 0;
+  J.lorenzo_trial = o->allow_lorenzo != 0 && !dtype_int(J.d->dtype);  // integers: interpolation
   return HPEZ_OK;
 }
 
@@ -774,7 +774,7 @@ int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool
   a.box_cap = cap;
   a.max_ext = (int32_t)side;
   a.score_mul = 4096.0 / J.e;
-  fill_levels(a, J.e, &J.Q);
+  fill_levels(a, J.e, &J.Q, J.d->dtype);
   for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
   if (need_tables && !trial_box_ok<T>(a, false)) return HPEZ_OK;
   TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, (size_t)J.nbt * sizeof(TrialBox), hipMemcpyHostToDevice,
@@ -841,7 +841,7 @@ int t_ab(TJob<T>& J, TrialBatch<T>& tb, hipStream_t st)
     for (int l = 1; l <= Lb; l++) a.level[l - 1] = J.lv[v][l - 1];
     hpez_config q = J.Q;
     ab_pair(c, &q.alpha, &q.beta);
-    fill_levels(a, J.e, &q);
+    fill_levels(a, J.e, &q, J.d->dtype);
     t_add<T>(tb, a, J.d_gb, (uint32_t)J.gb.size(), 1, J.X, (T*)J.scratch, J.wq, J.absq + c,
              J.abhist + (size_t)c * J.nsym);
   }
@@ -1153,15 +1153,33 @@ extern "C" int hpez_tune_batch(hpez_ctx* ctx, int n, const hpez_field_desc* desc
   }
   if (!n) return HPEZ_OK;
   DeviceGuard dg(ctx_device(ctx));
+  // integer fields: their values as float64 in the context's auxiliary buffer
+  std::vector<const void*> in(d_in, d_in + n);
+  size_t aux = 0;
+  for (int i = 0; i < n; i++)
+    if (dtype_int(desc[i].dtype)) aux += (points_of(&desc[i]) * 8 + 255) & ~(size_t)255;
+  if (aux) {
+    int arc = HPEZ_OK;
+    uint8_t* p = (uint8_t*)ctx_aux(ctx, aux, &arc);
+    if (arc) return arc;
+    for (int i = 0; i < n; i++) {
+      if (!dtype_int(desc[i].dtype)) continue;
+      const uint64_t N = points_of(&desc[i]);
+      if (launch_int_to_f64(in[i], desc[i].dtype, (double*)p, N, stream) != hipSuccess)
+        return HPEZ_EDEVICE;
+      in[i] = p;
+      p += (N * 8 + 255) & ~(size_t)255;
+    }
+  }
   std::vector<int> f32, f64;
   for (int i = 0; i < n; i++) (desc[i].dtype == HPEZ_F32 ? f32 : f64).push_back(i);
   int rc = HPEZ_OK;
   if (!f32.empty())
-    rc = tune_group<float>(ctx, desc, d_in, opts, out_cfg, h_block_cfg, block_cfg_cap, f32, rcs,
-                           stream);
+    rc = tune_group<float>(ctx, desc, in.data(), opts, out_cfg, h_block_cfg, block_cfg_cap, f32,
+                           rcs, stream);
   if (!rc && !f64.empty())
-    rc = tune_group<double>(ctx, desc, d_in, opts, out_cfg, h_block_cfg, block_cfg_cap, f64, rcs,
-                            stream);
+    rc = tune_group<double>(ctx, desc, in.data(), opts, out_cfg, h_block_cfg, block_cfg_cap, f64,
+                            rcs, stream);
   if (rc) return rc;
   for (int i = 0; i < n; i++)
     if (rcs[i]) return rcs[i];
