@@ -500,19 +500,24 @@ def serving_section(args, binding, fields, torch, compress_gbps):
                 m = masters[(dt, nd)]
                 x = m[tuple(slice(0, v) for v in shp)].contiguous()
                 c = binding.tune(x, r.cfg, TUNE_OPTS)
-                src = (binding.compress(x, c).clone(), tuple(x.shape), x.dtype, c)
+                src = (binding.compress(x, c).clone(), tuple(x.shape), x.dtype, c, None)
                 produced.append(src)
-            r.data, r.out_shape, r.out_dtype, r.cfg = src
+            r.data, r.out_shape, r.out_dtype, r.cfg = src[:4]
 
     def on_done(r):
+        # results the run keeps stay charged against the server's budget until
+        # released: up to 64 produced streams (decompress inputs) and the sample
         if r.op == "compress" and not r.error:
-            produced.append((r.result, tuple(r.data.shape), r.data.dtype, r.config))
+            produced.append((r.result, tuple(r.data.shape), r.data.dtype, r.config, r))
             if len(produced) > 64:
-                produced.pop(0)
+                old = produced.pop(0)[4]
+                if old is not None and old.rid not in sample:
+                    srv.release(old)
         if r.rid not in sample:
             r.data = None
             if r.op == "decompress":
                 r.result = None
+                srv.release(r)
 
     srv = Server(device=0, slots=args.serve_slots, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
                  max_batch=16)

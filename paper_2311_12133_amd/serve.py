@@ -15,9 +15,13 @@ the device.
 Admission counts, per request, the library's workspace for the call
 (hpez_footprint, plus the tuner's when tuning) and the output buffer.  A slot
 context keeps its workspace between batches up to `keep_bytes` and trims it
-above, so idle slots hold at most that much beyond the admitted work.  A
-request larger than the whole budget, or one the library rejects, completes
-with its error code; the others are unaffected.
+above; that much per slot is reserved from the budget when the server starts.
+A completed request's result stays on the device and stays charged against
+the budget (its own size: compressed streams are copied out of their
+worst-case buffers) until the caller calls `Server.release(r)`; the rest of
+its admitted bytes return on completion.  A request larger than the whole
+budget, or one the library rejects, completes with its error code; the others
+are unaffected.
 
 Every request's result is the same as the plain call's on the same input: the
 batch entry points take the same steps per field as the plain ones (checked in
@@ -73,7 +77,7 @@ class LibraryBackend:
     """Runs batches through the library: per slot one HIP stream (default
     priority) and one context."""
 
-    def __init__(self, device: int = 0, keep_bytes: int = 2 << 30):
+    def __init__(self, device: int = 0, keep_bytes: int = 512 << 20):
         import torch
         self.torch = torch
         self.device = device
@@ -82,6 +86,16 @@ class LibraryBackend:
     def make_slot(self, i: int) -> dict:
         return dict(id=i, stream=self.torch.cuda.Stream(device=self.device),
                     ctx=binding.Context(self.device))
+
+    def reserved_bytes(self, slots: int) -> int:
+        """Device bytes held outside any request: each slot's kept workspace."""
+        return slots * self.keep
+
+    def result_bytes(self, r) -> int:
+        """Device bytes a completed request's result holds."""
+        if r.result is None:
+            return 0
+        return int(r.result.numel() * r.result.element_size())
 
     def close_slot(self, slot: dict):
         slot["ctx"].close()
@@ -174,7 +188,8 @@ class LibraryBackend:
             r = batch[i]
             r.config = cfgs[i]
             if sizes[k]:
-                r.result = outs[k][: sizes[k]]
+                # a right-sized copy: the worst-case buffer is freed here
+                r.result = outs[k][: sizes[k]].clone()
             else:
                 r.error = r.error or -1
 
@@ -200,9 +215,15 @@ class LibraryBackend:
 
 class Server:
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 64 << 30,
-                 max_batch: int = 16, keep_bytes: int = 2 << 30, backend=None):
+                 max_batch: int = 16, keep_bytes: int = 512 << 20, backend=None):
         self.backend = backend if backend is not None else LibraryBackend(device, keep_bytes)
         self.budget = int(hbm_budget)
+        reserve = getattr(self.backend, "reserved_bytes", None)
+        self.reserved = int(reserve(slots)) if reserve else 0
+        if self.reserved > self.budget:
+            raise ValueError("the slots' kept workspace exceeds the HBM budget")
+        self._used = self.reserved  # reserved + admitted work + held results
+        self._held = {}  # rid -> result bytes still charged
         self.max_batch = int(max_batch)
         self.slots = []
         for i in range(slots):
@@ -235,6 +256,31 @@ class Server:
                 r.done = t
             self._done.put((slot, mem, batch))
 
+    def _result_bytes(self, r) -> int:
+        f = getattr(self.backend, "result_bytes", None)
+        return int(f(r)) if f else 0
+
+    def _complete(self, mem, batch):
+        """Return a finished batch's admitted bytes except its results' (which
+        stay charged until release)."""
+        held = 0
+        for r in batch:
+            b = self._result_bytes(r) if not r.error else 0
+            if b:
+                self._held[r.rid] = b
+                held += b
+        self._used -= mem - held
+
+    def release(self, r):
+        """The caller no longer keeps r's result on the device: its bytes
+        return to the budget."""
+        self._used -= self._held.pop(r.rid, 0)
+
+    @property
+    def charged(self) -> int:
+        """Bytes charged now: reserved slot workspace, admitted work, held results."""
+        return self._used
+
     # -- dispatcher -------------------------------------------------------------
     def run(self, requests, on_arrival=None, on_done=None):
         """Serve `requests` (arrival times relative to the start).  on_arrival(r),
@@ -245,7 +291,6 @@ class Server:
         n = len(reqs)
         pending = deque()
         free = deque(self.slots)
-        free_mem = self.budget
         nxt = 0
         finished = 0
         self._t0 = time.perf_counter()
@@ -261,7 +306,7 @@ class Server:
                     if on_arrival is not None:
                         on_arrival(r)
                     self.backend.prepare(r)
-                    if r.mem > self.budget:
+                    if r.mem > self.budget - self.reserved:
                         r.error = -2  # larger than the whole budget
                         r.admitted = r.done = time.perf_counter() - self._t0
                         finished += 1
@@ -276,7 +321,7 @@ class Server:
                     except queue.Empty:
                         break
                     free.append(slot)
-                    free_mem += mem
+                    self._complete(mem, batch)
                     finished += len(batch)
                     if on_done is not None:
                         for r in batch:
@@ -288,15 +333,26 @@ class Server:
                     for r in pending:
                         if r.op != op:
                             continue
-                        if mem + r.mem > free_mem or len(take) == self.max_batch:
+                        if self._used + mem + r.mem > self.budget or len(take) == self.max_batch:
                             break
                         take.append(r)
                         mem += r.mem
                     if not take:
+                        if len(free) == len(self.slots):
+                            # nothing runs, yet the head does not fit: results the
+                            # caller still holds fill the budget; it fails (-2)
+                            # rather than waiting for a release that may not come
+                            r = pending.popleft()
+                            r.error = -2
+                            r.admitted = r.done = time.perf_counter() - self._t0
+                            finished += 1
+                            if on_done is not None:
+                                on_done(r)
+                            continue
                         break
                     for r in take:
                         pending.remove(r)
-                    free_mem -= mem
+                    self._used += mem
                     free.popleft()["inbox"].put((take, mem))
                     # the slot object moves with the batch; it comes back on completion
                 if finished >= n:
@@ -308,7 +364,7 @@ class Server:
                 try:
                     slot, mem, batch = self._done.get(timeout=wait)
                     free.append(slot)
-                    free_mem += mem
+                    self._complete(mem, batch)
                     finished += len(batch)
                     if on_done is not None:
                         for r in batch:

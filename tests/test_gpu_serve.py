@@ -90,7 +90,7 @@ def test_small_budget_still_serves_everything(torch_cuda):
     from paper_2311_12133_amd.serve import Server
     print("[case] serve with a budget of about two requests", flush=True)
     reqs, alone = make_requests(torch_cuda, n_comp=6, seed=11)
-    srv = Server(device=0, slots=3, hbm_budget=1, max_batch=4)
+    srv = Server(device=0, slots=3, hbm_budget=1, max_batch=4, keep_bytes=0)
     for r in reqs:
         srv.backend.prepare(r)
     srv.budget = 2 * max(r.mem for r in reqs)

@@ -134,3 +134,68 @@ def test_summary_percentiles():
     st = summarize(rs)
     assert st["p50_ms"] == pytest.approx(50.0)
     assert st["p99_ms"] == pytest.approx(99.0)
+
+
+class HoldingBackend(FakeBackend):
+    """Results stay on the device: each successful request holds
+    data["result_bytes"] until the caller releases it."""
+
+    def __init__(self, per_item=0.002, keep=0):
+        super().__init__(per_item)
+        self.keep = keep
+        self.held = 0
+        self.peak_charged = 0
+        self.srv = None
+
+    def reserved_bytes(self, slots):
+        return slots * self.keep
+
+    def result_bytes(self, r):
+        return r.data.get("result_bytes", 0) if r.result is not None else 0
+
+    def run(self, batch, slot):
+        with self.lock:
+            # everything the server has charged while this batch starts
+            self.peak_charged = max(self.peak_charged, self.srv.charged)
+        super().run(batch, slot)
+
+
+def test_held_results_and_reserve_are_charged():
+    be = HoldingBackend(keep=50)
+    srv = Server(slots=2, hbm_budget=400, max_batch=4, backend=be)
+    be.srv = srv
+    assert srv.charged == 100  # the two slots' kept workspace
+    rs = reqs(40, 0.0005, mem=60, extra={i: dict(result_bytes=20) for i in range(40)})
+    kept = []
+
+    def on_done(r):
+        kept.append(r)
+        if len(kept) > 5:  # the caller keeps the last five results
+            srv.release(kept.pop(0))
+
+    st = srv.run(rs, on_done=on_done)
+    assert st["completed"] == 40
+    assert be.peak_charged <= 400
+    # the five kept results are still charged, the rest returned
+    assert srv.charged == 100 + 5 * 20
+    for r in kept:
+        srv.release(r)
+    assert srv.charged == 100
+
+
+def test_unreleased_results_cannot_stall_the_server():
+    # the caller never releases: once results fill the budget, requests that
+    # cannot fit fail instead of waiting forever
+    be = HoldingBackend()
+    srv = Server(slots=2, hbm_budget=200, max_batch=2, backend=be)
+    be.srv = srv
+    rs = reqs(20, 0.001, mem=50, extra={i: dict(result_bytes=40) for i in range(20)})
+    st = srv.run(rs)
+    assert st["completed"] + st["failed"] == 20
+    assert st["failed"] > 0
+    assert all(r.error == -2 for r in rs if r.error)
+
+
+def test_reserve_larger_than_budget_rejected():
+    with pytest.raises(ValueError):
+        Server(slots=4, hbm_budget=100, backend=HoldingBackend(keep=30))
