@@ -363,6 +363,35 @@ int hpez_fit_eb(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
                 const hpez_config* cfg, const hpez_fit_opts* opts, hpez_fit_result* res,
                 hipStream_t stream);
 
+/* Launch shapes measured on the device (hpez_autotune).  A choice is cached in
+ * the context per kernel kind (0: face steps, value = lanes per work-group |
+ * points per lane << 16; 1: tuner region trials, value = lanes per work-group),
+ * dtype class (0 float32, 1 float64 and integer fields) and size class (floor
+ * log2 of the launch's points, resp. of a region's cells).  ms_before and
+ * ms_best are the kind's kernel-group times under the previous shape and the
+ * chosen one. */
+typedef struct {
+  int32_t kind;
+  int32_t dtype;
+  int32_t size_class;
+  uint32_t value;
+  double ms_before;
+  double ms_best;
+} hpez_tile_choice;
+
+/* Measure launch shapes for the calls on this field and cache the fastest in
+ * the context: the face steps of hpez_compress / hpez_decompress under cfg
+ * (lanes per work-group 64, 128 or 256 times 1, 2, 4 or 8 points per lane),
+ * and, when topts is not NULL, the region trials of hpez_tune (64, 256 or 1024
+ * lanes).  Every size class the field's calls use is tried candidate by
+ * candidate (best of three timed calls after a warm-up), the others keeping
+ * their shapes.  Shapes never change a result.  Up to cap choices are written
+ * to out; *n_out receives their number.  Allocates a stream and a
+ * reconstruction buffer for the duration of the call.  Synchronous. */
+int hpez_autotune(hpez_ctx* ctx, const hpez_field_desc* desc, const void* d_in,
+                  const hpez_config* cfg, const hpez_tune_opts* topts, hpez_tile_choice* out,
+                  int cap, int* n_out, hipStream_t stream);
+
 /* Per-kernel timing (tracing aid).  While enabled, every kernel group the
  * context launches is bracketed by HIP events on its stream; each entry point
  * folds the elapsed times into per-name totals before returning.  `bytes` is

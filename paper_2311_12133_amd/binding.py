@@ -71,6 +71,11 @@ class FitResult(C.Structure):
                 ("bytes", C.c_uint64), ("iterations", C.c_uint32), ("pad", C.c_uint32)]
 
 
+class TileChoice(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("size_class", C.c_int32),
+                ("value", C.c_uint32), ("ms_before", C.c_double), ("ms_best", C.c_double)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("bytes", C.c_uint64),
                 ("total_ms", C.c_double)]
@@ -81,7 +86,7 @@ EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_
            "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read",
            "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch",
            "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc",
-           "hpez_quality_eval", "hpez_fit_eb"]
+           "hpez_quality_eval", "hpez_fit_eb", "hpez_autotune"]
 
 _lib = None
 _lock = threading.Lock()
@@ -124,6 +129,8 @@ def lib():
             L.hpez_quality_eval.argtypes = [vp, P(FieldDesc), vp, vp, C.c_uint32, P(Quality), vp]
             L.hpez_fit_eb.argtypes = [vp, P(FieldDesc), vp, P(Config), P(FitOpts), P(FitResult),
                                       vp]
+            L.hpez_autotune.argtypes = [vp, P(FieldDesc), vp, P(Config), P(TuneOpts),
+                                        P(TileChoice), C.c_int, P(C.c_int), vp]
             _lib = L
     return _lib
 
@@ -170,6 +177,13 @@ class Context:
         if self.ptr:
             lib().hpez_ctx_destroy(self.ptr)
             self.ptr = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:
@@ -584,6 +598,34 @@ def fit_eb(x, cfg: dict, metric: str, target: float, steps_per_octave: int = 64,
                              _stream_ptr(stream)), "hpez_fit_eb")
     return dict(e=r.e, e_hi=r.e_hi, quality=_quality_dict(r.quality), bytes=r.bytes,
                 iterations=r.iterations)
+
+
+def autotune(x, cfg: dict, tune_opts: dict | None = None, stream=None, context=None) -> list:
+    """hpez_autotune: measure launch shapes for this field's compress /
+    decompress (and tune, with tune_opts) and cache the fastest in the
+    context.  Returns the choices (kind "faces" or "trials", size class, shape,
+    and the group times before and after)."""
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous device tensor")
+    keep = []
+    d = desc_from(tuple(x.shape) if x.dim() else (1,), _dtype_of(x), cfg["eb"], cfg["eb_mode"])
+    c = config_from(cfg, keep)
+    to = _tune_opts(tune_opts) if tune_opts is not None else None
+    out = (TileChoice * 64)()
+    n = C.c_int()
+    _check(lib().hpez_autotune(_cx(context, x.device.index or 0), C.byref(d),
+                               C.c_void_p(x.data_ptr()), C.byref(c),
+                               C.byref(to) if to is not None else None, out, 64, C.byref(n),
+                               _stream_ptr(stream)), "hpez_autotune")
+    res = []
+    for i in range(min(n.value, 64)):
+        t = out[i]
+        shape = (dict(lanes=t.value & 0xFFFF, points_per_lane=t.value >> 16) if t.kind == 0
+                 else dict(lanes=t.value))
+        res.append(dict(kind="faces" if t.kind == 0 else "trials", dtype_class=t.dtype,
+                        size_class=t.size_class, shape=shape, ms_before=round(t.ms_before, 4),
+                        ms_best=round(t.ms_best, 4)))
+    return res
 
 
 def profile_enable(device: int = 0, on: bool = True):

@@ -12,6 +12,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <map>
+#include <set>
 #include <new>
 #include <thread>
 #include <vector>
@@ -48,6 +50,10 @@ struct hpez_ctx {
   hipEvent_t ev_sync = nullptr;  // host waits for part of a stream's work
   void* aux = nullptr;           // integer fields' float64 copies (ctx_aux)
   size_t aux_bytes = 0;
+  // launch shapes (hpez_autotune): cached choices, the ones being tried, and
+  // the keys looked up since `seen` was cleared
+  std::map<uint64_t, uint32_t> tiles, tile_try;
+  std::set<uint64_t> tile_seen;
   // second stream for work that can overlap the caller's stream, with the
   // events that fork it from and join it back to that stream
   hipStream_t side = nullptr;
@@ -2229,6 +2235,37 @@ uint8_t* ctx_pin_tab(hpez_ctx* c, size_t bytes, int* rc)
 }
 
 int ctx_device(hpez_ctx* c) { return c->device; }
+
+static uint64_t tile_key(int kind, int dtype, uint64_t work)
+{
+  int b = 0;
+  while (b < 63 && (work >> (b + 1))) b++;  // floor log2
+  return (uint64_t)kind << 16 | (uint64_t)dtype << 8 | (uint64_t)b;
+}
+
+void ctx_tile_seen(hpez_ctx* c, bool clear, std::vector<uint64_t>* keys)
+{
+  if (keys) keys->assign(c->tile_seen.begin(), c->tile_seen.end());
+  if (clear) c->tile_seen.clear();
+}
+
+void ctx_tile_try(hpez_ctx* c, uint64_t key, uint32_t value)
+{
+  if (value) c->tile_try[key] = value;
+  else c->tile_try.erase(key);
+}
+
+void ctx_tile_set(hpez_ctx* c, uint64_t key, uint32_t value) { c->tiles[key] = value; }
+
+uint32_t ctx_tile(hpez_ctx* c, int kind, int dtype, uint64_t work, uint32_t deflt)
+{
+  const uint64_t k = tile_key(kind, dtype, work);
+  c->tile_seen.insert(k);
+  auto t = c->tile_try.find(k);
+  if (t != c->tile_try.end()) return t->second;
+  auto f = c->tiles.find(k);
+  return f != c->tiles.end() ? f->second : deflt;
+}
 
 hipStream_t ctx_fork(hpez_ctx* c, hipStream_t st)
 {

@@ -327,12 +327,13 @@ int block_job_prepare(hpez_ctx* ctx, BlockJobHost<T>& J)
   return HPEZ_OK;
 }
 
-// face-step launch geometry of a step: work-groups of 256 lanes
-static uint64_t face_wgs(uint64_t pts)
+// face-step launch geometry of a step: work-groups of `per` points (lanes
+// times points per lane; the kernel strides over the rest)
+static uint64_t face_wgs(uint64_t pts, uint64_t per)
 {
-  uint64_t b = (pts + 255) / 256;
+  uint64_t b = (pts + per - 1) / per;
   if (b > 65536) b = 65536;
-  return b;
+  return b ? b : 1;
 }
 
 template <typename T>
@@ -394,6 +395,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
     int cnt;
     uint64_t wgs;
     bool narrow;
+    uint32_t threads;
   };
   std::vector<Launch> launches;
   size_t ei = 0, wi = 0;
@@ -404,7 +406,16 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
     for (int j = 0; j < n; j++)
       if (!jobs[j].sgrp[l].empty()) ng = std::max(ng, jobs[j].sgrp[l].back() + 1);
     for (int gi = 0; gi < ng; gi++) {
-      Launch L{ei, wi, 0, 0, true};
+      // the launch shape for this launch's size class (hpez_autotune)
+      uint64_t gpts = 0;
+      for (int j = 0; j < n; j++)
+        for (size_t k = 0; k < jobs[j].steps[l].size(); k++)
+          if (jobs[j].sgrp[l][k] == gi) gpts += jobs[j].steps[l][k].off[4];
+      const uint32_t tile =
+          gpts ? ctx_tile(ctx, kTileFace, sizeof(T) == 4 ? 0 : 1, gpts, face_tile(256, 1))
+               : face_tile(256, 1);
+      Launch L{ei, wi, 0, 0, true, face_threads(tile)};
+      const uint64_t per = (uint64_t)face_threads(tile) * face_ppl(tile);
       for (int j = 0; j < n; j++)
       for (size_t k = 0; k < jobs[j].steps[l].size(); k++) {
         if (jobs[j].sgrp[l][k] != gi) continue;
@@ -420,7 +431,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
         E.xface = jobs[j].xface ? 1 : 0;
         E.fcode2 = jobs[j].fcode2 ? 1 : 0;
         E.wg_begin = L.wgs;
-        E.wg_count = face_wgs(tot);
+        E.wg_count = face_wgs(tot, per);
         hw[wi++] = L.wgs;
         L.wgs += E.wg_count;
         L.narrow = L.narrow && tot < (1ull << 32);
@@ -495,7 +506,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
                total_blocks * 729ull * (sizeof(T) + 2), cs);
   for (const Launch& L : launches)
     BCK(launch_face_steps<T>((const FaceEntry<T>*)dt + L.e0, (const uint64_t*)(dt + off_wg) + L.w0,
-                             L.cnt, L.wgs, L.narrow, mode, st));
+                             L.cnt, L.wgs, L.narrow, mode, L.threads, st));
   ctx_span_end(ctx, ev, mode == 0 ? "faces_predict" : "faces_reconstruct",
                face_pts * (sizeof(T) + 2), st);
   if (cs != st) {

@@ -115,7 +115,8 @@ hipError_t launch_planes(const PlaneJob<T>* d_tab, const uint64_t* d_wg_begin, i
 // one fused face step: entries [0, n) of the device table, total work-groups
 template <typename T>
 hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_begin, int n,
-                             uint64_t total_wg, bool narrow, int mode, hipStream_t st);
+                             uint64_t total_wg, bool narrow, int mode, uint32_t threads,
+                             hipStream_t st);
 // the block phase of jobs [0, n): d_begin[j] = first global block index of job j
 // (d_begin[n] = total); lds = largest box of the jobs
 template <typename T>

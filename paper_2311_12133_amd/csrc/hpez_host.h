@@ -100,6 +100,23 @@ hipError_t launch_f64_to_int(const double* in, int dt, void* out, uint64_t n, hi
 // grown on demand, separate from the workspace
 void* ctx_aux(hpez_ctx* c, size_t bytes, int* rc);
 
+// Launch shapes chosen per context by hpez_autotune (measured on the device),
+// keyed by kernel kind, dtype and the work's size class (floor log2 of its
+// points or cells); the default applies until a shape is cached.  Shapes never
+// change results, only speed.
+enum TileKind { kTileFace = 0, kTileTrial = 1 };
+uint32_t ctx_tile(hpez_ctx* c, int kind, int dtype, uint64_t work, uint32_t deflt);
+// the cache's keys (kind << 16 | dtype << 8 | size class), for hpez_autotune:
+// keys looked up since the last clear, a shape being tried for one key (value
+// 0 removes it), and the chosen shape of a key
+void ctx_tile_seen(hpez_ctx* c, bool clear, std::vector<uint64_t>* keys);
+void ctx_tile_try(hpez_ctx* c, uint64_t key, uint32_t value);
+void ctx_tile_set(hpez_ctx* c, uint64_t key, uint32_t value);
+// face steps: lanes per work-group (64..256) and points per lane
+inline uint32_t face_tile(uint32_t threads, uint32_t ppl) { return threads | ppl << 16; }
+inline uint32_t face_threads(uint32_t t) { return t & 0xFFFFu; }
+inline uint32_t face_ppl(uint32_t t) { return t >> 16; }
+
 // context services (api.cpp)
 void* ctx_ws(hpez_ctx* c, size_t bytes, int* rc);
 uint8_t* ctx_pin(hpez_ctx* c, size_t bytes, int* rc);

@@ -1276,10 +1276,12 @@ hipError_t launch_face_init(const FaceGeo& f, const Geom& g, const Lattice& lat,
 
 template <typename T>
 hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_begin, int n,
-                             uint64_t total_wg, bool narrow, int mode, hipStream_t st)
+                             uint64_t total_wg, bool narrow, int mode, uint32_t threads,
+                             hipStream_t st)
 {
   if (!total_wg || n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)total_wg), block(256);
+  if (threads < 64 || threads > 256 || (threads & 63)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)total_wg), block(threads);
   if (mode == 0 && narrow)
     hipLaunchKernelGGL((face_step_kernel<T, 0, uint32_t>), grid, block, 0, st, d_tab, d_wg_begin, n);
   else if (mode == 0)
@@ -1375,7 +1377,7 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
   template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
                                            size_t, int, int, hipStream_t);                        \
   template hipError_t launch_face_steps<T>(const FaceEntry<T>*, const uint64_t*, int, uint64_t,   \
-                                           bool, int, hipStream_t);                               \
+                                           bool, int, uint32_t, hipStream_t);                     \
   template hipError_t launch_minmax_faces<T>(const T*, const Geom&, const FaceGeo&, double*, int*, \
                                              int, hipStream_t);
 INST(float)

@@ -502,6 +502,7 @@ int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
 // per lane count), the others one by one.
 template <typename T>
 struct TrialBatch {
+  hpez_ctx* ctx = nullptr;          // lanes per region size class (hpez_autotune)
   std::vector<TrialJob<T>> grp[3];  // by lanes per work-group: 64, 256, 1024
   struct Single {
     TrialArgs a;
@@ -532,7 +533,9 @@ void t_add(TrialBatch<T>& tb, const TrialArgs& a, const TrialBox* boxes, uint32_
     j.n_boxes = n_boxes;
     j.n_cand = n_cand;
     j.wg_begin = 0;
-    const int lanes = trial_lanes(a.box_cap);
+    int lanes = trial_lanes(a.box_cap);
+    if (tb.ctx)
+      lanes = (int)ctx_tile(tb.ctx, kTileTrial, sizeof(T) == 4 ? 0 : 1, a.box_cap, (uint32_t)lanes);
     tb.grp[lanes == 64 ? 0 : lanes == 256 ? 1 : 2].push_back(j);
   } else {
     tb.single.push_back({a, boxes, n_boxes, n_cand, X, scratch, wq, score, hist});
@@ -999,6 +1002,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
   if (any_stats) TCK(hipStreamSynchronize(st));
   {
     TrialBatch<T> tb;
+    tb.ctx = ctx;
     for (auto& J : jobs)
       if ((rc = t_global(J, tb, st))) return rc;
     bool ahead = false;
@@ -1007,6 +1011,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     if (side) {
       join.on = true;
       TrialBatch<T> sb;
+      sb.ctx = ctx;
       for (auto& J : jobs)
         if ((rc = t_blocks_ahead(J, sb, side))) return rc;
       hipEvent_t evb = ctx_span_begin(ctx, side);
@@ -1034,6 +1039,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
   TCK(hipStreamSynchronize(st));
   {
     TrialBatch<T> tb;
+    tb.ctx = ctx;
     for (auto& J : jobs)
       if ((rc = t_hist(J, tb, st))) return rc;
     if ((rc = t_launch(ctx, tb, true, d_tab, tab_cap, st))) return rc;
@@ -1052,6 +1058,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
   }
   if (any_ab) {
     TrialBatch<T> tb;
+    tb.ctx = ctx;
     for (auto& J : jobs)
       if ((rc = t_ab(J, tb, st))) return rc;
     hipEvent_t ev = ctx_span_begin(ctx, st);
@@ -1068,6 +1075,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
   }
   {
     TrialBatch<T> tb;
+    tb.ctx = ctx;
     for (auto& J : jobs)
       if ((rc = t_blocks(J, tb, st))) return rc;
     hipEvent_t ev = ctx_span_begin(ctx, st);
