@@ -99,10 +99,25 @@ double entropy_bits_pairs(const uint32_t* pairs, uint32_t n)
   uint64_t tot = 0;
   for (uint32_t i = 0; i < n; i++) tot += a[2 * i + 1];
   if (tot == 0) return 0.0;
+  // c log2(tot / c) per bin, summed in bin order; the term of a small count is
+  // computed once per count (the same expression, so the same bits): most bins
+  // of a trial histogram hold small counts that repeat
+  constexpr uint32_t kSmall = 4096;
+  static thread_local double term[kSmall];
+  static thread_local uint64_t term_tot[kSmall];
   double acc = 0.0;
   for (uint32_t i = 0; i < n; i++) {
-    const double c = (double)a[2 * i + 1];
-    acc += c * std::log2((double)tot / c);
+    const uint32_t ci = a[2 * i + 1];
+    const double c = (double)ci;
+    if (ci < kSmall) {
+      if (term_tot[ci] != tot + 1) {
+        term[ci] = c * std::log2((double)tot / c);
+        term_tot[ci] = tot + 1;  // + 1: a zeroed entry never matches
+      }
+      acc += term[ci];
+    } else {
+      acc += c * std::log2((double)tot / c);
+    }
   }
   return acc / (double)tot;
 }
