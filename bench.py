@@ -200,6 +200,11 @@ def main():
                    max_err_over_eb=round(qual["max_abs_err"] / e, 6), ssim_window=8,
                    eval_ms=round(q_ms, 3), eval_GBps=round(2 * nbytes / (q_ms * 1e-3) / 1e9, 1))
 
+    # the last stream's decompression recorded as a HIP graph (hpez_decompress_plan)
+    # and replayed, outside the timed steps; every replay equals the eager output
+    graph = plan_section(binding, torch, [out[: times[-1][3]]], [torch.empty_like(rec)], [rec],
+                         nbytes)
+
     tune_s = sum(t[0] for t in times) / len(times)
     comp_s = sum(t[1] for t in times) / len(times)
     dec_s = sum(t[2] for t in times) / len(times)
@@ -279,6 +284,7 @@ def main():
         "bits_per_value": round(size * 8 / x.size, 4),
         "max_err_over_eb": round(err / e, 6),
         "quality": quality,
+        "decompress_graph": graph,
         "autotune": tiles,
         "roofline": roofline,
         "calls_roofline": calls,
@@ -289,6 +295,37 @@ def main():
         "serving": serving,
     }
     print(json.dumps(res))
+
+
+def plan_section(binding, torch, streams, outs, refs, nbytes, reps=10):
+    """Decompression plan of `streams` into `outs` (hpez_decompress_plan: one
+    eager decompression, then the same device work recorded as a HIP graph),
+    then `reps` replays, each timed from launch to synchronisation (median);
+    every replay's outputs are compared with `refs` on the device."""
+    t0 = time.perf_counter()
+    plan = binding.DecompressPlan(streams, outs=outs)
+    torch.cuda.synchronize()
+    make_ms = (time.perf_counter() - t0) * 1e3
+    ts = []
+    try:
+        for _ in range(reps):
+            for o in outs:
+                o.zero_()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            plan.launch()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - ta)
+            if plan.status() != [0] * len(streams):
+                raise SystemExit("decompression plan replay reported a corrupt stream")
+            for o, r in zip(outs, refs):
+                if not torch.equal(o.view(torch.uint8), r.view(torch.uint8)):
+                    raise SystemExit("decompression plan replay differs from the eager call")
+    finally:
+        plan.close()
+    ms = sorted(ts)[len(ts) // 2] * 1e3
+    return dict(ms=round(ms, 3), GBps=round(nbytes / (ms * 1e-3) / 1e9, 2),
+                make_ms=round(make_ms, 2), replays=reps, identical=True)
 
 
 def f64_section(args, binding, fields, torch, shape):
@@ -422,6 +459,8 @@ def batch_section(args, binding, fields, torch):
     if not (same and same_rec):
         raise SystemExit("batched results differ from the plain calls'")
     med = lambda v: sorted(v)[len(v) // 2]
+    # the batch's decompression recorded once as a HIP graph and replayed
+    graph = plan_section(binding, torch, sb, recs_p, recs_b, nbytes, reps=args.batch_steps)
     pc, pd = med([t[0] for t in tp]), med([t[1] for t in tp])
     bc, bd = med([t[0] for t in tb_]), med([t[1] for t in tb_])
     comp = sum(s.numel() for s in sb)
@@ -436,6 +475,9 @@ def batch_section(args, binding, fields, torch):
         "batched_tune_compress_GBps": round(nbytes / bc / 1e9, 2),
         "batched_decompress_GBps": round(nbytes / bd / 1e9, 2),
         "identical": True,
+        "graph_decompress_ms": graph["ms"],
+        "speedup_graph_decompress": round(pd * 1e3 / graph["ms"], 3),
+        "graph_decompress_GBps": graph["GBps"],
         "kernel_groups_batched": groups,
     }
 

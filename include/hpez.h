@@ -15,7 +15,8 @@
  *   - Device pointers ("d_") are memory on the context's GPU (for instance
  *     torch tensors' data_ptr()); host pointers ("h_" or unprefixed structs) are
  *     ordinary process memory.  The caller owns every buffer it passes; the
- *     library keeps no pointer past the call.
+ *     library keeps no pointer past the call (except a decompression plan,
+ *     which borrows its streams and outputs while it lives).
  *   - `stream` is a hipStream_t (NULL = the default stream) on which all
  *     device work of the call is ordered.  Calls that need a result on the host
  *     (compress: the stream size; tune: the decisions) synchronise that stream
@@ -238,6 +239,45 @@ int hpez_decompress(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_o
 int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const uint64_t* in_size,
                           void* const* d_out, const uint64_t* out_cap, int* rcs,
                           hipStream_t stream);
+
+/* Decompression plans: the decompression of fixed streams into fixed outputs
+ * (the inverse D_theta of Eq. 1, Sec. 4 steps 3-4 reversed) recorded once as
+ * a HIP graph and replayed stream-ordered, with no host synchronisation and
+ * no host work per replay.  For streams that are decompressed many times
+ * (fields kept compressed in device memory and expanded on each read).
+ *
+ * hpez_decompress_plan takes the arguments of hpez_decompress_batch (device
+ * streams d_in[i] of in_size[i] bytes, device outputs d_out[i] of out_cap[i]
+ * bytes, rcs[i] per stream on the host) and runs that decompression once on
+ * `stream` (synchronising it), which checks every stream and fills d_out;
+ * any failure is returned as by hpez_decompress_batch and no plan is made.
+ * It then records the same device work into a graph.  The plan holds its own
+ * workspace and host staging (hpez_footprint's decompression need per
+ * stream, plus the decode tables); `ctx` only lends its tuned launch shapes
+ * (hpez_autotune), and may be used for other calls meanwhile.  d_in[i] and
+ * d_out[i] are borrowed: they must stay allocated, and the streams' bytes
+ * unchanged, while the plan lives.  Returns HPEZ_ENOMEM if the plan's memory
+ * cannot be allocated, HPEZ_EDEVICE if recording or instantiation fails.
+ *
+ * hpez_plan_launch enqueues one replay on `stream` and returns; the outputs
+ * are complete when the stream reaches that point and are bit-identical to
+ * hpez_decompress_batch's.  Replays of one plan must not overlap (they share
+ * the plan's workspace): keep them on one stream or order them with events.
+ *
+ * hpez_plan_status synchronises `stream` and reads the device status of the
+ * last replay enqueued before it on that stream: rcs[i] (host, n entries)
+ * receives HPEZ_OK or HPEZ_ECORRUPT for stream i, and the first nonzero one
+ * is returned.
+ *
+ * hpez_plan_destroy frees the plan; no replay of it may still be running
+ * (synchronise the streams it was launched on first). */
+typedef struct hpez_plan hpez_plan;
+int hpez_decompress_plan(hpez_ctx* ctx, int n, const void* const* d_in, const uint64_t* in_size,
+                         void* const* d_out, const uint64_t* out_cap, int* rcs,
+                         hipStream_t stream, hpez_plan** out_plan);
+int hpez_plan_launch(hpez_plan* plan, hipStream_t stream);
+int hpez_plan_status(hpez_plan* plan, hipStream_t stream, int* rcs);
+void hpez_plan_destroy(hpez_plan* plan);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): hpez_decompress on GPU

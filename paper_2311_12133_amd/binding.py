@@ -86,7 +86,8 @@ EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_
            "hpez_tune", "hpez_footprint", "hpez_profile_enable", "hpez_profile_read",
            "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch",
            "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc",
-           "hpez_quality_eval", "hpez_fit_eb", "hpez_autotune"]
+           "hpez_quality_eval", "hpez_fit_eb", "hpez_autotune", "hpez_decompress_plan",
+           "hpez_plan_launch", "hpez_plan_status", "hpez_plan_destroy"]
 
 _lib = None
 _lock = threading.Lock()
@@ -131,6 +132,12 @@ def lib():
                                       vp]
             L.hpez_autotune.argtypes = [vp, P(FieldDesc), vp, P(Config), P(TuneOpts),
                                         P(TileChoice), C.c_int, P(C.c_int), vp]
+            L.hpez_decompress_plan.argtypes = [vp, C.c_int, P(vp), P(u64), P(vp), P(u64),
+                                               P(C.c_int), vp, P(vp)]
+            L.hpez_plan_launch.argtypes = [vp, vp]
+            L.hpez_plan_status.argtypes = [vp, vp, P(C.c_int)]
+            L.hpez_plan_destroy.argtypes = [vp]
+            L.hpez_plan_destroy.restype = None
             _lib = L
     return _lib
 
@@ -554,6 +561,68 @@ def decompress_batch(streams, stream=None, outs=None, context=None, rcs_out=None
         rcs_out[:] = [int(rcs[i]) for i in range(n)]
     _check(rc, "hpez_decompress_batch")
     return res
+
+
+class DecompressPlan:
+    """hpez_decompress_plan: the decompression of fixed device streams into
+    fixed device outputs, run once (checked, outputs filled) and recorded as a
+    HIP graph; launch() replays it on a stream with no host work, status()
+    synchronises and returns the per-stream codes of the last replay.  The
+    streams and outputs (kept referenced here) must not change meanwhile."""
+
+    def __init__(self, streams, outs=None, stream=None, context=None):
+        torch = _torch()
+        n = len(streams)
+        if n == 0:
+            raise ValueError("a plan needs at least one stream")
+        dev = streams[0].device.index or 0
+        if outs is None:
+            heads = torch.stack([torch.nn.functional.pad(s[:512], (0, max(0, 512 - min(512, s.numel()))))
+                                 for s in streams]).cpu().numpy()
+            outs = []
+            for i, s in enumerate(streams):
+                info = inspect(heads[i].tobytes())
+                outs.append(torch.empty(info["dims"], dtype=_torch_dtype(info["dtype"]),
+                                        device=s.device))
+        self.streams, self.outs, self.n, self.device = list(streams), list(outs), n, dev
+        ins, optr = (C.c_void_p * n)(), (C.c_void_p * n)()
+        isz, caps = (C.c_uint64 * n)(), (C.c_uint64 * n)()
+        rcs = (C.c_int * n)()
+        for i, (s, o) in enumerate(zip(self.streams, self.outs)):
+            ins[i], isz[i] = s.data_ptr(), s.numel()
+            optr[i], caps[i] = o.data_ptr(), o.numel() * o.element_size()
+        self.ptr = C.c_void_p()
+        rc = lib().hpez_decompress_plan(_cx(context, dev), n, ins, isz, optr, caps, rcs,
+                                        _stream_ptr(stream), C.byref(self.ptr))
+        self.rcs = [int(rcs[i]) for i in range(n)]
+        _check(rc, "hpez_decompress_plan")
+
+    def launch(self, stream=None):
+        _check(lib().hpez_plan_launch(self.ptr, _stream_ptr(stream)), "hpez_plan_launch")
+        return self.outs
+
+    def status(self, stream=None) -> list:
+        rcs = (C.c_int * self.n)()
+        lib().hpez_plan_status(self.ptr, _stream_ptr(stream), rcs)
+        return [int(rcs[i]) for i in range(self.n)]
+
+    def close(self):
+        if self.ptr:
+            lib().hpez_plan_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _quality_dict(q: Quality) -> dict:

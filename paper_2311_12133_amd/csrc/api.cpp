@@ -58,6 +58,19 @@ struct hpez_ctx {
   // events that fork it from and join it back to that stream
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // recording a decompression plan (hpez_decompress_plan): the call repeats
+  // the device work of the eager call just made on this context, whose host
+  // results (headers, code lengths, block configurations) are still in its
+  // staging; nothing is synchronised, fetched or allocated, and each stream's
+  // end-of-call check is recorded in `checks` instead of being made
+  bool capture = false;
+  struct Check {
+    int idx;              // the stream's index in the call
+    const int* status;    // device status word
+    const uint64_t* tot;  // device count of verbatim values (or outliers)
+    uint64_t want;        // the count the header gives
+  };
+  std::vector<Check> checks;
   // kernel timing (hpez_profile_enable)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -1778,6 +1791,9 @@ int decompress_jobs(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, hipStream_t st)
   for (auto& J : jobs) d_take(J, bw, pb);
   bool need_sync = false;
   for (auto& J : jobs) {
+    // a recording keeps the lengths and configurations the eager call fetched
+    // (same staging addresses); constant fields still record their copies
+    if (ctx->capture && J.Lo.predictor != 2) continue;
     rc = d_fetch(J, st, &need_sync);
     if (rc) return rc;
   }
@@ -1794,6 +1810,7 @@ int decompress_jobs(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, hipStream_t st)
   }
   rc = block_phase<T>(ctx, bj, 1, bw, st);
   if (rc) return rc;
+  if (ctx->capture) return HPEZ_OK;  // checks: decompress_group
   for (auto& J : jobs) {
     if (J.rc || J.Lo.predictor == 2) continue;
     HIPCK(hipMemcpyAsync(J.h_status, J.status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1888,7 +1905,13 @@ int decompress_group(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, const std::vecto
 {
   const int rc = decompress_jobs<T>(ctx, jobs, st);
   if (rc) return rc;
-  for (size_t k = 0; k < idx.size(); k++) rcs[idx[k]] = jobs[k].rc;
+  for (size_t k = 0; k < idx.size(); k++) {
+    rcs[idx[k]] = jobs[k].rc;
+    const DJob<T>& J = jobs[k];
+    if (ctx->capture && !J.rc && J.Lo.predictor != 2)
+      ctx->checks.push_back({idx[k], J.status, J.zoff + J.nch,
+                             J.Lo.predictor == 1 ? J.Lo.n_outlier : J.Lo.n_unpred});
+  }
   return HPEZ_OK;
 }
 }  // namespace
@@ -2100,12 +2123,12 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
   if (rc) return rc;
   for (int i = 0; i < n; i++) {
     rcs[i] = in_size[i] < (uint64_t)kHdrBytes ? HPEZ_ECORRUPT : HPEZ_OK;
-    if (!rcs[i])
+    if (!rcs[i] && !ctx->capture)  // a recording reads the eager call's prefixes
       HIPCK(hipMemcpyAsync(ctx->pin_pre + (size_t)i * kPrefixBytes, d_in[i],
                            std::min<uint64_t>(in_size[i], kPrefixBytes), hipMemcpyDeviceToHost,
                            stream));
   }
-  HIPCK(hipStreamSynchronize(stream));
+  if (!ctx->capture) HIPCK(hipStreamSynchronize(stream));
   std::vector<int> i32, i64;
   std::vector<DJob<float>> j32;
   std::vector<DJob<double>> j64;
@@ -2167,7 +2190,7 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
     if (!int_out[k] || rcs[i64[k]]) continue;
     HIPCK(launch_f64_to_int(j64[k].out, j64[k].d.dtype, int_out[k], points_of(&j64[k].d), stream));
   }
-  if (aux) HIPCK(hipStreamSynchronize(stream));
+  if (aux && !ctx->capture) HIPCK(hipStreamSynchronize(stream));
   for (int i = 0; i < n; i++)
     if (rcs[i]) return rcs[i];
   return HPEZ_OK;
@@ -2341,3 +2364,201 @@ int decompress_fixed(int device, void* ws, size_t ws_bytes, const void* d_in, ui
 }
 
 }  // namespace hpez
+
+// ---------------------------------------------------------------------------
+// Decompression plans: the device work of one decompression call recorded as
+// a HIP graph on a private context, replayed without host work.
+
+struct hpez_plan {
+  // private contexts (workspace and staging of the replays): one for the
+  // float32 streams, one for the others (float64 arithmetic).  A call's two
+  // dtype groups reuse one context's host staging one after the other, which
+  // a graph's copy nodes, reading host memory when replayed, cannot share.
+  hpez_ctx* pc[2] = {nullptr, nullptr};
+  hipStream_t cs = nullptr;  // the stream the graph is recorded on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int n = 0;
+  std::vector<hpez_ctx::Check> checks;  // idx: the stream's index in the plan
+  uint8_t* h_res = nullptr;             // pinned: status words and counts read back
+};
+
+namespace {
+
+void plan_free(hpez_plan* p)
+{
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cs) (void)hipStreamDestroy(p->cs);
+  if (p->h_res) (void)hipHostFree(p->h_res);
+  for (hpez_ctx* c : p->pc)
+    if (c) hpez_ctx_destroy(c);
+  delete p;
+}
+
+// true if the graph holds a memset node: the recorded work clears memory only
+// by copies and kernels, so such a node means an unexpected call was recorded
+bool graph_has_memset(hipGraph_t g)
+{
+  size_t nn = 0;
+  if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return true;
+  std::vector<hipGraphNode_t> nodes(nn);
+  if (nn && hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return true;
+  for (hipGraphNode_t nd : nodes) {
+    hipGraphNodeType t;
+    if (hipGraphNodeGetType(nd, &t) != hipSuccess || t == hipGraphNodeTypeMemset) return true;
+  }
+  return false;
+}
+
+int plan_device(const hpez_plan* p) { return p->pc[0] ? p->pc[0]->device : p->pc[1]->device; }
+
+// the streams of one dtype group, as hpez_decompress_batch arguments
+struct PlanGroup {
+  std::vector<int> idx;
+  std::vector<const void*> in;
+  std::vector<uint64_t> size, cap;
+  std::vector<void*> out;
+  std::vector<int> rcs;
+  int call(hpez_ctx* c, hipStream_t st)
+  {
+    return hpez_decompress_batch(c, (int)idx.size(), in.data(), size.data(), out.data(), cap.data(),
+                                 rcs.data(), st);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int hpez_decompress_plan(hpez_ctx* ctx, int n, const void* const* d_in, const uint64_t* in_size,
+                         void* const* d_out, const uint64_t* out_cap, int* rcs,
+                         hipStream_t stream, hpez_plan** out_plan)
+{
+  if (!out_plan) return HPEZ_EINVAL;
+  *out_plan = nullptr;
+  if (!ctx || n < 1 || !d_in || !in_size || !d_out || !out_cap || !rcs) return HPEZ_EINVAL;
+  for (int i = 0; i < n; i++)
+    if (!d_in[i] || !d_out[i]) return HPEZ_EINVAL;
+  DevScope ds(ctx->device);
+  // headers: the dtype group of every stream
+  std::vector<uint8_t> hdr((size_t)n * kHdrBytes, 0);
+  for (int i = 0; i < n; i++) {
+    rcs[i] = in_size[i] < (uint64_t)kHdrBytes ? HPEZ_ECORRUPT : HPEZ_OK;
+    if (!rcs[i])
+      HIPCK(hipMemcpyAsync(hdr.data() + (size_t)i * kHdrBytes, d_in[i], kHdrBytes,
+                           hipMemcpyDeviceToHost, stream));
+  }
+  HIPCK(hipStreamSynchronize(stream));
+  PlanGroup grp[2];
+  for (int i = 0; i < n; i++) {
+    hpez_field_desc dd;
+    hpez_config cc;
+    Layout L;
+    if (!rcs[i]) rcs[i] = read_header(hdr.data() + (size_t)i * kHdrBytes, in_size[i], &dd, &cc, &L);
+    if (rcs[i]) return rcs[i];
+    PlanGroup& G = grp[dd.dtype == HPEZ_F32 ? 0 : 1];
+    G.idx.push_back(i);
+    G.in.push_back(d_in[i]);
+    G.size.push_back(in_size[i]);
+    G.out.push_back(d_out[i]);
+    G.cap.push_back(out_cap[i]);
+    G.rcs.push_back(HPEZ_OK);
+  }
+  hpez_plan* p = new (std::nothrow) hpez_plan;
+  if (!p) return HPEZ_ENOMEM;
+  p->n = n;
+  // the eager calls: check every stream, fill the outputs and size each
+  // group's workspace and staging
+  int rc = HPEZ_OK;
+  for (int g = 0; g < 2 && !rc; g++) {
+    PlanGroup& G = grp[g];
+    if (G.idx.empty()) continue;
+    rc = hpez_ctx_create(&p->pc[g], ctx->device);
+    if (rc) break;
+    p->pc[g]->tiles = ctx->tiles;
+    rc = G.call(p->pc[g], stream);
+    for (size_t k = 0; k < G.idx.size(); k++) rcs[G.idx[k]] = G.rcs[k];
+  }
+  if (!rc && hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking) != hipSuccess) rc = HPEZ_EDEVICE;
+  if (rc) {
+    plan_free(p);
+    return rc;
+  }
+  // the recording: same jobs, same buffers; no growth (fixed) and no second
+  // stream, so every node lands on the recorded stream
+  if (hipStreamBeginCapture(p->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    plan_free(p);
+    return HPEZ_EDEVICE;
+  }
+  for (int g = 0; g < 2 && !rc; g++) {
+    if (!p->pc[g]) continue;
+    p->pc[g]->capture = true;
+    p->pc[g]->fixed = true;
+    rc = grp[g].call(p->pc[g], p->cs);
+    p->pc[g]->capture = false;
+  }
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->cs, &gr);
+  p->graph = gr;
+  if (rc || e != hipSuccess || !gr || graph_has_memset(gr) ||
+      hipGraphInstantiateWithFlags(&p->exec, gr, 0) != hipSuccess) {
+    plan_free(p);
+    return rc ? rc : HPEZ_EDEVICE;
+  }
+  for (int g = 0; g < 2; g++) {
+    if (!p->pc[g]) continue;
+    for (hpez_ctx::Check c : p->pc[g]->checks) {
+      c.idx = grp[g].idx[c.idx];
+      p->checks.push_back(c);
+    }
+  }
+  if (hipHostMalloc((void**)&p->h_res, p->checks.size() * 16 + 16, hipHostMallocDefault) !=
+      hipSuccess) {
+    p->h_res = nullptr;
+    plan_free(p);
+    return HPEZ_ENOMEM;
+  }
+  *out_plan = p;
+  return HPEZ_OK;
+}
+
+int hpez_plan_launch(hpez_plan* plan, hipStream_t stream)
+{
+  if (!plan || !plan->exec) return HPEZ_EINVAL;
+  DevScope ds(plan_device(plan));
+  return hipGraphLaunch(plan->exec, stream) == hipSuccess ? HPEZ_OK : HPEZ_EDEVICE;
+}
+
+int hpez_plan_status(hpez_plan* plan, hipStream_t stream, int* rcs)
+{
+  if (!plan || !rcs) return HPEZ_EINVAL;
+  DevScope ds(plan_device(plan));
+  const size_t nc = plan->checks.size();
+  uint64_t* tot = reinterpret_cast<uint64_t*>(plan->h_res);
+  int* status = reinterpret_cast<int*>(plan->h_res + nc * 8);
+  for (size_t k = 0; k < nc; k++) {
+    const hpez_ctx::Check& c = plan->checks[k];
+    HIPCK(hipMemcpyAsync(&status[k], c.status, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCK(hipMemcpyAsync(&tot[k], c.tot, 8, hipMemcpyDeviceToHost, stream));
+  }
+  HIPCK(hipStreamSynchronize(stream));
+  for (int i = 0; i < plan->n; i++) rcs[i] = HPEZ_OK;
+  for (size_t k = 0; k < nc; k++) {
+    const hpez_ctx::Check& c = plan->checks[k];
+    if (status[k] || tot[k] != c.want) rcs[c.idx] = HPEZ_ECORRUPT;
+  }
+  for (int i = 0; i < plan->n; i++)
+    if (rcs[i]) return rcs[i];
+  return HPEZ_OK;
+}
+
+void hpez_plan_destroy(hpez_plan* plan)
+{
+  if (!plan) return;
+  DevScope ds(plan_device(plan));
+  plan_free(plan);
+}
+
+}  // extern "C"

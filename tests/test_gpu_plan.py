@@ -1,0 +1,159 @@
+"""GPU: decompression plans (hpez_decompress_plan, hpez_plan_launch,
+hpez_plan_status).  A plan records a decompression as a HIP graph; every
+replay must give the oracle's reconstruction bit for bit.  Each test replays
+several times, with the outputs cleared and the program's own eager work and
+synchronisations between replays, and checks every replay and its device
+status.  Streams: block-wise tuned float32 (128^3, through the face and block
+kernels) and float64 fields, an integer field, a Lorenzo stream, a constant
+field, 1-D and 4-D fields."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from cfgs import make_cfg
+from oracle import oracle as O
+from paper_2311_12133_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+TUNE = dict(global_rate=0.05, sub_rate=0.04, lorenzo_coef=1.0, block_log2=5, allow_freeze=1,
+            allow_lorenzo=1, block_wise=1)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_12133_amd import binding
+    binding.lib()
+    return torch
+
+
+def int_field(shape, seed=4):
+    rng = np.random.default_rng(seed)
+    g = fields.gaussian_field(shape, -5.0 / 3.0, rng)
+    g = (g - g.min()) / (g.max() - g.min())
+    return np.round(-20000.0 + g * 40000.0).astype(np.int16)
+
+
+@pytest.fixture(scope="module")
+def streams(torch_cuda):
+    """(device stream, oracle reconstruction, label) of each case."""
+    from paper_2311_12133_amd import binding
+    torch = torch_cuda
+    cases = []
+
+    def add(x, cfg, label, tune=False):
+        print(f"[case] plan input {label}", flush=True)
+        xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        if tune:
+            cfg = binding.tune(xt, cfg, TUNE)
+        s = binding.compress(xt, cfg)
+        torch.cuda.synchronize()
+        cases.append((s, O.decompress(s.cpu().numpy().tobytes()), label))
+
+    add(fields.random_field((128, 128, 128), 11, np.float32, "smooth"),
+        make_cfg((128, 128, 128), eb=1e-3), "f32 128^3 tuned", tune=True)
+    add(fields.random_field((70, 66, 97), 12, np.float64, "mixed"),
+        make_cfg((70, 66, 97), dtype="f64", eb=1e-4), "f64 tuned", tune=True)
+    add(int_field((37, 70, 129)), make_cfg((37, 70, 129), dtype="i16", eb=3.0, eb_mode="abs",
+                                           kind="nat"), "i16")
+    add(fields.random_field((64, 80, 50), 13, np.float32, "rough"),
+        make_cfg((64, 80, 50), eb=1e-3, predictor="lorenzo"), "lorenzo")
+    add(np.full((20, 30, 40), 3.5, np.float32), make_cfg((20, 30, 40), eb=1e-3), "constant")
+    add(fields.random_field((5000,), 14, np.float64, "smooth"),
+        make_cfg((5000,), dtype="f64", eb=1e-3, kind="nak"), "1-D")
+    add(fields.random_field((9, 17, 33, 5), 15, np.float32, "mixed"),
+        make_cfg((9, 17, 33, 5), eb=1e-3, kind="nat", md=1), "4-D")
+    return cases
+
+
+def check_replays(torch, plan, refs, labels, stream=None, other=None, reps=3):
+    from paper_2311_12133_amd import binding
+    for r in range(reps):
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            for o in plan.outs:
+                o.zero_()
+        if other is not None:
+            # eager work of the program between replays
+            binding.decompress(other)
+        torch.cuda.synchronize()
+        print(f"[case] replay {r}", flush=True)
+        plan.launch(stream)
+        assert plan.status(stream) == [0] * len(refs)
+        torch.cuda.synchronize()
+        for o, ref, lab in zip(plan.outs, refs, labels):
+            got = o.cpu().numpy()
+            assert got.dtype == ref.dtype and np.array_equal(got.view(np.uint8), ref.view(np.uint8)), \
+                f"replay {r}: {lab} differs from the oracle"
+
+
+def test_plan_single_stream(torch_cuda, streams):
+    from paper_2311_12133_amd import binding
+    s, ref, lab = streams[0]
+    print(f"[case] single plan {lab}", flush=True)
+    plan = binding.DecompressPlan([s])
+    try:
+        assert plan.rcs == [0]
+        torch_cuda.cuda.synchronize()
+        assert np.array_equal(plan.outs[0].cpu().numpy(), ref)  # the eager call's output
+        check_replays(torch_cuda, plan, [ref], [lab], other=streams[1][0])
+    finally:
+        plan.close()
+
+
+def test_plan_batch(torch_cuda, streams):
+    from paper_2311_12133_amd import binding
+    print("[case] batch plan of every case", flush=True)
+    plan = binding.DecompressPlan([c[0] for c in streams])
+    try:
+        assert plan.rcs == [0] * len(streams)
+        check_replays(torch_cuda, plan, [c[1] for c in streams], [c[2] for c in streams],
+                      other=streams[0][0])
+    finally:
+        plan.close()
+
+
+def test_plan_on_caller_stream(torch_cuda, streams):
+    from paper_2311_12133_amd import binding
+    torch = torch_cuda
+    st = torch.cuda.Stream()
+    sel = [streams[1], streams[2], streams[3]]
+    print("[case] plan on a caller stream", flush=True)
+    with torch.cuda.stream(st):
+        plan = binding.DecompressPlan([c[0] for c in sel], stream=st)
+    try:
+        check_replays(torch, plan, [c[1] for c in sel], [c[2] for c in sel], stream=st,
+                      other=streams[4][0])
+    finally:
+        st.synchronize()
+        plan.close()
+
+
+def test_plan_outlives_other_calls_on_its_context(torch_cuda, streams):
+    """The plan keeps its own workspace: calls on the context it was made from,
+    which grow and trim that context's workspace, leave its replays intact."""
+    from paper_2311_12133_amd import binding
+    torch = torch_cuda
+    s, ref, lab = streams[1]
+    with binding.Context(0) as cx:
+        plan = binding.DecompressPlan([s], context=cx)
+        try:
+            binding.decompress(streams[0][0], context=cx)
+            cx.trim(0)
+            torch.cuda.synchronize()
+            check_replays(torch, plan, [ref], [lab], reps=2)
+        finally:
+            plan.close()
+
+
+def test_plan_rejects_small_output(torch_cuda, streams):
+    from paper_2311_12133_amd import binding
+    torch = torch_cuda
+    s, ref, _ = streams[2]
+    small = torch.empty(ref.size - 1, dtype=torch.int16, device="cuda")
+    with pytest.raises(binding.HpezError) as ei:
+        binding.DecompressPlan([s], outs=[small])
+    assert ei.value.code == -5
