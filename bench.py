@@ -205,6 +205,10 @@ def main():
     graph = plan_section(binding, torch, [out[: times[-1][3]]], [torch.empty_like(rec)], [rec],
                          nbytes)
 
+    # the lossless stage after Huffman coding on the last stream (Sec. 4 step 5),
+    # outside the timed steps: container size and encode / decode rates
+    lossless = lossless_section(binding, torch, out[: times[-1][3]], nbytes)
+
     tune_s = sum(t[0] for t in times) / len(times)
     comp_s = sum(t[1] for t in times) / len(times)
     dec_s = sum(t[2] for t in times) / len(times)
@@ -285,6 +289,7 @@ def main():
         "max_err_over_eb": round(err / e, 6),
         "quality": quality,
         "decompress_graph": graph,
+        "lossless": lossless,
         "autotune": tiles,
         "roofline": roofline,
         "calls_roofline": calls,
@@ -295,6 +300,34 @@ def main():
         "serving": serving,
     }
     print(json.dumps(res))
+
+
+def lossless_section(binding, torch, stream, nbytes, reps=5):
+    """hpez_lossless_encode / hpez_lossless_decode of one compressed stream:
+    the container's size, the whole-pipeline ratio with it, and the median
+    encode and decode times (launch to synchronisation; both calls synchronise
+    to read sizes); the decoded bytes must equal the stream."""
+    te, td = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        z = binding.lossless_encode(stream)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        back = binding.lossless_decode(z)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        te.append(tb - ta)
+        td.append(tc - tb)
+    if not torch.equal(back, stream):
+        raise SystemExit("lossless stage round trip differs")
+    med = lambda v: sorted(v)[len(v) // 2]
+    n = stream.numel()
+    return dict(stream_bytes=int(n), container_bytes=int(z.numel()),
+                stage_ratio=round(n / z.numel(), 4),
+                compression_ratio=round(nbytes / z.numel(), 3),
+                encode_ms=round(med(te) * 1e3, 3), decode_ms=round(med(td) * 1e3, 3),
+                encode_GBps=round(n / med(te) / 1e9, 2), decode_GBps=round(n / med(td) / 1e9, 2))
 
 
 def plan_section(binding, torch, streams, outs, refs, nbytes, reps=10):

@@ -279,6 +279,35 @@ int hpez_plan_launch(hpez_plan* plan, hipStream_t stream);
 int hpez_plan_status(hpez_plan* plan, hipStream_t stream, int* rcs);
 void hpez_plan_destroy(hpez_plan* plan);
 
+/* Lossless stage after Huffman coding (Sec. 4, step 5), for any byte string
+ * (normally a stream of hpez_compress).  The bytes become tokens: a nonzero
+ * byte v is token v (1..255); a maximal run of k zero bytes is floor(k/4096)
+ * tokens 4351 followed, when r = k mod 4096 is not 0, by token 255 + r.  The
+ * tokens are Huffman-coded (canonical code, chunks of 1024, as the
+ * quantization codes); if that is not smaller than the input, the input is
+ * stored.  Container (little-endian): u32 magic "HPZL", u16 version 1, u16
+ * mode (0 stored, 1 coded), u64 n, u64 n_tokens, u64 payload_bits, u32 chunk,
+ * u32 sym_min, u32 sym_max, u32 run limit (4096); then the n bytes (mode 0),
+ * or code lengths u8[sym_max - sym_min + 1], chunk bit counts
+ * u16[ceil(n_tokens / 1024)] and payload u32[ceil(payload_bits / 32)], each
+ * section starting 8-byte aligned (mode 1).
+ *
+ * hpez_lossless_bound: the largest container for n input bytes (48 + n).
+ * hpez_lossless_encode: d_in (device, n bytes, n < 2^32 - 1, else
+ *   HPEZ_EUNSUPPORTED) into d_out (device, out_cap >= the bound, else
+ *   HPEZ_ENOSPC); *out_size (host) receives the container's size.
+ *   Synchronises the stream (the codebook is built on the host).
+ * hpez_lossless_decode: the container d_in (device, in_size bytes) into d_out
+ *   (device, out_cap bytes); *out_size (host) receives n (also when out_cap is
+ *   too small: HPEZ_ENOSPC).  HPEZ_ECORRUPT for a malformed container.  Reads
+ *   the header with one synchronisation; a coded container synchronises again
+ *   to check the decoding, a stored one returns after enqueueing its copy. */
+int hpez_lossless_bound(uint64_t n, uint64_t* out_bytes);
+int hpez_lossless_encode(hpez_ctx* ctx, const void* d_in, uint64_t n, void* d_out,
+                         uint64_t out_cap, uint64_t* out_size, hipStream_t stream);
+int hpez_lossless_decode(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void* d_out,
+                         uint64_t out_cap, uint64_t* out_size, hipStream_t stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): hpez_decompress on GPU
  * `device` with no allocation.  The device workspace is the library's static

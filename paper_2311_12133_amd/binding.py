@@ -87,7 +87,8 @@ EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_
            "hpez_compress_batch", "hpez_decompress_batch", "hpez_tune_batch",
            "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc",
            "hpez_quality_eval", "hpez_fit_eb", "hpez_autotune", "hpez_decompress_plan",
-           "hpez_plan_launch", "hpez_plan_status", "hpez_plan_destroy"]
+           "hpez_plan_launch", "hpez_plan_status", "hpez_plan_destroy", "hpez_lossless_bound",
+           "hpez_lossless_encode", "hpez_lossless_decode"]
 
 _lib = None
 _lock = threading.Lock()
@@ -138,6 +139,9 @@ def lib():
             L.hpez_plan_status.argtypes = [vp, vp, P(C.c_int)]
             L.hpez_plan_destroy.argtypes = [vp]
             L.hpez_plan_destroy.restype = None
+            L.hpez_lossless_bound.argtypes = [u64, P(u64)]
+            L.hpez_lossless_encode.argtypes = [vp, vp, u64, vp, u64, P(u64), vp]
+            L.hpez_lossless_decode.argtypes = [vp, vp, u64, vp, u64, P(u64), vp]
             _lib = L
     return _lib
 
@@ -561,6 +565,41 @@ def decompress_batch(streams, stream=None, outs=None, context=None, rcs_out=None
         rcs_out[:] = [int(rcs[i]) for i in range(n)]
     _check(rc, "hpez_decompress_batch")
     return res
+
+
+def lossless_encode(data, stream=None, context=None):
+    """hpez_lossless_encode: the lossless-stage container (uint8 device tensor)
+    of the bytes of the contiguous device tensor `data` (Sec. 4 step 5)."""
+    torch = _torch()
+    b = data.reshape(-1).view(torch.uint8)
+    n = b.numel()
+    cap = C.c_uint64()
+    _check(lib().hpez_lossless_bound(n, C.byref(cap)), "hpez_lossless_bound")
+    out = torch.empty(cap.value, dtype=torch.uint8, device=b.device)
+    size = C.c_uint64()
+    _check(lib().hpez_lossless_encode(_cx(context, b.device.index or 0),
+                                      C.c_void_p(b.data_ptr() if n else 0), n,
+                                      C.c_void_p(out.data_ptr()), cap.value, C.byref(size),
+                                      _stream_ptr(stream)), "hpez_lossless_encode")
+    return out[: size.value]
+
+
+def lossless_decode(z, out=None, stream=None, context=None):
+    """hpez_lossless_decode: the bytes (uint8 device tensor) a container holds."""
+    torch = _torch()
+    size = C.c_uint64()
+    dev = z.device.index or 0
+    if out is None:
+        hdr = z[:48].cpu().numpy().tobytes()
+        if len(hdr) < 48:
+            raise HpezError(-4, "hpez_lossless_decode", "short container")
+        n = struct.unpack_from("<Q", hdr, 8)[0]
+        out = torch.empty(n, dtype=torch.uint8, device=z.device)
+    _check(lib().hpez_lossless_decode(_cx(context, dev), C.c_void_p(z.data_ptr()), z.numel(),
+                                      C.c_void_p(out.data_ptr() if out.numel() else 0),
+                                      out.numel(), C.byref(size), _stream_ptr(stream)),
+           "hpez_lossless_decode")
+    return out[: size.value]
 
 
 class DecompressPlan:
