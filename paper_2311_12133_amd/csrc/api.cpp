@@ -58,6 +58,14 @@ struct hpez_ctx {
   // events that fork it from and join it back to that stream
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // streams for the independent per-field work of a batch (ctx_fork_pool),
+  // with the events that fork them from and join them back to the caller's
+  // stream; made on first use
+  static constexpr int kPool = 4;
+  hipStream_t pool[kPool] = {};
+  hipEvent_t pool_join[kPool] = {};
+  hipEvent_t pool_fork = nullptr;
+  int pool_n = 0;
   // recording a decompression plan (hpez_decompress_plan): the call repeats
   // the device work of the eager call just made on this context, whose host
   // results (headers, code lengths, block configurations) are still in its
@@ -1410,6 +1418,52 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
                         (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), st);
 }
 
+// Up to k streams (at most hpez_ctx::kPool) for independent per-field work,
+// each made to wait for the work queued so far on st; returns how many (0:
+// keep everything on st, as fixed contexts do), or -1 when a HIP call failed.
+// ctx_join_pool makes st wait for all of them.  A recording uses the streams
+// the eager call made (the fork and join events make them branches of the
+// recorded graph) and creates none.
+int ctx_fork_pool(hpez_ctx* c, hipStream_t st, int k, hipStream_t* out)
+{
+  if ((c->fixed && !c->capture) || k < 2) return 0;
+  if (k > hpez_ctx::kPool) k = hpez_ctx::kPool;
+  while (!c->capture && c->pool_n < k) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      break;
+    }
+    c->pool[c->pool_n] = s;
+    c->pool_join[c->pool_n] = e;
+    c->pool_n++;
+  }
+  if (!c->pool_fork && (c->capture || hipEventCreateWithFlags(&c->pool_fork, hipEventDisableTiming) !=
+                                         hipSuccess)) {
+    c->pool_fork = nullptr;
+    return 0;
+  }
+  if (k > c->pool_n) k = c->pool_n;
+  if (k < 2) return 0;
+  if (hipEventRecord(c->pool_fork, st) != hipSuccess) return -1;
+  for (int i = 0; i < k; i++) {
+    if (hipStreamWaitEvent(c->pool[i], c->pool_fork, 0) != hipSuccess) return -1;
+    out[i] = c->pool[i];
+  }
+  return k;
+}
+
+int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k)
+{
+  for (int i = 0; i < k; i++)
+    if (hipEventRecord(c->pool_join[i], c->pool[i]) != hipSuccess ||
+        hipStreamWaitEvent(st, c->pool_join[i], 0) != hipSuccess)
+      return HPEZ_EDEVICE;
+  return HPEZ_OK;
+}
+
 // Compress jobs [0, n) of one dtype.  A job's own failure (non-finite input,
 // ENOSPC, ...) stays in its rc; device errors end the whole call.
 template <typename T>
@@ -1434,17 +1488,28 @@ int compress_jobs(hpez_ctx* ctx, std::vector<CJob<T>>& jobs, hipStream_t st)
   Bump pb{ctx->pinned};
   for (auto& J : jobs) c_take(J, bw, pb);
 
-  for (auto& J : jobs) {
-    rc = c_minmax(ctx, J, st);
+  // the per-field phases of several fields on the context's stream pool (the
+  // fields' launches are small and independent)
+  hipStream_t ps[hpez_ctx::kPool];
+  int np = ctx_fork_pool(ctx, st, n, ps);
+  if (np < 0) return HPEZ_EDEVICE;
+  auto js = [&](int i) { return np ? ps[i % np] : st; };
+  for (int i = 0; i < n; i++) {
+    rc = c_minmax(ctx, jobs[i], js(i));
     if (rc) return rc;
   }
+  if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
   HIPCK(hipStreamSynchronize(st));
   std::vector<BlockJobHost<T>> bj;
-  for (auto& J : jobs) {
-    rc = c_predict(ctx, J, st);
+  np = ctx_fork_pool(ctx, st, n, ps);
+  if (np < 0) return HPEZ_EDEVICE;
+  for (int i = 0; i < n; i++) {
+    CJob<T>& J = jobs[i];
+    rc = c_predict(ctx, J, js(i));
     if (rc) return rc;
     if (!J.rc && !J.kind && J.fast) bj.push_back(c_block_job(J));
   }
+  if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
   rc = block_phase<T>(ctx, bj, 0, bw, st);
   if (rc) return rc;
   for (auto& J : jobs)
@@ -1460,11 +1525,15 @@ int compress_jobs(hpez_ctx* ctx, std::vector<CJob<T>>& jobs, hipStream_t st)
   host_parallel(n, [&](int i) {
     if (!jobs[i].rc && !jobs[i].kind) c_codebook(jobs[i]);
   });
-  for (auto& J : jobs) {
+  np = ctx_fork_pool(ctx, st, n, ps);
+  if (np < 0) return HPEZ_EDEVICE;
+  for (int i = 0; i < n; i++) {
+    CJob<T>& J = jobs[i];
     if (J.rc || J.kind) continue;
-    rc = c_encode(ctx, J, st);
+    rc = c_encode(ctx, J, js(i));
     if (rc) return rc;
   }
+  if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
   HIPCK(hipStreamSynchronize(st));
   prof_collect(ctx);
   // the Lorenzo alternative (Sec. 6.5) runs per field after the rest
@@ -1802,12 +1871,21 @@ int decompress_jobs(hpez_ctx* ctx, std::vector<DJob<T>>& jobs, hipStream_t st)
     if (jobs[i].Lo.predictor != 2) d_tables(jobs[i]);
   });
   std::vector<BlockJobHost<T>> bj;
+  // decode, verbatim values, anchors and the levels above the blocks of
+  // several fields on the context's stream pool
+  int nd = 0;
+  for (auto& J : jobs) nd += !J.rc && J.Lo.predictor != 2;
+  hipStream_t ps[hpez_ctx::kPool];
+  const int np = ctx_fork_pool(ctx, st, nd, ps);
+  if (np < 0) return HPEZ_EDEVICE;
+  int k = 0;
   for (auto& J : jobs) {
     if (J.rc || J.Lo.predictor == 2) continue;
-    rc = d_decode(ctx, J, st);
+    rc = d_decode(ctx, J, np ? ps[k++ % np] : st);
     if (rc) return rc;
     if (!J.rc && J.fast && J.Lo.predictor == HPEZ_INTERP) bj.push_back(d_block_job(J));
   }
+  if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
   rc = block_phase<T>(ctx, bj, 1, bw, st);
   if (rc) return rc;
   if (ctx->capture) return HPEZ_OK;  // checks: decompress_group
@@ -1948,6 +2026,11 @@ void hpez_ctx_destroy(hpez_ctx* ctx)
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  for (int i = 0; i < ctx->pool_n; i++) {
+    (void)hipEventDestroy(ctx->pool_join[i]);
+    (void)hipStreamDestroy(ctx->pool[i]);
+  }
+  if (ctx->pool_fork) (void)hipEventDestroy(ctx->pool_fork);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -2486,8 +2569,9 @@ int hpez_decompress_plan(hpez_ctx* ctx, int n, const void* const* d_in, const ui
     plan_free(p);
     return rc;
   }
-  // the recording: same jobs, same buffers; no growth (fixed) and no second
-  // stream, so every node lands on the recorded stream
+  // the recording: same jobs, same buffers; no growth (fixed), no block-phase
+  // second stream; per-field work of several streams forks onto the pool
+  // streams the eager call made, which the recording joins as branches
   if (hipStreamBeginCapture(p->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     plan_free(p);
     return HPEZ_EDEVICE;
