@@ -1418,52 +1418,6 @@ int c_encode(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
                         (uint32_t*)(out + Lo.off_payload), (uint16_t*)(out + Lo.off_chunks), st);
 }
 
-// Up to k streams (at most hpez_ctx::kPool) for independent per-field work,
-// each made to wait for the work queued so far on st; returns how many (0:
-// keep everything on st, as fixed contexts do), or -1 when a HIP call failed.
-// ctx_join_pool makes st wait for all of them.  A recording uses the streams
-// the eager call made (the fork and join events make them branches of the
-// recorded graph) and creates none.
-int ctx_fork_pool(hpez_ctx* c, hipStream_t st, int k, hipStream_t* out)
-{
-  if ((c->fixed && !c->capture) || k < 2) return 0;
-  if (k > hpez_ctx::kPool) k = hpez_ctx::kPool;
-  while (!c->capture && c->pool_n < k) {
-    hipStream_t s = nullptr;
-    hipEvent_t e = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      (void)hipStreamDestroy(s);
-      break;
-    }
-    c->pool[c->pool_n] = s;
-    c->pool_join[c->pool_n] = e;
-    c->pool_n++;
-  }
-  if (!c->pool_fork && (c->capture || hipEventCreateWithFlags(&c->pool_fork, hipEventDisableTiming) !=
-                                         hipSuccess)) {
-    c->pool_fork = nullptr;
-    return 0;
-  }
-  if (k > c->pool_n) k = c->pool_n;
-  if (k < 2) return 0;
-  if (hipEventRecord(c->pool_fork, st) != hipSuccess) return -1;
-  for (int i = 0; i < k; i++) {
-    if (hipStreamWaitEvent(c->pool[i], c->pool_fork, 0) != hipSuccess) return -1;
-    out[i] = c->pool[i];
-  }
-  return k;
-}
-
-int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k)
-{
-  for (int i = 0; i < k; i++)
-    if (hipEventRecord(c->pool_join[i], c->pool[i]) != hipSuccess ||
-        hipStreamWaitEvent(st, c->pool_join[i], 0) != hipSuccess)
-      return HPEZ_EDEVICE;
-  return HPEZ_OK;
-}
-
 // Compress jobs [0, n) of one dtype.  A job's own failure (non-finite input,
 // ENOSPC, ...) stays in its rc; device errors end the whole call.
 template <typename T>
@@ -2399,6 +2353,52 @@ int ctx_join(hpez_ctx* c, hipStream_t st)
   if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
       hipStreamWaitEvent(st, c->ev_join, 0) != hipSuccess)
     return HPEZ_EDEVICE;
+  return HPEZ_OK;
+}
+
+// Up to k streams (at most hpez_ctx::kPool) for independent per-field work,
+// each made to wait for the work queued so far on st; returns how many (0:
+// keep everything on st, as fixed contexts do), or -1 when a HIP call failed.
+// ctx_join_pool makes st wait for all of them.  A recording uses the streams
+// the eager call made (the fork and join events make them branches of the
+// recorded graph) and creates none.
+int ctx_fork_pool(hpez_ctx* c, hipStream_t st, int k, hipStream_t* out)
+{
+  if ((c->fixed && !c->capture) || k < 2) return 0;
+  if (k > hpez_ctx::kPool) k = hpez_ctx::kPool;
+  while (!c->capture && c->pool_n < k) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      break;
+    }
+    c->pool[c->pool_n] = s;
+    c->pool_join[c->pool_n] = e;
+    c->pool_n++;
+  }
+  if (!c->pool_fork && (c->capture || hipEventCreateWithFlags(&c->pool_fork, hipEventDisableTiming) !=
+                                         hipSuccess)) {
+    c->pool_fork = nullptr;
+    return 0;
+  }
+  if (k > c->pool_n) k = c->pool_n;
+  if (k < 2) return 0;
+  if (hipEventRecord(c->pool_fork, st) != hipSuccess) return -1;
+  for (int i = 0; i < k; i++) {
+    if (hipStreamWaitEvent(c->pool[i], c->pool_fork, 0) != hipSuccess) return -1;
+    out[i] = c->pool[i];
+  }
+  return k;
+}
+
+int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k)
+{
+  for (int i = 0; i < k; i++)
+    if (hipEventRecord(c->pool_join[i], c->pool[i]) != hipSuccess ||
+        hipStreamWaitEvent(st, c->pool_join[i], 0) != hipSuccess)
+      return HPEZ_EDEVICE;
   return HPEZ_OK;
 }
 

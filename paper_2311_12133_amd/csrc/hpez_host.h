@@ -127,6 +127,12 @@ int ctx_device(hpez_ctx* c);
 // (nullptr on failure: the caller then queues everything on st).  ctx_join
 // makes st wait for what was queued on the second stream since.
 hipStream_t ctx_fork(hpez_ctx* c, hipStream_t st);
+// A pool of up to four context streams for independent per-field work of a
+// batch: ctx_fork_pool makes up to k of them wait for the work queued so far on
+// st and returns how many (0: keep everything on st), or -1 when a HIP call
+// failed; ctx_join_pool makes st wait for those k.
+int ctx_fork_pool(hpez_ctx* c, hipStream_t st, int k, hipStream_t* out);
+int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k);
 int ctx_join(hpez_ctx* c, hipStream_t st);
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
 void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);

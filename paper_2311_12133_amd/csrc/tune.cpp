@@ -1006,14 +1006,24 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     }
   } join{ctx, st};
 
-  for (auto& J : jobs)
-    if ((rc = t_minmax(J, st))) return rc;
+  // per-field launches of several fields on the context's stream pool
+  const int nj = (int)jobs.size();
+  hipStream_t ps[4];
+  int np = ctx_fork_pool(ctx, st, nj, ps);
+  if (np < 0) return HPEZ_EDEVICE;
+  auto js = [&](int i) { return np ? ps[i % np] : st; };
+  for (int i = 0; i < nj; i++)
+    if ((rc = t_minmax(jobs[i], js(i)))) return rc;
+  if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
   TCK(hipStreamSynchronize(st));
   bool any_stats = false;
-  for (auto& J : jobs) {
-    if ((rc = t_stats(ctx, J, st))) return rc;
-    any_stats |= J.stats;
+  np = ctx_fork_pool(ctx, st, nj, ps);
+  if (np < 0) return HPEZ_EDEVICE;
+  for (int i = 0; i < nj; i++) {
+    if ((rc = t_stats(ctx, jobs[i], js(i)))) return rc;
+    any_stats |= jobs[i].stats;
   }
+  if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
   if (any_stats) TCK(hipStreamSynchronize(st));
   {
     TrialBatch<T> tb;
@@ -1040,14 +1050,18 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
         }
       ctx_span_end(ctx, evb, "tune_block_trials", bb, side);
     }
-    for (auto& J : jobs)
-      if ((rc = t_lorenzo(J, st))) return rc;
+    // the fields' Lorenzo trials on the pool, beside the fused trial launch
+    np = ctx_fork_pool(ctx, st, nj, ps);
+    if (np < 0) return HPEZ_EDEVICE;
+    for (int i = 0; i < nj; i++)
+      if ((rc = t_lorenzo(jobs[i], js(i)))) return rc;
     hipEvent_t ev = ctx_span_begin(ctx, st);
     if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
     uint64_t bytes = 0;
     for (auto& J : jobs)
       if (!J.done) bytes += (uint64_t)J.nvar * J.gb.size() * J.gcap * sizeof(T);
     ctx_span_end(ctx, ev, "tune_trials", bytes, st);
+    if (np && (rc = ctx_join_pool(ctx, st, np))) return rc;
     for (auto& J : jobs)
       if ((rc = t_global_copy(J, st))) return rc;
   }
