@@ -254,6 +254,14 @@ struct TJob {
   bool lorenzo = false, lorenzo_trial = false;
   bool blocks = false;
   bool spec = false;  // block trials already queued on the second stream
+  // the block trials' boxes, built and uploaded for this freeze decision
+  // (bb_frozen) ahead of the trials: box side, anchor level and largest box
+  bool bb_ready = false;
+  int bb_frozen = -2;
+  hipStream_t bb_stream = nullptr;  // the stream their upload is ordered on
+  int64_t bb_side = 0;
+  int bb_al = 0;
+  uint64_t bb_cap = 0;
   double HL = 0.0;     // entropy of the Lorenzo trial's codes
   TrialArgs ba;
   // Sec. 6.4: the (alpha, beta) trials (when tune_ab)
@@ -745,20 +753,20 @@ int t_hist_copy(TJob<T>& J, hipStream_t st)
 // upload on st, arguments in J.ba.  Nothing is queued when `need_tables` is set
 // and the trials would not run from the job tables (they would use the shared
 // scratch area); *ok tells which.
+// The block-wise trials' boxes (Sec. 6.6): the centred sub-block of every
+// block, staged in h_bscore (free until the trials' scores come back) and
+// uploaded on st.  They depend on the freeze decision only (through the number
+// of active dims), so the batch builds them while the (alpha, beta) trials run.
 template <typename T>
-int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool need_tables,
-                 bool* ok)
+int t_block_boxes(TJob<T>& J, int frozen, hipStream_t st)
 {
-  const hpez_field_desc* d = J.d;
-  const hpez_tune_opts* o = J.o;
-  *ok = false;
   const Geom& g = J.g;
-  const Geom gf = make_geom(d, frozen);
+  const Geom gf = make_geom(J.d, frozen);
   const int64_t B = J.B;
   int64_t nb[4];
   for (int k = 0; k < 4; k++) nb[k] = (g.n[k] + B - 1) / B;
   const int nact = n_active(gf);
-  const int64_t side = sub_side(B, o->sub_rate, nact > 0 ? nact : 1);
+  const int64_t side = sub_side(B, J.o->sub_rate, nact > 0 ? nact : 1);
   int64_t As = 1;
   int al = 0;
   while (As * 2 <= side - 1) {
@@ -768,9 +776,9 @@ int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool
   static_assert(sizeof(unsigned long long) * kNCand >= sizeof(TrialBox), "box staging");
   TrialBox* bx = reinterpret_cast<TrialBox*>(J.h_bscore);
   uint64_t cap = 0;
+  // blocks in row-major order: the block index advanced like an odometer
+  int64_t b[4] = {0, 0, 0, 0};
   for (int64_t bi = 0; bi < J.nbt; bi++) {
-    int64_t b[4];
-    unravel(bi, nb, b);
     uint64_t pts = 1;
     for (int k = 0; k < 4; k++) {
       const int64_t ext = g.n[k] - b[k] * B < B ? g.n[k] - b[k] * B : B;
@@ -779,7 +787,35 @@ int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool
       pts *= (uint64_t)bx[bi].m[k];
     }
     cap = std::max(cap, pts);
+    for (int k = 3; k >= 0; k--) {
+      if (++b[k] < nb[k]) break;
+      b[k] = 0;
+    }
   }
+  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, (size_t)J.nbt * sizeof(TrialBox), hipMemcpyHostToDevice,
+                     st));
+  J.bb_ready = true;
+  J.bb_frozen = frozen;
+  J.bb_stream = st;
+  J.bb_side = side;
+  J.bb_al = al;
+  J.bb_cap = cap;
+  return HPEZ_OK;
+}
+
+template <typename T>
+int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool need_tables,
+                 bool* ok)
+{
+  *ok = false;
+  if (!(J.bb_ready && J.bb_frozen == frozen && J.bb_stream == st)) {
+    const int rc = t_block_boxes(J, frozen, st);
+    if (rc) return rc;
+  }
+  const Geom& g = J.g;
+  const int64_t side = J.bb_side;
+  const int al = J.bb_al;
+  const uint64_t cap = J.bb_cap;
   if ((size_t)J.nbt * kNCand * cap * sizeof(T) > J.scratch_bytes && cap * sizeof(T) > kTrialLdsBytes)
     return need_tables ? HPEZ_OK : HPEZ_ENOMEM;
   TrialArgs& a = J.ba;
@@ -795,8 +831,6 @@ int t_block_args(TJob<T>& J, int frozen, TrialBatch<T>& tb, hipStream_t st, bool
   fill_levels(a, J.e, &J.Q, J.d->dtype);
   for (int i = 0; i < kNCand; i++) a.cand[i] = J.cand[i];
   if (need_tables && !trial_box_ok<T>(a, false)) return HPEZ_OK;
-  TCK(hipMemcpyAsync(J.d_bb, J.h_bscore, (size_t)J.nbt * sizeof(TrialBox), hipMemcpyHostToDevice,
-                     st));
   t_add<T>(tb, a, J.d_bb, (uint32_t)J.nbt, kNCand, J.X, (T*)J.scratch, J.wq, J.bscore, nullptr);
   *ok = true;
   return HPEZ_OK;
@@ -1098,6 +1132,9 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     ctx_span_end(ctx, ev, "tune_ab_trials", bytes, st);
     for (auto& J : jobs)
       if ((rc = t_ab_copy(J, st))) return rc;
+    // the block trials' boxes on the host while the (alpha, beta) trials run
+    for (auto& J : jobs)
+      if (!J.done && J.blocks && !J.spec && (rc = t_block_boxes(J, J.frozen, st))) return rc;
     TCK(hipStreamSynchronize(st));
     for (auto& J : jobs)
       if ((rc = t_ab_decide(J, st))) return rc;
