@@ -2120,6 +2120,7 @@ int hpez_compress_batch(hpez_ctx* ctx, int n, const hpez_field_desc* d,
   if (!rc && !f64.empty())
     rc = compress_group<double>(ctx, n, d, in.data(), c, d_out, out_cap, out_sizes, f64, &first,
                                 stream);
+  if (rc) ctx_drain(ctx, stream);
   return rc ? rc : first;
 }
 
@@ -2222,7 +2223,10 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
   }
   rc = decompress_group<float>(ctx, j32, i32, rcs, stream);
   if (!rc) rc = decompress_group<double>(ctx, j64, i64, rcs, stream);
-  if (rc) return rc;
+  if (rc) {
+    ctx_drain(ctx, stream);
+    return rc;
+  }
   for (size_t k = 0; k < j64.size(); k++) {
     if (!int_out[k] || rcs[i64[k]]) continue;
     HIPCK(launch_f64_to_int(j64[k].out, j64[k].d.dtype, int_out[k], points_of(&j64[k].d), stream));
@@ -2400,6 +2404,19 @@ int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k)
         hipStreamWaitEvent(st, c->pool_join[i], 0) != hipSuccess)
       return HPEZ_EDEVICE;
   return HPEZ_OK;
+}
+
+// After a call fails between its launches (a call-level error other than a
+// failed HIP call): wait for the work it queued on the caller's stream, the
+// second stream and the pool, so that no copy from the context's host staging
+// is still pending when the next call rewrites that staging.  Not while
+// recording a plan (nothing runs then).  Errors of the waits are ignored.
+void ctx_drain(hpez_ctx* c, hipStream_t st)
+{
+  if (c->capture) return;
+  (void)hipStreamSynchronize(st);
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  for (int i = 0; i < c->pool_n; i++) (void)hipStreamSynchronize(c->pool[i]);
 }
 
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st)

@@ -133,6 +133,9 @@ hipStream_t ctx_fork(hpez_ctx* c, hipStream_t st);
 // failed; ctx_join_pool makes st wait for those k.
 int ctx_fork_pool(hpez_ctx* c, hipStream_t st, int k, hipStream_t* out);
 int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k);
+// after a call-level failure between launches: wait for the call's queued
+// work on st, the second stream and the pool (staging may then be reused)
+void ctx_drain(hpez_ctx* c, hipStream_t st);
 int ctx_join(hpez_ctx* c, hipStream_t st);
 hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
 void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);

@@ -246,7 +246,10 @@ int hpez_lossless_encode(hpez_ctx* ctx, const void* d_in, uint64_t n, void* d_ou
   rc = encode_payload(ctx, tok, h.ntok, kLLChunk, h_len, h_cw, smin, smax, dlen, dcw, hist,
                       kTokSyms, flags, ticket, h_tab, reinterpret_cast<uint32_t*>(out + h.off_payload),
                       reinterpret_cast<uint16_t*>(out + h.off_chunks), st);
-  if (rc) return rc;
+  if (rc) {
+    ctx_drain(ctx, st);
+    return rc;
+  }
   LLCK(hipStreamSynchronize(st));
   ctx_prof_collect(ctx);
   *out_size = h.total;

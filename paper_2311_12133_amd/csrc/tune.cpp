@@ -1254,7 +1254,10 @@ extern "C" int hpez_tune_batch(hpez_ctx* ctx, int n, const hpez_field_desc* desc
   if (!rc && !f64.empty())
     rc = tune_group<double>(ctx, desc, in.data(), opts, out_cfg, h_block_cfg, block_cfg_cap, f64,
                             rcs, stream);
-  if (rc) return rc;
+  if (rc) {
+    ctx_drain(ctx, stream);
+    return rc;
+  }
   for (int i = 0; i < n; i++)
     if (rcs[i]) return rcs[i];
   return HPEZ_OK;
