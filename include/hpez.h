@@ -475,6 +475,11 @@ typedef struct {
 } hpez_kernel_stat;
 
 int hpez_profile_enable(hpez_ctx* ctx, int on);
+/* While profiling: record only the spans of the group named `group` (one of
+ * the names hpez_profile_read reports), so that timing one group costs two
+ * events per launch instead of two per group; NULL or "" records all groups
+ * again.  The setting stays until changed. */
+int hpez_profile_only(hpez_ctx* ctx, const char* group);
 /* Copy up to cap entries into out; *n receives the number of entries. */
 int hpez_profile_read(hpez_ctx* ctx, hpez_kernel_stat* out, int cap, int* n);
 

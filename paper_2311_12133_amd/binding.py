@@ -88,7 +88,7 @@ EXPORTS = ["hpez_strerror", "hpez_ctx_create", "hpez_ctx_destroy", "hpez_config_
            "hpez_ctx_trim", "hpez_ctx_set_limit", "hpez_ctx_workspace", "hpez_decompress_noalloc",
            "hpez_quality_eval", "hpez_fit_eb", "hpez_autotune", "hpez_decompress_plan",
            "hpez_plan_launch", "hpez_plan_status", "hpez_plan_destroy", "hpez_lossless_bound",
-           "hpez_lossless_encode", "hpez_lossless_decode"]
+           "hpez_lossless_encode", "hpez_lossless_decode", "hpez_profile_only"]
 
 _lib = None
 _lock = threading.Lock()
@@ -139,6 +139,7 @@ def lib():
             L.hpez_plan_status.argtypes = [vp, vp, P(C.c_int)]
             L.hpez_plan_destroy.argtypes = [vp]
             L.hpez_plan_destroy.restype = None
+            L.hpez_profile_only.argtypes = [vp, C.c_char_p]
             L.hpez_lossless_bound.argtypes = [u64, P(u64)]
             L.hpez_lossless_encode.argtypes = [vp, vp, u64, vp, u64, P(u64), vp]
             L.hpez_lossless_decode.argtypes = [vp, vp, u64, vp, u64, P(u64), vp]
@@ -739,6 +740,12 @@ def autotune(x, cfg: dict, tune_opts: dict | None = None, stream=None, context=N
 def profile_enable(device: int = 0, on: bool = True):
     """Start (clearing totals) or stop per-kernel event timing in the library."""
     _check(lib().hpez_profile_enable(ctx(device), int(on)), "hpez_profile_enable")
+
+
+def profile_only(group: str | None, device: int = 0):
+    """Record only one kernel group's spans while profiling (None: all)."""
+    _check(lib().hpez_profile_only(ctx(device), group.encode() if group else None),
+           "hpez_profile_only")
 
 
 def profile_read(device: int = 0):

@@ -14,6 +14,7 @@
 #include <atomic>
 #include <map>
 #include <set>
+#include <string>
 #include <new>
 #include <thread>
 #include <vector>
@@ -81,6 +82,7 @@ struct hpez_ctx {
   std::vector<Check> checks;
   // kernel timing (hpez_profile_enable)
   bool prof = false;
+  std::string prof_only;  // record only the spans of this group (empty: all)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<ProfRec> pend;
@@ -109,7 +111,7 @@ struct Span {
   Span(hpez_ctx* c_, const char* name_, uint64_t bytes_, hipStream_t st_)
       : c(c_), st(st_), name(name_), bytes(bytes_)
   {
-    if (c && c->prof) {
+    if (c && c->prof && (c->prof_only.empty() || c->prof_only == name_)) {
       a = c->take_event();
       if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
     }
@@ -583,7 +585,7 @@ int encode_payload(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint32_t chu
   }
   if (hipMemsetAsync(d_flags, 0, nch * 8, st) != hipSuccess) return HPEZ_EDEVICE;
   if (hipMemsetAsync(d_ticket, 0, 4, st) != hipSuccess) return HPEZ_EDEVICE;
-  hipEvent_t ev = ctx_span_begin(ctx, st);
+  hipEvent_t ev = ctx_span_begin(ctx, st, "encode");
   if (launch_encode1(a, code, payload, chunks, d_flags, d_ticket, d_tab, dlen, dcw, st) !=
       hipSuccess)
     return HPEZ_EDEVICE;
@@ -612,7 +614,7 @@ int encode_payload_packed(hpez_ctx* ctx, const uint16_t* code, uint64_t N, uint3
   a.lds_tab = a.ntab <= kEncTab;
   a.packed_ok = true;
   a.ltab = d_ltab;
-  hipEvent_t ev = ctx_span_begin(ctx, st);
+  hipEvent_t ev = ctx_span_begin(ctx, st, "encode");
   if (launch_encode1(a, code, payload, chunks, d_flags, d_ticket, d_tab, nullptr, nullptr, st) !=
       hipSuccess)
     return HPEZ_EDEVICE;
@@ -2247,6 +2249,13 @@ int hpez_profile_enable(hpez_ctx* ctx, int on)
   return HPEZ_OK;
 }
 
+int hpez_profile_only(hpez_ctx* ctx, const char* group)
+{
+  if (!ctx) return HPEZ_EINVAL;
+  ctx->prof_only = group ? group : "";
+  return HPEZ_OK;
+}
+
 int hpez_profile_read(hpez_ctx* ctx, hpez_kernel_stat* out, int cap, int* n)
 {
   if (!ctx || !n || (cap > 0 && !out)) return HPEZ_EINVAL;
@@ -2419,9 +2428,10 @@ void ctx_drain(hpez_ctx* c, hipStream_t st)
   for (int i = 0; i < c->pool_n; i++) (void)hipStreamSynchronize(c->pool[i]);
 }
 
-hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st)
+hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st, const char* name)
 {
   if (!c->prof) return nullptr;
+  if (!c->prof_only.empty() && (!name || c->prof_only != name)) return nullptr;
   hipEvent_t a = c->take_event();
   if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
   return a;

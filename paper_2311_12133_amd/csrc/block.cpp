@@ -490,7 +490,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   uint8_t* dt = (uint8_t*)d_tables;
   BCK(hipMemcpyAsync(dt, h_tables, bytes, hipMemcpyHostToDevice, st));
 
-  hipEvent_t ev = ctx_span_begin(ctx, st);
+  hipEvent_t ev = ctx_span_begin(ctx, st, mode == 0 ? "faces_predict" : "faces_reconstruct");
   BCK(launch_planes<T>((const PlaneJob<T>*)(dt + off_planes), (const uint64_t*)(dt + off_pwg), np,
                        plane_wgs, plane_lds, mode, st));
   // The coarse levels of every block on the block lattices need only the
@@ -499,7 +499,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   // beside the face steps.
   hipStream_t cs = launches.empty() ? st : ctx_fork(ctx, st);
   if (!cs) cs = st;
-  hipEvent_t evc = ctx_span_begin(ctx, cs);
+  hipEvent_t evc = ctx_span_begin(ctx, cs, mode == 0 ? "coarse_predict" : "coarse_reconstruct");
   BCK(launch_coarse_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
                             n, total_blocks, mode, cs));
   ctx_span_end(ctx, evc, mode == 0 ? "coarse_predict" : "coarse_reconstruct",
@@ -519,7 +519,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
           hipSuccess ||
       n_cu <= 0)
     return HPEZ_EDEVICE;
-  ev = ctx_span_begin(ctx, st);
+  ev = ctx_span_begin(ctx, st, mode == 0 ? "blocks_predict" : "blocks_reconstruct");
   BCK(launch_block_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
                            n, total_blocks, lds, n_cu, mode, st));
   ctx_span_end(ctx, ev, mode == 0 ? "blocks_predict" : "blocks_reconstruct",

@@ -137,7 +137,10 @@ int ctx_join_pool(hpez_ctx* c, hipStream_t st, int k);
 // work on st, the second stream and the pool (staging may then be reused)
 void ctx_drain(hpez_ctx* c, hipStream_t st);
 int ctx_join(hpez_ctx* c, hipStream_t st);
-hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st);
+// name: the group the span will close with (spans of other groups are not
+// recorded while hpez_profile_only names one; a span opened without a name
+// is then not recorded either)
+hipEvent_t ctx_span_begin(hpez_ctx* c, hipStream_t st, const char* name = nullptr);
 void ctx_span_end(hpez_ctx* c, hipEvent_t a, const char* name, uint64_t bytes, hipStream_t st);
 void ctx_prof_collect(hpez_ctx* c);
 // hpez_decompress on the device's fixed context: workspace `ws` (ws_bytes,

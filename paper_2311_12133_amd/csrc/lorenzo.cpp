@@ -74,7 +74,7 @@ int lorenzo_compress(hpez_ctx* ctx, const hpez_field_desc* d, const T* X, const 
   a.chunk = c->chunk;
   LCK(hipMemsetAsync(pcount, 0, (nch + 1) * 4, st));
   LCK(hipMemsetAsync(bad, 0, 4, st));
-  hipEvent_t ev = ctx_span_begin(ctx, st);
+  hipEvent_t ev = ctx_span_begin(ctx, st, "lorenzo_codes");
   LCK(launch_lorenzo_codes<T>(X, g, N, a, code, pcount, bad, st));
   ctx_span_end(ctx, ev, "lorenzo_codes", N * (s + 2), st);
   LCK(hipMemsetAsync(hist, 0, (size_t)nsym * 4, st));

@@ -183,7 +183,7 @@ int hpez_lossless_encode(hpez_ctx* ctx, const void* d_in, uint64_t n, void* d_ou
   uint32_t* ticket = bw.take<uint32_t>(4);
   // tokens and their histogram
   {
-    hipEvent_t ev = ctx_span_begin(ctx, st);
+    hipEvent_t ev = ctx_span_begin(ctx, st, "lossless_tokens");
     LLCK(hipMemsetAsync(hist, 0, kTokSyms * 4, st));
     LLCK(launch_ll_count(in, n, cnt, st));
     LLCK(launch_scan_u32_to_u64(cnt, ntile, toff_tile, &scal[0], tmp1, st));
@@ -339,7 +339,7 @@ int hpez_lossless_decode(hpez_ctx* ctx, const void* d_in, uint64_t in_size, void
   LLCK(hipMemsetAsync(dtabs + fo, 0, nfl * 8, st));
   int* status = reinterpret_cast<int*>(dtabs);
   {
-    hipEvent_t ev = ctx_span_begin(ctx, st);
+    hipEvent_t ev = ctx_span_begin(ctx, st, "lossless_expand");
     LLCK(launch_decode2(da, reinterpret_cast<const uint32_t*>(in + h.off_payload),
                         reinterpret_cast<const uint16_t*>(in + h.off_chunks),
                         reinterpret_cast<uint64_t*>(dtabs + fo), reinterpret_cast<uint32_t*>(dtabs + 16),

@@ -514,7 +514,7 @@ int t_stats(hpez_ctx* ctx, TJob<T>& J, hipStream_t st)
   }
   J.count = (int64_t)lat.total;
   J.stats = true;
-  hipEvent_t ev = ctx_span_begin(ctx, st);
+  hipEvent_t ev = ctx_span_begin(ctx, st, "tune_stats");
   TCK(launch_stats<T>(J.X, gs, lat, 256.0 / J.e, J.sums, st));
   ctx_span_end(ctx, ev, "tune_stats", lat.total * (1 + 4 * n_active(gs)) * sizeof(T), st);
   TCK(hipMemcpyAsync(J.h_sums, J.sums, 12 * 8 * kStatSlots, hipMemcpyDeviceToHost, st));
@@ -1073,7 +1073,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
       sb.ctx = ctx;
       for (auto& J : jobs)
         if ((rc = t_blocks_ahead(J, sb, side))) return rc;
-      hipEvent_t evb = ctx_span_begin(ctx, side);
+      hipEvent_t evb = ctx_span_begin(ctx, side, "tune_block_trials");
       if ((rc = t_launch(ctx, sb, false, d_tab2, tab_cap, side, h_tab2))) return rc;
       uint64_t bb = 0;
       for (auto& J : jobs)
@@ -1089,7 +1089,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     if (np < 0) return HPEZ_EDEVICE;
     for (int i = 0; i < nj; i++)
       if ((rc = t_lorenzo(jobs[i], js(i)))) return rc;
-    hipEvent_t ev = ctx_span_begin(ctx, st);
+    hipEvent_t ev = ctx_span_begin(ctx, st, "tune_trials");
     if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
     uint64_t bytes = 0;
     for (auto& J : jobs)
@@ -1124,7 +1124,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     tb.ctx = ctx;
     for (auto& J : jobs)
       if ((rc = t_ab(J, tb, st))) return rc;
-    hipEvent_t ev = ctx_span_begin(ctx, st);
+    hipEvent_t ev = ctx_span_begin(ctx, st, "tune_ab_trials");
     if ((rc = t_launch(ctx, tb, true, d_tab, tab_cap, st))) return rc;
     uint64_t bytes = 0;
     for (auto& J : jobs)
@@ -1144,7 +1144,7 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
     tb.ctx = ctx;
     for (auto& J : jobs)
       if ((rc = t_blocks(J, tb, st))) return rc;
-    hipEvent_t ev = ctx_span_begin(ctx, st);
+    hipEvent_t ev = ctx_span_begin(ctx, st, "tune_block_trials");
     if ((rc = t_launch(ctx, tb, false, d_tab, tab_cap, st))) return rc;
     uint64_t bytes = 0;
     for (auto& J : jobs)
