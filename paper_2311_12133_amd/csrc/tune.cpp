@@ -1084,8 +1084,11 @@ int tune_jobs(hpez_ctx* ctx, std::vector<TJob<T>>& jobs, hipStream_t st)
         }
       ctx_span_end(ctx, evb, "tune_block_trials", bb, side);
     }
-    // the fields' Lorenzo trials on the pool, beside the fused trial launch
-    np = ctx_fork_pool(ctx, st, nj, ps);
+    // the fields' Lorenzo trials on the pool (one stream even for one field),
+    // beside the fused trial launch
+    bool any_lz = false;
+    for (auto& J : jobs) any_lz |= !J.done && J.lorenzo_trial;
+    np = any_lz ? ctx_fork_pool(ctx, st, nj > 2 ? nj : 2, ps) : 0;
     if (np < 0) return HPEZ_EDEVICE;
     for (int i = 0; i < nj; i++)
       if ((rc = t_lorenzo(jobs[i], js(i)))) return rc;
