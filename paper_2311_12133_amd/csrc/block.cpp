@@ -89,7 +89,7 @@ size_t block_tables_bound(int n)
   const size_t ent = kMaxFaceSteps * (size_t)n;
   return al(ent * sizeof(FaceEntry<T>)) + al((ent + kMaxFaceSteps) * 8) +
          al(n * sizeof(BlockJobDev<T>)) + al((n + 1) * 8) + 256 +
-         al(3 * (size_t)n * sizeof(PlaneJob<T>)) + al((3 * (size_t)n + 1) * 8);
+         al(3 * (size_t)n * sizeof(PlaneJob<T>)) + al((3 * (size_t)n + 1) * 8) + al((n + 1) * 8);
 }
 
 template <typename T>
@@ -348,7 +348,8 @@ size_t block_jobs_table_bytes(const BlockJobHost<T>* jobs, int n)
   }
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   return al(ent * sizeof(FaceEntry<T>)) + al((ent + slots) * 8) + al(n * sizeof(BlockJobDev<T>)) +
-         al((n + 1) * 8) + 256 + al(3 * (size_t)n * sizeof(PlaneJob<T>)) + al((3 * (size_t)n + 1) * 8);
+         al((n + 1) * 8) + 256 + al(3 * (size_t)n * sizeof(PlaneJob<T>)) + al((3 * (size_t)n + 1) * 8) +
+         al((n + 1) * 8);
 }
 
 template <typename T>
@@ -386,7 +387,8 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   const size_t off_begin = off_jobs + al(n * sizeof(BlockJobDev<T>));
   const size_t off_planes = off_begin + al((n + 1) * 8);
   const size_t off_pwg = off_planes + al(3 * (size_t)n * sizeof(PlaneJob<T>));
-  const size_t bytes = off_pwg + al((3 * (size_t)n + 1) * 8);
+  const size_t off_begin2 = off_pwg + al((3 * (size_t)n + 1) * 8);
+  const size_t bytes = off_begin2 + al((n + 1) * 8);
   std::memset(h_tables, 0, bytes);
   FaceEntry<T>* he = (FaceEntry<T>*)h_tables;
   uint64_t* hw = (uint64_t*)(h_tables + off_wg);
@@ -447,24 +449,42 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   BlockJobDev<T>* hj = (BlockJobDev<T>*)(h_tables + off_jobs);
   uint64_t* hb = (uint64_t*)(h_tables + off_begin);
   uint64_t total_blocks = 0, npts = 0;
-  size_t lds = 0;
-  for (int j = 0; j < n; j++) {
-    hj[j].a = jobs[j].ba;
-    hj[j].f = jobs[j].f;
-    hj[j].X = jobs[j].X;
-    hj[j].code = jobs[j].code;
-    hj[j].bcfg = jobs[j].d_bcfg;
-    hj[j].hist = jobs[j].hist;
-    hj[j].out = jobs[j].out;
-    hj[j].cval = jobs[j].cval;
-    hj[j].ccode = jobs[j].ccode;
-    hj[j].block_begin = total_blocks;
-    hb[j] = total_blocks;
+  // jobs whose box has at most two active dims (33 x 33 points or fewer) take
+  // the 256-lane block kernel, several work-groups per CU; the table lists
+  // them after the others, and begin2 rebases their block indices
+  const size_t small_box = (((size_t)33 * 33 * sizeof(T) + 15) & ~(size_t)15) + (size_t)kBlockHistWin * 4;
+  auto is_small = [&](const BlockJobHost<T>& J) {
+    const int na = (int)J.g.act[0] + (int)J.g.act[1] + (int)J.g.act[2] + (int)J.g.act[3];
+    return na <= 2 && J.lds <= small_box;
+  };
+  std::vector<int> perm;
+  for (int pass = 0; pass < 2; pass++)
+    for (int j = 0; j < n; j++)
+      if (is_small(jobs[j]) == (pass == 1)) perm.push_back(j);
+  int nbig = 0;
+  while (nbig < n && !is_small(jobs[perm[nbig]])) nbig++;
+  size_t lds = 0, lds_small = 0;
+  for (int k = 0; k < n; k++) {
+    const int j = perm[k];
+    size_t& L = k < nbig ? lds : lds_small;
+    L = std::max(L, jobs[j].lds);
+    hj[k].a = jobs[j].ba;
+    hj[k].f = jobs[j].f;
+    hj[k].X = jobs[j].X;
+    hj[k].code = jobs[j].code;
+    hj[k].bcfg = jobs[j].d_bcfg;
+    hj[k].hist = jobs[j].hist;
+    hj[k].out = jobs[j].out;
+    hj[k].cval = jobs[j].cval;
+    hj[k].ccode = jobs[j].ccode;
+    hj[k].block_begin = total_blocks;
+    hb[k] = total_blocks;
     total_blocks += jobs[j].nblocks;
     npts += jobs[j].npts;
-    lds = std::max(lds, jobs[j].lds);
   }
   hb[n] = total_blocks;
+  uint64_t* hb2 = (uint64_t*)(h_tables + off_begin2);
+  for (int k = nbig; k <= n; k++) hb2[k - nbig] = hb[k] - hb[nbig];
   PlaneJob<T>* hp = (PlaneJob<T>*)(h_tables + off_planes);
   uint64_t* hpw = (uint64_t*)(h_tables + off_pwg);
   int np = 0;
@@ -520,8 +540,13 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
       n_cu <= 0)
     return HPEZ_EDEVICE;
   ev = ctx_span_begin(ctx, st, mode == 0 ? "blocks_predict" : "blocks_reconstruct");
-  BCK(launch_block_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
-                           n, total_blocks, lds, n_cu, mode, st));
+  if (nbig)
+    BCK(launch_block_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
+                             nbig, hb[nbig], lds, n_cu, mode, false, st));
+  if (nbig < n)
+    BCK(launch_block_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs) + nbig,
+                             (const uint64_t*)(dt + off_begin2), n - nbig, hb[n] - hb[nbig],
+                             lds_small, n_cu, mode, true, st));
   ctx_span_end(ctx, ev, mode == 0 ? "blocks_predict" : "blocks_reconstruct",
                npts * (sizeof(T) + 2), st);
   return HPEZ_OK;

@@ -7,6 +7,7 @@ namespace hpez {
 
 constexpr int kBlockHistWin = 4096;  // LDS histogram window of the block kernel
 constexpr int kBlockThreads = 1024;  // work-group size of the block kernel
+constexpr int kSmallBoxThreads = 256;  // ... for boxes of at most two active dims
 // coarse levels on the block lattice: levels above kCoarseL (strides >= 4);
 // a block's lattice has at most 9 x 9 x 32 cells (one inactive dim of 32)
 constexpr int kCoarseL = 2;
@@ -118,11 +119,12 @@ hipError_t launch_face_steps(const FaceEntry<T>* d_tab, const uint64_t* d_wg_beg
                              uint64_t total_wg, bool narrow, int mode, uint32_t threads,
                              hipStream_t st);
 // the block phase of jobs [0, n): d_begin[j] = first global block index of job j
-// (d_begin[n] = total); lds = largest box of the jobs
+// (d_begin[n] = total); lds = largest box of the jobs; small: every job's box
+// has at most two active dims (the 256-lane kernel, four work-groups per CU)
 template <typename T>
 hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
-                             uint64_t total_blocks, size_t lds, int n_cu,
-                             int mode, hipStream_t st);
+                             uint64_t total_blocks, size_t lds, int n_cu, int mode, bool small,
+                             hipStream_t st);
 
 // the coarse levels of every block of jobs [0, n) on the block lattices
 template <typename T>

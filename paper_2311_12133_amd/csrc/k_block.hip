@@ -940,15 +940,20 @@ __device__ __forceinline__ void hist_flush(const uint32_t* lh, const BlockJobDev
 // Persistent work-groups (one per CU): blocks are taken from a counter; for
 // float boxes the next block's loads are issued before the current block's
 // levels, so they complete while it computes.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobDev<T>* __restrict__ jobs,
+// NT = kBlockThreads: any box, one work-group per CU.  NT = kSmallBoxThreads:
+// only boxes of at most two active dims and 33 x 33 points or fewer (so at
+// most 33 x 33 load items and 2 x 32 face codes), several work-groups per CU;
+// the full-block schedule (three active dims) is not compiled in.
+template <typename T, int MODE, int NT>
+__global__ void __launch_bounds__(NT, NT == kBlockThreads ? 1 : 4) block_kernel(const BlockJobDev<T>* __restrict__ jobs,
                                                               const uint64_t* __restrict__ begin,
                                                               int njobs,
                                                               uint32_t lh_off)
 {
-  constexpr int NT = kBlockThreads;
+  constexpr bool FULL = NT == kBlockThreads;  // full blocks (33^3 slot layout) possible
   constexpr bool PREF = sizeof(T) == 4;
-  constexpr int UP = PREF ? (33 * 33 * 9 + NT - 1) / NT : 1;  // items per lane held across a block
+  // items per lane held across a block
+  constexpr int UP = PREF ? ((FULL ? 33 * 33 * 9 : 33 * 33) + NT - 1) / NT : 1;
   extern __shared__ unsigned char lds_raw[];
   T* L = reinterpret_cast<T*>(lds_raw);
   const uint64_t nbt = begin[njobs];
@@ -973,7 +978,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     Box bx;
     block_geometry(J.a.g, (int64_t)(gbi - begin[j]), J.a.nb, bk, bx);
     const BoxItems its = box_items(bx);
-    const bool fast1 = full_block(bk, bx, J.a.cand[gmem(J.bcfg)[gbi - begin[j]]]);
+    const bool fast1 = FULL && full_block(bk, bx, J.a.cand[gmem(J.bcfg)[gbi - begin[j]]]);
 #pragma unroll
     for (int u = 0; u < UP; u++)
       pv[u] = load_item<T, MODE>(J.f, gmem(J.X), J.a.g.st[0], J.a.g.st[1], bk, bx, its,
@@ -1003,7 +1008,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     Block3 bk;
     Box bx;
     block_geometry(a.g, (int64_t)bi, a.nb, bk, bx);
-    const bool fast = PREF && full_block(bk, bx, a.cand[gmem(J.bcfg)[bi]]);
+    const bool fast = FULL && PREF && full_block(bk, bx, a.cand[gmem(J.bcfg)[bi]]);
     // stream position of the brick's first point (all earlier bricks are full
     // along the dims before the last partial one)
     const uint64_t brick_base = brick_start(a.g, bk);
@@ -1060,7 +1065,9 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     // compress: the codes of the brick's own faces (c_d = 0 on an active dim)
     // from the face code arrays; loaded now, stored and counted after the
     // levels, so the loads complete while the block computes
-    constexpr int FC = MODE == 0 ? 3 : 1;  // face codes per lane (3 x 32 x 32 <= 3 NT)
+    // face codes per lane: 3 x 32 x 32 <= 3 NT for any box; a box of at most two
+    // active dims has at most 2 x 32 face codes (<= NT)
+    constexpr int FC = MODE == 0 ? (FULL ? 3 : 1) : 1;
     uint32_t fcv[FC], fcd[FC];
     bool fok[FC];
     if (MODE == 0) {
@@ -1110,7 +1117,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
       Box bx2;
       block_geometry(J2.a.g, (int64_t)(bn - begin[j2]), J2.a.nb, bk2, bx2);
       const BoxItems its2 = box_items(bx2);
-      const bool fast2 = full_block(bk2, bx2, J2.a.cand[gmem(J2.bcfg)[bn - begin[j2]]]);
+      const bool fast2 = FULL && full_block(bk2, bx2, J2.a.cand[gmem(J2.bcfg)[bn - begin[j2]]]);
 #pragma unroll
       for (int u = 0; u < UP; u++)
         pv[u] = load_item<T, MODE>(J2.f, gmem(J2.X), J2.a.g.st[0], J2.a.g.st[1], bk2, bx2, its2,
@@ -1128,7 +1135,7 @@ __global__ void __launch_bounds__(kBlockThreads, 1) block_kernel(const BlockJobD
     // ---- the levels below B with the block's configuration
     const hpez_interp c = a.cand[gmem(J.bcfg)[bi]];
     uint32_t nR = 0;
-    if constexpr (PREF) {
+    if constexpr (PREF && FULL) {
       if (fast) {
         FBlock<T> fb{L,         code + brick_base, out,       lh,  hist, bk.o0, bk.o1, bk.o2, st0, st1,
                      bx.E0 - 1, bx.E1 - 1,         bx.E2 - 1, a.R, lo,   0.0,   0.0,   0.0,   0u};
@@ -1341,28 +1348,40 @@ size_t block_lds_bytes(const Geom& g)
   return ((pts * sizeof(T) + 15) & ~(size_t)15) + (size_t)kBlockHistWin * 4;
 }
 
+template <typename T, int NT>
+void launch_block_kernel(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n, unsigned grid,
+                         size_t lds, uint32_t lh_off, int mode, hipStream_t st)
+{
+  if (mode == 0) {
+    (void)hipFuncSetAttribute((const void*)block_kernel<T, 0, NT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((block_kernel<T, 0, NT>), dim3(grid), dim3(NT), lds, st, d_jobs, d_begin, n,
+                       lh_off);
+  } else {
+    (void)hipFuncSetAttribute((const void*)block_kernel<T, 1, NT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((block_kernel<T, 1, NT>), dim3(grid), dim3(NT), lds, st, d_jobs, d_begin, n,
+                       lh_off);
+  }
+}
+
 template <typename T>
 hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_begin, int n,
-                             uint64_t total_blocks, size_t lds, int n_cu,
-                             int mode, hipStream_t st)
+                             uint64_t total_blocks, size_t lds, int n_cu, int mode, bool small,
+                             hipStream_t st)
 {
   if (!total_blocks || n <= 0) return hipSuccess;
-  // one work-group per CU (the box takes the CU's LDS), blocks dealt round-robin;
-  // the histogram window takes the last kBlockHistWin words
+  // persistent work-groups, blocks dealt round-robin: one per CU for any box
+  // (the box takes the CU's LDS), four per CU for boxes of at most two active
+  // dims; the histogram window takes the last kBlockHistWin words
   if (lds < (size_t)kBlockHistWin * 4) return hipErrorInvalidValue;
   const uint32_t lh_off = (uint32_t)(lds - (size_t)kBlockHistWin * 4);
-  const unsigned grid = (unsigned)(total_blocks < (uint64_t)n_cu ? total_blocks : (uint64_t)n_cu);
-  if (mode == 0) {
-    (void)hipFuncSetAttribute((const void*)block_kernel<T, 0>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((block_kernel<T, 0>), dim3(grid), dim3(kBlockThreads), lds, st, d_jobs, d_begin,
-                       n, lh_off);
-  } else {
-    (void)hipFuncSetAttribute((const void*)block_kernel<T, 1>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((block_kernel<T, 1>), dim3(grid), dim3(kBlockThreads), lds, st, d_jobs, d_begin,
-                       n, lh_off);
-  }
+  const uint64_t per = small ? 4 * (uint64_t)n_cu : (uint64_t)n_cu;
+  const unsigned grid = (unsigned)(total_blocks < per ? total_blocks : per);
+  if (small)
+    launch_block_kernel<T, kSmallBoxThreads>(d_jobs, d_begin, n, grid, lds, lh_off, mode, st);
+  else
+    launch_block_kernel<T, kBlockThreads>(d_jobs, d_begin, n, grid, lds, lh_off, mode, st);
   return hipGetLastError();
 }
 
@@ -1375,7 +1394,7 @@ hipError_t launch_block_jobs(const BlockJobDev<T>* d_jobs, const uint64_t* d_beg
   template hipError_t launch_coarse_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
                                             int, hipStream_t);                                     \
   template hipError_t launch_block_jobs<T>(const BlockJobDev<T>*, const uint64_t*, int, uint64_t, \
-                                           size_t, int, int, hipStream_t);                        \
+                                           size_t, int, int, bool, hipStream_t);                  \
   template hipError_t launch_face_steps<T>(const FaceEntry<T>*, const uint64_t*, int, uint64_t,   \
                                            bool, int, uint32_t, hipStream_t);                     \
   template hipError_t launch_minmax_faces<T>(const T*, const Geom&, const FaceGeo&, double*, int*, \
