@@ -203,8 +203,12 @@ def test_huffman_long_codes(torch_cuda, nsym, maxlen):
               f"huffman {nsym} Fibonacci symbols ({x.size} points)")
 
 
+# the last four sit at the split between the block kernel's 1024-lane launch
+# (any box) and its 256-lane one (at most two active dims, at most 33 x 33
+# points): a tiny box with three active dims, a thin one with three, and two
+# with one or two active dims
 FAST_SHAPES = [(64, 64, 64), (65, 33, 97), (96, 31, 130), (33, 64, 1), (200, 161), (1, 77, 64),
-               (40, 40, 40)]
+               (40, 40, 40), (10, 12, 9), (3, 50, 40), (17, 1, 33), (1, 1, 3000)]
 
 
 @pytest.mark.parametrize("shape", FAST_SHAPES, ids=["x".join(map(str, s)) for s in FAST_SHAPES])
