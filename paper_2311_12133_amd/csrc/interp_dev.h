@@ -106,8 +106,13 @@ __device__ __forceinline__ int md_colour(const int64_t* x, unsigned odd, int64_t
 template <typename T>
 __device__ __forceinline__ T recon(T p, double qd, double twoe)
 {
-  const double v = (double)p + qd * fabs(twoe);
-  return (T)(twoe < 0 ? rint(v) : v);
+  if constexpr (sizeof(T) == 4) {
+    // float kernels never see an integer field (those run in double): twoe > 0
+    return (T)((double)p + qd * twoe);
+  } else {
+    const double v = (double)p + qd * fabs(twoe);
+    return (T)(twoe < 0 ? rint(v) : v);
+  }
 }
 
 // Linear-scale quantization (Sec. 4, step 3): bins of width 2 e_l, rounding
