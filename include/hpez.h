@@ -269,8 +269,8 @@ int hpez_decompress_batch(hpez_ctx* ctx, int n, const void* const* d_in, const u
  * receives HPEZ_OK or HPEZ_ECORRUPT for stream i, and the first nonzero one
  * is returned.
  *
- * hpez_plan_destroy frees the plan; no replay of it may still be running
- * (synchronise the streams it was launched on first). */
+ * hpez_plan_destroy waits for the last replay launched (an event recorded
+ * after each launch), then frees the plan. */
 typedef struct hpez_plan hpez_plan;
 int hpez_decompress_plan(hpez_ctx* ctx, int n, const void* const* d_in, const uint64_t* in_size,
                          void* const* d_out, const uint64_t* out_cap, int* rcs,

@@ -2491,6 +2491,7 @@ struct hpez_plan {
   int n = 0;
   std::vector<hpez_ctx::Check> checks;  // idx: the stream's index in the plan
   uint8_t* h_res = nullptr;             // pinned: status words and counts read back
+  hipEvent_t done = nullptr;            // recorded after every replay (destroy waits on it)
 };
 
 namespace {
@@ -2502,6 +2503,7 @@ void plan_free(hpez_plan* p)
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cs) (void)hipStreamDestroy(p->cs);
   if (p->h_res) (void)hipHostFree(p->h_res);
+  if (p->done) (void)hipEventDestroy(p->done);
   for (hpez_ctx* c : p->pc)
     if (c) hpez_ctx_destroy(c);
   delete p;
@@ -2631,6 +2633,11 @@ int hpez_decompress_plan(hpez_ctx* ctx, int n, const void* const* d_in, const ui
     plan_free(p);
     return HPEZ_ENOMEM;
   }
+  if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+    p->done = nullptr;
+    plan_free(p);
+    return HPEZ_EDEVICE;
+  }
   *out_plan = p;
   return HPEZ_OK;
 }
@@ -2639,7 +2646,10 @@ int hpez_plan_launch(hpez_plan* plan, hipStream_t stream)
 {
   if (!plan || !plan->exec) return HPEZ_EINVAL;
   DevScope ds(plan_device(plan));
-  return hipGraphLaunch(plan->exec, stream) == hipSuccess ? HPEZ_OK : HPEZ_EDEVICE;
+  if (hipGraphLaunch(plan->exec, stream) != hipSuccess ||
+      hipEventRecord(plan->done, stream) != hipSuccess)
+    return HPEZ_EDEVICE;
+  return HPEZ_OK;
 }
 
 int hpez_plan_status(hpez_plan* plan, hipStream_t stream, int* rcs)
@@ -2669,6 +2679,9 @@ void hpez_plan_destroy(hpez_plan* plan)
 {
   if (!plan) return;
   DevScope ds(plan_device(plan));
+  // the last replay launched (on whatever stream) ends before the plan's
+  // memory is released
+  if (plan->done) (void)hipEventSynchronize(plan->done);
   plan_free(plan);
 }
 

@@ -157,3 +157,20 @@ def test_plan_rejects_small_output(torch_cuda, streams):
     with pytest.raises(binding.HpezError) as ei:
         binding.DecompressPlan([s], outs=[small])
     assert ei.value.code == -5
+
+
+def test_plan_destroy_waits_for_replay(torch_cuda, streams):
+    """Destroying a plan right after launching a replay (no synchronisation in
+    between) waits for that replay before its memory is released."""
+    from paper_2311_12133_amd import binding
+    torch = torch_cuda
+    s, ref, lab = streams[0]
+    print(f"[case] destroy after launch {lab}", flush=True)
+    plan = binding.DecompressPlan([s])
+    out = plan.outs[0]
+    out.zero_()
+    torch.cuda.synchronize()
+    plan.launch()
+    plan.close()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
