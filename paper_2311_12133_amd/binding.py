@@ -246,8 +246,12 @@ def _interp_bytes(src) -> bytes:
     if len(order) != 4:
         order = list(order)
         order = order + [j for j in range(4) if j not in order]
-    return bytes((int(src["kind"]), int(src.get("md", 0)), int(src.get("same_level", 0)),
-                  *(int(v) for v in order), 0))
+    try:  # integer-valued entries (the usual case): no conversions
+        return bytes((src["kind"], src.get("md", 0), src.get("same_level", 0), order[0], order[1],
+                      order[2], order[3], 0))
+    except TypeError:
+        return bytes((int(src["kind"]), int(src.get("md", 0)), int(src.get("same_level", 0)),
+                      *(int(v) for v in order), 0))
 
 
 def _fill_interp(dst: Interp, src):
