@@ -942,6 +942,13 @@ int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, co
       bsa.twoe = twoe;
       bsa.R = c->radius;
       for (uint32_t i = 0; i < c->n_cand; i++) bsa.cand[i] = c->cand[i];
+      // level points per block, about 4096 of them per work-group
+      uint64_t ppb = 1;
+      for (int dd = 0; dd < 4; dd++) {
+        const int64_t ext = B < g.n[dd] ? B : g.n[dd];
+        ppb *= (uint64_t)(g.act[dd] ? ext / s : ext);
+      }
+      bsa.pieces = (uint32_t)(ppb / 4096 < 1 ? 1 : ppb / 4096 > 256 ? 256 : ppb / 4096);
       for (int t = 0; t < 2 * nact; t++) {
         bsa.t = t;
         HIPCK(launch_block_step<T>(bsa, X, W, code, d_bcfg, d_wq, mode, st));

@@ -57,6 +57,7 @@ struct BlockStepArgs {
   int64_t s, B;
   int64_t nb[4];
   int32_t t;          // step index processed by this launch
+  uint32_t pieces;    // work-groups per block
   double el, inv2e, twoe;
   uint32_t R;
   hpez_interp cand[16];

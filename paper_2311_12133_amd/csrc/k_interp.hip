@@ -72,30 +72,46 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
   }
 }
 
+// v[d] for a run-time d in [0, 4) without indexing a private array (which
+// would place the array in scratch memory)
+__device__ __forceinline__ int64_t pick4(const int64_t* v, int d)
+{
+  return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : v[3];
+}
+
 // Step index of a level point under a configuration: 1D style, 2 * pass + half
 // (the pass is the last dimension in pass order whose coordinate is an odd
 // multiple of s; the half is 1 for coordinates at 3s mod 4s with same-level
 // cubic); multi-dimensional, 2 * (number of odd coordinates - 1) + half (the
-// half is the checkerboard colour with same-level cubic).
+// half is the checkerboard colour with same-level cubic).  The stride s = 2^ls
+// is a power of two and coordinates are nonnegative, so x / s is x >> ls.
 __device__ __forceinline__ int step_of(const hpez_interp& c, const int32_t* act, const int64_t* x,
-                                       int64_t s, unsigned* odd_out, int* pdim_out, int* half_out)
+                                       int ls, unsigned* odd_out, int* pdim_out, int* half_out)
 {
   unsigned odd = 0;
   for (int d = 0; d < 4; d++)
-    if (act[d] && (x[d] / s) & 1) odd |= 1u << d;
+    if (act[d] && (x[d] >> ls) & 1) odd |= 1u << d;
   *odd_out = odd;
   if (c.md) {
     *pdim_out = -1;
-    const int half = (c.kind != 0 && c.same_level) ? md_colour(x, odd, s) : 0;
+    int half = 0;
+    if (c.kind != 0 && c.same_level) {
+      int64_t t = 0;
+      for (int d = 0; d < 4; d++)
+        if (odd >> d & 1u) t += x[d] >> (ls + 1);
+      half = (int)(t & 1);
+    }
     *half_out = half;
     return 2 * (__popc(odd) - 1) + half;
   }
   int pass = -1, pd = -1, k = 0;
-  bool seen[4] = {false, false, false, false};
+  unsigned seen = 0, actm = 0;
+  for (int d = 0; d < 4; d++)
+    if (act[d]) actm |= 1u << d;
   for (int i = 0; i < 4; i++) {
     const int d = c.order[i];
-    if (d < 4 && act[d] && !seen[d]) {
-      seen[d] = true;
+    if (d < 4 && (actm >> d & 1u) && !(seen >> d & 1u)) {
+      seen |= 1u << d;
       if (odd >> d & 1u) {
         pass = k;
         pd = d;
@@ -104,11 +120,27 @@ __device__ __forceinline__ int step_of(const hpez_interp& c, const int32_t* act,
     }
   }
   *pdim_out = pd;
-  const int half = (c.kind != 0 && c.same_level && ((x[pd] / s) & 3) == 3) ? 1 : 0;
+  const int half = (c.kind != 0 && c.same_level && ((pick4(x, pd) >> ls) & 3) == 3) ? 1 : 0;
   *half_out = half;
   return 2 * pass + half;
 }
 
+// Per-dim coordinate classes of a block's points at one level: every j in
+// [1, J] (any), odd j, even j; x = lo + j s.  Frozen and size-1 dims take
+// every coordinate lo + j, j in [0, J).
+enum : int { kJAny = 0, kJOdd = 1, kJEven = 2 };
+
+// Interior points of every block at one level, one step index of each block's
+// own configuration.  A step's points inside one block form at most six
+// product sets of per-dim progressions: a 1D pass has its pass dim odd, the
+// dims before it in pass order anything and the dims after it even; a
+// multi-dimensional sub-step with c odd dims has one set per choice of c odd
+// active dims.  One work-group takes one of `pieces` parts of one block: its
+// first lane lays the block's sets out in LDS, the lanes walk their points,
+// and the step test (which also splits same-level halves and checkerboard
+// colours) keeps exactly the step's points.  A block's extent along an
+// active dim is below B, so its lower corner is an even multiple of s and the
+// parity of x / s is the parity of j.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const T* __restrict__ X,
                                                          T* __restrict__ W,
@@ -116,46 +148,146 @@ __global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const 
                                                          const uint8_t* __restrict__ bcfg,
                                                          const double* __restrict__ wq)
 {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.lat.total;
-       k += stride) {
-    int64_t x[4];
-    lattice_point(a.lat, k, x);
-    bool face = false, level = false;
-    for (int d = 0; d < 4; d++) {
-      if (!a.g.act[d]) continue;
-      if (x[d] % a.B == 0) face = true;
-      if ((x[d] / a.s) & 1) level = true;
-    }
-    if (face || !level) continue;
-    int64_t b[4], lo[4], hi[4];
-    for (int d = 0; d < 4; d++) {
-      b[d] = x[d] / a.B;
-      lo[d] = b[d] * a.B;
-      hi[d] = lo[d] + a.B < a.g.n[d] - 1 ? lo[d] + a.B : a.g.n[d] - 1;
-    }
-    const int64_t bi = ((b[0] * a.nb[1] + b[1]) * a.nb[2] + b[2]) * a.nb[3] + b[3];
-    const hpez_interp c = a.cand[bcfg[bi]];
-    unsigned odd;
-    int pd, half;
-    if (step_of(c, a.g.act, x, a.s, &odd, &pd, &half) != a.t) continue;
-    const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
-    T p;
-    if (!c.md) {
-      p = spline<T, T>(W, idx, a.s * a.g.st[pd], x[pd], a.s, lo[pd], hi[pd], c.kind, half);
-    } else {
-      bool first = true;
-      T acc = (T)0;
-      for (int d = 0; d < 4; d++) {
-        if (!(odd >> d & 1u)) continue;
-        const T pdv = spline<T, T>(W, idx, a.s * a.g.st[d], x[d], a.s, lo[d], hi[d], c.kind, half);
-        const T term = (T)wq[(c.kind * 16 + odd) * 4 + d] * pdv;
-        acc = first ? term : acc + term;
-        first = false;
+  __shared__ uint32_t s_first[6][4], s_step[6][4], s_cnt[6][4];
+  __shared__ uint64_t s_start[7];
+  __shared__ int s_nbox;
+  const int ls = __builtin_ctzll((unsigned long long)a.s);
+  const uint64_t nbt = (uint64_t)a.nb[0] * a.nb[1] * a.nb[2] * a.nb[3];
+  const uint32_t P = a.pieces;
+  for (uint64_t u = blockIdx.x; u < nbt * P; u += gridDim.x) {
+    const uint64_t bi = u / P;
+    const uint32_t piece = (uint32_t)(u - bi * P);
+    int64_t lo[4], hi[4], J[4];
+    {
+      uint64_t r = bi;
+      for (int d = 3; d >= 0; d--) {
+        const uint64_t q = r / (uint64_t)a.nb[d];
+        lo[d] = (int64_t)(r - q * (uint64_t)a.nb[d]) * a.B;
+        r = q;
       }
-      p = acc;
     }
-    finish<T, MODE>(p, idx, brick_pos(a.g.n, x), X, W, code, a.el, a.inv2e, a.twoe, a.R);
+    for (int d = 0; d < 4; d++) {
+      hi[d] = lo[d] + a.B < a.g.n[d] - 1 ? lo[d] + a.B : a.g.n[d] - 1;
+      const int64_t top = lo[d] + a.B - 1 < a.g.n[d] - 1 ? lo[d] + a.B - 1 : a.g.n[d] - 1;
+      J[d] = a.g.act[d] ? (top - lo[d]) >> ls : top - lo[d] + 1;
+    }
+    const hpez_interp c = a.cand[bcfg[bi]];
+    if (threadIdx.x == 0) {
+      // progression of dim d in set bx for class cl; returns its length
+      auto put = [&](int bx, int d, int cl) -> uint64_t {
+        uint32_t f = 1, st = 1, n = (uint32_t)J[d];
+        if (!a.g.act[d]) {
+          f = 0;
+        } else if (cl == kJOdd) {
+          st = 2;
+          n = (uint32_t)((J[d] + 1) >> 1);
+        } else if (cl == kJEven) {
+          f = 2;
+          st = 2;
+          n = (uint32_t)(J[d] >> 1);
+        }
+        s_first[bx][d] = f;
+        s_step[bx][d] = st;
+        s_cnt[bx][d] = n;
+        return n;
+      };
+      int nbox = 0;
+      uint64_t run = 0;
+      const bool halves = c.kind != 0 && c.same_level;
+      if (!(a.t & 1) || halves) {
+        if (c.md) {
+          const int want = (a.t >> 1) + 1;
+          for (unsigned odd = 1; odd < 16 && nbox < 6; odd++) {
+            bool ok = (int)__popc(odd) == want;
+            for (int d = 0; d < 4; d++)
+              if ((odd >> d & 1u) && !a.g.act[d]) ok = false;
+            if (!ok) continue;
+            s_start[nbox] = run;
+            uint64_t prod = 1;
+            for (int d = 0; d < 4; d++) prod *= put(nbox, d, (odd >> d & 1u) ? kJOdd : kJEven);
+            run += prod;
+            nbox++;
+          }
+        } else {
+          // pass position of each dim, 4 bits per dim (15: not in the pass order)
+          unsigned pos = 0xffffu, actm = 0;
+          int np = 0;
+          for (int d = 0; d < 4; d++)
+            if (a.g.act[d]) actm |= 1u << d;
+          for (int i = 0; i < 4; i++) {
+            const int d = c.order[i];
+            if (d < 4 && (actm >> d & 1u) && (pos >> (4 * d) & 15u) == 15u)
+              pos = (pos & ~(15u << (4 * d))) | ((unsigned)np++ << (4 * d));
+          }
+          const int k = a.t >> 1;
+          if (k < np) {
+            s_start[0] = 0;
+            uint64_t prod = 1;
+            for (int d = 0; d < 4; d++) {
+              const unsigned pd = pos >> (4 * d) & 15u;
+              prod *= put(0, d, pd == (unsigned)k ? kJOdd
+                                : pd != 15u && pd > (unsigned)k ? kJEven
+                                                                : kJAny);
+            }
+            run = prod;
+            nbox = 1;
+          }
+        }
+      }
+      s_start[nbox] = run;
+      s_nbox = nbox;
+    }
+    __syncthreads();
+    const int nbox = s_nbox;
+    const uint64_t total = s_start[nbox];
+    const bool narrow = total <= 0xffffffffull;
+    for (uint64_t k = (uint64_t)piece * blockDim.x + threadIdx.x; k < total;
+         k += (uint64_t)P * blockDim.x) {
+      int bx = 0;
+      while (bx + 1 < nbox && k >= s_start[bx + 1]) bx++;
+      int64_t x[4];
+      if (narrow) {
+        uint32_t r = (uint32_t)(k - s_start[bx]);
+        for (int d = 3; d >= 0; d--) {
+          const uint32_t n = s_cnt[bx][d];
+          const uint32_t q = r / n;
+          const int64_t j = (int64_t)s_first[bx][d] + (int64_t)s_step[bx][d] * (r - q * n);
+          x[d] = lo[d] + (a.g.act[d] ? j << ls : j);
+          r = q;
+        }
+      } else {
+        uint64_t r = k - s_start[bx];
+        for (int d = 3; d >= 0; d--) {
+          const uint64_t n = s_cnt[bx][d];
+          const uint64_t q = r / n;
+          const int64_t j = (int64_t)s_first[bx][d] + (int64_t)s_step[bx][d] * (int64_t)(r - q * n);
+          x[d] = lo[d] + (a.g.act[d] ? j << ls : j);
+          r = q;
+        }
+      }
+      unsigned odd;
+      int pd, half;
+      if (step_of(c, a.g.act, x, ls, &odd, &pd, &half) != a.t) continue;
+      const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
+      T p;
+      if (!c.md) {
+        p = spline<T, T>(W, idx, a.s * pick4(a.g.st, pd), pick4(x, pd), a.s, pick4(lo, pd),
+                         pick4(hi, pd), c.kind, half);
+      } else {
+        bool first = true;
+        T acc = (T)0;
+        for (int d = 0; d < 4; d++) {
+          if (!(odd >> d & 1u)) continue;
+          const T pdv = spline<T, T>(W, idx, a.s * a.g.st[d], x[d], a.s, lo[d], hi[d], c.kind, half);
+          const T term = (T)wq[(c.kind * 16 + odd) * 4 + d] * pdv;
+          acc = first ? term : acc + term;
+          first = false;
+        }
+        p = acc;
+      }
+      finish<T, MODE>(p, idx, brick_pos(a.g.n, x), X, W, code, a.el, a.inv2e, a.twoe, a.R);
+    }
+    __syncthreads();
   }
 }
 
@@ -208,13 +340,15 @@ hipError_t launch_block_step(const BlockStepArgs& a, const T* X, T* W, uint16_t*
                              const uint8_t* d_block_cfg, const double* d_wq, int mode,
                              hipStream_t st)
 {
-  if (a.lat.total == 0) return hipSuccess;
+  if (a.lat.total == 0 || a.pieces == 0) return hipSuccess;
+  const uint64_t units = (uint64_t)a.nb[0] * a.nb[1] * a.nb[2] * a.nb[3] * a.pieces;
+  const unsigned grid = (unsigned)(units < (1u << 20) ? units : (1u << 20));
   if (mode == 0)
-    hipLaunchKernelGGL((block_step_kernel<T, 0>), dim3(grid_for(a.lat.total)), dim3(256), 0, st,
-                       a, X, W, code, d_block_cfg, d_wq);
+    hipLaunchKernelGGL((block_step_kernel<T, 0>), dim3(grid), dim3(256), 0, st, a, X, W, code,
+                       d_block_cfg, d_wq);
   else
-    hipLaunchKernelGGL((block_step_kernel<T, 1>), dim3(grid_for(a.lat.total)), dim3(256), 0, st,
-                       a, X, W, code, d_block_cfg, d_wq);
+    hipLaunchKernelGGL((block_step_kernel<T, 1>), dim3(grid), dim3(256), 0, st, a, X, W, code,
+                       d_block_cfg, d_wq);
   return hipGetLastError();
 }
 
