@@ -47,6 +47,12 @@ struct StepArgs {
   double el, inv2e, twoe;
   uint32_t R;
   int32_t mdhalf;     // multi-dimensional same-level: 0 all points, 1 + c only colour c
+  // block faces (filter): the lattice points whose coordinate along face
+  // dim fdim[f] is a multiple of B, f < nface, filled in by the launcher
+  int32_t nface;
+  int32_t fdim[4];
+  Lattice flat[4];
+  uint64_t fstart[5];
 };
 
 // Interior points of every block at one level, one step index of each block's

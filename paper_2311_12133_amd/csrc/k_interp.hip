@@ -40,15 +40,20 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
                                                    T* __restrict__ W, uint16_t* __restrict__ code)
 {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.lat.total;
-       k += stride) {
+  const uint64_t total = a.filter ? a.fstart[a.nface] : a.lat.total;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
     int64_t x[4];
-    lattice_point(a.lat, k, x);
     if (a.filter) {
-      bool face = false;
+      // a point on several faces is taken by its first face dim only
+      int f = 0;
+      while (f + 1 < a.nface && k >= a.fstart[f + 1]) f++;
+      lattice_point(a.flat[f], k - a.fstart[f], x);
+      bool earlier = false;
       for (int d = 0; d < 4; d++)
-        if (a.g.act[d] && x[d] % a.B == 0) face = true;
-      if (!face) continue;
+        if (d < a.fdim[f] && a.g.act[d] && (x[d] & (a.B - 1)) == 0) earlier = true;
+      if (earlier) continue;
+    } else {
+      lattice_point(a.lat, k, x);
     }
     if (a.md && a.mdhalf && md_colour(x, a.odd, a.s) != a.mdhalf - 1) continue;
     const int64_t idx = x[0] * a.g.st[0] + x[1] * a.g.st[1] + x[2] * a.g.st[2] + x[3];
@@ -321,17 +326,50 @@ static unsigned grid_for(uint64_t total)
   return (unsigned)b;
 }
 
+// The points of lattice L whose coordinate along d is a multiple of B (a
+// power of two): a sub-lattice along d, or none.
+static bool face_lattice(const Lattice& L, int d, int64_t B, Lattice* out)
+{
+  const uint64_t cnt = L.cnt[d];
+  uint64_t k0 = 0;
+  while (k0 < cnt && k0 < (uint64_t)B && (L.first[d] + L.step[d] * (int64_t)k0) % B != 0) k0++;
+  if (k0 >= cnt || k0 >= (uint64_t)B) return false;
+  uint64_t dk = 1;
+  while ((L.step[d] * (int64_t)dk) % B != 0) dk <<= 1;
+  *out = L;
+  out->first[d] = L.first[d] + L.step[d] * (int64_t)k0;
+  out->step[d] = L.step[d] * (int64_t)dk;
+  out->cnt[d] = (uint32_t)((cnt - 1 - k0) / dk + 1);
+  out->total = 1;
+  for (int e = 0; e < 4; e++) out->total *= out->cnt[e];
+  return true;
+}
+
 template <typename T>
-hipError_t launch_step(const StepArgs& a, const T* X, T* W, uint16_t* code, int mode,
+hipError_t launch_step(const StepArgs& a0, const T* X, T* W, uint16_t* code, int mode,
                        hipStream_t st)
 {
-  if (a.lat.total == 0) return hipSuccess;
+  if (a0.lat.total == 0) return hipSuccess;
+  StepArgs a = a0;
+  uint64_t total = a.lat.total;
+  if (a.filter) {
+    a.nface = 0;
+    a.fstart[0] = 0;
+    for (int d = 0; d < 4; d++) {
+      if (!a.g.act[d] || !face_lattice(a.lat, d, a.B, &a.flat[a.nface])) continue;
+      a.fdim[a.nface] = d;
+      a.fstart[a.nface + 1] = a.fstart[a.nface] + a.flat[a.nface].total;
+      a.nface++;
+    }
+    total = a.fstart[a.nface];
+    if (total == 0) return hipSuccess;
+  }
   if (mode == 0)
-    hipLaunchKernelGGL((step_kernel<T, 0>), dim3(grid_for(a.lat.total)), dim3(256), 0, st, a, X,
-                       W, code);
+    hipLaunchKernelGGL((step_kernel<T, 0>), dim3(grid_for(total)), dim3(256), 0, st, a, X, W,
+                       code);
   else
-    hipLaunchKernelGGL((step_kernel<T, 1>), dim3(grid_for(a.lat.total)), dim3(256), 0, st, a, X,
-                       W, code);
+    hipLaunchKernelGGL((step_kernel<T, 1>), dim3(grid_for(total)), dim3(256), 0, st, a, X, W,
+                       code);
   return hipGetLastError();
 }
 
