@@ -828,14 +828,33 @@ uint64_t grid_points(const Geom& g, int64_t s)
   return p;
 }
 
+// Odd block steps (second halves of same-level passes) have points only in
+// blocks whose candidate uses same-level cubic: false when no block's does
+// (h_bcfg: host copy of the block choices, or null to judge by the candidates).
+bool block_halves_used(const hpez_config* c, const Geom& g, int64_t B, const uint8_t* h_bcfg)
+{
+  bool cand_h[256] = {};
+  bool any = false;
+  for (uint32_t i = 0; i < c->n_cand; i++)
+    any |= cand_h[i] = c->cand[i].kind != 0 && c->cand[i].same_level;
+  if (!any || !h_bcfg) return any;
+  uint64_t nb = 1;
+  for (int d = 0; d < 4; d++) nb *= (uint64_t)((g.n[d] + B - 1) / B);
+  for (uint64_t b = 0; b < nb; b++)
+    if (cand_h[h_bcfg[b]]) return true;
+  return false;
+}
+
 template <typename T>
 int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, const Geom& g,
                double e, const T* X, T* W, uint16_t* code, const uint8_t* d_bcfg,
-               const double* d_wq, const double* h_wq, int mode, hipStream_t st, int l_stop = 0)
+               const uint8_t* h_bcfg, const double* d_wq, const double* h_wq, int mode,
+               hipStream_t st, int l_stop = 0)
 {
   const int L = c->anchor_log2;
   const int64_t B = c->block_log2 ? (int64_t)1 << c->block_log2 : 0;
   const int nact = n_active(g);
+  int halves = -1;  // block_halves_used, once a level with blocks is reached
   for (int l = L; l > l_stop; l--) {
     const int64_t s = (int64_t)1 << (l - 1);
     // algorithmic traffic of the level: each of its points reads its value
@@ -948,8 +967,11 @@ int run_levels(hpez_ctx* ctx, const hpez_field_desc* d, const hpez_config* c, co
         const int64_t ext = B < g.n[dd] ? B : g.n[dd];
         ppb *= (uint64_t)(g.act[dd] ? ext / s : ext);
       }
-      bsa.pieces = (uint32_t)(ppb / 4096 < 1 ? 1 : ppb / 4096 > 256 ? 256 : ppb / 4096);
+      const uint64_t P = ppb / 4096;
+      bsa.pieces = (uint32_t)(P < 1 ? 1 : P > 256 ? 256 : P);
+      if (halves < 0) halves = block_halves_used(c, g, B, h_bcfg) ? 1 : 0;
       for (int t = 0; t < 2 * nact; t++) {
+        if ((t & 1) && !halves) continue;
         bsa.t = t;
         HIPCK(launch_block_step<T>(bsa, X, W, code, d_bcfg, d_wq, mode, st));
       }
@@ -1232,7 +1254,8 @@ int c_predict(hpez_ctx* ctx, CJob<T>& J, hipStream_t st)
   const Lattice al = anchor_lattice(J.g, c->anchor_log2);
   Lo.n_anchor = al.total;
   HIPCK(launch_anchors<T>(J.g, al, J.X, J.W, J.code, J.anc, c->radius, 0, st));
-  const int rc = run_levels<T>(ctx, d, c, J.g, e, J.X, J.W, J.code, J.dbcfg, J.dwq, J.h_wq, 0, st,
+  const int rc = run_levels<T>(ctx, d, c, J.g, e, J.X, J.W, J.code, J.dbcfg,
+                               c->block_log2 ? c->block_cfg : nullptr, J.dwq, J.h_wq, 0, st,
                                J.fast ? c->block_log2 : 0);
   if (rc) return rc;
   HIPCK(hipMemsetAsync(J.hist, 0, (size_t)J.nsym * 4, st));
@@ -1774,8 +1797,9 @@ int d_decode(hpez_ctx* ctx, DJob<T>& J, hipStream_t st)
   }
   HIPCK(launch_anchors<T>(J.g, al, nullptr, J.out, J.code, (T*)(in + Lo.off_anchor), c->radius, 1,
                           st));
-  return run_levels<T>(ctx, &J.d, c, J.g, Lo.e, nullptr, J.out, J.code, in + Lo.off_blocks, J.dwq,
-                       J.h_wq, 1, st, J.fast ? c->block_log2 : 0);
+  return run_levels<T>(ctx, &J.d, c, J.g, Lo.e, nullptr, J.out, J.code, in + Lo.off_blocks,
+                       J.nb ? J.h_bcfg : nullptr, J.dwq, J.h_wq, 1, st,
+                       J.fast ? c->block_log2 : 0);
 }
 
 template <typename T>

@@ -11,19 +11,57 @@ namespace hpez {
 // global atomics.
 constexpr int kHistWin = 4096;
 
+// Codes R - 1, R and R + 1 (most of them on smooth data, so lanes of a
+// wavefront would contend for the same LDS bin) are counted in registers and
+// added once per lane at the end; the rest go to the LDS window or global.
+// Lanes read eight codes at a time when the array is 16-byte aligned.
 __global__ void __launch_bounds__(256) histogram_kernel(const uint16_t* __restrict__ code,
                                                         uint64_t n, uint32_t* __restrict__ hist,
-                                                        uint32_t lo)
+                                                        uint32_t lo, uint32_t R)
 {
   __shared__ uint32_t h[kHistWin];
   for (int i = threadIdx.x; i < kHistWin; i += 256) h[i] = 0;
   __syncthreads();
+  uint32_t near[3] = {0, 0, 0};
+  auto add = [&](uint32_t c) {
+    const uint32_t d = c - (R - 1);
+    if (d < 3) {
+      near[0] += d == 0;
+      near[1] += d == 1;
+      near[2] += d == 2;
+    } else {
+      const uint32_t w = c - lo;
+      if (w < (uint32_t)kHistWin) atomicAdd(&h[w], 1u);
+      else atomicAdd(&hist[c], 1u);
+    }
+  };
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t c = code[i];
-    const uint32_t w = c - lo;
-    if (w < (uint32_t)kHistWin) atomicAdd(&h[w], 1u);
-    else atomicAdd(&hist[c], 1u);
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(code) & 15) == 0) {
+    const uint64_t ng = n / 8;
+    const uint4* v8 = reinterpret_cast<const uint4*>(code);
+    for (uint64_t g = gid; g < ng; g += stride) {
+      const uint4 v = v8[g];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        add(w[k] & 0xffffu);
+        add(w[k] >> 16);
+      }
+    }
+    done = ng * 8;
+  }
+  for (uint64_t i = done + gid; i < n; i += stride) add(code[i]);
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    uint32_t c = near[k];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) {
+      const uint32_t b = R - 1 + (uint32_t)k, w = b - lo;
+      if (w < (uint32_t)kHistWin) atomicAdd(&h[w], c);
+      else atomicAdd(&hist[b], c);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kHistWin; i += 256)
@@ -38,7 +76,8 @@ hipError_t launch_histogram(const uint16_t* code, uint64_t n, uint32_t* hist, ui
   uint64_t blocks = (n + 256 * 16 - 1) / (256 * 16);
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(histogram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, code, n, hist, lo);
+  hipLaunchKernelGGL(histogram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, code, n, hist, lo,
+                     R);
   return hipGetLastError();
 }
 

@@ -162,6 +162,9 @@ __global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const 
   for (uint64_t u = blockIdx.x; u < nbt * P; u += gridDim.x) {
     const uint64_t bi = u / P;
     const uint32_t piece = (uint32_t)(u - bi * P);
+    const hpez_interp c = a.cand[bcfg[bi]];
+    // second halves exist only with same-level cubic (uniform: no barrier)
+    if ((a.t & 1) && !(c.kind != 0 && c.same_level)) continue;
     int64_t lo[4], hi[4], J[4];
     {
       uint64_t r = bi;
@@ -176,7 +179,6 @@ __global__ void __launch_bounds__(256) block_step_kernel(BlockStepArgs a, const 
       const int64_t top = lo[d] + a.B - 1 < a.g.n[d] - 1 ? lo[d] + a.B - 1 : a.g.n[d] - 1;
       J[d] = a.g.act[d] ? (top - lo[d]) >> ls : top - lo[d] + 1;
     }
-    const hpez_interp c = a.cand[bcfg[bi]];
     if (threadIdx.x == 0) {
       // progression of dim d in set bx for class cl; returns its length
       auto put = [&](int bx, int d, int cl) -> uint64_t {

@@ -122,6 +122,25 @@ def test_block_wise(torch_cuda, dtype):
         roundtrip(torch_cuda, x, cfg, f"block-wise B={B}")
 
 
+@pytest.mark.parametrize("use", ["none", "one", "all"])
+def test_block_wise_same_level_use(torch_cuda, use):
+    """Generic block steps (float64) with same-level candidates offered: no
+    block on them (the second-half steps are skipped), exactly one block on
+    one, every block on one."""
+    x = fields.random_field((45, 40, 52), 21, np.float64, "mixed")
+    cand = candidates(3)
+    B = 8
+    nb = int(np.prod([(s + B - 1) // B for s in x.shape]))
+    bc = (np.arange(nb) * 5 % 9).astype(np.uint8)
+    if use == "one":
+        bc[nb // 2] = 9
+    elif use == "all":
+        bc[:] = 9 + np.arange(nb) % 2
+    cfg = make_cfg(x.shape, dtype="f64", eb=1e-3, kind="nat", anchor_log2=4, block_log2=3,
+                   cand=cand, block_cfg=bc)
+    roundtrip(torch_cuda, x, cfg, f"same-level use {use}")
+
+
 def test_chunk_sizes(torch_cuda):
     x = fields.random_field((50, 61, 33), 2, np.float32, "smooth")
     for chunk in (64, 256, 1024):
