@@ -250,6 +250,13 @@ __device__ __forceinline__ void hist_add_wave(uint32_t* lh, uint32_t* gh, uint32
   }
 }
 
+// v[d] for a run-time d in [0, 4) without indexing a private array (which
+// would place the array in scratch memory)
+__device__ __forceinline__ int64_t pick4(const int64_t* v, int d)
+{
+  return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : v[3];
+}
+
 __device__ __forceinline__ void lattice_point(const Lattice& L, uint64_t k, int64_t* x)
 {
   uint64_t r = k;

@@ -77,13 +77,6 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a, const T* __restri
   }
 }
 
-// v[d] for a run-time d in [0, 4) without indexing a private array (which
-// would place the array in scratch memory)
-__device__ __forceinline__ int64_t pick4(const int64_t* v, int d)
-{
-  return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : v[3];
-}
-
 // Step index of a level point under a configuration: 1D style, 2 * pass + half
 // (the pass is the last dimension in pass order whose coordinate is an odd
 // multiple of s; the half is 1 for coordinates at 3s mod 4s with same-level

@@ -85,20 +85,31 @@ __device__ void trial_step(const TrialArgs& a, const TrialBox& bx, const int64_t
     total *= cnt[d];
   }
   const double el = a.el[level], inv2e = a.inv2e[level], twoe = a.twoe[level];
+  const bool narrow = total <= 0xffffffffull;
   for (uint64_t k = threadIdx.x; k < total; k += blockDim.x) {
     int64_t x[4];
-    uint64_t rr = k;
-    for (int d = 3; d >= 0; d--) {
-      const uint64_t q = rr / cnt[d];
-      x[d] = r[d] + (int64_t)(rr - q * cnt[d]) * m[d];
-      rr = q;
+    if (narrow) {
+      uint32_t rr = (uint32_t)k;
+      for (int d = 3; d >= 0; d--) {
+        const uint32_t q = rr / cnt[d];
+        x[d] = r[d] + (int64_t)(rr - q * cnt[d]) * m[d];
+        rr = q;
+      }
+    } else {
+      uint64_t rr = k;
+      for (int d = 3; d >= 0; d--) {
+        const uint64_t q = rr / cnt[d];
+        x[d] = r[d] + (int64_t)(rr - q * cnt[d]) * m[d];
+        rr = q;
+      }
     }
     const int64_t idx = x[0] * bst[0] + x[1] * bst[1] + x[2] * bst[2] + x[3];
     const int64_t fidx = (bx.o[0] + x[0]) * a.fg.st[0] + (bx.o[1] + x[1]) * a.fg.st[1] +
                          (bx.o[2] + x[2]) * a.fg.st[2] + (bx.o[3] + x[3]);
     T p;
     if (!md) {
-      p = spline<T, P>(W, idx, s * bst[pd], x[pd], s, 0, bx.m[pd] - 1, kind, sl);
+      p = spline<T, P>(W, idx, s * pick4(bst, pd), pick4(x, pd), s, 0, pick4(bx.m, pd) - 1, kind,
+                       sl);
     } else {
       bool first = true;
       T acc = (T)0;
@@ -185,27 +196,37 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
         __syncthreads();
       }
     } else {
-      int pos[4] = {-1, -1, -1, -1}, np = 0;
+      // pass position of each dim, 4 bits per dim (15: not in the pass order)
+      unsigned pos = 0xffffu;
+      int np = 0;
       for (int i = 0; i < 4; i++) {
         const int d = ip.order[i];
-        if (d < 4 && act[d] && pos[d] < 0) pos[d] = np++;
+        bool fresh = false;
+        for (int e = 0; e < 4; e++)
+          if (e == d && act[e] && (pos >> (4 * e) & 15u) == 15u) fresh = true;
+        if (fresh) pos = (pos & ~(15u << (4 * d))) | ((unsigned)np++ << (4 * d));
       }
       for (int k = 0; k < np; k++) {
         int pd = 0;
         for (int d = 0; d < 4; d++)
-          if (pos[d] == k) pd = d;
+          if ((pos >> (4 * d) & 15u) == (unsigned)k) pd = d;
         for (int d = 0; d < 4; d++) {
+          const unsigned pdd = pos >> (4 * d) & 15u;
           if (!act[d]) { r[d] = 0; m[d] = 1; }
           else if (d == pd) { r[d] = s; m[d] = 2 * s; }
-          else if (pos[d] < k) { r[d] = 0; m[d] = s; }
+          else if (pdd == 15u || pdd < (unsigned)k) { r[d] = 0; m[d] = s; }
           else { r[d] = 0; m[d] = 2 * s; }
         }
         if (ip.kind != 0 && ip.same_level) {
-          m[pd] = 4 * s;
-          r[pd] = s;
+          for (int d = 0; d < 4; d++)
+            if (d == pd) {
+              m[d] = 4 * s;
+              r[d] = s;
+            }
           trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh, sq);
           __syncthreads();
-          r[pd] = 3 * s;
+          for (int d = 0; d < 4; d++)
+            if (d == pd) r[d] = 3 * s;
           trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 1, pd, 0, s, l, wq, sc, hist, lh, sq);
         } else {
           trial_step<T, P>(a, bx, bst, X, W, r, m, ip.kind, 0, 0, pd, 0, s, l, wq, sc, hist, lh, sq);
@@ -232,8 +253,13 @@ __device__ void trial_body(const TrialArgs& a, const TrialBox& bx, const T* __re
   }
 }
 
+// regions too large for LDS: the region's working copy in global scratch,
+// 1024 lanes per (region, candidate) (few work-groups, each a long serial
+// walk through the levels)
+constexpr int kTrialGlobalThreads = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(256) trial_kernel_global(TrialArgs a,
+__global__ void __launch_bounds__(kTrialGlobalThreads) trial_kernel_global(TrialArgs a,
                                                            const TrialBox* __restrict__ boxes,
                                                            const T* __restrict__ X,
                                                            T* __restrict__ scratch,
@@ -516,8 +542,8 @@ hipError_t launch_trials(const TrialArgs& a, const TrialBox* d_boxes, uint32_t n
     hipLaunchKernelGGL((trial_kernel_lds<T>), dim3(n_boxes, n_cand), dim3(256), lds, st, a,
                        d_boxes, X, d_wq, d_score, d_hist);
   } else
-    hipLaunchKernelGGL((trial_kernel_global<T>), dim3(n_boxes, n_cand), dim3(256), hb, st, a,
-                       d_boxes, X, scratch, d_wq, d_score, d_hist);
+    hipLaunchKernelGGL((trial_kernel_global<T>), dim3(n_boxes, n_cand), dim3(kTrialGlobalThreads),
+                       hb, st, a, d_boxes, X, scratch, d_wq, d_score, d_hist);
   return hipGetLastError();
 }
 
