@@ -141,6 +141,27 @@ def test_block_wise_same_level_use(torch_cuda, use):
     roundtrip(torch_cuda, x, cfg, f"same-level use {use}")
 
 
+GENERIC_BLOCK = [((30, 64, 70), "f64", 1, 8), ((9, 17, 33, 5), "f32", -1, 4),
+                 ((11, 6, 20, 13), "f64", 2, 4)]
+
+
+@pytest.mark.parametrize("shape,dt,frozen,B", GENERIC_BLOCK,
+                         ids=["x".join(map(str, s)) + f"-{d}-fz{f}-B{b}"
+                              for s, d, f, b in GENERIC_BLOCK])
+def test_block_wise_generic_frozen_4d(torch_cuda, shape, dt, frozen, B):
+    """Generic block steps where a dim takes every coordinate of a block (a
+    frozen dim) and in four dims, every candidate in use."""
+    nd = len(shape)
+    cand = candidates(nd)
+    nb = int(np.prod([(s + B - 1) // B for s in shape]))
+    bc = (np.arange(nb) * 7 % len(cand)).astype(np.uint8)
+    x = fields.random_field(shape, nb + nd, np.float32 if dt == "f32" else np.float64, "mixed")
+    cfg = make_cfg(shape, dtype=dt, eb=1e-3, kind="nat", md=1, frozen_dim=frozen,
+                   anchor_log2=3 if B == 4 else 4, block_log2=int(np.log2(B)), cand=cand,
+                   block_cfg=bc)
+    roundtrip(torch_cuda, x, cfg, f"generic blocks {shape} {dt} frozen {frozen} B={B}")
+
+
 def test_chunk_sizes(torch_cuda):
     x = fields.random_field((50, 61, 33), 2, np.float32, "smooth")
     for chunk in (64, 256, 1024):
