@@ -162,6 +162,17 @@ def test_block_wise_generic_frozen_4d(torch_cuda, shape, dt, frozen, B):
     roundtrip(torch_cuda, x, cfg, f"generic blocks {shape} {dt} frozen {frozen} B={B}")
 
 
+@pytest.mark.parametrize("pred", ["interp", "lorenzo"])
+@pytest.mark.parametrize("radius", [1, 2, 3])
+def test_smallest_radii(torch_cuda, pred, radius):
+    """Radius 1-3 on the paths with a separate code histogram: the bins next to
+    the zero-error code reach the ends of the code range (radius 1 has only the
+    verbatim code and the zero-error code)."""
+    x = fields.random_field((23, 31, 40), radius, np.float64, "mixed")
+    cfg = make_cfg(x.shape, dtype="f64", eb=1e-3, kind="nak", radius=radius, predictor=pred)
+    roundtrip(torch_cuda, x, cfg, f"radius {radius} {pred}")
+
+
 def test_chunk_sizes(torch_cuda):
     x = fields.random_field((50, 61, 33), 2, np.float32, "smooth")
     for chunk in (64, 256, 1024):
