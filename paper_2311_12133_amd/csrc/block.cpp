@@ -398,6 +398,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
     uint64_t wgs;
     bool narrow;
     uint32_t threads;
+    int level;
   };
   std::vector<Launch> launches;
   size_t ei = 0, wi = 0;
@@ -416,7 +417,7 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
       const uint32_t tile =
           gpts ? ctx_tile(ctx, kTileFace, sizeof(T) == 4 ? 0 : 1, gpts, face_tile(256, 1))
                : face_tile(256, 1);
-      Launch L{ei, wi, 0, 0, true, face_threads(tile)};
+      Launch L{ei, wi, 0, 0, true, face_threads(tile), l};
       const uint64_t per = (uint64_t)face_threads(tile) * face_ppl(tile);
       for (int j = 0; j < n; j++)
       for (size_t k = 0; k < jobs[j].steps[l].size(); k++) {
@@ -514,19 +515,28 @@ int run_block_jobs(hpez_ctx* ctx, BlockJobHost<T>* jobs, int n, int mode, void* 
   BCK(launch_planes<T>((const PlaneJob<T>*)(dt + off_planes), (const uint64_t*)(dt + off_pwg), np,
                        plane_wgs, plane_lds, mode, st));
   // The coarse levels of every block on the block lattices need only the
-  // planes' lattice points; the face steps fill the other face points.  The
-  // two write disjoint arrays, so the coarse levels run on the second stream
-  // beside the face steps.
-  hipStream_t cs = launches.empty() ? st : ctx_fork(ctx, st);
+  // face points of the coarse face levels (s >= 4): from the planes, or from
+  // the face steps of those levels for fields whose planes do not fit, which
+  // come first (launches run from the top level down).  The face steps of
+  // levels 2 and 1 fill the other face points; they and the coarse levels
+  // write disjoint arrays, so the coarse levels run on the second stream
+  // beside them.
+  auto face_launch = [&](const Launch& L) {
+    return launch_face_steps<T>((const FaceEntry<T>*)dt + L.e0,
+                                (const uint64_t*)(dt + off_wg) + L.w0, L.cnt, L.wgs, L.narrow,
+                                mode, L.threads, st);
+  };
+  size_t li = 0;
+  for (; li < launches.size() && launches[li].level > kCoarseL; li++)
+    BCK(face_launch(launches[li]));
+  hipStream_t cs = li == launches.size() ? st : ctx_fork(ctx, st);
   if (!cs) cs = st;
   hipEvent_t evc = ctx_span_begin(ctx, cs, mode == 0 ? "coarse_predict" : "coarse_reconstruct");
   BCK(launch_coarse_jobs<T>((const BlockJobDev<T>*)(dt + off_jobs), (const uint64_t*)(dt + off_begin),
                             n, total_blocks, mode, cs));
   ctx_span_end(ctx, evc, mode == 0 ? "coarse_predict" : "coarse_reconstruct",
                total_blocks * 729ull * (sizeof(T) + 2), cs);
-  for (const Launch& L : launches)
-    BCK(launch_face_steps<T>((const FaceEntry<T>*)dt + L.e0, (const uint64_t*)(dt + off_wg) + L.w0,
-                             L.cnt, L.wgs, L.narrow, mode, L.threads, st));
+  for (; li < launches.size(); li++) BCK(face_launch(launches[li]));
   ctx_span_end(ctx, ev, mode == 0 ? "faces_predict" : "faces_reconstruct",
                face_pts * (sizeof(T) + 2), st);
   if (cs != st) {
