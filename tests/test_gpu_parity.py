@@ -279,20 +279,22 @@ def test_block_fast_path(torch_cuda, shape):
         roundtrip(torch_cuda, x, cfg, f"fast {shape} {kw}")
 
 
-def test_block_fast_path_planes_too_large(torch_cuda):
-    """Block-wise B = 32 on a field whose face planes are too large for the
-    plane kernel (600 x 600 planes: the coarse face levels run as face steps,
-    which the coarse block levels read).  Three compressions of each
-    configuration must equal the oracle's stream."""
+@pytest.mark.parametrize("shape", [(36, 600, 600), (3, 40000)], ids=["36x600x600", "3x40000"])
+def test_block_fast_path_planes_too_large(torch_cuda, shape):
+    """Block-wise B = 32 on fields whose face planes are too large for the
+    plane kernel (600 x 600 planes; a face line of 10^4 lattice cells): the
+    coarse face levels run as face steps, which the coarse block levels read.
+    Three compressions of each configuration must equal the oracle's stream."""
     from paper_2311_12133_amd import binding
-    shape = (36, 600, 600)
+    nd = len(shape)
     x = fields.random_field(shape, 600, np.float32, "mixed")
-    cand = candidates(3)
+    cand = candidates(nd)
     nb = int(np.prod([(s + 31) // 32 for s in shape]))
     bc = np.random.default_rng(nb).integers(0, len(cand), nb).astype(np.uint8)
     xt = torch_cuda.from_numpy(x).cuda()
     for kw in (dict(kind="nak"), dict(kind="nat", md=1)):
-        cfg = make_cfg(shape, eb=1e-3, anchor_log2=6, block_log2=5, cand=cand, block_cfg=bc, **kw)
+        cfg = make_cfg(shape, eb=1e-3, anchor_log2=6 if nd == 3 else 7, block_log2=5, cand=cand,
+                       block_cfg=bc, **kw)
         got = roundtrip(torch_cuda, x, cfg, f"large planes {kw}")
         for _ in range(2):
             again = binding.compress(xt, cfg).cpu().numpy().tobytes()
