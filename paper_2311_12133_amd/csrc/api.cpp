@@ -830,7 +830,7 @@ uint64_t grid_points(const Geom& g, int64_t s)
 
 // Odd block steps (second halves of same-level passes) have points only in
 // blocks whose candidate uses same-level cubic: false when no block's does
-// (h_bcfg: host copy of the block choices, or null to judge by the candidates).
+// (h_bcfg: host copy of the block choices, or null to decide from the candidates).
 bool block_halves_used(const hpez_config* c, const Geom& g, int64_t B, const uint8_t* h_bcfg)
 {
   bool cand_h[256] = {};
